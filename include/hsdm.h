@@ -1,0 +1,141 @@
+/*
+ * hsdm.h -- C ABI of libhsdm: the dense path from a Hamiltonian H and an
+ * overlap S to eigenpairs and density matrices on one AMD Instinct MI355X
+ * (gfx950), in FP64.
+ *
+ * The problem is the generalized eigenproblem  H C = S C eps  (Eq. (3) of the
+ * ELSI 2.x paper, arXiv:1912.13403) with H symmetric and S symmetric positive
+ * definite, followed by the density matrix  p_ij = sum_l f_l c_il c_jl
+ * (Eq. (4)) and the energy-weighted density matrix
+ * q_ij = sum_l eps_l f_l c_il c_jl (Eq. (17)), the occupations f_l and the
+ * chemical potential coming from the eigenvalues and the electron count
+ * (Sec. 2.6, normalization of Eq. (16) for one unit task).
+ *
+ * Conventions shared by every call
+ *   - Matrices are column-major FP64 in DEVICE memory of the handle's device:
+ *     element (i, j) of X with leading dimension ldx is X[i + j*ldx], and
+ *     ldx >= n.  Vectors of length n are device arrays unless stated.
+ *   - Only the LOWER triangle of H and S is read; inputs are never modified.
+ *   - Outputs D, E are written in full (both triangles); eigenvectors are
+ *     columns in ascending eigenvalue order, normalized so that C^T S C = I.
+ *   - The caller owns every buffer passed in; the handle owns its workspace
+ *     and the cached factor of S.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it in order; every call that returns a status other
+ *     than an argument error synchronizes that stream before returning.
+ *   - One handle must not be used by two host threads at once; different
+ *     handles are independent.
+ *   - Return value: HSDM_OK, a negative number -k if argument k (1-based,
+ *     the handle counting as argument 1) is invalid, or a positive status
+ *     below.  After a non-zero status the outputs are undefined.  The library
+ *     never aborts.
+ */
+#ifndef HSDM_H
+#define HSDM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hsdm_ctx *hsdm_handle;
+
+enum hsdm_status {
+  HSDM_OK = 0,
+  HSDM_NOT_SPD = 1,        /* S is not positive definite; hsdm_status_detail = failing column (1-based) */
+  HSDM_NO_CONVERGE = 2,    /* an eigenvalue iteration did not converge */
+  HSDM_MU_FAIL = 3,        /* chemical potential search failed (non-finite eigenvalues) */
+  HSDM_DEVICE_ERROR = 4,   /* HIP error or out of device memory; see hsdm_last_error */
+  HSDM_SYNC_TIMEOUT = 5    /* a bounded inter-workgroup wait ran out (device overloaded) */
+};
+
+/* Keys of hsdm_set_real / hsdm_set_int. */
+enum hsdm_key {
+  HSDM_KEY_FMAX = 1,       /* real: maximum occupation per state (2 spin-degenerate, 1 per spin channel); default 2 */
+  HSDM_KEY_FCUT = 2,       /* real: states with f <= fcut * fmax get no eigenvector (f is below it); default 1e-16 */
+  HSDM_KEY_DEG_TOL = 3,    /* real: kT = 0 degeneracy window; < 0 selects 1e-12 * ||H||_1 (default) */
+  HSDM_KEY_TIMING = 4      /* int: 1 records per-phase times (hsdm_phase_times), 0 off (default) */
+};
+
+/* Create a handle bound to HIP device `device` (~ elsi_init, Sec. 2.1). */
+int hsdm_init(hsdm_handle *h, int device);
+/* Release the handle and its device workspace (~ elsi_finalize). */
+int hsdm_finalize(hsdm_handle h);
+/* Forget the cached factor of S (~ elsi_reinit, Sec. 2.7: a new geometry
+ * brings a new overlap matrix; everything else is kept).  The factor is
+ * cached per (S pointer, n, lds); call this whenever S changes in place. */
+int hsdm_reinit(hsdm_handle h);
+int hsdm_set_real(hsdm_handle h, int key, double value);
+int hsdm_set_int(hsdm_handle h, int key, long value);
+
+/* All eigenpairs of H C = S C eps (Eq. (3)).
+ *   eval[n]        device, ascending eigenvalues (out)
+ *   C[ldc * n]     device, eigenvectors (out), C^T S C = I
+ * Path: Cholesky S = L L^T with L^{-1} (cached), A = L^{-1} H L^{-T},
+ * full-to-band, band-to-tridiagonal, divide and conquer, back-transforms. */
+int hsdm_solve_ev_real(hsdm_handle h, int n, const double *H, int ldh, const double *S, int lds,
+                       double *eval, double *C, int ldc, void *stream);
+
+/* Density matrices from H, S and the electron count (Eqs. (3), (4), (17),
+ * Sec. 2.6).  kT > 0: Fermi-Dirac occupations with mu from bisection on
+ * sum_l f_l = n_electrons; kT = 0: step occupations, degenerate states at the
+ * Fermi level sharing the remainder equally.
+ *   D[ldd * n]      device, density matrix (out)
+ *   E[lde * n]      device, energy-weighted density matrix (out), nullable
+ *   eval[n]         device, ascending eigenvalues (out), nullable
+ *   band_energy     HOST, sum_l f_l eps_l = Tr(D H) (out), nullable
+ *   mu              HOST, chemical potential (out), nullable
+ * Only eigenvectors of states with f_l > fcut * fmax are formed. */
+int hsdm_solve_dm_real(hsdm_handle h, int n, const double *H, int ldh, const double *S, int lds,
+                       double n_electrons, double kT, double *D, int ldd, double *E, int lde,
+                       double *eval, double *band_energy, double *mu, void *stream);
+
+/* ---- phase entry points (same conventions; used to test and compose) ---- */
+
+/* S = L L^T and L^{-1}; L and Linv written in full (zeros above the diagonal). */
+int hsdm_cholesky_inverse(hsdm_handle h, int n, const double *S, int lds, double *L, int ldl,
+                          double *Linv, int ldli, void *stream);
+/* Lower triangle of A = Linv H Linv^T (the standard form of Eq. (3)); the
+ * strict upper triangle of A is left unspecified. */
+int hsdm_standard_form(hsdm_handle h, int n, const double *H, int ldh, const double *Linv,
+                       int ldli, double *A, int lda, void *stream);
+/* Two-stage reduction of the symmetric A (lower triangle read) to the
+ * tridiagonal (d[n], e[n-1]); if Q is non-null the orthogonal Q with
+ * A = Q T Q^T is formed (Q[ldq * n]). */
+int hsdm_tridiagonalize(hsdm_handle h, int n, const double *A, int lda, double *d, double *e,
+                        double *Q, int ldq, void *stream);
+/* Eigenpairs of the symmetric tridiagonal (d[n], e[n-1]) by divide and
+ * conquer: w[n] ascending, Z[ldz * n]. */
+int hsdm_tridiag_eigh(hsdm_handle h, int n, const double *d, const double *e, double *w,
+                      double *Z, int ldz, void *stream);
+/* Occupations f[n] (device) for ascending eval[n]; mu, band_energy and
+ * n_occupied (#{f > fcut * fmax}) returned on the HOST (nullable). */
+int hsdm_occupations(hsdm_handle h, int n, const double *eval, double n_electrons, double kT,
+                     double deg_tol, double *f, double *mu, double *band_energy, int *n_occupied,
+                     void *stream);
+/* D = C diag(f) C^T and E = C diag(f eval) C^T from the first m columns of
+ * C[ldc * m]; E nullable. */
+int hsdm_density(hsdm_handle h, int n, int m, const double *C, int ldc, const double *f,
+                 const double *eval, double *D, int ldd, double *E, int lde, void *stream);
+/* FP64 GEMM on the matrix cores: C = alpha op(A) op(B) + beta C,
+ * op(X) = X ('N') or X^T ('T'); op(A) is m x k, op(B) is k x n. */
+int hsdm_dgemm(hsdm_handle h, char transa, char transb, int m, int n, int k, double alpha,
+               const double *A, int lda, const double *B, int ldb, double beta, double *C,
+               int ldc, void *stream);
+
+/* ---- diagnostics ---- */
+const char *hsdm_status_string(int status);
+/* Text of the last error on this handle ("" if none). */
+const char *hsdm_last_error(hsdm_handle h);
+/* Detail of the last positive status (failing column for HSDM_NOT_SPD). */
+int hsdm_status_detail(hsdm_handle h);
+/* Per-phase times in ms of the last solve when HSDM_KEY_TIMING is on:
+ * times[0..nphase-1] in the order of hsdm_phase_name(i); returns the number
+ * of phases written (at most cap). */
+int hsdm_phase_times(hsdm_handle h, double *times, int cap);
+const char *hsdm_phase_name(int i);
+int hsdm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,662 @@
+// C ABI of libhsdm: handle, argument checks, workspace, and the phase driver
+// of the dense H, S -> eigenpairs / density-matrix path.  Every phase is a
+// kernel of this library; the host only enqueues work on the caller's stream
+// and reads back the status word and the scalar results at the end.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hsdm.h"
+#include "hsdm_internal.h"
+#include "hsdm_phases.h"
+#include "hsdm_util.h"
+
+namespace {
+
+constexpr int BAND = 32;
+constexpr int NPHASE = 9;
+const char* kPhaseNames[NPHASE] = {"cholesky_inverse", "standard_form", "full_to_band",
+                                   "band_to_tridiagonal", "divide_conquer", "backtransform_stage2",
+                                   "backtransform_stage1", "backtransform_cholesky", "density"};
+
+__global__ void reset_status_kernel(DevStatusWord* st, OccOut* occ) {
+  if (threadIdx.x == 0) {
+    st->code = 0;
+    st->detail = 0;
+    occ->mu = 0.0;
+    occ->band_energy = 0.0;
+    occ->sum_f = 0.0;
+    occ->m = 0;
+    occ->iters = 0;
+  }
+}
+
+__global__ void set_int_kernel(int* p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+__global__ void eye_kernel(double* Z, long ldz, int n) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)n * n) return;
+  const int i = (int)(idx % n), j = (int)(idx / n);
+  Z[i + (long)j * ldz] = (i == j) ? 1.0 : 0.0;
+}
+
+__global__ void copy_vec_kernel(const double* a, double* b, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+struct Pinned {
+  DevStatusWord st;
+  OccOut occ;
+};
+
+}  // namespace
+
+struct hsdm_ctx {
+  int device = 0;
+  double fmax = 2.0;
+  double fcut_rel = 1e-16;
+  double deg_tol = -1.0;
+  bool timing = false;
+  std::string err;
+  int detail = 0;
+  // workspace
+  int ws_n = 0;
+  double* ws = nullptr;
+  int* iws = nullptr;
+  long* d_goff = nullptr;
+  DevStatusWord* st = nullptr;
+  OccOut* occ = nullptr;
+  Pinned* host = nullptr;
+  StedcPlan* plan = nullptr;
+  Sb2stLayout lay{};
+  // carved pointers
+  double *Lbuf, *Linv, *Abuf, *Vst, *Zbuf, *Cbuf, *T1, *tau1, *AB, *sy_scr, *dvec, *evec, *lam,
+      *fvec, *V2, *tau2, *T2, *dc_scr, *bt1_scr, *colsum, *hnorm;
+  int *dc_iscr, *progress;
+  unsigned* bar;
+  // cached factor of S
+  const double* s_ptr = nullptr;
+  int s_n = 0, s_ld = 0;
+  bool s_valid = false;
+  // phase timing
+  hipEvent_t ev[NPHASE + 1] = {};
+  double phase_ms[NPHASE] = {};
+  bool phase_done[NPHASE] = {};
+};
+
+namespace {
+
+int fail_dev(hsdm_ctx* h, hipError_t e, const char* where) {
+  h->err = std::string(where) + ": " + hipGetErrorString(e);
+  return HSDM_DEVICE_ERROR;
+}
+
+#define DEV_TRY(h, x)                                \
+  do {                                               \
+    hipError_t _e = (x);                             \
+    if (_e != hipSuccess) return fail_dev(h, _e, #x); \
+  } while (0)
+
+void free_ws(hsdm_ctx* h) {
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->iws) (void)hipFree(h->iws);
+  if (h->d_goff) (void)hipFree(h->d_goff);
+  stedc_plan_destroy(h->plan);
+  h->ws = nullptr;
+  h->iws = nullptr;
+  h->d_goff = nullptr;
+  h->plan = nullptr;
+  h->ws_n = 0;
+  h->s_valid = false;
+}
+
+int ensure_ws(hsdm_ctx* h, int n) {
+  if (h->ws_n == n && h->ws) return HSDM_OK;
+  free_ws(h);
+  const size_t nn = (size_t)n * n;
+  const Sb2stLayout L = sb2st_layout(n, BAND);
+  const int npanel = (n > BAND) ? ceil_div(n - 1, BAND) : 0;
+  size_t off = 0;
+  auto take = [&](size_t cnt) {
+    size_t o = off;
+    off += (cnt + 31) & ~(size_t)31;  // 256-byte aligned pieces
+    return o;
+  };
+  const size_t oL = take(nn), oLi = take(nn), oA = take(nn), oV = take(nn), oZ = take(nn),
+               oC = take(nn);
+  const size_t oT1 = take((size_t)(npanel + 1) * BAND * BAND), otau1 = take(n + 1);
+  const size_t oAB = take((size_t)2 * BAND * n), osy = take(sy2sb_scratch_doubles(n, BAND));
+  const size_t od = take(n), oe = take(n), olam = take(n), of = take(n);
+  const size_t oV2 = take(L.v2_doubles + 1), otau2 = take((size_t)L.ngroups * BAND + 1),
+               oT2 = take((size_t)L.ngroups * BAND * BAND + 1);
+  const size_t odc = take(stedc_scratch_doubles(n)), obt1 = take(bt1_scratch_doubles(n, BAND, n));
+  const size_t ocs = take(n), ohn = take(1);
+  hipError_t e = hipMalloc(&h->ws, off * sizeof(double));
+  if (e != hipSuccess) {
+    h->ws = nullptr;
+    return fail_dev(h, e, "workspace allocation");
+  }
+  const size_t ni = stedc_iscratch_ints(n) + (size_t)n + 128;
+  e = hipMalloc(&h->iws, ni * sizeof(int));
+  if (e != hipSuccess) {
+    free_ws(h);
+    return fail_dev(h, e, "workspace allocation");
+  }
+  double* w = h->ws;
+  h->Lbuf = w + oL; h->Linv = w + oLi; h->Abuf = w + oA; h->Vst = w + oV; h->Zbuf = w + oZ;
+  h->Cbuf = w + oC; h->T1 = w + oT1; h->tau1 = w + otau1; h->AB = w + oAB; h->sy_scr = w + osy;
+  h->dvec = w + od; h->evec = w + oe; h->lam = w + olam; h->fvec = w + of; h->V2 = w + oV2;
+  h->tau2 = w + otau2; h->T2 = w + oT2; h->dc_scr = w + odc; h->bt1_scr = w + obt1;
+  h->colsum = w + ocs; h->hnorm = w + ohn;
+  h->dc_iscr = h->iws;
+  h->progress = h->iws + stedc_iscratch_ints(n);
+  h->bar = (unsigned*)(h->progress + n + 64);
+  h->lay = L;
+  std::vector<long> goff(L.nblk + 1);
+  sb2st_group_offsets(L, goff.data());
+  e = hipMalloc(&h->d_goff, sizeof(long) * (L.nblk + 1));
+  if (e != hipSuccess) {
+    free_ws(h);
+    return fail_dev(h, e, "workspace allocation");
+  }
+  e = hipMemcpy(h->d_goff, goff.data(), sizeof(long) * (L.nblk + 1), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_ws(h);
+    return fail_dev(h, e, "workspace upload");
+  }
+  h->plan = stedc_plan_create(n);
+  if (!h->plan) {
+    free_ws(h);
+    h->err = "divide-and-conquer plan allocation failed";
+    return HSDM_DEVICE_ERROR;
+  }
+  h->ws_n = n;
+  return HSDM_OK;
+}
+
+void mark(hsdm_ctx* h, int phase, hipStream_t s) {
+  if (h->timing) {
+    (void)hipEventRecord(h->ev[phase], s);
+    if (phase > 0) h->phase_done[phase - 1] = true;
+  }
+}
+
+int finish(hsdm_ctx* h, hipStream_t s) {
+  DEV_TRY(h, hipMemcpyAsync(&h->host->st, h->st, sizeof(DevStatusWord), hipMemcpyDeviceToHost, s));
+  DEV_TRY(h, hipMemcpyAsync(&h->host->occ, h->occ, sizeof(OccOut), hipMemcpyDeviceToHost, s));
+  DEV_TRY(h, hipStreamSynchronize(s));
+  if (h->timing) {
+    for (int p = 0; p < NPHASE; p++) {
+      h->phase_ms[p] = 0.0;
+      if (!h->phase_done[p]) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, h->ev[p], h->ev[p + 1]) == hipSuccess) h->phase_ms[p] = ms;
+    }
+  }
+  const int code = h->host->st.code;
+  h->detail = h->host->st.detail;
+  switch (code) {
+    case DS_OK: return HSDM_OK;
+    case DS_NOT_SPD:
+      h->s_valid = false;
+      h->err = "S is not positive definite (column " + std::to_string(h->detail) + ")";
+      return HSDM_NOT_SPD;
+    case DS_NO_CONVERGE: h->err = "eigenvalue iteration did not converge"; return HSDM_NO_CONVERGE;
+    case DS_MU_FAIL: h->err = "chemical potential search failed"; return HSDM_MU_FAIL;
+    default:
+      h->s_valid = false;
+      h->err = "inter-workgroup wait timed out";
+      return HSDM_SYNC_TIMEOUT;
+  }
+}
+
+bool bad_ld(int ld, int n) { return ld < (n > 1 ? n : 1); }
+
+// Cholesky + inverse of S into the cache (skipped when cached).
+int factor_s(hsdm_ctx* h, int n, const double* S, int lds, hipStream_t s) {
+  if (h->s_valid && h->s_ptr == S && h->s_n == n && h->s_ld == lds) return HSDM_OK;
+  DEV_TRY(h, dev_copy(S, lds, h->Lbuf, n, n, n, s));
+  DEV_TRY(h, dev_fill(h->Linv, n, n, n, 0.0, s));
+  DEV_TRY(h, chol_inv(n, h->Lbuf, n, h->Linv, n, h->Abuf, n, h->st, s));
+  h->s_ptr = S;
+  h->s_n = n;
+  h->s_ld = lds;
+  h->s_valid = true;
+  return HSDM_OK;
+}
+
+// A = Linv H Linv^T (lower).  Zbuf and Vst serve as scratch.
+int standard_form(hsdm_ctx* h, int n, const double* H, int ldh, const double* Li, int ldli,
+                  double* A, int lda, hipStream_t s) {
+  DEV_TRY(h, dev_sym_full(H, ldh, h->Zbuf, n, n, s));
+  GemmArgs g{};
+  g.m = n; g.n = n; g.k = n; g.A = Li; g.lda = ldli; g.B = h->Zbuf; g.ldb = n; g.C = h->Vst;
+  g.ldc = n; g.alpha = 1.0; g.beta = 0.0; g.flags = GF_KA_LOWER;
+  DEV_TRY(h, gemm_launch(g, s));
+  g = GemmArgs{};
+  g.m = n; g.n = n; g.k = n; g.A = h->Vst; g.lda = n; g.B = Li; g.ldb = ldli; g.C = A; g.ldc = lda;
+  g.alpha = 1.0; g.beta = 0.0; g.ta = 0; g.tb = 1;
+  g.flags = GF_KB_UPPER | GF_C_LOWER_TILES | GF_C_LOWER_ONLY;
+  DEV_TRY(h, gemm_launch(g, s));
+  return HSDM_OK;
+}
+
+// Two-stage reduction of h->Abuf (lower) to (dvec, evec); reflectors kept.
+int reduce(hsdm_ctx* h, int n, hipStream_t s, int phase_band) {
+  DEV_TRY(h, sy2sb_run(n, BAND, h->Abuf, n, h->Vst, n, h->tau1, h->T1, h->AB, 2 * BAND, h->sy_scr,
+                       h->bar, h->st, s));
+  mark(h, phase_band, s);
+  DEV_TRY(h, sb2st_run(h->lay, h->AB, 2 * BAND, h->dvec, h->evec, h->V2, h->tau2, h->d_goff,
+                       h->progress, h->st, s));
+  return HSDM_OK;
+}
+
+struct OccHook {
+  hsdm_ctx* h;
+  int n;
+  double ne, kT;
+};
+
+hipError_t occ_hook(void* ctx, const double* lam, hipStream_t s) {
+  OccHook* o = (OccHook*)ctx;
+  hsdm_ctx* h = o->h;
+  const bool auto_tol = h->deg_tol < 0.0;
+  return occupations_launch(o->n, lam, h->fmax, o->ne, o->kT, auto_tol ? 0.0 : h->deg_tol,
+                            auto_tol ? h->hnorm : nullptr, h->fcut_rel * h->fmax, h->fvec, h->occ,
+                            h->st, s);
+}
+
+int check_handle(hsdm_handle h) { return h ? 0 : -1; }
+
+}  // namespace
+
+extern "C" {
+
+int hsdm_version(void) { return 100; }
+
+int hsdm_init(hsdm_handle* out, int device) {
+  if (!out) return -1;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return HSDM_DEVICE_ERROR;
+  if (device < 0 || device >= ndev) return -2;
+  hsdm_ctx* h = new hsdm_ctx();
+  h->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete h;
+    return HSDM_DEVICE_ERROR;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, sizeof(DevStatusWord) + sizeof(OccOut) + 64) != hipSuccess) {
+    delete h;
+    return HSDM_DEVICE_ERROR;
+  }
+  h->st = (DevStatusWord*)p;
+  h->occ = (OccOut*)((char*)p + 32);
+  if (hipHostMalloc((void**)&h->host, sizeof(Pinned), hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(p);
+    delete h;
+    return HSDM_DEVICE_ERROR;
+  }
+  for (int i = 0; i <= NPHASE; i++) (void)hipEventCreate(&h->ev[i]);
+  *out = h;
+  return HSDM_OK;
+}
+
+int hsdm_finalize(hsdm_handle h) {
+  if (!h) return -1;
+  (void)hipSetDevice(h->device);
+  free_ws(h);
+  if (h->st) (void)hipFree(h->st);
+  if (h->host) (void)hipHostFree(h->host);
+  for (int i = 0; i <= NPHASE; i++)
+    if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+  delete h;
+  return HSDM_OK;
+}
+
+int hsdm_reinit(hsdm_handle h) {
+  if (!h) return -1;
+  h->s_valid = false;
+  h->s_ptr = nullptr;
+  return HSDM_OK;
+}
+
+int hsdm_set_real(hsdm_handle h, int key, double v) {
+  if (!h) return -1;
+  switch (key) {
+    case HSDM_KEY_FMAX:
+      if (!(v > 0.0) || !std::isfinite(v)) return -3;
+      h->fmax = v;
+      return HSDM_OK;
+    case HSDM_KEY_FCUT:
+      if (!(v >= 0.0) || !(v < 1.0)) return -3;
+      h->fcut_rel = v;
+      return HSDM_OK;
+    case HSDM_KEY_DEG_TOL:
+      if (std::isnan(v)) return -3;
+      h->deg_tol = v;
+      return HSDM_OK;
+    default: return -2;
+  }
+}
+
+int hsdm_set_int(hsdm_handle h, int key, long v) {
+  if (!h) return -1;
+  if (key == HSDM_KEY_TIMING) {
+    h->timing = (v != 0);
+    return HSDM_OK;
+  }
+  return -2;
+}
+
+const char* hsdm_status_string(int status) {
+  switch (status) {
+    case HSDM_OK: return "ok";
+    case HSDM_NOT_SPD: return "S is not positive definite";
+    case HSDM_NO_CONVERGE: return "eigenvalue iteration did not converge";
+    case HSDM_MU_FAIL: return "chemical potential search failed";
+    case HSDM_DEVICE_ERROR: return "device error";
+    case HSDM_SYNC_TIMEOUT: return "inter-workgroup wait timed out";
+    default: return status < 0 ? "invalid argument" : "unknown status";
+  }
+}
+
+const char* hsdm_last_error(hsdm_handle h) { return h ? h->err.c_str() : "null handle"; }
+int hsdm_status_detail(hsdm_handle h) { return h ? h->detail : 0; }
+
+int hsdm_phase_times(hsdm_handle h, double* times, int cap) {
+  if (!h || !times) return 0;
+  int k = cap < NPHASE ? cap : NPHASE;
+  for (int i = 0; i < k; i++) times[i] = h->phase_ms[i];
+  return k;
+}
+
+const char* hsdm_phase_name(int i) { return (i >= 0 && i < NPHASE) ? kPhaseNames[i] : ""; }
+
+int hsdm_dgemm(hsdm_handle h, char transa, char transb, int m, int n, int k, double alpha,
+               const double* A, int lda, const double* B, int ldb, double beta, double* C,
+               int ldc, void* stream) {
+  if (!h) return -1;
+  const int ta = (transa == 'T' || transa == 't') ? 1 : ((transa == 'N' || transa == 'n') ? 0 : -1);
+  const int tb = (transb == 'T' || transb == 't') ? 1 : ((transb == 'N' || transb == 'n') ? 0 : -1);
+  if (ta < 0) return -2;
+  if (tb < 0) return -3;
+  if (m < 0) return -4;
+  if (n < 0) return -5;
+  if (k < 0) return -6;
+  if (m > 0 && k > 0 && !A) return -8;
+  if (lda < (ta ? (k > 1 ? k : 1) : (m > 1 ? m : 1))) return -9;
+  if (n > 0 && k > 0 && !B) return -10;
+  if (ldb < (tb ? (n > 1 ? n : 1) : (k > 1 ? k : 1))) return -11;
+  if (m > 0 && n > 0 && !C) return -13;
+  if (ldc < (m > 1 ? m : 1)) return -14;
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  DEV_TRY(h, hipSetDevice(h->device));
+  GemmArgs g{};
+  g.m = m; g.n = n; g.k = k; g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.alpha = alpha; g.beta = beta; g.ta = ta; g.tb = tb;
+  DEV_TRY(h, gemm_launch(g, s));
+  DEV_TRY(h, hipStreamSynchronize(s));
+  return HSDM_OK;
+}
+
+int hsdm_cholesky_inverse(hsdm_handle h, int n, const double* S, int lds, double* L, int ldl,
+                          double* Linv, int ldli, void* stream) {
+  if (!h) return -1;
+  if (n < 1) return -2;
+  if (!S) return -3;
+  if (bad_ld(lds, n)) return -4;
+  if (!L) return -5;
+  if (bad_ld(ldl, n)) return -6;
+  if (!Linv) return -7;
+  if (bad_ld(ldli, n)) return -8;
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  DEV_TRY(h, hipSetDevice(h->device));
+  int r = ensure_ws(h, n);
+  if (r) return r;
+  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  DEV_TRY(h, hipGetLastError());
+  DEV_TRY(h, dev_copy(S, lds, L, ldl, n, n, s));
+  DEV_TRY(h, dev_fill(Linv, ldli, n, n, 0.0, s));
+  DEV_TRY(h, chol_inv(n, L, ldl, Linv, ldli, h->Abuf, n, h->st, s));
+  return finish(h, s);
+}
+
+int hsdm_standard_form(hsdm_handle h, int n, const double* H, int ldh, const double* Linv,
+                       int ldli, double* A, int lda, void* stream) {
+  if (!h) return -1;
+  if (n < 1) return -2;
+  if (!H) return -3;
+  if (bad_ld(ldh, n)) return -4;
+  if (!Linv) return -5;
+  if (bad_ld(ldli, n)) return -6;
+  if (!A) return -7;
+  if (bad_ld(lda, n)) return -8;
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  DEV_TRY(h, hipSetDevice(h->device));
+  int r = ensure_ws(h, n);
+  if (r) return r;
+  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  DEV_TRY(h, hipGetLastError());
+  r = standard_form(h, n, H, ldh, Linv, ldli, A, lda, s);
+  if (r) return r;
+  return finish(h, s);
+}
+
+int hsdm_tridiagonalize(hsdm_handle h, int n, const double* A, int lda, double* d, double* e,
+                        double* Q, int ldq, void* stream) {
+  if (!h) return -1;
+  if (n < 1) return -2;
+  if (!A) return -3;
+  if (bad_ld(lda, n)) return -4;
+  if (!d) return -5;
+  if (n > 1 && !e) return -6;
+  if (Q && bad_ld(ldq, n)) return -8;
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  DEV_TRY(h, hipSetDevice(h->device));
+  int r = ensure_ws(h, n);
+  if (r) return r;
+  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  DEV_TRY(h, hipGetLastError());
+  DEV_TRY(h, dev_copy(A, lda, h->Abuf, n, n, n, s));
+  r = reduce(h, n, s, 0);
+  if (r) return r;
+  hipLaunchKernelGGL(copy_vec_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, h->dvec, d, n);
+  DEV_TRY(h, hipGetLastError());
+  if (n > 1) {
+    hipLaunchKernelGGL(copy_vec_kernel, dim3(ceil_div(n - 1, 256)), dim3(256), 0, s, h->evec, e,
+                       n - 1);
+    DEV_TRY(h, hipGetLastError());
+  }
+  if (Q) {
+    const long tot = (long)n * n;
+    hipLaunchKernelGGL(eye_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Q,
+                       (long)ldq, n);
+    DEV_TRY(h, hipGetLastError());
+    DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->T2, h->d_goff, s));
+    DEV_TRY(h, bt2_apply(h->lay, h->V2, h->T2, h->d_goff, Q, ldq, n, nullptr, s));
+    DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, Q, ldq, n, nullptr, h->bt1_scr, s));
+  }
+  return finish(h, s);
+}
+
+int hsdm_tridiag_eigh(hsdm_handle h, int n, const double* d, const double* e, double* w, double* Z,
+                      int ldz, void* stream) {
+  if (!h) return -1;
+  if (n < 1) return -2;
+  if (!d) return -3;
+  if (n > 1 && !e) return -4;
+  if (!w) return -5;
+  if (!Z) return -6;
+  if (bad_ld(ldz, n)) return -7;
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  DEV_TRY(h, hipSetDevice(h->device));
+  int r = ensure_ws(h, n);
+  if (r) return r;
+  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  DEV_TRY(h, hipGetLastError());
+  DEV_TRY(h, stedc_run(h->plan, d, e, w, Z, ldz, h->dc_scr, h->dc_iscr, nullptr, nullptr, nullptr,
+                       h->st, s));
+  return finish(h, s);
+}
+
+int hsdm_occupations(hsdm_handle h, int n, const double* eval, double ne, double kT,
+                     double deg_tol, double* f, double* mu, double* band_energy, int* n_occ,
+                     void* stream) {
+  if (!h) return -1;
+  if (n < 1) return -2;
+  if (!eval) return -3;
+  if (!(ne >= 0.0) || ne > h->fmax * n) return -4;
+  if (!(kT >= 0.0) || !std::isfinite(kT)) return -5;
+  if (!(deg_tol >= 0.0)) return -6;
+  if (!f) return -7;
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  DEV_TRY(h, hipSetDevice(h->device));
+  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  DEV_TRY(h, hipGetLastError());
+  DEV_TRY(h, occupations_launch(n, eval, h->fmax, ne, kT, deg_tol, nullptr, h->fcut_rel * h->fmax,
+                                f, h->occ, h->st, s));
+  int r = finish(h, s);
+  if (mu) *mu = h->host->occ.mu;
+  if (band_energy) *band_energy = h->host->occ.band_energy;
+  if (n_occ) *n_occ = h->host->occ.m;
+  return r;
+}
+
+int hsdm_density(hsdm_handle h, int n, int m, const double* C, int ldc, const double* f,
+                 const double* eval, double* D, int ldd, double* E, int lde, void* stream) {
+  if (!h) return -1;
+  if (n < 1) return -2;
+  if (m < 0 || m > n) return -3;
+  if (m > 0 && !C) return -4;
+  if (bad_ld(ldc, n)) return -5;
+  if (m > 0 && !f) return -6;
+  if (m > 0 && E && !eval) return -7;
+  if (!D) return -8;
+  if (bad_ld(ldd, n)) return -9;
+  if (E && bad_ld(lde, n)) return -11;
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  DEV_TRY(h, hipSetDevice(h->device));
+  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  DEV_TRY(h, hipGetLastError());
+  DEV_TRY(h, density_launch(n, m, C, ldc, f, eval, D, ldd, E, lde, nullptr, s));
+  return finish(h, s);
+}
+
+static int check_hs(hsdm_handle h, int n, const double* H, int ldh, const double* S, int lds) {
+  if (!h) return -1;
+  if (n < 1) return -2;
+  if (!H) return -3;
+  if (bad_ld(ldh, n)) return -4;
+  if (!S) return -5;
+  if (bad_ld(lds, n)) return -6;
+  return 0;
+}
+
+int hsdm_solve_ev_real(hsdm_handle h, int n, const double* H, int ldh, const double* S, int lds,
+                       double* eval, double* C, int ldc, void* stream) {
+  int a = check_hs(h, n, H, ldh, S, lds);
+  if (a) return a;
+  if (!eval) return -7;
+  if (!C) return -8;
+  if (bad_ld(ldc, n)) return -9;
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  DEV_TRY(h, hipSetDevice(h->device));
+  int r = ensure_ws(h, n);
+  if (r) return r;
+  for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
+  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  DEV_TRY(h, hipGetLastError());
+  mark(h, 0, s);
+  if ((r = factor_s(h, n, S, lds, s))) return r;
+  mark(h, 1, s);
+  if ((r = standard_form(h, n, H, ldh, h->Linv, n, h->Abuf, n, s))) return r;
+  mark(h, 2, s);
+  if ((r = reduce(h, n, s, 3))) return r;
+  mark(h, 4, s);
+  DEV_TRY(h, stedc_run(h->plan, h->dvec, h->evec, eval, h->Zbuf, n, h->dc_scr, h->dc_iscr,
+                       nullptr, nullptr, nullptr, h->st, s));
+  mark(h, 5, s);
+  DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->T2, h->d_goff, s));
+  DEV_TRY(h, bt2_apply(h->lay, h->V2, h->T2, h->d_goff, h->Zbuf, n, n, nullptr, s));
+  mark(h, 6, s);
+  DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, n, nullptr, h->bt1_scr, s));
+  mark(h, 7, s);
+  GemmArgs g{};
+  g.m = n; g.n = n; g.k = n; g.A = h->Linv; g.lda = n; g.B = h->Zbuf; g.ldb = n; g.C = C;
+  g.ldc = ldc; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.flags = GF_KA_UPPER;
+  DEV_TRY(h, gemm_launch(g, s));
+  mark(h, 8, s);
+  mark(h, 9, s);
+  return finish(h, s);
+}
+
+int hsdm_solve_dm_real(hsdm_handle h, int n, const double* H, int ldh, const double* S, int lds,
+                       double ne, double kT, double* D, int ldd, double* E, int lde, double* eval,
+                       double* band_energy, double* mu, void* stream) {
+  int a = check_hs(h, n, H, ldh, S, lds);
+  if (a) return a;
+  if (!(ne >= 0.0) || !std::isfinite(ne) || ne > h->fmax * n) return -7;
+  if (!(kT >= 0.0) || !std::isfinite(kT)) return -8;
+  if (!D) return -9;
+  if (bad_ld(ldd, n)) return -10;
+  if (E && bad_ld(lde, n)) return -12;
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  DEV_TRY(h, hipSetDevice(h->device));
+  int r = ensure_ws(h, n);
+  if (r) return r;
+  for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
+  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  DEV_TRY(h, hipGetLastError());
+  mark(h, 0, s);
+  if ((r = factor_s(h, n, S, lds, s))) return r;
+  mark(h, 1, s);
+  if (h->deg_tol < 0.0) DEV_TRY(h, dev_norm1_sym(H, ldh, n, h->colsum, h->hnorm, s));
+  if ((r = standard_form(h, n, H, ldh, h->Linv, n, h->Abuf, n, s))) return r;
+  mark(h, 2, s);
+  if ((r = reduce(h, n, s, 3))) return r;
+  mark(h, 4, s);
+  OccHook hook{h, n, ne, kT};
+  const int* m_dev = &h->occ->m;
+  DEV_TRY(h, stedc_run(h->plan, h->dvec, h->evec, h->lam, h->Zbuf, n, h->dc_scr, h->dc_iscr,
+                       m_dev, occ_hook, &hook, h->st, s));
+  mark(h, 5, s);
+  DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->T2, h->d_goff, s));
+  DEV_TRY(h, bt2_apply(h->lay, h->V2, h->T2, h->d_goff, h->Zbuf, n, n, m_dev, s));
+  mark(h, 6, s);
+  DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, n, m_dev, h->bt1_scr, s));
+  mark(h, 7, s);
+  GemmArgs g{};
+  g.m = n; g.n = n; g.k = n; g.A = h->Linv; g.lda = n; g.B = h->Zbuf; g.ldb = n; g.C = h->Cbuf;
+  g.ldc = n; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.flags = GF_KA_UPPER;
+  g.ndev = m_dev;
+  DEV_TRY(h, gemm_launch(g, s));
+  mark(h, 8, s);
+  DEV_TRY(h, density_launch(n, n, h->Cbuf, n, h->fvec, h->lam, D, ldd, E, lde, m_dev, s));
+  mark(h, 9, s);
+  if (eval) {
+    hipLaunchKernelGGL(copy_vec_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, h->lam, eval, n);
+    DEV_TRY(h, hipGetLastError());
+  }
+  r = finish(h, s);
+  if (mu) *mu = h->host->occ.mu;
+  if (band_energy) *band_energy = h->host->occ.band_energy;
+  return r;
+}
+
+}  // extern "C"

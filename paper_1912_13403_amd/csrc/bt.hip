@@ -1,0 +1,236 @@
+// Back-transformation of eigenvectors through the two reduction stages.
+//
+// Stage 2 (bulge chasing): the reflectors H_{s,t} of B consecutive sweeps
+// that share the task index t are combined into one block reflector
+// G = I - V T V^T (V: 2B x B parallelogram, T: B x B upper triangular), so
+// that applying them is three small matrix products on the FP64 matrix
+// cores.  Ordering: Q2 Z = H_{0,0} H_{0,1} ... Z must apply later sweeps
+// first; group (b, t) (sweep block b) overlaps groups (b+1, t-2 .. t) and
+// (b, t-1), so all groups with equal  t + 2 (nblk - 1 - b)  are independent
+// and one launch per such level applies them, each workgroup one group to
+// one slab of 64 columns of Z.
+//
+// Stage 1 (panels): Z <- (I - V_p T_p V_p^T) Z for p from the last panel to
+// the first, as three GEMMs per panel (the tall V_p^T Z with split-K).
+#include "hsdm_internal.h"
+#include "hsdm_phases.h"
+
+namespace {
+
+constexpr int B = 32;
+constexpr int H2 = 2 * B;  // rows of a group
+constexpr int SW = 64;     // columns of Z per workgroup
+
+// T factor of every group: T_jj = tau_j, T(0:j, j) = -tau_j T(0:j,0:j) V^T v_j
+__global__ __launch_bounds__(256) void group_t_kernel(const double* V2, const double* tau2,
+                                                      double* T2) {
+  const long gi = blockIdx.x;
+  const double* V = V2 + gi * H2 * B;
+  const double* tau = tau2 + gi * B;
+  __shared__ double Vs[H2][B + 1];
+  __shared__ double Gm[B][B + 1];
+  __shared__ double Tl[B][B + 1];
+  const int t = threadIdx.x;
+  for (int e = t; e < H2 * B; e += 256) Vs[e % H2][e / H2] = V[e];
+  __syncthreads();
+  for (int e = t; e < B * B; e += 256) {
+    const int a = e % B, b = e / B;
+    double s = 0.0;
+    if (a < b)
+      for (int r = 0; r < H2; r++) s += Vs[r][a] * Vs[r][b];
+    Gm[a][b] = s;
+    Tl[a][b] = 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < B; j++) {
+    const double tj = tau[j];
+    if (t < j) {
+      double s = 0.0;
+      for (int k = t; k < j; k++) s += Tl[t][k] * Gm[k][j];
+      Tl[t][j] = -tj * s;
+    }
+    if (t == j) Tl[j][j] = tj;
+    __syncthreads();
+  }
+  double* T = T2 + gi * B * B;
+  for (int e = t; e < B * B; e += 256) T[e] = Tl[e % B][e / B];
+}
+
+// Apply the groups of one level to Z.
+__global__ __launch_bounds__(256) void group_apply_kernel(int n, int nblk, int level, int sb_lo,
+                                                          const double* V2, const double* T2,
+                                                          const long* goff, double* Z, long ldz,
+                                                          int m_host, const int* m_dev) {
+  const int sb = sb_lo + blockIdx.x;
+  const int t = level - 2 * (nblk - 1 - sb);
+  const int tg = (n - 1 - sb * B + B - 1) / B;
+  if (t < 0 || t >= tg) return;
+  const int m = m_dev ? *m_dev : m_host;
+  const int c0 = blockIdx.y * SW;
+  if (c0 >= m) return;
+  const int nc = min(SW, m - c0);
+  const int rb = sb * B + 1 + t * B;
+  const int hh = min(H2, n - rb);
+  const long gi = goff[sb] + t;
+  const double* V = V2 + gi * H2 * B;
+  const double* T = T2 + gi * B * B;
+
+  __shared__ double Vs[H2][B + 1];
+  __shared__ double Ts[B][B + 1];
+  __shared__ double Zs[H2][SW + 1];
+  __shared__ double Ws[B][SW + 1];
+  __shared__ double W2s[B][SW + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < H2 * B; e += 256) Vs[e % H2][e / H2] = V[e];
+  for (int e = tid; e < B * B; e += 256) Ts[e % B][e / B] = T[e];
+  for (int e = tid; e < H2 * SW; e += 256) {
+    const int r = e % H2, c = e / H2;
+    Zs[r][c] = (r < hh && c < nc) ? Z[rb + r + (long)(c0 + c) * ldz] : 0.0;
+  }
+  __syncthreads();
+  const int l16 = lane & 15, l4 = lane >> 4;
+  // W = V^T Zs  (B x SW): wave w -> row block (w & 1), column blocks 2*(w>>1) + {0,1}
+  {
+    const int a = w & 1;
+    dbl4 acc[2] = {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}};
+    for (int k0 = 0; k0 < H2; k0 += 4) {
+      const double fa = Vs[k0 + l4][16 * a + l16];
+#pragma unroll
+      for (int q = 0; q < 2; q++) {
+        const int b = 2 * (w >> 1) + q;
+        const double fb = Zs[k0 + l4][16 * b + l16];
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb, acc[q], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      const int b = 2 * (w >> 1) + q;
+#pragma unroll
+      for (int r = 0; r < 4; r++) Ws[16 * a + l4 + 4 * r][16 * b + l16] = acc[q][r];
+    }
+  }
+  __syncthreads();
+  // W2 = T W (T upper triangular)
+  {
+    const int a = w & 1;
+    dbl4 acc[2] = {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}};
+    for (int k0 = 16 * a; k0 < B; k0 += 4) {
+      const double fa = Ts[16 * a + l16][k0 + l4];
+#pragma unroll
+      for (int q = 0; q < 2; q++) {
+        const int b = 2 * (w >> 1) + q;
+        const double fb = Ws[k0 + l4][16 * b + l16];
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb, acc[q], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      const int b = 2 * (w >> 1) + q;
+#pragma unroll
+      for (int r = 0; r < 4; r++) W2s[16 * a + l4 + 4 * r][16 * b + l16] = acc[q][r];
+    }
+  }
+  __syncthreads();
+  // Zs - V W2: wave w -> rows 16w .. 16w+15, all 4 column blocks; written to Z
+  {
+    dbl4 acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; b++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) acc[b][r] = Zs[16 * w + l4 + 4 * r][16 * b + l16];
+    for (int k0 = 0; k0 < B; k0 += 4) {
+      const double fa = -Vs[16 * w + l16][k0 + l4];
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        const double fb = W2s[k0 + l4][16 * b + l16];
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb, acc[b], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+      const int c = 16 * b + l16;
+      if (c >= nc) continue;
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int row = 16 * w + l4 + 4 * r;
+        if (row < hh) Z[rb + row + (long)(c0 + c) * ldz] = acc[b][r];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t bt2_prepare(const Sb2stLayout& L, const double* V2, const double* tau2, double* T2,
+                       const long* d_goff, hipStream_t s) {
+  (void)d_goff;
+  if (L.ngroups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(group_t_kernel, dim3((unsigned)L.ngroups), dim3(256), 0, s, V2, tau2, T2);
+  return hipGetLastError();
+}
+
+hipError_t bt2_apply(const Sb2stLayout& L, const double* V2, const double* T2, const long* d_goff,
+                     double* Z, long ldz, int m, const int* m_dev, hipStream_t s) {
+  if (L.ngroups <= 0 || m <= 0) return hipSuccess;
+  const int n = L.n, nblk = L.nblk;
+  const int nslab = ceil_div(m, SW);
+  auto tg = [&](int sb) { return (n - 1 - sb * B + B - 1) / B; };
+  const int lmax = (tg(0) - 1) + 2 * (nblk - 1);
+  for (int level = 0; level <= lmax; level++) {
+    int lo = nblk - 1 - level / 2;
+    if (lo < 0) lo = 0;
+    int hi = -1;  // largest sb with a valid task at this level
+    for (int sb = nblk - 1; sb >= lo; sb--) {
+      const int t = level - 2 * (nblk - 1 - sb);
+      if (t >= 0 && t < tg(sb)) {
+        hi = sb;
+        break;
+      }
+    }
+    if (hi < 0) continue;
+    int first = hi;
+    while (first - 1 >= lo) {
+      const int t = level - 2 * (nblk - 1 - (first - 1));
+      if (t < 0 || t >= tg(first - 1)) break;
+      first--;
+    }
+    hipLaunchKernelGGL(group_apply_kernel, dim3(hi - first + 1, nslab), dim3(256), 0, s, n, nblk,
+                       level, first, V2, T2, d_goff, Z, ldz, m, m_dev);
+    HSDM_TRY(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+size_t bt1_scratch_doubles(int n, int B_, int m) {
+  const int nsplit = ceil_div(n, 1024) + 1;
+  return (size_t)B_ * m * (2 + nsplit) + 64;
+}
+
+hipError_t bt1_apply(int n, int B_, const double* Vst, long ldv, const double* T1, double* Z,
+                     long ldz, int m, const int* m_dev, double* scratch, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  double* W = scratch;
+  double* W2 = W + (size_t)B_ * m;
+  double* part = W2 + (size_t)B_ * m;
+  const int npanel = (n > B_) ? ceil_div(n - 1, B_) : 0;
+  for (int p = npanel - 1; p >= 0; p--) {
+    const int c0 = p * B_, r0 = c0 + B_, h = n - r0;
+    if (h <= 0) continue;
+    const double* Vp = Vst + r0 + (long)c0 * ldv;
+    const double* Tp = T1 + (size_t)p * B_ * B_;
+    double* Zp = Z + r0;
+    GemmArgs g{};
+    g.m = B_; g.n = m; g.k = h; g.A = Vp; g.lda = ldv; g.B = Zp; g.ldb = ldz; g.C = W; g.ldc = B_;
+    g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.ndev = m_dev;
+    HSDM_TRY(gemm_splitk_launch(g, 1024, part, s));
+    g = GemmArgs{};
+    g.m = B_; g.n = m; g.k = B_; g.A = Tp; g.lda = B_; g.B = W; g.ldb = B_; g.C = W2; g.ldc = B_;
+    g.alpha = 1.0; g.beta = 0.0; g.flags = GF_KA_UPPER; g.ndev = m_dev;
+    HSDM_TRY(gemm_launch(g, s));
+    g = GemmArgs{};
+    g.m = h; g.n = m; g.k = B_; g.A = Vp; g.lda = ldv; g.B = W2; g.ldb = B_; g.C = Zp; g.ldc = ldz;
+    g.alpha = -1.0; g.beta = 1.0; g.ndev = m_dev;
+    HSDM_TRY(gemm_launch(g, s));
+  }
+  return hipSuccess;
+}

@@ -1,0 +1,125 @@
+// Cholesky factorization S = L L^T together with L^{-1}.
+//
+// The overlap matrix of Eq. (3) is SPD; its factor is what the paper's
+// benchmark section calls the once-per-geometry step.  The path keeps the
+// explicit inverse L^{-1}: every later use of the factor (the standard form
+// L^{-1} H L^{-T} and the back-transformation C = L^{-T} Y) then becomes a
+// plain GEMM on the matrix cores, and L^{-1} is cached with S.
+//
+// Recursion on [[L11, 0], [L21, L22]]:
+//   L11, L11^{-1}      <- recurse on S11
+//   L21 = S21 L11^{-T} (GEMM, triangular B)
+//   S22 <- S22 - L21 L21^T (GEMM, lower tiles)
+//   L22, L22^{-1}      <- recurse on S22
+//   (L^{-1})21 = -L22^{-1} L21 L11^{-1} (two GEMMs, triangular operands)
+// Leaves of at most 64 columns are factored and inverted by one wavefront in
+// LDS.  A non-positive pivot is reported through the device status word with
+// its 1-based column.
+#include "hsdm_internal.h"
+#include "hsdm_util.h"
+
+namespace {
+
+constexpr int LEAF = 64;
+
+__global__ __launch_bounds__(64) void chol_leaf_kernel(int nb, double* A, long lda, double* Li,
+                                                       long ldi, DevStatusWord* st, int col0) {
+  __shared__ double L[LEAF][LEAF + 1];
+  __shared__ double X[LEAF][LEAF + 1];
+  const int t = threadIdx.x;  // thread t owns row t
+  for (int j = 0; j < nb; j++) L[t][j] = (t < nb && t >= j) ? A[t + (long)j * lda] : 0.0;
+  for (int j = nb; j < LEAF; j++) L[t][j] = 0.0;
+  __syncthreads();
+  bool ok = true;
+  for (int k = 0; k < nb; k++) {
+    const double piv = L[k][k];
+    if (!(piv > 0.0)) {
+      if (t == 0) dev_set_status(st, DS_NOT_SPD, col0 + k + 1);
+      ok = false;
+      break;
+    }
+    const double lkk = sqrt(piv);
+    __syncthreads();
+    if (t == k) L[k][k] = lkk;
+    if (t > k && t < nb) L[t][k] = L[t][k] / lkk;
+    __syncthreads();
+    if (t > k && t < nb) {
+      const double ltk = L[t][k];
+      for (int j = k + 1; j <= t; j++) L[t][j] -= ltk * L[j][k];
+    }
+    __syncthreads();
+  }
+  // inverse of the unit-free lower factor: thread c solves L x = e_c
+  if (ok && t < nb) {
+    const int c = t;
+    X[c][c] = 1.0 / L[c][c];
+    for (int i = c + 1; i < nb; i++) {
+      double s = 0.0;
+      for (int k = c; k < i; k++) s += L[i][k] * X[k][c];
+      X[i][c] = -s / L[i][i];
+    }
+  }
+  __syncthreads();
+  if (t < nb) {
+    for (int j = 0; j < nb; j++) {
+      const bool low = t >= j;
+      A[t + (long)j * lda] = low ? L[t][j] : 0.0;
+      Li[t + (long)j * ldi] = (low && ok) ? X[t][j] : (low ? NAN : 0.0);
+    }
+  }
+}
+
+hipError_t rec(int n, double* A, long lda, double* Li, long ldi, double* T, long ldt,
+               DevStatusWord* st, int col0, hipStream_t s) {
+  if (n <= LEAF) {
+    hipLaunchKernelGGL(chol_leaf_kernel, dim3(1), dim3(64), 0, s, n, A, lda, Li, ldi, st, col0);
+    return hipGetLastError();
+  }
+  int n1 = ((n / 2) / LEAF) * LEAF;
+  if (n1 == 0) n1 = LEAF;
+  const int n2 = n - n1;
+  double* A21 = A + n1;
+  double* A22 = A + n1 + (long)n1 * lda;
+  double* Li21 = Li + n1;
+  double* Li22 = Li + n1 + (long)n1 * ldi;
+
+  HSDM_TRY(rec(n1, A, lda, Li, ldi, T, ldt, st, col0, s));
+  // T = S21 * L11^{-T}
+  GemmArgs g{};
+  g.m = n2; g.n = n1; g.k = n1;
+  g.A = A21; g.lda = lda; g.B = Li; g.ldb = ldi; g.C = T; g.ldc = ldt;
+  g.alpha = 1.0; g.beta = 0.0; g.ta = 0; g.tb = 1; g.flags = GF_KB_UPPER;
+  HSDM_TRY(gemm_launch(g, s));
+  HSDM_TRY(dev_copy(T, ldt, A21, lda, n2, n1, s));
+  HSDM_TRY(dev_fill(A + (long)n1 * lda, lda, n1, n2, 0.0, s));  // strict upper block of L
+  // S22 -= L21 L21^T (lower)
+  g = GemmArgs{};
+  g.m = n2; g.n = n2; g.k = n1;
+  g.A = A21; g.lda = lda; g.B = A21; g.ldb = lda; g.C = A22; g.ldc = lda;
+  g.alpha = -1.0; g.beta = 1.0; g.ta = 0; g.tb = 1;
+  g.flags = GF_C_LOWER_TILES | GF_C_LOWER_ONLY;
+  HSDM_TRY(gemm_launch(g, s));
+  HSDM_TRY(rec(n2, A22, lda, Li22, ldi, T, ldt, st, col0 + n1, s));
+  // T = L21 * L11^{-1}
+  g = GemmArgs{};
+  g.m = n2; g.n = n1; g.k = n1;
+  g.A = A21; g.lda = lda; g.B = Li; g.ldb = ldi; g.C = T; g.ldc = ldt;
+  g.alpha = 1.0; g.beta = 0.0; g.ta = 0; g.tb = 0; g.flags = GF_KB_LOWER;
+  HSDM_TRY(gemm_launch(g, s));
+  // (L^{-1})21 = -L22^{-1} * T
+  g = GemmArgs{};
+  g.m = n2; g.n = n1; g.k = n2;
+  g.A = Li22; g.lda = ldi; g.B = T; g.ldb = ldt; g.C = Li21; g.ldc = ldi;
+  g.alpha = -1.0; g.beta = 0.0; g.ta = 0; g.tb = 0; g.flags = GF_KA_LOWER;
+  HSDM_TRY(gemm_launch(g, s));
+  HSDM_TRY(dev_fill(Li + (long)n1 * ldi, ldi, n1, n2, 0.0, s));  // strict upper block
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t chol_inv(int n, double* A, long lda, double* Li, long ldi, double* T, long ldt,
+                    DevStatusWord* st, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  return rec(n, A, lda, Li, ldi, T, ldt, st, 0, s);
+}

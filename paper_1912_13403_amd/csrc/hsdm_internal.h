@@ -1,0 +1,85 @@
+// Internal declarations shared by the HIP sources of libhsdm (not installed).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+#define HSDM_DEV __device__ __forceinline__
+
+// ---------------------------------------------------------------------------
+// GEMM: C = alpha * op(A) * op(B) + beta * C, FP64, column-major.
+// op(A) is m x k, op(B) is k x n.
+enum GemmFlags {
+  GF_C_LOWER_TILES = 1,   // skip output tiles that lie entirely above the diagonal
+  GF_C_LOWER_ONLY = 2,    // never write elements with row < col
+  GF_KA_LOWER = 4,        // op(A) lower triangular: row i only needs k <= i
+  GF_KA_UPPER = 8,        // op(A) upper triangular: row i only needs k >= i
+  GF_KB_UPPER = 16,       // op(B) upper triangular: column j only needs k <= j
+  GF_KB_LOWER = 32,       // op(B) lower triangular: column j only needs k >= j
+  GF_A_SYM_LOWER = 64,    // A symmetric, only its lower triangle is read (m == k)
+};
+
+struct GemmArgs {
+  int m, n, k;
+  const double* A; long lda;
+  const double* B; long ldb;
+  double* C; long ldc;
+  double alpha, beta;
+  int ta, tb;             // 0: as stored, 1: transposed
+  int flags;
+  const int* acol;        // optional: op(A)[:, kk] = A[:, acol[kk]] (ta == 0)
+  const int* ccol;        // optional: column j of the product goes to C[:, ccol[j]]
+  const int* ndev;        // optional: device-side column count, n is its upper bound
+};
+
+// One GEMM of a device-side batch.  Sizes may be written by an earlier kernel.
+struct GemmDesc {
+  int m, n, k;
+  int pad;
+  const double* A; long lda;
+  const double* B; long ldb;
+  double* C; long ldc;
+  const int* acol;
+  const int* ccol;
+};
+
+hipError_t gemm_launch(const GemmArgs& g, hipStream_t s);
+// Split-K: K cut into slices of kchunk; part holds ceil(k/kchunk) * m * n
+// partial products, summed in slice order (reproducible), then C = sum + beta C.
+hipError_t gemm_splitk_launch(const GemmArgs& g, int kchunk, double* part, hipStream_t s);
+// Batched launch: every descriptor uses the same alpha, beta, ta, tb, flags;
+// max_m, max_n bound the sizes any descriptor can take.
+hipError_t gemm_batched_launch(const GemmDesc* d_desc, int count, int max_m, int max_n,
+                               double alpha, double beta, int ta, int tb, int flags,
+                               hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Device status word shared by all kernels of a solve (first error wins).
+enum DevStatus {
+  DS_OK = 0,
+  DS_NOT_SPD = 1,       // detail: failing column (1-based)
+  DS_NO_CONVERGE = 2,   // detail: which phase
+  DS_MU_FAIL = 3,
+  DS_SYNC_TIMEOUT = 4,  // a bounded inter-workgroup wait ran out
+};
+
+struct DevStatusWord {
+  int code;
+  int detail;
+};
+
+HSDM_DEV void dev_set_status(DevStatusWord* st, int code, int detail) {
+  if (atomicCAS(&st->code, 0, code) == 0) st->detail = detail;
+}
+
+// Launch-error helper.
+#define HSDM_TRY(x)                          \
+  do {                                       \
+    hipError_t _e = (x);                     \
+    if (_e != hipSuccess) return _e;         \
+  } while (0)
+
+inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }

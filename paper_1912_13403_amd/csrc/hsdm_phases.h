@@ -1,0 +1,56 @@
+// Host launchers of the reduction, tridiagonal and back-transformation phases.
+#pragma once
+#include "hsdm_internal.h"
+
+// sy2sb.hip -- full -> band (half-bandwidth B).  A (lower triangle) is
+// overwritten; Vst receives the explicit panel reflectors (n x n, lower
+// trapezoid), tau1 the scalars, T1 one B x B triangular factor per panel, AB
+// the band in band storage (ldab >= 2B rows per column, rows > B zeroed).
+size_t sy2sb_scratch_doubles(int n, int B);
+hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, double* tau1,
+                     double* T1, double* AB, int ldab, double* scratch, unsigned* bar,
+                     DevStatusWord* st, hipStream_t s);
+
+// sb2st.hip -- band -> tridiagonal by bulge chasing.  AB is overwritten;
+// d (n) and e (n-1) receive the tridiagonal; the stage-2 reflectors are
+// stored group-wise in V2 (see sb2st_layout) with their scalars in tau2.
+struct Sb2stLayout {
+  int n, B;
+  int nsweep;       // sweeps that create reflectors
+  int nblk;         // sweep blocks of B sweeps
+  int tmax;         // max tasks per sweep
+  long ngroups;     // groups (sweep block, task)
+  long v2_doubles;  // size of V2 (2B x B per group)
+};
+Sb2stLayout sb2st_layout(int n, int B);
+// group offset table: first group index of each sweep block (nblk + 1 entries)
+void sb2st_group_offsets(const Sb2stLayout& L, long* offs);
+hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, double* e, double* V2,
+                     double* tau2, const long* d_goff, int* progress, DevStatusWord* st,
+                     hipStream_t s);
+
+// bt.hip -- back-transformations.
+// Z (n x m) <- Q2 Z, the stage-2 reflectors applied group by group.
+hipError_t bt2_prepare(const Sb2stLayout& L, const double* V2, const double* tau2, double* T2,
+                       const long* d_goff, hipStream_t s);
+hipError_t bt2_apply(const Sb2stLayout& L, const double* V2, const double* T2, const long* d_goff,
+                     double* Z, long ldz, int m, const int* m_dev, hipStream_t s);
+// Z (n x m) <- Q1 Z, the stage-1 panel reflectors (I - V T V^T), last panel first.
+size_t bt1_scratch_doubles(int n, int B, int m);
+hipError_t bt1_apply(int n, int B, const double* Vst, long ldv, const double* T1, double* Z,
+                     long ldz, int m, const int* m_dev, double* scratch, hipStream_t s);
+
+// stedc.hip -- all eigenvalues (ascending) and eigenvectors of a symmetric
+// tridiagonal by divide and conquer.  When m_dev is given, only the first
+// *m_dev eigenvectors of the final merge are formed (the occupations are
+// evaluated between the final eigenvalues and the final vectors through the
+// callback).
+struct StedcPlan;
+StedcPlan* stedc_plan_create(int n);
+void stedc_plan_destroy(StedcPlan* p);
+size_t stedc_scratch_doubles(int n);
+size_t stedc_iscratch_ints(int n);
+typedef hipError_t (*StedcEigvalHook)(void* ctx, const double* lam, hipStream_t s);
+hipError_t stedc_run(StedcPlan* p, const double* d, const double* e, double* lam, double* Z,
+                     long ldz, double* scratch, int* iscratch, const int* m_dev,
+                     StedcEigvalHook hook, void* hook_ctx, DevStatusWord* st, hipStream_t s);

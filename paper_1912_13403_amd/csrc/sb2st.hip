@@ -1,0 +1,283 @@
+// Stage 2 of the two-stage tridiagonalization: band (half-bandwidth B) ->
+// symmetric tridiagonal by bulge chasing.
+//
+// Sweep s removes column s below the subdiagonal.  Its task t owns the rows
+// R_t = [s+1+tB, s+(t+1)B]:
+//   - t = 0 first builds the reflector from column s (rows R_0);
+//   - the current reflector is applied on both sides of the diagonal block
+//     R_t x R_t and from the right to the block R_{t+1} x R_t below it, which
+//     fills that block (the bulge);
+//   - the next reflector is built from the first column of that block and
+//     applied from the left to the rest of it; it is handed to task t+1.
+// Task (s, t) touches only what tasks (s-1, t) and (s-1, t+1) wrote, so sweep
+// s may run task t once sweep s-1 has finished task t+1: sweeps proceed as a
+// pipeline, each two tasks behind its predecessor.
+//
+// One wavefront runs one sweep at a time (64 lanes; the B x B blocks live in
+// LDS); workgroups of 4 wavefronts are launched cooperatively so that every
+// wavefront is resident.  Progress counters in global memory carry the
+// dependencies with agent-scope release/acquire; every wait is bounded and
+// reports through the status word if it runs out.
+//
+// Storage: lower band storage AB[(r-c) + c*ldab], ldab = 2B (offsets up to
+// 2B-1 hold the bulge).  Each reflector H_{s,t} (v, tau; v[0] = 1) is stored
+// for the back-transformation in group (s / B, t): a 2B x B block whose
+// column s % B holds v at rows (s % B) .. (s % B) + len - 1.
+#include "hsdm_internal.h"
+#include "hsdm_phases.h"
+
+namespace {
+
+constexpr int WPB = 4;  // wavefronts per workgroup
+constexpr int DONE = 1 << 30;
+
+HSDM_DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+HSDM_DEV double wsum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+HSDM_DEV double hsum(double v) { return v + __shfl_xor(v, 32, 64); }
+
+HSDM_DEV void wait_ge(int* p, int target, DevStatusWord* st) {
+  if ((threadIdx.x & 63) == 0) {
+    long spins = 0;
+    while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      ++spins;
+      if (spins > (1L << 27) ||
+          ((spins & 4095) == 0 &&
+           __hip_atomic_load(&st->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+        dev_set_status(st, DS_SYNC_TIMEOUT, 2);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  wave_sync();
+}
+
+HSDM_DEV void publish(int* p, int v) {
+  wave_sync();
+  if ((threadIdx.x & 63) == 0) __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int B>
+__global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, double* AB, int ldab,
+                                                         double* V2, double* tau2,
+                                                         const long* goff, int* progress,
+                                                         DevStatusWord* st) {
+  static_assert(2 * B == 64, "one lane per row of a 2B-row group column");
+  __shared__ double Dl_all[WPB][B][B + 1];
+  __shared__ double Bl_all[WPB][B][B + 1];
+  __shared__ double vc_all[WPB][B], vn_all[WPB][B], wv_all[WPB][B];
+  const int lane = threadIdx.x & 63, wv_id = threadIdx.x >> 6;
+  double(*Dl)[B + 1] = Dl_all[wv_id];
+  double(*Bl)[B + 1] = Bl_all[wv_id];
+  double* vc = vc_all[wv_id];
+  double* vn = vn_all[wv_id];
+  double* wk = wv_all[wv_id];
+  const int gw = blockIdx.x * WPB + wv_id, TW = gridDim.x * WPB;
+  const int li = lane % B, hf = lane / B;  // row index and column half (B/2 columns each)
+  constexpr int HB = B / 2;
+
+  for (int s = gw; s < nsweep; s += TW) {
+    const int ntask = (n - 1 - s + B - 1) / B;
+    double tau = 0.0;
+    for (int t = 0; t < ntask; t++) {
+      if (s > 0) wait_ge(progress + s - 1, t + 2, st);
+      const int rs = s + 1 + t * B;
+      const int len = min(B, n - rs);
+      const int rs2 = rs + B;
+      const int len2 = (rs2 < n) ? min(B, n - rs2) : 0;
+      // load the diagonal block (symmetrized) and the block below
+      for (int q = 0; q < HB; q++) {
+        const int j = hf * HB + q;
+        double dv = 0.0, bv = 0.0;
+        if (li < len && j < len && li >= j) dv = AB[(li - j) + (long)(rs + j) * ldab];
+        if (li < len2 && j < len) bv = AB[(B + li - j) + (long)(rs + j) * ldab];
+        Bl[li][j] = bv;
+        if (li >= j) {
+          Dl[li][j] = dv;
+          Dl[j][li] = dv;
+        }
+      }
+      if (t == 0) {
+        // reflector from column s, rows s+1 .. s+len
+        const double x = (lane < len) ? AB[(1 + lane) + (long)s * ldab] : 0.0;
+        const double alpha = __shfl(x, 0, 64);
+        const double sig = wsum((lane >= 1 && lane < len) ? x * x : 0.0);
+        double beta = alpha, scal = 0.0;
+        tau = 0.0;
+        if (sig > 0.0) {
+          const double nrm = sqrt(alpha * alpha + sig);
+          beta = (alpha >= 0.0) ? -nrm : nrm;
+          tau = (beta - alpha) / beta;
+          scal = 1.0 / (alpha - beta);
+        }
+        if (lane < B) vc[lane] = (lane == 0) ? 1.0 : ((lane < len) ? x * scal : 0.0);
+        if (lane < len) AB[(1 + lane) + (long)s * ldab] = (lane == 0) ? beta : 0.0;
+      } else {
+        if (lane < B) vc[lane] = vn[lane];
+      }
+      wave_sync();
+      // store H_{s,t} for the back-transformation
+      {
+        const int k = s % B;
+        const long gi = goff[s / B] + t;
+        double* col = V2 + (gi * B + k) * (long)(2 * B);
+        const int r = lane - k;
+        col[lane] = (r >= 0 && r < len) ? vc[r] : 0.0;
+        if (lane == 0) tau2[gi * B + k] = tau;
+      }
+      // two-sided update of the diagonal block: y = tau D v, w = y - (tau/2)(v.y) v
+      {
+        double p = 0.0;
+        for (int q = 0; q < HB; q++) {
+          const int j = hf * HB + q;
+          p += Dl[li][j] * vc[j];
+        }
+        const double y = tau * hsum(p);
+        const double vy = wsum(hf == 0 ? vc[li] * y : 0.0);
+        const double w = y - 0.5 * tau * vy * vc[li];
+        if (hf == 0) wk[li] = w;
+        wave_sync();
+        const double vi = vc[li];
+        for (int q = 0; q < HB; q++) {
+          const int j = hf * HB + q;
+          Dl[li][j] -= vi * wk[j] + w * vc[j];
+        }
+      }
+      double tau_n = 0.0;
+      if (len2 > 0) {
+        // right application to the block below: Bk <- Bk (I - tau v v^T)
+        double p = 0.0;
+        for (int q = 0; q < HB; q++) {
+          const int j = hf * HB + q;
+          p += Bl[li][j] * vc[j];
+        }
+        const double z = tau * hsum(p);
+        for (int q = 0; q < HB; q++) {
+          const int j = hf * HB + q;
+          Bl[li][j] -= z * vc[j];
+        }
+        wave_sync();
+        // next reflector from the first column of the block
+        const double x = (lane < len2) ? Bl[lane][0] : 0.0;
+        const double alpha = __shfl(x, 0, 64);
+        const double sig = wsum((lane >= 1 && lane < len2) ? x * x : 0.0);
+        double beta = alpha, scal = 0.0;
+        if (sig > 0.0) {
+          const double nrm = sqrt(alpha * alpha + sig);
+          beta = (alpha >= 0.0) ? -nrm : nrm;
+          tau_n = (beta - alpha) / beta;
+          scal = 1.0 / (alpha - beta);
+        }
+        if (lane < B) vn[lane] = (lane == 0) ? 1.0 : ((lane < len2) ? x * scal : 0.0);
+        wave_sync();
+        // left application to columns 1..: w_j = tau_n sum_r vn_r Bk[r][j]
+        // (lane owns column li, rows of its half)
+        double pc = 0.0;
+        for (int q = 0; q < HB; q++) {
+          const int r = hf * HB + q;
+          pc += vn[r] * Bl[r][li];
+        }
+        const double wj = tau_n * hsum(pc);
+        wave_sync();
+        if (li >= 1) {
+          for (int q = 0; q < HB; q++) {
+            const int r = hf * HB + q;
+            Bl[r][li] -= vn[r] * wj;
+          }
+        } else {
+          for (int q = 0; q < HB; q++) {
+            const int r = hf * HB + q;
+            Bl[r][0] = (r == 0) ? beta : 0.0;
+          }
+        }
+        wave_sync();
+      }
+      // write back
+      for (int q = 0; q < HB; q++) {
+        const int j = hf * HB + q;
+        if (li < len && j < len && li >= j) AB[(li - j) + (long)(rs + j) * ldab] = Dl[li][j];
+        if (li < len2 && j < len) AB[(B + li - j) + (long)(rs + j) * ldab] = Bl[li][j];
+      }
+      tau = tau_n;
+      publish(progress + s, t + 1);
+    }
+    publish(progress + s, DONE);
+  }
+}
+
+__global__ void extract_tridiag_kernel(int n, const double* AB, int ldab, double* d, double* e) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  d[i] = AB[(long)i * ldab];
+  if (i + 1 < n) e[i] = AB[1 + (long)i * ldab];
+}
+
+__global__ void fill_int_kernel(int* p, long n, int v) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void fill_dbl_kernel(double* p, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+}  // namespace
+
+Sb2stLayout sb2st_layout(int n, int B) {
+  Sb2stLayout L{};
+  L.n = n;
+  L.B = B;
+  L.nsweep = n >= 3 ? n - 2 : 0;
+  L.nblk = (L.nsweep + B - 1) / B;
+  L.tmax = n >= 2 ? (n - 1 + B - 1) / B : 0;
+  long g = 0;
+  for (int sb = 0; sb < L.nblk; sb++) g += (n - 1 - sb * B + B - 1) / B;
+  L.ngroups = g;
+  L.v2_doubles = g * 2L * B * B;
+  return L;
+}
+
+void sb2st_group_offsets(const Sb2stLayout& L, long* offs) {
+  long g = 0;
+  for (int sb = 0; sb < L.nblk; sb++) {
+    offs[sb] = g;
+    g += (L.n - 1 - sb * L.B + L.B - 1) / L.B;
+  }
+  offs[L.nblk] = g;
+}
+
+hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, double* e, double* V2,
+                     double* tau2, const long* d_goff, int* progress, DevStatusWord* st,
+                     hipStream_t s) {
+  const int n = L.n;
+  if (L.B != 32) return hipErrorInvalidValue;
+  if (L.nsweep > 0) {
+    hipLaunchKernelGGL(fill_dbl_kernel, dim3(4096), dim3(256), 0, s, V2, L.v2_doubles);
+    HSDM_TRY(hipGetLastError());
+    hipLaunchKernelGGL(fill_dbl_kernel, dim3(1024), dim3(256), 0, s, tau2, L.ngroups * L.B);
+    HSDM_TRY(hipGetLastError());
+    hipLaunchKernelGGL(fill_int_kernel, dim3(ceil_div(L.nsweep, 256)), dim3(256), 0, s, progress,
+                       (long)L.nsweep, 0);
+    HSDM_TRY(hipGetLastError());
+    int nsweep = L.nsweep;
+    int nwg = ceil_div(nsweep, WPB);
+    if (nwg > 256) nwg = 256;
+    void* args[] = {(void*)&n, (void*)&nsweep, (void*)&AB, (void*)&ldab, (void*)&V2,
+                    (void*)&tau2, (void*)&d_goff, (void*)&progress, (void*)&st};
+    HSDM_TRY(hipLaunchCooperativeKernel((const void*)sb2st_kernel<32>, dim3(nwg), dim3(64 * WPB),
+                                        args, 0, s));
+  }
+  hipLaunchKernelGGL(extract_tridiag_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, AB, ldab,
+                     d, e);
+  return hipGetLastError();
+}

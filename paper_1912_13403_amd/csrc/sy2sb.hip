@@ -1,0 +1,312 @@
+// Stage 1 of the two-stage tridiagonalization: full symmetric -> band of
+// half-bandwidth B (the paper's GPU outlook names the two-stage reduction as
+// the part that exposes matrix-matrix work).
+//
+// For panel p (columns c0 = pB .. c0+B-1, rows r0 = c0+B .. n-1, h = n-r0):
+//  1. Householder QR of the h x B panel.  One cooperative launch; workgroup g
+//     keeps rows [256g, 256g+256) of the panel in LDS.  Per column a single
+//     grid-wide exchange of partial sums is enough: every workgroup
+//     contributes sum_i x_i^2 and sum_i x_i a_ic (rows below the pivot) and
+//     derives the reflector and the update coefficients locally, in the same
+//     fixed reduction order (bitwise reproducible).  The block reflector
+//     Q = I - V T V^T (T upper triangular) is formed in the same launch.
+//  2. Two-sided update of the trailing block A22 <- Q^T A22 Q, with only the
+//     lower triangle of A22 stored:
+//        Y = V T,  X = A22 Y (symmetric operand),  M = Y^T X,
+//        W = X - V M / 2,  A22 <- A22 - [V W][W V]^T (lower tiles).
+//     Both large products run on the FP64 MFMA GEMM.
+// After the last panel the band (diagonal blocks and the R factors) is
+// copied into band storage for the bulge-chasing stage.
+#include "hsdm_internal.h"
+#include "hsdm_phases.h"
+#include "hsdm_util.h"
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int CH = 256;  // panel rows per workgroup
+
+HSDM_DEV void grid_sync(unsigned* bar, unsigned nblk, unsigned& epoch, DevStatusWord* st) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    epoch += 1;
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = epoch * nblk;
+    long spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      ++spins;
+      if (spins > (1L << 26) ||
+          ((spins & 4095) == 0 &&
+           __hip_atomic_load(&st->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+        dev_set_status(st, DS_SYNC_TIMEOUT, 1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+}
+
+// Householder QR of the h x B panel P (ldp); V receives the explicit unit
+// lower trapezoidal reflectors, tau the scalars, Tt the B x B triangular
+// factor (column-major, ld B).  part, prow, gpart are scratch.
+template <int B>
+__global__ __launch_bounds__(NT) void panel_qr_kernel(int h, double* P, long ldp, double* V,
+                                                      long ldv, double* tau_out, double* Tt,
+                                                      double* part, double* prow, double* gpart,
+                                                      unsigned* bar, DevStatusWord* st) {
+  static_assert(NT % B == 0, "threads must tile the panel width");
+  constexpr int RG = NT / B;        // row groups
+  constexpr int RPG = CH / RG;      // rows per group
+  __shared__ double Pl[CH][B + 1];
+  __shared__ double red[RG][B + 1];
+  __shared__ double ddl[B], wl[B], taul[B];
+  __shared__ double Gm[B][B + 1], Tl[B][B + 1];
+
+  const int g = blockIdx.x, G = gridDim.x;
+  const int t = threadIdx.x, c = t % B, rg = t / B;
+  const int row0 = g * CH;
+  const int nrows = min(CH, h - row0);
+  unsigned epoch = 0;
+
+  for (int i = t / B; i < CH; i += RG) Pl[i][c] = (i < nrows) ? P[row0 + i + (long)c * ldp] : 0.0;
+  __syncthreads();
+
+  const int ncol = min(B, h);
+  for (int j = 0; j < B; j++) {
+    if (j >= ncol) {
+      if (g == 0 && t == 0) taul[j] = 0.0;
+      continue;
+    }
+    // partial sums over rows strictly below the pivot
+    double s = 0.0;
+    if (c >= j) {
+      for (int q = 0; q < RPG; q++) {
+        const int i = rg * RPG + q;
+        if (i < nrows && row0 + i > j) s += Pl[i][j] * Pl[i][c];
+      }
+    }
+    red[rg][c] = s;
+    __syncthreads();
+    double* pb = part + (size_t)(j & 1) * G * B;
+    double* rb = prow + (size_t)(j & 1) * B;
+    if (t < B) {
+      double a = 0.0;
+      for (int r = 0; r < RG; r++) a += red[r][t];
+      pb[(size_t)g * B + t] = a;
+      if (g == 0) rb[t] = Pl[j][t];  // pivot row (global row j lives in group 0)
+    }
+    grid_sync(bar, G, epoch, st);
+    if (t < B) {
+      double a = 0.0;
+      if (t >= j)
+        for (int q = 0; q < G; q++) a += pb[(size_t)q * B + t];
+      ddl[t] = a;
+    }
+    __syncthreads();
+    const double sigma = ddl[j];
+    const double alpha = rb[j];
+    double tau = 0.0, beta = alpha, scal = 0.0;
+    if (sigma > 0.0) {
+      const double nrm = sqrt(alpha * alpha + sigma);
+      beta = (alpha >= 0.0) ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    if (t < B) wl[t] = (t > j) ? tau * (rb[t] + ddl[t] * scal) : 0.0;
+    if (t == 0) taul[j] = tau;
+    __syncthreads();
+    // rank-1 update of the columns right of j (rows below the pivot)
+    if (c > j) {
+      const double wc = wl[c];
+      for (int q = 0; q < RPG; q++) {
+        const int i = rg * RPG + q;
+        if (i < nrows && row0 + i > j) Pl[i][c] -= (Pl[i][j] * scal) * wc;
+      }
+    }
+    __syncthreads();
+    if (c == j) {
+      for (int q = 0; q < RPG; q++) {
+        const int i = rg * RPG + q;
+        if (i < nrows && row0 + i > j) Pl[i][j] *= scal;
+      }
+    }
+    if (g == 0 && rg == 0) {
+      if (c > j) Pl[j][c] -= wl[c];
+      if (c == j) Pl[j][j] = beta;
+    }
+    __syncthreads();
+  }
+
+  // write back R / V in place, the explicit V, and partial Gram V^T V
+  for (int i = t / B; i < nrows; i += RG) {
+    const int gi = row0 + i;
+    P[gi + (long)c * ldp] = Pl[i][c];
+    V[gi + (long)c * ldv] = (gi > c) ? Pl[i][c] : (gi == c ? 1.0 : 0.0);
+  }
+  if (g == 0 && t < B) tau_out[t] = taul[t];
+  for (int e = t; e < B * B; e += NT) {
+    const int a = e % B, b = e / B;
+    double s = 0.0;
+    if (a <= b) {
+      for (int i = 0; i < nrows; i++) {
+        const int gi = row0 + i;
+        const double va = (gi > a) ? Pl[i][a] : (gi == a ? 1.0 : 0.0);
+        const double vb = (gi > b) ? Pl[i][b] : (gi == b ? 1.0 : 0.0);
+        s += va * vb;
+      }
+    }
+    gpart[(size_t)g * B * B + e] = s;
+  }
+  grid_sync(bar, G, epoch, st);
+  if (g != 0) return;
+  for (int e = t; e < B * B; e += NT) {
+    const int a = e % B, b = e / B;
+    double s = 0.0;
+    for (int q = 0; q < G; q++) s += gpart[(size_t)q * B * B + e];
+    Gm[a][b] = s;
+    Tl[a][b] = 0.0;
+  }
+  __syncthreads();
+  // T: T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) (V^T v_j)(0:j)
+  for (int j = 0; j < B; j++) {
+    if (t < j) {
+      double s = 0.0;
+      for (int k = t; k < j; k++) s += Tl[t][k] * Gm[k][j];
+      Tl[t][j] = -taul[j] * s;
+    }
+    if (t == j) Tl[j][j] = taul[j];
+    __syncthreads();
+  }
+  for (int e = t; e < B * B; e += NT) Tt[e] = Tl[e % B][e / B];
+}
+
+// Band extraction: AB[(r-c) + c*ldab] = A[r + c*lda] for 0 <= r-c <= B, zero
+// for B < r-c < ldab.
+__global__ void band_extract_kernel(int n, int B, const double* A, long lda, double* AB,
+                                    int ldab) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)n * ldab) return;
+  const int off = (int)(idx % ldab), c = (int)(idx / ldab);
+  const int r = c + off;
+  AB[idx] = (off <= B && r < n) ? A[r + (long)c * lda] : 0.0;
+}
+
+// P = U^T W for h x B tall operands: per-workgroup partial sums, then a
+// fixed-order reduction (reproducible).
+template <int B>
+__global__ __launch_bounds__(NT) void atb_partial_kernel(int h, const double* U, long ldu,
+                                                         const double* W, long ldw,
+                                                         double* part) {
+  const int g = blockIdx.x, t = threadIdx.x;
+  const int r0 = g * CH, nr = min(CH, h - r0);
+  __shared__ double Us[CH][B + 1], Ws[CH][B + 1];
+  for (int e = t; e < CH * B; e += NT) {
+    const int i = e % CH, c = e / CH;
+    Us[i][c] = (i < nr) ? U[r0 + i + (long)c * ldu] : 0.0;
+    Ws[i][c] = (i < nr) ? W[r0 + i + (long)c * ldw] : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < B * B; e += NT) {
+    const int a = e % B, b = e / B;
+    double s = 0.0;
+    for (int i = 0; i < nr; i++) s += Us[i][a] * Ws[i][b];
+    part[(size_t)g * B * B + e] = s;
+  }
+}
+
+template <int B>
+__global__ void atb_reduce_kernel(int G, const double* part, double* out, long ldo) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= B * B) return;
+  double s = 0.0;
+  for (int q = 0; q < G; q++) s += part[(size_t)q * B * B + e];
+  out[(e % B) + (long)(e / B) * ldo] = s;
+}
+
+__global__ void zero_u32_kernel(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+}  // namespace
+
+size_t sy2sb_scratch_doubles(int n, int B) {
+  const int G = ceil_div(n, CH) + 1;
+  // part(2GB) + prow(2B) + gpart(G B^2) + atb parts(G B^2) + Y,VW,WV (n x 2B each) + M (B^2)
+  return (size_t)2 * G * B + 2 * B + (size_t)2 * G * B * B + (size_t)5 * n * 2 * B + B * B + 64;
+}
+
+hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, double* tau1,
+                     double* T1, double* AB, int ldab, double* scratch, unsigned* bar,
+                     DevStatusWord* st, hipStream_t s) {
+  if (B != 32) return hipErrorInvalidValue;
+  constexpr int BB = 32;
+  const int Gmax = ceil_div(n, CH) + 1;
+  double* part = scratch;
+  double* prow = part + (size_t)2 * Gmax * B;
+  double* gpart = prow + 2 * B;
+  double* apart = gpart + (size_t)Gmax * B * B;
+  double* Y = apart + (size_t)Gmax * B * B;      // n x B
+  double* VW = Y + (size_t)n * B;                // n x 2B  [V W]
+  double* WV = VW + (size_t)n * 2 * B;           // n x 2B  [W V]
+  double* M = WV + (size_t)n * 2 * B;            // B x B
+
+  const int npanel = (n > B) ? ceil_div(n - 1, B) : 0;
+  for (int p = 0; p < npanel; p++) {
+    const int c0 = p * B, r0 = c0 + B, h = n - r0;
+    if (h <= 0) break;
+    double* Pp = A + r0 + (long)c0 * lda;
+    double* Vp = Vst + r0 + (long)c0 * ldv;
+    double* Tp = T1 + (size_t)p * B * B;
+    const int G = ceil_div(h, CH);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, bar, 1);
+    HSDM_TRY(hipGetLastError());
+    void* args[] = {(void*)&h, (void*)&Pp, (void*)&lda, (void*)&Vp, (void*)&ldv,
+                    (void*)&tau1, (void*)&Tp, (void*)&part, (void*)&prow, (void*)&gpart,
+                    (void*)&bar, (void*)&st};
+    double* tau_p = tau1 + c0;
+    args[5] = (void*)&tau_p;
+    HSDM_TRY(hipLaunchCooperativeKernel((const void*)panel_qr_kernel<BB>, dim3(G), dim3(NT), args,
+                                        0, s));
+    if (h <= 1) continue;
+    double* A22 = A + r0 + (long)r0 * lda;
+    // Y = V T
+    GemmArgs g{};
+    g.m = h; g.n = B; g.k = B; g.A = Vp; g.lda = ldv; g.B = Tp; g.ldb = B; g.C = Y; g.ldc = n;
+    g.alpha = 1.0; g.beta = 0.0; g.flags = GF_KB_UPPER;
+    HSDM_TRY(gemm_launch(g, s));
+    // X = A22 Y  -> VW[:, B:2B]
+    double* Xp = VW + (size_t)n * B;
+    g = GemmArgs{};
+    g.m = h; g.n = B; g.k = h; g.A = A22; g.lda = lda; g.B = Y; g.ldb = n; g.C = Xp; g.ldc = n;
+    g.alpha = 1.0; g.beta = 0.0; g.flags = GF_A_SYM_LOWER;
+    HSDM_TRY(gemm_launch(g, s));
+    // M = Y^T X
+    hipLaunchKernelGGL((atb_partial_kernel<BB>), dim3(G), dim3(NT), 0, s, h, Y, (long)n, Xp,
+                       (long)n, apart);
+    HSDM_TRY(hipGetLastError());
+    hipLaunchKernelGGL((atb_reduce_kernel<BB>), dim3(ceil_div(B * B, 256)), dim3(256), 0, s, G,
+                       apart, M, (long)B);
+    HSDM_TRY(hipGetLastError());
+    // W = X - V M / 2 (in place in VW[:, B:2B])
+    g = GemmArgs{};
+    g.m = h; g.n = B; g.k = B; g.A = Vp; g.lda = ldv; g.B = M; g.ldb = B; g.C = Xp; g.ldc = n;
+    g.alpha = -0.5; g.beta = 1.0;
+    HSDM_TRY(gemm_launch(g, s));
+    // VW[:, 0:B] = V ; WV = [W V]
+    HSDM_TRY(dev_copy(Vp, ldv, VW, n, h, B, s));
+    HSDM_TRY(dev_copy(Xp, n, WV, n, h, B, s));
+    HSDM_TRY(dev_copy(Vp, ldv, WV + (size_t)n * B, n, h, B, s));
+    // A22 -= [V W][W V]^T  (lower)
+    g = GemmArgs{};
+    g.m = h; g.n = h; g.k = 2 * B; g.A = VW; g.lda = n; g.B = WV; g.ldb = n; g.C = A22;
+    g.ldc = lda; g.alpha = -1.0; g.beta = 1.0; g.ta = 0; g.tb = 1;
+    g.flags = GF_C_LOWER_TILES | GF_C_LOWER_ONLY;
+    HSDM_TRY(gemm_launch(g, s));
+  }
+  const long tot = (long)n * ldab;
+  hipLaunchKernelGGL(band_extract_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n,
+                     B, A, lda, AB, ldab);
+  return hipGetLastError();
+}

@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports every function include/hsdm.h
+declares; host-side argument checks (no GPU, no compute)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hsdm.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hsdm_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1912_13403_amd import hsdm
+    if not os.path.exists(hsdm.LIB_PATH):
+        from paper_1912_13403_amd import build
+        build.build()
+    return hsdm.load_library()
+
+
+def test_header_declares_the_paths_calls():
+    names = _declared()
+    for must in ("hsdm_init", "hsdm_finalize", "hsdm_reinit", "hsdm_solve_ev_real",
+                 "hsdm_solve_dm_real"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1912_13403_amd import hsdm
+    names = _declared()
+    assert names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(hsdm.EXPORTED) == names
+
+
+def test_status_strings_and_version(lib):
+    assert lib.hsdm_status_string(0) == b"ok"
+    assert lib.hsdm_status_string(1).startswith(b"S is not positive")
+    assert lib.hsdm_status_string(-3) == b"invalid argument"
+    assert lib.hsdm_version() >= 100
+
+
+def test_null_handle_is_argument_one(lib):
+    vp = ctypes.c_void_p
+    assert lib.hsdm_solve_ev_real(None, 4, vp(8), 4, vp(8), 4, vp(8), vp(8), 4, None) == -1
+    assert lib.hsdm_solve_dm_real(None, 4, vp(8), 4, vp(8), 4, 1.0, 0.0, vp(8), 4, None, 4, None,
+                                  None, None, None) == -1
+    assert lib.hsdm_finalize(None) == -1
+    assert lib.hsdm_reinit(None) == -1
+    assert lib.hsdm_set_real(None, 1, 2.0) == -1
+    assert lib.hsdm_init(None, 0) == -1
+    assert lib.hsdm_last_error(None) == b"null handle"

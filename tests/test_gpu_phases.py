@@ -1,0 +1,166 @@
+"""Per-phase parity of the HIP path against the FP64 CPU oracle and against
+closed forms.  Every call goes through the C ABI (libhsdm.so)."""
+import numpy as np
+import pytest
+
+from paper_1912_13403_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def h(torch_dev):
+    from paper_1912_13403_amd import hsdm
+    with hsdm.Handle(0) as handle:
+        yield handle
+
+
+def _g(torch_dev, x):
+    torch, dev = torch_dev
+    return torch.from_numpy(np.asfortranarray(x)).to(dev)
+
+
+def _c(x):
+    return x.detach().cpu().numpy()
+
+
+def _sym(X):
+    return np.tril(X) + np.tril(X, -1).T
+
+
+@pytest.mark.parametrize("ta,tb", [("N", "N"), ("N", "T"), ("T", "N"), ("T", "T")])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (17, 5, 3), (200, 130, 77), (300, 260, 513)])
+def test_dgemm_matches_fp64(torch_dev, h, ta, tb, m, n, k):
+    rng = np.random.default_rng(m * 7 + n * 3 + k)
+    A = rng.standard_normal((k, m) if ta == "T" else (m, k))
+    B = rng.standard_normal((n, k) if tb == "T" else (k, n))
+    C0 = rng.standard_normal((m, n))
+    ref = 1.5 * ((A.T if ta == "T" else A) @ (B.T if tb == "T" else B)) - 0.5 * C0
+    C = h.hsdm_dgemm(ta, tb, 1.5, _g(torch_dev, A), _g(torch_dev, B), -0.5, _g(torch_dev, C0))
+    err = np.max(np.abs(_c(C) - ref)) / max(1.0, np.max(np.abs(ref)))
+    assert err < 1e-13 * max(1, k)
+
+
+@pytest.mark.parametrize("n", [1, 5, 64, 65, 300, 513])
+def test_cholesky_inverse(oracle, torch_dev, h, n):
+    _, S = inputs.sized_problem(n, cfg=100 + n)
+    L, Li = h.hsdm_cholesky_inverse(_g(torch_dev, S))
+    L, Li = _c(L), _c(Li)
+    Lo, info = oracle.cholesky(S)
+    assert info == 0
+    assert np.max(np.abs(L - Lo)) < 1e-13
+    assert np.max(np.abs(np.triu(L, 1))) == 0.0 and np.max(np.abs(np.triu(Li, 1))) == 0.0
+    assert np.max(np.abs(Li @ Lo - np.eye(n))) < 1e-13 * n
+
+
+def test_cholesky_reports_failing_column(torch_dev, h):
+    from paper_1912_13403_amd import hsdm
+    n = 150
+    S = np.eye(n)
+    S[97, 97] = -2.0
+    with pytest.raises(hsdm.HsdmError) as ei:
+        h.hsdm_cholesky_inverse(_g(torch_dev, S))
+    assert ei.value.status == hsdm.HSDM_NOT_SPD and ei.value.detail == 98
+
+
+@pytest.mark.parametrize("n", [7, 100, 333])
+def test_standard_form(oracle, torch_dev, h, n):
+    H, S = inputs.sized_problem(n, cfg=200 + n)
+    L, info = oracle.cholesky(S)
+    Li = np.linalg.inv(L)
+    Li = np.tril(Li)
+    A = _c(h.hsdm_standard_form(_g(torch_dev, H), _g(torch_dev, Li)))
+    Aref = oracle.standard_form(H, L)
+    assert np.max(np.abs(np.tril(A) - np.tril(Aref))) < 1e-12 * oracle.norm1(H)
+
+
+@pytest.mark.parametrize("n", [2, 3, 33, 64, 65, 130, 257, 600])
+def test_tridiagonalize(oracle, torch_dev, h, n):
+    H, _ = inputs.sized_problem(n, cfg=300 + n)
+    A = _sym(H)
+    d, e, Q = h.hsdm_tridiagonalize(_g(torch_dev, A))
+    d, e, Q = _c(d), _c(e), _c(Q)
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) < 1e-13 * n
+    assert np.max(np.abs(Q @ T @ Q.T - A)) < 1e-13 * n * oracle.norm1(H)
+    w_t, _ = oracle.tridiag_eigh(d, e)
+    w_a, _ = oracle.solve_ev(A, np.eye(n))
+    assert np.max(np.abs(w_t - w_a)) < 1e-12 * oracle.norm1(H)
+
+
+def _tridiag_cases():
+    rng = np.random.default_rng(9)
+    out = []
+    for n in (1, 2, 5, 64, 65, 200, 513, 1100):
+        out.append((f"random{n}", rng.standard_normal(n), rng.standard_normal(max(n - 1, 0))))
+    n = 300  # closed-form chain: d = 0, e = -1
+    out.append(("chain300", np.zeros(n), -np.ones(n - 1)))
+    # glued pieces: exact zero couplings (rho = 0 merges)
+    d = rng.standard_normal(400)
+    e = rng.standard_normal(399)
+    e[[63, 127, 199, 250]] = 0.0
+    out.append(("split400", d, e))
+    # nearly degenerate spectrum: Wilkinson-like W+ of size 201
+    m = 100
+    out.append(("wilkinson201", np.abs(np.arange(-m, m + 1)).astype(float), np.ones(2 * m)))
+    # many equal diagonal entries and tiny couplings (heavy deflation)
+    d = np.repeat(rng.standard_normal(30), 20)
+    e = 1e-14 * rng.standard_normal(599)
+    out.append(("clustered600", d, e))
+    return out
+
+
+@pytest.mark.parametrize("name,d,e", _tridiag_cases(), ids=[c[0] for c in _tridiag_cases()])
+def test_tridiag_eigh_divide_and_conquer(oracle, torch_dev, h, name, d, e):
+    torch, dev = torch_dev
+    n = len(d)
+    w, Z = h.hsdm_tridiag_eigh(torch.from_numpy(d).to(dev), torch.from_numpy(np.asarray(e)).to(dev))
+    w, Z = _c(w), _c(Z)
+    T = np.diag(d) + (np.diag(e, 1) + np.diag(e, -1) if n > 1 else 0.0)
+    tn = max(np.max(np.abs(T).sum(axis=0)), 1e-300)
+    w_ref, _ = oracle.tridiag_eigh(d, e)
+    assert np.all(np.diff(w) >= 0)
+    assert np.max(np.abs(w - w_ref)) <= 1e-13 * tn * max(1, np.log2(n))
+    assert np.max(np.abs(T @ Z - Z * w)) <= 1e-13 * tn * n ** 0.5
+    assert np.max(np.abs(Z.T @ Z - np.eye(n))) <= 1e-13 * n
+    if name.startswith("chain"):
+        k = np.arange(1, n + 1)
+        exact = np.sort(-2.0 * np.cos(k * np.pi / (n + 1)))
+        assert np.max(np.abs(w - exact)) < 1e-13 * 4
+
+
+@pytest.mark.parametrize("kT", [0.0, 0.01, 0.3])
+def test_occupations(oracle, torch_dev, h, kT):
+    torch, dev = torch_dev
+    rng = np.random.default_rng(11)
+    eps = np.sort(rng.uniform(-2, 2, 3000))
+    ne = 1234.0
+    f, mu, eb, m = h.hsdm_occupations(torch.from_numpy(eps).to(dev), ne, kT, deg_tol=1e-12)
+    fr, mur = oracle.occupations(eps, ne, kT, deg_tol=1e-12)
+    f = _c(f)
+    assert np.max(np.abs(f - fr)) < 1e-12
+    assert abs(mu - mur) < 1e-12
+    assert abs(eb - np.sum(fr * eps)) < 1e-10
+    assert m == int(np.sum(fr > 2e-16))
+
+
+def test_density_from_pairs(oracle, torch_dev, h):
+    torch, dev = torch_dev
+    n = 300
+    H, S = inputs.sized_problem(n, cfg=400)
+    w, C = oracle.solve_ev(H, S)
+    f, _ = oracle.occupations(w, 140.0, 0.02)
+    m = int(np.sum(f > 2e-16))
+    D, E = h.hsdm_density(_g(torch_dev, C[:, :m]), torch.from_numpy(f).to(dev),
+                          torch.from_numpy(w).to(dev))
+    Dr, Er = oracle.density(C, f, w)
+    assert np.max(np.abs(_c(D) - Dr)) < 1e-12
+    assert np.max(np.abs(_c(E) - Er)) < 1e-12

@@ -1,0 +1,176 @@
+"""End-to-end parity of hsdm_solve_ev_real / hsdm_solve_dm_real (C ABI)
+against the FP64 CPU oracle, at sizes spanning several tiles with ragged
+tails, plus the closed-form and invariant pins.
+
+Tolerances: |d eps| <= 1e-10 ||H||_1, residual
+max_l ||H c_l - S c_l eps_l||_1 / (n ||H||_1) <= 1e-12, ||dD||_max <= 1e-9,
+||dE||_max <= 1e-9 max(1, ||H||_1)."""
+import numpy as np
+import pytest
+
+from paper_1912_13403_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def h(torch_dev):
+    from paper_1912_13403_amd import hsdm
+    with hsdm.Handle(0) as handle:
+        yield handle
+
+
+def _g(torch_dev, x):
+    torch, dev = torch_dev
+    return torch.from_numpy(np.asfortranarray(x)).to(dev)
+
+
+def _c(x):
+    return x.detach().cpu().numpy()
+
+
+def _sym(X):
+    return np.tril(X) + np.tril(X, -1).T
+
+
+def _check_ev(oracle, H, S, w, C, w_ref):
+    n = H.shape[0]
+    Hf, Sf = _sym(H), _sym(S)
+    scale = oracle.norm1(H)
+    assert np.max(np.abs(w - w_ref)) <= 1e-10 * scale
+    res = Hf @ C - (Sf @ C) * w
+    assert np.max(np.abs(res).sum(axis=0)) / (n * scale) <= 1e-12
+    assert np.max(np.abs(C.T @ Sf @ C - np.eye(n))) <= 1e-12 * n
+
+
+@pytest.mark.parametrize("n", [1, 2, 33, 100, 300, 700])
+def test_solve_ev_parity(oracle, torch_dev, h, n):
+    H, S = inputs.sized_problem(n, cfg=500 + n)
+    h.hsdm_reinit()
+    w, C = h.hsdm_solve_ev_real(_g(torch_dev, H), _g(torch_dev, S))
+    w_ref, _ = oracle.solve_ev(H, S)
+    _check_ev(oracle, H, S, _c(w), _c(C), w_ref)
+
+
+@pytest.mark.parametrize("n,ne,kT", [(2, 2.0, 0.0), (65, 31.0, 0.0), (300, 150.0, 0.01),
+                                     (513, 256.0, 0.005), (700, 333.0, 0.02)])
+def test_solve_dm_parity(oracle, torch_dev, h, n, ne, kT):
+    H, S = inputs.sized_problem(n, cfg=600 + n)
+    h.hsdm_reinit()
+    out = h.hsdm_solve_dm_real(_g(torch_dev, H), _g(torch_dev, S), ne, kT)
+    ref = oracle.solve_dm(H, S, ne, kT)
+    scale = oracle.norm1(H)
+    assert np.max(np.abs(_c(out["eval"]) - ref["eval"])) <= 1e-10 * scale
+    assert np.max(np.abs(_c(out["D"]) - ref["D"])) <= 1e-9
+    assert np.max(np.abs(_c(out["E"]) - ref["E"])) <= 1e-9 * max(1.0, scale)
+    assert abs(out["band_energy"] - ref["band_energy"]) <= 1e-10 * scale * max(ne, 1.0)
+    if kT > 0:
+        assert abs(out["mu"] - ref["mu"]) <= 1e-10 * scale
+
+
+def test_cfg0_full_parity_and_invariants(oracle, torch_dev, h):
+    H, S, p = inputs.config_problem("cfg0_n512")
+    h.hsdm_reinit()
+    out = h.hsdm_solve_dm_real(_g(torch_dev, H), _g(torch_dev, S), p["n_electrons"], p["kT"])
+    ref = oracle.solve_dm(H, S, p["n_electrons"], p["kT"])
+    D, E = _c(out["D"]), _c(out["E"])
+    assert np.max(np.abs(D - ref["D"])) <= 1e-9
+    assert np.max(np.abs(E - ref["E"])) <= 1e-9 * oracle.norm1(H)
+    Hf, Sf = _sym(H), _sym(S)
+    ne = p["n_electrons"]
+    assert abs(np.trace(D @ Sf) - ne) < 1e-10 * ne
+    assert np.max(np.abs(Sf @ E - Hf @ D)) < 1e-10
+    P = D / 2.0
+    assert np.max(np.abs(P @ Sf @ P - P)) < 1e-10
+    assert np.array_equal(D, D.T) and np.array_equal(E, E.T)
+
+
+def test_chain_closed_form_through_gpu(torch_dev, h):
+    n, t = 257, -1.0
+    H, S = inputs.chain(n, t)
+    h.hsdm_reinit()
+    w, C = h.hsdm_solve_ev_real(_g(torch_dev, H), _g(torch_dev, S))
+    k = np.arange(1, n + 1)
+    exact = np.sort(2 * t * np.cos(k * np.pi / (n + 1)))
+    assert np.max(np.abs(_c(w) - exact)) < 1e-13 * 8
+    ne = 2 * 100
+    out = h.hsdm_solve_dm_real(_g(torch_dev, H), _g(torch_dev, S), ne, 0.0)
+    j = np.arange(1, n + 1)
+    U = np.sqrt(2.0 / (n + 1)) * np.sin(np.outer(j, k) * np.pi / (n + 1))
+    order = np.argsort(2 * t * np.cos(k * np.pi / (n + 1)), kind="stable")
+    U = U[:, order]
+    Dx = 2.0 * U[:, :100] @ U[:, :100].T
+    assert np.max(np.abs(_c(out["D"]) - Dx)) < 1e-11
+
+
+def test_s_factor_cache_and_reinit(oracle, torch_dev, h):
+    n = 200
+    H, S = inputs.sized_problem(n, cfg=700)
+    H2, S2 = inputs.sized_problem(n, cfg=701)
+    h.hsdm_reinit()
+    Sg = _g(torch_dev, S)
+    r1 = h.hsdm_solve_dm_real(_g(torch_dev, H), Sg, 100.0, 0.01)
+    # same S buffer, new H: factor reused
+    r2 = h.hsdm_solve_dm_real(_g(torch_dev, H2), Sg, 100.0, 0.01)
+    ref2 = oracle.solve_dm(H2, S, 100.0, 0.01)
+    assert np.max(np.abs(_c(r2["D"]) - ref2["D"])) <= 1e-9
+    # S overwritten in place: reinit forgets the factor
+    Sg.copy_(_g(torch_dev, S2))
+    h.hsdm_reinit()
+    r3 = h.hsdm_solve_dm_real(_g(torch_dev, H), Sg, 100.0, 0.01)
+    ref3 = oracle.solve_dm(H, S2, 100.0, 0.01)
+    assert np.max(np.abs(_c(r3["D"]) - ref3["D"])) <= 1e-9
+    assert r1["band_energy"] != r3["band_energy"]
+
+
+def test_repeat_is_bitwise_deterministic(torch_dev, h):
+    n = 400
+    H, S = inputs.sized_problem(n, cfg=800)
+    outs = []
+    for _ in range(2):
+        h.hsdm_reinit()
+        r = h.hsdm_solve_dm_real(_g(torch_dev, H), _g(torch_dev, S), 200.0, 0.01)
+        outs.append((_c(r["D"]), _c(r["E"]), r["mu"]))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+
+
+def test_edge_electron_counts(oracle, torch_dev, h):
+    n = 96
+    H, S = inputs.sized_problem(n, cfg=900)
+    Sf = _sym(S)
+    h.hsdm_reinit()
+    r0 = h.hsdm_solve_dm_real(_g(torch_dev, H), _g(torch_dev, S), 0.0, 0.0)
+    assert np.max(np.abs(_c(r0["D"]))) == 0.0
+    rf = h.hsdm_solve_dm_real(_g(torch_dev, H), _g(torch_dev, S), 2.0 * n, 0.0)
+    assert np.max(np.abs(_c(rf["D"]) - 2.0 * np.linalg.inv(Sf))) < 1e-10
+
+
+def test_argument_errors(torch_dev, h):
+    from paper_1912_13403_amd import hsdm
+    torch, dev = torch_dev
+    lib = hsdm.load_library()
+    H = torch.zeros((4, 4), dtype=torch.float64, device=dev)
+    p = H.data_ptr()
+    assert lib.hsdm_solve_dm_real(h._h, 0, p, 4, p, 4, 1.0, 0.0, p, 4, None, 4, None, None, None,
+                                  None) == -2
+    assert lib.hsdm_solve_dm_real(h._h, 4, p, 3, p, 4, 1.0, 0.0, p, 4, None, 4, None, None, None,
+                                  None) == -4
+    assert lib.hsdm_solve_dm_real(h._h, 4, p, 4, p, 4, 9.0, 0.0, p, 4, None, 4, None, None, None,
+                                  None) == -7
+    assert lib.hsdm_solve_dm_real(h._h, 4, p, 4, p, 4, 1.0, -1.0, p, 4, None, 4, None, None, None,
+                                  None) == -8
+    S = -torch.eye(4, dtype=torch.float64, device=dev)
+    with pytest.raises(hsdm.HsdmError) as ei:
+        h.hsdm_reinit()
+        h.hsdm_solve_dm_real(torch.eye(4, dtype=torch.float64, device=dev), S, 1.0, 0.0)
+    assert ei.value.status == hsdm.HSDM_NOT_SPD and ei.value.detail == 1
