@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void group_t_kernel(const double* V2, const do
 }
 
 // Apply the groups of one level to Z.
-__global__ __launch_bounds__(256) void group_apply_kernel(int n, int nblk, int level, int sb_lo,
+__global__ __launch_bounds__(256, 2) void group_apply_kernel(int n, int nblk, int level, int sb_lo,
                                                           const double* V2, const double* T2,
                                                           const long* goff, double* Z, long ldz,
                                                           int m_host, const int* m_dev) {

@@ -13,9 +13,9 @@
 
 namespace {
 
-constexpr int NT = 256, BT = 64, BK = 16, LD = BT + 4;
+constexpr int NT = 256, BT = 64, BK = 16, LD = BT + 16;
 
-__global__ __launch_bounds__(NT) void dm_kernel(int n, int m_host, const int* m_dev,
+__global__ __launch_bounds__(NT, 2) void dm_kernel(int n, int m_host, const int* m_dev,
                                                 const double* C, long ldc, const double* f,
                                                 const double* eps, double* D, long ldd,
                                                 double* E, long lde) {

@@ -3,29 +3,34 @@
 // Every dense contraction of the path runs through this kernel: the
 // Cholesky/inverse recursion, the standard-form products, the two-sided
 // full-to-band update, the divide-and-conquer merges and the
-// back-transforms.  Tiles of BM x BN outputs per 256-thread workgroup
-// (4 wavefronts in a 2x2 grid, each owning (BM/2) x (BN/2)), K staged
-// through LDS in slices of 16 with register prefetch of the next slice
-// (double-buffered LDS).  Tile order is XCD-aware: consecutive workgroup ids
-// are dealt round-robin over the 8 XCDs, so ids are remapped such that each
-// XCD owns a contiguous run of tiles, walked in groups of 8 tile-rows to keep
-// the A and B panels of one XCD inside its own L2.
+// back-transforms.
+//
+// A workgroup computes a BM x BN tile with WM x WN wavefronts, each owning a
+// (BM/WM) x (BN/WN) sub-tile of 16x16 MFMA blocks.  K is staged through LDS
+// in slices of 16 with register prefetch of the next slice (double-buffered
+// LDS, one barrier per slice).  Each operand keeps in LDS the orientation it
+// has in memory, so global loads are coalesced and LDS stores are
+// conflict-free: a row-contiguous tile is stored [k][row] with a row stride
+// of (BM + 16) doubles, a k-contiguous tile [row][k] with stride 17; both
+// make the MFMA operand reads conflict-free.  Loads are branch-free (clamped
+// addresses, masked values).  Tile order is XCD-aware: workgroup ids are
+// dealt round-robin over the 8 XCDs, so ids are remapped such that each XCD
+// owns a contiguous run of tiles, walked in groups of 8 tile-rows so that the
+// A and B panels of one XCD stay in its L2.
+#include <cstdlib>
+
 #include "hsdm_internal.h"
 
 namespace {
 
-constexpr int NT = 256;
 constexpr int BK = 16;
-constexpr int PAD = 4;
 
-template <int BM, int BN>
-struct Cfg {
-  static constexpr int WM = BM / 2, WN = BN / 2;
-  static constexpr int FM = WM / 16, FN = WN / 16;
-  static constexpr int LDA_S = BM + PAD, LDB_S = BN + PAD;
-  static constexpr int AE = BM * BK / NT;  // A elements staged per thread
-  static constexpr int BE = BN * BK / NT;
-};
+// A operand modes
+constexpr int AM_DENSE = 0;
+constexpr int AM_SYM = 1;     // symmetric A, lower triangle stored (TA = 0)
+constexpr int AM_GATHER = 2;  // op(A)[:, kk] = A[:, acol[kk]] (TA = 0)
+constexpr int AM_TRIL = 3;    // op(A) = lower triangle of A, diagonal included (TA = 0)
+constexpr int AM_SLT = 4;     // op(A) = (strict lower triangle of A)^T (TA = 1)
 
 struct Prob {
   int m, n, k;
@@ -37,110 +42,119 @@ struct Prob {
   const int* ndev;  // optional device-side column count (n is then an upper bound)
 };
 
-// Load element (i, kk) of op(A) into a register, zero outside [0,m)x[kb,ke).
-template <int BM, int BN>
-HSDM_DEV void load_a(const Prob& p, int ta, int flags, int i0, int k0, int kb, int ke,
-                     double (&r)[Cfg<BM, BN>::AE]) {
+template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
+struct G {
+  static constexpr int NT = 64 * WM * WN;
+  static constexpr int WTM = BM / WM, WTN = BN / WN;
+  static constexpr int FM = WTM / 16, FN = WTN / 16;
+  static constexpr bool A_KC = (TA == 1);  // A tile stored [row][k]
+  static constexpr bool B_KC = (TB == 0);  // B tile stored [col][k]
+  static constexpr int LDA = A_KC ? (BK + 1) : (BM + 16);
+  static constexpr int LDB = B_KC ? (BK + 1) : (BN + 16);
+  static constexpr int ASZ = A_KC ? BM * (BK + 1) : BK * (BM + 16);
+  static constexpr int BSZ = B_KC ? BN * (BK + 1) : BK * (BN + 16);
+  static constexpr int AE = BM * BK / NT;
+  static constexpr int BE = BN * BK / NT;
+  static constexpr int SMEM = 2 * (ASZ + BSZ);
+  static constexpr int BMc = BM, BNc = BN;
+  static_assert(AE >= 1 && BE >= 1, "tile too small for the thread count");
+  static_assert(FM >= 1 && FN >= 1, "wave tile below one MFMA block");
+};
+
+// ---- global -> registers ------------------------------------------------------
+template <class C, int TA, int AM>
+HSDM_DEV void load_a(const Prob& p, int i0, int k0, int kb, int ke, double (&r)[C::AE]) {
   const int t = threadIdx.x;
-  constexpr int AE = Cfg<BM, BN>::AE;
-  if (flags & GF_A_SYM_LOWER) {
-    // symmetric A, lower triangle stored; choose a coalesced pattern per tile
-    const bool all_lower = i0 >= k0 + BK - 1;
-    const bool all_upper = i0 + BM - 1 < k0;
-    if (all_upper) {
-      // element (i,kk) = A[kk + i*lda]: contiguous along kk
+  if constexpr (TA == 1) {
+    // op(A)[i, kk] = A[kk + i*lda]: k-contiguous
 #pragma unroll
-      for (int q = 0; q < AE; q++) {
-        int kk = k0 + (t % BK), i = i0 + t / BK + q * (NT / BK);
-        r[q] = (i < p.m && kk >= kb && kk < ke) ? p.A[kk + (long)i * p.lda] : 0.0;
+    for (int q = 0; q < C::AE; q++) {
+      const int kk = k0 + (t % BK), i = i0 + t / BK + q * (C::NT / BK);
+      bool ok = (i < p.m) && (kk >= kb) && (kk < ke);
+      if constexpr (AM == AM_SLT) ok = ok && (kk > i);
+      const int ic = min(i, p.m - 1), kc = min(max(kk, kb), ke - 1);
+      const double v = p.A[kc + (long)ic * p.lda];
+      r[q] = ok ? v : 0.0;
+    }
+  } else {
+    constexpr int RS = C::NT / C::BMc;  // k columns per pass
+#pragma unroll
+    for (int q = 0; q < C::AE; q++) {
+      const int i = i0 + (t % C::BMc), kk = k0 + t / C::BMc + q * RS;
+      bool ok = (i < p.m) && (kk >= kb) && (kk < ke);
+      if constexpr (AM == AM_TRIL) ok = ok && (i >= kk);
+      const int ic = min(i, p.m - 1), kc = min(max(kk, kb), ke - 1);
+      long addr;
+      if constexpr (AM == AM_SYM) {
+        addr = (ic >= kc) ? ic + (long)kc * p.lda : kc + (long)ic * p.lda;
+      } else if constexpr (AM == AM_GATHER) {
+        addr = ic + (long)p.acol[kc] * p.lda;
+      } else {
+        addr = ic + (long)kc * p.lda;
       }
-    } else {
-#pragma unroll
-      for (int q = 0; q < AE; q++) {
-        int i = i0 + (t % BM), kk = k0 + t / BM + q * (NT / BM);
-        double v = 0.0;
-        if (i < p.m && kk >= kb && kk < ke)
-          v = (all_lower || i >= kk) ? p.A[i + (long)kk * p.lda] : p.A[kk + (long)i * p.lda];
-        r[q] = v;
-      }
-    }
-    return;
-  }
-  if (ta == 0) {
-#pragma unroll
-    for (int q = 0; q < AE; q++) {
-      int i = i0 + (t % BM), kk = k0 + t / BM + q * (NT / BM);
-      double v = 0.0;
-      if (i < p.m && kk >= kb && kk < ke) {
-        long col = p.acol ? (long)p.acol[kk] : (long)kk;
-        v = p.A[i + col * p.lda];
-      }
-      r[q] = v;
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < AE; q++) {
-      int kk = k0 + (t % BK), i = i0 + t / BK + q * (NT / BK);
-      r[q] = (i < p.m && kk >= kb && kk < ke) ? p.A[kk + (long)i * p.lda] : 0.0;
+      const double v = p.A[addr];
+      r[q] = ok ? v : 0.0;
     }
   }
 }
 
-template <int BM, int BN>
-HSDM_DEV void store_a(int ta, int flags, int i0, int k0, double* As,
-                      const double (&r)[Cfg<BM, BN>::AE]) {
+template <class C, int TA>
+HSDM_DEV void store_a(double* As, const double (&r)[C::AE]) {
   const int t = threadIdx.x;
-  constexpr int AE = Cfg<BM, BN>::AE, LD = Cfg<BM, BN>::LDA_S;
-  bool trans_pattern = (ta != 0);
-  if (flags & GF_A_SYM_LOWER) trans_pattern = (i0 + BM - 1 < k0);
-  if (!trans_pattern) {
+  if constexpr (TA == 1) {
 #pragma unroll
-    for (int q = 0; q < AE; q++) As[(t / BM + q * (NT / BM)) * LD + (t % BM)] = r[q];
+    for (int q = 0; q < C::AE; q++) As[(t / BK + q * (C::NT / BK)) * C::LDA + (t % BK)] = r[q];
   } else {
+    constexpr int RS = C::NT / C::BMc;
 #pragma unroll
-    for (int q = 0; q < AE; q++) As[(t % BK) * LD + t / BK + q * (NT / BK)] = r[q];
+    for (int q = 0; q < C::AE; q++) As[(t / C::BMc + q * RS) * C::LDA + t % C::BMc] = r[q];
   }
 }
 
-template <int BM, int BN>
-HSDM_DEV void load_b(const Prob& p, int tb, int j0, int k0, int kb, int ke,
-                     double (&r)[Cfg<BM, BN>::BE]) {
+template <class C, int TB>
+HSDM_DEV void load_b(const Prob& p, int j0, int k0, int kb, int ke, double (&r)[C::BE]) {
   const int t = threadIdx.x;
-  constexpr int BE = Cfg<BM, BN>::BE;
-  if (tb == 0) {
-    // op(B)[kk, j] = B[kk + j*ldb]: contiguous along kk
+  if constexpr (TB == 0) {
+    // op(B)[kk, j] = B[kk + j*ldb]: k-contiguous
 #pragma unroll
-    for (int q = 0; q < BE; q++) {
-      int kk = k0 + (t % BK), j = j0 + t / BK + q * (NT / BK);
-      r[q] = (j < p.n && kk >= kb && kk < ke) ? p.B[kk + (long)j * p.ldb] : 0.0;
+    for (int q = 0; q < C::BE; q++) {
+      const int kk = k0 + (t % BK), j = j0 + t / BK + q * (C::NT / BK);
+      const bool ok = (j < p.n) && (kk >= kb) && (kk < ke);
+      const int jc = min(j, p.n - 1), kc = min(max(kk, kb), ke - 1);
+      const double v = p.B[kc + (long)jc * p.ldb];
+      r[q] = ok ? v : 0.0;
     }
   } else {
+    constexpr int RS = C::NT / C::BNc;
 #pragma unroll
-    for (int q = 0; q < BE; q++) {
-      int j = j0 + (t % BN), kk = k0 + t / BN + q * (NT / BN);
-      r[q] = (j < p.n && kk >= kb && kk < ke) ? p.B[j + (long)kk * p.ldb] : 0.0;
+    for (int q = 0; q < C::BE; q++) {
+      const int j = j0 + (t % C::BNc), kk = k0 + t / C::BNc + q * RS;
+      const bool ok = (j < p.n) && (kk >= kb) && (kk < ke);
+      const int jc = min(j, p.n - 1), kc = min(max(kk, kb), ke - 1);
+      const double v = p.B[jc + (long)kc * p.ldb];
+      r[q] = ok ? v : 0.0;
     }
   }
 }
 
-template <int BM, int BN>
-HSDM_DEV void store_b(int tb, double* Bs, const double (&r)[Cfg<BM, BN>::BE]) {
+template <class C, int TB>
+HSDM_DEV void store_b(double* Bs, const double (&r)[C::BE]) {
   const int t = threadIdx.x;
-  constexpr int BE = Cfg<BM, BN>::BE, LD = Cfg<BM, BN>::LDB_S;
-  if (tb == 0) {
+  if constexpr (TB == 0) {
 #pragma unroll
-    for (int q = 0; q < BE; q++) Bs[(t % BK) * LD + t / BK + q * (NT / BK)] = r[q];
+    for (int q = 0; q < C::BE; q++) Bs[(t / BK + q * (C::NT / BK)) * C::LDB + (t % BK)] = r[q];
   } else {
+    constexpr int RS = C::NT / C::BNc;
 #pragma unroll
-    for (int q = 0; q < BE; q++) Bs[(t / BN + q * (NT / BN)) * LD + (t % BN)] = r[q];
+    for (int q = 0; q < C::BE; q++) Bs[(t / C::BNc + q * RS) * C::LDB + t % C::BNc] = r[q];
   }
 }
 
-// Compute one BM x BN output tile.
-template <int BM, int BN>
-HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int ta, int tb, int flags,
-                        int tm, int tn, double* smem, int klo = 0, int khi = 1 << 30) {
-  using C = Cfg<BM, BN>;
+// ---- one output tile -------------------------------------------------------------
+template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
+HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int flags, int tm, int tn,
+                        double* smem, int klo, int khi) {
+  using C = G<BM, BN, WM, WN, TA, TB, AM>;
   const int i0 = tm * BM, j0 = tn * BN;
   int kb = klo, ke = min(p.k, khi);
   if (flags & GF_KA_LOWER) ke = min(ke, i0 + BM);
@@ -149,11 +163,14 @@ HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int ta, int tb
   if (flags & GF_KB_LOWER) kb = max(kb, j0);
   const int kstart = (kb / BK) * BK;
 
-  double* As[2] = {smem, smem + BK * C::LDA_S};
-  double* Bs[2] = {smem + 2 * BK * C::LDA_S, smem + 2 * BK * C::LDA_S + BK * C::LDB_S};
+  double* As0 = smem;
+  double* As1 = smem + C::ASZ;
+  double* Bs0 = smem + 2 * C::ASZ;
+  double* Bs1 = Bs0 + C::BSZ;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % WM, wn = wave / WM;
+  const int l16 = lane & 15, l4 = lane >> 4;
 
   dbl4 acc[C::FM][C::FN];
 #pragma unroll
@@ -162,30 +179,36 @@ HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int ta, int tb
     for (int b = 0; b < C::FN; b++) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   double ra[C::AE], rb[C::BE];
-  int buf = 0;
   if (kstart < ke) {
-    load_a<BM, BN>(p, ta, flags, i0, kstart, kb, ke, ra);
-    load_b<BM, BN>(p, tb, j0, kstart, kb, ke, rb);
-    store_a<BM, BN>(ta, flags, i0, kstart, As[0], ra);
-    store_b<BM, BN>(tb, Bs[0], rb);
+    load_a<C, TA, AM>(p, i0, kstart, kb, ke, ra);
+    load_b<C, TB>(p, j0, kstart, kb, ke, rb);
+    store_a<C, TA>(As0, ra);
+    store_b<C, TB>(Bs0, rb);
   }
   __syncthreads();
+  int buf = 0;
   for (int k0 = kstart; k0 < ke; k0 += BK) {
     const bool more = k0 + BK < ke;
     if (more) {
-      load_a<BM, BN>(p, ta, flags, i0, k0 + BK, kb, ke, ra);
-      load_b<BM, BN>(p, tb, j0, k0 + BK, kb, ke, rb);
+      load_a<C, TA, AM>(p, i0, k0 + BK, kb, ke, ra);
+      load_b<C, TB>(p, j0, k0 + BK, kb, ke, rb);
     }
-    const double* as = As[buf];
-    const double* bs = Bs[buf];
+    const double* as = buf ? As1 : As0;
+    const double* bs = buf ? Bs1 : Bs0;
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
+      const int kr = ks + l4;
       double fa[C::FM], fb[C::FN];
-      const int kr = ks + (lane >> 4);
 #pragma unroll
-      for (int a = 0; a < C::FM; a++) fa[a] = as[kr * C::LDA_S + wm * C::WM + a * 16 + (lane & 15)];
+      for (int a = 0; a < C::FM; a++) {
+        const int row = wm * C::WTM + a * 16 + l16;
+        fa[a] = C::A_KC ? as[row * C::LDA + kr] : as[kr * C::LDA + row];
+      }
 #pragma unroll
-      for (int b = 0; b < C::FN; b++) fb[b] = bs[kr * C::LDB_S + wn * C::WN + b * 16 + (lane & 15)];
+      for (int b = 0; b < C::FN; b++) {
+        const int col = wn * C::WTN + b * 16 + l16;
+        fb[b] = C::B_KC ? bs[col * C::LDB + kr] : bs[kr * C::LDB + col];
+      }
 #pragma unroll
       for (int a = 0; a < C::FM; a++)
 #pragma unroll
@@ -193,8 +216,8 @@ HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int ta, int tb
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
     }
     if (more) {
-      store_a<BM, BN>(ta, flags, i0, k0 + BK, As[buf ^ 1], ra);
-      store_b<BM, BN>(tb, Bs[buf ^ 1], rb);
+      store_a<C, TA>(buf ? As0 : As1, ra);
+      store_b<C, TB>(buf ? Bs0 : Bs1, rb);
     }
     __syncthreads();
     buf ^= 1;
@@ -206,13 +229,13 @@ HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int ta, int tb
   for (int a = 0; a < C::FM; a++)
 #pragma unroll
     for (int b = 0; b < C::FN; b++) {
-      const int col = j0 + wn * C::WN + b * 16 + (lane & 15);
+      const int col = j0 + wn * C::WTN + b * 16 + l16;
       if (col >= p.n) continue;
-      const long ccol = p.ccol ? (long)p.ccol[col] : (long)col;
-      double* cp = p.C + ccol * p.ldc;
+      const long cc = p.ccol ? (long)p.ccol[col] : (long)col;
+      double* cp = p.C + cc * p.ldc;
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        const int row = i0 + wm * C::WM + a * 16 + (lane >> 4) + 4 * r;
+        const int row = i0 + wm * C::WTM + a * 16 + l4 + 4 * r;
         if (row >= p.m) continue;
         if ((flags & GF_C_LOWER_ONLY) && row < col) continue;
         double v = alpha * acc[a][b][r];
@@ -238,15 +261,12 @@ HSDM_DEV bool map_tile(int bid, int nblk, int tiles_m, int tiles_n, int& tm, int
   return true;
 }
 
-template <int BM, int BN>
-constexpr int smem_doubles() {
-  return 2 * BK * (Cfg<BM, BN>::LDA_S + Cfg<BM, BN>::LDB_S);
-}
-
-template <int BM, int BN>
-__global__ __launch_bounds__(NT) void gemm_kernel(Prob p, double alpha, double beta, int ta,
-                                                  int tb, int flags, int kchunk, long split_stride) {
-  __shared__ double smem[smem_doubles<BM, BN>()];
+template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
+__global__ __launch_bounds__(64 * WM * WN, 512 / (64 * WM * WN)) void gemm_kernel(Prob p, double alpha, double beta,
+                                                            int flags, int kchunk,
+                                                            long split_stride) {
+  using C = G<BM, BN, WM, WN, TA, TB, AM>;
+  __shared__ double smem[C::SMEM];
   if (p.ndev) p.n = min(p.n, *p.ndev);
   if (p.n <= 0) return;
   const int tiles_m = (p.m + BM - 1) / BM, tiles_n = (p.n + BN - 1) / BN;
@@ -257,17 +277,18 @@ __global__ __launch_bounds__(NT) void gemm_kernel(Prob p, double alpha, double b
     // split-K: slice blockIdx.y writes its partial product to C + y*split_stride
     const int klo = blockIdx.y * kchunk;
     p.C += (long)blockIdx.y * split_stride;
-    gemm_tile<BM, BN>(p, alpha, 0.0, ta, tb, flags, tm, tn, smem, klo, klo + kchunk);
+    gemm_tile<BM, BN, WM, WN, TA, TB, AM>(p, alpha, 0.0, flags, tm, tn, smem, klo, klo + kchunk);
     return;
   }
-  gemm_tile<BM, BN>(p, alpha, beta, ta, tb, flags, tm, tn, smem);
+  gemm_tile<BM, BN, WM, WN, TA, TB, AM>(p, alpha, beta, flags, tm, tn, smem, 0, 1 << 30);
 }
 
-template <int BM, int BN>
-__global__ __launch_bounds__(NT) void gemm_batched_kernel(const GemmDesc* desc, double alpha,
-                                                          double beta, int ta, int tb,
-                                                          int flags) {
-  __shared__ double smem[smem_doubles<BM, BN>()];
+template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
+__global__ __launch_bounds__(64 * WM * WN, 512 / (64 * WM * WN)) void gemm_batched_kernel(const GemmDesc* desc,
+                                                                    double alpha, double beta,
+                                                                    int flags) {
+  using C = G<BM, BN, WM, WN, TA, TB, AM>;
+  __shared__ double smem[C::SMEM];
   const GemmDesc d = desc[blockIdx.y];
   if (d.m <= 0 || d.n <= 0) return;
   Prob p{d.m, d.n, d.k, d.A, d.lda, d.B, d.ldb, d.C, d.ldc, d.acol, d.ccol, nullptr};
@@ -277,26 +298,16 @@ __global__ __launch_bounds__(NT) void gemm_batched_kernel(const GemmDesc* desc, 
   if ((flags & GF_C_LOWER_TILES) && (tm + 1) * BM - 1 < tn * BN) return;
   if (d.k <= 0) {
     // empty contraction: C = beta * C on the tile
-    const int i = tm * BM + (threadIdx.x % BM);
-    for (int j = tn * BN + threadIdx.x / BM; j < min(p.n, (tn + 1) * BN); j += NT / BM) {
-      if (i >= p.m) break;
-      long cc = p.ccol ? (long)p.ccol[j] : (long)j;
+    for (int e = threadIdx.x; e < BM * BN; e += C::NT) {
+      const int i = tm * BM + e % BM, j = tn * BN + e / BM;
+      if (i >= p.m || j >= p.n) continue;
+      const long cc = p.ccol ? (long)p.ccol[j] : (long)j;
       double* c = p.C + cc * p.ldc + i;
       *c = (beta != 0.0) ? beta * *c : 0.0;
     }
     return;
   }
-  gemm_tile<BM, BN>(p, alpha, beta, ta, tb, flags, tm, tn, smem);
-}
-
-template <int BM, int BN>
-hipError_t launch_single(const GemmArgs& g, hipStream_t s) {
-  Prob p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.acol, g.ccol, g.ndev};
-  long tiles = (long)ceil_div(g.m, BM) * ceil_div(g.n, BN);
-  int nblk = (int)(((tiles + 7) / 8) * 8);
-  hipLaunchKernelGGL((gemm_kernel<BM, BN>), dim3(nblk), dim3(NT), 0, s, p,
-                     g.alpha, g.beta, g.ta, g.tb, g.flags, 0, 0L);
-  return hipGetLastError();
+  gemm_tile<BM, BN, WM, WN, TA, TB, AM>(p, alpha, beta, flags, tm, tn, smem, 0, 1 << 30);
 }
 
 // sum of nsplit partial m x n products (ld m) into C: C = sum + beta C
@@ -325,6 +336,80 @@ __global__ void scale_kernel(int m, int n, double* C, long ldc, double beta, con
   *c = (beta != 0.0) ? beta * *c : 0.0;
 }
 
+// ---- dispatch ----------------------------------------------------------------------
+template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
+hipError_t launch_cfg(const Prob& p, double alpha, double beta, int flags, int nsplit, int kchunk,
+                      long stride, hipStream_t s) {
+  long tiles = (long)ceil_div(p.m, BM) * ceil_div(p.n, BN);
+  int nblk = (int)(((tiles + 7) / 8) * 8);
+  hipLaunchKernelGGL((gemm_kernel<BM, BN, WM, WN, TA, TB, AM>), dim3(nblk, nsplit),
+                     dim3(64 * WM * WN), 0, s, p, alpha, beta, flags, kchunk, stride);
+  return hipGetLastError();
+}
+
+// tile configuration: 0 = 128x128 (8 waves), 1 = 128x64 (4 waves), 2 = 64x64 (4 waves)
+int pick_cfg(int m, int n, int nsplit) {
+  static int forced = -2;
+  if (forced == -2) {
+    const char* e = getenv("HSDM_GEMM_CFG");
+    forced = e ? atoi(e) : -1;
+  }
+  if (forced >= 0 && forced <= 2) return forced;
+  const long t128 = (long)ceil_div(m, 128) * ceil_div(n, 128) * nsplit;
+  const long t12864 = (long)ceil_div(m, 128) * ceil_div(n, 64) * nsplit;
+  if (t128 >= 512) return 0;
+  if (t12864 >= 512) return 1;
+  return 2;
+}
+
+template <int TA, int TB, int AM>
+hipError_t launch_t(const Prob& p, double alpha, double beta, int flags, int nsplit, int kchunk,
+                    long stride, hipStream_t s) {
+  switch (pick_cfg(p.m, p.n, nsplit)) {
+    case 0:
+      return launch_cfg<128, 128, 2, 4, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
+                                                    s);
+    case 1:
+      return launch_cfg<128, 64, 2, 2, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
+                                                   s);
+    default:
+      return launch_cfg<64, 64, 2, 2, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
+                                                  s);
+  }
+}
+
+hipError_t launch_any(const Prob& p, int ta, int tb, int am, double alpha, double beta, int flags,
+                      int nsplit, int kchunk, long stride, hipStream_t s) {
+  if (am == AM_TRIL) {
+    if (tb) return launch_t<0, 1, AM_TRIL>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+    return launch_t<0, 0, AM_TRIL>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+  }
+  if (am == AM_SLT) {
+    if (tb) return launch_t<1, 1, AM_SLT>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+    return launch_t<1, 0, AM_SLT>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+  }
+  if (am == AM_SYM) return launch_t<0, 0, AM_SYM>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+  if (am == AM_GATHER) {
+    if (tb) return launch_t<0, 1, AM_GATHER>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+    return launch_t<0, 0, AM_GATHER>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+  }
+  if (ta == 0 && tb == 0)
+    return launch_t<0, 0, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+  if (ta == 0 && tb == 1)
+    return launch_t<0, 1, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+  if (ta == 1 && tb == 0)
+    return launch_t<1, 0, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+  return launch_t<1, 1, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+}
+
+int a_mode(const GemmArgs& g) {
+  if (g.flags & GF_A_TRIL) return AM_TRIL;
+  if (g.flags & GF_A_SLT) return AM_SLT;
+  if (g.flags & GF_A_SYM_LOWER) return AM_SYM;
+  if (g.acol) return AM_GATHER;
+  return AM_DENSE;
+}
+
 }  // namespace
 
 hipError_t gemm_launch(const GemmArgs& g, hipStream_t s) {
@@ -336,24 +421,22 @@ hipError_t gemm_launch(const GemmArgs& g, hipStream_t s) {
                        g.n, g.C, g.ldc, g.beta, g.ccol, g.ndev);
     return hipGetLastError();
   }
-  // Large outputs: 128x128 tiles; otherwise 64x64 to keep >= 256 workgroups.
-  long big_tiles = (long)ceil_div(g.m, 128) * ceil_div(g.n, 128);
-  if (big_tiles >= 512) return launch_single<128, 128>(g, s);
-  return launch_single<64, 64>(g, s);
+  const int am = a_mode(g);
+  if ((am == AM_SYM || am == AM_GATHER || am == AM_TRIL) && g.ta != 0) return hipErrorInvalidValue;
+  if (am == AM_SLT && g.ta != 1) return hipErrorInvalidValue;
+  Prob p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.acol, g.ccol, g.ndev};
+  return launch_any(p, g.ta, g.tb, am, g.alpha, g.beta, g.flags, 1, 0, 0L, s);
 }
 
 hipError_t gemm_splitk_launch(const GemmArgs& g, int kchunk, double* part, hipStream_t s) {
   if (g.m <= 0 || g.n <= 0) return hipSuccess;
   if (g.k <= kchunk || kchunk <= 0) return gemm_launch(g, s);
-  if (g.ccol || (g.flags & (GF_C_LOWER_ONLY | GF_C_LOWER_TILES))) return hipErrorInvalidValue;
+  if (g.ccol || (g.flags & (GF_C_LOWER_ONLY | GF_C_LOWER_TILES)) || a_mode(g) != AM_DENSE)
+    return hipErrorInvalidValue;
   const int nsplit = ceil_div(g.k, kchunk);
   Prob p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, part, (long)g.m, g.acol, nullptr, g.ndev};
   const long stride = (long)g.m * g.n;
-  long tiles = (long)ceil_div(g.m, 64) * ceil_div(g.n, 64);
-  int nblk = (int)(((tiles + 7) / 8) * 8);
-  hipLaunchKernelGGL((gemm_kernel<64, 64>), dim3(nblk, nsplit), dim3(NT), 0, s, p, g.alpha, 0.0,
-                     g.ta, g.tb, g.flags, kchunk, stride);
-  HSDM_TRY(hipGetLastError());
+  HSDM_TRY(launch_any(p, g.ta, g.tb, AM_DENSE, g.alpha, 0.0, g.flags, nsplit, kchunk, stride, s));
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((stride + 255) / 256)), dim3(256), 0, s,
                      g.m, g.n, nsplit, part, g.C, g.ldc, g.beta, g.ndev);
   return hipGetLastError();
@@ -363,9 +446,10 @@ hipError_t gemm_batched_launch(const GemmDesc* d_desc, int count, int max_m, int
                                double alpha, double beta, int ta, int tb, int flags,
                                hipStream_t s) {
   if (count <= 0 || max_m <= 0 || max_n <= 0) return hipSuccess;
+  if (ta != 0 || tb != 0) return hipErrorInvalidValue;
   long tiles = (long)ceil_div(max_m, 64) * ceil_div(max_n, 64);
   int nblk = (int)(((tiles + 7) / 8) * 8);
-  hipLaunchKernelGGL((gemm_batched_kernel<64, 64>), dim3(nblk, count), dim3(NT), 0, s,
-                     d_desc, alpha, beta, ta, tb, flags);
+  hipLaunchKernelGGL((gemm_batched_kernel<64, 64, 2, 2, 0, 0, AM_GATHER>), dim3(nblk, count),
+                     dim3(256), 0, s, d_desc, alpha, beta, flags);
   return hipGetLastError();
 }

@@ -20,6 +20,8 @@ enum GemmFlags {
   GF_KB_UPPER = 16,       // op(B) upper triangular: column j only needs k <= j
   GF_KB_LOWER = 32,       // op(B) lower triangular: column j only needs k >= j
   GF_A_SYM_LOWER = 64,    // A symmetric, only its lower triangle is read (m == k)
+  GF_A_TRIL = 128,        // op(A) = lower triangle of A (diagonal included), ta = 0
+  GF_A_SLT = 256,         // op(A) = transpose of the strict lower triangle of A, ta = 1
 };
 
 struct GemmArgs {

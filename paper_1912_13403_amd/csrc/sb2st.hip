@@ -44,9 +44,11 @@ HSDM_DEV double wsum(double v) {
 HSDM_DEV double hsum(double v) { return v + __shfl_xor(v, 32, 64); }
 
 HSDM_DEV void wait_ge(int* p, int target, DevStatusWord* st) {
+  // poll with relaxed loads (an acquire per poll would invalidate the L2 each
+  // time); one acquire fence once the counter is reached
   if ((threadIdx.x & 63) == 0) {
     long spins = 0;
-    while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       ++spins;
       if (spins > (1L << 27) ||
           ((spins & 4095) == 0 &&
@@ -57,6 +59,7 @@ HSDM_DEV void wait_ge(int* p, int target, DevStatusWord* st) {
       __builtin_amdgcn_s_sleep(1);
     }
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   wave_sync();
 }
 

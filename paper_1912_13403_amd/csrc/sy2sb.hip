@@ -33,7 +33,7 @@ HSDM_DEV void grid_sync(unsigned* bar, unsigned nblk, unsigned& epoch, DevStatus
     __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned target = epoch * nblk;
     long spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       ++spins;
       if (spins > (1L << 26) ||
           ((spins & 4095) == 0 &&
@@ -44,6 +44,8 @@ HSDM_DEV void grid_sync(unsigned* bar, unsigned nblk, unsigned& epoch, DevStatus
       __builtin_amdgcn_s_sleep(1);
     }
   }
+  // poll relaxed; one agent-scope acquire once the barrier is complete
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   __syncthreads();
 }
 
@@ -276,11 +278,15 @@ hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, d
     g.m = h; g.n = B; g.k = B; g.A = Vp; g.lda = ldv; g.B = Tp; g.ldb = B; g.C = Y; g.ldc = n;
     g.alpha = 1.0; g.beta = 0.0; g.flags = GF_KB_UPPER;
     HSDM_TRY(gemm_launch(g, s));
-    // X = A22 Y  -> VW[:, B:2B]
+    // X = A22 Y  -> VW[:, B:2B], A22 symmetric with its lower triangle stored:
+    // X = tril(A22) Y + strict_tril(A22)^T Y, both passes reading the lower
+    // triangle with coalesced loads
     double* Xp = VW + (size_t)n * B;
     g = GemmArgs{};
     g.m = h; g.n = B; g.k = h; g.A = A22; g.lda = lda; g.B = Y; g.ldb = n; g.C = Xp; g.ldc = n;
-    g.alpha = 1.0; g.beta = 0.0; g.flags = GF_A_SYM_LOWER;
+    g.alpha = 1.0; g.beta = 0.0; g.flags = GF_A_TRIL | GF_KA_LOWER;
+    HSDM_TRY(gemm_launch(g, s));
+    g.ta = 1; g.beta = 1.0; g.flags = GF_A_SLT | GF_KA_UPPER;
     HSDM_TRY(gemm_launch(g, s));
     // M = Y^T X
     hipLaunchKernelGGL((atb_partial_kernel<BB>), dim3(G), dim3(NT), 0, s, h, Y, (long)n, Xp,
