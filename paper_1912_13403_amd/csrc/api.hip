@@ -248,6 +248,7 @@ int standard_form(hsdm_ctx* h, int n, const double* H, int ldh, const double* Li
 
 // Two-stage reduction of h->Abuf (lower) to (dvec, evec); reflectors kept.
 int reduce(hsdm_ctx* h, int n, hipStream_t s, int phase_band) {
+  DEV_TRY(h, bt1_zero_fill(n, BAND, h->Vst, n, s));
   DEV_TRY(h, sy2sb_run(n, BAND, h->Abuf, n, h->Vst, n, h->tau1, h->T1, h->AB, 2 * BAND, h->sy_scr,
                        h->bar, h->st, s));
   mark(h, phase_band, s);

@@ -201,34 +201,125 @@ hipError_t bt2_apply(const Sb2stLayout& L, const double* V2, const double* T2, c
   return hipSuccess;
 }
 
+namespace {
+
+// ---- stage 1 ------------------------------------------------------------------
+// GP consecutive panels form one block reflector of width GP*B:
+//   (I - V1 T1 V1^T)(I - V2 T2 V2^T) = I - [V1 V2] [[T1, -T1 V1^T V2 T2], [0, T2]] [V1 V2]^T
+// applied panel group by panel group, last group first.  The explicit panel
+// reflectors are zero above their first row, so the grouped V is dense with a
+// staircase of zeros.
+constexpr int GP = 4;
+
+// T of one panel group from the per-panel T's and the Gram G = V^T V (ld W).
+__global__ __launch_bounds__(256) void group_t1_kernel(int np, int Bp, const double* T1p,
+                                                       const double* Gm, double* Tq) {
+  const int W = np * Bp;
+  __shared__ double X[3 * 32 * 32];  // (i*Bp) x Bp block, i <= 3, Bp <= 32
+  const int t = threadIdx.x;
+  for (int e = t; e < W * W; e += 256) {
+    const int r = e % W, c = e / W;
+    const int pr = r / Bp, pc = c / Bp;
+    Tq[r + (long)c * W] = (pr == pc) ? T1p[(size_t)pr * Bp * Bp + (r % Bp) + (c % Bp) * Bp] : 0.0;
+  }
+  __syncthreads();
+  for (int i = 1; i < np; i++) {
+    const int rows = i * Bp;
+    const double* Ti = T1p + (size_t)i * Bp * Bp;
+    // X = G[0:rows, iBp:(i+1)Bp] * T_i
+    for (int e = t; e < rows * Bp; e += 256) {
+      const int r = e % rows, c = e / rows;
+      double acc = 0.0;
+      for (int q = 0; q <= c; q++) acc += Gm[r + (long)(rows + q) * W] * Ti[q + c * Bp];
+      X[r + c * rows] = acc;
+    }
+    __syncthreads();
+    // Tq[0:rows, block] = -Tq[0:rows, 0:rows] * X  (Tq upper triangular)
+    for (int e = t; e < rows * Bp; e += 256) {
+      const int r = e % rows, c = e / rows;
+      double acc = 0.0;
+      for (int q = r; q < rows; q++) acc += Tq[r + (long)q * W] * X[q + c * rows];
+      Tq[r + (long)(rows + c) * W] = -acc;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void zero_upper_panels_kernel(int n, int B_, double* Vst, long ldv) {
+  // rows above each panel's first reflector row: Vst[0 : (p+1)B, pB : (p+1)B] = 0
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = (int)(idx / n), r = (int)(idx % n);
+  if (c >= n) return;
+  const int p = c / B_;
+  if (r < (p + 1) * B_) Vst[r + (long)c * ldv] = 0.0;
+}
+
+}  // namespace
+
+static int npanel_of(int n, int B_) { return (n > B_) ? ceil_div(n - 1, B_) : 0; }
+
 size_t bt1_scratch_doubles(int n, int B_, int m) {
-  const int nsplit = ceil_div(n, 1024) + 1;
-  return (size_t)B_ * m * (2 + nsplit) + 64;
+  const size_t W = (size_t)GP * B_;
+  const size_t nsplit = ceil_div(n, 1024) + 1;
+  const size_t ngroup = ceil_div(npanel_of(n, B_), GP) + 1;
+  // W, W2 (W x m), split-K partials (nsplit x W x m), Gram + partials, T of each group
+  return W * m * (2 + nsplit) + W * W * (1 + nsplit) + ngroup * W * W + 64;
+}
+
+hipError_t bt1_zero_fill(int n, int B_, double* Vst, long ldv, hipStream_t s) {
+  const long tot = (long)n * n;
+  hipLaunchKernelGGL(zero_upper_panels_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                     s, n, B_, Vst, ldv);
+  return hipGetLastError();
 }
 
 hipError_t bt1_apply(int n, int B_, const double* Vst, long ldv, const double* T1, double* Z,
                      long ldz, int m, const int* m_dev, double* scratch, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  double* W = scratch;
-  double* W2 = W + (size_t)B_ * m;
-  double* part = W2 + (size_t)B_ * m;
-  const int npanel = (n > B_) ? ceil_div(n - 1, B_) : 0;
-  for (int p = npanel - 1; p >= 0; p--) {
-    const int c0 = p * B_, r0 = c0 + B_, h = n - r0;
+  const int np_all = npanel_of(n, B_);
+  if (np_all == 0) return hipSuccess;
+  const int W = GP * B_;
+  const size_t nsplit = ceil_div(n, 1024) + 1;
+  double* Wb = scratch;
+  double* W2 = Wb + (size_t)W * m;
+  double* part = W2 + (size_t)W * m;
+  double* Gm = part + nsplit * W * m;
+  double* Gpart = Gm + (size_t)W * W;
+  double* Tall = Gpart + nsplit * W * W;
+  const int ngroup = ceil_div(np_all, GP);
+  // T factors of the panel groups
+  for (int q = 0; q < ngroup; q++) {
+    const int p0 = q * GP, np = min(GP, np_all - p0);
+    const int r0 = (p0 + 1) * B_, h = n - r0, w = np * B_;
+    const double* Vq = Vst + r0 + (long)p0 * B_ * ldv;
+    double* Tq = Tall + (size_t)q * W * W;
+    if (np > 1) {
+      GemmArgs g{};
+      g.m = w; g.n = w; g.k = h; g.A = Vq; g.lda = ldv; g.B = Vq; g.ldb = ldv; g.C = Gm; g.ldc = w;
+      g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
+      HSDM_TRY(gemm_splitk_launch(g, 1024, Gpart, s));
+    }
+    hipLaunchKernelGGL(group_t1_kernel, dim3(1), dim3(256), 0, s, np, B_,
+                       T1 + (size_t)p0 * B_ * B_, Gm, Tq);
+    HSDM_TRY(hipGetLastError());
+  }
+  for (int q = ngroup - 1; q >= 0; q--) {
+    const int p0 = q * GP, np = min(GP, np_all - p0);
+    const int r0 = (p0 + 1) * B_, h = n - r0, w = np * B_;
     if (h <= 0) continue;
-    const double* Vp = Vst + r0 + (long)c0 * ldv;
-    const double* Tp = T1 + (size_t)p * B_ * B_;
-    double* Zp = Z + r0;
+    const double* Vq = Vst + r0 + (long)p0 * B_ * ldv;
+    const double* Tq = Tall + (size_t)q * W * W;
+    double* Zq = Z + r0;
     GemmArgs g{};
-    g.m = B_; g.n = m; g.k = h; g.A = Vp; g.lda = ldv; g.B = Zp; g.ldb = ldz; g.C = W; g.ldc = B_;
+    g.m = w; g.n = m; g.k = h; g.A = Vq; g.lda = ldv; g.B = Zq; g.ldb = ldz; g.C = Wb; g.ldc = w;
     g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.ndev = m_dev;
     HSDM_TRY(gemm_splitk_launch(g, 1024, part, s));
     g = GemmArgs{};
-    g.m = B_; g.n = m; g.k = B_; g.A = Tp; g.lda = B_; g.B = W; g.ldb = B_; g.C = W2; g.ldc = B_;
+    g.m = w; g.n = m; g.k = w; g.A = Tq; g.lda = w; g.B = Wb; g.ldb = w; g.C = W2; g.ldc = w;
     g.alpha = 1.0; g.beta = 0.0; g.flags = GF_KA_UPPER; g.ndev = m_dev;
     HSDM_TRY(gemm_launch(g, s));
     g = GemmArgs{};
-    g.m = h; g.n = m; g.k = B_; g.A = Vp; g.lda = ldv; g.B = W2; g.ldb = B_; g.C = Zp; g.ldc = ldz;
+    g.m = h; g.n = m; g.k = w; g.A = Vq; g.lda = ldv; g.B = W2; g.ldb = w; g.C = Zq; g.ldc = ldz;
     g.alpha = -1.0; g.beta = 1.0; g.ndev = m_dev;
     HSDM_TRY(gemm_launch(g, s));
   }

@@ -347,7 +347,8 @@ hipError_t launch_cfg(const Prob& p, double alpha, double beta, int flags, int n
   return hipGetLastError();
 }
 
-// tile configuration: 0 = 128x128 (8 waves), 1 = 128x64 (4 waves), 2 = 64x64 (4 waves)
+// tile configuration: 0 = 128x128 (8 waves), 1 = 128x64 (4 waves), 2 = 64x64 (4 waves),
+// 3 = 128x32 (4 waves, skinny n), 4 = 32x128 (4 waves, skinny m)
 int pick_cfg(int m, int n, int nsplit) {
   static int forced = -2;
   if (forced == -2) {
@@ -355,6 +356,8 @@ int pick_cfg(int m, int n, int nsplit) {
     forced = e ? atoi(e) : -1;
   }
   if (forced >= 0 && forced <= 2) return forced;
+  if (n <= 32) return 3;
+  if (m <= 32) return 4;
   const long t128 = (long)ceil_div(m, 128) * ceil_div(n, 128) * nsplit;
   const long t12864 = (long)ceil_div(m, 128) * ceil_div(n, 64) * nsplit;
   if (t128 >= 512) return 0;
@@ -371,6 +374,12 @@ hipError_t launch_t(const Prob& p, double alpha, double beta, int flags, int nsp
                                                     s);
     case 1:
       return launch_cfg<128, 64, 2, 2, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
+                                                   s);
+    case 3:
+      return launch_cfg<128, 32, 4, 1, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
+                                                   s);
+    case 4:
+      return launch_cfg<32, 128, 1, 4, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
                                                    s);
     default:
       return launch_cfg<64, 64, 2, 2, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
@@ -431,12 +440,15 @@ hipError_t gemm_launch(const GemmArgs& g, hipStream_t s) {
 hipError_t gemm_splitk_launch(const GemmArgs& g, int kchunk, double* part, hipStream_t s) {
   if (g.m <= 0 || g.n <= 0) return hipSuccess;
   if (g.k <= kchunk || kchunk <= 0) return gemm_launch(g, s);
-  if (g.ccol || (g.flags & (GF_C_LOWER_ONLY | GF_C_LOWER_TILES)) || a_mode(g) != AM_DENSE)
+  const int am = a_mode(g);
+  if (g.ccol || (g.flags & (GF_C_LOWER_ONLY | GF_C_LOWER_TILES)) || am == AM_GATHER ||
+      am == AM_SYM)
     return hipErrorInvalidValue;
+  if ((am == AM_TRIL && g.ta != 0) || (am == AM_SLT && g.ta != 1)) return hipErrorInvalidValue;
   const int nsplit = ceil_div(g.k, kchunk);
   Prob p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, part, (long)g.m, g.acol, nullptr, g.ndev};
   const long stride = (long)g.m * g.n;
-  HSDM_TRY(launch_any(p, g.ta, g.tb, AM_DENSE, g.alpha, 0.0, g.flags, nsplit, kchunk, stride, s));
+  HSDM_TRY(launch_any(p, g.ta, g.tb, am, g.alpha, 0.0, g.flags, nsplit, kchunk, stride, s));
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((stride + 255) / 256)), dim3(256), 0, s,
                      g.m, g.n, nsplit, part, g.C, g.ldc, g.beta, g.ndev);
   return hipGetLastError();

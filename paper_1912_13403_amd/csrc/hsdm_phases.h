@@ -35,8 +35,11 @@ hipError_t bt2_prepare(const Sb2stLayout& L, const double* V2, const double* tau
                        const long* d_goff, hipStream_t s);
 hipError_t bt2_apply(const Sb2stLayout& L, const double* V2, const double* T2, const long* d_goff,
                      double* Z, long ldz, int m, const int* m_dev, hipStream_t s);
-// Z (n x m) <- Q1 Z, the stage-1 panel reflectors (I - V T V^T), last panel first.
+// Z (n x m) <- Q1 Z, the stage-1 panel reflectors (I - V T V^T), applied in
+// groups of 4 panels, last group first.  Vst must hold zeros above each
+// panel's first reflector row (bt1_zero_fill, before the reduction).
 size_t bt1_scratch_doubles(int n, int B, int m);
+hipError_t bt1_zero_fill(int n, int B, double* Vst, long ldv, hipStream_t s);
 hipError_t bt1_apply(int n, int B, const double* Vst, long ldv, const double* T1, double* Z,
                      long ldz, int m, const int* m_dev, double* scratch, hipStream_t s);
 

@@ -347,12 +347,24 @@ __global__ __launch_bounds__(256) void build_qblk_kernel(int n, const double* Qc
   }
 }
 
-// Secular equation, one root per thread.
+HSDM_DEV double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+HSDM_DEV double wave_prod(double v) {
+  for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Secular equation, one root per wavefront (the sums over the k poles are
+// split over the 64 lanes and combined in a fixed order).
 __global__ __launch_bounds__(256) void secular_kernel(LevelBufs b, int m0, DevStatusWord* st) {
   const int mi = m0 + blockIdx.y;
   const int lo = b.merges[3 * mi];
   const int k = b.meta[(long)mi * META];
-  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= k) return;
   const double rho = b.rho[mi];
   const double* dk = b.dk + lo;
@@ -362,8 +374,9 @@ __global__ __launch_bounds__(256) void secular_kernel(LevelBufs b, int m0, DevSt
   if (j < k - 1) {
     const double gap = dk[j + 1] - dk[j];
     const double mid = 0.5 * gap;
-    double f = 1.0 / rho;
-    for (int i = 0; i < k; i++) f += zk[i] * zk[i] / ((dk[i] - dk[j]) - mid);
+    double f = 0.0;
+    for (int i = lane; i < k; i += 64) f += zk[i] * zk[i] / ((dk[i] - dk[j]) - mid);
+    f = 1.0 / rho + wave_sum(f);
     if (f >= 0.0) {
       o = j; tl = 0.0; th = mid;
     } else {
@@ -371,7 +384,8 @@ __global__ __launch_bounds__(256) void secular_kernel(LevelBufs b, int m0, DevSt
     }
   } else {
     double zz = 0.0;
-    for (int i = 0; i < k; i++) zz += zk[i] * zk[i];
+    for (int i = lane; i < k; i += 64) zz += zk[i] * zk[i];
+    zz = wave_sum(zz);
     o = j; tl = 0.0; th = rho * zz * (1.0 + 8.0 * DBL_EPSILON);
   }
   const double dorg = dk[o];
@@ -380,12 +394,16 @@ __global__ __launch_bounds__(256) void secular_kernel(LevelBufs b, int m0, DevSt
   bool conv = false;
   for (int it = 0; it < 100; it++) {
     double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
-    for (int i = 0; i < k; i++) {
+    for (int i = lane; i < k; i += 64) {
       const double del = (dk[i] - dorg) - tau;
       const double q = zk[i] / del;
       if (i <= j) { psi += zk[i] * q; dpsi += q * q; }
       else { phi += zk[i] * q; dphi += q * q; }
     }
+    psi = wave_sum(psi);
+    dpsi = wave_sum(dpsi);
+    phi = wave_sum(phi);
+    dphi = wave_sum(dphi);
     const double f = 1.0 / rho + psi + phi;
     if (f == 0.0) { conv = true; break; }
     if (f < 0.0) tl = tau; else th = tau;
@@ -419,29 +437,34 @@ __global__ __launch_bounds__(256) void secular_kernel(LevelBufs b, int m0, DevSt
     tau = tn;
     if (small) { conv = true; break; }
   }
-  if (!conv) dev_set_status(st, DS_NO_CONVERGE, 2);
-  b.rorg[lo + j] = o;
-  b.rtau[lo + j] = tau;
-  b.rlam[lo + j] = dorg + tau;
+  if (lane == 0) {
+    if (!conv) dev_set_status(st, DS_NO_CONVERGE, 2);
+    b.rorg[lo + j] = o;
+    b.rtau[lo + j] = tau;
+    b.rlam[lo + j] = dorg + tau;
+  }
 }
 
-// Loewner: z_i from the roots.
+// Loewner: z_i from the roots, one wavefront per i (the product over the
+// roots is split over the lanes; every factor is a ratio below one).
 __global__ __launch_bounds__(256) void zhat_kernel(LevelBufs b, int m0) {
   const int mi = m0 + blockIdx.y;
   const int lo = b.merges[3 * mi];
   const int k = b.meta[(long)mi * META];
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= k) return;
   const double rho = b.rho[mi];
   const double* dk = b.dk + lo;
   const double di = dk[i];
-  double p = ((dk[b.rorg[lo + k - 1]] - di) + b.rtau[lo + k - 1]) / rho;
-  for (int j = 0; j < k - 1; j++) {
+  double p = 1.0;
+  for (int j = lane; j < k - 1; j += 64) {
     const double num = (dk[b.rorg[lo + j]] - di) + b.rtau[lo + j];
     const double den = (j < i) ? (dk[j] - di) : (dk[j + 1] - di);
     p *= num / den;
   }
-  b.zhat[lo + i] = copysign(sqrt(fmax(p, 0.0)), b.zk[lo + i]);
+  p = wave_prod(p) * (((dk[b.rorg[lo + k - 1]] - di) + b.rtau[lo + k - 1]) / rho);
+  if (lane == 0) b.zhat[lo + i] = copysign(sqrt(fmax(p, 0.0)), b.zk[lo + i]);
 }
 
 // Order of the merged eigenvalues (roots and deflated values), ascending;
@@ -709,9 +732,9 @@ hipError_t stedc_run(StedcPlan* p, const double* d, const double* e, double* lam
     hipLaunchKernelGGL(build_qblk_kernel, dim3(ceil_div(maxN, 256), cnt), dim3(256), 0, s, n, Qcur,
                        (long)n, b, m0);
     HSDM_TRY(hipGetLastError());
-    hipLaunchKernelGGL(secular_kernel, dim3(ceil_div(maxN, 256), cnt), dim3(256), 0, s, b, m0, st);
+    hipLaunchKernelGGL(secular_kernel, dim3(ceil_div(maxN, 4), cnt), dim3(256), 0, s, b, m0, st);
     HSDM_TRY(hipGetLastError());
-    hipLaunchKernelGGL(zhat_kernel, dim3(ceil_div(maxN, 256), cnt), dim3(256), 0, s, b, m0);
+    hipLaunchKernelGGL(zhat_kernel, dim3(ceil_div(maxN, 4), cnt), dim3(256), 0, s, b, m0);
     HSDM_TRY(hipGetLastError());
     hipLaunchKernelGGL(order_kernel, dim3(ceil_div(maxN, 256), cnt), dim3(256), 0, s, lam, b, m0);
     HSDM_TRY(hipGetLastError());

@@ -24,7 +24,8 @@
 namespace {
 
 constexpr int NT = 256;
-constexpr int CH = 256;  // panel rows per workgroup
+constexpr int CH = 256;      // panel rows per workgroup
+constexpr int SPLITK = 1024; // K slice of the symmetric product X = A22 Y
 
 HSDM_DEV void grid_sync(unsigned* bar, unsigned nblk, unsigned& epoch, DevStatusWord* st) {
   __syncthreads();
@@ -99,10 +100,17 @@ __global__ __launch_bounds__(NT) void panel_qr_kernel(int h, double* P, long ldp
       if (g == 0) rb[t] = Pl[j][t];  // pivot row (global row j lives in group 0)
     }
     grid_sync(bar, G, epoch, st);
+    {
+      // RG threads per column sum strided subsets, then a fixed-order combine
+      double a = 0.0;
+      if (c >= j)
+        for (int q = rg; q < G; q += RG) a += pb[(size_t)q * B + c];
+      red[rg][c] = a;
+    }
+    __syncthreads();
     if (t < B) {
       double a = 0.0;
-      if (t >= j)
-        for (int q = 0; q < G; q++) a += pb[(size_t)q * B + t];
+      for (int r = 0; r < RG; r++) a += red[r][t];
       ddl[t] = a;
     }
     __syncthreads();
@@ -236,7 +244,10 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
 size_t sy2sb_scratch_doubles(int n, int B) {
   const int G = ceil_div(n, CH) + 1;
   // part(2GB) + prow(2B) + gpart(G B^2) + atb parts(G B^2) + Y,VW,WV (n x 2B each) + M (B^2)
-  return (size_t)2 * G * B + 2 * B + (size_t)2 * G * B * B + (size_t)5 * n * 2 * B + B * B + 64;
+  // + split-K partials of X (nsplit x n x B)
+  const size_t nsplit = ceil_div(n, SPLITK) + 1;
+  return (size_t)2 * G * B + 2 * B + (size_t)2 * G * B * B + (size_t)5 * n * 2 * B + B * B + 64 +
+         nsplit * n * B;
 }
 
 hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, double* tau1,
@@ -253,6 +264,7 @@ hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, d
   double* VW = Y + (size_t)n * B;                // n x 2B  [V W]
   double* WV = VW + (size_t)n * 2 * B;           // n x 2B  [W V]
   double* M = WV + (size_t)n * 2 * B;            // B x B
+  double* skpart = M + B * B + 64;               // split-K partials
 
   const int npanel = (n > B) ? ceil_div(n - 1, B) : 0;
   for (int p = 0; p < npanel; p++) {
@@ -285,9 +297,9 @@ hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, d
     g = GemmArgs{};
     g.m = h; g.n = B; g.k = h; g.A = A22; g.lda = lda; g.B = Y; g.ldb = n; g.C = Xp; g.ldc = n;
     g.alpha = 1.0; g.beta = 0.0; g.flags = GF_A_TRIL | GF_KA_LOWER;
-    HSDM_TRY(gemm_launch(g, s));
+    HSDM_TRY(gemm_splitk_launch(g, SPLITK, skpart, s));
     g.ta = 1; g.beta = 1.0; g.flags = GF_A_SLT | GF_KA_UPPER;
-    HSDM_TRY(gemm_launch(g, s));
+    HSDM_TRY(gemm_splitk_launch(g, SPLITK, skpart, s));
     // M = Y^T X
     hipLaunchKernelGGL((atb_partial_kernel<BB>), dim3(G), dim3(NT), 0, s, h, Y, (long)n, Xp,
                        (long)n, apart);
