@@ -206,7 +206,10 @@ int finish(hsdm_ctx* h, hipStream_t s) {
       h->s_valid = false;
       h->err = "S is not positive definite (column " + std::to_string(h->detail) + ")";
       return HSDM_NOT_SPD;
-    case DS_NO_CONVERGE: h->err = "eigenvalue iteration did not converge"; return HSDM_NO_CONVERGE;
+    case DS_NO_CONVERGE:
+      h->err = std::string("eigenvalue iteration did not converge (") +
+               (h->detail == 1 ? "leaf QL" : "secular equation") + ")";
+      return HSDM_NO_CONVERGE;
     case DS_MU_FAIL: h->err = "chemical potential search failed"; return HSDM_MU_FAIL;
     default:
       h->s_valid = false;

@@ -19,7 +19,6 @@ namespace {
 
 constexpr int B = 32;
 constexpr int H2 = 2 * B;  // rows of a group
-constexpr int SW = 64;     // columns of Z per workgroup
 
 // T factor of every group: T_jj = tau_j, T(0:j, j) = -tau_j T(0:j,0:j) V^T v_j
 __global__ __launch_bounds__(256) void group_t_kernel(const double* V2, const double* tau2,
@@ -56,8 +55,13 @@ __global__ __launch_bounds__(256) void group_t_kernel(const double* V2, const do
   for (int e = t; e < B * B; e += 256) T[e] = Tl[e % B][e / B];
 }
 
-// Apply the groups of one level to Z.
-__global__ __launch_bounds__(256, 2) void group_apply_kernel(int n, int nblk, int level, int sb_lo,
+// Apply the groups of one level to Z: workgroup (group, slab of 128 columns),
+// 8 wavefronts.  Z block (2B x 128) and W (B x 128) live in LDS; V and T are
+// read from L2.  Zero 16x16 blocks of the parallelogram V are skipped:
+// V(r, c) != 0 only for c <= r <= c + B - 1.
+constexpr int SWA = 128;
+
+__global__ __launch_bounds__(512) void group_apply_kernel(int n, int nblk, int level, int sb_lo,
                                                           const double* V2, const double* T2,
                                                           const long* goff, double* Z, long ldz,
                                                           int m_host, const int* m_dev) {
@@ -66,94 +70,85 @@ __global__ __launch_bounds__(256, 2) void group_apply_kernel(int n, int nblk, in
   const int tg = (n - 1 - sb * B + B - 1) / B;
   if (t < 0 || t >= tg) return;
   const int m = m_dev ? *m_dev : m_host;
-  const int c0 = blockIdx.y * SW;
+  const int c0 = blockIdx.y * SWA;
   if (c0 >= m) return;
-  const int nc = min(SW, m - c0);
+  const int nc = min(SWA, m - c0);
   const int rb = sb * B + 1 + t * B;
   const int hh = min(H2, n - rb);
   const long gi = goff[sb] + t;
-  const double* V = V2 + gi * H2 * B;
-  const double* T = T2 + gi * B * B;
+  const double* V = V2 + gi * H2 * B;   // (H2 x B), column-major
+  const double* T = T2 + gi * B * B;    // (B x B), column-major
 
-  __shared__ double Vs[H2][B + 1];
-  __shared__ double Ts[B][B + 1];
-  __shared__ double Zs[H2][SW + 1];
-  __shared__ double Ws[B][SW + 1];
-  __shared__ double W2s[B][SW + 1];
+  __shared__ double Zs[H2][SWA + 1];
+  __shared__ double Ws[B][SWA + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int e = tid; e < H2 * B; e += 256) Vs[e % H2][e / H2] = V[e];
-  for (int e = tid; e < B * B; e += 256) Ts[e % B][e / B] = T[e];
-  for (int e = tid; e < H2 * SW; e += 256) {
+  const int l16 = lane & 15, l4 = lane >> 4;
+  for (int e = tid; e < H2 * SWA; e += 512) {
     const int r = e % H2, c = e / H2;
     Zs[r][c] = (r < hh && c < nc) ? Z[rb + r + (long)(c0 + c) * ldz] : 0.0;
   }
   __syncthreads();
-  const int l16 = lane & 15, l4 = lane >> 4;
-  // W = V^T Zs  (B x SW): wave w -> row block (w & 1), column blocks 2*(w>>1) + {0,1}
+  // phase 1: W = V^T Zs (B x SWA); wave w: row block a = w & 1, column blocks 2(w>>1) + {0,1}
+  const int a = w & 1, cb0 = 2 * (w >> 1);
   {
-    const int a = w & 1;
-    dbl4 acc[2] = {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}};
-    for (int k0 = 0; k0 < H2; k0 += 4) {
-      const double fa = Vs[k0 + l4][16 * a + l16];
-#pragma unroll
-      for (int q = 0; q < 2; q++) {
-        const int b = 2 * (w >> 1) + q;
-        const double fb = Zs[k0 + l4][16 * b + l16];
-        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb, acc[q], 0, 0, 0);
-      }
+    dbl4 acc0 = dbl4{0, 0, 0, 0}, acc1 = dbl4{0, 0, 0, 0};
+    const int kbeg = 16 * a, kend = 16 * a + 48;  // rows where column block a of V is nonzero
+#pragma unroll 4
+    for (int k0 = kbeg; k0 < kend; k0 += 4) {
+      const double fa = V[(k0 + l4) + (long)(16 * a + l16) * H2];
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Zs[k0 + l4][16 * cb0 + l16], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Zs[k0 + l4][16 * cb0 + 16 + l16], acc1, 0, 0,
+                                                  0);
     }
 #pragma unroll
-    for (int q = 0; q < 2; q++) {
-      const int b = 2 * (w >> 1) + q;
-#pragma unroll
-      for (int r = 0; r < 4; r++) Ws[16 * a + l4 + 4 * r][16 * b + l16] = acc[q][r];
+    for (int r = 0; r < 4; r++) {
+      Ws[16 * a + l4 + 4 * r][16 * cb0 + l16] = acc0[r];
+      Ws[16 * a + l4 + 4 * r][16 * cb0 + 16 + l16] = acc1[r];
     }
   }
   __syncthreads();
-  // W2 = T W (T upper triangular)
+  // phase 2: W2 = T W (T upper triangular), same block mapping
   {
-    const int a = w & 1;
-    dbl4 acc[2] = {dbl4{0, 0, 0, 0}, dbl4{0, 0, 0, 0}};
+    dbl4 acc0 = dbl4{0, 0, 0, 0}, acc1 = dbl4{0, 0, 0, 0};
+#pragma unroll 2
     for (int k0 = 16 * a; k0 < B; k0 += 4) {
-      const double fa = Ts[16 * a + l16][k0 + l4];
-#pragma unroll
-      for (int q = 0; q < 2; q++) {
-        const int b = 2 * (w >> 1) + q;
-        const double fb = Ws[k0 + l4][16 * b + l16];
-        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb, acc[q], 0, 0, 0);
-      }
+      const double fa = T[(16 * a + l16) + (long)(k0 + l4) * B];
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Ws[k0 + l4][16 * cb0 + l16], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Ws[k0 + l4][16 * cb0 + 16 + l16], acc1, 0, 0,
+                                                  0);
     }
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 2; q++) {
-      const int b = 2 * (w >> 1) + q;
-#pragma unroll
-      for (int r = 0; r < 4; r++) W2s[16 * a + l4 + 4 * r][16 * b + l16] = acc[q][r];
+    for (int r = 0; r < 4; r++) {
+      Ws[16 * a + l4 + 4 * r][16 * cb0 + l16] = acc0[r];
+      Ws[16 * a + l4 + 4 * r][16 * cb0 + 16 + l16] = acc1[r];
     }
   }
   __syncthreads();
-  // Zs - V W2: wave w -> rows 16w .. 16w+15, all 4 column blocks; written to Z
+  // phase 3: Zs - V W2; wave w: row block rr = w & 3, column blocks 4(w>>2) + {0..3}
   {
+    const int rr = w & 3, cb = 4 * (w >> 2);
+    const int kbeg = (rr == 3) ? 16 : 0, kend = (rr == 0) ? 16 : 32;
     dbl4 acc[4];
 #pragma unroll
-    for (int b = 0; b < 4; b++)
+    for (int q = 0; q < 4; q++)
 #pragma unroll
-      for (int r = 0; r < 4; r++) acc[b][r] = Zs[16 * w + l4 + 4 * r][16 * b + l16];
-    for (int k0 = 0; k0 < B; k0 += 4) {
-      const double fa = -Vs[16 * w + l16][k0 + l4];
+      for (int r = 0; r < 4; r++) acc[q][r] = Zs[16 * rr + l4 + 4 * r][16 * (cb + q) + l16];
+    for (int k0 = kbeg; k0 < kend; k0 += 4) {
+      const double fa = -V[(16 * rr + l16) + (long)(k0 + l4) * H2];
 #pragma unroll
-      for (int b = 0; b < 4; b++) {
-        const double fb = W2s[k0 + l4][16 * b + l16];
-        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb, acc[b], 0, 0, 0);
-      }
+      for (int q = 0; q < 4; q++)
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Ws[k0 + l4][16 * (cb + q) + l16], acc[q],
+                                                      0, 0, 0);
     }
 #pragma unroll
-    for (int b = 0; b < 4; b++) {
-      const int c = 16 * b + l16;
+    for (int q = 0; q < 4; q++) {
+      const int c = 16 * (cb + q) + l16;
       if (c >= nc) continue;
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        const int row = 16 * w + l4 + 4 * r;
-        if (row < hh) Z[rb + row + (long)(c0 + c) * ldz] = acc[b][r];
+        const int row = 16 * rr + l4 + 4 * r;
+        if (row < hh) Z[rb + row + (long)(c0 + c) * ldz] = acc[q][r];
       }
     }
   }
@@ -173,7 +168,7 @@ hipError_t bt2_apply(const Sb2stLayout& L, const double* V2, const double* T2, c
                      double* Z, long ldz, int m, const int* m_dev, hipStream_t s) {
   if (L.ngroups <= 0 || m <= 0) return hipSuccess;
   const int n = L.n, nblk = L.nblk;
-  const int nslab = ceil_div(m, SW);
+  const int nslab = ceil_div(m, SWA);
   auto tg = [&](int sb) { return (n - 1 - sb * B + B - 1) / B; };
   const int lmax = (tg(0) - 1) + 2 * (nblk - 1);
   for (int level = 0; level <= lmax; level++) {
@@ -194,7 +189,7 @@ hipError_t bt2_apply(const Sb2stLayout& L, const double* V2, const double* T2, c
       if (t < 0 || t >= tg(first - 1)) break;
       first--;
     }
-    hipLaunchKernelGGL(group_apply_kernel, dim3(hi - first + 1, nslab), dim3(256), 0, s, n, nblk,
+    hipLaunchKernelGGL(group_apply_kernel, dim3(hi - first + 1, nslab), dim3(512), 0, s, n, nblk,
                        level, first, V2, T2, d_goff, Z, ldz, m, m_dev);
     HSDM_TRY(hipGetLastError());
   }

@@ -246,10 +246,14 @@ HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int flags, int
 }
 
 // Map a workgroup id to a tile: XCD-contiguous runs, then groups of 8 rows.
+// The grid may be larger than the tile count (sizes read on the device), so
+// the runs are sized by the actual count: XCD x gets tiles [x*per, (x+1)*per).
 HSDM_DEV bool map_tile(int bid, int nblk, int tiles_m, int tiles_n, int& tm, int& tn) {
-  const int per = nblk / 8;  // nblk is a multiple of 8
+  const int ntiles = tiles_m * tiles_n;
+  const int per = (ntiles + 7) / 8;
+  if (bid >= 8 * per) return false;
   const int t = (bid % 8) * per + bid / 8;
-  if (t >= tiles_m * tiles_n) return false;
+  if (t >= ntiles) return false;
   constexpr int GROUP = 8;
   const int in_group = GROUP * tiles_n;
   const int g = t / in_group;

@@ -28,7 +28,7 @@
 
 namespace {
 
-constexpr int WPB = 4;  // wavefronts per workgroup
+constexpr int WPB = 8;  // wavefronts per workgroup
 constexpr int DONE = 1 << 30;
 
 HSDM_DEV void wave_sync() {
@@ -43,12 +43,18 @@ HSDM_DEV double wsum(double v) {
 
 HSDM_DEV double hsum(double v) { return v + __shfl_xor(v, 32, 64); }
 
-HSDM_DEV void wait_ge(int* p, int target, DevStatusWord* st) {
-  // poll with relaxed loads (an acquire per poll would invalidate the L2 each
-  // time); one acquire fence once the counter is reached
+// Sweep s waits for sweep s-1.  Consecutive sweeps run on the wavefronts of
+// one workgroup except across workgroup boundaries, so the hand-off uses
+// workgroup scope (no cache maintenance: the wavefronts share the CU's
+// caches) when both sweeps are in the same workgroup, agent scope otherwise.
+HSDM_DEV void wait_ge(int* p, int target, bool agent, DevStatusWord* st) {
+  // poll with relaxed loads; one acquire fence once the counter is reached
   if ((threadIdx.x & 63) == 0) {
     long spins = 0;
-    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    for (;;) {
+      const int v = agent ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                          : __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (v >= target) break;
       ++spins;
       if (spins > (1L << 27) ||
           ((spins & 4095) == 0 &&
@@ -59,13 +65,21 @@ HSDM_DEV void wait_ge(int* p, int target, DevStatusWord* st) {
       __builtin_amdgcn_s_sleep(1);
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (agent)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  else
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   wave_sync();
 }
 
-HSDM_DEV void publish(int* p, int v) {
+HSDM_DEV void publish(int* p, int v, bool agent) {
   wave_sync();
-  if ((threadIdx.x & 63) == 0) __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if ((threadIdx.x & 63) == 0) {
+    if (agent)
+      __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
 }
 
 template <int B>
@@ -89,9 +103,12 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
 
   for (int s = gw; s < nsweep; s += TW) {
     const int ntask = (n - 1 - s + B - 1) / B;
+    // sweep s-1 runs on wavefront gw-1 (same workgroup unless gw is its first)
+    const bool wait_agent = (wv_id == 0);
+    const bool pub_agent = (wv_id == WPB - 1);
     double tau = 0.0;
     for (int t = 0; t < ntask; t++) {
-      if (s > 0) wait_ge(progress + s - 1, t + 2, st);
+      if (s > 0) wait_ge(progress + s - 1, t + 2, wait_agent, st);
       const int rs = s + 1 + t * B;
       const int len = min(B, n - rs);
       const int rs2 = rs + B;
@@ -210,9 +227,9 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
         if (li < len2 && j < len) AB[(B + li - j) + (long)(rs + j) * ldab] = Bl[li][j];
       }
       tau = tau_n;
-      publish(progress + s, t + 1);
+      publish(progress + s, t + 1, pub_agent);
     }
-    publish(progress + s, DONE);
+    publish(progress + s, DONE, pub_agent);
   }
 }
 
@@ -275,6 +292,8 @@ hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, doub
     int nsweep = L.nsweep;
     int nwg = ceil_div(nsweep, WPB);
     if (nwg > 256) nwg = 256;
+    // (sweep s and s-1 share a workgroup iff s is not the first sweep of its
+    // wavefront group; TW = nwg * WPB keeps that true for every round)
     void* args[] = {(void*)&n, (void*)&nsweep, (void*)&AB, (void*)&ldab, (void*)&V2,
                     (void*)&tau2, (void*)&d_goff, (void*)&progress, (void*)&st};
     HSDM_TRY(hipLaunchCooperativeKernel((const void*)sb2st_kernel<32>, dim3(nwg), dim3(64 * WPB),

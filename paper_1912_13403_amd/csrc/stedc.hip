@@ -392,7 +392,7 @@ __global__ __launch_bounds__(256) void secular_kernel(LevelBufs b, int m0, DevSt
   const bool last = (j == k - 1);
   double tau = 0.5 * (tl + th);
   bool conv = false;
-  for (int it = 0; it < 100; it++) {
+  for (int it = 0; it < 200; it++) {
     double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
     for (int i = lane; i < k; i += 64) {
       const double del = (dk[i] - dorg) - tau;
@@ -405,8 +405,18 @@ __global__ __launch_bounds__(256) void secular_kernel(LevelBufs b, int m0, DevSt
     phi = wave_sum(phi);
     dphi = wave_sum(dphi);
     const double f = 1.0 / rho + psi + phi;
-    if (f == 0.0) { conv = true; break; }
+    // converged once f is within the rounding error of its own evaluation
+    // (psi <= 0 <= phi, so the absolute sum is 1/rho - psi + phi; the second
+    // term covers the rounding of the differences (d_i - d_origin) - tau)
+    const double ferr =
+        8.0 * DBL_EPSILON * ((1.0 / rho - psi + phi) + fabs(tau) * (dpsi + dphi));
+    if (f == 0.0 || fabs(f) <= ferr) { conv = true; break; }
     if (f < 0.0) tl = tau; else th = tau;
+    if (th - tl <= 4.0 * DBL_EPSILON * fmax(fabs(tl), fabs(th))) {
+      tau = 0.5 * (tl + th);
+      conv = true;
+      break;
+    }
     const double DL = (dk[j] - dorg) - tau;
     double eta;
     bool ok = true;
