@@ -83,19 +83,32 @@ __global__ __launch_bounds__(512) void group_apply_kernel(int n, int nblk, int l
   __shared__ double Ws[B][SWA + 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
+  const int a = w & 1, cb0 = 2 * (w >> 1);
+  const int rr = w & 3, cb = 4 * (w >> 2);
+  // all V and T operand fragments of this lane, loaded up front so that their
+  // latency overlaps the Z block load
+  double v1[12], t2[8], v3[8];
+#pragma unroll
+  for (int q = 0; q < 12; q++) v1[q] = V[(16 * a + 4 * q + l4) + (long)(16 * a + l16) * H2];
+#pragma unroll
+  for (int q = 0; q < 8; q++) {
+    const int k0 = 4 * q;
+    t2[q] = (k0 >= 16 * a) ? T[(16 * a + l16) + (long)(k0 + l4) * B] : 0.0;
+    v3[q] = -V[(16 * rr + l16) + (long)(k0 + l4) * H2];
+  }
   for (int e = tid; e < H2 * SWA; e += 512) {
     const int r = e % H2, c = e / H2;
     Zs[r][c] = (r < hh && c < nc) ? Z[rb + r + (long)(c0 + c) * ldz] : 0.0;
   }
   __syncthreads();
   // phase 1: W = V^T Zs (B x SWA); wave w: row block a = w & 1, column blocks 2(w>>1) + {0,1}
-  const int a = w & 1, cb0 = 2 * (w >> 1);
+  // (column block a of V is nonzero in rows 16a .. 16a+47 only)
   {
     dbl4 acc0 = dbl4{0, 0, 0, 0}, acc1 = dbl4{0, 0, 0, 0};
-    const int kbeg = 16 * a, kend = 16 * a + 48;  // rows where column block a of V is nonzero
-#pragma unroll 4
-    for (int k0 = kbeg; k0 < kend; k0 += 4) {
-      const double fa = V[(k0 + l4) + (long)(16 * a + l16) * H2];
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+      const int k0 = 16 * a + 4 * q;
+      const double fa = v1[q];
       acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Zs[k0 + l4][16 * cb0 + l16], acc0, 0, 0, 0);
       acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Zs[k0 + l4][16 * cb0 + 16 + l16], acc1, 0, 0,
                                                   0);
@@ -110,9 +123,10 @@ __global__ __launch_bounds__(512) void group_apply_kernel(int n, int nblk, int l
   // phase 2: W2 = T W (T upper triangular), same block mapping
   {
     dbl4 acc0 = dbl4{0, 0, 0, 0}, acc1 = dbl4{0, 0, 0, 0};
-#pragma unroll 2
-    for (int k0 = 16 * a; k0 < B; k0 += 4) {
-      const double fa = T[(16 * a + l16) + (long)(k0 + l4) * B];
+#pragma unroll
+    for (int q = 4 * a; q < 8; q++) {
+      const int k0 = 4 * q;
+      const double fa = t2[q];
       acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Ws[k0 + l4][16 * cb0 + l16], acc0, 0, 0, 0);
       acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Ws[k0 + l4][16 * cb0 + 16 + l16], acc1, 0, 0,
                                                   0);
@@ -127,15 +141,17 @@ __global__ __launch_bounds__(512) void group_apply_kernel(int n, int nblk, int l
   __syncthreads();
   // phase 3: Zs - V W2; wave w: row block rr = w & 3, column blocks 4(w>>2) + {0..3}
   {
-    const int rr = w & 3, cb = 4 * (w >> 2);
-    const int kbeg = (rr == 3) ? 16 : 0, kend = (rr == 0) ? 16 : 32;
+    const int qbeg = (rr == 3) ? 4 : 0, qend = (rr == 0) ? 4 : 8;
     dbl4 acc[4];
 #pragma unroll
     for (int q = 0; q < 4; q++)
 #pragma unroll
       for (int r = 0; r < 4; r++) acc[q][r] = Zs[16 * rr + l4 + 4 * r][16 * (cb + q) + l16];
-    for (int k0 = kbeg; k0 < kend; k0 += 4) {
-      const double fa = -V[(16 * rr + l16) + (long)(k0 + l4) * H2];
+#pragma unroll
+    for (int kq = 0; kq < 8; kq++) {
+      if (kq < qbeg || kq >= qend) continue;
+      const int k0 = 4 * kq;
+      const double fa = v3[kq];
 #pragma unroll
       for (int q = 0; q < 4; q++)
         acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Ws[k0 + l4][16 * (cb + q) + l16], acc[q],

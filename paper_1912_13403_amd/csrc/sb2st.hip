@@ -31,9 +31,12 @@ namespace {
 constexpr int WPB = 8;  // wavefronts per workgroup
 constexpr int DONE = 1 << 30;
 
+// Orders LDS accesses between the lanes of one wavefront: the LDS executes a
+// wavefront's instructions in order, so a compiler barrier is enough (no wait
+// on outstanding global memory operations).
 HSDM_DEV void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
 }
 
 HSDM_DEV double wsum(double v) {

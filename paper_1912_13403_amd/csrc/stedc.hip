@@ -34,9 +34,12 @@ constexpr int LEAF = 64;
 constexpr int META = 8;  // k, ndef, nrot, ntop, nmix, nbot, ncols, limit
 constexpr int CHK = 1024;
 
+// Orders LDS accesses between the lanes of one wavefront: the LDS executes a
+// wavefront's instructions in order, so a compiler barrier is enough (no wait
+// on outstanding global memory operations).
 HSDM_DEV void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
 }
 
 // ---------------------------------------------------------------------------
