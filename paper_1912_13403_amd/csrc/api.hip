@@ -76,7 +76,7 @@ struct hsdm_ctx {
   Sb2stLayout lay{};
   // carved pointers
   double *Lbuf, *Linv, *Abuf, *Vst, *Zbuf, *Cbuf, *T1, *tau1, *AB, *sy_scr, *dvec, *evec, *lam,
-      *fvec, *V2, *tau2, *T2, *dc_scr, *bt1_scr, *colsum, *hnorm;
+      *fvec, *V2, *tau2, *F2, *dc_scr, *bt1_scr, *colsum, *hnorm;
   int *dc_iscr, *progress;
   unsigned* bar;
   // cached factor of S
@@ -133,7 +133,7 @@ int ensure_ws(hsdm_ctx* h, int n) {
   const size_t oAB = take((size_t)2 * BAND * n), osy = take(sy2sb_scratch_doubles(n, BAND));
   const size_t od = take(n), oe = take(n), olam = take(n), of = take(n);
   const size_t oV2 = take(L.v2_doubles + 1), otau2 = take((size_t)L.ngroups * BAND + 1),
-               oT2 = take((size_t)L.ngroups * BAND * BAND + 1);
+               oF2 = take(bt2_pack_doubles(L) + 1);
   const size_t odc = take(stedc_scratch_doubles(n)), obt1 = take(bt1_scratch_doubles(n, BAND, n));
   const size_t ocs = take(n), ohn = take(1);
   hipError_t e = hipMalloc(&h->ws, off * sizeof(double));
@@ -151,7 +151,7 @@ int ensure_ws(hsdm_ctx* h, int n) {
   h->Lbuf = w + oL; h->Linv = w + oLi; h->Abuf = w + oA; h->Vst = w + oV; h->Zbuf = w + oZ;
   h->Cbuf = w + oC; h->T1 = w + oT1; h->tau1 = w + otau1; h->AB = w + oAB; h->sy_scr = w + osy;
   h->dvec = w + od; h->evec = w + oe; h->lam = w + olam; h->fvec = w + of; h->V2 = w + oV2;
-  h->tau2 = w + otau2; h->T2 = w + oT2; h->dc_scr = w + odc; h->bt1_scr = w + obt1;
+  h->tau2 = w + otau2; h->F2 = w + oF2; h->dc_scr = w + odc; h->bt1_scr = w + obt1;
   h->colsum = w + ocs; h->hnorm = w + ohn;
   h->dc_iscr = h->iws;
   h->progress = h->iws + stedc_iscratch_ints(n);
@@ -487,8 +487,8 @@ int hsdm_tridiagonalize(hsdm_handle h, int n, const double* A, int lda, double* 
     hipLaunchKernelGGL(eye_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Q,
                        (long)ldq, n);
     DEV_TRY(h, hipGetLastError());
-    DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->T2, h->d_goff, s));
-    DEV_TRY(h, bt2_apply(h->lay, h->V2, h->T2, h->d_goff, Q, ldq, n, nullptr, s));
+    DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
+    DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, Q, ldq, n, nullptr, h->st, s));
     DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, Q, ldq, n, nullptr, h->bt1_scr, s));
   }
   return finish(h, s);
@@ -595,8 +595,8 @@ int hsdm_solve_ev_real(hsdm_handle h, int n, const double* H, int ldh, const dou
   DEV_TRY(h, stedc_run(h->plan, h->dvec, h->evec, eval, h->Zbuf, n, h->dc_scr, h->dc_iscr,
                        nullptr, nullptr, nullptr, h->st, s));
   mark(h, 5, s);
-  DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->T2, h->d_goff, s));
-  DEV_TRY(h, bt2_apply(h->lay, h->V2, h->T2, h->d_goff, h->Zbuf, n, n, nullptr, s));
+  DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
+  DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, n, nullptr, h->st, s));
   mark(h, 6, s);
   DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, n, nullptr, h->bt1_scr, s));
   mark(h, 7, s);
@@ -640,8 +640,8 @@ int hsdm_solve_dm_real(hsdm_handle h, int n, const double* H, int ldh, const dou
   DEV_TRY(h, stedc_run(h->plan, h->dvec, h->evec, h->lam, h->Zbuf, n, h->dc_scr, h->dc_iscr,
                        m_dev, occ_hook, &hook, h->st, s));
   mark(h, 5, s);
-  DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->T2, h->d_goff, s));
-  DEV_TRY(h, bt2_apply(h->lay, h->V2, h->T2, h->d_goff, h->Zbuf, n, n, m_dev, s));
+  DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
+  DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, n, m_dev, h->st, s));
   mark(h, 6, s);
   DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, n, m_dev, h->bt1_scr, s));
   mark(h, 7, s);

@@ -1,14 +1,11 @@
 // Back-transformation of eigenvectors through the two reduction stages.
 //
 // Stage 2 (bulge chasing): the reflectors H_{s,t} of B consecutive sweeps
-// that share the task index t are combined into one block reflector
-// G = I - V T V^T (V: 2B x B parallelogram, T: B x B upper triangular), so
-// that applying them is three small matrix products on the FP64 matrix
-// cores.  Ordering: Q2 Z = H_{0,0} H_{0,1} ... Z must apply later sweeps
-// first; group (b, t) (sweep block b) overlaps groups (b+1, t-2 .. t) and
-// (b, t-1), so all groups with equal  t + 2 (nblk - 1 - b)  are independent
-// and one launch per such level applies them, each workgroup one group to
-// one slab of 64 columns of Z.
+// (sweep block b) that share the task index t are combined into one block
+// reflector G = I - V T V^T (V: 2B x B parallelogram, T: B x B upper
+// triangular) acting on rows r B + 1 .. r B + 2B, r = b + t, so that applying
+// it is three small products on the FP64 matrix cores.  Q2 Z applies later
+// sweeps first: group (b, r) must follow (b+1, r-1 .. r+1) and (b, r-1).
 //
 // Stage 1 (panels): Z <- (I - V_p T_p V_p^T) Z for p from the last panel to
 // the first, as three GEMMs per panel (the tall V_p^T Z with split-K).
@@ -20,9 +17,14 @@ namespace {
 constexpr int B = 32;
 constexpr int H2 = 2 * B;  // rows of a group
 
-// T factor of every group: T_jj = tau_j, T(0:j, j) = -tau_j T(0:j,0:j) V^T v_j
-__global__ __launch_bounds__(256) void group_t_kernel(const double* V2, const double* tau2,
-                                                      double* T2) {
+// Compact record of one group (GREC doubles): the parallelogram of V by
+// columns, Vc[32 j + i] = V[j + i][j] (i, j < B), then T column-major.
+constexpr int GREC = 2 * B * B;
+
+// T factor of every group (T_jj = tau_j, T(0:j, j) = -tau_j T(0:j,0:j) V^T v_j),
+// then the compact record.
+__global__ __launch_bounds__(256) void group_pack_kernel(const double* V2, const double* tau2,
+                                                         double* F2) {
   const long gi = blockIdx.x;
   const double* V = V2 + gi * H2 * B;
   const double* tau = tau2 + gi * B;
@@ -51,165 +53,231 @@ __global__ __launch_bounds__(256) void group_t_kernel(const double* V2, const do
     if (t == j) Tl[j][j] = tj;
     __syncthreads();
   }
-  double* T = T2 + gi * B * B;
-  for (int e = t; e < B * B; e += 256) T[e] = Tl[e % B][e / B];
+  double* F = F2 + gi * (long)GREC;
+  for (int e = t; e < B * B; e += 256) {
+    const int j = e / B, i = e % B;
+    F[e] = Vs[j + i][j];
+    F[B * B + e] = Tl[i][j];
+  }
 }
 
-// Apply the groups of one level to Z: workgroup (group, slab of 128 columns),
-// 8 wavefronts.  Z block (2B x 128) and W (B x 128) live in LDS; V and T are
-// read from L2.  Zero 16x16 blocks of the parallelogram V are skipped:
-// V(r, c) != 0 only for c <= r <= c + B - 1.
-constexpr int SWA = 128;
+// Z <- Q2 Z for one strip of 16 columns per workgroup.  Columns of Z are
+// independent, so a workgroup applies every group to its strip with no
+// other workgroup involved.  Its PW wavefronts take the sweep blocks in turn
+// (wavefront w: b = nblk-1-w, nblk-1-w-PW, ...); each walks its block's
+// groups upward (r = b + t, t = 0, 1, ...), keeping the group's 64 x 16
+// window of Z in registers in MFMA accumulator layout: lane l holds rows
+// 4i + l/16 of each 16-row block at column l%16, which is also the layout
+// of a B operand, so the three products chain with no data movement.  After
+// group (b, r) the lower half (rows of block r) is final for sweep block b
+// and is stored; the upper half becomes the next window's lower half.
+// Group (b, r) needs (b+1, r+1) done (and with it (b+1, r-1 .. r), and (b, r-1)
+// by construction).  A wavefront stays one group further behind its
+// predecessor than that requires, so the row block and the compact record
+// of its next group are loaded while the current group is computed; the
+// record is staged in the wavefront's own LDS area, from which the MFMA A
+// operands (V^T, T, -V, zero parts skipped) are read.  Progress counters
+// live in LDS; their keys grow monotonically across a wavefront's sweep
+// blocks.
+constexpr int PW = 4;            // wavefronts per workgroup (one per SIMD)
+constexpr int KEYM = 1 << 13;    // > tasks per sweep block
+constexpr int NFRAG = 60;        // A operands per group: 24 (V^T) + 12 (T) + 24 (-V)
+constexpr int VS = B + 2;        // LDS column stride of V (conflict-free operand reads)
+constexpr int TS = B + 1;        // LDS column stride of T
+constexpr int NST = GREC / 64;   // record doubles per lane
 
-__global__ __launch_bounds__(512) void group_apply_kernel(int n, int nblk, int level, int sb_lo,
-                                                          const double* V2, const double* T2,
-                                                          const long* goff, double* Z, long ldz,
-                                                          int m_host, const int* m_dev) {
-  const int sb = sb_lo + blockIdx.x;
-  const int t = level - 2 * (nblk - 1 - sb);
-  const int tg = (n - 1 - sb * B + B - 1) / B;
-  if (t < 0 || t >= tg) return;
+HSDM_DEV int key_of(int nblk, int b) { return (nblk - 1 - b) * KEYM; }
+
+__global__ __launch_bounds__(64 * PW) void bt2_strip_kernel(int n, int nblk, const double* F2,
+                                                            const long* goff, double* Z, long ldz,
+                                                            int m_host, const int* m_dev,
+                                                            DevStatusWord* st) {
   const int m = m_dev ? *m_dev : m_host;
-  const int c0 = blockIdx.y * SWA;
+  const int c0 = blockIdx.x * 16;
   if (c0 >= m) return;
-  const int nc = min(SWA, m - c0);
-  const int rb = sb * B + 1 + t * B;
-  const int hh = min(H2, n - rb);
-  const long gi = goff[sb] + t;
-  const double* V = V2 + gi * H2 * B;   // (H2 x B), column-major
-  const double* T = T2 + gi * B * B;    // (B x B), column-major
-
-  __shared__ double Zs[H2][SWA + 1];
-  __shared__ double Ws[B][SWA + 1];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  __shared__ int prog[PW];
+  __shared__ double Vl_all[PW][B * VS];
+  __shared__ double Tl_all[PW][B * TS];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double* Vl = Vl_all[w];
+  double* Tl = Tl_all[w];
+  if (lane == 0) prog[w] = -1;
+  __syncthreads();
   const int l16 = lane & 15, l4 = lane >> 4;
-  const int a = w & 1, cb0 = 2 * (w >> 1);
-  const int rr = w & 3, cb = 4 * (w >> 2);
-  // all V and T operand fragments of this lane, loaded up front so that their
-  // latency overlaps the Z block load
-  double v1[12], t2[8], v3[8];
+  const int col = c0 + l16;
+  const bool cok = col < m;
+  double* Zc = Z + (long)(cok ? col : 0) * ldz;
+  const int pw = (w + PW - 1) % PW;
+  bool failed = false;
+
+  auto tgb = [&](int b) { return (n - 1 - b * B + B - 1) / B; };
+  auto ld4 = [&](int r0, dbl4& z) {
 #pragma unroll
-  for (int q = 0; q < 12; q++) v1[q] = V[(16 * a + 4 * q + l4) + (long)(16 * a + l16) * H2];
+    for (int i = 0; i < 4; i++) {
+      const int row = r0 + 4 * i + l4;
+      z[i] = (cok && row < n) ? Zc[row] : 0.0;
+    }
+  };
+  auto st4 = [&](int r0, const dbl4& z) {
 #pragma unroll
-  for (int q = 0; q < 8; q++) {
-    const int k0 = 4 * q;
-    t2[q] = (k0 >= 16 * a) ? T[(16 * a + l16) + (long)(k0 + l4) * B] : 0.0;
-    v3[q] = -V[(16 * rr + l16) + (long)(k0 + l4) * H2];
-  }
-  for (int e = tid; e < H2 * SWA; e += 512) {
-    const int r = e % H2, c = e / H2;
-    Zs[r][c] = (r < hh && c < nc) ? Z[rb + r + (long)(c0 + c) * ldz] : 0.0;
-  }
-  __syncthreads();
-  // phase 1: W = V^T Zs (B x SWA); wave w: row block a = w & 1, column blocks 2(w>>1) + {0,1}
-  // (column block a of V is nonzero in rows 16a .. 16a+47 only)
-  {
-    dbl4 acc0 = dbl4{0, 0, 0, 0}, acc1 = dbl4{0, 0, 0, 0};
+    for (int i = 0; i < 4; i++) {
+      const int row = r0 + 4 * i + l4;
+      if (cok && row < n) Zc[row] = z[i];
+    }
+  };
+  // record of a group -> registers (coalesced) -> this wavefront's LDS area
+  auto ld_rec = [&](const double* G, double* r) {
 #pragma unroll
-    for (int q = 0; q < 12; q++) {
-      const int k0 = 16 * a + 4 * q;
-      const double fa = v1[q];
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Zs[k0 + l4][16 * cb0 + l16], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Zs[k0 + l4][16 * cb0 + 16 + l16], acc1, 0, 0,
-                                                  0);
+    for (int q = 0; q < NST; q++) r[q] = G[q * 64 + lane];
+  };
+  auto put_rec = [&](const double* r) {
+#pragma unroll
+    for (int q = 0; q < NST; q++) {
+      const int e = q * 64 + lane;
+      if (q < NST / 2) Vl[(e >> 5) * VS + (e & 31)] = r[q];
+      else Tl[((e - B * B) >> 5) * TS + (e & 31)] = r[q];
+    }
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+  };
+  // A operands from LDS: lane l gets A[row l%16][k l/16] of each 16 x 4 block
+  auto get_ops = [&](double* f) {
+#pragma unroll
+    for (int q = 0; q < 24; q++) {  // V^T: row block a, k step 4a .. 4a+11
+      const int a = q / 12, kq = 4 * a + q % 12;
+      const int j = 16 * a + l16, i = 4 * kq + l4 - j;
+      const double v = Vl[j * VS + (i & 31)];
+      f[q] = (i >= 0 && i < B) ? v : 0.0;
     }
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-      Ws[16 * a + l4 + 4 * r][16 * cb0 + l16] = acc0[r];
-      Ws[16 * a + l4 + 4 * r][16 * cb0 + 16 + l16] = acc1[r];
-    }
-  }
-  __syncthreads();
-  // phase 2: W2 = T W (T upper triangular), same block mapping
-  {
-    dbl4 acc0 = dbl4{0, 0, 0, 0}, acc1 = dbl4{0, 0, 0, 0};
-#pragma unroll
-    for (int q = 4 * a; q < 8; q++) {
-      const int k0 = 4 * q;
-      const double fa = t2[q];
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Ws[k0 + l4][16 * cb0 + l16], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Ws[k0 + l4][16 * cb0 + 16 + l16], acc1, 0, 0,
-                                                  0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 4; r++) {
-      Ws[16 * a + l4 + 4 * r][16 * cb0 + l16] = acc0[r];
-      Ws[16 * a + l4 + 4 * r][16 * cb0 + 16 + l16] = acc1[r];
-    }
-  }
-  __syncthreads();
-  // phase 3: Zs - V W2; wave w: row block rr = w & 3, column blocks 4(w>>2) + {0..3}
-  {
-    const int qbeg = (rr == 3) ? 4 : 0, qend = (rr == 0) ? 4 : 8;
-    dbl4 acc[4];
-#pragma unroll
-    for (int q = 0; q < 4; q++)
-#pragma unroll
-      for (int r = 0; r < 4; r++) acc[q][r] = Zs[16 * rr + l4 + 4 * r][16 * (cb + q) + l16];
-#pragma unroll
-    for (int kq = 0; kq < 8; kq++) {
-      if (kq < qbeg || kq >= qend) continue;
-      const int k0 = 4 * kq;
-      const double fa = v3[kq];
-#pragma unroll
-      for (int q = 0; q < 4; q++)
-        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, Ws[k0 + l4][16 * (cb + q) + l16], acc[q],
-                                                      0, 0, 0);
+    for (int q = 0; q < 12; q++) {  // T: a = 0, k steps 0..7; a = 1, k steps 4..7
+      const int a = (q < 8) ? 0 : 1, kq = (q < 8) ? q : q - 4;
+      f[24 + q] = Tl[(4 * kq + l4) * TS + 16 * a + l16];
     }
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      const int c = 16 * (cb + q) + l16;
-      if (c >= nc) continue;
-#pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const int row = 16 * rr + l4 + 4 * r;
-        if (row < hh) Z[rb + row + (long)(c0 + c) * ldz] = acc[q][r];
+    for (int q = 0; q < 24; q++) {  // -V: Z row block rq, k steps by rq
+      int rq, kq;
+      if (q < 4) { rq = 0; kq = q; }
+      else if (q < 12) { rq = 1; kq = q - 4; }
+      else if (q < 20) { rq = 2; kq = q - 12; }
+      else { rq = 3; kq = q - 16; }
+      const int j = 4 * kq + l4, i = 16 * rq + l16 - j;
+      const double v = Vl[j * VS + (i & 31)];
+      f[36 + q] = (i >= 0 && i < B) ? -v : 0.0;
+    }
+  };
+  auto publish = [&](int v) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0) __hip_atomic_store(&prog[w], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
+  auto wait_for = [&](int target) {
+    long spins = 0;
+    while (__hip_atomic_load(&prog[pw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+      if (++spins > (1L << 26)) {
+        failed = true;
+        break;
       }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  };
+
+  for (int b = nblk - 1 - w; b >= 0 && !failed; b -= PW) {
+    const int T = tgb(b);
+    const bool has_pred = (b + 1 <= nblk - 1);
+    const int T1 = has_pred ? tgb(b + 1) : 0;
+    const int kb = key_of(nblk, b), kp = has_pred ? key_of(nblk, b + 1) : 0;
+    const double* Gb = F2 + goff[b] * (long)GREC;
+    double f[NFRAG], rec[NST];
+    dbl4 z0, z1, z2, z3, n0, n1;
+    ld_rec(Gb, rec);
+    put_rec(rec);
+    if (has_pred) wait_for(kp + min(1, T1));
+    if (failed) break;
+    ld4(b * B + 1, z0);
+    ld4(b * B + 17, z1);
+    ld4(b * B + 33, z2);
+    ld4(b * B + 49, z3);
+    for (int t = 0; t < T; t++) {
+      const int rb = (b + t) * B + 1;  // first row of the group
+      const bool more = t + 1 < T;
+      if (more) {
+        // record and new row block of group t + 1 (the latter needs (b+1, t+1))
+        ld_rec(Gb + (long)(t + 1) * GREC, rec);
+        if (has_pred) wait_for(kp + min(t + 2, T1));
+        if (failed) break;
+        ld4(rb + 64, n0);
+        ld4(rb + 80, n1);
+      }
+      get_ops(f);
+      // W = V^T Z (two 16-row blocks)
+      dbl4 w0 = dbl4{0, 0, 0, 0}, w1 = dbl4{0, 0, 0, 0};
+#pragma unroll
+      for (int kq = 0; kq < 12; kq++) {
+        const dbl4& zq = (kq < 4) ? z0 : (kq < 8) ? z1 : z2;
+        w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[kq], zq[kq & 3], w0, 0, 0, 0);
+      }
+#pragma unroll
+      for (int kq = 4; kq < 16; kq++) {
+        const dbl4& zq = (kq < 8) ? z1 : (kq < 12) ? z2 : z3;
+        w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[12 + kq - 4], zq[kq & 3], w1, 0, 0, 0);
+      }
+      // W2 = T W
+      dbl4 u0 = dbl4{0, 0, 0, 0}, u1 = dbl4{0, 0, 0, 0};
+#pragma unroll
+      for (int kq = 0; kq < 8; kq++)
+        u0 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[24 + kq], (kq < 4) ? w0[kq] : w1[kq - 4], u0,
+                                                  0, 0, 0);
+#pragma unroll
+      for (int kq = 4; kq < 8; kq++)
+        u1 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[32 + kq - 4], w1[kq - 4], u1, 0, 0, 0);
+      // Z += (-V) W2
+#pragma unroll
+      for (int kq = 0; kq < 4; kq++)
+        z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[36 + kq], u0[kq], z0, 0, 0, 0);
+#pragma unroll
+      for (int kq = 0; kq < 8; kq++) {
+        const double uk = (kq < 4) ? u0[kq] : u1[kq - 4];
+        z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[40 + kq], uk, z1, 0, 0, 0);
+        z2 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[48 + kq], uk, z2, 0, 0, 0);
+      }
+#pragma unroll
+      for (int kq = 4; kq < 8; kq++)
+        z3 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[56 + kq - 4], u1[kq - 4], z3, 0, 0, 0);
+      st4(rb, z0);
+      st4(rb + 16, z1);
+      if (!more) {
+        st4(rb + 32, z2);
+        st4(rb + 48, z3);
+      }
+      z0 = z2;
+      z1 = z3;
+      z2 = n0;
+      z3 = n1;
+      if (more) put_rec(rec);
+      publish(kb + t + 1);
     }
   }
+  if (failed && lane == 0) dev_set_status(st, DS_SYNC_TIMEOUT, 3);
 }
 
 }  // namespace
 
-hipError_t bt2_prepare(const Sb2stLayout& L, const double* V2, const double* tau2, double* T2,
-                       const long* d_goff, hipStream_t s) {
-  (void)d_goff;
+size_t bt2_pack_doubles(const Sb2stLayout& L) { return (size_t)L.ngroups * GREC; }
+
+hipError_t bt2_prepare(const Sb2stLayout& L, const double* V2, const double* tau2, double* F2,
+                       hipStream_t s) {
   if (L.ngroups <= 0) return hipSuccess;
-  hipLaunchKernelGGL(group_t_kernel, dim3((unsigned)L.ngroups), dim3(256), 0, s, V2, tau2, T2);
+  hipLaunchKernelGGL(group_pack_kernel, dim3((unsigned)L.ngroups), dim3(256), 0, s, V2, tau2, F2);
   return hipGetLastError();
 }
 
-hipError_t bt2_apply(const Sb2stLayout& L, const double* V2, const double* T2, const long* d_goff,
-                     double* Z, long ldz, int m, const int* m_dev, hipStream_t s) {
+hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff, double* Z,
+                     long ldz, int m, const int* m_dev, DevStatusWord* st, hipStream_t s) {
   if (L.ngroups <= 0 || m <= 0) return hipSuccess;
-  const int n = L.n, nblk = L.nblk;
-  const int nslab = ceil_div(m, SWA);
-  auto tg = [&](int sb) { return (n - 1 - sb * B + B - 1) / B; };
-  const int lmax = (tg(0) - 1) + 2 * (nblk - 1);
-  for (int level = 0; level <= lmax; level++) {
-    int lo = nblk - 1 - level / 2;
-    if (lo < 0) lo = 0;
-    int hi = -1;  // largest sb with a valid task at this level
-    for (int sb = nblk - 1; sb >= lo; sb--) {
-      const int t = level - 2 * (nblk - 1 - sb);
-      if (t >= 0 && t < tg(sb)) {
-        hi = sb;
-        break;
-      }
-    }
-    if (hi < 0) continue;
-    int first = hi;
-    while (first - 1 >= lo) {
-      const int t = level - 2 * (nblk - 1 - (first - 1));
-      if (t < 0 || t >= tg(first - 1)) break;
-      first--;
-    }
-    hipLaunchKernelGGL(group_apply_kernel, dim3(hi - first + 1, nslab), dim3(512), 0, s, n, nblk,
-                       level, first, V2, T2, d_goff, Z, ldz, m, m_dev);
-    HSDM_TRY(hipGetLastError());
-  }
-  return hipSuccess;
+  hipLaunchKernelGGL(bt2_strip_kernel, dim3(ceil_div(m, 16)), dim3(64 * PW), 0, s, L.n, L.nblk,
+                     F2, d_goff, Z, ldz, m, m_dev, st);
+  return hipGetLastError();
 }
 
 namespace {

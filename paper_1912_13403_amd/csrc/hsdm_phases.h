@@ -30,11 +30,14 @@ hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, doub
                      hipStream_t s);
 
 // bt.hip -- back-transformations.
-// Z (n x m) <- Q2 Z, the stage-2 reflectors applied group by group.
-hipError_t bt2_prepare(const Sb2stLayout& L, const double* V2, const double* tau2, double* T2,
-                       const long* d_goff, hipStream_t s);
-hipError_t bt2_apply(const Sb2stLayout& L, const double* V2, const double* T2, const long* d_goff,
-                     double* Z, long ldz, int m, const int* m_dev, hipStream_t s);
+// Z (n x m) <- Q2 Z.  bt2_prepare forms the T factor of every group and packs
+// V, T into matrix-core operand order (bt2_pack_doubles doubles); bt2_apply
+// applies all groups, one workgroup per strip of 16 columns of Z.
+size_t bt2_pack_doubles(const Sb2stLayout& L);
+hipError_t bt2_prepare(const Sb2stLayout& L, const double* V2, const double* tau2, double* F2,
+                       hipStream_t s);
+hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff, double* Z,
+                     long ldz, int m, const int* m_dev, DevStatusWord* st, hipStream_t s);
 // Z (n x m) <- Q1 Z, the stage-1 panel reflectors (I - V T V^T), applied in
 // groups of 4 panels, last group first.  Vst must hold zeros above each
 // panel's first reflector row (bt1_zero_fill, before the reduction).

@@ -110,22 +110,37 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
     const bool wait_agent = (wv_id == 0);
     const bool pub_agent = (wv_id == WPB - 1);
     double tau = 0.0;
+    const long g0 = goff[s / B];
     for (int t = 0; t < ntask; t++) {
       if (s > 0) wait_ge(progress + s - 1, t + 2, wait_agent, st);
       const int rs = s + 1 + t * B;
       const int len = min(B, n - rs);
       const int rs2 = rs + B;
       const int len2 = (rs2 < n) ? min(B, n - rs2) : 0;
-      // load the diagonal block (symmetrized) and the block below
-      for (int q = 0; q < HB; q++) {
-        const int j = hf * HB + q;
-        double dv = 0.0, bv = 0.0;
-        if (li < len && j < len && li >= j) dv = AB[(li - j) + (long)(rs + j) * ldab];
-        if (li < len2 && j < len) bv = AB[(B + li - j) + (long)(rs + j) * ldab];
-        Bl[li][j] = bv;
-        if (li >= j) {
-          Dl[li][j] = dv;
-          Dl[j][li] = dv;
+      // load the diagonal block (symmetrized) and the block below: all loads
+      // are issued before the first use (addresses clamped into the band,
+      // values masked), so one memory round trip covers the whole task
+      {
+        double dv[HB], bv[HB];
+#pragma unroll
+        for (int q = 0; q < HB; q++) {
+          const int j = hf * HB + q;
+          const bool dok = li < len && j < len && li >= j;
+          const bool bok = li < len2 && j < len;
+          const long cj = (long)min(rs + j, n - 1) * ldab;
+          dv[q] = AB[(dok ? li - j : 0) + cj];
+          bv[q] = AB[(bok ? B + li - j : 0) + cj];
+          dv[q] = dok ? dv[q] : 0.0;
+          bv[q] = bok ? bv[q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < HB; q++) {
+          const int j = hf * HB + q;
+          Bl[li][j] = bv[q];
+          if (li >= j) {
+            Dl[li][j] = dv[q];
+            Dl[j][li] = dv[q];
+          }
         }
       }
       if (t == 0) {
@@ -150,7 +165,7 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
       // store H_{s,t} for the back-transformation
       {
         const int k = s % B;
-        const long gi = goff[s / B] + t;
+        const long gi = g0 + t;
         double* col = V2 + (gi * B + k) * (long)(2 * B);
         const int r = lane - k;
         col[lane] = (r >= 0 && r < len) ? vc[r] : 0.0;
