@@ -8,7 +8,12 @@ back-transformations and D, E.  Inputs are resident in HBM before the timed
 region.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
-                  [--no-cpu-baseline]
+                  [--no-cpu-baseline] [--copy-calibration]
+
+The roofline entry is that of the kernel with the largest total time over the
+timed steps, from HIP events recorded around each of its launches on the
+solve's stream; its "traffic" comes from the committed counter summary
+profiles/traffic_<config>.json while the kernel's source is unchanged.
 """
 from __future__ import annotations
 
@@ -23,22 +28,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix-core peak
-
-
-def phase_flops(n: int, m: int, B: int = 32) -> dict:
-    """Algorithmic FP64 flops of each phase for n, m back-transformed vectors."""
-    n3 = float(n) ** 3
-    return {
-        "cholesky_inverse": 2.0 * n3 / 3.0,          # n^3/3 Cholesky + n^3/3 inverse
-        "standard_form": 4.0 * n3 / 3.0,             # L^-1 H (n^3) + (.) L^-T lower (n^3/3)
-        "full_to_band": 4.0 * n3 / 3.0,              # two-sided panel updates
-        "band_to_tridiagonal": 6.0 * B * n * n,      # bulge chasing
-        "divide_conquer": 2.0 * float(n) * n * m,    # final merge on m vectors (lower levels extra)
-        "backtransform_stage2": 2.0 * float(n) * n * m,
-        "backtransform_stage1": 2.0 * float(n) * n * m,
-        "backtransform_cholesky": float(n) * n * m,
-        "density": 2.0 * float(n) * n * m,           # D and E, lower triangles
-    }
 
 
 def make_inputs(name, dev):
@@ -66,7 +55,7 @@ def cpu_baseline(target_n: int):
     from oracle import oracle as O
     from paper_1912_13403_amd import inputs
 
-    ns = 2048
+    ns = 2560
     H, S = inputs.real_problem(ns, 128.0, 0.05, cfg=2)
     t0 = time.perf_counter()
     O.solve_dm(H, S, ns / 2.0, 0.005)
@@ -84,6 +73,74 @@ def cpu_baseline(target_n: int):
     }
 
 
+# source file of each timed kernel (a stored traffic measurement is only used
+# while the kernel's source is unchanged)
+KERNEL_SOURCES = {
+    "gemm_kernel": ["gemm.hip", "hsdm_internal.h", "hsdm_util.h"],
+    "gemm_batched_kernel": ["gemm.hip", "hsdm_internal.h", "hsdm_util.h"],
+    "sb2st_kernel": ["sb2st.hip", "hsdm_internal.h"],
+    "bt2_strip_kernel": ["bt.hip", "hsdm_internal.h"],
+    "panel_qr_kernel": ["sy2sb.hip", "hsdm_internal.h"],
+    "dm_kernel": ["dm.hip", "hsdm_internal.h", "hsdm_util.h"],
+}
+
+
+def kernel_source_sha(name: str):
+    import hashlib
+    base = name.split("<")[0]
+    files = KERNEL_SOURCES.get(base)
+    if not files:
+        return None
+    h = hashlib.sha1()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1912_13403_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each divided by the copy-kernel calibration
+    factor), or None if there is none for this kernel and source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or k.get("source_sha1") != kernel_source_sha(kernel):
+        return None
+    return (k["fetch_kib_per_dispatch"] / rec["copy_factor_fetch"]
+            + k["write_kib_per_dispatch"] / rec["copy_factor_write"]) * 1024.0
+
+
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
+
+
+def roofline(stats, workload):
+    """Roofline of the kernel with the largest total time in the timed steps:
+    algorithmic flops (or bytes) per launch over the mean launch time from the
+    HIP events recorded around every launch."""
+    name = max(stats, key=lambda k: stats[k]["ms"])
+    st = stats[name]
+    per_launch_s = st["ms"] * 1e-3 / st["launches"]
+    if st["flops"] > 0:
+        achieved = st["flops"] / st["launches"] / per_launch_s / 1e12
+        peak, unit, bound = FP64_PEAK_TFLOPS, "TFLOP/s", "mfma"
+        if name.startswith("sb2st"):
+            bound = "alu"
+    else:
+        achieved = st["bytes"] / st["launches"] / per_launch_s / 1e9
+        peak, unit, bound = HBM_PEAK_GBS, "GB/s", "hbm"
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": stored_traffic(workload, name),
+            "kernel": name, "launches_per_step": st["launches"],
+            "mean_launch_ms": 1e3 * per_launch_s,
+            "algorithmic_flops_per_launch": st["flops"] / st["launches"],
+            "algorithmic_bytes_per_launch": st["bytes"] / st["launches"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +148,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="cfg2_n16384")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-warm", action="store_true",
+                    help="skip the extra solve with the S factor cached")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain device copy of 2 GiB (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -102,13 +164,22 @@ def main():
     from paper_1912_13403_amd import hsdm
 
     dev = torch.device("cuda", 0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {src.numel() * 8} bytes read, {dst.numel() * 8} written",
+              file=sys.stderr, flush=True)
+        del src, dst
+        torch.cuda.empty_cache()
     t0 = time.perf_counter()
     H, S, Hd, Sd, p = make_inputs(args.config, dev)
     n = p["n"]
     print(f"[bench] inputs ready n={n} in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
           flush=True)
     h = hsdm.Handle(0)
-    h.hsdm_set_int(hsdm.HSDM_KEY_TIMING, 1)
+    h.hsdm_set_int(hsdm.HSDM_KEY_TIMING, 2)
     D = hsdm.empty_colmajor(n, n, dev)
     E = hsdm.empty_colmajor(n, n, dev)
     w = torch.empty(n, dtype=torch.float64, device=dev)
@@ -122,7 +193,7 @@ def main():
         step()
         print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    times, phases = [], []
+    times, phases, kstats = [], [], []
     t_all = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
@@ -130,14 +201,17 @@ def main():
         torch.cuda.synchronize()
         times.append(time.perf_counter() - ts)
         phases.append(h.phase_times())
+        kstats.append(h.kernel_stats())
         print(f"[bench] step {i}: {times[-1]:.3f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_all
-    # warm S factor (SCF repeat: the factor of S is reused)
-    ts = time.perf_counter()
-    h.hsdm_solve_dm_real(Hd, Sd, p["n_electrons"], p["kT"], out=out)
-    torch.cuda.synchronize()
-    warm = time.perf_counter() - ts
+    # warm S factor (SCF repeat: the factor of S is reused), outside the timed steps
+    warm = None
+    if not args.skip_warm:
+        ts = time.perf_counter()
+        h.hsdm_solve_dm_real(Hd, Sd, p["n_electrons"], p["kT"], out=out)
+        torch.cuda.synchronize()
+        warm = time.perf_counter() - ts
 
     ph = {k: float(np.median([q[k] for q in phases])) for k in phases[0]}
     f_cut = 1e-16 * p["f_max"]
@@ -146,15 +220,18 @@ def main():
     x = (ev - r["mu"]) / p["kT"]
     f = p["f_max"] / (1.0 + np.exp(np.clip(x, -700, 700)))
     m = int(np.sum(f > f_cut))
-    fl = phase_flops(n, m)
-    dom = max(ph, key=lambda k: ph[k])
-    roof = {}
-    gemm_phase = "standard_form"
-    achieved = fl[gemm_phase] / (ph[gemm_phase] * 1e-3) / 1e12
-    roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-            "kernel": "gemm_kernel<128,128> (standard form: L^-1 H then (.) L^-T, lower)",
-            "flops_per_launch_set": fl[gemm_phase], "ms": ph[gemm_phase]}
+    # per-kernel totals summed over the timed steps
+    agg = {}
+    for ks in kstats:
+        for k, v in ks.items():
+            a = agg.setdefault(k, {"ms": 0.0, "flops": 0.0, "bytes": 0.0, "launches": 0})
+            for f in a:
+                a[f] += v[f]
+    roof = roofline(agg, args.config)
+    top = sorted(agg.items(), key=lambda kv: -kv[1]["ms"])[:8]
+    kernels = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] // args.steps,
+                   "tflops": (v["flops"] / (v["ms"] * 1e-3) / 1e12) if v["ms"] > 0 and v["flops"] > 0
+                   else None} for k, v in top}
     ms = 1000.0 * float(np.mean(times))
     rec = {
         "metric": "n=16384 H,S->D solve time",
@@ -174,7 +251,8 @@ def main():
                    "n": n, "n_electrons": p["n_electrons"], "kT": p["kT"], "m_occupied": m},
         "roofline": roof,
         "phases_ms": ph,
-        "dominant_phase": dom,
+        "dominant_phase": max(ph, key=lambda k: ph[k]),
+        "kernels": kernels,
         "warm_s_factor_s": warm,
         "mu": r["mu"],
         "band_energy": r["band_energy"],

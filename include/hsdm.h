@@ -53,7 +53,8 @@ enum hsdm_key {
   HSDM_KEY_FMAX = 1,       /* real: maximum occupation per state (2 spin-degenerate, 1 per spin channel); default 2 */
   HSDM_KEY_FCUT = 2,       /* real: states with f <= fcut * fmax get no eigenvector (f is below it); default 1e-16 */
   HSDM_KEY_DEG_TOL = 3,    /* real: kT = 0 degeneracy window; < 0 selects 1e-12 * ||H||_1 (default) */
-  HSDM_KEY_TIMING = 4      /* int: 1 records per-phase times (hsdm_phase_times), 0 off (default) */
+  HSDM_KEY_TIMING = 4      /* int: 1 records per-phase times (hsdm_phase_times); 2 also times every
+                              launch of the main kernels of a solve (hsdm_kernel_stat); 0 off (default) */
 };
 
 /* Create a handle bound to HIP device `device` (~ elsi_init, Sec. 2.1). */
@@ -133,6 +134,16 @@ int hsdm_status_detail(hsdm_handle h);
  * of phases written (at most cap). */
 int hsdm_phase_times(hsdm_handle h, double *times, int cap);
 const char *hsdm_phase_name(int i);
+
+/* Per-kernel totals of the last solve when HSDM_KEY_TIMING is 2 (HIP events
+ * recorded around each launch on the solve's stream; the solve synchronizes
+ * before they are read).  hsdm_kernel_count returns the number of kernels
+ * seen so far by this handle; hsdm_kernel_stat returns the name of kernel i
+ * (NULL if i is out of range) and writes out[0] = total time in ms, out[1] =
+ * algorithmic FP64 flops, out[2] = algorithmic bytes (0 where not defined),
+ * out[3] = number of launches, all for the last solve. */
+int hsdm_kernel_count(hsdm_handle h);
+const char *hsdm_kernel_stat(hsdm_handle h, int i, double *out);
 int hsdm_version(void);
 
 #ifdef __cplusplus

@@ -62,6 +62,8 @@ struct hsdm_ctx {
   double fcut_rel = 1e-16;
   double deg_tol = -1.0;
   bool timing = false;
+  bool ktiming = false;
+  KTimer* kt = nullptr;
   std::string err;
   int detail = 0;
   // workspace
@@ -190,6 +192,10 @@ int finish(hsdm_ctx* h, hipStream_t s) {
   DEV_TRY(h, hipMemcpyAsync(&h->host->st, h->st, sizeof(DevStatusWord), hipMemcpyDeviceToHost, s));
   DEV_TRY(h, hipMemcpyAsync(&h->host->occ, h->occ, sizeof(OccOut), hipMemcpyDeviceToHost, s));
   DEV_TRY(h, hipStreamSynchronize(s));
+  if (h->ktiming) {
+    kt_collect(h->kt, h->host->occ.m);
+    kt_activate(nullptr);
+  }
   if (h->timing) {
     for (int p = 0; p < NPHASE; p++) {
       h->phase_ms[p] = 0.0;
@@ -277,6 +283,17 @@ hipError_t occ_hook(void* ctx, const double* lam, hipStream_t s) {
 
 int check_handle(hsdm_handle h) { return h ? 0 : -1; }
 
+// Kernel timing for the duration of one solve (finish() folds the records).
+struct KtScope {
+  explicit KtScope(hsdm_ctx* h) {
+    if (h->ktiming) {
+      kt_reset(h->kt);
+      kt_activate(h->kt);
+    }
+  }
+  ~KtScope() { kt_activate(nullptr); }
+};
+
 }  // namespace
 
 extern "C" {
@@ -308,6 +325,7 @@ int hsdm_init(hsdm_handle* out, int device) {
     return HSDM_DEVICE_ERROR;
   }
   for (int i = 0; i <= NPHASE; i++) (void)hipEventCreate(&h->ev[i]);
+  h->kt = kt_create();
   *out = h;
   return HSDM_OK;
 }
@@ -320,6 +338,7 @@ int hsdm_finalize(hsdm_handle h) {
   if (h->host) (void)hipHostFree(h->host);
   for (int i = 0; i <= NPHASE; i++)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+  kt_destroy(h->kt);
   delete h;
   return HSDM_OK;
 }
@@ -353,7 +372,9 @@ int hsdm_set_real(hsdm_handle h, int key, double v) {
 int hsdm_set_int(hsdm_handle h, int key, long v) {
   if (!h) return -1;
   if (key == HSDM_KEY_TIMING) {
+    if (v < 0 || v > 2) return -3;
     h->timing = (v != 0);
+    h->ktiming = (v == 2);
     return HSDM_OK;
   }
   return -2;
@@ -382,6 +403,13 @@ int hsdm_phase_times(hsdm_handle h, double* times, int cap) {
 }
 
 const char* hsdm_phase_name(int i) { return (i >= 0 && i < NPHASE) ? kPhaseNames[i] : ""; }
+
+int hsdm_kernel_count(hsdm_handle h) { return h ? kt_count(h->kt) : 0; }
+
+const char* hsdm_kernel_stat(hsdm_handle h, int i, double* out) {
+  if (!h) return nullptr;
+  return kt_stat(h->kt, i, out);
+}
 
 int hsdm_dgemm(hsdm_handle h, char transa, char transb, int m, int n, int k, double alpha,
                const double* A, int lda, const double* B, int ldb, double beta, double* C,
@@ -582,6 +610,7 @@ int hsdm_solve_ev_real(hsdm_handle h, int n, const double* H, int ldh, const dou
   DEV_TRY(h, hipSetDevice(h->device));
   int r = ensure_ws(h, n);
   if (r) return r;
+  KtScope kts(h);
   for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
   hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
@@ -624,6 +653,7 @@ int hsdm_solve_dm_real(hsdm_handle h, int n, const double* H, int ldh, const dou
   DEV_TRY(h, hipSetDevice(h->device));
   int r = ensure_ws(h, n);
   if (r) return r;
+  KtScope kts(h);
   for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
   hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());

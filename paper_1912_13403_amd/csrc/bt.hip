@@ -275,8 +275,13 @@ hipError_t bt2_prepare(const Sb2stLayout& L, const double* V2, const double* tau
 hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff, double* Z,
                      long ldz, int m, const int* m_dev, DevStatusWord* st, hipStream_t s) {
   if (L.ngroups <= 0 || m <= 0) return hipSuccess;
+  // algorithmic: per group and column of Z, V^T z (B^2 multiply-adds on the
+  // parallelogram), T w (B(B+1)/2) and z - V w (B^2)
+  const double fl = 2.0 * (double)L.ngroups * (2.0 * B * B + 0.5 * B * (B + 1)) * m;
+  kt_begin("bt2_strip_kernel", fl, 0.0, m_dev ? m : 0, s);
   hipLaunchKernelGGL(bt2_strip_kernel, dim3(ceil_div(m, 16)), dim3(64 * PW), 0, s, L.n, L.nblk,
                      F2, d_goff, Z, ldz, m, m_dev, st);
+  kt_end(s);
   return hipGetLastError();
 }
 

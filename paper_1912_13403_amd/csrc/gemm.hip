@@ -19,6 +19,8 @@
 // A and B panels of one XCD stay in its L2.
 #include <cstdlib>
 
+#include <string>
+
 #include "hsdm_internal.h"
 
 namespace {
@@ -342,12 +344,23 @@ __global__ void scale_kernel(int m, int n, double* C, long ldc, double beta, con
 
 // ---- dispatch ----------------------------------------------------------------------
 template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
+const char* kernel_name() {
+  static const std::string nm = "gemm_kernel<" + std::to_string(BM) + ", " + std::to_string(BN) +
+                                ", " + std::to_string(WM) + ", " + std::to_string(WN) + ", " +
+                                std::to_string(TA) + ", " + std::to_string(TB) + ", " +
+                                std::to_string(AM) + ">";
+  return nm.c_str();
+}
+
+template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
 hipError_t launch_cfg(const Prob& p, double alpha, double beta, int flags, int nsplit, int kchunk,
-                      long stride, hipStream_t s) {
+                      long stride, double flops, hipStream_t s) {
   long tiles = (long)ceil_div(p.m, BM) * ceil_div(p.n, BN);
   int nblk = (int)(((tiles + 7) / 8) * 8);
+  kt_begin(kernel_name<BM, BN, WM, WN, TA, TB, AM>(), flops, 0.0, p.ndev ? p.n : 0, s);
   hipLaunchKernelGGL((gemm_kernel<BM, BN, WM, WN, TA, TB, AM>), dim3(nblk, nsplit),
                      dim3(64 * WM * WN), 0, s, p, alpha, beta, flags, kchunk, stride);
+  kt_end(s);
   return hipGetLastError();
 }
 
@@ -371,48 +384,60 @@ int pick_cfg(int m, int n, int nsplit) {
 
 template <int TA, int TB, int AM>
 hipError_t launch_t(const Prob& p, double alpha, double beta, int flags, int nsplit, int kchunk,
-                    long stride, hipStream_t s) {
+                    long stride, double fl, hipStream_t s) {
   switch (pick_cfg(p.m, p.n, nsplit)) {
     case 0:
       return launch_cfg<128, 128, 2, 4, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
-                                                    s);
+                                                    fl, s);
     case 1:
       return launch_cfg<128, 64, 2, 2, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
-                                                   s);
+                                                   fl, s);
     case 3:
       return launch_cfg<128, 32, 4, 1, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
-                                                   s);
+                                                   fl, s);
     case 4:
       return launch_cfg<32, 128, 1, 4, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
-                                                   s);
+                                                   fl, s);
     default:
       return launch_cfg<64, 64, 2, 2, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
-                                                  s);
+                                                  fl, s);
   }
 }
 
 hipError_t launch_any(const Prob& p, int ta, int tb, int am, double alpha, double beta, int flags,
-                      int nsplit, int kchunk, long stride, hipStream_t s) {
+                      int nsplit, int kchunk, long stride, double fl, hipStream_t s) {
   if (am == AM_TRIL) {
-    if (tb) return launch_t<0, 1, AM_TRIL>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
-    return launch_t<0, 0, AM_TRIL>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+    if (tb) return launch_t<0, 1, AM_TRIL>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
+    return launch_t<0, 0, AM_TRIL>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
   }
   if (am == AM_SLT) {
-    if (tb) return launch_t<1, 1, AM_SLT>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
-    return launch_t<1, 0, AM_SLT>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+    if (tb) return launch_t<1, 1, AM_SLT>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
+    return launch_t<1, 0, AM_SLT>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
   }
-  if (am == AM_SYM) return launch_t<0, 0, AM_SYM>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+  if (am == AM_SYM) return launch_t<0, 0, AM_SYM>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
   if (am == AM_GATHER) {
-    if (tb) return launch_t<0, 1, AM_GATHER>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
-    return launch_t<0, 0, AM_GATHER>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+    if (tb) return launch_t<0, 1, AM_GATHER>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
+    return launch_t<0, 0, AM_GATHER>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
   }
   if (ta == 0 && tb == 0)
-    return launch_t<0, 0, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+    return launch_t<0, 0, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
   if (ta == 0 && tb == 1)
-    return launch_t<0, 1, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+    return launch_t<0, 1, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
   if (ta == 1 && tb == 0)
-    return launch_t<1, 0, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
-  return launch_t<1, 1, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, s);
+    return launch_t<1, 0, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
+  return launch_t<1, 1, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
+}
+
+// Algorithmic flops of one product: 2 m n k, halved for a lower-triangular
+// result (square C), for a triangular op(A) or op(B), and for each half of a
+// symmetric operand.
+double gemm_flops(const GemmArgs& g) {
+  double f = 2.0 * g.m * g.n * (double)g.k;
+  if ((g.flags & (GF_C_LOWER_TILES | GF_C_LOWER_ONLY)) && g.m == g.n) f *= (g.n + 1.0) / (2.0 * g.n);
+  if (g.flags & (GF_KA_LOWER | GF_KA_UPPER)) f *= 0.5;
+  if (g.flags & (GF_KB_LOWER | GF_KB_UPPER)) f *= 0.5;
+  if (g.flags & (GF_A_TRIL | GF_A_SLT)) f *= 0.5;
+  return f;
 }
 
 int a_mode(const GemmArgs& g) {
@@ -438,7 +463,7 @@ hipError_t gemm_launch(const GemmArgs& g, hipStream_t s) {
   if ((am == AM_SYM || am == AM_GATHER || am == AM_TRIL) && g.ta != 0) return hipErrorInvalidValue;
   if (am == AM_SLT && g.ta != 1) return hipErrorInvalidValue;
   Prob p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.acol, g.ccol, g.ndev};
-  return launch_any(p, g.ta, g.tb, am, g.alpha, g.beta, g.flags, 1, 0, 0L, s);
+  return launch_any(p, g.ta, g.tb, am, g.alpha, g.beta, g.flags, 1, 0, 0L, gemm_flops(g), s);
 }
 
 hipError_t gemm_splitk_launch(const GemmArgs& g, int kchunk, double* part, hipStream_t s) {
@@ -452,7 +477,8 @@ hipError_t gemm_splitk_launch(const GemmArgs& g, int kchunk, double* part, hipSt
   const int nsplit = ceil_div(g.k, kchunk);
   Prob p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, part, (long)g.m, g.acol, nullptr, g.ndev};
   const long stride = (long)g.m * g.n;
-  HSDM_TRY(launch_any(p, g.ta, g.tb, am, g.alpha, 0.0, g.flags, nsplit, kchunk, stride, s));
+  HSDM_TRY(
+      launch_any(p, g.ta, g.tb, am, g.alpha, 0.0, g.flags, nsplit, kchunk, stride, gemm_flops(g), s));
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((stride + 255) / 256)), dim3(256), 0, s,
                      g.m, g.n, nsplit, part, g.C, g.ldc, g.beta, g.ndev);
   return hipGetLastError();
@@ -465,7 +491,9 @@ hipError_t gemm_batched_launch(const GemmDesc* d_desc, int count, int max_m, int
   if (ta != 0 || tb != 0) return hipErrorInvalidValue;
   long tiles = (long)ceil_div(max_m, 64) * ceil_div(max_n, 64);
   int nblk = (int)(((tiles + 7) / 8) * 8);
+  kt_begin("gemm_batched_kernel<64, 64, 2, 2, 0, 0, 2>", 0.0, 0.0, 0, s);
   hipLaunchKernelGGL((gemm_batched_kernel<64, 64, 2, 2, 0, 0, AM_GATHER>), dim3(nblk, count),
                      dim3(256), 0, s, d_desc, alpha, beta, flags);
+  kt_end(s);
   return hipGetLastError();
 }

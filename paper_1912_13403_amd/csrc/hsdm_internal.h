@@ -59,6 +59,24 @@ hipError_t gemm_batched_launch(const GemmDesc* d_desc, int count, int max_m, int
                                hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// Kernel timer (ktimer.hip): per-launch HIP events on the launching stream,
+// active for the calling thread between kt_activate(k) and kt_activate(nullptr).
+struct KTimer;
+KTimer* kt_create();
+void kt_destroy(KTimer* k);
+void kt_activate(KTimer* k);
+void kt_reset(KTimer* k);
+// flops / bytes: algorithmic work of this launch; nbound > 0 marks work that
+// scales with a device-side count (the occupied states) bounded by nbound.
+void kt_begin(const char* name, double flops, double bytes, int nbound, hipStream_t s);
+void kt_end(hipStream_t s);
+// After the stream is synchronized: fold records into per-kernel totals (m =
+// the device-side count for records with nbound > 0, < 0 if unknown).
+void kt_collect(KTimer* k, int m);
+int kt_count(const KTimer* k);
+const char* kt_stat(const KTimer* k, int i, double* out4);
+
+// ---------------------------------------------------------------------------
 // Device status word shared by all kernels of a solve (first error wins).
 enum DevStatus {
   DS_OK = 0,

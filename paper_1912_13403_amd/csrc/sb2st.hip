@@ -314,8 +314,13 @@ hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, doub
     // wavefront group; TW = nwg * WPB keeps that true for every round)
     void* args[] = {(void*)&n, (void*)&nsweep, (void*)&AB, (void*)&ldab, (void*)&V2,
                     (void*)&tau2, (void*)&d_goff, (void*)&progress, (void*)&st};
+    // algorithmic: about 6 B n^2 flops; each task reads and writes the lower
+    // half of its diagonal block and the block below (24 B^2 bytes), n^2 / 2B tasks
+    const double nn = (double)n * n;
+    kt_begin("sb2st_kernel<32>", 6.0 * L.B * nn, 12.0 * L.B * nn, 0, s);
     HSDM_TRY(hipLaunchCooperativeKernel((const void*)sb2st_kernel<32>, dim3(nwg), dim3(64 * WPB),
                                         args, 0, s));
+    kt_end(s);
   }
   hipLaunchKernelGGL(extract_tridiag_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, AB, ldab,
                      d, e);

@@ -281,8 +281,12 @@ hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, d
                     (void*)&bar, (void*)&st};
     double* tau_p = tau1 + c0;
     args[5] = (void*)&tau_p;
+    // algorithmic: Householder QR of the h x B panel (2 h B^2 flops), the
+    // panel read and written once
+    kt_begin("panel_qr_kernel<32>", 2.0 * h * B * B, 16.0 * h * B, 0, s);
     HSDM_TRY(hipLaunchCooperativeKernel((const void*)panel_qr_kernel<BB>, dim3(G), dim3(NT), args,
                                         0, s));
+    kt_end(s);
     if (h <= 1) continue;
     double* A22 = A + r0 + (long)r0 * lda;
     // Y = V T

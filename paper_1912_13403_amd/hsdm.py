@@ -38,7 +38,8 @@ EXPORTED = [
     "hsdm_solve_ev_real", "hsdm_solve_dm_real", "hsdm_cholesky_inverse", "hsdm_standard_form",
     "hsdm_tridiagonalize", "hsdm_tridiag_eigh", "hsdm_occupations", "hsdm_density",
     "hsdm_dgemm", "hsdm_status_string", "hsdm_last_error", "hsdm_status_detail",
-    "hsdm_phase_times", "hsdm_phase_name", "hsdm_version",
+    "hsdm_phase_times", "hsdm_phase_name", "hsdm_kernel_count", "hsdm_kernel_stat",
+    "hsdm_version",
 ]
 
 _lib = None
@@ -78,6 +79,8 @@ def load_library(path: str = LIB_PATH):
         "hsdm_status_detail": ([_vp], _i),
         "hsdm_phase_times": ([_vp, ctypes.POINTER(_d), _i], _i),
         "hsdm_phase_name": ([_i], ctypes.c_char_p),
+        "hsdm_kernel_count": ([_vp], _i),
+        "hsdm_kernel_stat": ([_vp, _i, ctypes.POINTER(_d)], ctypes.c_char_p),
         "hsdm_version": ([], _i),
     }
     for name, (args, res) in sig.items():
@@ -167,6 +170,19 @@ class Handle:
         buf = (ctypes.c_double * 16)()
         k = self._lib.hsdm_phase_times(self._h, buf, 16)
         return {self._lib.hsdm_phase_name(i).decode(): buf[i] for i in range(k)}
+
+    def kernel_stats(self):
+        """Per-kernel totals of the last solve (HSDM_KEY_TIMING = 2):
+        name -> {"ms", "flops", "bytes", "launches"}."""
+        out = {}
+        buf = (ctypes.c_double * 4)()
+        for i in range(self._lib.hsdm_kernel_count(self._h)):
+            name = self._lib.hsdm_kernel_stat(self._h, i, buf)
+            if name is None:
+                continue
+            out[name.decode()] = {"ms": buf[0], "flops": buf[1], "bytes": buf[2],
+                                  "launches": int(buf[3])}
+        return out
 
     # ---- solves ------------------------------------------------------------
     def hsdm_solve_ev_real(self, H, S):

@@ -1,0 +1,119 @@
+"""Summaries of rocprofv3 output for the kernels of the solve.
+
+  python -m paper_1912_13403_amd.profiling stats DIR
+      per-kernel calls / total / average duration from the *_kernel_stats.csv
+      (or *_kernel_trace.csv) that `rocprofv3 --kernel-trace --stats
+      --output-format csv -d DIR` wrote.
+
+  python -m paper_1912_13403_amd.profiling traffic FETCH_DIR WRITE_DIR OUT.json
+      mean FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of every kernel from two
+      `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
+      `bench.py --copy-calibration`, with the calibration factors: what each
+      counter reads for the plain 2 GiB device copy that run starts with,
+      divided by the bytes that copy moves.  bench.py divides a kernel's
+      counters by these factors to get its HBM bytes per launch.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+COPY_BYTES = 8 << 28  # bench.py --copy-calibration: 2^28 doubles read and written
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _find(d, pattern):
+    hits = sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no {pattern} under {d}")
+    return hits[0]
+
+
+def _short(name):
+    name = name.replace("(anonymous namespace)::", "")
+    if name.startswith("void "):
+        name = name[5:]
+    i = name.find("(")
+    return name[:i] if i > 0 else name
+
+
+def stats(d):
+    """name -> (calls, total_ms, mean_us) from a kernel trace csv."""
+    path = _find(d, "*kernel_trace.csv")
+    agg = {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            name = _short(row.get("Kernel_Name", ""))
+            t = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-6
+            a = agg.setdefault(name, [0, 0.0])
+            a[0] += 1
+            a[1] += t
+    return {k: (v[0], v[1], 1e3 * v[1] / v[0]) for k, v in agg.items()}
+
+
+def print_stats(d, top=25):
+    st = stats(d)
+    tot = sum(v[1] for v in st.values())
+    print(f"{'total ms':>10} {'%':>5} {'calls':>7} {'mean us':>10}  kernel")
+    for k, (c, t, m) in sorted(st.items(), key=lambda kv: -kv[1][1])[:top]:
+        print(f"{t:10.2f} {100 * t / tot:5.1f} {c:7d} {m:10.1f}  {k}")
+    print(f"{tot:10.2f} total kernel time (ms)")
+
+
+def _counter(d, counter):
+    path = _find(d, "*counter_collection.csv")
+    per = {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            if row.get("Counter_Name") != counter:
+                continue
+            key = (row.get("Dispatch_Id") or row.get("Correlation_Id"), _short(row["Kernel_Name"]))
+            per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    return per
+
+
+def _source_sha(kernel):
+    sys.path.insert(0, ROOT)
+    import bench  # noqa: E402  (the same hash bench.py checks)
+    return bench.kernel_source_sha(kernel)
+
+
+def traffic(fetch_dir, write_dir, out_path, workload="cfg2_n16384"):
+    res = {"workload": workload, "copy_bytes": COPY_BYTES, "kernels": {}}
+    for counter, d, fkey in (("FETCH_SIZE", fetch_dir, "fetch"), ("WRITE_SIZE", write_dir, "write")):
+        per = _counter(d, counter)
+        by = {}
+        for (_, name), v in per.items():
+            by.setdefault(name, []).append(v)
+        # the calibration copy is the torch elementwise copy with the largest reading
+        copies = [v for (_, name), v in per.items() if "copy" in name.lower()]
+        if not copies:
+            raise RuntimeError(f"no copy kernel in the {counter} run")
+        res[f"copy_factor_{fkey}"] = max(copies) * 1024.0 / COPY_BYTES
+        for name, vals in by.items():
+            k = res["kernels"].setdefault(name, {})
+            k[f"{fkey}_kib_per_dispatch"] = sum(vals) / len(vals)
+            k["dispatches"] = len(vals)
+    for name, k in res["kernels"].items():
+        k["source_sha1"] = _source_sha(name)
+    res["kernels"] = {k: v for k, v in res["kernels"].items()
+                      if "fetch_kib_per_dispatch" in v and "write_kib_per_dispatch" in v
+                      and v["source_sha1"]}
+    with open(out_path, "w") as fh:
+        json.dump(res, fh, indent=1, sort_keys=True)
+    return res
+
+
+if __name__ == "__main__":
+    if len(sys.argv) >= 3 and sys.argv[1] == "stats":
+        print_stats(sys.argv[2])
+    elif len(sys.argv) >= 5 and sys.argv[1] == "traffic":
+        r = traffic(sys.argv[2], sys.argv[3], sys.argv[4])
+        print(json.dumps({k: r[k] for k in r if k != "kernels"}))
+    else:
+        print(__doc__)
+        sys.exit(2)
