@@ -516,7 +516,7 @@ int hsdm_tridiagonalize(hsdm_handle h, int n, const double* A, int lda, double* 
                        (long)ldq, n);
     DEV_TRY(h, hipGetLastError());
     DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
-    DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, Q, ldq, n, nullptr, h->st, s));
+    DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, Q, ldq, n, nullptr, h->progress, h->st, s));
     DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, Q, ldq, n, nullptr, h->bt1_scr, s));
   }
   return finish(h, s);
@@ -625,7 +625,7 @@ int hsdm_solve_ev_real(hsdm_handle h, int n, const double* H, int ldh, const dou
                        nullptr, nullptr, nullptr, h->st, s));
   mark(h, 5, s);
   DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
-  DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, n, nullptr, h->st, s));
+  DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, n, nullptr, h->progress, h->st, s));
   mark(h, 6, s);
   DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, n, nullptr, h->bt1_scr, s));
   mark(h, 7, s);
@@ -671,7 +671,7 @@ int hsdm_solve_dm_real(hsdm_handle h, int n, const double* H, int ldh, const dou
                        m_dev, occ_hook, &hook, h->st, s));
   mark(h, 5, s);
   DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
-  DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, n, m_dev, h->st, s));
+  DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, n, m_dev, h->progress, h->st, s));
   mark(h, 6, s);
   DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, n, m_dev, h->bt1_scr, s));
   mark(h, 7, s);

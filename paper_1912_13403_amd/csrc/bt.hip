@@ -79,6 +79,11 @@ __global__ __launch_bounds__(256) void group_pack_kernel(const double* V2, const
 // operands (V^T, T, -V, zero parts skipped) are read.  Progress counters
 // live in LDS; their keys grow monotonically across a wavefront's sweep
 // blocks.
+__global__ void fill_i32_kernel(int* p, int cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) p[i] = 0;
+}
+
 constexpr int PW = 4;            // wavefronts per workgroup (one per SIMD)
 constexpr int KEYM = 1 << 13;    // > tasks per sweep block
 constexpr int NFRAG = 60;        // A operands per group: 24 (V^T) + 12 (T) + 24 (-V)
@@ -88,21 +93,57 @@ constexpr int NST = GREC / 64;   // record doubles per lane
 
 HSDM_DEV int key_of(int nblk, int b) { return (nblk - 1 - b) * KEYM; }
 
-__global__ __launch_bounds__(64 * PW) void bt2_strip_kernel(int n, int nblk, const double* F2,
+// The sweep blocks are cut into NSPLIT ranges of about equal work; workgroup
+// (k, strip) applies range k (k = 0 holds the last sweep blocks, which come
+// first) to its strip once workgroup (k-1, strip) has finished, so that the
+// strips' work is spread over NSPLIT times as many workgroups.
+constexpr int NSPLIT = 4;
+struct SplitRanges {
+  int hi[NSPLIT];  // range k covers sweep blocks lo[k] .. hi[k] (hi[k] = lo[k-1] - 1)
+  int lo[NSPLIT];
+};
+
+__global__ __launch_bounds__(64 * PW) void bt2_strip_kernel(int n, int nblk, SplitRanges R,
+                                                            int nstrip, const double* F2,
                                                             const long* goff, double* Z, long ldz,
                                                             int m_host, const int* m_dev,
-                                                            DevStatusWord* st) {
+                                                            int* done, DevStatusWord* st) {
   const int m = m_dev ? *m_dev : m_host;
-  const int c0 = blockIdx.x * 16;
-  if (c0 >= m) return;
+  const int strip = blockIdx.x % nstrip, kr = blockIdx.x / nstrip;
+  const int c0 = strip * 16;
+  if (c0 >= m) return;  // (every range of this strip returns here)
   __shared__ int prog[PW];
+  __shared__ int wg_failed;
   __shared__ double Vl_all[PW][B * VS];
   __shared__ double Tl_all[PW][B * TS];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double* Vl = Vl_all[w];
   double* Tl = Tl_all[w];
   if (lane == 0) prog[w] = -1;
+  if (threadIdx.x == 0) {
+    // range kr - 1 of this strip must be complete (its workgroup has a lower
+    // index, so it was dispatched earlier and is running or finished)
+    int bad = 0;
+    if (kr > 0) {
+      long spins = 0;
+      while (__hip_atomic_load(&done[strip], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < kr) {
+        if (++spins > (1L << 26) ||
+            ((spins & 4095) == 0 &&
+             __hip_atomic_load(&st->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+          bad = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    wg_failed = bad;
+  }
   __syncthreads();
+  if (wg_failed) {
+    if (threadIdx.x == 0) dev_set_status(st, DS_SYNC_TIMEOUT, 3);
+    return;
+  }
   const int l16 = lane & 15, l4 = lane >> 4;
   const int col = c0 + l16;
   const bool cok = col < m;
@@ -182,9 +223,9 @@ __global__ __launch_bounds__(64 * PW) void bt2_strip_kernel(int n, int nblk, con
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   };
 
-  for (int b = nblk - 1 - w; b >= 0 && !failed; b -= PW) {
+  for (int b = R.hi[kr] - w; b >= R.lo[kr] && !failed; b -= PW) {
     const int T = tgb(b);
-    const bool has_pred = (b + 1 <= nblk - 1);
+    const bool has_pred = (b + 1 <= R.hi[kr]);
     const int T1 = has_pred ? tgb(b + 1) : 0;
     const int kb = key_of(nblk, b), kp = has_pred ? key_of(nblk, b + 1) : 0;
     const double* Gb = F2 + goff[b] * (long)GREC;
@@ -259,6 +300,13 @@ __global__ __launch_bounds__(64 * PW) void bt2_strip_kernel(int n, int nblk, con
     }
   }
   if (failed && lane == 0) dev_set_status(st, DS_SYNC_TIMEOUT, 3);
+  // every wavefront's stores reach agent scope before the range is marked done
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&done[strip], kr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 }  // namespace
@@ -273,14 +321,34 @@ hipError_t bt2_prepare(const Sb2stLayout& L, const double* V2, const double* tau
 }
 
 hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff, double* Z,
-                     long ldz, int m, const int* m_dev, DevStatusWord* st, hipStream_t s) {
+                     long ldz, int m, const int* m_dev, int* iscratch, DevStatusWord* st,
+                     hipStream_t s) {
   if (L.ngroups <= 0 || m <= 0) return hipSuccess;
+  const int n = L.n, nblk = L.nblk;
+  // sweep-block ranges of about equal work (tasks), last blocks first
+  auto tgb = [&](int b) { return (n - 1 - b * B + B - 1) / B; };
+  long tot = 0;
+  for (int b = 0; b < nblk; b++) tot += tgb(b);
+  SplitRanges R{};
+  int b = nblk - 1;
+  for (int k = 0; k < NSPLIT; k++) {
+    R.hi[k] = b;
+    const long want = tot * (k + 1) / NSPLIT;
+    long acc = 0;
+    for (int q = nblk - 1; q > b; q--) acc += tgb(q);
+    while (b >= 0 && (acc < want || k == NSPLIT - 1)) acc += tgb(b--);
+    R.lo[k] = b + 1;
+  }
+  const int nstrip = ceil_div(m, 16);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(ceil_div(nstrip, 256)), dim3(256), 0, s, iscratch,
+                     nstrip);
+  HSDM_TRY(hipGetLastError());
   // algorithmic: per group and column of Z, V^T z (B^2 multiply-adds on the
   // parallelogram), T w (B(B+1)/2) and z - V w (B^2)
   const double fl = 2.0 * (double)L.ngroups * (2.0 * B * B + 0.5 * B * (B + 1)) * m;
   kt_begin("bt2_strip_kernel", fl, 0.0, m_dev ? m : 0, s);
-  hipLaunchKernelGGL(bt2_strip_kernel, dim3(ceil_div(m, 16)), dim3(64 * PW), 0, s, L.n, L.nblk,
-                     F2, d_goff, Z, ldz, m, m_dev, st);
+  hipLaunchKernelGGL(bt2_strip_kernel, dim3(nstrip * NSPLIT), dim3(64 * PW), 0, s, n, nblk, R,
+                     nstrip, F2, d_goff, Z, ldz, m, m_dev, iscratch, st);
   kt_end(s);
   return hipGetLastError();
 }

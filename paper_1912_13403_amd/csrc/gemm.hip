@@ -175,10 +175,35 @@ HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int flags, int
   const int l16 = lane & 15, l4 = lane >> 4;
 
   dbl4 acc[C::FM][C::FN];
+  // With alpha = +-1 the accumulators start from (beta / alpha) C, exact in
+  // FP64, so the C tile is read while the first A and B slices load instead
+  // of after the contraction.
+  const bool cinit = (beta != 0.0) && (alpha == 1.0 || alpha == -1.0);
+  if (cinit) {
+    const double sc = beta * alpha;  // beta / alpha for alpha = +-1
 #pragma unroll
-  for (int a = 0; a < C::FM; a++)
+    for (int b = 0; b < C::FN; b++) {
+      const int col = j0 + wn * C::WTN + b * 16 + l16;
+      const bool cok = col < p.n;
+      const long cc = cok ? (p.ccol ? (long)p.ccol[col] : (long)col) : 0L;
+      const double* cp = p.C + cc * p.ldc;
 #pragma unroll
-    for (int b = 0; b < C::FN; b++) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+      for (int a = 0; a < C::FM; a++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int row = i0 + wm * C::WTM + a * 16 + l4 + 4 * r;
+          bool ok = cok && row < p.m;
+          if (flags & GF_C_LOWER_ONLY) ok = ok && row >= col;
+          const double v = cp[min(row, p.m - 1)];  // in bounds for every lane
+          acc[a][b][r] = ok ? sc * v : 0.0;
+        }
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < C::FM; a++)
+#pragma unroll
+      for (int b = 0; b < C::FN; b++) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  }
 
   double ra[C::AE], rb[C::BE];
   if (kstart < ke) {
@@ -241,7 +266,7 @@ HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int flags, int
         if (row >= p.m) continue;
         if ((flags & GF_C_LOWER_ONLY) && row < col) continue;
         double v = alpha * acc[a][b][r];
-        if (beta != 0.0) v += beta * cp[row];
+        if (beta != 0.0 && !cinit) v += beta * cp[row];
         cp[row] = v;
       }
     }

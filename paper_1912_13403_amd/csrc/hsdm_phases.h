@@ -36,8 +36,10 @@ hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, doub
 size_t bt2_pack_doubles(const Sb2stLayout& L);
 hipError_t bt2_prepare(const Sb2stLayout& L, const double* V2, const double* tau2, double* F2,
                        hipStream_t s);
+// iscratch: ceil(m / 16) ints of device scratch (cleared here).
 hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff, double* Z,
-                     long ldz, int m, const int* m_dev, DevStatusWord* st, hipStream_t s);
+                     long ldz, int m, const int* m_dev, int* iscratch, DevStatusWord* st,
+                     hipStream_t s);
 // Z (n x m) <- Q1 Z, the stage-1 panel reflectors (I - V T V^T), applied in
 // groups of 4 panels, last group first.  Vst must hold zeros above each
 // panel's first reflector row (bt1_zero_fill, before the reduction).
