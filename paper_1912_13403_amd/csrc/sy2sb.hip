@@ -243,13 +243,25 @@ __global__ void zero_u32_kernel(unsigned* p, int n) {
 
 size_t sy2sb_scratch_doubles(int n, int B) {
   const int G = ceil_div(n, CH) + 1;
-  // part(2GB) + prow(2B) + gpart(G B^2) + atb parts(G B^2) + Y,VW,WV (n x 2B each) + M (B^2)
-  // + split-K partials of X (nsplit x n x B)
+  // part(2GB) + prow(2B) + gpart(G B^2) + atb parts(G B^2) + Y (n x B) + VW, WV (n x 4B each)
+  // + M (B^2) + Q (2B^2) + split-K partials (nsplit x n x B)
   const size_t nsplit = ceil_div(n, SPLITK) + 1;
-  return (size_t)2 * G * B + 2 * B + (size_t)2 * G * B * B + (size_t)5 * n * 2 * B + B * B + 64 +
+  return (size_t)2 * G * B + 2 * B + (size_t)2 * G * B * B + (size_t)9 * n * B + 3 * B * B + 64 +
          nsplit * n * B;
 }
 
+// Panels are reduced in pairs with one trailing update per pair.  For the
+// pair (p, p+1), with A22 the trailing block of panel p:
+//   panel p:   QR -> V1, T1;  Y1 = V1 T1;  X1 = A22 Y1;  W1 = X1 - V1 (Y1^T X1) / 2;
+//              only the B columns of panel p+1 receive the update
+//              A22[:, 0:B] -= V1 W1[0:B]^T + W1 V1[0:B]^T;
+//   panel p+1: QR -> V2, T2 on the updated columns;  Y2 = V2 T2;
+//              X2 = A22'' Y2 with A22'' = A22[B:, B:] - V1b W1b^T - W1b V1b^T
+//                 = A22[B:, B:] Y2 - [V1b W1b] ([W1b V1b]^T Y2)   (b: rows B..)
+//              W2 = X2 - V2 (Y2^T X2) / 2;
+//   then one rank-4B update A22[B:, B:] -= [V1b W1b V2 W2][W1b V1b W2 V2]^T,
+// which halves the passes over the trailing matrix.  The products are the
+// same as panel by panel; only the order of the roundings differs.
 hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, double* tau1,
                      double* T1, double* AB, int ldab, double* scratch, unsigned* bar,
                      DevStatusWord* st, hipStream_t s) {
@@ -261,71 +273,128 @@ hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, d
   double* gpart = prow + 2 * B;
   double* apart = gpart + (size_t)Gmax * B * B;
   double* Y = apart + (size_t)Gmax * B * B;      // n x B
-  double* VW = Y + (size_t)n * B;                // n x 2B  [V W]
-  double* WV = VW + (size_t)n * 2 * B;           // n x 2B  [W V]
-  double* M = WV + (size_t)n * 2 * B;            // B x B
-  double* skpart = M + B * B + 64;               // split-K partials
+  double* VW = Y + (size_t)n * B;                // n x 4B  [V1 W1 V2 W2], row i <-> row r0 + i
+  double* WV = VW + (size_t)n * 4 * B;           // n x 4B  [W1 V1 W2 V2]
+  double* M = WV + (size_t)n * 4 * B;            // B x B
+  double* Qc = M + B * B;                        // 2B x B
+  double* skpart = Qc + 2 * B * B + 64;          // split-K partials
 
-  const int npanel = (n > B) ? ceil_div(n - 1, B) : 0;
-  for (int p = 0; p < npanel; p++) {
+  // Householder QR of panel p (rows r0.., columns c0..c0+B-1)
+  auto qr_panel = [&](int p) -> hipError_t {
     const int c0 = p * B, r0 = c0 + B, h = n - r0;
-    if (h <= 0) break;
     double* Pp = A + r0 + (long)c0 * lda;
     double* Vp = Vst + r0 + (long)c0 * ldv;
     double* Tp = T1 + (size_t)p * B * B;
+    double* tau_p = tau1 + c0;
     const int G = ceil_div(h, CH);
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, bar, 1);
     HSDM_TRY(hipGetLastError());
     void* args[] = {(void*)&h, (void*)&Pp, (void*)&lda, (void*)&Vp, (void*)&ldv,
-                    (void*)&tau1, (void*)&Tp, (void*)&part, (void*)&prow, (void*)&gpart,
+                    (void*)&tau_p, (void*)&Tp, (void*)&part, (void*)&prow, (void*)&gpart,
                     (void*)&bar, (void*)&st};
-    double* tau_p = tau1 + c0;
-    args[5] = (void*)&tau_p;
     // algorithmic: Householder QR of the h x B panel (2 h B^2 flops), the
     // panel read and written once
     kt_begin("panel_qr_kernel<32>", 2.0 * h * B * B, 16.0 * h * B, 0, s);
     HSDM_TRY(hipLaunchCooperativeKernel((const void*)panel_qr_kernel<BB>, dim3(G), dim3(NT), args,
                                         0, s));
     kt_end(s);
-    if (h <= 1) continue;
-    double* A22 = A + r0 + (long)r0 * lda;
-    // Y = V T
+    return hipSuccess;
+  };
+  // W (h x B, ld n, holding X on entry) = X - V M / 2 with Y = V T, X = A[r:, r:] Y,
+  // M = Y^T X.  Vp: the panel's V (ld ldv), Tp its T; Y receives V T.
+  auto make_w = [&](int r, int h, const double* Vp, const double* Tp, double* Wp,
+                    bool correct, const double* VWc, const double* WVc) -> hipError_t {
     GemmArgs g{};
     g.m = h; g.n = B; g.k = B; g.A = Vp; g.lda = ldv; g.B = Tp; g.ldb = B; g.C = Y; g.ldc = n;
     g.alpha = 1.0; g.beta = 0.0; g.flags = GF_KB_UPPER;
     HSDM_TRY(gemm_launch(g, s));
-    // X = A22 Y  -> VW[:, B:2B], A22 symmetric with its lower triangle stored:
-    // X = tril(A22) Y + strict_tril(A22)^T Y, both passes reading the lower
-    // triangle with coalesced loads
-    double* Xp = VW + (size_t)n * B;
+    // X = A[r:, r:] Y: A symmetric with its lower triangle stored,
+    // X = tril(A) Y + strict_tril(A)^T Y, both passes reading the lower triangle
+    const double* Ar = A + r + (long)r * lda;
     g = GemmArgs{};
-    g.m = h; g.n = B; g.k = h; g.A = A22; g.lda = lda; g.B = Y; g.ldb = n; g.C = Xp; g.ldc = n;
+    g.m = h; g.n = B; g.k = h; g.A = Ar; g.lda = lda; g.B = Y; g.ldb = n; g.C = Wp; g.ldc = n;
     g.alpha = 1.0; g.beta = 0.0; g.flags = GF_A_TRIL | GF_KA_LOWER;
     HSDM_TRY(gemm_splitk_launch(g, SPLITK, skpart, s));
     g.ta = 1; g.beta = 1.0; g.flags = GF_A_SLT | GF_KA_UPPER;
     HSDM_TRY(gemm_splitk_launch(g, SPLITK, skpart, s));
+    if (correct) {
+      // X -= [V1b W1b] ([W1b V1b]^T Y): the delayed update of the first panel
+      g = GemmArgs{};
+      g.m = 2 * B; g.n = B; g.k = h; g.A = WVc; g.lda = n; g.B = Y; g.ldb = n; g.C = Qc;
+      g.ldc = 2 * B; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
+      HSDM_TRY(gemm_splitk_launch(g, SPLITK, skpart, s));
+      g = GemmArgs{};
+      g.m = h; g.n = B; g.k = 2 * B; g.A = VWc; g.lda = n; g.B = Qc; g.ldb = 2 * B; g.C = Wp;
+      g.ldc = n; g.alpha = -1.0; g.beta = 1.0;
+      HSDM_TRY(gemm_launch(g, s));
+    }
     // M = Y^T X
-    hipLaunchKernelGGL((atb_partial_kernel<BB>), dim3(G), dim3(NT), 0, s, h, Y, (long)n, Xp,
+    const int G = ceil_div(h, CH);
+    hipLaunchKernelGGL((atb_partial_kernel<BB>), dim3(G), dim3(NT), 0, s, h, Y, (long)n, Wp,
                        (long)n, apart);
     HSDM_TRY(hipGetLastError());
     hipLaunchKernelGGL((atb_reduce_kernel<BB>), dim3(ceil_div(B * B, 256)), dim3(256), 0, s, G,
                        apart, M, (long)B);
     HSDM_TRY(hipGetLastError());
-    // W = X - V M / 2 (in place in VW[:, B:2B])
+    // W = X - V M / 2
     g = GemmArgs{};
-    g.m = h; g.n = B; g.k = B; g.A = Vp; g.lda = ldv; g.B = M; g.ldb = B; g.C = Xp; g.ldc = n;
+    g.m = h; g.n = B; g.k = B; g.A = Vp; g.lda = ldv; g.B = M; g.ldb = B; g.C = Wp; g.ldc = n;
     g.alpha = -0.5; g.beta = 1.0;
-    HSDM_TRY(gemm_launch(g, s));
-    // VW[:, 0:B] = V ; WV = [W V]
-    HSDM_TRY(dev_copy(Vp, ldv, VW, n, h, B, s));
-    HSDM_TRY(dev_copy(Xp, n, WV, n, h, B, s));
-    HSDM_TRY(dev_copy(Vp, ldv, WV + (size_t)n * B, n, h, B, s));
-    // A22 -= [V W][W V]^T  (lower)
-    g = GemmArgs{};
-    g.m = h; g.n = h; g.k = 2 * B; g.A = VW; g.lda = n; g.B = WV; g.ldb = n; g.C = A22;
-    g.ldc = lda; g.alpha = -1.0; g.beta = 1.0; g.ta = 0; g.tb = 1;
+    return gemm_launch(g, s);
+  };
+  // A[r:, r:] -= VWr WVr^T (lower), k columns
+  auto syr2k = [&](int r, int h, const double* VWr, const double* WVr, int k) -> hipError_t {
+    GemmArgs g{};
+    g.m = h; g.n = h; g.k = k; g.A = VWr; g.lda = n; g.B = WVr; g.ldb = n;
+    g.C = A + r + (long)r * lda; g.ldc = lda; g.alpha = -1.0; g.beta = 1.0; g.ta = 0; g.tb = 1;
     g.flags = GF_C_LOWER_TILES | GF_C_LOWER_ONLY;
-    HSDM_TRY(gemm_launch(g, s));
+    return gemm_launch(g, s);
+  };
+
+  const int npanel = (n > B) ? ceil_div(n - 1, B) : 0;
+  for (int p = 0; p < npanel;) {
+    const int c0 = p * B, r0 = c0 + B, h = n - r0;
+    if (h <= 0) break;
+    HSDM_TRY(qr_panel(p));
+    if (h <= 1) {
+      p++;
+      continue;
+    }
+    const double* V1 = Vst + r0 + (long)c0 * ldv;
+    const double* T1p = T1 + (size_t)p * B * B;
+    double* W1 = VW + (size_t)n * B;
+    HSDM_TRY(make_w(r0, h, V1, T1p, W1, false, nullptr, nullptr));
+    // VW[:, 0:2B] = [V1 W1], WV[:, 0:2B] = [W1 V1]
+    HSDM_TRY(dev_copy(V1, ldv, VW, n, h, B, s));
+    HSDM_TRY(dev_copy(W1, n, WV, n, h, B, s));
+    HSDM_TRY(dev_copy(V1, ldv, WV + (size_t)n * B, n, h, B, s));
+    const int h2 = h - B;
+    const bool pair = (p + 1 < npanel) && h2 > 1;
+    if (!pair) {
+      HSDM_TRY(syr2k(r0, h, VW, WV, 2 * B));
+      p++;
+      continue;
+    }
+    // columns of panel p+1: A[r0:, r0:r0+B] -= [V1 W1] [W1 V1][0:B]^T (lower part)
+    {
+      GemmArgs g{};
+      g.m = h; g.n = B; g.k = 2 * B; g.A = VW; g.lda = n; g.B = WV; g.ldb = n;
+      g.C = A + r0 + (long)r0 * lda; g.ldc = lda; g.alpha = -1.0; g.beta = 1.0; g.ta = 0;
+      g.tb = 1; g.flags = GF_C_LOWER_ONLY;
+      HSDM_TRY(gemm_launch(g, s));
+    }
+    HSDM_TRY(qr_panel(p + 1));
+    const int r1 = r0 + B;
+    const double* V2 = Vst + r1 + (long)r0 * ldv;
+    const double* T2p = T1 + (size_t)(p + 1) * B * B;
+    double* W2 = VW + B + (size_t)3 * n * B;
+    HSDM_TRY(make_w(r1, h2, V2, T2p, W2, true, VW + B, WV + B));
+    // VW[B:, 2B:4B] = [V2 W2], WV[B:, 2B:4B] = [W2 V2]
+    HSDM_TRY(dev_copy(V2, ldv, VW + B + (size_t)2 * n * B, n, h2, B, s));
+    HSDM_TRY(dev_copy(W2, n, WV + B + (size_t)2 * n * B, n, h2, B, s));
+    HSDM_TRY(dev_copy(V2, ldv, WV + B + (size_t)3 * n * B, n, h2, B, s));
+    HSDM_TRY(syr2k(r1, h2, VW + B, WV + B, 4 * B));
+    p += 2;
   }
   const long tot = (long)n * ldab;
   hipLaunchKernelGGL(band_extract_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n,
