@@ -272,24 +272,36 @@ HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int flags, int
     }
 }
 
-// Map a workgroup id to a tile: XCD-contiguous runs, then groups of 8 rows.
-// The grid may be larger than the tile count (sizes read on the device), so
-// the runs are sized by the actual count: XCD x gets tiles [x*per, (x+1)*per).
-HSDM_DEV bool map_tile(int bid, int nblk, int tiles_m, int tiles_n, int& tm, int& tn) {
-  const int ntiles = tiles_m * tiles_n;
-  const int per = (ntiles + 7) / 8;
-  if (bid >= 8 * per) return false;
-  const int t = (bid % 8) * per + bid / 8;
-  if (t >= ntiles) return false;
+// Map a workgroup id to a tile.  Workgroups are dealt to the 8 XCDs in turn
+// (id % 8), so XCD x takes the tile rows x, x + 8, x + 16, ... (tile columns
+// when there are more of them): triangular products, whose work grows or
+// shrinks with the row, stay balanced across the XCDs.  Within an XCD the
+// tiles run in groups of 8 of its rows, column by column, so that both
+// operand panels are reused from its L2.  The grid may be larger than needed
+// (sizes read on the device); surplus ids return false.
+HSDM_DEV bool map_tile(int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const bool by_row = tiles_m >= tiles_n;
+  const int major = by_row ? tiles_m : tiles_n, minor = by_row ? tiles_n : tiles_m;
+  const int x = bid % 8, li = bid / 8;
+  const int lines = (major - x + 7) / 8;  // tile rows (columns) of XCD x
+  if (lines <= 0 || li >= lines * minor) return false;
   constexpr int GROUP = 8;
-  const int in_group = GROUP * tiles_n;
-  const int g = t / in_group;
+  const int in_group = GROUP * minor;
+  const int g = li / in_group;
   const int first = g * GROUP;
-  const int gs = min(tiles_m - first, GROUP);
-  const int r = t % in_group;
-  tm = first + r % gs;
-  tn = r / gs;
+  const int gs = min(lines - first, GROUP);
+  const int r = li % in_group;
+  const int a = x + 8 * (first + r % gs), c = r / gs;
+  tm = by_row ? a : c;
+  tn = by_row ? c : a;
   return true;
+}
+
+// workgroups needed for a tiles_m x tiles_n grid of tiles
+inline int tile_grid(long tiles_m, long tiles_n) {
+  const long major = tiles_m >= tiles_n ? tiles_m : tiles_n;
+  const long minor = tiles_m >= tiles_n ? tiles_n : tiles_m;
+  return (int)(8 * ((major + 7) / 8) * minor);
 }
 
 template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
@@ -302,7 +314,7 @@ __global__ __launch_bounds__(64 * WM * WN, 512 / (64 * WM * WN)) void gemm_kerne
   if (p.n <= 0) return;
   const int tiles_m = (p.m + BM - 1) / BM, tiles_n = (p.n + BN - 1) / BN;
   int tm, tn;
-  if (!map_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn)) return;
+  if (!map_tile(blockIdx.x, tiles_m, tiles_n, tm, tn)) return;
   if ((flags & GF_C_LOWER_TILES) && (tm + 1) * BM - 1 < tn * BN) return;
   if (kchunk > 0) {
     // split-K: slice blockIdx.y writes its partial product to C + y*split_stride
@@ -325,7 +337,7 @@ __global__ __launch_bounds__(64 * WM * WN, 512 / (64 * WM * WN)) void gemm_batch
   Prob p{d.m, d.n, d.k, d.A, d.lda, d.B, d.ldb, d.C, d.ldc, d.acol, d.ccol, nullptr};
   const int tiles_m = (p.m + BM - 1) / BM, tiles_n = (p.n + BN - 1) / BN;
   int tm, tn;
-  if (!map_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn)) return;
+  if (!map_tile(blockIdx.x, tiles_m, tiles_n, tm, tn)) return;
   if ((flags & GF_C_LOWER_TILES) && (tm + 1) * BM - 1 < tn * BN) return;
   if (d.k <= 0) {
     // empty contraction: C = beta * C on the tile
@@ -380,8 +392,7 @@ const char* kernel_name() {
 template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
 hipError_t launch_cfg(const Prob& p, double alpha, double beta, int flags, int nsplit, int kchunk,
                       long stride, double flops, hipStream_t s) {
-  long tiles = (long)ceil_div(p.m, BM) * ceil_div(p.n, BN);
-  int nblk = (int)(((tiles + 7) / 8) * 8);
+  const int nblk = tile_grid(ceil_div(p.m, BM), ceil_div(p.n, BN));
   kt_begin(kernel_name<BM, BN, WM, WN, TA, TB, AM>(), flops, 0.0, p.ndev ? p.n : 0, s);
   hipLaunchKernelGGL((gemm_kernel<BM, BN, WM, WN, TA, TB, AM>), dim3(nblk, nsplit),
                      dim3(64 * WM * WN), 0, s, p, alpha, beta, flags, kchunk, stride);
@@ -514,8 +525,7 @@ hipError_t gemm_batched_launch(const GemmDesc* d_desc, int count, int max_m, int
                                hipStream_t s) {
   if (count <= 0 || max_m <= 0 || max_n <= 0) return hipSuccess;
   if (ta != 0 || tb != 0) return hipErrorInvalidValue;
-  long tiles = (long)ceil_div(max_m, 64) * ceil_div(max_n, 64);
-  int nblk = (int)(((tiles + 7) / 8) * 8);
+  const int nblk = tile_grid(ceil_div(max_m, 64), ceil_div(max_n, 64));
   kt_begin("gemm_batched_kernel<64, 64, 2, 2, 0, 0, 2>", 0.0, 0.0, 0, s);
   hipLaunchKernelGGL((gemm_batched_kernel<64, 64, 2, 2, 0, 0, AM_GATHER>), dim3(nblk, count),
                      dim3(256), 0, s, d_desc, alpha, beta, flags);

@@ -25,7 +25,7 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int CH = 256;      // panel rows per workgroup
-constexpr int SPLITK = 1024; // K slice of the symmetric product X = A22 Y
+constexpr int SPLITK = 512;  // K slice of the symmetric product X = A22 Y
 
 HSDM_DEV void grid_sync(unsigned* bar, unsigned nblk, unsigned& epoch, DevStatusWord* st) {
   __syncthreads();
