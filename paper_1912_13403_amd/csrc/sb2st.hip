@@ -14,10 +14,12 @@
 // pipeline, each two tasks behind its predecessor.
 //
 // One wavefront runs one sweep at a time (64 lanes; the B x B blocks live in
-// LDS); workgroups of 4 wavefronts are launched cooperatively so that every
-// wavefront is resident.  Progress counters in global memory carry the
-// dependencies with agent-scope release/acquire; every wait is bounded and
-// reports through the status word if it runs out.
+// LDS); workgroups of 8 wavefronts are launched cooperatively so that every
+// wavefront is resident.  Consecutive sweeps run on consecutive wavefronts:
+// inside a workgroup the hand-off is a progress counter in LDS, between
+// workgroups a counter in global memory with agent-scope release/acquire;
+// every wait is bounded and reports through the status word if it runs out.
+// Sums over the rows of a block use DPP and LDS swizzle moves.
 //
 // Storage: lower band storage AB[(r-c) + c*ldab], ldab = 2B (offsets up to
 // 2B-1 hold the bulge).  Each reflector H_{s,t} (v, tau; v[0] = 1) is stored
@@ -29,7 +31,9 @@
 namespace {
 
 constexpr int WPB = 8;  // wavefronts per workgroup
-constexpr int DONE = 1 << 30;
+constexpr int DONE = 1 << 30;      // global counter of a finished sweep
+constexpr int KROUND = 1 << 20;    // LDS counters: KROUND * round + tasks done
+constexpr int KDONE = 1 << 19;     //   ... + KDONE once the sweep is finished
 
 // Orders LDS accesses between the lanes of one wavefront: the LDS executes a
 // wavefront's instructions in order, so a compiler barrier is enough (no wait
@@ -39,9 +43,39 @@ HSDM_DEV void wave_sync() {
   asm volatile("" ::: "memory");
 }
 
+template <int CTRL>
+HSDM_DEV double dpp(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+template <int PAT>
+HSDM_DEV double swz(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(unsigned)u, PAT);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(unsigned)(u >> 32), PAT);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+HSDM_DEV double first_lane(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((int)(unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum of a value that is zero outside lanes 0..31, returned in every lane:
+// lane xor 1 and xor 2 (quad permutations), rotations by 4 and 8 inside rows
+// of 16, lane xor 16 (swizzle, bit-mask mode), then lane 0's total.
 HSDM_DEV double wsum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp<0xB1>(v);
+  v += dpp<0x4E>(v);
+  v += dpp<0x124>(v);
+  v += dpp<0x128>(v);
+  v += swz<0x401F>(v);
+  return first_lane(v);
 }
 
 HSDM_DEV double hsum(double v) { return v + __shfl_xor(v, 32, 64); }
@@ -75,6 +109,26 @@ HSDM_DEV void wait_ge(int* p, int target, bool agent, DevStatusWord* st) {
   wave_sync();
 }
 
+// Hand-offs between the wavefronts of one workgroup: a counter in LDS.
+HSDM_DEV void wait_lds(int* p, int target, DevStatusWord* st) {
+  long spins = 0;
+  while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+    if (++spins > (1L << 27)) {
+      if ((threadIdx.x & 63) == 0) dev_set_status(st, DS_SYNC_TIMEOUT, 2);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  wave_sync();
+}
+
+HSDM_DEV void publish_lds(int* p, int v) {
+  wave_sync();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if ((threadIdx.x & 63) == 0) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 HSDM_DEV void publish(int* p, int v, bool agent) {
   wave_sync();
   if ((threadIdx.x & 63) == 0) {
@@ -94,7 +148,10 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
   __shared__ double Dl_all[WPB][B][B + 1];
   __shared__ double Bl_all[WPB][B][B + 1];
   __shared__ double vc_all[WPB][B], vn_all[WPB][B], wv_all[WPB][B];
+  __shared__ int lprog[WPB];
   const int lane = threadIdx.x & 63, wv_id = threadIdx.x >> 6;
+  if (lane == 0) lprog[wv_id] = -1;
+  __syncthreads();
   double(*Dl)[B + 1] = Dl_all[wv_id];
   double(*Bl)[B + 1] = Bl_all[wv_id];
   double* vc = vc_all[wv_id];
@@ -104,15 +161,22 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
   const int li = lane % B, hf = lane / B;  // row index and column half (B/2 columns each)
   constexpr int HB = B / 2;
 
-  for (int s = gw; s < nsweep; s += TW) {
+  for (int s = gw, round = 0; s < nsweep; s += TW, round++) {
     const int ntask = (n - 1 - s + B - 1) / B;
-    // sweep s-1 runs on wavefront gw-1 (same workgroup unless gw is its first)
-    const bool wait_agent = (wv_id == 0);
-    const bool pub_agent = (wv_id == WPB - 1);
+    // sweep s-1 runs on wavefront gw-1: in the same workgroup (LDS counter)
+    // unless this is the workgroup's first wavefront (global counter)
+    const bool first_wave = (wv_id == 0);
+    const bool last_wave = (wv_id == WPB - 1);
+    const int kbase = round * KROUND;
     double tau = 0.0;
     const long g0 = goff[s / B];
     for (int t = 0; t < ntask; t++) {
-      if (s > 0) wait_ge(progress + s - 1, t + 2, wait_agent, st);
+      if (s > 0) {
+        if (first_wave)
+          wait_ge(progress + s - 1, t + 2, true, st);
+        else
+          wait_lds(&lprog[wv_id - 1], kbase + t + 2, st);
+      }
       const int rs = s + 1 + t * B;
       const int len = min(B, n - rs);
       const int rs2 = rs + B;
@@ -146,7 +210,7 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
       if (t == 0) {
         // reflector from column s, rows s+1 .. s+len
         const double x = (lane < len) ? AB[(1 + lane) + (long)s * ldab] : 0.0;
-        const double alpha = __shfl(x, 0, 64);
+        const double alpha = first_lane(x);
         const double sig = wsum((lane >= 1 && lane < len) ? x * x : 0.0);
         double beta = alpha, scal = 0.0;
         tau = 0.0;
@@ -205,7 +269,7 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
         wave_sync();
         // next reflector from the first column of the block
         const double x = (lane < len2) ? Bl[lane][0] : 0.0;
-        const double alpha = __shfl(x, 0, 64);
+        const double alpha = first_lane(x);
         const double sig = wsum((lane >= 1 && lane < len2) ? x * x : 0.0);
         double beta = alpha, scal = 0.0;
         if (sig > 0.0) {
@@ -245,9 +309,11 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
         if (li < len2 && j < len) AB[(B + li - j) + (long)(rs + j) * ldab] = Bl[li][j];
       }
       tau = tau_n;
-      publish(progress + s, t + 1, pub_agent);
+      publish_lds(&lprog[wv_id], kbase + t + 1);
+      if (last_wave) publish(progress + s, t + 1, true);
     }
-    publish(progress + s, DONE, pub_agent);
+    publish_lds(&lprog[wv_id], kbase + KDONE);
+    if (last_wave) publish(progress + s, DONE, true);
   }
 }
 
