@@ -50,72 +50,114 @@ HSDM_DEV void grid_sync(unsigned* bar, unsigned nblk, unsigned& epoch, DevStatus
   __syncthreads();
 }
 
+// Sum of v[0..B-1] over the 64 lanes of a wavefront (B = 32), by recursive
+// halving: after the step with partner lane ^ 2^k (k = 5 .. 1) a lane keeps
+// the half of its values selected by that lane bit, so lane l ends up with
+// the sum for index l >> 1 over the 32 lanes sharing bit 0; a last exchange
+// with lane ^ 1 completes the sum over all 64 lanes.
+template <int NV>
+HSDM_DEV double wave_reduce_scatter(double (&v)[NV]) {
+  static_assert(NV == 32, "32 values over 64 lanes");
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int step = 0; step < 5; step++) {
+    const int half = 16 >> step;           // values kept after this step
+    const int bit = 32 >> step;            // partner lane ^ bit
+    const bool hi = (lane & bit) != 0;     // keep the upper half of the current range
+#pragma unroll
+    for (int k = 0; k < half; k++) {
+      const double send = hi ? v[k] : v[half + k];
+      const double keep = hi ? v[half + k] : v[k];
+      v[k] = keep + __shfl_xor(send, bit, 64);
+    }
+  }
+  return v[0] + __shfl_xor(v[0], 1, 64);
+}
+
 // Householder QR of the h x B panel P (ldp); V receives the explicit unit
 // lower trapezoidal reflectors, tau the scalars, Tt the B x B triangular
 // factor (column-major, ld B).  part, prow, gpart are scratch.
+// Workgroup g holds rows [256 g, 256 g + 256) of the panel, one row per
+// thread in registers; the column sums of each step are reduced inside the
+// wavefronts by shuffles, across the 4 wavefronts through LDS and across
+// the workgroups through global partial sums and one grid barrier.
 template <int B>
 __global__ __launch_bounds__(NT) void panel_qr_kernel(int h, double* P, long ldp, double* V,
                                                       long ldv, double* tau_out, double* Tt,
                                                       double* part, double* prow, double* gpart,
                                                       unsigned* bar, DevStatusWord* st) {
-  static_assert(NT % B == 0, "threads must tile the panel width");
-  constexpr int RG = NT / B;        // row groups
-  constexpr int RPG = CH / RG;      // rows per group
+  static_assert(NT == CH && B == 32, "one row per thread, 32 columns");
+  constexpr int NW = NT / 64;
+  constexpr int RG = NT / B;  // threads per column when combining partial sums
+  __shared__ double red[NW][B];
+  __shared__ double ddl[B], wl[B], taul[B], rowl[B];
   __shared__ double Pl[CH][B + 1];
-  __shared__ double red[RG][B + 1];
-  __shared__ double ddl[B], wl[B], taul[B];
   __shared__ double Gm[B][B + 1], Tl[B][B + 1];
+  __shared__ double cmb[RG][B + 1];
 
   const int g = blockIdx.x, G = gridDim.x;
-  const int t = threadIdx.x, c = t % B, rg = t / B;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int row0 = g * CH;
   const int nrows = min(CH, h - row0);
+  const int gi = row0 + t;
+  const bool rok = t < nrows;
   unsigned epoch = 0;
 
-  for (int i = t / B; i < CH; i += RG) Pl[i][c] = (i < nrows) ? P[row0 + i + (long)c * ldp] : 0.0;
-  __syncthreads();
+  double a[B];
+#pragma unroll
+  for (int c = 0; c < B; c++) a[c] = rok ? P[gi + (long)c * ldp] : 0.0;
 
   const int ncol = min(B, h);
   for (int j = 0; j < B; j++) {
     if (j >= ncol) {
-      if (g == 0 && t == 0) taul[j] = 0.0;
+      if (t == 0) taul[j] = 0.0;
       continue;
     }
-    // partial sums over rows strictly below the pivot
-    double s = 0.0;
-    if (c >= j) {
-      for (int q = 0; q < RPG; q++) {
-        const int i = rg * RPG + q;
-        if (i < nrows && row0 + i > j) s += Pl[i][j] * Pl[i][c];
-      }
+    // partial sums over this workgroup's rows strictly below the pivot:
+    // sum_i a_ij a_ic for every column c (only c >= j are used)
+    const bool below = rok && gi > j;
+    double aj = 0.0;
+#pragma unroll
+    for (int c = 0; c < B; c++) aj = (c == j) ? a[c] : aj;
+    double v[B];
+#pragma unroll
+    for (int c = 0; c < B; c++) v[c] = below ? aj * a[c] : 0.0;
+    const double ws = wave_reduce_scatter(v);
+    if ((lane & 1) == 0) red[wv][lane >> 1] = ws;
+    // the pivot row (global row j, in workgroup 0) is published by its thread
+    if (g == 0 && t == j) {
+#pragma unroll
+      for (int c = 0; c < B; c++) rowl[c] = a[c];
     }
-    red[rg][c] = s;
     __syncthreads();
     double* pb = part + (size_t)(j & 1) * G * B;
     double* rb = prow + (size_t)(j & 1) * B;
     if (t < B) {
-      double a = 0.0;
-      for (int r = 0; r < RG; r++) a += red[r][t];
-      pb[(size_t)g * B + t] = a;
-      if (g == 0) rb[t] = Pl[j][t];  // pivot row (global row j lives in group 0)
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; w++) sum += red[w][t];
+      pb[(size_t)g * B + t] = sum;
+      if (g == 0) rb[t] = rowl[t];
     }
     grid_sync(bar, G, epoch, st);
     {
       // RG threads per column sum strided subsets, then a fixed-order combine
-      double a = 0.0;
+      const int c = t % B, rg = t / B;
+      double s2 = 0.0;
       if (c >= j)
-        for (int q = rg; q < G; q += RG) a += pb[(size_t)q * B + c];
-      red[rg][c] = a;
+        for (int q = rg; q < G; q += RG) s2 += pb[(size_t)q * B + c];
+      cmb[rg][c] = s2;
     }
     __syncthreads();
     if (t < B) {
-      double a = 0.0;
-      for (int r = 0; r < RG; r++) a += red[r][t];
-      ddl[t] = a;
+      double s2 = 0.0;
+      for (int r = 0; r < RG; r++) s2 += cmb[r][t];
+      ddl[t] = s2;
+      rowl[t] = rb[t];
     }
     __syncthreads();
     const double sigma = ddl[j];
-    const double alpha = rb[j];
+    const double alpha = rowl[j];
     double tau = 0.0, beta = alpha, scal = 0.0;
     if (sigma > 0.0) {
       const double nrm = sqrt(alpha * alpha + sigma);
@@ -123,67 +165,67 @@ __global__ __launch_bounds__(NT) void panel_qr_kernel(int h, double* P, long ldp
       tau = (beta - alpha) / beta;
       scal = 1.0 / (alpha - beta);
     }
-    if (t < B) wl[t] = (t > j) ? tau * (rb[t] + ddl[t] * scal) : 0.0;
+    if (t < B) wl[t] = (t > j) ? tau * (rowl[t] + ddl[t] * scal) : 0.0;
     if (t == 0) taul[j] = tau;
     __syncthreads();
-    // rank-1 update of the columns right of j (rows below the pivot)
-    if (c > j) {
-      const double wc = wl[c];
-      for (int q = 0; q < RPG; q++) {
-        const int i = rg * RPG + q;
-        if (i < nrows && row0 + i > j) Pl[i][c] -= (Pl[i][j] * scal) * wc;
+    // update of this thread's row: below the pivot a_ic -= (a_ij scal) w_c and
+    // a_ij becomes v_i; the pivot row gets a_jc -= w_c and beta
+    if (below) {
+      const double vi = aj * scal;
+#pragma unroll
+      for (int c = 0; c < B; c++)
+        if (c > j) a[c] -= vi * wl[c];
+#pragma unroll
+      for (int c = 0; c < B; c++)
+        if (c == j) a[c] = vi;
+    } else if (rok && gi == j) {
+#pragma unroll
+      for (int c = 0; c < B; c++) {
+        if (c > j) a[c] -= wl[c];
+        if (c == j) a[c] = beta;
       }
     }
-    __syncthreads();
-    if (c == j) {
-      for (int q = 0; q < RPG; q++) {
-        const int i = rg * RPG + q;
-        if (i < nrows && row0 + i > j) Pl[i][j] *= scal;
-      }
-    }
-    if (g == 0 && rg == 0) {
-      if (c > j) Pl[j][c] -= wl[c];
-      if (c == j) Pl[j][j] = beta;
-    }
-    __syncthreads();
   }
 
-  // write back R / V in place, the explicit V, and partial Gram V^T V
-  for (int i = t / B; i < nrows; i += RG) {
-    const int gi = row0 + i;
-    P[gi + (long)c * ldp] = Pl[i][c];
-    V[gi + (long)c * ldv] = (gi > c) ? Pl[i][c] : (gi == c ? 1.0 : 0.0);
+  // write back R / V in place and the explicit V; the rows go to LDS for the
+  // partial Gram V^T V
+  if (rok) {
+#pragma unroll
+    for (int c = 0; c < B; c++) {
+      P[gi + (long)c * ldp] = a[c];
+      const double vv = (gi > c) ? a[c] : (gi == c ? 1.0 : 0.0);
+      V[gi + (long)c * ldv] = vv;
+      Pl[t][c] = vv;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < B; c++) Pl[t][c] = 0.0;
   }
   if (g == 0 && t < B) tau_out[t] = taul[t];
+  __syncthreads();
   for (int e = t; e < B * B; e += NT) {
-    const int a = e % B, b = e / B;
-    double s = 0.0;
-    if (a <= b) {
-      for (int i = 0; i < nrows; i++) {
-        const int gi = row0 + i;
-        const double va = (gi > a) ? Pl[i][a] : (gi == a ? 1.0 : 0.0);
-        const double vb = (gi > b) ? Pl[i][b] : (gi == b ? 1.0 : 0.0);
-        s += va * vb;
-      }
-    }
-    gpart[(size_t)g * B * B + e] = s;
+    const int ca = e % B, cb = e / B;
+    double sum = 0.0;
+    if (ca <= cb)
+      for (int i = 0; i < nrows; i++) sum += Pl[i][ca] * Pl[i][cb];
+    gpart[(size_t)g * B * B + e] = sum;
   }
   grid_sync(bar, G, epoch, st);
   if (g != 0) return;
   for (int e = t; e < B * B; e += NT) {
-    const int a = e % B, b = e / B;
-    double s = 0.0;
-    for (int q = 0; q < G; q++) s += gpart[(size_t)q * B * B + e];
-    Gm[a][b] = s;
-    Tl[a][b] = 0.0;
+    const int ca = e % B, cb = e / B;
+    double sum = 0.0;
+    for (int q = 0; q < G; q++) sum += gpart[(size_t)q * B * B + e];
+    Gm[ca][cb] = sum;
+    Tl[ca][cb] = 0.0;
   }
   __syncthreads();
   // T: T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) (V^T v_j)(0:j)
   for (int j = 0; j < B; j++) {
     if (t < j) {
-      double s = 0.0;
-      for (int k = t; k < j; k++) s += Tl[t][k] * Gm[k][j];
-      Tl[t][j] = -taul[j] * s;
+      double sum = 0.0;
+      for (int k = t; k < j; k++) sum += Tl[t][k] * Gm[k][j];
+      Tl[t][j] = -taul[j] * sum;
     }
     if (t == j) Tl[j][j] = taul[j];
     __syncthreads();
