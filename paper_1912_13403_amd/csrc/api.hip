@@ -80,7 +80,6 @@ struct hsdm_ctx {
   double *Lbuf, *Linv, *Abuf, *Vst, *Zbuf, *Cbuf, *T1, *tau1, *AB, *sy_scr, *dvec, *evec, *lam,
       *fvec, *V2, *tau2, *F2, *dc_scr, *bt1_scr, *colsum, *hnorm;
   int *dc_iscr, *progress;
-  unsigned* bar;
   // cached factor of S
   const double* s_ptr = nullptr;
   int s_n = 0, s_ld = 0;
@@ -157,7 +156,6 @@ int ensure_ws(hsdm_ctx* h, int n) {
   h->colsum = w + ocs; h->hnorm = w + ohn;
   h->dc_iscr = h->iws;
   h->progress = h->iws + stedc_iscratch_ints(n);
-  h->bar = (unsigned*)(h->progress + n + 64);
   h->lay = L;
   std::vector<long> goff(L.nblk + 1);
   sb2st_group_offsets(L, goff.data());
@@ -259,7 +257,7 @@ int standard_form(hsdm_ctx* h, int n, const double* H, int ldh, const double* Li
 int reduce(hsdm_ctx* h, int n, hipStream_t s, int phase_band) {
   DEV_TRY(h, bt1_zero_fill(n, BAND, h->Vst, n, s));
   DEV_TRY(h, sy2sb_run(n, BAND, h->Abuf, n, h->Vst, n, h->tau1, h->T1, h->AB, 2 * BAND, h->sy_scr,
-                       h->bar, h->st, s));
+                       h->st, s));
   mark(h, phase_band, s);
   DEV_TRY(h, sb2st_run(h->lay, h->AB, 2 * BAND, h->dvec, h->evec, h->V2, h->tau2, h->d_goff,
                        h->progress, h->st, s));

@@ -8,8 +8,8 @@
 // the band in band storage (ldab >= 2B rows per column, rows > B zeroed).
 size_t sy2sb_scratch_doubles(int n, int B);
 hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, double* tau1,
-                     double* T1, double* AB, int ldab, double* scratch, unsigned* bar,
-                     DevStatusWord* st, hipStream_t s);
+                     double* T1, double* AB, int ldab, double* scratch, DevStatusWord* st,
+                     hipStream_t s);
 
 // sb2st.hip -- band -> tridiagonal by bulge chasing.  AB is overwritten;
 // d (n) and e (n-1) receive the tridiagonal; the stage-2 reflectors are

@@ -27,29 +27,6 @@ constexpr int NT = 256;
 constexpr int CH = 256;      // panel rows per workgroup
 constexpr int SPLITK = 512;  // K slice of the symmetric product X = A22 Y
 
-HSDM_DEV void grid_sync(unsigned* bar, unsigned nblk, unsigned& epoch, DevStatusWord* st) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    epoch += 1;
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned target = epoch * nblk;
-    long spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      ++spins;
-      if (spins > (1L << 26) ||
-          ((spins & 4095) == 0 &&
-           __hip_atomic_load(&st->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
-        dev_set_status(st, DS_SYNC_TIMEOUT, 1);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-  }
-  // poll relaxed; one agent-scope acquire once the barrier is complete
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  __syncthreads();
-}
-
 // Sum of v[0..B-1] over the 64 lanes of a wavefront (B = 32), by recursive
 // halving: after the step with partner lane ^ 2^k (k = 5 .. 1) a lane keeps
 // the half of its values selected by that lane bit, so lane l ends up with
@@ -74,6 +51,36 @@ HSDM_DEV double wave_reduce_scatter(double (&v)[NV]) {
   return v[0] + __shfl_xor(v[0], 1, 64);
 }
 
+// Exchange between the workgroups of a panel without a barrier: every slot
+// of the exchange buffers holds a NaN before the launch; a workgroup writes
+// its values with agent-scope atomic stores (coherent at agent scope without
+// cache maintenance), and a reader polls each slot with agent-scope atomic
+// loads until it is no longer NaN (sums of finite values never are).
+HSDM_DEV void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+HSDM_DEV double ld_ready(const double* p, DevStatusWord* st) {
+  double v = __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  long spins = 0;
+  while (v != v) {
+    if (++spins > (1L << 24) ||
+        ((spins & 1023) == 0 &&
+         __hip_atomic_load(&st->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+      dev_set_status(st, DS_SYNC_TIMEOUT, 1);
+      return 0.0;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    v = __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return v;
+}
+
+__global__ void fill_nan_kernel(double* p, long cnt) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) p[i] = __builtin_nan("");
+}
+
 // Householder QR of the h x B panel P (ldp); V receives the explicit unit
 // lower trapezoidal reflectors, tau the scalars, Tt the B x B triangular
 // factor (column-major, ld B).  part, prow, gpart are scratch.
@@ -85,7 +92,7 @@ template <int B>
 __global__ __launch_bounds__(NT) void panel_qr_kernel(int h, double* P, long ldp, double* V,
                                                       long ldv, double* tau_out, double* Tt,
                                                       double* part, double* prow, double* gpart,
-                                                      unsigned* bar, DevStatusWord* st) {
+                                                      DevStatusWord* st) {
   static_assert(NT == CH && B == 32, "one row per thread, 32 columns");
   constexpr int NW = NT / 64;
   constexpr int RG = NT / B;  // threads per column when combining partial sums
@@ -101,121 +108,130 @@ __global__ __launch_bounds__(NT) void panel_qr_kernel(int h, double* P, long ldp
   const int nrows = min(CH, h - row0);
   const int gi = row0 + t;
   const bool rok = t < nrows;
-  unsigned epoch = 0;
-
+  // a[k] holds column j + k of this thread's row during step j: the array
+  // shifts down by one column per step, so every index below is static and
+  // finished columns go to Pl[t][j]
   double a[B];
 #pragma unroll
   for (int c = 0; c < B; c++) a[c] = rok ? P[gi + (long)c * ldp] : 0.0;
 
   const int ncol = min(B, h);
   for (int j = 0; j < B; j++) {
-    if (j >= ncol) {
-      if (t == 0) taul[j] = 0.0;
-      continue;
-    }
-    // partial sums over this workgroup's rows strictly below the pivot:
-    // sum_i a_ij a_ic for every column c (only c >= j are used)
-    const bool below = rok && gi > j;
-    double aj = 0.0;
+    const bool below = rok && gi > j;  // rows strictly below the pivot
+    const bool piv = rok && gi == j;   // the pivot row (in workgroup 0)
+    if (j < ncol) {
+      // partial sums over this workgroup's rows below the pivot:
+      // sum_i a_ij a_i,j+k for k = 0 .. B-1-j
+      const double aj = a[0];
+      double v[B];
 #pragma unroll
-    for (int c = 0; c < B; c++) aj = (c == j) ? a[c] : aj;
-    double v[B];
+      for (int k = 0; k < B; k++) v[k] = below ? aj * a[k] : 0.0;
+      const double ws = wave_reduce_scatter(v);
+      if ((lane & 1) == 0) red[wv][lane >> 1] = ws;
+      if (g == 0 && piv) {
 #pragma unroll
-    for (int c = 0; c < B; c++) v[c] = below ? aj * a[c] : 0.0;
-    const double ws = wave_reduce_scatter(v);
-    if ((lane & 1) == 0) red[wv][lane >> 1] = ws;
-    // the pivot row (global row j, in workgroup 0) is published by its thread
-    if (g == 0 && t == j) {
-#pragma unroll
-      for (int c = 0; c < B; c++) rowl[c] = a[c];
-    }
-    __syncthreads();
-    double* pb = part + (size_t)(j & 1) * G * B;
-    double* rb = prow + (size_t)(j & 1) * B;
-    if (t < B) {
-      double sum = 0.0;
-#pragma unroll
-      for (int w = 0; w < NW; w++) sum += red[w][t];
-      pb[(size_t)g * B + t] = sum;
-      if (g == 0) rb[t] = rowl[t];
-    }
-    grid_sync(bar, G, epoch, st);
-    {
-      // RG threads per column sum strided subsets, then a fixed-order combine
-      const int c = t % B, rg = t / B;
-      double s2 = 0.0;
-      if (c >= j)
-        for (int q = rg; q < G; q += RG) s2 += pb[(size_t)q * B + c];
-      cmb[rg][c] = s2;
-    }
-    __syncthreads();
-    if (t < B) {
-      double s2 = 0.0;
-      for (int r = 0; r < RG; r++) s2 += cmb[r][t];
-      ddl[t] = s2;
-      rowl[t] = rb[t];
-    }
-    __syncthreads();
-    const double sigma = ddl[j];
-    const double alpha = rowl[j];
-    double tau = 0.0, beta = alpha, scal = 0.0;
-    if (sigma > 0.0) {
-      const double nrm = sqrt(alpha * alpha + sigma);
-      beta = (alpha >= 0.0) ? -nrm : nrm;
-      tau = (beta - alpha) / beta;
-      scal = 1.0 / (alpha - beta);
-    }
-    if (t < B) wl[t] = (t > j) ? tau * (rowl[t] + ddl[t] * scal) : 0.0;
-    if (t == 0) taul[j] = tau;
-    __syncthreads();
-    // update of this thread's row: below the pivot a_ic -= (a_ij scal) w_c and
-    // a_ij becomes v_i; the pivot row gets a_jc -= w_c and beta
-    if (below) {
-      const double vi = aj * scal;
-#pragma unroll
-      for (int c = 0; c < B; c++)
-        if (c > j) a[c] -= vi * wl[c];
-#pragma unroll
-      for (int c = 0; c < B; c++)
-        if (c == j) a[c] = vi;
-    } else if (rok && gi == j) {
-#pragma unroll
-      for (int c = 0; c < B; c++) {
-        if (c > j) a[c] -= wl[c];
-        if (c == j) a[c] = beta;
+        for (int k = 0; k < B; k++) rowl[k] = a[k];
       }
+      __syncthreads();
+      if (G == 1) {
+        // single workgroup: the sums and the pivot row are already in LDS
+        if (t < B) {
+          double sum = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; w++) sum += red[w][t];
+          ddl[t] = sum;
+        }
+      } else {
+        double* pb = part + (size_t)j * G * B;  // this column's slots (NaN before)
+        double* rb = prow + (size_t)j * B;
+        if (t < B) {
+          double sum = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; w++) sum += red[w][t];
+          st_agent(&pb[(size_t)g * B + t], sum);
+          if (g == 0) st_agent(&rb[t], rowl[t]);
+        }
+        {
+          // RG threads per column sum strided subsets, then a fixed-order combine
+          const int k = t % B, rg = t / B;
+          double s2 = 0.0;
+          if (k < B - j)
+            for (int q = rg; q < G; q += RG) s2 += ld_ready(&pb[(size_t)q * B + k], st);
+          cmb[rg][k] = s2;
+        }
+        __syncthreads();
+        if (t < B) {
+          double s2 = 0.0;
+          for (int r = 0; r < RG; r++) s2 += cmb[r][t];
+          ddl[t] = s2;
+          rowl[t] = ld_ready(&rb[t], st);
+        }
+      }
+      __syncthreads();
+      const double sigma = ddl[0];
+      const double alpha = rowl[0];
+      double tau = 0.0, beta = alpha, scal = 0.0;
+      if (sigma > 0.0) {
+        const double nrm = sqrt(alpha * alpha + sigma);
+        beta = (alpha >= 0.0) ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      if (t < B) wl[t] = (t >= 1 && t < B - j) ? tau * (rowl[t] + ddl[t] * scal) : 0.0;
+      if (t == 0) taul[j] = tau;
+      __syncthreads();
+      // below the pivot a_i,j+k -= (a_ij scal) w_k and a_ij becomes v_i; the
+      // pivot row gets a_j,j+k -= w_k and beta
+      if (below) {
+        const double vi = aj * scal;
+#pragma unroll
+        for (int k = 1; k < B; k++) a[k] -= vi * wl[k];
+        a[0] = vi;
+      } else if (piv) {
+#pragma unroll
+        for (int k = 1; k < B; k++) a[k] -= wl[k];
+        a[0] = beta;
+      }
+    } else if (t == 0) {
+      taul[j] = 0.0;
     }
+    // column j of this row is final: record it and shift
+    Pl[t][j] = a[0];
+#pragma unroll
+    for (int k = 0; k < B - 1; k++) a[k] = a[k + 1];
+    a[B - 1] = 0.0;
   }
+  __syncthreads();
 
-  // write back R / V in place and the explicit V; the rows go to LDS for the
-  // partial Gram V^T V
-  if (rok) {
-#pragma unroll
-    for (int c = 0; c < B; c++) {
-      P[gi + (long)c * ldp] = a[c];
-      const double vv = (gi > c) ? a[c] : (gi == c ? 1.0 : 0.0);
+  // write back R / V in place and the explicit V (also to LDS for the Gram)
+#pragma unroll 4
+  for (int c = 0; c < B; c++) {
+    const double x = Pl[t][c];
+    const double vv = (gi > c) ? x : (gi == c ? 1.0 : 0.0);
+    if (rok) {
+      P[gi + (long)c * ldp] = x;
       V[gi + (long)c * ldv] = vv;
-      Pl[t][c] = vv;
     }
-  } else {
-#pragma unroll
-    for (int c = 0; c < B; c++) Pl[t][c] = 0.0;
+    Pl[t][c] = rok ? vv : 0.0;
   }
   if (g == 0 && t < B) tau_out[t] = taul[t];
   __syncthreads();
+  // partial Gram of this workgroup's rows; workgroup 0 sums them
   for (int e = t; e < B * B; e += NT) {
     const int ca = e % B, cb = e / B;
     double sum = 0.0;
     if (ca <= cb)
       for (int i = 0; i < nrows; i++) sum += Pl[i][ca] * Pl[i][cb];
-    gpart[(size_t)g * B * B + e] = sum;
+    if (g == 0)
+      Gm[ca][cb] = sum;
+    else
+      st_agent(&gpart[(size_t)g * B * B + e], sum);
   }
-  grid_sync(bar, G, epoch, st);
   if (g != 0) return;
   for (int e = t; e < B * B; e += NT) {
     const int ca = e % B, cb = e / B;
-    double sum = 0.0;
-    for (int q = 0; q < G; q++) sum += gpart[(size_t)q * B * B + e];
+    double sum = Gm[ca][cb];
+    for (int q = 1; q < G; q++) sum += ld_ready(&gpart[(size_t)q * B * B + e], st);
     Gm[ca][cb] = sum;
     Tl[ca][cb] = 0.0;
   }
@@ -276,20 +292,17 @@ __global__ void atb_reduce_kernel(int G, const double* part, double* out, long l
   out[(e % B) + (long)(e / B) * ldo] = s;
 }
 
-__global__ void zero_u32_kernel(unsigned* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
 
 }  // namespace
 
 size_t sy2sb_scratch_doubles(int n, int B) {
   const int G = ceil_div(n, CH) + 1;
-  // part(2GB) + prow(2B) + gpart(G B^2) + atb parts(G B^2) + Y (n x B) + VW, WV (n x 4B each)
-  // + M (B^2) + Q (2B^2) + split-K partials (nsplit x n x B)
+  // panel exchange slots: part (B columns x G x B) + prow (B x B) + gpart (G B^2);
+  // atb parts (G B^2) + Y (n x B) + VW, WV (n x 4B each) + M (B^2) + Q (2B^2)
+  // + split-K partials (nsplit x n x B)
   const size_t nsplit = ceil_div(n, SPLITK) + 1;
-  return (size_t)2 * G * B + 2 * B + (size_t)2 * G * B * B + (size_t)9 * n * B + 3 * B * B + 64 +
-         nsplit * n * B;
+  return (size_t)G * B * B + (size_t)B * B + (size_t)2 * G * B * B + (size_t)9 * n * B +
+         3 * B * B + 64 + nsplit * n * B;
 }
 
 // Panels are reduced in pairs with one trailing update per pair.  For the
@@ -305,14 +318,14 @@ size_t sy2sb_scratch_doubles(int n, int B) {
 // which halves the passes over the trailing matrix.  The products are the
 // same as panel by panel; only the order of the roundings differs.
 hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, double* tau1,
-                     double* T1, double* AB, int ldab, double* scratch, unsigned* bar,
-                     DevStatusWord* st, hipStream_t s) {
+                     double* T1, double* AB, int ldab, double* scratch, DevStatusWord* st,
+                     hipStream_t s) {
   if (B != 32) return hipErrorInvalidValue;
   constexpr int BB = 32;
   const int Gmax = ceil_div(n, CH) + 1;
-  double* part = scratch;
-  double* prow = part + (size_t)2 * Gmax * B;
-  double* gpart = prow + 2 * B;
+  double* part = scratch;                        // B x Gmax x B exchange slots
+  double* prow = part + (size_t)B * Gmax * B;    // B x B
+  double* gpart = prow + (size_t)B * B;          // Gmax x B x B
   double* apart = gpart + (size_t)Gmax * B * B;
   double* Y = apart + (size_t)Gmax * B * B;      // n x B
   double* VW = Y + (size_t)n * B;                // n x 4B  [V1 W1 V2 W2], row i <-> row r0 + i
@@ -329,11 +342,18 @@ hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, d
     double* Tp = T1 + (size_t)p * B * B;
     double* tau_p = tau1 + c0;
     const int G = ceil_div(h, CH);
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, bar, 1);
-    HSDM_TRY(hipGetLastError());
+    if (G > 1) {
+      // exchange slots of this launch back to NaN (part, prow, gpart are contiguous)
+      const long cnt = (long)B * G * B + (long)B * B + (long)B * B * G;
+      const long span = (long)(gpart - part) + (long)B * B * G;
+      hipLaunchKernelGGL(fill_nan_kernel, dim3((unsigned)((span + 255) / 256)), dim3(256), 0, s,
+                         part, span);
+      HSDM_TRY(hipGetLastError());
+      (void)cnt;
+    }
     void* args[] = {(void*)&h, (void*)&Pp, (void*)&lda, (void*)&Vp, (void*)&ldv,
                     (void*)&tau_p, (void*)&Tp, (void*)&part, (void*)&prow, (void*)&gpart,
-                    (void*)&bar, (void*)&st};
+                    (void*)&st};
     // algorithmic: Householder QR of the h x B panel (2 h B^2 flops), the
     // panel read and written once
     kt_begin("panel_qr_kernel<32>", 2.0 * h * B * B, 16.0 * h * B, 0, s);
