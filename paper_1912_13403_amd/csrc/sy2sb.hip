@@ -27,28 +27,65 @@ constexpr int NT = 256;
 constexpr int CH = 256;      // panel rows per workgroup
 constexpr int SPLITK = 512;  // K slice of the symmetric product X = A22 Y
 
-// Sum of v[0..B-1] over the 64 lanes of a wavefront (B = 32), by recursive
-// halving: after the step with partner lane ^ 2^k (k = 5 .. 1) a lane keeps
-// the half of its values selected by that lane bit, so lane l ends up with
-// the sum for index l >> 1 over the 32 lanes sharing bit 0; a last exchange
-// with lane ^ 1 completes the sum over all 64 lanes.
+template <int CTRL>
+HSDM_DEV double dpp_mov(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+template <int PAT>
+HSDM_DEV double swizzle(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(unsigned)u, PAT);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(unsigned)(u >> 32), PAT);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// value of the partner lane (lane ^ 2^S): quad permutations for S = 0, 1,
+// swizzles in bit-mask mode for S = 2, 3, 4, a shuffle for S = 5
+template <int S>
+HSDM_DEV double xchg(double v) {
+  if constexpr (S == 0) return dpp_mov<0xB1>(v);             // quad_perm [1,0,3,2]
+  else if constexpr (S == 1) return dpp_mov<0x4E>(v);        // quad_perm [2,3,0,1]
+  else if constexpr (S <= 4) return swizzle<0x1F | ((1 << S) << 10)>(v);
+  else return __shfl_xor(v, 32, 64);
+}
+
+template <int S, int NV>
+HSDM_DEV void halve(double (&v)[NV], bool hi) {
+  constexpr int half = 16 >> S;
+#pragma unroll
+  for (int k = 0; k < half; k++) {
+    const double send = hi ? v[k] : v[half + k];
+    const double keep = hi ? v[half + k] : v[k];
+    v[k] = keep + xchg<S>(send);
+  }
+}
+
+// Sum of v[0..31] over the 64 lanes of a wavefront by recursive halving:
+// after the exchange with lane ^ 2^S a lane keeps the half of its values
+// selected by that lane bit (cheapest exchanges first, for the largest
+// halves).  Lane l ends with the sum for index bitrev5(l & 31) (see
+// rs_index) over the 32 lanes sharing bit 5; the exchange with lane ^ 32
+// completes it over all 64 lanes.
 template <int NV>
 HSDM_DEV double wave_reduce_scatter(double (&v)[NV]) {
   static_assert(NV == 32, "32 values over 64 lanes");
   const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int step = 0; step < 5; step++) {
-    const int half = 16 >> step;           // values kept after this step
-    const int bit = 32 >> step;            // partner lane ^ bit
-    const bool hi = (lane & bit) != 0;     // keep the upper half of the current range
-#pragma unroll
-    for (int k = 0; k < half; k++) {
-      const double send = hi ? v[k] : v[half + k];
-      const double keep = hi ? v[half + k] : v[k];
-      v[k] = keep + __shfl_xor(send, bit, 64);
-    }
-  }
-  return v[0] + __shfl_xor(v[0], 1, 64);
+  halve<0>(v, (lane & 1) != 0);
+  halve<1>(v, (lane & 2) != 0);
+  halve<2>(v, (lane & 4) != 0);
+  halve<3>(v, (lane & 8) != 0);
+  halve<4>(v, (lane & 16) != 0);
+  return v[0] + xchg<5>(v[0]);
+}
+
+// index of the value lane l holds after wave_reduce_scatter
+HSDM_DEV int rs_index(int lane) {
+  return ((lane & 1) << 4) | ((lane & 2) << 2) | (lane & 4) | ((lane & 8) >> 2) |
+         ((lane & 16) >> 4);
 }
 
 // Exchange between the workgroups of a panel without a barrier: every slot
@@ -127,7 +164,7 @@ __global__ __launch_bounds__(NT) void panel_qr_kernel(int h, double* P, long ldp
 #pragma unroll
       for (int k = 0; k < B; k++) v[k] = below ? aj * a[k] : 0.0;
       const double ws = wave_reduce_scatter(v);
-      if ((lane & 1) == 0) red[wv][lane >> 1] = ws;
+      if (lane < 32) red[wv][rs_index(lane)] = ws;
       if (g == 0 && piv) {
 #pragma unroll
         for (int k = 0; k < B; k++) rowl[k] = a[k];
