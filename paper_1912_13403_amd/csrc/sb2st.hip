@@ -302,11 +302,25 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
         }
         wave_sync();
       }
-      // write back
-      for (int q = 0; q < HB; q++) {
-        const int j = hf * HB + q;
-        if (li < len && j < len && li >= j) AB[(li - j) + (long)(rs + j) * ldab] = Dl[li][j];
-        if (li < len2 && j < len) AB[(B + li - j) + (long)(rs + j) * ldab] = Bl[li][j];
+      // write back: all LDS values first, then the stores (column j of the
+      // band: rows li of both blocks are consecutive)
+      {
+        double dv[HB], bv[HB];
+#pragma unroll
+        for (int q = 0; q < HB; q++) {
+          const int j = hf * HB + q;
+          dv[q] = Dl[li][j];
+          bv[q] = Bl[li][j];
+        }
+        // element (rs + li, rs + j) of D sits at (li - j) + (rs + j) ldab
+        double* col = AB + (long)(rs + hf * HB) * ldab + (li - hf * HB);
+#pragma unroll
+        for (int q = 0; q < HB; q++) {
+          const int j = hf * HB + q;
+          double* cj = col + (long)q * (ldab - 1);
+          if (li < len && j < len && li >= j) cj[0] = dv[q];
+          if (li < len2 && j < len) cj[B] = bv[q];
+        }
       }
       tau = tau_n;
       publish_lds(&lprog[wv_id], kbase + t + 1);
