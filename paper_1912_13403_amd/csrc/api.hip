@@ -131,7 +131,7 @@ int ensure_ws(hsdm_ctx* h, int n) {
   const size_t oL = take(nn), oLi = take(nn), oA = take(nn), oV = take(nn), oZ = take(nn),
                oC = take(nn);
   const size_t oT1 = take((size_t)(npanel + 1) * BAND * BAND), otau1 = take(n + 1);
-  const size_t oAB = take((size_t)2 * BAND * n), osy = take(sy2sb_scratch_doubles(n, BAND));
+  const size_t oAB = take((size_t)2 * BAND * (n + BAND + 1)), osy = take(sy2sb_scratch_doubles(n, BAND));
   const size_t od = take(n), oe = take(n), olam = take(n), of = take(n);
   const size_t oV2 = take(L.v2_doubles + 1), otau2 = take((size_t)L.ngroups * BAND + 1),
                oF2 = take(bt2_pack_doubles(L) + 1);

@@ -11,7 +11,8 @@ hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, d
                      double* T1, double* AB, int ldab, double* scratch, DevStatusWord* st,
                      hipStream_t s);
 
-// sb2st.hip -- band -> tridiagonal by bulge chasing.  AB is overwritten;
+// sb2st.hip -- band -> tridiagonal by bulge chasing.  ldab must be 2B and AB
+// must have B + 1 spare columns after the n used ones.  AB is overwritten;
 // d (n) and e (n-1) receive the tridiagonal; the stage-2 reflectors are
 // stored group-wise in V2 (see sb2st_layout) with their scalars in tau2.
 struct Sb2stLayout {

@@ -182,20 +182,22 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
       const int rs2 = rs + B;
       const int len2 = (rs2 < n) ? min(B, n - rs2) : 0;
       // load the diagonal block (symmetrized) and the block below: all loads
-      // are issued before the first use (addresses clamped into the band,
-      // values masked), so one memory round trip covers the whole task
+      // are issued before the first use through one base pointer per lane
+      // (the band storage has B + 1 spare columns, so every address is inside
+      // it; invalid values are masked)
       {
         double dv[HB], bv[HB];
+        const double* col = AB + (long)(rs + hf * HB) * ldab + (li - hf * HB);
+#pragma unroll
+        for (int q = 0; q < HB; q++) {
+          dv[q] = col[(long)q * (ldab - 1)];
+          bv[q] = col[(long)q * (ldab - 1) + B];
+        }
 #pragma unroll
         for (int q = 0; q < HB; q++) {
           const int j = hf * HB + q;
-          const bool dok = li < len && j < len && li >= j;
-          const bool bok = li < len2 && j < len;
-          const long cj = (long)min(rs + j, n - 1) * ldab;
-          dv[q] = AB[(dok ? li - j : 0) + cj];
-          bv[q] = AB[(bok ? B + li - j : 0) + cj];
-          dv[q] = dok ? dv[q] : 0.0;
-          bv[q] = bok ? bv[q] : 0.0;
+          dv[q] = (li < len && j < len && li >= j) ? dv[q] : 0.0;
+          bv[q] = (li < len2 && j < len) ? bv[q] : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < HB; q++) {
@@ -378,7 +380,7 @@ hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, doub
                      double* tau2, const long* d_goff, int* progress, DevStatusWord* st,
                      hipStream_t s) {
   const int n = L.n;
-  if (L.B != 32) return hipErrorInvalidValue;
+  if (L.B != 32 || ldab != 2 * L.B) return hipErrorInvalidValue;
   if (L.nsweep > 0) {
     hipLaunchKernelGGL(fill_dbl_kernel, dim3(4096), dim3(256), 0, s, V2, L.v2_doubles);
     HSDM_TRY(hipGetLastError());
