@@ -78,7 +78,17 @@ HSDM_DEV double wsum(double v) {
   return first_lane(v);
 }
 
-HSDM_DEV double hsum(double v) { return v + __shfl_xor(v, 32, 64); }
+// v + (the value of lane ^ 32): v_permlane32_swap of each 32-bit half gives
+// the lower lanes' value and the upper lanes' value in every lane.
+HSDM_DEV double hsum(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+  const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double a = __builtin_bit_cast(double, ((unsigned long long)(unsigned)ph[0] << 32) | (unsigned)pl[0]);
+  const double b = __builtin_bit_cast(double, ((unsigned long long)(unsigned)ph[1] << 32) | (unsigned)pl[1]);
+  return a + b;
+}
 
 // Sweep s waits for sweep s-1.  Consecutive sweeps run on the wavefronts of
 // one workgroup except across workgroup boundaries, so the hand-off uses
