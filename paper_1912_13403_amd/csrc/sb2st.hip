@@ -13,13 +13,13 @@
 // s may run task t once sweep s-1 has finished task t+1: sweeps proceed as a
 // pipeline, each two tasks behind its predecessor.
 //
-// One wavefront runs one sweep at a time (64 lanes; the B x B blocks live in
-// LDS); workgroups of 8 wavefronts are launched cooperatively so that every
+// One wavefront runs one sweep at a time (64 lanes; the two B x B blocks of
+// a task live in registers, sums over lanes use DPP and permlane swaps);
+// workgroups of 8 wavefronts are launched cooperatively so that every
 // wavefront is resident.  Consecutive sweeps run on consecutive wavefronts:
 // inside a workgroup the hand-off is a progress counter in LDS, between
 // workgroups a counter in global memory with agent-scope release/acquire;
 // every wait is bounded and reports through the status word if it runs out.
-// Sums over the rows of a block use DPP and LDS swizzle moves.
 //
 // Storage: lower band storage AB[(r-c) + c*ldab], ldab = 2B (offsets up to
 // 2B-1 hold the bulge).  Each reflector H_{s,t} (v, tau; v[0] = 1) is stored
@@ -51,14 +51,6 @@ HSDM_DEV double dpp(double v) {
   return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
-template <int PAT>
-HSDM_DEV double swz(double v) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const int lo = __builtin_amdgcn_ds_swizzle((int)(unsigned)u, PAT);
-  const int hi = __builtin_amdgcn_ds_swizzle((int)(unsigned)(u >> 32), PAT);
-  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-
 HSDM_DEV double first_lane(double v) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
   const unsigned lo = __builtin_amdgcn_readfirstlane((int)(unsigned)u);
@@ -66,28 +58,63 @@ HSDM_DEV double first_lane(double v) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// Sum of a value that is zero outside lanes 0..31, returned in every lane:
-// lane xor 1 and xor 2 (quad permutations), rotations by 4 and 8 inside rows
-// of 16, lane xor 16 (swizzle, bit-mask mode), then lane 0's total.
-HSDM_DEV double wsum(double v) {
-  v += dpp<0xB1>(v);
-  v += dpp<0x4E>(v);
-  v += dpp<0x124>(v);
-  v += dpp<0x128>(v);
-  v += swz<0x401F>(v);
-  return first_lane(v);
+HSDM_DEV long uniform(long v) {
+  const unsigned long long u = (unsigned long long)v;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((int)(unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+  return (long)(((unsigned long long)hi << 32) | lo);
 }
 
-// v + (the value of lane ^ 32): v_permlane32_swap of each 32-bit half gives
-// the lower lanes' value and the upper lanes' value in every lane.
-HSDM_DEV double hsum(double v) {
+HSDM_DEV double join(unsigned lo, unsigned hi) {
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// v + (the value of lane ^ 16): v_permlane16_swap of each 32-bit half gives
+// the even rows' value and the odd rows' value (rows of 16 lanes) in every lane.
+HSDM_DEV double xor16_sum(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
+  const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return join(pl[0], ph[0]) + join(pl[1], ph[1]);
+}
+
+// v + (the value of lane ^ 32), by v_permlane32_swap.
+HSDM_DEV double xor32_sum(double v) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
   const unsigned lo = (unsigned)u, hi = (unsigned)(u >> 32);
   const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
   const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-  const double a = __builtin_bit_cast(double, ((unsigned long long)(unsigned)ph[0] << 32) | (unsigned)pl[0]);
-  const double b = __builtin_bit_cast(double, ((unsigned long long)(unsigned)ph[1] << 32) | (unsigned)pl[1]);
-  return a + b;
+  return join(pl[0], ph[0]) + join(pl[1], ph[1]);
+}
+
+// Sum over the 8 lanes 8I .. 8I+7 (lane xor 1, xor 2, then the mirror lane
+// inside the half row, which lies in the other quad).
+HSDM_DEV double sum8(double v) {
+  v += dpp<0xB1>(v);
+  v += dpp<0x4E>(v);
+  v += dpp<0x141>(v);
+  return v;
+}
+
+// Sum over the 8 lanes J, J+8, .., J+56 (lane xor 8 by a rotation by 8
+// inside rows of 16, then xor 16 and xor 32).
+HSDM_DEV double sumI(double v) {
+  v += dpp<0x128>(v);
+  v = xor16_sum(v);
+  return xor32_sum(v);
+}
+
+// The value of lane 8I in every lane 8I .. 8I+7: the first lane of each quad
+// to the quad, then lanes 4..7 of each half row take lane 0's copy (row
+// shift right by 4, written to banks 1 and 3 only).
+HSDM_DEV double bcast8(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, 0x00, 0xF, 0xF, false);
+  int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x00, 0xF, 0xF, false);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, 0x114, 0xF, 0xA, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, 0x114, 0xF, 0xA, false);
+  return join((unsigned)lo, (unsigned)hi);
 }
 
 // Sweep s waits for sweep s-1.  Consecutive sweeps run on the wavefronts of
@@ -149,27 +176,55 @@ HSDM_DEV void publish(int* p, int v, bool agent) {
   }
 }
 
+// Reflector from x (x[0] = alpha, sig = sum of x[i]^2 over i >= 1):
+// H = I - tau v v^T, v[0] = 1, H x = beta e_0 (LAPACK's dlarfg convention
+// without the rescaling loop).
+HSDM_DEV void make_reflector(double alpha, double sig, double& beta, double& tau, double& scal) {
+  beta = alpha;
+  tau = 0.0;
+  scal = 0.0;
+  if (sig > 0.0) {
+    const double nrm = sqrt(alpha * alpha + sig);
+    beta = (alpha >= 0.0) ? -nrm : nrm;
+    tau = (beta - alpha) / beta;
+    scal = 1.0 / (alpha - beta);
+  }
+}
+
+// A task works on two B x B blocks (B = 32): the diagonal block D (rows and
+// columns R_t, held in full although only its lower triangle is stored) and
+// the block K below it (rows R_{t+1}, columns R_t).  Lane l = 8 I + J holds
+// the 16 elements (I + 8a, J + 8b), a, b < 4, of each block in registers, so
+// that a product with a vector is 16 FMAs per lane plus a sum over the 8
+// lanes of a row group (sum8) or of a column group (sumI), and the rank-one
+// and rank-two updates need no data from other lanes.  The reflector v is
+// kept in both index sets (rows I + 8a, columns J + 8b); one copy through LDS
+// per task turns the row form of the next reflector into the column form.
 template <int B>
 __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, double* AB, int ldab,
                                                          double* V2, double* tau2,
                                                          const long* goff, int* progress,
                                                          DevStatusWord* st) {
-  static_assert(2 * B == 64, "one lane per row of a 2B-row group column");
-  __shared__ double Dl_all[WPB][B][B + 1];
-  __shared__ double Bl_all[WPB][B][B + 1];
-  __shared__ double vc_all[WPB][B], vn_all[WPB][B], wv_all[WPB][B];
+  static_assert(B == 32, "8 x 8 lanes, 4 x 4 elements each");
+  __shared__ double vl_all[WPB][B];
   __shared__ int lprog[WPB];
   const int lane = threadIdx.x & 63, wv_id = threadIdx.x >> 6;
   if (lane == 0) lprog[wv_id] = -1;
   __syncthreads();
-  double(*Dl)[B + 1] = Dl_all[wv_id];
-  double(*Bl)[B + 1] = Bl_all[wv_id];
-  double* vc = vc_all[wv_id];
-  double* vn = vn_all[wv_id];
-  double* wk = wv_all[wv_id];
+  double* vl = vl_all[wv_id];
   const int gw = blockIdx.x * WPB + wv_id, TW = gridDim.x * WPB;
-  const int li = lane % B, hf = lane / B;  // row index and column half (B/2 columns each)
-  constexpr int HB = B / 2;
+  const int I = lane >> 3, J = lane & 7;
+  // Element (i, j), i >= j, of a block whose first row and column is r sits
+  // at (i - j) + (r + j) LD = (r LD) + i + (LD - 1) j in the band storage.
+  // With i = I + 8a, j = J + 8b that is a per-lane base (P for i >= j, Q for
+  // the transposed position of i < j) plus a constant.
+  constexpr int LD = 2 * B;
+  const int P = I + (LD - 1) * J, Q = J + (LD - 1) * I, M = (I >= J) ? P : Q;
+  auto offl = [&](int a, int b) { return P + 8 * a + 8 * (LD - 1) * b; };
+  auto offd = [&](int a, int b) {
+    return a > b ? P + 8 * a + 8 * (LD - 1) * b
+                 : (a < b ? Q + 8 * b + 8 * (LD - 1) * a : M + 8 * LD * a);
+  };
 
   for (int s = gw, round = 0; s < nsweep; s += TW, round++) {
     const int ntask = (n - 1 - s + B - 1) / B;
@@ -179,7 +234,8 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
     const bool last_wave = (wv_id == WPB - 1);
     const int kbase = round * KROUND;
     double tau = 0.0;
-    const long g0 = goff[s / B];
+    double vr[4], vc[4];  // current reflector at rows I + 8a and columns J + 8b
+    const long g0 = uniform(goff[s / B]);
     for (int t = 0; t < ntask; t++) {
       if (s > 0) {
         if (first_wave)
@@ -191,150 +247,164 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
       const int len = min(B, n - rs);
       const int rs2 = rs + B;
       const int len2 = (rs2 < n) ? min(B, n - rs2) : 0;
-      // load the diagonal block (symmetrized) and the block below: all loads
-      // are issued before the first use through one base pointer per lane
-      // (the band storage has B + 1 spare columns, so every address is inside
-      // it; invalid values are masked)
-      {
-        double dv[HB], bv[HB];
-        const double* col = AB + (long)(rs + hf * HB) * ldab + (li - hf * HB);
+      // every address below stays inside the band storage (B + 1 spare
+      // columns); values outside the blocks are masked after the loads
+      double* const blk = AB + (long)rs * LD;
+      double d[4][4], k[4][4];
 #pragma unroll
-        for (int q = 0; q < HB; q++) {
-          dv[q] = col[(long)q * (ldab - 1)];
-          bv[q] = col[(long)q * (ldab - 1) + B];
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+          d[a][b] = blk[offd(a, b)];
+          k[a][b] = blk[B + offl(a, b)];
         }
 #pragma unroll
-        for (int q = 0; q < HB; q++) {
-          const int j = hf * HB + q;
-          dv[q] = (li < len && j < len && li >= j) ? dv[q] : 0.0;
-          bv[q] = (li < len2 && j < len) ? bv[q] : 0.0;
-        }
+      for (int a = 0; a < 4; a++)
 #pragma unroll
-        for (int q = 0; q < HB; q++) {
-          const int j = hf * HB + q;
-          Bl[li][j] = bv[q];
-          if (li >= j) {
-            Dl[li][j] = dv[q];
-            Dl[j][li] = dv[q];
-          }
+        for (int b = 0; b < 4; b++) {
+          const int i = I + 8 * a, j = J + 8 * b;
+          d[a][b] = (i < len && j < len) ? d[a][b] : 0.0;
+          k[a][b] = (i < len2 && j < len) ? k[a][b] : 0.0;
         }
-      }
       if (t == 0) {
         // reflector from column s, rows s+1 .. s+len
-        const double x = (lane < len) ? AB[(1 + lane) + (long)s * ldab] : 0.0;
-        const double alpha = first_lane(x);
-        const double sig = wsum((lane >= 1 && lane < len) ? x * x : 0.0);
-        double beta = alpha, scal = 0.0;
-        tau = 0.0;
-        if (sig > 0.0) {
-          const double nrm = sqrt(alpha * alpha + sig);
-          beta = (alpha >= 0.0) ? -nrm : nrm;
-          tau = (beta - alpha) / beta;
-          scal = 1.0 / (alpha - beta);
+        double xr[4], xc[4];
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+          const int i = I + 8 * a, j = J + 8 * a;
+          xr[a] = (i < len) ? AB[(1 + i) + (long)s * LD] : 0.0;
+          xc[a] = (j < len) ? AB[(1 + j) + (long)s * LD] : 0.0;
         }
-        if (lane < B) vc[lane] = (lane == 0) ? 1.0 : ((lane < len) ? x * scal : 0.0);
-        if (lane < len) AB[(1 + lane) + (long)s * ldab] = (lane == 0) ? beta : 0.0;
-      } else {
-        if (lane < B) vc[lane] = vn[lane];
+        const double alpha = first_lane(xr[0]);
+        double ps = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; a++) ps += (I + 8 * a >= 1) ? xr[a] * xr[a] : 0.0;
+        const double sig = first_lane(sumI(ps));
+        double beta, scal;
+        make_reflector(alpha, sig, beta, tau, scal);
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+          const int i = I + 8 * a, j = J + 8 * a;
+          vr[a] = (i == 0) ? 1.0 : xr[a] * scal;
+          vc[a] = (j == 0) ? 1.0 : xc[a] * scal;
+        }
+        if (J == 0) {
+#pragma unroll
+          for (int a = 0; a < 4; a++) {
+            const int i = I + 8 * a;
+            vl[i] = vr[a];
+            if (i < len) AB[(1 + i) + (long)s * LD] = (i == 0) ? beta : 0.0;
+          }
+        }
+        wave_sync();
       }
-      wave_sync();
-      // store H_{s,t} for the back-transformation
+      // store H_{s,t} for the back-transformation (v is in LDS)
       {
-        const int k = s % B;
+        const int kk = s % B;
         const long gi = g0 + t;
-        double* col = V2 + (gi * B + k) * (long)(2 * B);
-        const int r = lane - k;
-        col[lane] = (r >= 0 && r < len) ? vc[r] : 0.0;
-        if (lane == 0) tau2[gi * B + k] = tau;
+        double* col = V2 + (gi * B + kk) * (long)(2 * B);
+        const int r = lane - kk;
+        col[lane] = (r >= 0 && r < len) ? vl[r] : 0.0;
+        if (lane == 0) tau2[gi * B + kk] = tau;
       }
-      // two-sided update of the diagonal block: y = tau D v, w = y - (tau/2)(v.y) v
+      // two-sided update of D: y = tau D v, w = y - (tau/2)(v.y) v,
+      // D <- D - v w^T - w v^T (y and w in both index sets)
       {
-        double p = 0.0;
-        for (int q = 0; q < HB; q++) {
-          const int j = hf * HB + q;
-          p += Dl[li][j] * vc[j];
+        double yr[4], yc[4];
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+          double p = 0.0;
+#pragma unroll
+          for (int b = 0; b < 4; b++) p += d[a][b] * vc[b];
+          yr[a] = p;
         }
-        const double y = tau * hsum(p);
-        const double vy = wsum(hf == 0 ? vc[li] * y : 0.0);
-        const double w = y - 0.5 * tau * vy * vc[li];
-        if (hf == 0) wk[li] = w;
-        wave_sync();
-        const double vi = vc[li];
-        for (int q = 0; q < HB; q++) {
-          const int j = hf * HB + q;
-          Dl[li][j] -= vi * wk[j] + w * vc[j];
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+          double p = 0.0;
+#pragma unroll
+          for (int a = 0; a < 4; a++) p += d[a][b] * vr[a];
+          yc[b] = p;
         }
+#pragma unroll
+        for (int a = 0; a < 4; a++) yr[a] = tau * sum8(yr[a]);
+#pragma unroll
+        for (int b = 0; b < 4; b++) yc[b] = tau * sumI(yc[b]);
+        double pv = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; a++) pv += vr[a] * yr[a];
+        const double h = 0.5 * tau * sumI(pv);
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+          yr[a] -= h * vr[a];
+          yc[a] -= h * vc[a];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+          for (int b = 0; b < 4; b++) d[a][b] -= vr[a] * yc[b] + yr[a] * vc[b];
       }
-      double tau_n = 0.0;
+      double tau_n = 0.0, vnr[4] = {0.0, 0.0, 0.0, 0.0}, vnc[4] = {0.0, 0.0, 0.0, 0.0};
       if (len2 > 0) {
-        // right application to the block below: Bk <- Bk (I - tau v v^T)
-        double p = 0.0;
-        for (int q = 0; q < HB; q++) {
-          const int j = hf * HB + q;
-          p += Bl[li][j] * vc[j];
-        }
-        const double z = tau * hsum(p);
-        for (int q = 0; q < HB; q++) {
-          const int j = hf * HB + q;
-          Bl[li][j] -= z * vc[j];
-        }
-        wave_sync();
-        // next reflector from the first column of the block
-        const double x = (lane < len2) ? Bl[lane][0] : 0.0;
-        const double alpha = first_lane(x);
-        const double sig = wsum((lane >= 1 && lane < len2) ? x * x : 0.0);
-        double beta = alpha, scal = 0.0;
-        if (sig > 0.0) {
-          const double nrm = sqrt(alpha * alpha + sig);
-          beta = (alpha >= 0.0) ? -nrm : nrm;
-          tau_n = (beta - alpha) / beta;
-          scal = 1.0 / (alpha - beta);
-        }
-        if (lane < B) vn[lane] = (lane == 0) ? 1.0 : ((lane < len2) ? x * scal : 0.0);
-        wave_sync();
-        // left application to columns 1..: w_j = tau_n sum_r vn_r Bk[r][j]
-        // (lane owns column li, rows of its half)
-        double pc = 0.0;
-        for (int q = 0; q < HB; q++) {
-          const int r = hf * HB + q;
-          pc += vn[r] * Bl[r][li];
-        }
-        const double wj = tau_n * hsum(pc);
-        wave_sync();
-        if (li >= 1) {
-          for (int q = 0; q < HB; q++) {
-            const int r = hf * HB + q;
-            Bl[r][li] -= vn[r] * wj;
-          }
-        } else {
-          for (int q = 0; q < HB; q++) {
-            const int r = hf * HB + q;
-            Bl[r][0] = (r == 0) ? beta : 0.0;
-          }
-        }
-        wave_sync();
-      }
-      // write back: all LDS values first, then the stores (column j of the
-      // band: rows li of both blocks are consecutive)
-      {
-        double dv[HB], bv[HB];
+        // right application to K: K <- K (I - tau v v^T)
 #pragma unroll
-        for (int q = 0; q < HB; q++) {
-          const int j = hf * HB + q;
-          dv[q] = Dl[li][j];
-          bv[q] = Bl[li][j];
-        }
-        // element (rs + li, rs + j) of D sits at (li - j) + (rs + j) ldab
-        double* col = AB + (long)(rs + hf * HB) * ldab + (li - hf * HB);
+        for (int a = 0; a < 4; a++) {
+          double p = 0.0;
 #pragma unroll
-        for (int q = 0; q < HB; q++) {
-          const int j = hf * HB + q;
-          double* cj = col + (long)q * (ldab - 1);
-          if (li < len && j < len && li >= j) cj[0] = dv[q];
-          if (li < len2 && j < len) cj[B] = bv[q];
+          for (int b = 0; b < 4; b++) p += k[a][b] * vc[b];
+          const double z = tau * sum8(p);
+#pragma unroll
+          for (int b = 0; b < 4; b++) k[a][b] -= z * vc[b];
+        }
+        // next reflector from column 0 of K (lanes J = 0, b = 0)
+        double xr[4];
+#pragma unroll
+        for (int a = 0; a < 4; a++) xr[a] = bcast8(k[a][0]);
+        const double alpha = first_lane(xr[0]);
+        double ps = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; a++) ps += (I + 8 * a >= 1) ? xr[a] * xr[a] : 0.0;
+        const double sig = first_lane(sumI(ps));
+        double beta, scal;
+        make_reflector(alpha, sig, beta, tau_n, scal);
+#pragma unroll
+        for (int a = 0; a < 4; a++) vnr[a] = (I + 8 * a == 0) ? 1.0 : xr[a] * scal;
+        if (J == 0) {
+#pragma unroll
+          for (int a = 0; a < 4; a++) vl[I + 8 * a] = vnr[a];
+        }
+        wave_sync();
+#pragma unroll
+        for (int b = 0; b < 4; b++) vnc[b] = vl[J + 8 * b];
+        // left application to columns 1..: K <- (I - tau_n vn vn^T) K
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+          double p = 0.0;
+#pragma unroll
+          for (int a = 0; a < 4; a++) p += vnr[a] * k[a][b];
+          const double w = tau_n * sumI(p);
+          const int j = J + 8 * b;
+#pragma unroll
+          for (int a = 0; a < 4; a++) {
+            const int i = I + 8 * a;
+            k[a][b] = (j == 0) ? ((i == 0) ? beta : 0.0) : k[a][b] - vnr[a] * w;
+          }
         }
       }
+      // write back the lower triangle of D and all of K
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+          const int i = I + 8 * a, j = J + 8 * b;
+          if (i >= j && i < len) blk[offl(a, b)] = d[a][b];
+          if (i < len2 && j < len) blk[B + offl(a, b)] = k[a][b];
+        }
       tau = tau_n;
+#pragma unroll
+      for (int a = 0; a < 4; a++) {
+        vr[a] = vnr[a];
+        vc[a] = vnc[a];
+      }
       publish_lds(&lprog[wv_id], kbase + t + 1);
       if (last_wave) publish(progress + s, t + 1, true);
     }
