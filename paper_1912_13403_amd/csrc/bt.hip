@@ -356,45 +356,61 @@ hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff,
 namespace {
 
 // ---- stage 1 ------------------------------------------------------------------
-// GP consecutive panels form one block reflector of width GP*B:
+// GP consecutive panels form one block reflector of width W = GP*B:
 //   (I - V1 T1 V1^T)(I - V2 T2 V2^T) = I - [V1 V2] [[T1, -T1 V1^T V2 T2], [0, T2]] [V1 V2]^T
 // applied panel group by panel group, last group first.  The explicit panel
 // reflectors are zero above their first row, so the grouped V is dense with a
-// staircase of zeros.
-constexpr int GP = 4;
+// staircase of zeros.  T of a group is built from the panel T's by doubling
+// the block size: at each level the blocks of size b pair up and the
+// off-diagonal block of the pair is -T_a (G_ab T_b), G = V^T V, two batched
+// products for all pairs of all groups.  A wide group makes the update of Z
+// (read and written once per group) compute-bound.
+constexpr int GP = 16;
 
-// T of one panel group from the per-panel T's and the Gram G = V^T V (ld W).
-__global__ __launch_bounds__(256) void group_t1_kernel(int np, int Bp, const double* T1p,
-                                                       const double* Gm, double* Tq) {
-  const int W = np * Bp;
-  __shared__ double X[3 * 32 * 32];  // (i*Bp) x Bp block, i <= 3, Bp <= 32
-  const int t = threadIdx.x;
-  for (int e = t; e < W * W; e += 256) {
-    const int r = e % W, c = e / W;
-    const int pr = r / Bp, pc = c / Bp;
-    Tq[r + (long)c * W] = (pr == pc) ? T1p[(size_t)pr * Bp * Bp + (r % Bp) + (c % Bp) * Bp] : 0.0;
+__global__ void group_t_init_kernel(int ngroup, int np_all, int Bp, const double* T1p,
+                                    double* Tall) {
+  // Tall[q] (W x W): the panel T's on the diagonal, zero elsewhere
+  const int W = GP * Bp;
+  const long tot = (long)ngroup * W * W;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x) {
+    const int q = (int)(e / ((long)W * W));
+    const int rc = (int)(e % ((long)W * W));
+    const int r = rc % W, c = rc / W;
+    const int pr = r / Bp, pc = c / Bp, p = q * GP + pr;
+    double v = 0.0;
+    if (pr == pc && p < np_all) v = T1p[(size_t)p * Bp * Bp + (r % Bp) + (size_t)(c % Bp) * Bp];
+    Tall[e] = v;
   }
-  __syncthreads();
-  for (int i = 1; i < np; i++) {
-    const int rows = i * Bp;
-    const double* Ti = T1p + (size_t)i * Bp * Bp;
-    // X = G[0:rows, iBp:(i+1)Bp] * T_i
-    for (int e = t; e < rows * Bp; e += 256) {
-      const int r = e % rows, c = e / rows;
-      double acc = 0.0;
-      for (int q = 0; q <= c; q++) acc += Gm[r + (long)(rows + q) * W] * Ti[q + c * Bp];
-      X[r + c * rows] = acc;
-    }
-    __syncthreads();
-    // Tq[0:rows, block] = -Tq[0:rows, 0:rows] * X  (Tq upper triangular)
-    for (int e = t; e < rows * Bp; e += 256) {
-      const int r = e % rows, c = e / rows;
-      double acc = 0.0;
-      for (int q = r; q < rows; q++) acc += Tq[r + (long)q * W] * X[q + c * rows];
-      Tq[r + (long)(rows + c) * W] = -acc;
-    }
-    __syncthreads();
-  }
+}
+
+// Descriptors of one doubling level (block size b): for group q and pair j,
+// a = rows [2jb, (2j+1)b), c = columns [(2j+1)b, (2j+2)b) of the group, both
+// cut to the group's width w:  X = G[a, c] T[c, c];  T[a, c] = -T[a, a] X.
+__global__ void group_t_desc_kernel(int ngroup, int np_all, int Bp, int b, const double* Gall,
+                                    double* Tall, double* Xall, GemmDesc* d1, GemmDesc* d2) {
+  const int W = GP * Bp, pairs = W / (2 * b);
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ngroup * pairs) return;
+  const int q = idx / pairs, j = idx % pairs;
+  const int w = min(GP, np_all - q * GP) * Bp;
+  const int a0 = 2 * j * b, c0 = a0 + b;
+  const int ma = max(0, min(b, w - a0)), nc = max(0, min(b, w - c0));
+  const double* G = Gall + (size_t)q * W * W;
+  double* T = Tall + (size_t)q * W * W;
+  double* X = Xall + (size_t)idx * b * b;
+  GemmDesc e{};
+  e.m = (nc > 0) ? ma : 0; e.n = nc; e.k = nc;
+  e.A = G + a0 + (long)c0 * W; e.lda = W;
+  e.B = T + c0 + (long)c0 * W; e.ldb = W;
+  e.C = X; e.ldc = b;
+  d1[idx] = e;
+  GemmDesc f{};
+  f.m = (nc > 0) ? ma : 0; f.n = nc; f.k = ma;
+  f.A = T + a0 + (long)a0 * W; f.lda = W;
+  f.B = X; f.ldb = b;
+  f.C = T + a0 + (long)c0 * W; f.ldc = W;
+  d2[idx] = f;
 }
 
 __global__ void zero_upper_panels_kernel(int n, int B_, double* Vst, long ldv) {
@@ -410,12 +426,21 @@ __global__ void zero_upper_panels_kernel(int n, int B_, double* Vst, long ldv) {
 
 static int npanel_of(int n, int B_) { return (n > B_) ? ceil_div(n - 1, B_) : 0; }
 
+namespace {
+constexpr int BT1_MAXSPLIT = 4;    // split-K slices of V^T Z
+constexpr int BT1_GCHUNK = 2048;   // k slice of the Gram products
+}  // namespace
+
 size_t bt1_scratch_doubles(int n, int B_, int m) {
   const size_t W = (size_t)GP * B_;
-  const size_t nsplit = ceil_div(n, 1024) + 1;
   const size_t ngroup = ceil_div(npanel_of(n, B_), GP) + 1;
-  // W, W2 (W x m), split-K partials (nsplit x W x m), Gram + partials, T of each group
-  return W * m * (2 + nsplit) + W * W * (1 + nsplit) + ngroup * W * W + 64;
+  const size_t gsplit = ceil_div(n, BT1_GCHUNK) + 1;
+  const size_t ndesc = ngroup * GP;
+  // V^T Z and T (V^T Z) (W x m each), split-K partials, the Gram of every
+  // group with the partials of one, T of every group, the pair products of
+  // one level, two descriptor arrays
+  return W * m * (2 + BT1_MAXSPLIT) + W * W * (2 * ngroup + gsplit) + ngroup * W * W / 2 +
+         2 * ndesc * (sizeof(GemmDesc) / sizeof(double) + 1) + 64;
 }
 
 hipError_t bt1_zero_fill(int n, int B_, double* Vst, long ldv, hipStream_t s) {
@@ -431,29 +456,41 @@ hipError_t bt1_apply(int n, int B_, const double* Vst, long ldv, const double* T
   const int np_all = npanel_of(n, B_);
   if (np_all == 0) return hipSuccess;
   const int W = GP * B_;
-  const size_t nsplit = ceil_div(n, 1024) + 1;
+  const int ngroup = ceil_div(np_all, GP);
+  const size_t gsplit = ceil_div(n, BT1_GCHUNK) + 1;
+  const size_t ndesc = (size_t)ngroup * GP;
   double* Wb = scratch;
   double* W2 = Wb + (size_t)W * m;
   double* part = W2 + (size_t)W * m;
-  double* Gm = part + nsplit * W * m;
-  double* Gpart = Gm + (size_t)W * W;
-  double* Tall = Gpart + nsplit * W * W;
-  const int ngroup = ceil_div(np_all, GP);
-  // T factors of the panel groups
+  double* Gall = part + (size_t)BT1_MAXSPLIT * W * m;
+  double* Tall = Gall + (size_t)ngroup * W * W;
+  double* Gpart = Tall + (size_t)ngroup * W * W;
+  double* Xall = Gpart + gsplit * W * W;
+  GemmDesc* d1 = reinterpret_cast<GemmDesc*>(Xall + (size_t)ngroup * W * W / 2);
+  GemmDesc* d2 = d1 + ndesc;
+  // Gram V_q^T V_q of every group (upper blocks are used)
   for (int q = 0; q < ngroup; q++) {
     const int p0 = q * GP, np = min(GP, np_all - p0);
+    if (np < 2) continue;
     const int r0 = (p0 + 1) * B_, h = n - r0, w = np * B_;
     const double* Vq = Vst + r0 + (long)p0 * B_ * ldv;
-    double* Tq = Tall + (size_t)q * W * W;
-    if (np > 1) {
-      GemmArgs g{};
-      g.m = w; g.n = w; g.k = h; g.A = Vq; g.lda = ldv; g.B = Vq; g.ldb = ldv; g.C = Gm; g.ldc = w;
-      g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
-      HSDM_TRY(gemm_splitk_launch(g, 1024, Gpart, s));
-    }
-    hipLaunchKernelGGL(group_t1_kernel, dim3(1), dim3(256), 0, s, np, B_,
-                       T1 + (size_t)p0 * B_ * B_, Gm, Tq);
+    GemmArgs g{};
+    g.m = w; g.n = w; g.k = h; g.A = Vq; g.lda = ldv; g.B = Vq; g.ldb = ldv;
+    g.C = Gall + (size_t)q * W * W; g.ldc = W;
+    g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
+    HSDM_TRY(gemm_splitk_launch(g, BT1_GCHUNK, Gpart, s));
+  }
+  // T of every group: panel T's on the diagonal, then the doubling levels
+  hipLaunchKernelGGL(group_t_init_kernel, dim3(1024), dim3(256), 0, s, ngroup, np_all, B_, T1,
+                     Tall);
+  HSDM_TRY(hipGetLastError());
+  for (int b = B_; b < W; b *= 2) {
+    const int cnt = ngroup * (W / (2 * b));
+    hipLaunchKernelGGL(group_t_desc_kernel, dim3(ceil_div(cnt, 64)), dim3(64), 0, s, ngroup,
+                       np_all, B_, b, Gall, Tall, Xall, d1, d2);
     HSDM_TRY(hipGetLastError());
+    HSDM_TRY(gemm_batched_dense_launch(d1, cnt, b, b, 1.0, 0.0, GF_KB_UPPER, s));
+    HSDM_TRY(gemm_batched_dense_launch(d2, cnt, b, b, -1.0, 0.0, GF_KA_UPPER, s));
   }
   for (int q = ngroup - 1; q >= 0; q--) {
     const int p0 = q * GP, np = min(GP, np_all - p0);
@@ -462,12 +499,16 @@ hipError_t bt1_apply(int n, int B_, const double* Vst, long ldv, const double* T
     const double* Vq = Vst + r0 + (long)p0 * B_ * ldv;
     const double* Tq = Tall + (size_t)q * W * W;
     double* Zq = Z + r0;
+    // V^T Z: split K so that the product fills the chip
+    const long tiles = (long)ceil_div(w, 128) * ceil_div(m, 128);
+    int nsp = (int)std::min<long>(BT1_MAXSPLIT, std::max<long>(1, ceil_div(512, (int)tiles)));
+    int kchunk = ceil_div(ceil_div(h, nsp), 16) * 16;
     GemmArgs g{};
     g.m = w; g.n = m; g.k = h; g.A = Vq; g.lda = ldv; g.B = Zq; g.ldb = ldz; g.C = Wb; g.ldc = w;
     g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.ndev = m_dev;
-    HSDM_TRY(gemm_splitk_launch(g, 1024, part, s));
+    HSDM_TRY(gemm_splitk_launch(g, kchunk, part, s));
     g = GemmArgs{};
-    g.m = w; g.n = m; g.k = w; g.A = Tq; g.lda = w; g.B = Wb; g.ldb = w; g.C = W2; g.ldc = w;
+    g.m = w; g.n = m; g.k = w; g.A = Tq; g.lda = W; g.B = Wb; g.ldb = w; g.C = W2; g.ldc = w;
     g.alpha = 1.0; g.beta = 0.0; g.flags = GF_KA_UPPER; g.ndev = m_dev;
     HSDM_TRY(gemm_launch(g, s));
     g = GemmArgs{};

@@ -532,3 +532,14 @@ hipError_t gemm_batched_launch(const GemmDesc* d_desc, int count, int max_m, int
   kt_end(s);
   return hipGetLastError();
 }
+
+hipError_t gemm_batched_dense_launch(const GemmDesc* d_desc, int count, int max_m, int max_n,
+                                     double alpha, double beta, int flags, hipStream_t s) {
+  if (count <= 0 || max_m <= 0 || max_n <= 0) return hipSuccess;
+  const int nblk = tile_grid(ceil_div(max_m, 64), ceil_div(max_n, 64));
+  kt_begin("gemm_batched_kernel<64, 64, 2, 2, 0, 0, 0>", 0.0, 0.0, 0, s);
+  hipLaunchKernelGGL((gemm_batched_kernel<64, 64, 2, 2, 0, 0, AM_DENSE>), dim3(nblk, count),
+                     dim3(256), 0, s, d_desc, alpha, beta, flags);
+  kt_end(s);
+  return hipGetLastError();
+}

@@ -57,6 +57,9 @@ hipError_t gemm_splitk_launch(const GemmArgs& g, int kchunk, double* part, hipSt
 hipError_t gemm_batched_launch(const GemmDesc* d_desc, int count, int max_m, int max_n,
                                double alpha, double beta, int ta, int tb, int flags,
                                hipStream_t s);
+// The same for plain operands (no gathered columns; acol and ccol unused).
+hipError_t gemm_batched_dense_launch(const GemmDesc* d_desc, int count, int max_m, int max_n,
+                                     double alpha, double beta, int flags, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Kernel timer (ktimer.hip): per-launch HIP events on the launching stream,

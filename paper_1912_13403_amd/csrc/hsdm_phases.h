@@ -42,7 +42,7 @@ hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff,
                      long ldz, int m, const int* m_dev, int* iscratch, DevStatusWord* st,
                      hipStream_t s);
 // Z (n x m) <- Q1 Z, the stage-1 panel reflectors (I - V T V^T), applied in
-// groups of 4 panels, last group first.  Vst must hold zeros above each
+// groups of 16 panels, last group first.  Vst must hold zeros above each
 // panel's first reflector row (bt1_zero_fill, before the reduction).
 size_t bt1_scratch_doubles(int n, int B, int m);
 hipError_t bt1_zero_fill(int n, int B, double* Vst, long ldv, hipStream_t s);
