@@ -2,20 +2,21 @@
 // density matrix q_ij = sum_l eps_l f_l c_il c_jl (Eq. 17) in one pass.
 //
 // Both are symmetric rank-m products of the same n x m eigenvector block C,
-// so one kernel computes the lower-triangular 64x64 tiles of both: the A
-// operand (rows of C) is staged once, the B operand (rows of C again) is
-// staged twice in LDS, scaled by f_l and by f_l eps_l on the way in, and two
-// sets of FP64 MFMA accumulators are kept per wavefront.  A tiled transpose
-// then completes the upper triangles.  m can be read from device memory (the
-// number of occupied states is only known on the device).
+// so one kernel computes the lower-triangular 128 x 128 tiles of both: a
+// workgroup of 16 wavefronts stages the A operand (rows of C) once and the B
+// operand (rows of C again) twice in LDS, scaled by f_l and by f_l eps_l on
+// the way in; wavefronts 0-7 accumulate the tile of D, 8-15 the tile of E
+// (64 x 32 each).  A tiled transpose then completes the upper triangles.  m
+// can be read from device memory (the number of occupied states is only
+// known on the device).
 #include "hsdm_internal.h"
 #include "hsdm_util.h"
 
 namespace {
 
-constexpr int NT = 256, BT = 64, BK = 16, LD = BT + 16;
+constexpr int NT = 1024, BT = 128, BK = 16, LD = BT + 16;
 
-__global__ __launch_bounds__(NT, 2) void dm_kernel(int n, int m_host, const int* m_dev,
+__global__ __launch_bounds__(NT) void dm_kernel(int n, int m_host, const int* m_dev,
                                                 const double* C, long ldc, const double* f,
                                                 const double* eps, double* D, long ldd,
                                                 double* E, long lde) {
@@ -23,43 +24,43 @@ __global__ __launch_bounds__(NT, 2) void dm_kernel(int n, int m_host, const int*
   if (tm < tn) return;
   const int m = m_dev ? *m_dev : m_host;
   __shared__ double As[2][BK * LD];
-  __shared__ double Bd[2][BK * LD];
-  __shared__ double Be[2][BK * LD];
+  __shared__ double Bs[2][2][BK * LD];  // [buffer][D or E]
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int which = wave >> 3;           // 0: D, 1: E
+  const int wm = wave & 1, wn = (wave >> 1) & 3;
   const int i0 = tm * BT, j0 = tn * BT;
-  const bool want_e = (E != nullptr);
+  const bool active = (which == 0) || (E != nullptr);
 
-  dbl4 accd[2][2], acce[2][2];
+  dbl4 acc[4][2];
 #pragma unroll
-  for (int a = 0; a < 2; a++)
+  for (int a = 0; a < 4; a++)
 #pragma unroll
-    for (int b = 0; b < 2; b++) {
-      accd[a][b] = dbl4{0, 0, 0, 0};
-      acce[a][b] = dbl4{0, 0, 0, 0};
-    }
-  // staging: thread t moves rows (t % 64) of the 64 x 16 slices, columns t/64 + 4q
-  double ra[4], rb[4], sf[4], se[4];
+    for (int b = 0; b < 2; b++) acc[a][b] = dbl4{0, 0, 0, 0};
+  // staging: thread t moves row t % 128 of the 128 x 16 slices, columns t / 128 and t / 128 + 8
+  double ra[2], rb[2], sf[2], se[2];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      const int kk = k0 + t / BT + 4 * q;
+    for (int q = 0; q < 2; q++) {
+      const int kk = k0 + t / BT + 8 * q;
       const int i = i0 + (t % BT), j = j0 + (t % BT);
       const bool kin = kk < m;
-      ra[q] = (kin && i < n) ? C[i + (long)kk * ldc] : 0.0;
-      rb[q] = (kin && j < n) ? C[j + (long)kk * ldc] : 0.0;
-      const double fk = kin ? f[kk] : 0.0;
-      sf[q] = fk;
-      se[q] = kin ? fk * eps[kk] : 0.0;
+      const int kc = kin ? kk : 0;
+      const double va = C[min(i, n - 1) + (long)kc * ldc];
+      const double vb = C[min(j, n - 1) + (long)kc * ldc];
+      ra[q] = (kin && i < n) ? va : 0.0;
+      rb[q] = (kin && j < n) ? vb : 0.0;
+      const double fk = f[kc], ek = eps[kc];
+      sf[q] = kin ? fk : 0.0;
+      se[q] = kin ? fk * ek : 0.0;
     }
   };
   auto store = [&](int b) {
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      const int r = t / BT + 4 * q, c = t % BT;
+    for (int q = 0; q < 2; q++) {
+      const int r = t / BT + 8 * q, c = t % BT;
       As[b][r * LD + c] = ra[q];
-      Bd[b][r * LD + c] = rb[q] * sf[q];
-      Be[b][r * LD + c] = rb[q] * se[q];
+      Bs[b][0][r * LD + c] = rb[q] * sf[q];
+      Bs[b][1][r * LD + c] = rb[q] * se[q];
     }
   };
   int buf = 0;
@@ -71,42 +72,42 @@ __global__ __launch_bounds__(NT, 2) void dm_kernel(int n, int m_host, const int*
   for (int k0 = 0; k0 < m; k0 += BK) {
     const bool more = k0 + BK < m;
     if (more) load(k0 + BK);
+    if (active) {
+      const double* as = As[buf];
+      const double* bs = Bs[buf][which];
 #pragma unroll
-    for (int ks = 0; ks < BK; ks += 4) {
-      const int kr = ks + (lane >> 4);
-      double fa[2], fd[2], fe[2];
+      for (int ks = 0; ks < BK; ks += 4) {
+        const int kr = ks + (lane >> 4);
+        double fa[4], fb[2];
 #pragma unroll
-      for (int a = 0; a < 2; a++) fa[a] = As[buf][kr * LD + wm * 32 + a * 16 + (lane & 15)];
+        for (int a = 0; a < 4; a++) fa[a] = as[kr * LD + wm * 64 + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int b = 0; b < 2; b++) {
-        fd[b] = Bd[buf][kr * LD + wn * 32 + b * 16 + (lane & 15)];
-        fe[b] = Be[buf][kr * LD + wn * 32 + b * 16 + (lane & 15)];
+        for (int b = 0; b < 2; b++) fb[b] = bs[kr * LD + wn * 32 + b * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+          for (int b = 0; b < 2; b++)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
       }
-#pragma unroll
-      for (int a = 0; a < 2; a++)
-#pragma unroll
-        for (int b = 0; b < 2; b++) {
-          accd[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fd[b], accd[a][b], 0, 0, 0);
-          if (want_e)
-            acce[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fe[b], acce[a][b], 0, 0, 0);
-        }
     }
     if (more) store(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
+  if (!active) return;
+  double* out = which ? E : D;
+  const long ldo = which ? lde : ldd;
 #pragma unroll
-  for (int a = 0; a < 2; a++)
+  for (int a = 0; a < 4; a++)
 #pragma unroll
     for (int b = 0; b < 2; b++) {
       const int col = j0 + wn * 32 + b * 16 + (lane & 15);
       if (col >= n) continue;
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        const int row = i0 + wm * 32 + a * 16 + (lane >> 4) + 4 * r;
+        const int row = i0 + wm * 64 + a * 16 + (lane >> 4) + 4 * r;
         if (row >= n || row < col) continue;
-        D[row + (long)col * ldd] = accd[a][b][r];
-        if (want_e) E[row + (long)col * lde] = acce[a][b][r];
+        out[row + (long)col * ldo] = acc[a][b][r];
       }
     }
 }
