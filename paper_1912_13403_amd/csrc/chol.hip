@@ -22,49 +22,73 @@ namespace {
 
 constexpr int LEAF = 64;
 
+HSDM_DEV double lane_value(double v, int lane) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)u, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// One wavefront factors and inverts a leaf of nb <= 64 columns.  Lane t
+// keeps row t of the factor in registers (right-looking: at step k the
+// column below the pivot is scaled and each later column j receives
+// -L[t][k] L[j][k], with L[j][k] read from lane j); entries above the
+// diagonal are computed along and discarded.  The inverse is formed by
+// forward substitution, lane c computing column c with the factor
+// broadcast from LDS.
 __global__ __launch_bounds__(64) void chol_leaf_kernel(int nb, double* A, long lda, double* Li,
                                                        long ldi, DevStatusWord* st, int col0) {
   __shared__ double L[LEAF][LEAF + 1];
-  __shared__ double X[LEAF][LEAF + 1];
-  const int t = threadIdx.x;  // thread t owns row t
-  for (int j = 0; j < nb; j++) L[t][j] = (t < nb && t >= j) ? A[t + (long)j * lda] : 0.0;
-  for (int j = nb; j < LEAF; j++) L[t][j] = 0.0;
-  __syncthreads();
+  const int t = threadIdx.x;
+  double row[LEAF];
+#pragma unroll
+  for (int j = 0; j < LEAF; j++) row[j] = (t < nb && j < nb && t >= j) ? A[t + (long)j * lda] : 0.0;
   bool ok = true;
-  for (int k = 0; k < nb; k++) {
-    const double piv = L[k][k];
-    if (!(piv > 0.0)) {
-      if (t == 0) dev_set_status(st, DS_NOT_SPD, col0 + k + 1);
-      ok = false;
-      break;
-    }
-    const double lkk = sqrt(piv);
-    __syncthreads();
-    if (t == k) L[k][k] = lkk;
-    if (t > k && t < nb) L[t][k] = L[t][k] / lkk;
-    __syncthreads();
-    if (t > k && t < nb) {
-      const double ltk = L[t][k];
-      for (int j = k + 1; j <= t; j++) L[t][j] -= ltk * L[j][k];
-    }
-    __syncthreads();
-  }
-  // inverse of the unit-free lower factor: thread c solves L x = e_c
-  if (ok && t < nb) {
-    const int c = t;
-    X[c][c] = 1.0 / L[c][c];
-    for (int i = c + 1; i < nb; i++) {
-      double s = 0.0;
-      for (int k = c; k < i; k++) s += L[i][k] * X[k][c];
-      X[i][c] = -s / L[i][i];
+#pragma unroll
+  for (int k = 0; k < LEAF; k++) {
+    if (k < nb && ok) {
+      const double piv = lane_value(row[k], k);
+      if (!(piv > 0.0)) {
+        if (t == 0) dev_set_status(st, DS_NOT_SPD, col0 + k + 1);
+        ok = false;
+      } else {
+        const double lkk = sqrt(piv), rl = 1.0 / lkk;
+        row[k] = (t == k) ? lkk : ((t > k) ? row[k] * rl : 0.0);
+        const double ltk = row[k];
+#pragma unroll
+        for (int j = k + 1; j < LEAF; j++) row[j] -= ltk * lane_value(row[k], j);
+      }
     }
   }
+  // the factor (lower triangle) to LDS and to A
+#pragma unroll
+  for (int j = 0; j < LEAF; j++) {
+    const double v = (t >= j && t < nb && j < nb) ? row[j] : 0.0;
+    L[t][j] = v;
+    if (t < nb && j < nb) A[t + (long)j * lda] = v;
+  }
+  __syncthreads();
+  // column c = t of the inverse: L x = e_c
+  double x[LEAF];
+#pragma unroll
+  for (int i = 0; i < LEAF; i++) {
+    double s = (i == t) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < i; k++) s -= L[i][k] * x[k];
+    x[i] = (i < nb) ? s / L[i][i] : 0.0;
+  }
+  // transpose through LDS so that each store instruction writes a column
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < LEAF; j++) L[j][t] = x[j];
   __syncthreads();
   if (t < nb) {
-    for (int j = 0; j < nb; j++) {
-      const bool low = t >= j;
-      A[t + (long)j * lda] = low ? L[t][j] : 0.0;
-      Li[t + (long)j * ldi] = (low && ok) ? X[t][j] : (low ? NAN : 0.0);
+#pragma unroll
+    for (int j = 0; j < LEAF; j++) {
+      if (j < nb) {
+        const bool low = t >= j;
+        Li[t + (long)j * ldi] = (low && ok) ? L[t][j] : (low ? NAN : 0.0);
+      }
     }
   }
 }
