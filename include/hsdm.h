@@ -54,7 +54,9 @@ enum hsdm_key {
   HSDM_KEY_FCUT = 2,       /* real: states with f <= fcut * fmax get no eigenvector (f is below it); default 1e-16 */
   HSDM_KEY_DEG_TOL = 3,    /* real: kT = 0 degeneracy window; < 0 selects 1e-12 * ||H||_1 (default) */
   HSDM_KEY_TIMING = 4      /* int: 1 records per-phase times (hsdm_phase_times); 2 also times every
-                              launch of the main kernels of a solve (hsdm_kernel_stat); 0 off (default) */
+                              launch of the main kernels of a solve (hsdm_kernel_stat); 3 times only
+                              the kernels launched once per solve (no event overhead on the many
+                              small launches); 0 off (default) */
 };
 
 /* Create a handle bound to HIP device `device` (~ elsi_init, Sec. 2.1). */
@@ -135,7 +137,7 @@ int hsdm_status_detail(hsdm_handle h);
 int hsdm_phase_times(hsdm_handle h, double *times, int cap);
 const char *hsdm_phase_name(int i);
 
-/* Per-kernel totals of the last solve when HSDM_KEY_TIMING is 2 (HIP events
+/* Per-kernel totals of the last solve when HSDM_KEY_TIMING is 2 or 3 (HIP events
  * recorded around each launch on the solve's stream; the solve synchronizes
  * before they are read).  hsdm_kernel_count returns the number of kernels
  * seen so far by this handle; hsdm_kernel_stat returns the name of kernel i

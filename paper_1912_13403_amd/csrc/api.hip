@@ -370,9 +370,10 @@ int hsdm_set_real(hsdm_handle h, int key, double v) {
 int hsdm_set_int(hsdm_handle h, int key, long v) {
   if (!h) return -1;
   if (key == HSDM_KEY_TIMING) {
-    if (v < 0 || v > 2) return -3;
+    if (v < 0 || v > 3) return -3;
     h->timing = (v != 0);
-    h->ktiming = (v == 2);
+    h->ktiming = (v >= 2);
+    kt_set_whole_only(h->kt, v == 3);
     return HSDM_OK;
   }
   return -2;

@@ -346,7 +346,7 @@ hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff,
   // algorithmic: per group and column of Z, V^T z (B^2 multiply-adds on the
   // parallelogram), T w (B(B+1)/2) and z - V w (B^2)
   const double fl = 2.0 * (double)L.ngroups * (2.0 * B * B + 0.5 * B * (B + 1)) * m;
-  kt_begin("bt2_strip_kernel", fl, 0.0, m_dev ? m : 0, s);
+  kt_begin("bt2_strip_kernel", fl, 0.0, m_dev ? m : 0, s, true);
   hipLaunchKernelGGL(bt2_strip_kernel, dim3(nstrip * NSPLIT), dim3(64 * PW), 0, s, n, nblk, R,
                      nstrip, F2, d_goff, Z, ldz, m, m_dev, iscratch, st);
   kt_end(s);

@@ -71,7 +71,10 @@ void kt_activate(KTimer* k);
 void kt_reset(KTimer* k);
 // flops / bytes: algorithmic work of this launch; nbound > 0 marks work that
 // scales with a device-side count (the occupied states) bounded by nbound.
-void kt_begin(const char* name, double flops, double bytes, int nbound, hipStream_t s);
+void kt_begin(const char* name, double flops, double bytes, int nbound, hipStream_t s,
+              bool whole_phase = false);
+// Restrict a timer to the launches marked whole_phase (one launch per solve).
+void kt_set_whole_only(KTimer* k, bool on);
 void kt_end(hipStream_t s);
 // After the stream is synchronized: fold records into per-kernel totals (m =
 // the device-side count for records with nbound > 0, < 0 if unknown).

@@ -1,7 +1,9 @@
 // Per-launch timing of the main kernels with HIP events recorded on the
 // stream each kernel is launched on.  A solve activates the handle's timer
 // for the calling thread; launchers bracket their kernel with kt_begin /
-// kt_end, which do nothing while no timer is active.  After the stream has
+// kt_end, which do nothing while no timer is active.  A timer restricted to
+// whole-phase kernels (one launch per solve) records only those, so that
+// the thousands of small launches of a solve carry no event overhead.  After the stream has
 // been synchronized the records are folded into per-kernel totals of time,
 // algorithmic flops and algorithmic bytes.
 #include <map>
@@ -24,6 +26,8 @@ struct KTimer {
   std::vector<hipEvent_t> pool;
   std::vector<double> ms, flops, bytes;
   std::vector<long> launches;
+  bool whole_only = false;  // record only launches marked whole-phase
+  bool pending = false;     // the last kt_begin recorded an event
 };
 
 namespace {
@@ -52,6 +56,10 @@ void kt_destroy(KTimer* k) {
 
 void kt_activate(KTimer* k) { kt_cur = k; }
 
+void kt_set_whole_only(KTimer* k, bool on) {
+  if (k) k->whole_only = on;
+}
+
 void kt_reset(KTimer* k) {
   if (!k) return;
   for (KtRec& r : k->recs) {
@@ -65,9 +73,12 @@ void kt_reset(KTimer* k) {
   std::fill(k->launches.begin(), k->launches.end(), 0L);
 }
 
-void kt_begin(const char* name, double flops, double bytes, int nbound, hipStream_t s) {
+void kt_begin(const char* name, double flops, double bytes, int nbound, hipStream_t s,
+              bool whole_phase) {
   KTimer* k = kt_cur;
   if (!k) return;
+  k->pending = false;
+  if (k->whole_only && !whole_phase) return;
   auto it = k->ids.find(name);
   int id;
   if (it == k->ids.end()) {
@@ -84,11 +95,13 @@ void kt_begin(const char* name, double flops, double bytes, int nbound, hipStrea
   KtRec r{id, flops, bytes, nbound, take_event(k), nullptr};
   if (r.e0) (void)hipEventRecord(r.e0, s);
   k->recs.push_back(r);
+  k->pending = true;
 }
 
 void kt_end(hipStream_t s) {
   KTimer* k = kt_cur;
-  if (!k || k->recs.empty()) return;
+  if (!k || !k->pending || k->recs.empty()) return;
+  k->pending = false;
   KtRec& r = k->recs.back();
   r.e1 = take_event(k);
   if (r.e1) (void)hipEventRecord(r.e1, s);

@@ -479,7 +479,7 @@ hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, doub
     // algorithmic: about 6 B n^2 flops; each task reads and writes the lower
     // half of its diagonal block and the block below (24 B^2 bytes), n^2 / 2B tasks
     const double nn = (double)n * n;
-    kt_begin("sb2st_kernel<32>", 6.0 * L.B * nn, 12.0 * L.B * nn, 0, s);
+    kt_begin("sb2st_kernel<32>", 6.0 * L.B * nn, 12.0 * L.B * nn, 0, s, true);
     HSDM_TRY(hipLaunchCooperativeKernel((const void*)sb2st_kernel<32>, dim3(nwg), dim3(64 * WPB),
                                         args, 0, s));
     kt_end(s);
