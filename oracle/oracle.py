@@ -219,3 +219,49 @@ def solve_dm(H, S, n_electrons, kT, f_max=2.0, deg_tol=None):
     if st:
         raise OracleError(st, col.value)
     return dict(eval=w, C=C, f=f, D=D, E=E, mu=mu.value, band_energy=eb.value)
+
+
+# ---- complex Hermitian problems (Eq. (13) unit tasks) ----------------------------
+#
+# A Hermitian pencil (H, S) is solved through its real symmetric embedding
+# [[Re A, -Im A], [Im A, Re A]] (2n x 2n).  The embedded pencil has the same
+# eigenvalues, each twice: u = x + i y with H u = eps S u maps to the two real
+# eigenvectors [x; y] and [-y; x].  With one occupation per real eigenpair and
+# twice the electron count, the real density matrix D_R holds
+# D = D_R[:n, :n] + i D_R[n:, :n], because the pair contributes
+# (x x^T + y y^T) = Re(u u^H) to the upper left block and (y x^T - x y^T) =
+# Im(u u^H) to the lower left block.  No complex arithmetic is needed, so this
+# route shares nothing with a complex eigensolver.  Parity pins: closed forms
+# of a ring threaded by a flux and of a chain in a random gauge, LAPACK's
+# Hermitian generalized solver, the congruence law and the density-matrix
+# invariants (tests/test_oracle_pins.py).
+
+
+def hermitian_embedding(A):
+    """[[Re A, -Im A], [Im A, Re A]] of the Hermitian matrix whose lower
+    triangle A holds (the imaginary parts of the diagonal are ignored)."""
+    A = np.asarray(A)
+    n = A.shape[0]
+    lo = np.tril(A, -1)
+    Ah = lo + lo.conj().T + np.diag(np.real(np.diag(A)))
+    R = np.zeros((2 * n, 2 * n), order="F")
+    R[:n, :n] = Ah.real
+    R[n:, n:] = Ah.real
+    R[n:, :n] = Ah.imag
+    R[:n, n:] = -Ah.imag
+    return R
+
+
+def solve_dm_complex(H, S, n_electrons, kT, f_max=1.0, deg_tol=None):
+    """Density matrix route for a Hermitian pencil (Eqs. (3), (4), (17)):
+    dict(eval, f, D, E, mu, band_energy) with complex D and E."""
+    n = np.asarray(H).shape[0]
+    R, SR = hermitian_embedding(H), hermitian_embedding(S)
+    if deg_tol is None:
+        deg_tol = default_deg_tol(R)
+    r = solve_dm(R, SR, 2.0 * n_electrons, kT, f_max=f_max, deg_tol=deg_tol)
+    D = r["D"][:n, :n] + 1j * r["D"][n:, :n]
+    E = r["E"][:n, :n] + 1j * r["E"][n:, :n]
+    ev = 0.5 * (r["eval"][0::2] + r["eval"][1::2])
+    f = 0.5 * (r["f"][0::2] + r["f"][1::2])
+    return dict(eval=ev, f=f, D=D, E=E, mu=r["mu"], band_energy=0.5 * r["band_energy"])

@@ -85,3 +85,92 @@ def ring(n, t=-1.0):
         H[0, n - 1] = t
         H[n - 1, 0] = t
     return H, S
+
+
+# ---- complex Hermitian problems (periodic, spin-polarized systems) ---------------
+#
+# One unit task of Eq. (13): H_k^a C = S_k C eps for k-point k and spin a.
+# Recipe of the batched periodic system (seed list [3, 1912, 13403, kindex]):
+#   k on a Gamma-centred 4 x 4 x 2 grid (fractions of the reciprocal vectors),
+#   lattice vectors R in {x, y, z};  size n_k ~ U{600..3000} per k-point;
+#   H0 real symmetric as in the real recipe (decay 32);  three banded complex
+#   H_R with Re, Im ~ N(0, 0.05^2) * exp(-|i-j|/32), zero beyond |i-j| > 64;
+#   H_k = H0 + sum_R (e^{i k.R} H_R + e^{-i k.R} H_R^H) / 2  (Hermitian);
+#   spin a = +-1:  H_k^a = H_k + a * 0.05 diag(m),  m_i ~ U(0, 1);
+#   S0 = I + 0.1 B B^T / n;  S_R banded complex, scaled to ||S_R||_1 = ||S_R||_inf
+#   = 0.1 so that lambda_min(S_k) >= 0.7;  S_k formed like H_k.
+# The electron count of the whole system is 0.4 * sum_k n_k with f_max = 1,
+# counted over all k-points and both spins; kT = 0.01.
+# Arrays are complex128, Fortran order.
+
+KGRID = (4, 4, 2)
+NKPT = KGRID[0] * KGRID[1] * KGRID[2]
+
+
+def kpoints():
+    """The 32 k-points of the grid as fractions (kx, ky, kz) of the reciprocal vectors."""
+    return [(i / KGRID[0], j / KGRID[1], l / KGRID[2])
+            for i in range(KGRID[0]) for j in range(KGRID[1]) for l in range(KGRID[2])]
+
+
+def kpoint_sizes(lo=600, hi=3000):
+    rng = np.random.default_rng([3, *SEED_TAIL])
+    return [int(v) for v in rng.integers(lo, hi + 1, NKPT)]
+
+
+def _banded_complex(rng, n, std, decay, width):
+    i = np.arange(n)
+    dist = np.abs(i[:, None] - i[None, :])
+    env = np.where(dist <= width, np.exp(-dist / float(decay)), 0.0)
+    return (rng.normal(0.0, std, (n, n)) + 1j * rng.normal(0.0, std, (n, n))) * env
+
+
+def kpoint_problem(kindex, n=None):
+    """(H_up, H_down, S) of k-point `kindex` of the recipe above (size n_k unless
+    `n` is given, which keeps the recipe at another size)."""
+    k = kpoints()[kindex]
+    n = kpoint_sizes()[kindex] if n is None else int(n)
+    rng = np.random.default_rng([3, *SEED_TAIL, int(kindex)])
+    B = rng.standard_normal((n, n))
+    S0 = 0.1 * (B @ B.T) / n
+    S0 = 0.5 * (S0 + S0.T) + np.eye(n)
+    del B
+    G = rng.normal(0.0, 0.1, (n, n))
+    i = np.arange(n)
+    U = np.triu(G * np.exp(-np.abs(i[:, None] - i[None, :]) / 32.0), 1)
+    H0 = U + U.T
+    H0[np.diag_indices(n)] = -1.0 + 2.0 * rng.random(n)
+    del G, U
+    H = H0.astype(np.complex128)
+    S = S0.astype(np.complex128)
+    for axis in range(3):
+        ph = np.exp(2j * np.pi * k[axis])
+        HR = _banded_complex(rng, n, 0.05, 32.0, 64)
+        H += 0.5 * (ph * HR + np.conj(ph) * HR.conj().T)
+        SR = _banded_complex(rng, n, 1.0, 8.0, 16)
+        SR *= 0.1 / max(np.abs(SR).sum(axis=0).max(), np.abs(SR).sum(axis=1).max())
+        S += 0.5 * (ph * SR + np.conj(ph) * SR.conj().T)
+    m = rng.random(n)
+    Hu = H + np.diag(0.05 * m)
+    Hd = H - np.diag(0.05 * m)
+    return np.asfortranarray(Hu), np.asfortranarray(Hd), np.asfortranarray(S)
+
+
+def ring_flux(n, phi, t=-1.0):
+    """Periodic ring threaded by a uniform flux: every bond j -> j+1 (mod n)
+    carries the phase e^{i phi}, i.e. H[j+1, j] = t e^{i phi}; S = I."""
+    H = np.zeros((n, n), dtype=np.complex128, order="F")
+    for j in range(n):
+        H[(j + 1) % n, j] += t * np.exp(1j * phi)
+        H[j, (j + 1) % n] += t * np.exp(-1j * phi)
+    return H, np.eye(n, dtype=np.complex128, order="F")
+
+
+def gauge_chain(n, seed=0, t=-1.0):
+    """Open chain in a random gauge: H = U H_chain U^H with U = diag(e^{i theta_j}),
+    S = I.  Returns (H, S, theta)."""
+    theta = np.random.default_rng([int(seed), *SEED_TAIL]).uniform(-np.pi, np.pi, n)
+    Hc, _ = chain(n, t)
+    u = np.exp(1j * theta)
+    H = (u[:, None] * Hc) * np.conj(u)[None, :]
+    return np.asfortranarray(H), np.eye(n, dtype=np.complex128, order="F"), theta
