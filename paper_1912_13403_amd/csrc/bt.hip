@@ -84,7 +84,7 @@ __global__ void fill_i32_kernel(int* p, int cnt) {
   if (i < cnt) p[i] = 0;
 }
 
-constexpr int PW = 4;            // wavefronts per workgroup (one per SIMD)
+constexpr int PW = 8;            // wavefronts per workgroup (two per SIMD)
 constexpr int KEYM = 1 << 13;    // > tasks per sweep block
 constexpr int NFRAG = 60;        // A operands per group: 24 (V^T) + 12 (T) + 24 (-V)
 constexpr int VS = B + 2;        // LDS column stride of V (conflict-free operand reads)
@@ -103,7 +103,8 @@ struct SplitRanges {
   int lo[NSPLIT];
 };
 
-__global__ __launch_bounds__(64 * PW) void bt2_strip_kernel(int n, int nblk, SplitRanges R,
+// Held to 256 registers per lane so that two wavefronts share each SIMD.
+__global__ __launch_bounds__(64 * PW) __attribute__((amdgpu_waves_per_eu(2))) void bt2_strip_kernel(int n, int nblk, SplitRanges R,
                                                             int nstrip, const double* F2,
                                                             const long* goff, double* Z, long ldz,
                                                             int m_host, const int* m_dev,
