@@ -92,6 +92,30 @@ int hsdm_solve_dm_real(hsdm_handle h, int n, const double *H, int ldh, const dou
                        double n_electrons, double kT, double *D, int ldd, double *E, int lde,
                        double *eval, double *band_energy, double *mu, void *stream);
 
+/* Density matrices of a Hermitian pencil: the complex H_k, S_k of one unit
+ * task of Eq. (13) (a k-point and spin channel), through the complex solver
+ * interface of Sec. 2.1.  H, S, D and E are interleaved complex128 (real,
+ * imaginary), column-major, leading dimensions counted in complex elements;
+ * only the lower triangles of H and S are read, and the imaginary parts of
+ * their diagonals are taken as zero.  Occupations as in hsdm_solve_dm_real
+ * (f_max from HSDM_KEY_FMAX: 1 for one spin channel).
+ *   D[ldd * n]      device, complex, Hermitian density matrix, both triangles (out)
+ *   E[lde * n]      device, complex, energy-weighted density matrix (out), nullable
+ *   eval[n]         device, ascending eigenvalues (out), nullable
+ *   band_energy     HOST, sum_l f_l eps_l = Tr(D H) (out), nullable
+ *   mu              HOST, chemical potential (out), nullable
+ * Method: the real symmetric embedding [[Re A, -Im A], [Im A, Re A]] (size
+ * 2n) of H and S has every eigenvalue of the pencil twice; it is solved by the
+ * real path with one occupation per real eigenpair and 2 n_electrons, and D,
+ * E are read from the left half of the real results (D = D_R[:n, :n] +
+ * i D_R[n:, :n]).  Workspace: that of a real solve of size 2n plus
+ * 4 (2n)^2 doubles, allocated on the first call of each size.  The factor of
+ * S is cached per (S pointer, n, lds) as in the real path.  Status codes as
+ * hsdm_solve_dm_real. */
+int hsdm_solve_dm_complex(hsdm_handle h, int n, const void *H, int ldh, const void *S, int lds,
+                          double n_electrons, double kT, void *D, int ldd, void *E, int lde,
+                          double *eval, double *band_energy, double *mu, void *stream);
+
 /* ---- phase entry points (same conventions; used to test and compose) ---- */
 
 /* S = L L^T and L^{-1}; L and Linv written in full (zeros above the diagonal). */

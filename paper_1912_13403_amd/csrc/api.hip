@@ -80,9 +80,14 @@ struct hsdm_ctx {
   double *Lbuf, *Linv, *Abuf, *Vst, *Zbuf, *Cbuf, *T1, *tau1, *AB, *sy_scr, *dvec, *evec, *lam,
       *fvec, *V2, *tau2, *F2, *dc_scr, *bt1_scr, *colsum, *hnorm;
   int *dc_iscr, *progress;
-  // cached factor of S
-  const double* s_ptr = nullptr;
+  // embedded Hermitian pencils: R(H), R(S), D_R, E_R (2n x 2n each)
+  int cws_n = 0;
+  double* cws = nullptr;
+  double *HR, *SR, *DR, *ER;
+  // cached factor of S, keyed by the caller's S (pointer, n, ld, complex)
+  const void* s_ptr = nullptr;
   int s_n = 0, s_ld = 0;
+  bool s_cplx = false;
   bool s_valid = false;
   // phase timing
   hipEvent_t ev[NPHASE + 1] = {};
@@ -102,6 +107,37 @@ int fail_dev(hsdm_ctx* h, hipError_t e, const char* where) {
     hipError_t _e = (x);                             \
     if (_e != hipSuccess) return fail_dev(h, _e, #x); \
   } while (0)
+
+void free_cws(hsdm_ctx* h) {
+  if (h->cws) (void)hipFree(h->cws);
+  h->cws = nullptr;
+  h->cws_n = 0;
+}
+
+// Workspace of the Hermitian route for complex size n (the real workspace is
+// that of size 2n).  Zero-filled once, so the upper triangles of R(H) and R(S),
+// which nothing writes, hold zeros.
+int ensure_cws(hsdm_ctx* h, int n) {
+  if (h->cws_n == n && h->cws) return HSDM_OK;
+  free_cws(h);
+  const size_t q = (size_t)4 * n * n;
+  hipError_t e = hipMalloc(&h->cws, 4 * q * sizeof(double));
+  if (e != hipSuccess) {
+    h->cws = nullptr;
+    return fail_dev(h, e, "workspace allocation");
+  }
+  e = hipMemset(h->cws, 0, 4 * q * sizeof(double));
+  if (e != hipSuccess) {
+    free_cws(h);
+    return fail_dev(h, e, "workspace clear");
+  }
+  h->HR = h->cws;
+  h->SR = h->cws + q;
+  h->DR = h->cws + 2 * q;
+  h->ER = h->cws + 3 * q;
+  h->cws_n = n;
+  return HSDM_OK;
+}
 
 void free_ws(hsdm_ctx* h) {
   if (h->ws) (void)hipFree(h->ws);
@@ -224,15 +260,28 @@ int finish(hsdm_ctx* h, hipStream_t s) {
 
 bool bad_ld(int ld, int n) { return ld < (n > 1 ? n : 1); }
 
-// Cholesky + inverse of S into the cache (skipped when cached).
-int factor_s(hsdm_ctx* h, int n, const double* S, int lds, hipStream_t s) {
-  if (h->s_valid && h->s_ptr == S && h->s_n == n && h->s_ld == lds) return HSDM_OK;
+// Identity of the caller's S for the factor cache.
+struct SKey {
+  const void* p;
+  int n, ld;
+  bool cplx;
+};
+
+bool s_cached(const hsdm_ctx* h, const SKey& k) {
+  return h->s_valid && h->s_ptr == k.p && h->s_n == k.n && h->s_ld == k.ld && h->s_cplx == k.cplx;
+}
+
+// Cholesky + inverse of the real symmetric S (n x n, lower) into the cache,
+// skipped when the cache holds the factor of the S that `key` names.
+int factor_s(hsdm_ctx* h, int n, const double* S, int lds, const SKey& key, hipStream_t s) {
+  if (s_cached(h, key)) return HSDM_OK;
   DEV_TRY(h, dev_copy(S, lds, h->Lbuf, n, n, n, s));
   DEV_TRY(h, dev_fill(h->Linv, n, n, n, 0.0, s));
   DEV_TRY(h, chol_inv(n, h->Lbuf, n, h->Linv, n, h->Abuf, n, h->st, s));
-  h->s_ptr = S;
-  h->s_n = n;
-  h->s_ld = lds;
+  h->s_ptr = key.p;
+  h->s_n = key.n;
+  h->s_ld = key.ld;
+  h->s_cplx = key.cplx;
   h->s_valid = true;
   return HSDM_OK;
 }
@@ -332,6 +381,7 @@ int hsdm_finalize(hsdm_handle h) {
   if (!h) return -1;
   (void)hipSetDevice(h->device);
   free_ws(h);
+  free_cws(h);
   if (h->st) (void)hipFree(h->st);
   if (h->host) (void)hipHostFree(h->host);
   for (int i = 0; i <= NPHASE; i++)
@@ -587,6 +637,46 @@ int hsdm_density(hsdm_handle h, int n, int m, const double* C, int ldc, const do
   return finish(h, s);
 }
 
+// Density-matrix solve of the real pencil (H, S) of size n into D, E (both
+// triangles) and h->lam (eigenvalues), with the S factor cached under `key`.
+// The caller has checked the arguments and sized the workspace; the status
+// words are read by finish().
+static int dm_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S, int lds,
+                   const SKey& key, double ne, double kT, double* D, int ldd, double* E, int lde,
+                   hipStream_t s) {
+  int r;
+  for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
+  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  DEV_TRY(h, hipGetLastError());
+  mark(h, 0, s);
+  if ((r = factor_s(h, n, S, lds, key, s))) return r;
+  mark(h, 1, s);
+  if (h->deg_tol < 0.0) DEV_TRY(h, dev_norm1_sym(H, ldh, n, h->colsum, h->hnorm, s));
+  if ((r = standard_form(h, n, H, ldh, h->Linv, n, h->Abuf, n, s))) return r;
+  mark(h, 2, s);
+  if ((r = reduce(h, n, s, 3))) return r;
+  mark(h, 4, s);
+  OccHook hook{h, n, ne, kT};
+  const int* m_dev = &h->occ->m;
+  DEV_TRY(h, stedc_run(h->plan, h->dvec, h->evec, h->lam, h->Zbuf, n, h->dc_scr, h->dc_iscr,
+                       m_dev, occ_hook, &hook, h->st, s));
+  mark(h, 5, s);
+  DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
+  DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, n, m_dev, h->progress, h->st, s));
+  mark(h, 6, s);
+  DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, n, m_dev, h->bt1_scr, s));
+  mark(h, 7, s);
+  GemmArgs g{};
+  g.m = n; g.n = n; g.k = n; g.A = h->Linv; g.lda = n; g.B = h->Zbuf; g.ldb = n; g.C = h->Cbuf;
+  g.ldc = n; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.flags = GF_KA_UPPER;
+  g.ndev = m_dev;
+  DEV_TRY(h, gemm_launch(g, s));
+  mark(h, 8, s);
+  DEV_TRY(h, density_launch(n, n, h->Cbuf, n, h->fvec, h->lam, D, ldd, E, lde, m_dev, s));
+  mark(h, 9, s);
+  return HSDM_OK;
+}
+
 static int check_hs(hsdm_handle h, int n, const double* H, int ldh, const double* S, int lds) {
   if (!h) return -1;
   if (n < 1) return -2;
@@ -614,7 +704,7 @@ int hsdm_solve_ev_real(hsdm_handle h, int n, const double* H, int ldh, const dou
   hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
   mark(h, 0, s);
-  if ((r = factor_s(h, n, S, lds, s))) return r;
+  if ((r = factor_s(h, n, S, lds, SKey{S, n, lds, false}, s))) return r;
   mark(h, 1, s);
   if ((r = standard_form(h, n, H, ldh, h->Linv, n, h->Abuf, n, s))) return r;
   mark(h, 2, s);
@@ -653,42 +743,53 @@ int hsdm_solve_dm_real(hsdm_handle h, int n, const double* H, int ldh, const dou
   int r = ensure_ws(h, n);
   if (r) return r;
   KtScope kts(h);
-  for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
-  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
-  DEV_TRY(h, hipGetLastError());
-  mark(h, 0, s);
-  if ((r = factor_s(h, n, S, lds, s))) return r;
-  mark(h, 1, s);
-  if (h->deg_tol < 0.0) DEV_TRY(h, dev_norm1_sym(H, ldh, n, h->colsum, h->hnorm, s));
-  if ((r = standard_form(h, n, H, ldh, h->Linv, n, h->Abuf, n, s))) return r;
-  mark(h, 2, s);
-  if ((r = reduce(h, n, s, 3))) return r;
-  mark(h, 4, s);
-  OccHook hook{h, n, ne, kT};
-  const int* m_dev = &h->occ->m;
-  DEV_TRY(h, stedc_run(h->plan, h->dvec, h->evec, h->lam, h->Zbuf, n, h->dc_scr, h->dc_iscr,
-                       m_dev, occ_hook, &hook, h->st, s));
-  mark(h, 5, s);
-  DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
-  DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, n, m_dev, h->progress, h->st, s));
-  mark(h, 6, s);
-  DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, n, m_dev, h->bt1_scr, s));
-  mark(h, 7, s);
-  GemmArgs g{};
-  g.m = n; g.n = n; g.k = n; g.A = h->Linv; g.lda = n; g.B = h->Zbuf; g.ldb = n; g.C = h->Cbuf;
-  g.ldc = n; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.flags = GF_KA_UPPER;
-  g.ndev = m_dev;
-  DEV_TRY(h, gemm_launch(g, s));
-  mark(h, 8, s);
-  DEV_TRY(h, density_launch(n, n, h->Cbuf, n, h->fvec, h->lam, D, ldd, E, lde, m_dev, s));
-  mark(h, 9, s);
-  if (eval) {
+  r = dm_core(h, n, H, ldh, S, lds, SKey{S, n, lds, false}, ne, kT, D, ldd, E, lde, s);
+  if (eval && r == HSDM_OK) {
     hipLaunchKernelGGL(copy_vec_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, h->lam, eval, n);
     DEV_TRY(h, hipGetLastError());
   }
-  r = finish(h, s);
+  if (r == HSDM_OK) r = finish(h, s);
   if (mu) *mu = h->host->occ.mu;
   if (band_energy) *band_energy = h->host->occ.band_energy;
+  return r;
+}
+
+int hsdm_solve_dm_complex(hsdm_handle h, int n, const void* H, int ldh, const void* S, int lds,
+                          double ne, double kT, void* D, int ldd, void* E, int lde, double* eval,
+                          double* band_energy, double* mu, void* stream) {
+  if (!h) return -1;
+  if (n < 1) return -2;
+  if (!H) return -3;
+  if (bad_ld(ldh, n)) return -4;
+  if (!S) return -5;
+  if (bad_ld(lds, n)) return -6;
+  if (!(ne >= 0.0) || !std::isfinite(ne) || ne > h->fmax * n) return -7;
+  if (!(kT >= 0.0) || !std::isfinite(kT)) return -8;
+  if (!D) return -9;
+  if (bad_ld(ldd, n)) return -10;
+  if (E && bad_ld(lde, n)) return -12;
+  if (n > (1 << 30) / 2) return -2;
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  DEV_TRY(h, hipSetDevice(h->device));
+  const int n2 = 2 * n;
+  int r = ensure_ws(h, n2);
+  if (r) return r;
+  if ((r = ensure_cws(h, n))) return r;
+  KtScope kts(h);
+  const SKey key{S, n, lds, true};
+  if (!s_cached(h, key)) DEV_TRY(h, herm_embed(n, S, lds, h->SR, n2, s));
+  DEV_TRY(h, herm_embed(n, H, ldh, h->HR, n2, s));
+  r = dm_core(h, n2, h->HR, n2, h->SR, n2, key, 2.0 * ne, kT, h->DR, n2, E ? h->ER : nullptr, n2,
+              s);
+  if (r == HSDM_OK) {
+    DEV_TRY(h, herm_extract(n, h->DR, n2, D, ldd, s));
+    if (E) DEV_TRY(h, herm_extract(n, h->ER, n2, E, lde, s));
+    if (eval) DEV_TRY(h, herm_pair_eval(n, h->lam, eval, s));
+    r = finish(h, s);
+  }
+  if (mu) *mu = h->host->occ.mu;
+  if (band_energy) *band_energy = 0.5 * h->host->occ.band_energy;
   return r;
 }
 

@@ -63,3 +63,13 @@ typedef hipError_t (*StedcEigvalHook)(void* ctx, const double* lam, hipStream_t 
 hipError_t stedc_run(StedcPlan* p, const double* d, const double* e, double* lam, double* Z,
                      long ldz, double* scratch, int* iscratch, const int* m_dev,
                      StedcEigvalHook hook, void* hook_ctx, DevStatusWord* st, hipStream_t s);
+
+// herm.hip -- Hermitian pencils through the real embedding
+// R(A) = [[Re A, -Im A], [Im A, Re A]] (2n x 2n).  A and X are interleaved
+// complex (double2), column-major, leading dimensions in complex elements.
+// herm_embed writes the lower triangle of R(A) from the lower triangle of A;
+// herm_extract reads X = R[:n, :n] + i R[n:, :n]; herm_pair_eval averages the
+// embedded pencil's eigenvalue pairs (2l, 2l + 1) into eval[l].
+hipError_t herm_embed(int n, const void* A, long lda, double* R, long ldr, hipStream_t s);
+hipError_t herm_extract(int n, const double* R, long ldr, void* X, long ldx, hipStream_t s);
+hipError_t herm_pair_eval(int n, const double* lam2, double* eval, hipStream_t s);

@@ -35,7 +35,8 @@ HSDM_KEY_TIMING = 4
 
 EXPORTED = [
     "hsdm_init", "hsdm_finalize", "hsdm_reinit", "hsdm_set_real", "hsdm_set_int",
-    "hsdm_solve_ev_real", "hsdm_solve_dm_real", "hsdm_cholesky_inverse", "hsdm_standard_form",
+    "hsdm_solve_ev_real", "hsdm_solve_dm_real", "hsdm_solve_dm_complex", "hsdm_cholesky_inverse",
+    "hsdm_standard_form",
     "hsdm_tridiagonalize", "hsdm_tridiag_eigh", "hsdm_occupations", "hsdm_density",
     "hsdm_dgemm", "hsdm_status_string", "hsdm_last_error", "hsdm_status_detail",
     "hsdm_phase_times", "hsdm_phase_name", "hsdm_kernel_count", "hsdm_kernel_stat",
@@ -65,6 +66,8 @@ def load_library(path: str = LIB_PATH):
         "hsdm_solve_ev_real": ([_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _vp], _i),
         "hsdm_solve_dm_real": ([_vp, _i, _vp, _i, _vp, _i, _d, _d, _vp, _i, _vp, _i, _vp,
                                 ctypes.POINTER(_d), ctypes.POINTER(_d), _vp], _i),
+        "hsdm_solve_dm_complex": ([_vp, _i, _vp, _i, _vp, _i, _d, _d, _vp, _i, _vp, _i, _vp,
+                                   ctypes.POINTER(_d), ctypes.POINTER(_d), _vp], _i),
         "hsdm_cholesky_inverse": ([_vp, _i, _vp, _i, _vp, _i, _vp, _i, _vp], _i),
         "hsdm_standard_form": ([_vp, _i, _vp, _i, _vp, _i, _vp, _i, _vp], _i),
         "hsdm_tridiagonalize": ([_vp, _i, _vp, _i, _vp, _vp, _vp, _i, _vp], _i),
@@ -106,12 +109,24 @@ def _colmajor(x: torch.Tensor) -> torch.Tensor:
     return x.t().contiguous().t()
 
 
+def _colmajor_c(x: torch.Tensor) -> torch.Tensor:
+    if x.dtype != torch.complex128:
+        raise TypeError("complex128 tensors expected")
+    if x.dim() == 2 and x.stride(0) == 1 and x.stride(1) >= max(1, x.shape[0]):
+        return x
+    return x.t().contiguous().t()
+
+
 def _ld(x: torch.Tensor) -> int:
     return int(max(1, x.stride(1))) if x.dim() == 2 else int(max(1, x.shape[0]))
 
 
 def empty_colmajor(n: int, m: int, device) -> torch.Tensor:
     return torch.empty((m, n), dtype=torch.float64, device=device).t()
+
+
+def empty_colmajor_c(n: int, m: int, device) -> torch.Tensor:
+    return torch.empty((m, n), dtype=torch.complex128, device=device).t()
 
 
 def _stream_ptr(device) -> int:
@@ -207,6 +222,22 @@ class Handle:
         mu = ctypes.c_double(0.0)
         eb = ctypes.c_double(0.0)
         self._check(self._lib.hsdm_solve_dm_real(
+            self._h, n, H.data_ptr(), _ld(H), S.data_ptr(), _ld(S), float(n_electrons), float(kT),
+            D.data_ptr(), _ld(D), E.data_ptr() if E is not None else None,
+            _ld(E) if E is not None else n, w.data_ptr() if w is not None else None,
+            ctypes.byref(eb), ctypes.byref(mu), _stream_ptr(self.device)))
+        return dict(D=D, E=E, eval=w, mu=mu.value, band_energy=eb.value)
+
+    def hsdm_solve_dm_complex(self, H, S, n_electrons, kT, want_e=True, want_eval=True):
+        """Hermitian pencil (complex128 tensors; lower triangles read)."""
+        H, S = _colmajor_c(H), _colmajor_c(S)
+        n = H.shape[0]
+        D = empty_colmajor_c(n, n, self.device)
+        E = empty_colmajor_c(n, n, self.device) if want_e else None
+        w = torch.empty(n, dtype=torch.float64, device=self.device) if want_eval else None
+        mu = ctypes.c_double(0.0)
+        eb = ctypes.c_double(0.0)
+        self._check(self._lib.hsdm_solve_dm_complex(
             self._h, n, H.data_ptr(), _ld(H), S.data_ptr(), _ld(S), float(n_electrons), float(kT),
             D.data_ptr(), _ld(D), E.data_ptr() if E is not None else None,
             _ld(E) if E is not None else n, w.data_ptr() if w is not None else None,

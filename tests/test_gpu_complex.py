@@ -1,0 +1,160 @@
+"""Hermitian pencils through the C ABI (hsdm_solve_dm_complex) against the
+FP64 CPU oracle's Hermitian route, on the seeded k-point recipe, at sizes
+whose embedded pencils span several tiles with ragged tails; plus the flux
+ring's closed form, the real-valued special case and the factor cache.
+
+Tolerances (as for real pencils): |d eps| <= 1e-10 ||H||_1,
+||dD||_max <= 1e-9, ||dE||_max <= 1e-9 max(1, ||H||_1),
+|d E_band| <= 1e-10 ||H||_1 N_e; ||H||_1 is the largest column sum of |H_ij|."""
+import numpy as np
+import pytest
+
+from paper_1912_13403_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def h(torch_dev):
+    from paper_1912_13403_amd import hsdm
+    with hsdm.Handle(0) as handle:
+        handle.hsdm_set_real(hsdm.HSDM_KEY_FMAX, 1.0)
+        yield handle
+
+
+def _g(torch_dev, x):
+    torch, dev = torch_dev
+    return torch.from_numpy(np.asfortranarray(x)).to(dev)
+
+
+def _c(x):
+    return x.detach().cpu().numpy()
+
+
+def _herm(A):
+    lo = np.tril(A, -1)
+    return lo + lo.conj().T + np.diag(np.real(np.diag(A)))
+
+
+def _norm1(A):
+    return float(np.abs(_herm(A)).sum(axis=0).max())
+
+
+def _check(r, ref, H, ne):
+    scale = _norm1(H)
+    assert np.max(np.abs(_c(r["eval"]) - ref["eval"])) <= 1e-10 * scale
+    assert np.max(np.abs(_c(r["D"]) - ref["D"])) <= 1e-9
+    assert np.max(np.abs(_c(r["E"]) - ref["E"])) <= 1e-9 * max(1.0, scale)
+    assert abs(r["band_energy"] - ref["band_energy"]) <= 1e-10 * scale * max(ne, 1.0)
+    assert abs(r["mu"] - ref["mu"]) <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("n,kindex,spin,kT", [(1, 0, 0, 0.01), (37, 3, 0, 0.01),
+                                              (150, 9, 1, 0.0), (333, 17, 1, 0.01)])
+def test_kpoint_parity(oracle, torch_dev, h, n, kindex, spin, kT):
+    Hu, Hd, S = inputs.kpoint_problem(kindex, n=n)
+    H = Hu if spin == 0 else Hd
+    ne = float(max(1, round(0.2 * n)))
+    print(f"[complex parity] n={n} k={kindex} spin={spin} kT={kT}", flush=True)
+    h.hsdm_reinit()
+    r = h.hsdm_solve_dm_complex(_g(torch_dev, H), _g(torch_dev, S), ne, kT)
+    ref = oracle.solve_dm_complex(H, S, ne, kT, f_max=1.0)
+    _check(r, ref, H, ne)
+
+
+def test_full_size_kpoint_parity_and_invariants(oracle, torch_dev, h):
+    torch, dev = torch_dev
+    kindex = 0
+    n = inputs.kpoint_sizes()[kindex]
+    Hu, Hd, S = inputs.kpoint_problem(kindex)
+    ne, kT = 0.2 * n, 0.01
+    print(f"[complex full-size] n={n}", flush=True)
+    h.hsdm_reinit()
+    Hg, Sg = _g(torch_dev, Hu), _g(torch_dev, S)
+    r = h.hsdm_solve_dm_complex(Hg, Sg, ne, kT)
+    ref = oracle.solve_dm_complex(Hu, S, ne, kT, f_max=1.0)
+    _check(r, ref, Hu, ne)
+    # S E = H D and Tr(D S) = N_e, formed on the host in FP64
+    D, E = _c(r["D"]), _c(r["E"])
+    Hf, Sf = _herm(Hu), _herm(S)
+    assert np.max(np.abs(Sf @ E - Hf @ D)) <= 1e-10 * _norm1(Hu)
+    assert abs(np.trace(D @ Sf).real - ne) <= 1e-10 * ne
+    assert np.max(np.abs(D - D.conj().T)) <= 1e-12
+
+
+def test_flux_ring_closed_form_through_gpu(torch_dev, h):
+    n, phi, ne = 64, 0.37, 20
+    H, S = inputs.ring_flux(n, phi)
+    h.hsdm_reinit()
+    r = h.hsdm_solve_dm_complex(_g(torch_dev, H), _g(torch_dev, S), float(ne), 0.0)
+    th = 2.0 * np.pi * np.arange(n) / n
+    eps = -2.0 * np.cos(th - phi)
+    o = np.argsort(eps)
+    U = np.exp(1j * np.outer(np.arange(n), th[o])) / np.sqrt(n)
+    assert np.max(np.abs(_c(r["eval"]) - eps[o])) <= 1e-12
+    D = U[:, :ne] @ U[:, :ne].conj().T
+    assert np.max(np.abs(_c(r["D"]) - D)) <= 1e-11
+
+
+def test_real_valued_input_matches_real_solve(torch_dev, h):
+    from paper_1912_13403_amd import hsdm
+    n, ne, kT = 200, 90.0, 0.02
+    H, S = inputs.sized_problem(n, cfg=900)
+    h.hsdm_reinit()
+    rc = h.hsdm_solve_dm_complex(_g(torch_dev, H.astype(np.complex128)),
+                                 _g(torch_dev, S.astype(np.complex128)), ne, kT)
+    with hsdm.Handle(0) as hr:
+        hr.hsdm_set_real(hsdm.HSDM_KEY_FMAX, 1.0)
+        rr = hr.hsdm_solve_dm_real(_g(torch_dev, H), _g(torch_dev, S), ne, kT)
+    assert np.max(np.abs(_c(rc["D"]) - _c(rr["D"]))) <= 1e-11
+    assert np.max(np.abs(_c(rc["D"]).imag)) <= 1e-12
+    assert np.max(np.abs(_c(rc["eval"]) - _c(rr["eval"]))) <= 1e-11
+
+
+def test_complex_factor_cache_and_reinit(oracle, torch_dev, h):
+    n, ne, kT = 120, 24.0, 0.01
+    Hu, Hd, S = inputs.kpoint_problem(4, n=n)
+    _, _, S2 = inputs.kpoint_problem(5, n=n)
+    h.hsdm_reinit()
+    Sg = _g(torch_dev, S)
+    r1 = h.hsdm_solve_dm_complex(_g(torch_dev, Hu), Sg, ne, kT)
+    # same S buffer, the other spin channel: the factor is reused
+    r2 = h.hsdm_solve_dm_complex(_g(torch_dev, Hd), Sg, ne, kT)
+    ref2 = oracle.solve_dm_complex(Hd, S, ne, kT, f_max=1.0)
+    assert np.max(np.abs(_c(r2["D"]) - ref2["D"])) <= 1e-9
+    # S overwritten in place: reinit forgets the factor
+    Sg.copy_(_g(torch_dev, S2))
+    h.hsdm_reinit()
+    r3 = h.hsdm_solve_dm_complex(_g(torch_dev, Hu), Sg, ne, kT)
+    ref3 = oracle.solve_dm_complex(Hu, S2, ne, kT, f_max=1.0)
+    assert np.max(np.abs(_c(r3["D"]) - ref3["D"])) <= 1e-9
+    assert r1["band_energy"] != r3["band_energy"]
+
+
+def test_complex_argument_errors(torch_dev, h):
+    import ctypes
+    from paper_1912_13403_amd import hsdm
+    torch, dev = torch_dev
+    lib = hsdm.load_library()
+    n = 8
+    A = torch.zeros((n, n), dtype=torch.complex128, device=dev)
+    p = A.data_ptr()
+    eb, mu = ctypes.c_double(), ctypes.c_double()
+    call = lambda *a: lib.hsdm_solve_dm_complex(h._h, *a, None, ctypes.byref(eb), ctypes.byref(mu),
+                                                None)
+    assert call(0, p, n, p, n, 1.0, 0.0, p, n, None, n) == -2
+    assert call(n, None, n, p, n, 1.0, 0.0, p, n, None, n) == -3
+    assert call(n, p, n - 1, p, n, 1.0, 0.0, p, n, None, n) == -4
+    assert call(n, p, n, None, n, 1.0, 0.0, p, n, None, n) == -5
+    assert call(n, p, n, p, n, 9.0, 0.0, p, n, None, n) == -7   # > f_max n with f_max = 1
+    assert call(n, p, n, p, n, 1.0, -1.0, p, n, None, n) == -8
+    assert call(n, p, n, p, n, 1.0, 0.0, None, n, None, n) == -9
+    assert call(n, p, n, p, n, 1.0, 0.0, p, 3, None, n) == -10
