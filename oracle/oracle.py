@@ -265,3 +265,90 @@ def solve_dm_complex(H, S, n_electrons, kT, f_max=1.0, deg_tol=None):
     ev = 0.5 * (r["eval"][0::2] + r["eval"][1::2])
     f = 0.5 * (r["f"][0::2] + r["f"][1::2])
     return dict(eval=ev, f=f, D=D, E=E, mu=r["mu"], band_energy=0.5 * r["band_energy"])
+
+
+# ---- unit tasks sharing one chemical potential (Eq. (16)) -----------------------
+#
+# The eigenvalues of all k-point x spin tasks are coupled by
+# sum_p w_p sum_l f_pl = N_e.  kT > 0: bisection on that monotone sum, to
+# adjacent doubles, with the same overflow-safe Fermi-Dirac form as the C
+# oracle.  kT = 0: all (eps, w) pairs sorted by eps are filled in order; the
+# Fermi level is the first at which the weighted count f_max sum w reaches N_e,
+# and the states of all tasks within deg_tol of it share what is left equally
+# per unit weight (the kT -> 0+ limit).
+
+
+def _fermi(x, f_max):
+    out = np.empty_like(x)
+    pos = x >= 0
+    t = np.exp(-x[pos])
+    out[pos] = f_max * t / (1.0 + t)
+    out[~pos] = f_max / (1.0 + np.exp(x[~pos]))
+    return out
+
+
+def occupations_shared(eps_list, weights, n_electrons, kT, f_max=2.0, deg_tol=0.0):
+    """Occupations of several tasks with one mu: (list of f, mu)."""
+    eps_all = np.concatenate([np.asarray(e, dtype=np.float64) for e in eps_list])
+    w_all = np.concatenate([np.full(len(e), float(w)) for e, w in zip(eps_list, weights)])
+    if kT > 0.0:
+        lo, hi = eps_all.min() - 50.0 * kT - 1.0, eps_all.max() + 50.0 * kT + 1.0
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if mid <= lo or mid >= hi:
+                break
+            if np.sum(w_all * _fermi((eps_all - mid) / kT, f_max)) < n_electrons:
+                lo = mid
+            else:
+                hi = mid
+        mu = 0.5 * (lo + hi)
+        return [_fermi((np.asarray(e) - mu) / kT, f_max) for e in eps_list], mu
+    if n_electrons <= 0.0:
+        return [np.zeros(len(e)) for e in eps_list], float(eps_all.min())
+    order = np.argsort(eps_all, kind="stable")
+    cum = f_max * np.cumsum(w_all[order])
+    i = int(np.argmax(cum >= n_electrons - 1e-12 * f_max))
+    ef = eps_all[order[i]]
+    below = eps_all < ef - deg_tol
+    group = (eps_all >= ef - deg_tol) & (eps_all <= ef + deg_tol)
+    share = min((n_electrons - f_max * w_all[below].sum()) / w_all[group].sum(), f_max)
+    above = eps_all[eps_all > ef + deg_tol]
+    if share < f_max * (1.0 - 1e-15) or above.size == 0:
+        mu = float(ef)
+    else:
+        mu = 0.5 * (eps_all[eps_all <= ef + deg_tol].max() + above.min())
+    fl = []
+    for e in eps_list:
+        e = np.asarray(e)
+        fl.append(np.where(e < ef - deg_tol, f_max, np.where(e <= ef + deg_tol, share, 0.0)))
+    return fl, mu
+
+
+def solve_dm_batch(Hs, Ss, n_electrons, kT, weights=None, f_max=2.0, deg_tol=None):
+    """Tasks (real, or Hermitian through the embedding) with one chemical
+    potential: dict(D, E, eval, f lists; mu; band_energy = sum_p w_p sum f eps)."""
+    cplx = np.iscomplexobj(Hs[0])
+    weights = [1.0] * len(Hs) if weights is None else list(weights)
+    pencils = [(hermitian_embedding(H), hermitian_embedding(S)) if cplx else (_f(H), _f(S))
+               for H, S in zip(Hs, Ss)]
+    if deg_tol is None:
+        deg_tol = max(default_deg_tol(R) for R, _ in pencils)
+    pairs = [solve_ev(R, SR) for R, SR in pencils]
+    ne = 2.0 * n_electrons if cplx else n_electrons
+    fl, mu = occupations_shared([w for w, _ in pairs], weights, ne, kT, f_max, deg_tol)
+    Ds, Es, evs, fs = [], [], [], []
+    eb = 0.0
+    for (w, C), f, wt in zip(pairs, fl, weights):
+        D, E = density(C, f, w)
+        eb += wt * float(np.sum(f * w))
+        if cplx:
+            n = C.shape[0] // 2
+            D = D[:n, :n] + 1j * D[n:, :n]
+            E = E[:n, :n] + 1j * E[n:, :n]
+            w = 0.5 * (w[0::2] + w[1::2])
+            f = 0.5 * (f[0::2] + f[1::2])
+        Ds.append(D)
+        Es.append(E)
+        evs.append(w)
+        fs.append(f)
+    return dict(D=Ds, E=Es, eval=evs, f=fs, mu=mu, band_energy=(0.5 if cplx else 1.0) * eb)
