@@ -116,6 +116,36 @@ int hsdm_solve_dm_complex(hsdm_handle h, int n, const void *H, int ldh, const vo
                           double n_electrons, double kT, void *D, int ldd, void *E, int lde,
                           double *eval, double *band_energy, double *mu, void *stream);
 
+/* Density matrices of nprob unit tasks that share one chemical potential:
+ * the k-point x spin-channel problems of a periodic, spin-polarized system
+ * (Eq. (13), Sec. 2.3), whose occupations are fixed together by the electron
+ * count sum_p weight[p] sum_l f_pl = n_electrons (Eq. (16); a k-point's two
+ * spin channels are two tasks with the same weight).  All tasks are real
+ * (is_complex = 0: double) or all Hermitian (is_complex = 1: interleaved
+ * complex128, as in hsdm_solve_dm_complex).  The arrays n, H, ldh, S, lds,
+ * weight, D, ldd, E, lde are HOST arrays of nprob entries; H[p], S[p], D[p],
+ * E[p] are device pointers.
+ *   weight          nullable (all 1); entries > 0
+ *   E               nullable, or entries nullable
+ *   band_energy     HOST, sum_p weight[p] sum_l f_pl eps_pl (out), nullable
+ *   mu              HOST, the shared chemical potential (out), nullable
+ * kT > 0: Fermi-Dirac occupations, mu by bisection on the weighted count;
+ * kT = 0: the Fermi level is the lowest eigenvalue of all tasks at which
+ * f_max * sum weight reaches n_electrons, and the states of all tasks within
+ * the degeneracy window of it share the remainder equally per unit weight.
+ * Each task runs the path of the single solves (its factor of S cached per
+ * (S[p], n[p], lds[p]) in a task context owned by the handle and kept until
+ * hsdm_finalize; hsdm_reinit forgets every task's factor); the tridiagonal
+ * eigenvectors of all tasks are kept until the joint occupations are known,
+ * then each task back-transforms its occupied vectors.  Status codes as the
+ * single solves; argument k is reported as -k (n, H, ... arrays: -4 for a
+ * missing array or a bad n[p], -5 ... -15 for the entry of problem p). */
+int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int *n,
+                        const void *const *H, const int *ldh, const void *const *S,
+                        const int *lds, const double *weight, double n_electrons, double kT,
+                        void *const *D, const int *ldd, void *const *E, const int *lde,
+                        double *band_energy, double *mu, void *stream);
+
 /* ---- phase entry points (same conventions; used to test and compose) ---- */
 
 /* S = L L^T and L^{-1}; L and Linv written in full (zeros above the diagonal). */

@@ -80,6 +80,11 @@ struct hsdm_ctx {
   double *Lbuf, *Linv, *Abuf, *Vst, *Zbuf, *Cbuf, *T1, *tau1, *AB, *sy_scr, *dvec, *evec, *lam,
       *fvec, *V2, *tau2, *F2, *dc_scr, *bt1_scr, *colsum, *hnorm;
   int *dc_iscr, *progress;
+  // per-task contexts of hsdm_solve_dm_batch (workspace and S factor each)
+  std::vector<hsdm_ctx*> subs;
+  std::vector<OccTask> h_tasks;
+  OccTask* d_tasks = nullptr;
+  int d_tasks_cap = 0;
   // embedded Hermitian pencils: R(H), R(S), D_R, E_R (2n x 2n each)
   int cws_n = 0;
   double* cws = nullptr;
@@ -114,11 +119,12 @@ void free_cws(hsdm_ctx* h) {
   h->cws_n = 0;
 }
 
-// Workspace of the Hermitian route for complex size n (the real workspace is
-// that of size 2n).  Zero-filled once, so the upper triangles of R(H) and R(S),
+// Workspace of the Hermitian route for complex sizes up to n (the real
+// workspace is that of size 2n); a size-n' problem uses it with leading
+// dimension 2n'.  Zero-filled once, so the upper triangles of R(H) and R(S),
 // which nothing writes, hold zeros.
 int ensure_cws(hsdm_ctx* h, int n) {
-  if (h->cws_n == n && h->cws) return HSDM_OK;
+  if (h->cws_n >= n && h->cws) return HSDM_OK;
   free_cws(h);
   const size_t q = (size_t)4 * n * n;
   hipError_t e = hipMalloc(&h->cws, 4 * q * sizeof(double));
@@ -380,6 +386,9 @@ int hsdm_init(hsdm_handle* out, int device) {
 int hsdm_finalize(hsdm_handle h) {
   if (!h) return -1;
   (void)hipSetDevice(h->device);
+  for (hsdm_ctx* c : h->subs) hsdm_finalize(c);
+  h->subs.clear();
+  if (h->d_tasks) (void)hipFree(h->d_tasks);
   free_ws(h);
   free_cws(h);
   if (h->st) (void)hipFree(h->st);
@@ -393,6 +402,7 @@ int hsdm_finalize(hsdm_handle h) {
 
 int hsdm_reinit(hsdm_handle h) {
   if (!h) return -1;
+  for (hsdm_ctx* c : h->subs) hsdm_reinit(c);
   h->s_valid = false;
   h->s_ptr = nullptr;
   return HSDM_OK;
@@ -790,6 +800,139 @@ int hsdm_solve_dm_complex(hsdm_handle h, int n, const void* H, int ldh, const vo
   }
   if (mu) *mu = h->host->occ.mu;
   if (band_energy) *band_energy = 0.5 * h->host->occ.band_energy;
+  return r;
+}
+
+int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int* n,
+                        const void* const* H, const int* ldh, const void* const* S,
+                        const int* lds, const double* weight, double ne, double kT,
+                        void* const* D, const int* ldd, void* const* E, const int* lde,
+                        double* band_energy, double* mu, void* stream) {
+  if (!h) return -1;
+  if (nprob < 1) return -2;
+  if (is_complex != 0 && is_complex != 1) return -3;
+  if (!n || !H || !ldh || !S || !lds || !D || !ldd || (E && !lde)) return -4;
+  double cap = 0.0;
+  int nmax = 0;
+  for (int p = 0; p < nprob; p++) {
+    if (n[p] < 1 || (is_complex && n[p] > (1 << 29))) return -4;
+    if (!H[p]) return -5;
+    if (bad_ld(ldh[p], n[p])) return -6;
+    if (!S[p]) return -7;
+    if (bad_ld(lds[p], n[p])) return -8;
+    const double w = weight ? weight[p] : 1.0;
+    if (!(w > 0.0) || !std::isfinite(w)) return -9;
+    if (!D[p]) return -12;
+    if (bad_ld(ldd[p], n[p])) return -13;
+    if (E && E[p] && bad_ld(lde[p], n[p])) return -15;
+    cap += w * n[p];
+    nmax = n[p] > nmax ? n[p] : nmax;
+  }
+  if (!(ne >= 0.0) || !std::isfinite(ne) || ne > h->fmax * cap * (1.0 + 1e-15)) return -10;
+  if (!(kT >= 0.0) || !std::isfinite(kT)) return -11;
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  DEV_TRY(h, hipSetDevice(h->device));
+  while ((int)h->subs.size() < nprob) {
+    hsdm_ctx* c = nullptr;
+    const int r = hsdm_init(&c, h->device);
+    if (r) {
+      h->err = "task context allocation failed";
+      return r;
+    }
+    h->subs.push_back(c);
+  }
+  int r;
+  if (is_complex && (r = ensure_cws(h, nmax))) return r;
+  if (h->d_tasks_cap < nprob) {
+    if (h->d_tasks) (void)hipFree(h->d_tasks);
+    h->d_tasks = nullptr;
+    h->d_tasks_cap = 0;
+    DEV_TRY(h, hipMalloc(&h->d_tasks, sizeof(OccTask) * nprob));
+    h->d_tasks_cap = nprob;
+  }
+  KtScope kts(h);
+  for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
+  h->h_tasks.assign(nprob, OccTask{});
+  // 1. every task: factor, standard form, two-stage reduction, eigenpairs of
+  //    the tridiagonal (all of them: the occupations are not known yet)
+  for (int p = 0; p < nprob; p++) {
+    hsdm_ctx* c = h->subs[p];
+    c->fmax = h->fmax;
+    c->fcut_rel = h->fcut_rel;
+    c->deg_tol = h->deg_tol;
+    c->timing = false;
+    c->ktiming = false;
+    c->err.clear();
+    const int nr = is_complex ? 2 * n[p] : n[p];
+    if ((r = ensure_ws(c, nr))) {
+      h->err = c->err;
+      return r;
+    }
+    const SKey key{S[p], n[p], lds[p], is_complex != 0};
+    const double *Hr = (const double*)H[p], *Sr = (const double*)S[p];
+    int ldhr = ldh[p], ldsr = lds[p];
+    if (is_complex) {
+      if (!s_cached(c, key)) DEV_TRY(h, herm_embed(n[p], S[p], lds[p], h->SR, nr, s));
+      DEV_TRY(h, herm_embed(n[p], H[p], ldh[p], h->HR, nr, s));
+      Hr = h->HR;
+      Sr = h->SR;
+      ldhr = ldsr = nr;
+    }
+    hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, c->st, c->occ);
+    DEV_TRY(h, hipGetLastError());
+    if ((r = factor_s(c, nr, Sr, ldsr, key, s))) return r;
+    if (c->deg_tol < 0.0) DEV_TRY(h, dev_norm1_sym(Hr, ldhr, nr, c->colsum, c->hnorm, s));
+    if ((r = standard_form(c, nr, Hr, ldhr, c->Linv, nr, c->Abuf, nr, s))) return r;
+    if ((r = reduce(c, nr, s, 3))) return r;
+    DEV_TRY(h, stedc_run(c->plan, c->dvec, c->evec, c->lam, c->Zbuf, nr, c->dc_scr, c->dc_iscr,
+                         nullptr, nullptr, nullptr, c->st, s));
+    h->h_tasks[p] = OccTask{c->lam, c->fvec, c->occ, c->deg_tol < 0.0 ? c->hnorm : nullptr, nr,
+                            weight ? weight[p] : 1.0};
+  }
+  // 2. one chemical potential for all tasks (Eq. (16))
+  DEV_TRY(h, hipMemcpyAsync(h->d_tasks, h->h_tasks.data(), sizeof(OccTask) * nprob,
+                            hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  DEV_TRY(h, hipGetLastError());
+  DEV_TRY(h, occupations_joint_launch(nprob, h->d_tasks, h->fmax, is_complex ? 2.0 * ne : ne, kT,
+                                      h->deg_tol, h->fcut_rel * h->fmax, h->occ, h->st, s));
+  // 3. every task: back-transforms of its occupied vectors, D and E
+  for (int p = 0; p < nprob; p++) {
+    hsdm_ctx* c = h->subs[p];
+    const int nr = is_complex ? 2 * n[p] : n[p];
+    const int* m_dev = &c->occ->m;
+    DEV_TRY(h, bt2_prepare(c->lay, c->V2, c->tau2, c->F2, s));
+    DEV_TRY(h, bt2_apply(c->lay, c->F2, c->d_goff, c->Zbuf, nr, nr, m_dev, c->progress, c->st, s));
+    DEV_TRY(h, bt1_apply(nr, BAND, c->Vst, nr, c->T1, c->Zbuf, nr, nr, m_dev, c->bt1_scr, s));
+    GemmArgs g{};
+    g.m = nr; g.n = nr; g.k = nr; g.A = c->Linv; g.lda = nr; g.B = c->Zbuf; g.ldb = nr;
+    g.C = c->Cbuf; g.ldc = nr; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
+    g.flags = GF_KA_UPPER; g.ndev = m_dev;
+    DEV_TRY(h, gemm_launch(g, s));
+    void* Ep = (E && E[p]) ? E[p] : nullptr;
+    if (is_complex) {
+      DEV_TRY(h, density_launch(nr, nr, c->Cbuf, nr, c->fvec, c->lam, h->DR, nr,
+                                Ep ? h->ER : nullptr, nr, m_dev, s));
+      DEV_TRY(h, herm_extract(n[p], h->DR, nr, D[p], ldd[p], s));
+      if (Ep) DEV_TRY(h, herm_extract(n[p], h->ER, nr, Ep, lde[p], s));
+    } else {
+      DEV_TRY(h, density_launch(nr, nr, c->Cbuf, nr, c->fvec, c->lam, (double*)D[p], ldd[p],
+                                (double*)Ep, Ep ? lde[p] : nr, m_dev, s));
+    }
+  }
+  // status of every task, then of the joint occupations
+  for (int p = 0; p < nprob; p++) {
+    hsdm_ctx* c = h->subs[p];
+    if ((r = finish(c, s))) {
+      h->detail = c->detail;
+      h->err = "task " + std::to_string(p) + ": " + c->err;
+      return r;
+    }
+  }
+  r = finish(h, s);
+  if (mu) *mu = h->host->occ.mu;
+  if (band_energy) *band_energy = (is_complex ? 0.5 : 1.0) * h->host->occ.band_energy;
   return r;
 }
 

@@ -31,6 +31,26 @@ hipError_t occupations_launch(int n, const double* eps, double fmax, double ne, 
                               double deg_tol, const double* hnorm, double fcut, double* f,
                               OccOut* out, DevStatusWord* st, hipStream_t s);
 
+// One unit task of a joint occupation (Eq. (16)): its ascending eigenvalues,
+// its weight, where its occupations and summary go, and (for the automatic
+// degeneracy window) its ||H||_1.
+struct OccTask {
+  const double* eps;
+  double* f;
+  OccOut* out;
+  const double* hnorm;
+  int n;
+  double w;
+};
+// Occupations of nt tasks with one chemical potential fixed by
+// sum_p w_p sum_l f_pl = ne.  Each task's OccOut receives the shared mu, its own
+// sum_l f eps, sum_l f and m = #{f > fcut}; `total` receives mu,
+// sum_p w_p sum_l f eps and sum_p w_p sum_l f.  deg_tol < 0 takes
+// 1e-12 max_p ||H_p||_1.  `tasks` is a device array.
+hipError_t occupations_joint_launch(int nt, const OccTask* tasks, double fmax, double ne, double kT,
+                                    double deg_tol, double fcut, OccOut* total, DevStatusWord* st,
+                                    hipStream_t s);
+
 // dm.hip: D = C diag(f) C^T and (optionally) E = C diag(f eps) C^T from the
 // first m columns of C (n x m, ldc); both written in full.
 hipError_t density_launch(int n, int m, const double* C, long ldc, const double* f,

@@ -35,8 +35,8 @@ HSDM_KEY_TIMING = 4
 
 EXPORTED = [
     "hsdm_init", "hsdm_finalize", "hsdm_reinit", "hsdm_set_real", "hsdm_set_int",
-    "hsdm_solve_ev_real", "hsdm_solve_dm_real", "hsdm_solve_dm_complex", "hsdm_cholesky_inverse",
-    "hsdm_standard_form",
+    "hsdm_solve_ev_real", "hsdm_solve_dm_real", "hsdm_solve_dm_complex", "hsdm_solve_dm_batch",
+    "hsdm_cholesky_inverse", "hsdm_standard_form",
     "hsdm_tridiagonalize", "hsdm_tridiag_eigh", "hsdm_occupations", "hsdm_density",
     "hsdm_dgemm", "hsdm_status_string", "hsdm_last_error", "hsdm_status_detail",
     "hsdm_phase_times", "hsdm_phase_name", "hsdm_kernel_count", "hsdm_kernel_stat",
@@ -68,6 +68,8 @@ def load_library(path: str = LIB_PATH):
                                 ctypes.POINTER(_d), ctypes.POINTER(_d), _vp], _i),
         "hsdm_solve_dm_complex": ([_vp, _i, _vp, _i, _vp, _i, _d, _d, _vp, _i, _vp, _i, _vp,
                                    ctypes.POINTER(_d), ctypes.POINTER(_d), _vp], _i),
+        "hsdm_solve_dm_batch": ([_vp, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _vp, _vp,
+                                 _vp, _vp, ctypes.POINTER(_d), ctypes.POINTER(_d), _vp], _i),
         "hsdm_cholesky_inverse": ([_vp, _i, _vp, _i, _vp, _i, _vp, _i, _vp], _i),
         "hsdm_standard_form": ([_vp, _i, _vp, _i, _vp, _i, _vp, _i, _vp], _i),
         "hsdm_tridiagonalize": ([_vp, _i, _vp, _i, _vp, _vp, _vp, _i, _vp], _i),
@@ -243,6 +245,32 @@ class Handle:
             _ld(E) if E is not None else n, w.data_ptr() if w is not None else None,
             ctypes.byref(eb), ctypes.byref(mu), _stream_ptr(self.device)))
         return dict(D=D, E=E, eval=w, mu=mu.value, band_energy=eb.value)
+
+    def hsdm_solve_dm_batch(self, Hs, Ss, n_electrons, kT, weights=None, want_e=True):
+        """Unit tasks sharing one chemical potential: lists of float64 (real
+        tasks) or complex128 (Hermitian tasks) tensors."""
+        cplx = Hs[0].dtype == torch.complex128
+        conv = _colmajor_c if cplx else _colmajor
+        empty = empty_colmajor_c if cplx else empty_colmajor
+        Hs = [conv(x) for x in Hs]
+        Ss = [conv(x) for x in Ss]
+        k = len(Hs)
+        ns = [int(x.shape[0]) for x in Hs]
+        Ds = [empty(m, m, self.device) for m in ns]
+        Es = [empty(m, m, self.device) for m in ns] if want_e else None
+        I = ctypes.c_int * k
+        P = ctypes.c_void_p * k
+        w = (ctypes.c_double * k)(*weights) if weights is not None else None
+        mu = ctypes.c_double(0.0)
+        eb = ctypes.c_double(0.0)
+        self._check(self._lib.hsdm_solve_dm_batch(
+            self._h, k, int(cplx), I(*ns), P(*[x.data_ptr() for x in Hs]), I(*[_ld(x) for x in Hs]),
+            P(*[x.data_ptr() for x in Ss]), I(*[_ld(x) for x in Ss]), w, float(n_electrons),
+            float(kT), P(*[x.data_ptr() for x in Ds]), I(*[_ld(x) for x in Ds]),
+            P(*[x.data_ptr() for x in Es]) if Es is not None else None,
+            I(*[_ld(x) for x in Es]) if Es is not None else None,
+            ctypes.byref(eb), ctypes.byref(mu), _stream_ptr(self.device)))
+        return dict(D=Ds, E=Es, mu=mu.value, band_energy=eb.value)
 
     # ---- phases --------------------------------------------------------------
     def hsdm_cholesky_inverse(self, S):
