@@ -85,6 +85,11 @@ struct hsdm_ctx {
   std::vector<OccTask> h_tasks;
   OccTask* d_tasks = nullptr;
   int d_tasks_cap = 0;
+  std::vector<int> tag_m;  // occupied-state count of each task of the last batch
+  std::vector<Sb2stTask> h_sb;
+  std::vector<int> h_wgmap;
+  void* d_sb = nullptr;  // Sb2stTask[nprob] then the workgroup -> task map
+  size_t d_sb_bytes = 0;
   // embedded Hermitian pencils: R(H), R(S), D_R, E_R (2n x 2n each)
   int cws_n = 0;
   double* cws = nullptr;
@@ -233,7 +238,8 @@ int finish(hsdm_ctx* h, hipStream_t s) {
   DEV_TRY(h, hipMemcpyAsync(&h->host->occ, h->occ, sizeof(OccOut), hipMemcpyDeviceToHost, s));
   DEV_TRY(h, hipStreamSynchronize(s));
   if (h->ktiming) {
-    kt_collect(h->kt, h->host->occ.m);
+    kt_collect(h->kt, h->host->occ.m, h->tag_m.empty() ? nullptr : h->tag_m.data(),
+               (int)h->tag_m.size());
     kt_activate(nullptr);
   }
   if (h->timing) {
@@ -344,7 +350,10 @@ struct KtScope {
       kt_activate(h->kt);
     }
   }
-  ~KtScope() { kt_activate(nullptr); }
+  ~KtScope() {
+    kt_activate(nullptr);
+    kt_set_tag(-1);
+  }
 };
 
 }  // namespace
@@ -389,6 +398,7 @@ int hsdm_finalize(hsdm_handle h) {
   for (hsdm_ctx* c : h->subs) hsdm_finalize(c);
   h->subs.clear();
   if (h->d_tasks) (void)hipFree(h->d_tasks);
+  if (h->d_sb) (void)hipFree(h->d_sb);
   free_ws(h);
   free_cws(h);
   if (h->st) (void)hipFree(h->st);
@@ -884,11 +894,68 @@ int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int* n,
     if ((r = factor_s(c, nr, Sr, ldsr, key, s))) return r;
     if (c->deg_tol < 0.0) DEV_TRY(h, dev_norm1_sym(Hr, ldhr, nr, c->colsum, c->hnorm, s));
     if ((r = standard_form(c, nr, Hr, ldhr, c->Linv, nr, c->Abuf, nr, s))) return r;
-    if ((r = reduce(c, nr, s, 3))) return r;
-    DEV_TRY(h, stedc_run(c->plan, c->dvec, c->evec, c->lam, c->Zbuf, nr, c->dc_scr, c->dc_iscr,
-                         nullptr, nullptr, nullptr, c->st, s));
+    DEV_TRY(h, bt1_zero_fill(nr, BAND, c->Vst, nr, s));
+    DEV_TRY(h, sy2sb_run(nr, BAND, c->Abuf, nr, c->Vst, nr, c->tau1, c->T1, c->AB, 2 * BAND,
+                         c->sy_scr, c->st, s));
+    DEV_TRY(h, sb2st_prepare(c->lay, c->V2, c->tau2, c->progress, s));
     h->h_tasks[p] = OccTask{c->lam, c->fvec, c->occ, c->deg_tol < 0.0 ? c->hnorm : nullptr, nr,
                             weight ? weight[p] : 1.0};
+  }
+  // bulge chasing of all bands, as many per cooperative launch as fit: each
+  // band alone is latency-bound and fills a small part of the device
+  {
+    h->h_sb.assign(nprob, Sb2stTask{});
+    h->h_wgmap.clear();
+    std::vector<int> first(1, 0);  // first task of each launch
+    std::vector<double> fl(1, 0.0), by(1, 0.0);
+    int in_launch = 0;
+    for (int p = 0; p < nprob; p++) {
+      hsdm_ctx* c = h->subs[p];
+      const int w = sb2st_group_nwg(c->lay);
+      if (w > 0 && in_launch + w > SB2ST_MAX_WG) {
+        first.push_back(p);
+        fl.push_back(0.0);
+        by.push_back(0.0);
+        in_launch = 0;
+      }
+      h->h_sb[p] = Sb2stTask{c->AB, c->V2, c->tau2, c->d_goff, c->progress, c->st, c->lay.n,
+                             c->lay.nsweep, in_launch, w};
+      for (int q = 0; q < w; q++) h->h_wgmap.push_back(p);
+      in_launch += w;
+      const double nn = (double)c->lay.n * c->lay.n;
+      fl.back() += 6.0 * BAND * nn;
+      by.back() += 12.0 * BAND * nn;
+    }
+    first.push_back(nprob);
+    const size_t tb = sizeof(Sb2stTask) * nprob;
+    const size_t need = tb + sizeof(int) * (h->h_wgmap.size() + 1);
+    if (h->d_sb_bytes < need) {
+      if (h->d_sb) (void)hipFree(h->d_sb);
+      h->d_sb = nullptr;
+      h->d_sb_bytes = 0;
+      DEV_TRY(h, hipMalloc(&h->d_sb, need));
+      h->d_sb_bytes = need;
+    }
+    Sb2stTask* d_sb = (Sb2stTask*)h->d_sb;
+    int* d_map = (int*)((char*)h->d_sb + tb);
+    DEV_TRY(h, hipMemcpyAsync(d_sb, h->h_sb.data(), tb, hipMemcpyHostToDevice, s));
+    if (!h->h_wgmap.empty())
+      DEV_TRY(h, hipMemcpyAsync(d_map, h->h_wgmap.data(), sizeof(int) * h->h_wgmap.size(),
+                                hipMemcpyHostToDevice, s));
+    int off = 0;
+    for (size_t g = 0; g + 1 < first.size(); g++) {
+      int cnt = 0;
+      for (int p = first[g]; p < first[g + 1]; p++) cnt += h->h_sb[p].nwg;
+      DEV_TRY(h, sb2st_group_launch(d_sb, d_map + off, cnt, fl[g], by[g], s));
+      off += cnt;
+    }
+  }
+  for (int p = 0; p < nprob; p++) {
+    hsdm_ctx* c = h->subs[p];
+    const int nr = is_complex ? 2 * n[p] : n[p];
+    DEV_TRY(h, sb2st_finish(c->lay, c->AB, 2 * BAND, c->dvec, c->evec, s));
+    DEV_TRY(h, stedc_run(c->plan, c->dvec, c->evec, c->lam, c->Zbuf, nr, c->dc_scr, c->dc_iscr,
+                         nullptr, nullptr, nullptr, c->st, s));
   }
   // 2. one chemical potential for all tasks (Eq. (16))
   DEV_TRY(h, hipMemcpyAsync(h->d_tasks, h->h_tasks.data(), sizeof(OccTask) * nprob,
@@ -899,6 +966,7 @@ int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int* n,
                                       h->deg_tol, h->fcut_rel * h->fmax, h->occ, h->st, s));
   // 3. every task: back-transforms of its occupied vectors, D and E
   for (int p = 0; p < nprob; p++) {
+    kt_set_tag(p);
     hsdm_ctx* c = h->subs[p];
     const int nr = is_complex ? 2 * n[p] : n[p];
     const int* m_dev = &c->occ->m;
@@ -921,16 +989,21 @@ int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int* n,
                                 (double*)Ep, Ep ? lde[p] : nr, m_dev, s));
     }
   }
+  kt_set_tag(-1);
   // status of every task, then of the joint occupations
+  h->tag_m.assign(nprob, 0);
   for (int p = 0; p < nprob; p++) {
     hsdm_ctx* c = h->subs[p];
     if ((r = finish(c, s))) {
       h->detail = c->detail;
       h->err = "task " + std::to_string(p) + ": " + c->err;
+      h->tag_m.clear();
       return r;
     }
+    h->tag_m[p] = c->host->occ.m;
   }
   r = finish(h, s);
+  h->tag_m.clear();
   if (mu) *mu = h->host->occ.mu;
   if (band_energy) *band_energy = (is_complex ? 0.5 : 1.0) * h->host->occ.band_energy;
   return r;

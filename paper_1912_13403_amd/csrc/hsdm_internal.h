@@ -76,9 +76,13 @@ void kt_begin(const char* name, double flops, double bytes, int nbound, hipStrea
 // Restrict a timer to the launches marked whole_phase (one launch per solve).
 void kt_set_whole_only(KTimer* k, bool on);
 void kt_end(hipStream_t s);
+// Records made after kt_set_tag(t) carry tag t (-1: none); a solve of several
+// tasks tags each task's launches with its index.
+void kt_set_tag(int t);
 // After the stream is synchronized: fold records into per-kernel totals (m =
-// the device-side count for records with nbound > 0, < 0 if unknown).
-void kt_collect(KTimer* k, int m);
+// the device-side count for records with nbound > 0, < 0 if unknown; a record
+// with tag t < ntag uses tag_m[t] instead).
+void kt_collect(KTimer* k, int m, const int* tag_m = nullptr, int ntag = 0);
 int kt_count(const KTimer* k);
 const char* kt_stat(const KTimer* k, int i, double* out4);
 

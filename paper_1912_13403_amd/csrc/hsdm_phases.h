@@ -29,6 +29,29 @@ void sb2st_group_offsets(const Sb2stLayout& L, long* offs);
 hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, double* e, double* V2,
                      double* tau2, const long* d_goff, int* progress, DevStatusWord* st,
                      hipStream_t s);
+// The same, split for several bands chased in one cooperative launch:
+// sb2st_prepare (clears the reflector store and the sweep counters) for each
+// band, one sb2st_group_launch over bands whose workgroup counts
+// (sb2st_group_nwg each) add up to at most SB2ST_MAX_WG, then sb2st_finish
+// (reads d and e off the band) for each.  d_tasks and d_wg_task are device
+// arrays: one Sb2stTask per band and the task index of each workgroup.
+constexpr int SB2ST_MAX_WG = 256;  // one 8-wavefront workgroup per compute unit
+struct Sb2stTask {
+  double* AB;  // ldab = 2B
+  double* V2;
+  double* tau2;
+  const long* goff;
+  int* progress;
+  DevStatusWord* st;
+  int n, nsweep, wg0, nwg;
+};
+hipError_t sb2st_prepare(const Sb2stLayout& L, double* V2, double* tau2, int* progress,
+                         hipStream_t s);
+hipError_t sb2st_finish(const Sb2stLayout& L, const double* AB, int ldab, double* d, double* e,
+                        hipStream_t s);
+int sb2st_group_nwg(const Sb2stLayout& L);
+hipError_t sb2st_group_launch(const Sb2stTask* d_tasks, const int* d_wg_task, int total_wg,
+                              double flops, double bytes, hipStream_t s);
 
 // bt.hip -- back-transformations.
 // Z (n x m) <- Q2 Z.  bt2_prepare forms the T factor of every group and packs

@@ -17,6 +17,7 @@ struct KtRec {
   double flops, bytes;
   int nbound;  // > 0: work scales with a device-side count bounded by nbound
   hipEvent_t e0, e1;
+  int tag;
 };
 
 struct KTimer {
@@ -32,6 +33,7 @@ struct KTimer {
 
 namespace {
 thread_local KTimer* kt_cur = nullptr;
+thread_local int kt_tag = -1;
 
 hipEvent_t take_event(KTimer* k) {
   if (!k->pool.empty()) {
@@ -55,6 +57,8 @@ void kt_destroy(KTimer* k) {
 }
 
 void kt_activate(KTimer* k) { kt_cur = k; }
+
+void kt_set_tag(int t) { kt_tag = t; }
 
 void kt_set_whole_only(KTimer* k, bool on) {
   if (k) k->whole_only = on;
@@ -92,7 +96,7 @@ void kt_begin(const char* name, double flops, double bytes, int nbound, hipStrea
   } else {
     id = it->second;
   }
-  KtRec r{id, flops, bytes, nbound, take_event(k), nullptr};
+  KtRec r{id, flops, bytes, nbound, take_event(k), nullptr, kt_tag};
   if (r.e0) (void)hipEventRecord(r.e0, s);
   k->recs.push_back(r);
   k->pending = true;
@@ -107,12 +111,13 @@ void kt_end(hipStream_t s) {
   if (r.e1) (void)hipEventRecord(r.e1, s);
 }
 
-void kt_collect(KTimer* k, int m) {
+void kt_collect(KTimer* k, int m, const int* tag_m, int ntag) {
   if (!k) return;
   for (KtRec& r : k->recs) {
     float t = 0.f;
     if (r.e0 && r.e1 && hipEventElapsedTime(&t, r.e0, r.e1) == hipSuccess) k->ms[r.id] += t;
-    const double sc = (r.nbound > 0 && m >= 0) ? (double)m / r.nbound : 1.0;
+    const int mr = (tag_m && r.tag >= 0 && r.tag < ntag) ? tag_m[r.tag] : m;
+    const double sc = (r.nbound > 0 && mr >= 0) ? (double)mr / r.nbound : 1.0;
     k->flops[r.id] += r.flops * sc;
     k->bytes[r.id] += r.bytes * sc;
     k->launches[r.id] += 1;

@@ -200,11 +200,11 @@ HSDM_DEV void make_reflector(double alpha, double sig, double& beta, double& tau
 // and rank-two updates need no data from other lanes.  The reflector v is
 // kept in both index sets (rows I + 8a, columns J + 8b); one copy through LDS
 // per task turns the row form of the next reflector into the column form.
+// Workgroup wg of the nwg that chase the bulges of one band: wavefront w of
+// the workgroup takes sweeps wg * WPB + w, then that plus nwg * WPB, and so on.
 template <int B>
-__global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, double* AB, int ldab,
-                                                         double* V2, double* tau2,
-                                                         const long* goff, int* progress,
-                                                         DevStatusWord* st) {
+HSDM_DEV void sb2st_body(int n, int nsweep, double* AB, int ldab, double* V2, double* tau2,
+                         const long* goff, int* progress, DevStatusWord* st, int wg, int nwg) {
   static_assert(B == 32, "8 x 8 lanes, 4 x 4 elements each");
   __shared__ double vl_all[WPB][B];
   __shared__ int lprog[WPB];
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
   if (lane == 0) lprog[wv_id] = -1;
   __syncthreads();
   double* vl = vl_all[wv_id];
-  const int gw = blockIdx.x * WPB + wv_id, TW = gridDim.x * WPB;
+  const int gw = wg * WPB + wv_id, TW = nwg * WPB;
   const int I = lane >> 3, J = lane & 7;
   // Element (i, j), i >= j, of a block whose first row and column is r sits
   // at (i - j) + (r + j) LD = (r LD) + i + (LD - 1) j in the band storage.
@@ -413,6 +413,27 @@ __global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, doub
   }
 }
 
+template <int B>
+__global__ __launch_bounds__(64 * WPB) void sb2st_kernel(int n, int nsweep, double* AB, int ldab,
+                                                         double* V2, double* tau2,
+                                                         const long* goff, int* progress,
+                                                         DevStatusWord* st) {
+  sb2st_body<B>(n, nsweep, AB, ldab, V2, tau2, goff, progress, st, blockIdx.x, gridDim.x);
+}
+
+// Several bands in one cooperative launch: workgroups wg0 .. wg0 + nwg - 1 of
+// the grid chase the bulges of task p = wg_task[blockIdx.x], each task with
+// its own band, reflector store, counters and status word.  All workgroups of
+// the grid are resident together, as in the single-band launch.
+template <int B>
+__global__ __launch_bounds__(64 * WPB) void sb2st_group_kernel(const Sb2stTask* tasks,
+                                                               const int* wg_task) {
+  const int p = __builtin_amdgcn_readfirstlane(wg_task[blockIdx.x]);
+  const Sb2stTask& q = tasks[p];
+  sb2st_body<B>(q.n, q.nsweep, q.AB, 2 * B, q.V2, q.tau2, q.goff, q.progress, q.st,
+                (int)blockIdx.x - q.wg0, q.nwg);
+}
+
 __global__ void extract_tridiag_kernel(int n, const double* AB, int ldab, double* d, double* e) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -456,6 +477,49 @@ void sb2st_group_offsets(const Sb2stLayout& L, long* offs) {
   offs[L.nblk] = g;
 }
 
+hipError_t sb2st_prepare(const Sb2stLayout& L, double* V2, double* tau2, int* progress,
+                         hipStream_t s) {
+  if (L.nsweep <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_dbl_kernel, dim3(4096), dim3(256), 0, s, V2, L.v2_doubles);
+  HSDM_TRY(hipGetLastError());
+  hipLaunchKernelGGL(fill_dbl_kernel, dim3(1024), dim3(256), 0, s, tau2, L.ngroups * L.B);
+  HSDM_TRY(hipGetLastError());
+  hipLaunchKernelGGL(fill_int_kernel, dim3(ceil_div(L.nsweep, 256)), dim3(256), 0, s, progress,
+                     (long)L.nsweep, 0);
+  return hipGetLastError();
+}
+
+hipError_t sb2st_finish(const Sb2stLayout& L, const double* AB, int ldab, double* d, double* e,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(extract_tridiag_kernel, dim3(ceil_div(L.n, 256)), dim3(256), 0, s, L.n, AB,
+                     ldab, d, e);
+  return hipGetLastError();
+}
+
+int sb2st_group_nwg(const Sb2stLayout& L) {
+  if (L.nsweep <= 0) return 0;
+  // A sweep trails its predecessor by two tasks, so the wavefront that
+  // finished sweep s (about (n - s) / B tasks) is needed again for sweep
+  // s + TW no earlier than 2 TW tasks later: TW >= n / 2B wavefronts keep the
+  // pipeline from waiting for a free wavefront.
+  int need = ceil_div(ceil_div(L.n, 2 * L.B), WPB) + 1;
+  if (need > SB2ST_MAX_WG) need = SB2ST_MAX_WG;
+  const int all = ceil_div(L.nsweep, WPB);
+  return need < all ? need : all;
+}
+
+hipError_t sb2st_group_launch(const Sb2stTask* d_tasks, const int* d_wg_task, int total_wg,
+                              double flops, double bytes, hipStream_t s) {
+  if (total_wg <= 0) return hipSuccess;
+  if (total_wg > SB2ST_MAX_WG) return hipErrorInvalidValue;
+  void* args[] = {(void*)&d_tasks, (void*)&d_wg_task};
+  kt_begin("sb2st_group_kernel<32>", flops, bytes, 0, s, true);
+  HSDM_TRY(hipLaunchCooperativeKernel((const void*)sb2st_group_kernel<32>, dim3(total_wg),
+                                      dim3(64 * WPB), args, 0, s));
+  kt_end(s);
+  return hipSuccess;
+}
+
 hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, double* e, double* V2,
                      double* tau2, const long* d_goff, int* progress, DevStatusWord* st,
                      hipStream_t s) {
@@ -471,7 +535,7 @@ hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, doub
     HSDM_TRY(hipGetLastError());
     int nsweep = L.nsweep;
     int nwg = ceil_div(nsweep, WPB);
-    if (nwg > 256) nwg = 256;
+    if (nwg > SB2ST_MAX_WG) nwg = SB2ST_MAX_WG;
     // (sweep s and s-1 share a workgroup iff s is not the first sweep of its
     // wavefront group; TW = nwg * WPB keeps that true for every round)
     void* args[] = {(void*)&n, (void*)&nsweep, (void*)&AB, (void*)&ldab, (void*)&V2,

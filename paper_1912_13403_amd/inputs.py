@@ -119,10 +119,21 @@ def kpoint_sizes(lo=600, hi=3000):
 
 
 def _banded_complex(rng, n, std, decay, width):
-    i = np.arange(n)
-    dist = np.abs(i[:, None] - i[None, :])
-    env = np.where(dist <= width, np.exp(-dist / float(decay)), 0.0)
-    return (rng.normal(0.0, std, (n, n)) + 1j * rng.normal(0.0, std, (n, n))) * env
+    """Complex n x n matrix with Re, Im ~ N(0, std^2) * exp(-|i-j|/decay) on the
+    diagonals |i-j| <= width (drawn diagonal by diagonal, -width first) and
+    zero elsewhere."""
+    A = np.zeros((n, n), dtype=np.complex128)
+    for d in range(-width, width + 1):
+        m = n - abs(d)
+        if m <= 0:
+            continue
+        v = (rng.normal(0.0, std, m) + 1j * rng.normal(0.0, std, m)) * np.exp(-abs(d) / decay)
+        i = np.arange(m)
+        if d >= 0:
+            A[i + d, i] = v
+        else:
+            A[i, i - d] = v
+    return A
 
 
 def kpoint_problem(kindex, n=None):
