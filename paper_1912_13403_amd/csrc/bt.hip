@@ -425,7 +425,9 @@ __global__ void zero_upper_panels_kernel(int n, int B_, double* Vst, long ldv) {
 
 }  // namespace
 
-static int npanel_of(int n, int B_) { return (n > B_) ? ceil_div(n - 1, B_) : 0; }
+// Panels the full-to-band reduction produced: panel p has rows below
+// (p + 1) B, so it exists iff (p + 1) B < n.
+static int npanel_of(int n, int B_) { return (n > B_) ? ceil_div(n - B_, B_) : 0; }
 
 namespace {
 constexpr int BT1_MAXSPLIT = 4;    // split-K slices of V^T Z

@@ -174,3 +174,18 @@ def test_argument_errors(torch_dev, h):
         h.hsdm_reinit()
         h.hsdm_solve_dm_real(torch.eye(4, dtype=torch.float64, device=dev), S, 1.0, 0.0)
     assert ei.value.status == hsdm.HSDM_NOT_SPD and ei.value.detail == 1
+
+
+def test_partial_last_panel_after_larger_solves(oracle, torch_dev, h):
+    """Sizes with n mod 32 not in {0, 1} (the band reduction's last panel is
+    partial) solved one after another on one handle, so the workspace of each
+    size reuses memory that held a larger problem: every result must match the
+    oracle whatever the workspace held before."""
+    for n in [600, 42, 300, 100, 47, 130, 97, 64]:
+        H, S = inputs.sized_problem(n, cfg=1400 + n)
+        ne, kT = n / 2.0, 0.01
+        h.hsdm_reinit()
+        r = h.hsdm_solve_dm_real(_g(torch_dev, H), _g(torch_dev, S), ne, kT)
+        ref = oracle.solve_dm(H, S, ne, kT)
+        err = np.max(np.abs(_c(r["D"]) - ref["D"]))
+        assert err <= 1e-9, f"n={n}: |dD| = {err:.3e}"
