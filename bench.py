@@ -16,6 +16,12 @@ FP64 tasks of sizes n_k ~ U{600..3000}, one chemical potential for all
 (N_e = 0.4 sum_k n_k, kT = 0.01, f_max = 1), cold S factors; the metric is
 tasks solved per second.
 
+With --config cfg4_serving it replays a stream of --requests requests
+(Poisson arrivals at 40/s, sizes log-uniform on [256, 8192], 60 % real and
+40 % Hermitian, 30 % SCF repeats sharing an earlier request's S) through the
+serving loop (paper_1912_13403_amd/serving.py) and reports the p50 latency,
+with p99 and solves/s beside it.
+
 The roofline entry is that of the kernel with the largest total time over the
 timed steps, from HIP events recorded around each of its launches on the
 solve's stream; its "traffic" comes from the committed counter summary
@@ -273,12 +279,88 @@ def batch_main(args):
     print(json.dumps(rec))
 
 
+def serving_main(args):
+    import numpy as np
+    import torch
+
+    from paper_1912_13403_amd import hsdm, inputs, serving
+
+    dev = torch.device("cuda", 0)
+
+    def gram(B):
+        Bt = torch.from_numpy(B).to(dev)
+        G = (Bt @ Bt.T).cpu().numpy()
+        del Bt
+        return G
+
+    t0 = time.perf_counter()
+    specs = inputs.request_specs(args.requests, rate=40.0, lo=256, hi=8192, seed=0)
+    probs, reqs = {}, []
+    for sp in specs:
+        base = probs[sp["base"]] if sp["repeat"] else None
+        probs[sp["rid"]] = inputs.request_problem(sp, base, gram=gram)
+        H, S = probs[sp["rid"]]
+        reqs.append(dict(sp, H=H, S=S))
+    torch.cuda.empty_cache()
+    print(f"[bench] {len(reqs)} requests ready in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    # warmup: a short stream of small requests (kernels loaded, contexts made)
+    warm = inputs.request_specs(4, rate=1000.0, lo=256, hi=512, seed=99)
+    wreqs = []
+    for sp in warm:
+        H, S = inputs.request_problem(dict(sp, repeat=False))
+        wreqs.append(dict(sp, H=H, S=S, repeat=False, base=-1 - sp["rid"]))
+    srv = serving.Server(0, hbm_budget=200e9, timing_level=3)
+    srv.run(wreqs)
+    srv.h.hsdm_release_tasks(0.0)
+    srv.s_dev.clear()
+    torch.cuda.synchronize()
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    ts = time.perf_counter()
+    recs = srv.run(reqs, log=log)
+    wall = time.perf_counter() - ts
+    summ = serving.summarize(recs)
+    ks = srv.h.kernel_stats()
+    roof = None
+    if any(v["ms"] > 0 for v in ks.values()):
+        roof = roofline({k: v for k, v in ks.items() if v["ms"] > 0}, args.config, 1)
+        roof["timed_in"] = "last round (kernels launched once per task)"
+    srv.close()
+    rec = {
+        "metric": "serving p50 latency",
+        "value": summ["p50_s"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": 1000.0 * wall,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"cfg4_serving: {len(reqs)} requests, Poisson 40/s, n log-uniform "
+                               "[256, 8192], 60% real / 40% Hermitian FP64, 30% SCF repeats, "
+                               "HBM budget 200 GB, continuous batching by rounds",
+                   "requests": len(reqs)},
+        "p99_s": summ["p99_s"],
+        "mean_latency_s": summ["mean_s"],
+        "solves_per_s": summ["solves_per_s"],
+        "rounds": summ["rounds"],
+        "offered_rate_per_s": 40.0,
+        "roofline": roof,
+    }
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="cfg2_n16384")
+    ap.add_argument("--requests", type=int, default=100,
+                    help="requests replayed by --config cfg4_serving")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-warm", action="store_true",
                     help="skip the extra solve with the S factor cached")
@@ -292,6 +374,8 @@ def main():
 
     if args.config == "cfg3_batch":
         return batch_main(args)
+    if args.config == "cfg4_serving":
+        return serving_main(args)
 
     import numpy as np
     import torch

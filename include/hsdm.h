@@ -146,6 +146,32 @@ int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int *n,
                         void *const *D, const int *ldd, void *const *E, const int *lde,
                         double *band_energy, double *mu, void *stream);
 
+/* Independent problems solved together (requests of a serving loop): real
+ * and Hermitian tasks mixed (is_complex[p]), each with its own electron
+ * count, kT and f_max (f_max nullable: the handle's), its own chemical
+ * potential and band energy (HOST arrays mu[nprob], band_energy[nprob],
+ * nullable).  Each task runs the path of the single solves; the bands of all
+ * tasks are chased in shared cooperative launches.  Task contexts (workspace
+ * and factor of S) are owned by the handle and picked by S identity, so a
+ * task whose S (pointer, n, lds) was factored in an earlier call reuses the
+ * factor; otherwise the least recently used context is taken.  Other
+ * arguments and status codes as hsdm_solve_dm_batch (-3: a missing array or
+ * a bad is_complex[p], -9: n_electrons[p], -10: kT[p], -11: f_max[p]). */
+int hsdm_solve_dm_group(hsdm_handle h, int nprob, const int *is_complex, const int *n,
+                        const void *const *H, const int *ldh, const void *const *S,
+                        const int *lds, const double *n_electrons, const double *kT,
+                        const double *f_max, void *const *D, const int *ldd, void *const *E,
+                        const int *lde, double *band_energy, double *mu, void *stream);
+/* Device bytes a task context of size n holds (its workspace; for Hermitian
+ * tasks the real workspace of size 2n plus the embedding buffers). */
+double hsdm_task_bytes(int n, int is_complex);
+/* Device bytes held by the handle: its own workspace and its task contexts. */
+double hsdm_workspace_bytes(hsdm_handle h);
+/* Release least recently used task contexts (and with them their factors of
+ * S) until the task contexts hold at most keep_bytes; synchronizes the
+ * device first. */
+int hsdm_release_tasks(hsdm_handle h, double keep_bytes);
+
 /* ---- phase entry points (same conventions; used to test and compose) ---- */
 
 /* S = L L^T and L^{-1}; L and Linv written in full (zeros above the diagonal). */

@@ -80,8 +80,11 @@ struct hsdm_ctx {
   double *Lbuf, *Linv, *Abuf, *Vst, *Zbuf, *Cbuf, *T1, *tau1, *AB, *sy_scr, *dvec, *evec, *lam,
       *fvec, *V2, *tau2, *F2, *dc_scr, *bt1_scr, *colsum, *hnorm;
   int *dc_iscr, *progress;
-  // per-task contexts of hsdm_solve_dm_batch (workspace and S factor each)
+  // per-task contexts of the multi-task solves (workspace and S factor each),
+  // picked by S identity, then least recently used
   std::vector<hsdm_ctx*> subs;
+  long last_use = 0;
+  long use_clock = 0;
   std::vector<OccTask> h_tasks;
   OccTask* d_tasks = nullptr;
   int d_tasks_cap = 0;
@@ -163,9 +166,13 @@ void free_ws(hsdm_ctx* h) {
   h->s_valid = false;
 }
 
-int ensure_ws(hsdm_ctx* h, int n) {
-  if (h->ws_n == n && h->ws) return HSDM_OK;
-  free_ws(h);
+struct WsLayout {
+  size_t oL, oLi, oA, oV, oZ, oC, oT1, otau1, oAB, osy, od, oe, olam, of, oV2, otau2, oF2, odc,
+      obt1, ocs, ohn, total, ints;
+};
+
+WsLayout ws_layout(int n) {
+  WsLayout w{};
   const size_t nn = (size_t)n * n;
   const Sb2stLayout L = sb2st_layout(n, BAND);
   const int npanel = (n > BAND) ? ceil_div(n - 1, BAND) : 0;
@@ -175,21 +182,42 @@ int ensure_ws(hsdm_ctx* h, int n) {
     off += (cnt + 31) & ~(size_t)31;  // 256-byte aligned pieces
     return o;
   };
-  const size_t oL = take(nn), oLi = take(nn), oA = take(nn), oV = take(nn), oZ = take(nn),
-               oC = take(nn);
-  const size_t oT1 = take((size_t)(npanel + 1) * BAND * BAND), otau1 = take(n + 1);
-  const size_t oAB = take((size_t)2 * BAND * (n + BAND + 1)), osy = take(sy2sb_scratch_doubles(n, BAND));
-  const size_t od = take(n), oe = take(n), olam = take(n), of = take(n);
-  const size_t oV2 = take(L.v2_doubles + 1), otau2 = take((size_t)L.ngroups * BAND + 1),
-               oF2 = take(bt2_pack_doubles(L) + 1);
-  const size_t odc = take(stedc_scratch_doubles(n)), obt1 = take(bt1_scratch_doubles(n, BAND, n));
-  const size_t ocs = take(n), ohn = take(1);
+  w.oL = take(nn); w.oLi = take(nn); w.oA = take(nn); w.oV = take(nn); w.oZ = take(nn);
+  w.oC = take(nn);
+  w.oT1 = take((size_t)(npanel + 1) * BAND * BAND); w.otau1 = take(n + 1);
+  w.oAB = take((size_t)2 * BAND * (n + BAND + 1)); w.osy = take(sy2sb_scratch_doubles(n, BAND));
+  w.od = take(n); w.oe = take(n); w.olam = take(n); w.of = take(n);
+  w.oV2 = take(L.v2_doubles + 1); w.otau2 = take((size_t)L.ngroups * BAND + 1);
+  w.oF2 = take(bt2_pack_doubles(L) + 1);
+  w.odc = take(stedc_scratch_doubles(n)); w.obt1 = take(bt1_scratch_doubles(n, BAND, n));
+  w.ocs = take(n); w.ohn = take(1);
+  w.total = off;
+  w.ints = stedc_iscratch_ints(n) + (size_t)n + 128;
+  return w;
+}
+
+// Device bytes of the workspace of a real solve of size n.
+double ws_bytes(int n) {
+  const WsLayout w = ws_layout(n);
+  return 8.0 * w.total + 4.0 * w.ints + 8.0 * (sb2st_layout(n, BAND).nblk + 1);
+}
+
+int ensure_ws(hsdm_ctx* h, int n) {
+  if (h->ws_n == n && h->ws) return HSDM_OK;
+  free_ws(h);
+  const Sb2stLayout L = sb2st_layout(n, BAND);
+  const WsLayout wl = ws_layout(n);
+  const size_t off = wl.total;
+  const size_t oL = wl.oL, oLi = wl.oLi, oA = wl.oA, oV = wl.oV, oZ = wl.oZ, oC = wl.oC,
+               oT1 = wl.oT1, otau1 = wl.otau1, oAB = wl.oAB, osy = wl.osy, od = wl.od,
+               oe = wl.oe, olam = wl.olam, of = wl.of, oV2 = wl.oV2, otau2 = wl.otau2,
+               oF2 = wl.oF2, odc = wl.odc, obt1 = wl.obt1, ocs = wl.ocs, ohn = wl.ohn;
   hipError_t e = hipMalloc(&h->ws, off * sizeof(double));
   if (e != hipSuccess) {
     h->ws = nullptr;
     return fail_dev(h, e, "workspace allocation");
   }
-  const size_t ni = stedc_iscratch_ints(n) + (size_t)n + 128;
+  const size_t ni = wl.ints;
   e = hipMalloc(&h->iws, ni * sizeof(int));
   if (e != hipSuccess) {
     free_ws(h);
@@ -813,78 +841,104 @@ int hsdm_solve_dm_complex(hsdm_handle h, int n, const void* H, int ldh, const vo
   return r;
 }
 
-int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int* n,
-                        const void* const* H, const int* ldh, const void* const* S,
-                        const int* lds, const double* weight, double ne, double kT,
-                        void* const* D, const int* ldd, void* const* E, const int* lde,
-                        double* band_energy, double* mu, void* stream) {
-  if (!h) return -1;
-  if (nprob < 1) return -2;
-  if (is_complex != 0 && is_complex != 1) return -3;
-  if (!n || !H || !ldh || !S || !lds || !D || !ldd || (E && !lde)) return -4;
-  double cap = 0.0;
-  int nmax = 0;
-  for (int p = 0; p < nprob; p++) {
-    if (n[p] < 1 || (is_complex && n[p] > (1 << 29))) return -4;
-    if (!H[p]) return -5;
-    if (bad_ld(ldh[p], n[p])) return -6;
-    if (!S[p]) return -7;
-    if (bad_ld(lds[p], n[p])) return -8;
-    const double w = weight ? weight[p] : 1.0;
-    if (!(w > 0.0) || !std::isfinite(w)) return -9;
-    if (!D[p]) return -12;
-    if (bad_ld(ldd[p], n[p])) return -13;
-    if (E && E[p] && bad_ld(lde[p], n[p])) return -15;
-    cap += w * n[p];
-    nmax = n[p] > nmax ? n[p] : nmax;
+}  // extern "C"
+
+namespace {
+
+// One task of a multi-task solve.
+struct TaskSpec {
+  int cplx, n;
+  const void *H, *S;
+  int ldh, lds;
+  void *D, *E;
+  int ldd, lde;
+  double w;             // weight in a shared electron count
+  double ne, kT, fmax;  // own electron count and occupations (independent tasks)
+};
+
+// Task contexts for the tasks of one call: first a context that holds the
+// factor of the task's S, then the least recently used of the others
+// (created as needed).
+int pick_contexts(hsdm_ctx* h, int nt, const TaskSpec* T, std::vector<hsdm_ctx*>& ctx) {
+  ctx.assign(nt, nullptr);
+  std::vector<char> used(h->subs.size(), 0);
+  for (int p = 0; p < nt; p++) {
+    const SKey key{T[p].S, T[p].n, T[p].lds, T[p].cplx != 0};
+    for (size_t i = 0; i < h->subs.size(); i++)
+      if (!used[i] && s_cached(h->subs[i], key)) {
+        used[i] = 1;
+        ctx[p] = h->subs[i];
+        break;
+      }
   }
-  if (!(ne >= 0.0) || !std::isfinite(ne) || ne > h->fmax * cap * (1.0 + 1e-15)) return -10;
-  if (!(kT >= 0.0) || !std::isfinite(kT)) return -11;
-  h->err.clear();
-  hipStream_t s = (hipStream_t)stream;
-  DEV_TRY(h, hipSetDevice(h->device));
-  while ((int)h->subs.size() < nprob) {
-    hsdm_ctx* c = nullptr;
-    const int r = hsdm_init(&c, h->device);
-    if (r) {
-      h->err = "task context allocation failed";
-      return r;
+  for (int p = 0; p < nt; p++) {
+    if (ctx[p]) continue;
+    long best = -1;
+    for (size_t i = 0; i < h->subs.size(); i++)
+      if (!used[i] && (best < 0 || h->subs[i]->last_use < h->subs[best]->last_use)) best = (long)i;
+    if (best < 0) {
+      hsdm_ctx* c = nullptr;
+      const int r = hsdm_init(&c, h->device);
+      if (r) {
+        h->err = "task context allocation failed";
+        return r;
+      }
+      h->subs.push_back(c);
+      used.push_back(0);
+      best = (long)h->subs.size() - 1;
     }
-    h->subs.push_back(c);
+    used[best] = 1;
+    ctx[p] = h->subs[best];
   }
-  int r;
-  if (is_complex && (r = ensure_cws(h, nmax))) return r;
-  if (h->d_tasks_cap < nprob) {
+  for (int p = 0; p < nt; p++) ctx[p]->last_use = ++h->use_clock;
+  return HSDM_OK;
+}
+
+// The tasks' path: A1-A6 for each task, the bands of all tasks in shared
+// cooperative launches, then the occupations (one chemical potential for all
+// tasks when `shared`, Eq. (16); else each task's own), then A8-A12 for
+// each task.  Outputs on the host: the shared mu and weighted band energy,
+// and each task's mu and band energy.
+int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, double kT,
+                double* eb_total, double* mu_shared, double* eb_each, double* mu_each,
+                hipStream_t s) {
+  int r, nmax_c = 0;
+  for (int p = 0; p < nt; p++)
+    if (T[p].cplx && T[p].n > nmax_c) nmax_c = T[p].n;
+  std::vector<hsdm_ctx*> ctx;
+  if ((r = pick_contexts(h, nt, T, ctx))) return r;
+  if (nmax_c > 0 && (r = ensure_cws(h, nmax_c))) return r;
+  if (h->d_tasks_cap < nt) {
     if (h->d_tasks) (void)hipFree(h->d_tasks);
     h->d_tasks = nullptr;
     h->d_tasks_cap = 0;
-    DEV_TRY(h, hipMalloc(&h->d_tasks, sizeof(OccTask) * nprob));
-    h->d_tasks_cap = nprob;
+    DEV_TRY(h, hipMalloc(&h->d_tasks, sizeof(OccTask) * nt));
+    h->d_tasks_cap = nt;
   }
   KtScope kts(h);
   for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
-  h->h_tasks.assign(nprob, OccTask{});
-  // 1. every task: factor, standard form, two-stage reduction, eigenpairs of
-  //    the tridiagonal (all of them: the occupations are not known yet)
-  for (int p = 0; p < nprob; p++) {
-    hsdm_ctx* c = h->subs[p];
-    c->fmax = h->fmax;
+  h->h_tasks.assign(nt, OccTask{});
+  // 1. every task: factor, standard form, full -> band
+  for (int p = 0; p < nt; p++) {
+    hsdm_ctx* c = ctx[p];
+    const TaskSpec& t = T[p];
+    c->fmax = shared ? h->fmax : t.fmax;
     c->fcut_rel = h->fcut_rel;
     c->deg_tol = h->deg_tol;
     c->timing = false;
     c->ktiming = false;
     c->err.clear();
-    const int nr = is_complex ? 2 * n[p] : n[p];
+    const int nr = t.cplx ? 2 * t.n : t.n;
     if ((r = ensure_ws(c, nr))) {
       h->err = c->err;
       return r;
     }
-    const SKey key{S[p], n[p], lds[p], is_complex != 0};
-    const double *Hr = (const double*)H[p], *Sr = (const double*)S[p];
-    int ldhr = ldh[p], ldsr = lds[p];
-    if (is_complex) {
-      if (!s_cached(c, key)) DEV_TRY(h, herm_embed(n[p], S[p], lds[p], h->SR, nr, s));
-      DEV_TRY(h, herm_embed(n[p], H[p], ldh[p], h->HR, nr, s));
+    const SKey key{t.S, t.n, t.lds, t.cplx != 0};
+    const double *Hr = (const double*)t.H, *Sr = (const double*)t.S;
+    int ldhr = t.ldh, ldsr = t.lds;
+    if (t.cplx) {
+      if (!s_cached(c, key)) DEV_TRY(h, herm_embed(t.n, t.S, t.lds, h->SR, nr, s));
+      DEV_TRY(h, herm_embed(t.n, t.H, t.ldh, h->HR, nr, s));
       Hr = h->HR;
       Sr = h->SR;
       ldhr = ldsr = nr;
@@ -899,18 +953,18 @@ int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int* n,
                          c->sy_scr, c->st, s));
     DEV_TRY(h, sb2st_prepare(c->lay, c->V2, c->tau2, c->progress, s));
     h->h_tasks[p] = OccTask{c->lam, c->fvec, c->occ, c->deg_tol < 0.0 ? c->hnorm : nullptr, nr,
-                            weight ? weight[p] : 1.0};
+                            t.w};
   }
-  // bulge chasing of all bands, as many per cooperative launch as fit: each
-  // band alone is latency-bound and fills a small part of the device
+  // 2. bulge chasing of all bands, as many per cooperative launch as fit:
+  //    each band alone is latency-bound and fills a small part of the device
   {
-    h->h_sb.assign(nprob, Sb2stTask{});
+    h->h_sb.assign(nt, Sb2stTask{});
     h->h_wgmap.clear();
     std::vector<int> first(1, 0);  // first task of each launch
     std::vector<double> fl(1, 0.0), by(1, 0.0);
     int in_launch = 0;
-    for (int p = 0; p < nprob; p++) {
-      hsdm_ctx* c = h->subs[p];
+    for (int p = 0; p < nt; p++) {
+      hsdm_ctx* c = ctx[p];
       const int w = sb2st_group_nwg(c->lay);
       if (w > 0 && in_launch + w > SB2ST_MAX_WG) {
         first.push_back(p);
@@ -926,8 +980,8 @@ int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int* n,
       fl.back() += 6.0 * BAND * nn;
       by.back() += 12.0 * BAND * nn;
     }
-    first.push_back(nprob);
-    const size_t tb = sizeof(Sb2stTask) * nprob;
+    first.push_back(nt);
+    const size_t tb = sizeof(Sb2stTask) * nt;
     const size_t need = tb + sizeof(int) * (h->h_wgmap.size() + 1);
     if (h->d_sb_bytes < need) {
       if (h->d_sb) (void)hipFree(h->d_sb);
@@ -950,25 +1004,37 @@ int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int* n,
       off += cnt;
     }
   }
-  for (int p = 0; p < nprob; p++) {
-    hsdm_ctx* c = h->subs[p];
-    const int nr = is_complex ? 2 * n[p] : n[p];
+  // 3. every task: eigenpairs of the tridiagonal (all of them when the
+  //    occupations are shared: they are not known yet)
+  for (int p = 0; p < nt; p++) {
+    hsdm_ctx* c = ctx[p];
+    const TaskSpec& t = T[p];
+    const int nr = t.cplx ? 2 * t.n : t.n;
     DEV_TRY(h, sb2st_finish(c->lay, c->AB, 2 * BAND, c->dvec, c->evec, s));
-    DEV_TRY(h, stedc_run(c->plan, c->dvec, c->evec, c->lam, c->Zbuf, nr, c->dc_scr, c->dc_iscr,
-                         nullptr, nullptr, nullptr, c->st, s));
+    if (shared) {
+      DEV_TRY(h, stedc_run(c->plan, c->dvec, c->evec, c->lam, c->Zbuf, nr, c->dc_scr,
+                           c->dc_iscr, nullptr, nullptr, nullptr, c->st, s));
+    } else {
+      OccHook hook{c, nr, t.cplx ? 2.0 * t.ne : t.ne, t.kT};
+      DEV_TRY(h, stedc_run(c->plan, c->dvec, c->evec, c->lam, c->Zbuf, nr, c->dc_scr,
+                           c->dc_iscr, &c->occ->m, occ_hook, &hook, c->st, s));
+    }
   }
-  // 2. one chemical potential for all tasks (Eq. (16))
-  DEV_TRY(h, hipMemcpyAsync(h->d_tasks, h->h_tasks.data(), sizeof(OccTask) * nprob,
-                            hipMemcpyHostToDevice, s));
+  // 4. one chemical potential for all tasks (Eq. (16))
   hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
-  DEV_TRY(h, occupations_joint_launch(nprob, h->d_tasks, h->fmax, is_complex ? 2.0 * ne : ne, kT,
-                                      h->deg_tol, h->fcut_rel * h->fmax, h->occ, h->st, s));
-  // 3. every task: back-transforms of its occupied vectors, D and E
-  for (int p = 0; p < nprob; p++) {
+  if (shared) {
+    DEV_TRY(h, hipMemcpyAsync(h->d_tasks, h->h_tasks.data(), sizeof(OccTask) * nt,
+                              hipMemcpyHostToDevice, s));
+    DEV_TRY(h, occupations_joint_launch(nt, h->d_tasks, h->fmax, ne, kT, h->deg_tol,
+                                        h->fcut_rel * h->fmax, h->occ, h->st, s));
+  }
+  // 5. every task: back-transforms of its occupied vectors, D and E
+  for (int p = 0; p < nt; p++) {
     kt_set_tag(p);
-    hsdm_ctx* c = h->subs[p];
-    const int nr = is_complex ? 2 * n[p] : n[p];
+    hsdm_ctx* c = ctx[p];
+    const TaskSpec& t = T[p];
+    const int nr = t.cplx ? 2 * t.n : t.n;
     const int* m_dev = &c->occ->m;
     DEV_TRY(h, bt2_prepare(c->lay, c->V2, c->tau2, c->F2, s));
     DEV_TRY(h, bt2_apply(c->lay, c->F2, c->d_goff, c->Zbuf, nr, nr, m_dev, c->progress, c->st, s));
@@ -978,22 +1044,21 @@ int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int* n,
     g.C = c->Cbuf; g.ldc = nr; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
     g.flags = GF_KA_UPPER; g.ndev = m_dev;
     DEV_TRY(h, gemm_launch(g, s));
-    void* Ep = (E && E[p]) ? E[p] : nullptr;
-    if (is_complex) {
+    if (t.cplx) {
       DEV_TRY(h, density_launch(nr, nr, c->Cbuf, nr, c->fvec, c->lam, h->DR, nr,
-                                Ep ? h->ER : nullptr, nr, m_dev, s));
-      DEV_TRY(h, herm_extract(n[p], h->DR, nr, D[p], ldd[p], s));
-      if (Ep) DEV_TRY(h, herm_extract(n[p], h->ER, nr, Ep, lde[p], s));
+                                t.E ? h->ER : nullptr, nr, m_dev, s));
+      DEV_TRY(h, herm_extract(t.n, h->DR, nr, t.D, t.ldd, s));
+      if (t.E) DEV_TRY(h, herm_extract(t.n, h->ER, nr, t.E, t.lde, s));
     } else {
-      DEV_TRY(h, density_launch(nr, nr, c->Cbuf, nr, c->fvec, c->lam, (double*)D[p], ldd[p],
-                                (double*)Ep, Ep ? lde[p] : nr, m_dev, s));
+      DEV_TRY(h, density_launch(nr, nr, c->Cbuf, nr, c->fvec, c->lam, (double*)t.D, t.ldd,
+                                (double*)t.E, t.E ? t.lde : nr, m_dev, s));
     }
   }
   kt_set_tag(-1);
-  // status of every task, then of the joint occupations
-  h->tag_m.assign(nprob, 0);
-  for (int p = 0; p < nprob; p++) {
-    hsdm_ctx* c = h->subs[p];
+  // status of every task, then of the shared occupations
+  h->tag_m.assign(nt, 0);
+  for (int p = 0; p < nt; p++) {
+    hsdm_ctx* c = ctx[p];
     if ((r = finish(c, s))) {
       h->detail = c->detail;
       h->err = "task " + std::to_string(p) + ": " + c->err;
@@ -1001,12 +1066,132 @@ int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int* n,
       return r;
     }
     h->tag_m[p] = c->host->occ.m;
+    const double half = T[p].cplx ? 0.5 : 1.0;
+    if (eb_each) eb_each[p] = half * c->host->occ.band_energy;
+    if (mu_each) mu_each[p] = c->host->occ.mu;
   }
   r = finish(h, s);
   h->tag_m.clear();
-  if (mu) *mu = h->host->occ.mu;
-  if (band_energy) *band_energy = (is_complex ? 0.5 : 1.0) * h->host->occ.band_energy;
+  if (mu_shared) *mu_shared = h->host->occ.mu;
+  if (eb_total) *eb_total = h->host->occ.band_energy;
   return r;
+}
+
+double ctx_bytes(const hsdm_ctx* c) {
+  double b = c->ws ? ws_bytes(c->ws_n) : 0.0;
+  if (c->cws) b += 16.0 * 8.0 * (double)c->cws_n * c->cws_n;
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int* n,
+                        const void* const* H, const int* ldh, const void* const* S,
+                        const int* lds, const double* weight, double ne, double kT,
+                        void* const* D, const int* ldd, void* const* E, const int* lde,
+                        double* band_energy, double* mu, void* stream) {
+  if (!h) return -1;
+  if (nprob < 1) return -2;
+  if (is_complex != 0 && is_complex != 1) return -3;
+  if (!n || !H || !ldh || !S || !lds || !D || !ldd || (E && !lde)) return -4;
+  double cap = 0.0;
+  std::vector<TaskSpec> T(nprob);
+  for (int p = 0; p < nprob; p++) {
+    if (n[p] < 1 || (is_complex && n[p] > (1 << 29))) return -4;
+    if (!H[p]) return -5;
+    if (bad_ld(ldh[p], n[p])) return -6;
+    if (!S[p]) return -7;
+    if (bad_ld(lds[p], n[p])) return -8;
+    const double w = weight ? weight[p] : 1.0;
+    if (!(w > 0.0) || !std::isfinite(w)) return -9;
+    if (!D[p]) return -12;
+    if (bad_ld(ldd[p], n[p])) return -13;
+    if (E && E[p] && bad_ld(lde[p], n[p])) return -15;
+    cap += w * n[p];
+    T[p] = TaskSpec{is_complex, n[p], H[p], S[p], ldh[p], lds[p], D[p], E ? E[p] : nullptr,
+                    ldd[p], E ? lde[p] : n[p], w, 0.0, 0.0, h->fmax};
+  }
+  if (!(ne >= 0.0) || !std::isfinite(ne) || ne > h->fmax * cap * (1.0 + 1e-15)) return -10;
+  if (!(kT >= 0.0) || !std::isfinite(kT)) return -11;
+  h->err.clear();
+  DEV_TRY(h, hipSetDevice(h->device));
+  double eb = 0.0, m = 0.0;
+  const int r = solve_tasks(h, nprob, T.data(), true, is_complex ? 2.0 * ne : ne, kT, &eb, &m,
+                            nullptr, nullptr, (hipStream_t)stream);
+  if (mu) *mu = m;
+  if (band_energy) *band_energy = (is_complex ? 0.5 : 1.0) * eb;
+  return r;
+}
+
+int hsdm_solve_dm_group(hsdm_handle h, int nprob, const int* is_complex, const int* n,
+                        const void* const* H, const int* ldh, const void* const* S,
+                        const int* lds, const double* n_electrons, const double* kT,
+                        const double* f_max, void* const* D, const int* ldd, void* const* E,
+                        const int* lde, double* band_energy, double* mu, void* stream) {
+  if (!h) return -1;
+  if (nprob < 1) return -2;
+  if (!is_complex || !n || !H || !ldh || !S || !lds || !n_electrons || !kT || !D || !ldd ||
+      (E && !lde))
+    return -3;
+  std::vector<TaskSpec> T(nprob);
+  for (int p = 0; p < nprob; p++) {
+    if (is_complex[p] != 0 && is_complex[p] != 1) return -3;
+    if (n[p] < 1 || (is_complex[p] && n[p] > (1 << 29))) return -4;
+    if (!H[p]) return -5;
+    if (bad_ld(ldh[p], n[p])) return -6;
+    if (!S[p]) return -7;
+    if (bad_ld(lds[p], n[p])) return -8;
+    const double fm = f_max ? f_max[p] : h->fmax;
+    if (!(fm > 0.0) || !std::isfinite(fm)) return -11;
+    if (!(n_electrons[p] >= 0.0) || !std::isfinite(n_electrons[p]) || n_electrons[p] > fm * n[p])
+      return -9;
+    if (!(kT[p] >= 0.0) || !std::isfinite(kT[p])) return -10;
+    if (!D[p]) return -12;
+    if (bad_ld(ldd[p], n[p])) return -13;
+    if (E && E[p] && bad_ld(lde[p], n[p])) return -15;
+    T[p] = TaskSpec{is_complex[p], n[p], H[p], S[p], ldh[p], lds[p], D[p],
+                    E ? E[p] : nullptr, ldd[p], E ? lde[p] : n[p], 1.0, n_electrons[p], kT[p], fm};
+  }
+  h->err.clear();
+  DEV_TRY(h, hipSetDevice(h->device));
+  return solve_tasks(h, nprob, T.data(), false, 0.0, 0.0, nullptr, nullptr, band_energy, mu,
+                     (hipStream_t)stream);
+}
+
+double hsdm_task_bytes(int n, int is_complex) {
+  if (n < 1) return 0.0;
+  const int nr = is_complex ? 2 * n : n;
+  return ws_bytes(nr) + (is_complex ? 16.0 * 8.0 * (double)n * n : 0.0);
+}
+
+double hsdm_workspace_bytes(hsdm_handle h) {
+  if (!h) return 0.0;
+  double b = ctx_bytes(h);
+  for (const hsdm_ctx* c : h->subs) b += ctx_bytes(c);
+  return b;
+}
+
+int hsdm_release_tasks(hsdm_handle h, double keep_bytes) {
+  if (!h) return -1;
+  if (!(keep_bytes >= 0.0)) return -2;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  auto tasks_bytes = [&]() {
+    double b = h->cws ? 16.0 * 8.0 * (double)h->cws_n * h->cws_n : 0.0;
+    for (const hsdm_ctx* c : h->subs) b += ctx_bytes(c);
+    return b;
+  };
+  while (!h->subs.empty() && tasks_bytes() > keep_bytes) {
+    size_t lru = 0;
+    for (size_t i = 1; i < h->subs.size(); i++)
+      if (h->subs[i]->last_use < h->subs[lru]->last_use) lru = i;
+    hsdm_finalize(h->subs[lru]);
+    h->subs.erase(h->subs.begin() + (long)lru);
+  }
+  if (h->subs.empty() && tasks_bytes() > keep_bytes) free_cws(h);
+  return HSDM_OK;
 }
 
 }  // extern "C"

@@ -36,6 +36,7 @@ HSDM_KEY_TIMING = 4
 EXPORTED = [
     "hsdm_init", "hsdm_finalize", "hsdm_reinit", "hsdm_set_real", "hsdm_set_int",
     "hsdm_solve_ev_real", "hsdm_solve_dm_real", "hsdm_solve_dm_complex", "hsdm_solve_dm_batch",
+    "hsdm_solve_dm_group", "hsdm_task_bytes", "hsdm_workspace_bytes", "hsdm_release_tasks",
     "hsdm_cholesky_inverse", "hsdm_standard_form",
     "hsdm_tridiagonalize", "hsdm_tridiag_eigh", "hsdm_occupations", "hsdm_density",
     "hsdm_dgemm", "hsdm_status_string", "hsdm_last_error", "hsdm_status_detail",
@@ -70,6 +71,11 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.POINTER(_d), ctypes.POINTER(_d), _vp], _i),
         "hsdm_solve_dm_batch": ([_vp, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _vp, _vp,
                                  _vp, _vp, ctypes.POINTER(_d), ctypes.POINTER(_d), _vp], _i),
+        "hsdm_solve_dm_group": ([_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                 _vp, _vp, _vp, _vp, _vp], _i),
+        "hsdm_task_bytes": ([_i, _i], _d),
+        "hsdm_workspace_bytes": ([_vp], _d),
+        "hsdm_release_tasks": ([_vp, _d], _i),
         "hsdm_cholesky_inverse": ([_vp, _i, _vp, _i, _vp, _i, _vp, _i, _vp], _i),
         "hsdm_standard_form": ([_vp, _i, _vp, _i, _vp, _i, _vp, _i, _vp], _i),
         "hsdm_tridiagonalize": ([_vp, _i, _vp, _i, _vp, _vp, _vp, _i, _vp], _i),
@@ -133,6 +139,11 @@ def empty_colmajor_c(n: int, m: int, device) -> torch.Tensor:
 
 def _stream_ptr(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
+
+
+def hsdm_task_bytes(n: int, is_complex: bool) -> float:
+    """Device bytes a task context of size n holds (no GPU needed)."""
+    return float(load_library().hsdm_task_bytes(int(n), int(bool(is_complex))))
 
 
 class Handle:
@@ -271,6 +282,43 @@ class Handle:
             I(*[_ld(x) for x in Es]) if Es is not None else None,
             ctypes.byref(eb), ctypes.byref(mu), _stream_ptr(self.device)))
         return dict(D=Ds, E=Es, mu=mu.value, band_energy=eb.value)
+
+    def hsdm_solve_dm_group(self, tasks, want_e=True):
+        """Independent problems in one call.  tasks: list of dicts with H, S
+        (float64 or complex128 tensors), n_electrons, kT and optionally f_max.
+        Returns a list of dicts (D, E, mu, band_energy)."""
+        k = len(tasks)
+        cplx = [int(t["H"].dtype == torch.complex128) for t in tasks]
+        Hs = [(_colmajor_c if c else _colmajor)(t["H"]) for t, c in zip(tasks, cplx)]
+        Ss = [(_colmajor_c if c else _colmajor)(t["S"]) for t, c in zip(tasks, cplx)]
+        ns = [int(x.shape[0]) for x in Hs]
+        Ds = [(empty_colmajor_c if c else empty_colmajor)(m, m, self.device)
+              for m, c in zip(ns, cplx)]
+        Es = ([(empty_colmajor_c if c else empty_colmajor)(m, m, self.device)
+               for m, c in zip(ns, cplx)] if want_e else None)
+        I = ctypes.c_int * k
+        P = ctypes.c_void_p * k
+        F = ctypes.c_double * k
+        fm = [t.get("f_max") for t in tasks]
+        fmax = F(*fm) if all(v is not None for v in fm) else None
+        mu = F()
+        eb = F()
+        self._check(self._lib.hsdm_solve_dm_group(
+            self._h, k, I(*cplx), I(*ns), P(*[x.data_ptr() for x in Hs]), I(*[_ld(x) for x in Hs]),
+            P(*[x.data_ptr() for x in Ss]), I(*[_ld(x) for x in Ss]),
+            F(*[float(t["n_electrons"]) for t in tasks]), F(*[float(t["kT"]) for t in tasks]),
+            fmax, P(*[x.data_ptr() for x in Ds]), I(*[_ld(x) for x in Ds]),
+            P(*[x.data_ptr() for x in Es]) if Es is not None else None,
+            I(*[_ld(x) for x in Es]) if Es is not None else None, eb, mu,
+            _stream_ptr(self.device)))
+        return [dict(D=Ds[p], E=Es[p] if Es is not None else None, mu=mu[p], band_energy=eb[p])
+                for p in range(k)]
+
+    def hsdm_workspace_bytes(self):
+        return float(self._lib.hsdm_workspace_bytes(self._h))
+
+    def hsdm_release_tasks(self, keep_bytes):
+        self._check(self._lib.hsdm_release_tasks(self._h, float(keep_bytes)))
 
     # ---- phases --------------------------------------------------------------
     def hsdm_cholesky_inverse(self, S):

@@ -136,14 +136,15 @@ def _banded_complex(rng, n, std, decay, width):
     return A
 
 
-def kpoint_problem(kindex, n=None):
+def kpoint_problem(kindex, n=None, gram=None):
     """(H_up, H_down, S) of k-point `kindex` of the recipe above (size n_k unless
-    `n` is given, which keeps the recipe at another size)."""
+    `n` is given, which keeps the recipe at another size).  ``gram(B)`` may
+    replace numpy's B @ B.T."""
     k = kpoints()[kindex]
     n = kpoint_sizes()[kindex] if n is None else int(n)
     rng = np.random.default_rng([3, *SEED_TAIL, int(kindex)])
     B = rng.standard_normal((n, n))
-    S0 = 0.1 * (B @ B.T) / n
+    S0 = 0.1 * (gram(B) if gram is not None else B @ B.T) / n
     S0 = 0.5 * (S0 + S0.T) + np.eye(n)
     del B
     G = rng.normal(0.0, 0.1, (n, n))
@@ -185,3 +186,60 @@ def gauge_chain(n, seed=0, t=-1.0):
     u = np.exp(1j * theta)
     H = (u[:, None] * Hc) * np.conj(u)[None, :]
     return np.asfortranarray(H), np.eye(n, dtype=np.complex128, order="F"), theta
+
+
+# ---- a stream of requests (serving) -----------------------------------------------
+#
+# Recipe (seed list [4, 1912, 13403]): Poisson arrivals at `rate` per second;
+# sizes log-uniform on [lo, hi]; 60 % real problems (the real recipe, decay 32,
+# S perturbation 0.1; N_e = n/2, kT = 0.01, f_max = 2), 40 % Hermitian (one
+# k-point and spin of the k-point recipe at that size; N_e = 0.2 n, kT = 0.01,
+# f_max = 1); 30 % SCF repeats of an earlier request of the same type: the same
+# S (shared, not copied) and H + 1e-3 Z with Z symmetric (Hermitian) standard
+# normal.  Problems are drawn by `make(spec)` so that a caller can draw them
+# lazily; `gram(B)` may replace numpy's B @ B.T for the real recipe.
+
+
+def request_specs(count, rate=40.0, lo=256, hi=8192, seed=0):
+    """Arrival times and shapes of `count` requests (no matrices)."""
+    rng = np.random.default_rng([4, *SEED_TAIL, int(seed)])
+    t = np.cumsum(rng.exponential(1.0 / rate, count))
+    specs = []
+    for i in range(count):
+        u = rng.random()
+        rep = None
+        if i > 0 and rng.random() < 0.3:
+            rep = int(rng.integers(0, i))
+        if rep is not None:
+            base = specs[rep]["base"]
+            specs.append(dict(rid=i, arrival=float(t[i]), cplx=specs[base]["cplx"],
+                              n=specs[base]["n"], base=base, repeat=True))
+        else:
+            n = int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+            specs.append(dict(rid=i, arrival=float(t[i]), cplx=bool(u < 0.4), n=n, base=i,
+                              repeat=False))
+    for s in specs:
+        s["n_electrons"] = 0.2 * s["n"] if s["cplx"] else 0.5 * s["n"]
+        s["kT"] = 0.01
+        s["f_max"] = 1.0 if s["cplx"] else 2.0
+    return specs
+
+
+def request_problem(spec, base_problem=None, gram=None):
+    """(H, S) of a request.  A repeat passes its base request's (H, S) as
+    base_problem and receives (H + 1e-3 Z, the same S object)."""
+    rid, n = spec["rid"], spec["n"]
+    if spec["repeat"]:
+        H0, S0 = base_problem
+        rng = np.random.default_rng([4, *SEED_TAIL, 7, int(rid)])
+        Z = rng.standard_normal((n, n))
+        if spec["cplx"]:
+            Z = Z + 1j * rng.standard_normal((n, n))
+            Z = np.tril(Z, -1) + np.tril(Z, -1).conj().T + np.diag(np.real(np.diag(Z)))
+        else:
+            Z = np.tril(Z) + np.tril(Z, -1).T
+        return np.asfortranarray(H0 + 1e-3 * Z), S0
+    if spec["cplx"]:
+        Hu, _, S = kpoint_problem(rid % NKPT, n=n, gram=gram)
+        return Hu, S
+    return real_problem(n, 32.0, 0.1, cfg=1000 + rid, gram=gram)

@@ -1,0 +1,97 @@
+"""The serving loop on the GPU: a mixed stream of real and Hermitian requests
+with SCF repeats, solved in rounds through hsdm_solve_dm_group; every result
+in the mix equals the same request solved alone (single-solve entry points)
+within the parity tolerance, and the smaller ones equal the oracle."""
+import numpy as np
+import pytest
+
+from paper_1912_13403_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda", 0)
+
+
+def _stream(count, seed, lo, hi):
+    specs = inputs.request_specs(count, rate=2000.0, lo=lo, hi=hi, seed=seed)
+    probs = {}
+    reqs = []
+    for s in specs:
+        base = probs[s["base"]] if s["repeat"] else None
+        probs[s["rid"]] = inputs.request_problem(s, base)
+        H, S = probs[s["rid"]]
+        reqs.append(dict(s, H=H, S=S))
+    return reqs
+
+
+def _alone(torch_dev, r):
+    torch, dev = torch_dev
+    from paper_1912_13403_amd import hsdm
+    with hsdm.Handle(0) as h:
+        h.hsdm_set_real(hsdm.HSDM_KEY_FMAX, r["f_max"])
+        H = torch.from_numpy(np.asfortranarray(r["H"])).to(dev)
+        S = torch.from_numpy(np.asfortranarray(r["S"])).to(dev)
+        f = h.hsdm_solve_dm_complex if r["cplx"] else h.hsdm_solve_dm_real
+        o = f(H, S, r["n_electrons"], r["kT"])
+        return o["D"].cpu().numpy(), o["E"].cpu().numpy(), o["mu"], o["band_energy"]
+
+
+@pytest.mark.parametrize("budget", [200e9, 0.0])
+def test_each_result_same_alone_and_in_the_mix(oracle, torch_dev, budget):
+    from paper_1912_13403_amd.serving import Server
+    reqs = _stream(12, seed=11, lo=40, hi=500)
+    print(f"[serving] budget={budget:g} sizes={[r['n'] for r in reqs]}", flush=True)
+    srv = Server(0, hbm_budget=budget)
+    try:
+        recs = srv.run(reqs, keep=lambda rid: True)
+    finally:
+        srv.close()
+    assert sorted(r["rid"] for r in recs) == list(range(len(reqs)))
+    rounds = {r["round"] for r in recs}
+    if budget == 0.0:
+        assert len(rounds) == len(reqs)  # one request per round
+    else:
+        assert len(rounds) < len(reqs)   # requests shared rounds
+    by = {r["rid"]: r for r in recs}
+    for q in reqs:
+        rec = by[q["rid"]]
+        D, E, mu, eb = _alone(torch_dev, q)
+        scale = float(np.abs(q["H"]).sum(axis=0).max())
+        assert np.max(np.abs(rec["D"].cpu().numpy() - D)) <= 1e-9
+        assert np.max(np.abs(rec["E"].cpu().numpy() - E)) <= 1e-9 * max(1.0, scale)
+        assert abs(rec["mu"] - mu) <= 1e-10 * scale
+        assert abs(rec["band_energy"] - eb) <= 1e-10 * scale * q["n_electrons"]
+        if q["n"] <= 200:
+            if q["cplx"]:
+                ref = oracle.solve_dm_complex(q["H"], q["S"], q["n_electrons"], q["kT"], f_max=1.0)
+            else:
+                ref = oracle.solve_dm(q["H"], q["S"], q["n_electrons"], q["kT"], f_max=2.0)
+            assert np.max(np.abs(rec["D"].cpu().numpy() - ref["D"])) <= 1e-9
+
+
+def test_group_argument_errors(torch_dev):
+    import ctypes
+    from paper_1912_13403_amd import hsdm
+    torch, dev = torch_dev
+    lib = hsdm.load_library()
+    n = 8
+    A = torch.zeros((n, n), dtype=torch.float64, device=dev)
+    I1, P1, F1 = ctypes.c_int * 1, ctypes.c_void_p * 1, ctypes.c_double * 1
+    ptr = P1(A.data_ptr())
+    with hsdm.Handle(0) as h:
+        def call(nprob=1, cplx=0, nv=n, ne=1.0, kT=0.0, fm=2.0):
+            return lib.hsdm_solve_dm_group(h._h, nprob, I1(cplx), I1(nv), ptr, I1(n), ptr, I1(n),
+                                           F1(ne), F1(kT), F1(fm), ptr, I1(n), None, None, None,
+                                           None, None)
+        assert call(nprob=0) == -2
+        assert call(cplx=3) == -3
+        assert call(nv=0) == -4
+        assert call(ne=17.0) == -9
+        assert call(kT=-1.0) == -10
+        assert call(fm=0.0) == -11
