@@ -89,6 +89,10 @@ struct hsdm_ctx {
   OccTask* d_tasks = nullptr;
   int d_tasks_cap = 0;
   std::vector<int> tag_m;  // occupied-state count of each task of the last batch
+  Sy2sbGroupHost sy_host;   // panel QR schedule of the last multi-task reduction
+  std::vector<Sy2sbArgs> sy_args;
+  void* d_qr = nullptr;
+  size_t d_qr_bytes = 0;
   std::vector<Sb2stTask> h_sb;
   std::vector<int> h_wgmap;
   void* d_sb = nullptr;  // Sb2stTask[nprob] then the workgroup -> task map
@@ -427,6 +431,7 @@ int hsdm_finalize(hsdm_handle h) {
   h->subs.clear();
   if (h->d_tasks) (void)hipFree(h->d_tasks);
   if (h->d_sb) (void)hipFree(h->d_sb);
+  if (h->d_qr) (void)hipFree(h->d_qr);
   free_ws(h);
   free_cws(h);
   if (h->st) (void)hipFree(h->st);
@@ -949,11 +954,32 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
     if (c->deg_tol < 0.0) DEV_TRY(h, dev_norm1_sym(Hr, ldhr, nr, c->colsum, c->hnorm, s));
     if ((r = standard_form(c, nr, Hr, ldhr, c->Linv, nr, c->Abuf, nr, s))) return r;
     DEV_TRY(h, bt1_zero_fill(nr, BAND, c->Vst, nr, s));
-    DEV_TRY(h, sy2sb_run(nr, BAND, c->Abuf, nr, c->Vst, nr, c->tau1, c->T1, c->AB, 2 * BAND,
-                         c->sy_scr, c->st, s));
-    DEV_TRY(h, sb2st_prepare(c->lay, c->V2, c->tau2, c->progress, s));
     h->h_tasks[p] = OccTask{c->lam, c->fvec, c->occ, c->deg_tol < 0.0 ? c->hnorm : nullptr, nr,
                             t.w};
+  }
+  // full -> band of all tasks, pair step by pair step, the panel QRs of a
+  // step in shared cooperative launches
+  {
+    h->sy_args.resize(nt);
+    for (int p = 0; p < nt; p++) {
+      hsdm_ctx* c = ctx[p];
+      const int nr = T[p].cplx ? 2 * T[p].n : T[p].n;
+      h->sy_args[p] = Sy2sbArgs{nr, c->Abuf, nr, c->Vst, nr, c->tau1, c->T1, c->AB, 2 * BAND,
+                                c->sy_scr, c->st};
+    }
+    const size_t need = sy2sb_group_bytes(nt, h->sy_args.data(), BAND, h->sy_host);
+    if (h->d_qr_bytes < need) {
+      if (h->d_qr) (void)hipFree(h->d_qr);
+      h->d_qr = nullptr;
+      h->d_qr_bytes = 0;
+      DEV_TRY(h, hipMalloc(&h->d_qr, need));
+      h->d_qr_bytes = need;
+    }
+    DEV_TRY(h, sy2sb_run_group(nt, h->sy_args.data(), BAND, h->sy_host, h->d_qr, s));
+    for (int p = 0; p < nt; p++) {
+      hsdm_ctx* c = ctx[p];
+      DEV_TRY(h, sb2st_prepare(c->lay, c->V2, c->tau2, c->progress, s));
+    }
   }
   // 2. bulge chasing of all bands, as many per cooperative launch as fit:
   //    each band alone is latency-bound and fills a small part of the device

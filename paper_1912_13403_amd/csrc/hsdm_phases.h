@@ -1,5 +1,6 @@
 // Host launchers of the reduction, tridiagonal and back-transformation phases.
 #pragma once
+#include <vector>
 #include "hsdm_internal.h"
 
 // sy2sb.hip -- full -> band (half-bandwidth B).  A (lower triangle) is
@@ -10,6 +11,38 @@ size_t sy2sb_scratch_doubles(int n, int B);
 hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, double* tau1,
                      double* T1, double* AB, int ldab, double* scratch, DevStatusWord* st,
                      hipStream_t s);
+
+// The same for several matrices at once: the tasks advance one panel pair
+// per round, and the Householder QRs of the round's panels run in shared
+// cooperative launches (each panel alone fills few compute units).  The
+// host vectors are the caller's (kept until the stream has run the work);
+// d_buf is device memory of sy2sb_group_bytes(...) bytes.
+struct Sy2sbArgs {
+  int n;
+  double* A;
+  long lda;
+  double* Vst;
+  long ldv;
+  double* tau1;
+  double* T1;
+  double* AB;
+  int ldab;
+  double* scratch;
+  DevStatusWord* st;
+};
+struct PanelQrTask {
+  double *P, *V, *tau, *T, *part, *prow, *gpart;
+  DevStatusWord* st;
+  long ldp, ldv, span;
+  int h, g0, G, pad;
+};
+struct Sy2sbGroupHost {
+  std::vector<PanelQrTask> desc;
+  std::vector<int> wgmap;
+};
+size_t sy2sb_group_bytes(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& host);
+hipError_t sy2sb_run_group(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& host, void* d_buf,
+                           hipStream_t s);
 
 // sb2st.hip -- band -> tridiagonal by bulge chasing.  ldab must be 2B and AB
 // must have B + 1 spare columns after the n used ones.  AB is overwritten;

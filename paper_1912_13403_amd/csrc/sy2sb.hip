@@ -126,10 +126,9 @@ __global__ void fill_nan_kernel(double* p, long cnt) {
 // wavefronts by shuffles, across the 4 wavefronts through LDS and across
 // the workgroups through global partial sums and one grid barrier.
 template <int B>
-__global__ __launch_bounds__(NT) void panel_qr_kernel(int h, double* P, long ldp, double* V,
-                                                      long ldv, double* tau_out, double* Tt,
-                                                      double* part, double* prow, double* gpart,
-                                                      DevStatusWord* st) {
+HSDM_DEV void panel_qr_body(int h, double* P, long ldp, double* V, long ldv, double* tau_out,
+                            double* Tt, double* part, double* prow, double* gpart,
+                            DevStatusWord* st, int g, int G) {
   static_assert(NT == CH && B == 32, "one row per thread, 32 columns");
   constexpr int NW = NT / 64;
   constexpr int RG = NT / B;  // threads per column when combining partial sums
@@ -139,7 +138,6 @@ __global__ __launch_bounds__(NT) void panel_qr_kernel(int h, double* P, long ldp
   __shared__ double Gm[B][B + 1], Tl[B][B + 1];
   __shared__ double cmb[RG][B + 1];
 
-  const int g = blockIdx.x, G = gridDim.x;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int row0 = g * CH;
   const int nrows = min(CH, h - row0);
@@ -286,6 +284,34 @@ __global__ __launch_bounds__(NT) void panel_qr_kernel(int h, double* P, long ldp
   for (int e = t; e < B * B; e += NT) Tt[e] = Tl[e % B][e / B];
 }
 
+template <int B>
+__global__ __launch_bounds__(NT) void panel_qr_kernel(int h, double* P, long ldp, double* V,
+                                                      long ldv, double* tau_out, double* Tt,
+                                                      double* part, double* prow, double* gpart,
+                                                      DevStatusWord* st) {
+  panel_qr_body<B>(h, P, ldp, V, ldv, tau_out, Tt, part, prow, gpart, st, blockIdx.x, gridDim.x);
+}
+
+// The panels of several tasks in one cooperative launch: workgroups g0 ..
+// g0 + G - 1 of the grid hold the rows of panel task wg_task[blockIdx.x].
+template <int B>
+__global__ __launch_bounds__(NT) void panel_qr_group_kernel(const PanelQrTask* tasks,
+                                                            const int* wg_task) {
+  const int p = __builtin_amdgcn_readfirstlane(wg_task[blockIdx.x]);
+  const PanelQrTask& q = tasks[p];
+  panel_qr_body<B>(q.h, q.P, q.ldp, q.V, q.ldv, q.tau, q.T, q.part, q.prow, q.gpart, q.st,
+                   (int)blockIdx.x - q.g0, q.G);
+}
+
+// Exchange slots of the panels of a grouped launch back to NaN (task
+// blockIdx.y of the list; span 0 for single-workgroup panels).
+__global__ void fill_nan_group_kernel(const PanelQrTask* tasks) {
+  const PanelQrTask& q = tasks[blockIdx.y];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < q.span;
+       i += (long)gridDim.x * blockDim.x)
+    q.part[i] = __builtin_nan("");
+}
+
 // Band extraction: AB[(r-c) + c*ldab] = A[r + c*lda] for 0 <= r-c <= B, zero
 // for B < r-c < ldab.
 __global__ void band_extract_kernel(int n, int B, const double* A, long lda, double* AB,
@@ -354,55 +380,91 @@ size_t sy2sb_scratch_doubles(int n, int B) {
 //   then one rank-4B update A22[B:, B:] -= [V1b W1b V2 W2][W1b V1b W2 V2]^T,
 // which halves the passes over the trailing matrix.  The products are the
 // same as panel by panel; only the order of the roundings differs.
-hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, double* tau1,
-                     double* T1, double* AB, int ldab, double* scratch, DevStatusWord* st,
-                     hipStream_t s) {
-  if (B != 32) return hipErrorInvalidValue;
-  constexpr int BB = 32;
-  const int Gmax = ceil_div(n, CH) + 1;
-  double* part = scratch;                        // B x Gmax x B exchange slots
-  double* prow = part + (size_t)B * Gmax * B;    // B x B
-  double* gpart = prow + (size_t)B * B;          // Gmax x B x B
-  double* apart = gpart + (size_t)Gmax * B * B;
-  double* Y = apart + (size_t)Gmax * B * B;      // n x B
-  double* VW = Y + (size_t)n * B;                // n x 4B  [V1 W1 V2 W2], row i <-> row r0 + i
-  double* WV = VW + (size_t)n * 4 * B;           // n x 4B  [W1 V1 W2 V2]
-  double* M = WV + (size_t)n * 4 * B;            // B x B
-  double* Qc = M + B * B;                        // 2B x B
-  double* skpart = Qc + 2 * B * B + 64;          // split-K partials
+namespace {
+
+// One matrix's full-to-band reduction: its pointers, the layout of its
+// scratch, and the steps between panel QRs.
+struct Sy2sb {
+  static constexpr int BB = 32;
+  int n, B;
+  double* A;
+  long lda;
+  double* Vst;
+  long ldv;
+  double *tau1, *T1, *AB;
+  int ldab;
+  DevStatusWord* st;
+  hipStream_t s;
+  int Gmax;
+  double *part, *prow, *gpart, *apart, *Y, *VW, *WV, *M, *Qc, *skpart;
+
+  Sy2sb(const Sy2sbArgs& a, int B_, hipStream_t s_)
+      : n(a.n), B(B_), A(a.A), lda(a.lda), Vst(a.Vst), ldv(a.ldv), tau1(a.tau1), T1(a.T1),
+        AB(a.AB), ldab(a.ldab), st(a.st), s(s_) {
+    Gmax = ceil_div(n, CH) + 1;
+    part = a.scratch;                      // B x Gmax x B exchange slots
+    prow = part + (size_t)B * Gmax * B;    // B x B
+    gpart = prow + (size_t)B * B;          // Gmax x B x B
+    apart = gpart + (size_t)Gmax * B * B;
+    Y = apart + (size_t)Gmax * B * B;      // n x B
+    VW = Y + (size_t)n * B;                // n x 4B  [V1 W1 V2 W2], row i <-> row r0 + i
+    WV = VW + (size_t)n * 4 * B;           // n x 4B  [W1 V1 W2 V2]
+    M = WV + (size_t)n * 4 * B;            // B x B
+    Qc = M + B * B;                        // 2B x B
+    skpart = Qc + 2 * B * B + 64;          // split-K partials
+  }
+  int npanel() const { return (n > B) ? ceil_div(n - 1, B) : 0; }
+  int height(int p) const { return n - (p + 1) * B; }
+  // panels reduced after panel p's QR: 1 (alone), 2 (p + 1 with it, its QR next)
+  int advance(int p) const {
+    const int h = height(p);
+    if (h <= 1) return 1;
+    return (p + 1 < npanel() && h - B > 1) ? 2 : 1;
+  }
 
   // Householder QR of panel p (rows r0.., columns c0..c0+B-1)
-  auto qr_panel = [&](int p) -> hipError_t {
+  PanelQrTask qr_desc(int p) const {
     const int c0 = p * B, r0 = c0 + B, h = n - r0;
-    double* Pp = A + r0 + (long)c0 * lda;
-    double* Vp = Vst + r0 + (long)c0 * ldv;
-    double* Tp = T1 + (size_t)p * B * B;
-    double* tau_p = tau1 + c0;
-    const int G = ceil_div(h, CH);
-    if (G > 1) {
-      // exchange slots of this launch back to NaN (part, prow, gpart are contiguous)
-      const long cnt = (long)B * G * B + (long)B * B + (long)B * B * G;
-      const long span = (long)(gpart - part) + (long)B * B * G;
-      hipLaunchKernelGGL(fill_nan_kernel, dim3((unsigned)((span + 255) / 256)), dim3(256), 0, s,
-                         part, span);
+    PanelQrTask q{};
+    q.P = A + r0 + (long)c0 * lda;
+    q.V = Vst + r0 + (long)c0 * ldv;
+    q.tau = tau1 + c0;
+    q.T = T1 + (size_t)p * B * B;
+    q.part = part;
+    q.prow = prow;
+    q.gpart = gpart;
+    q.st = st;
+    q.ldp = lda;
+    q.ldv = ldv;
+    q.h = h;
+    q.G = ceil_div(h, CH);
+    // exchange slots of a multi-workgroup panel back to NaN (part, prow,
+    // gpart are contiguous)
+    q.span = q.G > 1 ? (long)(gpart - part) + (long)B * B * q.G : 0;
+    return q;
+  }
+  hipError_t qr_panel(int p) {
+    PanelQrTask q = qr_desc(p);
+    if (q.span > 0) {
+      hipLaunchKernelGGL(fill_nan_kernel, dim3((unsigned)((q.span + 255) / 256)), dim3(256), 0, s,
+                         part, q.span);
       HSDM_TRY(hipGetLastError());
-      (void)cnt;
     }
-    void* args[] = {(void*)&h, (void*)&Pp, (void*)&lda, (void*)&Vp, (void*)&ldv,
-                    (void*)&tau_p, (void*)&Tp, (void*)&part, (void*)&prow, (void*)&gpart,
-                    (void*)&st};
+    void* args[] = {(void*)&q.h, (void*)&q.P, (void*)&q.ldp, (void*)&q.V, (void*)&q.ldv,
+                    (void*)&q.tau, (void*)&q.T, (void*)&q.part, (void*)&q.prow, (void*)&q.gpart,
+                    (void*)&q.st};
     // algorithmic: Householder QR of the h x B panel (2 h B^2 flops), the
     // panel read and written once
-    kt_begin("panel_qr_kernel<32>", 2.0 * h * B * B, 16.0 * h * B, 0, s);
-    HSDM_TRY(hipLaunchCooperativeKernel((const void*)panel_qr_kernel<BB>, dim3(G), dim3(NT), args,
-                                        0, s));
+    kt_begin("panel_qr_kernel<32>", 2.0 * q.h * B * B, 16.0 * q.h * B, 0, s);
+    HSDM_TRY(hipLaunchCooperativeKernel((const void*)panel_qr_kernel<BB>, dim3(q.G), dim3(NT),
+                                        args, 0, s));
     kt_end(s);
     return hipSuccess;
-  };
+  }
   // W (h x B, ld n, holding X on entry) = X - V M / 2 with Y = V T, X = A[r:, r:] Y,
   // M = Y^T X.  Vp: the panel's V (ld ldv), Tp its T; Y receives V T.
-  auto make_w = [&](int r, int h, const double* Vp, const double* Tp, double* Wp,
-                    bool correct, const double* VWc, const double* WVc) -> hipError_t {
+  hipError_t make_w(int r, int h, const double* Vp, const double* Tp, double* Wp, bool correct,
+                    const double* VWc, const double* WVc) {
     GemmArgs g{};
     g.m = h; g.n = B; g.k = B; g.A = Vp; g.lda = ldv; g.B = Tp; g.ldb = B; g.C = Y; g.ldc = n;
     g.alpha = 1.0; g.beta = 0.0; g.flags = GF_KB_UPPER;
@@ -435,30 +497,24 @@ hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, d
     hipLaunchKernelGGL((atb_reduce_kernel<BB>), dim3(ceil_div(B * B, 256)), dim3(256), 0, s, G,
                        apart, M, (long)B);
     HSDM_TRY(hipGetLastError());
-    // W = X - V M / 2
     g = GemmArgs{};
     g.m = h; g.n = B; g.k = B; g.A = Vp; g.lda = ldv; g.B = M; g.ldb = B; g.C = Wp; g.ldc = n;
     g.alpha = -0.5; g.beta = 1.0;
     return gemm_launch(g, s);
-  };
+  }
   // A[r:, r:] -= VWr WVr^T (lower), k columns
-  auto syr2k = [&](int r, int h, const double* VWr, const double* WVr, int k) -> hipError_t {
+  hipError_t syr2k(int r, int h, const double* VWr, const double* WVr, int k) {
     GemmArgs g{};
     g.m = h; g.n = h; g.k = k; g.A = VWr; g.lda = n; g.B = WVr; g.ldb = n;
     g.C = A + r + (long)r * lda; g.ldc = lda; g.alpha = -1.0; g.beta = 1.0; g.ta = 0; g.tb = 1;
     g.flags = GF_C_LOWER_TILES | GF_C_LOWER_ONLY;
     return gemm_launch(g, s);
-  };
-
-  const int npanel = (n > B) ? ceil_div(n - 1, B) : 0;
-  for (int p = 0; p < npanel;) {
+  }
+  // after the QR of panel p: its W, and either the trailing update (panel
+  // alone) or the update of panel p+1's columns (pair)
+  hipError_t after_first(int p) {
     const int c0 = p * B, r0 = c0 + B, h = n - r0;
-    if (h <= 0) break;
-    HSDM_TRY(qr_panel(p));
-    if (h <= 1) {
-      p++;
-      continue;
-    }
+    if (h <= 1) return hipSuccess;
     const double* V1 = Vst + r0 + (long)c0 * ldv;
     const double* T1p = T1 + (size_t)p * B * B;
     double* W1 = VW + (size_t)n * B;
@@ -467,23 +523,18 @@ hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, d
     HSDM_TRY(dev_copy(V1, ldv, VW, n, h, B, s));
     HSDM_TRY(dev_copy(W1, n, WV, n, h, B, s));
     HSDM_TRY(dev_copy(V1, ldv, WV + (size_t)n * B, n, h, B, s));
-    const int h2 = h - B;
-    const bool pair = (p + 1 < npanel) && h2 > 1;
-    if (!pair) {
-      HSDM_TRY(syr2k(r0, h, VW, WV, 2 * B));
-      p++;
-      continue;
-    }
+    if (advance(p) == 1) return syr2k(r0, h, VW, WV, 2 * B);
     // columns of panel p+1: A[r0:, r0:r0+B] -= [V1 W1] [W1 V1][0:B]^T (lower part)
-    {
-      GemmArgs g{};
-      g.m = h; g.n = B; g.k = 2 * B; g.A = VW; g.lda = n; g.B = WV; g.ldb = n;
-      g.C = A + r0 + (long)r0 * lda; g.ldc = lda; g.alpha = -1.0; g.beta = 1.0; g.ta = 0;
-      g.tb = 1; g.flags = GF_C_LOWER_ONLY;
-      HSDM_TRY(gemm_launch(g, s));
-    }
-    HSDM_TRY(qr_panel(p + 1));
-    const int r1 = r0 + B;
+    GemmArgs g{};
+    g.m = h; g.n = B; g.k = 2 * B; g.A = VW; g.lda = n; g.B = WV; g.ldb = n;
+    g.C = A + r0 + (long)r0 * lda; g.ldc = lda; g.alpha = -1.0; g.beta = 1.0; g.ta = 0;
+    g.tb = 1; g.flags = GF_C_LOWER_ONLY;
+    return gemm_launch(g, s);
+  }
+  // after the QR of panel p+1 of a pair: its W (with the first panel's
+  // delayed update) and the pair's rank-4B trailing update
+  hipError_t after_second(int p) {
+    const int r0 = (p + 1) * B, h2 = n - r0 - B, r1 = r0 + B;
     const double* V2 = Vst + r1 + (long)r0 * ldv;
     const double* T2p = T1 + (size_t)(p + 1) * B * B;
     double* W2 = VW + B + (size_t)3 * n * B;
@@ -492,11 +543,160 @@ hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, d
     HSDM_TRY(dev_copy(V2, ldv, VW + B + (size_t)2 * n * B, n, h2, B, s));
     HSDM_TRY(dev_copy(W2, n, WV + B + (size_t)2 * n * B, n, h2, B, s));
     HSDM_TRY(dev_copy(V2, ldv, WV + B + (size_t)3 * n * B, n, h2, B, s));
-    HSDM_TRY(syr2k(r1, h2, VW + B, WV + B, 4 * B));
-    p += 2;
+    return syr2k(r1, h2, VW + B, WV + B, 4 * B);
   }
-  const long tot = (long)n * ldab;
-  hipLaunchKernelGGL(band_extract_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n,
-                     B, A, lda, AB, ldab);
-  return hipGetLastError();
+  hipError_t finish() {
+    const long tot = (long)n * ldab;
+    hipLaunchKernelGGL(band_extract_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       n, B, A, lda, AB, ldab);
+    return hipGetLastError();
+  }
+};
+
+}  // namespace
+
+hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, double* tau1,
+                     double* T1, double* AB, int ldab, double* scratch, DevStatusWord* st,
+                     hipStream_t s) {
+  if (B != 32) return hipErrorInvalidValue;
+  Sy2sb R(Sy2sbArgs{n, A, lda, Vst, ldv, tau1, T1, AB, ldab, scratch, st}, B, s);
+  for (int p = 0; p < R.npanel();) {
+    if (R.height(p) <= 0) break;
+    HSDM_TRY(R.qr_panel(p));
+    HSDM_TRY(R.after_first(p));
+    const int adv = R.advance(p);
+    if (adv == 2) {
+      HSDM_TRY(R.qr_panel(p + 1));
+      HSDM_TRY(R.after_second(p));
+    }
+    p += adv;
+  }
+  return R.finish();
+}
+
+namespace {
+
+constexpr int PQR_MAX_WG = 256;  // one panel workgroup per compute unit (LDS)
+
+// The rounds of a multi-task reduction: round k performs one pair step of
+// every task that still has panels.  Returns, per round, the tasks and the
+// panel each starts at.
+std::vector<std::vector<std::pair<int, int>>> group_rounds(const std::vector<Sy2sb>& R) {
+  std::vector<std::vector<std::pair<int, int>>> rounds;
+  std::vector<int> p(R.size(), 0);
+  for (;;) {
+    std::vector<std::pair<int, int>> r;
+    for (size_t t = 0; t < R.size(); t++)
+      if (p[t] < R[t].npanel() && R[t].height(p[t]) > 0) r.emplace_back((int)t, p[t]);
+    if (r.empty()) break;
+    for (auto& e : r) p[e.first] += R[e.first].advance(e.second);
+    rounds.push_back(std::move(r));
+  }
+  return rounds;
+}
+
+// Descriptors of the grouped QR launches in schedule order: for each round,
+// the first panels, then the second panels; each list cut into launches of
+// at most PQR_MAX_WG workgroups.  launch = (first descriptor, count, first
+// map entry, workgroups).
+struct QrLaunch {
+  int d0, nd, m0, nwg;
+};
+
+void build_schedule(const std::vector<Sy2sb>& R, Sy2sbGroupHost& host,
+                    std::vector<std::vector<QrLaunch>>& first,
+                    std::vector<std::vector<QrLaunch>>& second,
+                    std::vector<std::vector<std::pair<int, int>>>& rounds) {
+  rounds = group_rounds(R);
+  host.desc.clear();
+  host.wgmap.clear();
+  first.assign(rounds.size(), {});
+  second.assign(rounds.size(), {});
+  auto emit = [&](const std::vector<PanelQrTask>& list, std::vector<QrLaunch>& out) {
+    size_t i = 0;
+    while (i < list.size()) {
+      QrLaunch L{(int)host.desc.size(), 0, (int)host.wgmap.size(), 0};
+      while (i < list.size() && (L.nd == 0 || L.nwg + list[i].G <= PQR_MAX_WG)) {
+        PanelQrTask q = list[i++];
+        q.g0 = L.nwg;
+        for (int w = 0; w < q.G; w++) host.wgmap.push_back(L.nd);  // index within the launch
+        L.nwg += q.G;
+        L.nd++;
+        host.desc.push_back(q);
+      }
+      out.push_back(L);
+    }
+  };
+  for (size_t k = 0; k < rounds.size(); k++) {
+    std::vector<PanelQrTask> a, b;
+    for (auto& e : rounds[k]) {
+      a.push_back(R[e.first].qr_desc(e.second));
+      if (R[e.first].advance(e.second) == 2) b.push_back(R[e.first].qr_desc(e.second + 1));
+    }
+    emit(a, first[k]);
+    emit(b, second[k]);
+  }
+}
+
+hipError_t launch_qr_group(const QrLaunch& L, PanelQrTask* d_desc, int* d_map, const double* fl,
+                           hipStream_t s) {
+  PanelQrTask* tasks = d_desc + L.d0;
+  const int* map = d_map + L.m0;
+  hipLaunchKernelGGL(fill_nan_group_kernel, dim3(64, L.nd), dim3(256), 0, s, tasks);
+  HSDM_TRY(hipGetLastError());
+  void* args[] = {(void*)&tasks, (void*)&map};
+  kt_begin("panel_qr_group_kernel<32>", *fl, 0.0, 0, s);
+  HSDM_TRY(hipLaunchCooperativeKernel((const void*)panel_qr_group_kernel<32>, dim3(L.nwg),
+                                      dim3(NT), args, 0, s));
+  kt_end(s);
+  return hipSuccess;
+}
+
+}  // namespace
+
+size_t sy2sb_group_bytes(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& host) {
+  std::vector<Sy2sb> R;
+  for (int i = 0; i < nt; i++) R.emplace_back(t[i], B, nullptr);
+  std::vector<std::vector<QrLaunch>> first, second;
+  std::vector<std::vector<std::pair<int, int>>> rounds;
+  build_schedule(R, host, first, second, rounds);
+  return sizeof(PanelQrTask) * (host.desc.size() + 1) + sizeof(int) * (host.wgmap.size() + 1);
+}
+
+hipError_t sy2sb_run_group(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& host, void* d_buf,
+                           hipStream_t s) {
+  if (B != 32) return hipErrorInvalidValue;
+  std::vector<Sy2sb> R;
+  for (int i = 0; i < nt; i++) R.emplace_back(t[i], B, s);
+  std::vector<std::vector<QrLaunch>> first, second;
+  std::vector<std::vector<std::pair<int, int>>> rounds;
+  build_schedule(R, host, first, second, rounds);
+  PanelQrTask* d_desc = (PanelQrTask*)d_buf;
+  int* d_map = (int*)((char*)d_buf + sizeof(PanelQrTask) * (host.desc.size() + 1));
+  if (!host.desc.empty()) {
+    HSDM_TRY(hipMemcpyAsync(d_desc, host.desc.data(), sizeof(PanelQrTask) * host.desc.size(),
+                            hipMemcpyHostToDevice, s));
+    HSDM_TRY(hipMemcpyAsync(d_map, host.wgmap.data(), sizeof(int) * host.wgmap.size(),
+                            hipMemcpyHostToDevice, s));
+  }
+  auto flops = [&](const QrLaunch& L) {
+    double f = 0.0;
+    for (int i = 0; i < L.nd; i++) f += 2.0 * host.desc[L.d0 + i].h * B * B;
+    return f;
+  };
+  for (size_t k = 0; k < rounds.size(); k++) {
+    for (const QrLaunch& L : first[k]) {
+      const double f = flops(L);
+      HSDM_TRY(launch_qr_group(L, d_desc, d_map, &f, s));
+    }
+    for (auto& e : rounds[k]) HSDM_TRY(R[e.first].after_first(e.second));
+    for (const QrLaunch& L : second[k]) {
+      const double f = flops(L);
+      HSDM_TRY(launch_qr_group(L, d_desc, d_map, &f, s));
+    }
+    for (auto& e : rounds[k])
+      if (R[e.first].advance(e.second) == 2) HSDM_TRY(R[e.first].after_second(e.second));
+  }
+  for (auto& r : R) HSDM_TRY(r.finish());
+  return hipSuccess;
 }
