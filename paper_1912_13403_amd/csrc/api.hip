@@ -93,6 +93,10 @@ struct hsdm_ctx {
   std::vector<Sy2sbArgs> sy_args;
   void* d_qr = nullptr;
   size_t d_qr_bytes = 0;
+  std::vector<Bt2Task> h_bt2;  // stage-2 back-transform descriptors of the last multi-task solve
+  std::vector<int> h_bt2map;
+  void* d_bt2 = nullptr;
+  size_t d_bt2_bytes = 0;
   std::vector<Sb2stTask> h_sb;
   std::vector<int> h_wgmap;
   void* d_sb = nullptr;  // Sb2stTask[nprob] then the workgroup -> task map
@@ -432,6 +436,7 @@ int hsdm_finalize(hsdm_handle h) {
   if (h->d_tasks) (void)hipFree(h->d_tasks);
   if (h->d_sb) (void)hipFree(h->d_sb);
   if (h->d_qr) (void)hipFree(h->d_qr);
+  if (h->d_bt2) (void)hipFree(h->d_bt2);
   free_ws(h);
   free_cws(h);
   if (h->st) (void)hipFree(h->st);
@@ -1055,15 +1060,36 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
     DEV_TRY(h, occupations_joint_launch(nt, h->d_tasks, h->fmax, ne, kT, h->deg_tol,
                                         h->fcut_rel * h->fmax, h->occ, h->st, s));
   }
-  // 5. every task: back-transforms of its occupied vectors, D and E
+  // 5. stage-2 back-transform of all tasks' occupied vectors in one launch
+  h->h_bt2.resize(nt);
+  for (int p = 0; p < nt; p++) {
+    hsdm_ctx* c = ctx[p];
+    const int nr = T[p].cplx ? 2 * T[p].n : T[p].n;
+    DEV_TRY(h, bt2_prepare(c->lay, c->V2, c->tau2, c->F2, s));
+    h->h_bt2[p] = bt2_task(c->lay, c->F2, c->d_goff, c->Zbuf, nr, nr, &c->occ->m, c->progress,
+                           c->st);
+  }
+  {
+    const size_t need = sizeof(Bt2Task) * (nt + 1) +
+                        sizeof(int) * (bt2_group_map_ints(nt, h->h_bt2.data()) + 1);
+    if (h->d_bt2_bytes < need) {
+      if (h->d_bt2) (void)hipFree(h->d_bt2);
+      h->d_bt2 = nullptr;
+      h->d_bt2_bytes = 0;
+      DEV_TRY(h, hipMalloc(&h->d_bt2, need));
+      h->d_bt2_bytes = need;
+    }
+    Bt2Task* d_t = (Bt2Task*)h->d_bt2;
+    int* d_m = (int*)((char*)h->d_bt2 + sizeof(Bt2Task) * (nt + 1));
+    DEV_TRY(h, bt2_group_apply(nt, h->h_bt2.data(), h->h_bt2map, d_t, d_m, s));
+  }
+  // 6. every task: the other back-transforms, D and E
   for (int p = 0; p < nt; p++) {
     kt_set_tag(p);
     hsdm_ctx* c = ctx[p];
     const TaskSpec& t = T[p];
     const int nr = t.cplx ? 2 * t.n : t.n;
     const int* m_dev = &c->occ->m;
-    DEV_TRY(h, bt2_prepare(c->lay, c->V2, c->tau2, c->F2, s));
-    DEV_TRY(h, bt2_apply(c->lay, c->F2, c->d_goff, c->Zbuf, nr, nr, m_dev, c->progress, c->st, s));
     DEV_TRY(h, bt1_apply(nr, BAND, c->Vst, nr, c->T1, c->Zbuf, nr, nr, m_dev, c->bt1_scr, s));
     GemmArgs g{};
     g.m = nr; g.n = nr; g.k = nr; g.A = c->Linv; g.lda = nr; g.B = c->Zbuf; g.ldb = nr;
@@ -1083,6 +1109,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
   kt_set_tag(-1);
   // status of every task, then of the shared occupations
   h->tag_m.assign(nt, 0);
+  double bt2_work = 0.0;
   for (int p = 0; p < nt; p++) {
     hsdm_ctx* c = ctx[p];
     if ((r = finish(c, s))) {
@@ -1092,10 +1119,12 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
       return r;
     }
     h->tag_m[p] = c->host->occ.m;
+    bt2_work += bt2_flops(c->lay, c->host->occ.m);
     const double half = T[p].cplx ? 0.5 : 1.0;
     if (eb_each) eb_each[p] = half * c->host->occ.band_energy;
     if (mu_each) mu_each[p] = c->host->occ.mu;
   }
+  kt_set_last_work("bt2_group_kernel", bt2_work, 0.0);
   r = finish(h, s);
   h->tag_m.clear();
   if (mu_shared) *mu_shared = h->host->occ.mu;

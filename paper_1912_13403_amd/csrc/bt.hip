@@ -97,20 +97,12 @@ HSDM_DEV int key_of(int nblk, int b) { return (nblk - 1 - b) * KEYM; }
 // (k, strip) applies range k (k = 0 holds the last sweep blocks, which come
 // first) to its strip once workgroup (k-1, strip) has finished, so that the
 // strips' work is spread over NSPLIT times as many workgroups.
-constexpr int NSPLIT = 4;
-struct SplitRanges {
-  int hi[NSPLIT];  // range k covers sweep blocks lo[k] .. hi[k] (hi[k] = lo[k-1] - 1)
-  int lo[NSPLIT];
-};
 
-// Held to 256 registers per lane so that two wavefronts share each SIMD.
-__global__ __launch_bounds__(64 * PW) __attribute__((amdgpu_waves_per_eu(2))) void bt2_strip_kernel(int n, int nblk, SplitRanges R,
-                                                            int nstrip, const double* F2,
-                                                            const long* goff, double* Z, long ldz,
-                                                            int m_host, const int* m_dev,
-                                                            int* done, DevStatusWord* st) {
-  const int m = m_dev ? *m_dev : m_host;
-  const int strip = blockIdx.x % nstrip, kr = blockIdx.x / nstrip;
+// Workgroup blk of one Z's launch: strip blk % nstrip, range blk / nstrip.
+HSDM_DEV void bt2_strip_body(int n, int nblk, const SplitRanges& R, int nstrip,
+                             const double* F2, const long* goff, double* Z, long ldz, int m,
+                             int* done, DevStatusWord* st, int blk) {
+  const int strip = blk % nstrip, kr = blk / nstrip;
   const int c0 = strip * 16;
   if (c0 >= m) return;  // (every range of this strip returns here)
   __shared__ int prog[PW];
@@ -310,6 +302,26 @@ __global__ __launch_bounds__(64 * PW) __attribute__((amdgpu_waves_per_eu(2))) vo
   }
 }
 
+// Held to 256 registers per lane so that two wavefronts share each SIMD.
+__global__ __launch_bounds__(64 * PW) __attribute__((amdgpu_waves_per_eu(2))) void bt2_strip_kernel(
+    int n, int nblk, SplitRanges R, int nstrip, const double* F2, const long* goff, double* Z,
+    long ldz, int m_host, const int* m_dev, int* done, DevStatusWord* st) {
+  const int m = m_dev ? *m_dev : m_host;
+  bt2_strip_body(n, nblk, R, nstrip, F2, goff, Z, ldz, m, done, st, blockIdx.x);
+}
+
+// Several Z's in one launch: workgroups b0 .. b0 + nstrip * NSPLIT - 1 of the
+// grid are the workgroups of task blk_task[blockIdx.x], in that task's own
+// order, so a range still waits only for a workgroup with a lower index.
+__global__ __launch_bounds__(64 * PW) __attribute__((amdgpu_waves_per_eu(2))) void bt2_group_kernel(
+    const Bt2Task* tasks, const int* blk_task) {
+  const int p = __builtin_amdgcn_readfirstlane(blk_task[blockIdx.x]);
+  const Bt2Task& q = tasks[p];
+  const int m = q.m_dev ? *q.m_dev : q.m;
+  bt2_strip_body(q.n, q.nblk, q.R, q.nstrip, q.F2, q.goff, q.Z, q.ldz, m, q.done, q.st,
+                 (int)blockIdx.x - q.b0);
+}
+
 }  // namespace
 
 size_t bt2_pack_doubles(const Sb2stLayout& L) { return (size_t)L.ngroups * GREC; }
@@ -321,35 +333,86 @@ hipError_t bt2_prepare(const Sb2stLayout& L, const double* V2, const double* tau
   return hipGetLastError();
 }
 
-hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff, double* Z,
-                     long ldz, int m, const int* m_dev, int* iscratch, DevStatusWord* st,
-                     hipStream_t s) {
-  if (L.ngroups <= 0 || m <= 0) return hipSuccess;
+Bt2Task bt2_task(const Sb2stLayout& L, const double* F2, const long* d_goff, double* Z,
+                 long ldz, int m, const int* m_dev, int* iscratch, DevStatusWord* st) {
   const int n = L.n, nblk = L.nblk;
   // sweep-block ranges of about equal work (tasks), last blocks first
   auto tgb = [&](int b) { return (n - 1 - b * B + B - 1) / B; };
   long tot = 0;
   for (int b = 0; b < nblk; b++) tot += tgb(b);
-  SplitRanges R{};
+  Bt2Task q{};
   int b = nblk - 1;
   for (int k = 0; k < NSPLIT; k++) {
-    R.hi[k] = b;
+    q.R.hi[k] = b;
     const long want = tot * (k + 1) / NSPLIT;
     long acc = 0;
-    for (int q = nblk - 1; q > b; q--) acc += tgb(q);
+    for (int r = nblk - 1; r > b; r--) acc += tgb(r);
     while (b >= 0 && (acc < want || k == NSPLIT - 1)) acc += tgb(b--);
-    R.lo[k] = b + 1;
+    q.R.lo[k] = b + 1;
   }
-  const int nstrip = ceil_div(m, 16);
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(ceil_div(nstrip, 256)), dim3(256), 0, s, iscratch,
-                     nstrip);
+  q.n = n;
+  q.nblk = nblk;
+  q.nstrip = ceil_div(m, 16);
+  q.F2 = F2;
+  q.goff = d_goff;
+  q.Z = Z;
+  q.ldz = ldz;
+  q.m = m;
+  q.m_dev = m_dev;
+  q.done = iscratch;
+  q.st = st;
+  return q;
+}
+
+double bt2_flops(const Sb2stLayout& L, int m) {
+  // per group and column of Z: V^T z (B^2 multiply-adds on the parallelogram),
+  // T w (B(B+1)/2) and z - V w (B^2)
+  return 2.0 * (double)L.ngroups * (2.0 * B * B + 0.5 * B * (B + 1)) * m;
+}
+
+hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff, double* Z,
+                     long ldz, int m, const int* m_dev, int* iscratch, DevStatusWord* st,
+                     hipStream_t s) {
+  if (L.ngroups <= 0 || m <= 0) return hipSuccess;
+  const Bt2Task q = bt2_task(L, F2, d_goff, Z, ldz, m, m_dev, iscratch, st);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(ceil_div(q.nstrip, 256)), dim3(256), 0, s, iscratch,
+                     q.nstrip);
   HSDM_TRY(hipGetLastError());
-  // algorithmic: per group and column of Z, V^T z (B^2 multiply-adds on the
-  // parallelogram), T w (B(B+1)/2) and z - V w (B^2)
-  const double fl = 2.0 * (double)L.ngroups * (2.0 * B * B + 0.5 * B * (B + 1)) * m;
-  kt_begin("bt2_strip_kernel", fl, 0.0, m_dev ? m : 0, s, true);
-  hipLaunchKernelGGL(bt2_strip_kernel, dim3(nstrip * NSPLIT), dim3(64 * PW), 0, s, n, nblk, R,
-                     nstrip, F2, d_goff, Z, ldz, m, m_dev, iscratch, st);
+  kt_begin("bt2_strip_kernel", bt2_flops(L, m), 0.0, m_dev ? m : 0, s, true);
+  hipLaunchKernelGGL(bt2_strip_kernel, dim3(q.nstrip * NSPLIT), dim3(64 * PW), 0, s, q.n, q.nblk,
+                     q.R, q.nstrip, F2, d_goff, Z, ldz, m, m_dev, iscratch, st);
+  kt_end(s);
+  return hipGetLastError();
+}
+
+size_t bt2_group_map_ints(int nt, const Bt2Task* tasks) {
+  size_t c = 0;
+  for (int i = 0; i < nt; i++) c += (size_t)tasks[i].nstrip * NSPLIT;
+  return c;
+}
+
+hipError_t bt2_group_apply(int nt, Bt2Task* tasks, std::vector<int>& hmap, Bt2Task* d_tasks,
+                           int* d_map, hipStream_t s) {
+  hmap.clear();
+  int b0 = 0;
+  for (int i = 0; i < nt; i++) {
+    Bt2Task& q = tasks[i];
+    q.b0 = b0;
+    const int cnt = (q.nblk > 0 && q.m > 0) ? q.nstrip * NSPLIT : 0;
+    for (int k = 0; k < cnt; k++) hmap.push_back(i);
+    b0 += cnt;
+    if (cnt > 0) {
+      hipLaunchKernelGGL(fill_i32_kernel, dim3(ceil_div(q.nstrip, 256)), dim3(256), 0, s, q.done,
+                         q.nstrip);
+      HSDM_TRY(hipGetLastError());
+    }
+  }
+  if (b0 == 0) return hipSuccess;
+  HSDM_TRY(hipMemcpyAsync(d_tasks, tasks, sizeof(Bt2Task) * nt, hipMemcpyHostToDevice, s));
+  HSDM_TRY(hipMemcpyAsync(d_map, hmap.data(), sizeof(int) * hmap.size(), hipMemcpyHostToDevice,
+                          s));
+  kt_begin("bt2_group_kernel", 0.0, 0.0, 0, s, true);
+  hipLaunchKernelGGL(bt2_group_kernel, dim3(b0), dim3(64 * PW), 0, s, d_tasks, d_map);
   kt_end(s);
   return hipGetLastError();
 }

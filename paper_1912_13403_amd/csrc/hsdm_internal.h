@@ -79,6 +79,9 @@ void kt_end(hipStream_t s);
 // Records made after kt_set_tag(t) carry tag t (-1: none); a solve of several
 // tasks tags each task's launches with its index.
 void kt_set_tag(int t);
+// Set the work of the most recent record of kernel `name` (work known only
+// after the launch, e.g. from device-side counts read back later).
+void kt_set_last_work(const char* name, double flops, double bytes);
 // After the stream is synchronized: fold records into per-kernel totals (m =
 // the device-side count for records with nbound > 0, < 0 if unknown; a record
 // with tag t < ntag uses tag_m[t] instead).

@@ -97,6 +97,34 @@ hipError_t bt2_prepare(const Sb2stLayout& L, const double* V2, const double* tau
 hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff, double* Z,
                      long ldz, int m, const int* m_dev, int* iscratch, DevStatusWord* st,
                      hipStream_t s);
+// Several Z's in one launch (one task each): bt2_task describes a task like
+// bt2_apply's arguments (m: host bound of the device count); bt2_group_apply
+// clears every task's counters and launches all their strips together.
+// tasks and hmap are the caller's host arrays (kept until the stream has run
+// the work); d_tasks holds nt descriptors, d_map bt2_group_map_ints ints.
+constexpr int NSPLIT = 4;
+struct SplitRanges {
+  int hi[NSPLIT];  // range k covers sweep blocks lo[k] .. hi[k] (hi[k] = lo[k-1] - 1)
+  int lo[NSPLIT];
+};
+struct Bt2Task {
+  SplitRanges R;
+  const double* F2;
+  const long* goff;
+  double* Z;
+  long ldz;
+  const int* m_dev;
+  int* done;
+  DevStatusWord* st;
+  int n, nblk, nstrip, m, b0, pad;
+};
+Bt2Task bt2_task(const Sb2stLayout& L, const double* F2, const long* d_goff, double* Z,
+                 long ldz, int m, const int* m_dev, int* iscratch, DevStatusWord* st);
+size_t bt2_group_map_ints(int nt, const Bt2Task* tasks);
+// algorithmic flops of Z <- Q2 Z for m columns
+double bt2_flops(const Sb2stLayout& L, int m);
+hipError_t bt2_group_apply(int nt, Bt2Task* tasks, std::vector<int>& hmap, Bt2Task* d_tasks,
+                           int* d_map, hipStream_t s);
 // Z (n x m) <- Q1 Z, the stage-1 panel reflectors (I - V T V^T), applied in
 // groups of 16 panels, last group first.  Vst must hold zeros above each
 // panel's first reflector row (bt1_zero_fill, before the reduction).

@@ -60,6 +60,20 @@ void kt_activate(KTimer* k) { kt_cur = k; }
 
 void kt_set_tag(int t) { kt_tag = t; }
 
+void kt_set_last_work(const char* name, double flops, double bytes) {
+  KTimer* k = kt_cur;
+  if (!k) return;
+  auto it = k->ids.find(name);
+  if (it == k->ids.end()) return;
+  for (auto r = k->recs.rbegin(); r != k->recs.rend(); ++r)
+    if (r->id == it->second) {
+      r->flops = flops;
+      r->bytes = bytes;
+      r->nbound = 0;
+      return;
+    }
+}
+
 void kt_set_whole_only(KTimer* k, bool on) {
   if (k) k->whole_only = on;
 }
