@@ -177,3 +177,45 @@ def test_batch_argument_errors(torch_dev, h):
     assert call(w=(ctypes.c_double * 1)(-1.0)) == -9
     assert call(ne=17.0) == -10
     assert call(kT=-0.1) == -11
+
+
+def test_batch_reports_failing_task(torch_dev, h):
+    """A task whose S is not positive definite stops the batch with status 1,
+    the task's index in the message and the failing column as detail."""
+    from paper_1912_13403_amd import hsdm
+    H1, S1 = inputs.sized_problem(40, cfg=1500)
+    H2, S2 = inputs.sized_problem(50, cfg=1501)
+    S2 = S2.copy()
+    S2[7, 7] = -1.0
+    _set_fmax(h, 2.0)
+    h.hsdm_reinit()
+    with pytest.raises(hsdm.HsdmError) as ei:
+        h.hsdm_solve_dm_batch([_g(torch_dev, H1), _g(torch_dev, H2)],
+                              [_g(torch_dev, S1), _g(torch_dev, S2)], 40.0, 0.01)
+    assert ei.value.status == hsdm.HSDM_NOT_SPD
+    assert "task 1" in str(ei.value)
+    assert ei.value.detail == 8
+    # the handle stays usable
+    r = h.hsdm_solve_dm_batch([_g(torch_dev, H1)], [_g(torch_dev, S1)], 20.0, 0.01)
+    assert np.isfinite(_c(r["D"][0])).all()
+
+
+def test_release_task_contexts(oracle, torch_dev, h):
+    """Task contexts hold their workspace until released; after a release a
+    solve of the same tasks recomputes everything and still matches."""
+    sizes = [64, 96, 130]
+    probs = [inputs.sized_problem(n, cfg=1600 + n) for n in sizes]
+    Hs = [_g(torch_dev, p[0]) for p in probs]
+    Ss = [_g(torch_dev, p[1]) for p in probs]
+    _set_fmax(h, 2.0)
+    h.hsdm_reinit()
+    h.hsdm_solve_dm_batch(Hs, Ss, 100.0, 0.01)
+    held = h.hsdm_workspace_bytes()
+    assert held > 0.0
+    h.hsdm_release_tasks(0.0)
+    assert h.hsdm_workspace_bytes() < held
+    r = h.hsdm_solve_dm_batch(Hs, Ss, 100.0, 0.01)
+    ref = oracle.solve_dm_batch([p[0] for p in probs], [p[1] for p in probs], 100.0, 0.01,
+                                f_max=2.0)
+    for D, Dr in zip(r["D"], ref["D"]):
+        assert np.max(np.abs(_c(D) - Dr)) <= 1e-9
