@@ -146,6 +146,21 @@ int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int *n,
                         void *const *D, const int *ldd, void *const *E, const int *lde,
                         double *band_energy, double *mu, void *stream);
 
+/* All eigenpairs of a Hermitian pencil H C = S C eps (Eq. (3) with the
+ * complex H_k, S_k of Eq. (13); the complex eigensolver interface of
+ * Sec. 2.1).  H, S, C interleaved complex128, column-major, leading
+ * dimensions in complex elements; lower triangles of H and S read.
+ *   eval[n]        device, ascending eigenvalues (out)
+ *   C[ldc * n]     device, complex eigenvectors (out), C^H S C = I
+ * Method: the real embedding of size 2n (every eigenvalue twice); column l
+ * of C is x + i y from the real eigenvector [x; y] of pair l.  For a complex
+ * eigenvalue of multiplicity k (eigenvalues within 1e-10 max(1, |eps|)) the
+ * 2k real eigenvectors are combined into k S-orthonormal complex ones by a
+ * pivoted Cholesky of their complex Gram matrix (status +2 if that fails).
+ * Workspace and factor cache as hsdm_solve_dm_complex. */
+int hsdm_solve_ev_complex(hsdm_handle h, int n, const void *H, int ldh, const void *S, int lds,
+                          double *eval, void *C, int ldc, void *stream);
+
 /* Independent problems solved together (requests of a serving loop): real
  * and Hermitian tasks mixed (is_complex[p]), each with its own electron
  * count, kT and f_max (f_max nullable: the handle's), its own chemical

@@ -2,7 +2,9 @@
 // of the dense H, S -> eigenpairs / density-matrix path.  Every phase is a
 // kernel of this library; the host only enqueues work on the caller's stream
 // and reads back the status word and the scalar results at the end.
+#include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -735,6 +737,38 @@ static int dm_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S
   return HSDM_OK;
 }
 
+// Eigenpairs of the real pencil (H, S) of size n: eigenvalues into eval,
+// eigenvectors (C^T S C = I) into C; the S factor cached under `key`.
+static int ev_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S, int lds,
+                   const SKey& key, double* eval, double* C, int ldc, hipStream_t s) {
+  int r;
+  for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
+  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  DEV_TRY(h, hipGetLastError());
+  mark(h, 0, s);
+  if ((r = factor_s(h, n, S, lds, key, s))) return r;
+  mark(h, 1, s);
+  if ((r = standard_form(h, n, H, ldh, h->Linv, n, h->Abuf, n, s))) return r;
+  mark(h, 2, s);
+  if ((r = reduce(h, n, s, 3))) return r;
+  mark(h, 4, s);
+  DEV_TRY(h, stedc_run(h->plan, h->dvec, h->evec, eval, h->Zbuf, n, h->dc_scr, h->dc_iscr,
+                       nullptr, nullptr, nullptr, h->st, s));
+  mark(h, 5, s);
+  DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
+  DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, n, nullptr, h->progress, h->st, s));
+  mark(h, 6, s);
+  DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, n, nullptr, h->bt1_scr, s));
+  mark(h, 7, s);
+  GemmArgs g{};
+  g.m = n; g.n = n; g.k = n; g.A = h->Linv; g.lda = n; g.B = h->Zbuf; g.ldb = n; g.C = C;
+  g.ldc = ldc; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.flags = GF_KA_UPPER;
+  DEV_TRY(h, gemm_launch(g, s));
+  mark(h, 8, s);
+  mark(h, 9, s);
+  return HSDM_OK;
+}
+
 static int check_hs(hsdm_handle h, int n, const double* H, int ldh, const double* S, int lds) {
   if (!h) return -1;
   if (n < 1) return -2;
@@ -758,31 +792,129 @@ int hsdm_solve_ev_real(hsdm_handle h, int n, const double* H, int ldh, const dou
   int r = ensure_ws(h, n);
   if (r) return r;
   KtScope kts(h);
-  for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
-  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
-  DEV_TRY(h, hipGetLastError());
-  mark(h, 0, s);
-  if ((r = factor_s(h, n, S, lds, SKey{S, n, lds, false}, s))) return r;
-  mark(h, 1, s);
-  if ((r = standard_form(h, n, H, ldh, h->Linv, n, h->Abuf, n, s))) return r;
-  mark(h, 2, s);
-  if ((r = reduce(h, n, s, 3))) return r;
-  mark(h, 4, s);
-  DEV_TRY(h, stedc_run(h->plan, h->dvec, h->evec, eval, h->Zbuf, n, h->dc_scr, h->dc_iscr,
-                       nullptr, nullptr, nullptr, h->st, s));
-  mark(h, 5, s);
-  DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
-  DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, n, nullptr, h->progress, h->st, s));
-  mark(h, 6, s);
-  DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, n, nullptr, h->bt1_scr, s));
-  mark(h, 7, s);
-  GemmArgs g{};
-  g.m = n; g.n = n; g.k = n; g.A = h->Linv; g.lda = n; g.B = h->Zbuf; g.ldb = n; g.C = C;
-  g.ldc = ldc; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.flags = GF_KA_UPPER;
-  DEV_TRY(h, gemm_launch(g, s));
-  mark(h, 8, s);
-  mark(h, 9, s);
+  if ((r = ev_core(h, n, H, ldh, S, lds, SKey{S, n, lds, false}, eval, C, ldc, s))) return r;
   return finish(h, s);
+}
+
+int hsdm_solve_ev_complex(hsdm_handle h, int n, const void* H, int ldh, const void* S, int lds,
+                          double* eval, void* C, int ldc, void* stream) {
+  if (!h) return -1;
+  if (n < 1 || n > (1 << 29)) return -2;
+  if (!H) return -3;
+  if (bad_ld(ldh, n)) return -4;
+  if (!S) return -5;
+  if (bad_ld(lds, n)) return -6;
+  if (!eval) return -7;
+  if (!C) return -8;
+  if (bad_ld(ldc, n)) return -9;
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  DEV_TRY(h, hipSetDevice(h->device));
+  const int n2 = 2 * n;
+  int r = ensure_ws(h, n2);
+  if (r) return r;
+  if ((r = ensure_cws(h, n))) return r;
+  KtScope kts(h);
+  const SKey key{S, n, lds, true};
+  if (!s_cached(h, key)) DEV_TRY(h, herm_embed(n, S, lds, h->SR, n2, s));
+  DEV_TRY(h, herm_embed(n, H, ldh, h->HR, n2, s));
+  // real eigenpairs of the embedded pencil (each eigenvalue twice) into lam, DR
+  if ((r = ev_core(h, n2, h->HR, n2, h->SR, n2, key, h->lam, h->DR, n2, s))) return r;
+  DEV_TRY(h, herm_pair_eval(n, h->lam, eval, s));
+  DEV_TRY(h, herm_extract_pairs(n, h->DR, n2, C, ldc, s));
+  if ((r = finish(h, s))) return r;
+  // A complex eigenvalue of multiplicity k has 2k real eigenvectors spanning
+  // a k-dimensional complex space; one vector per real pair may then be
+  // dependent.  For such clusters the complex basis is rebuilt from all 2k
+  // candidates u_j = x_j + i y_j with their complex S-inner products
+  // <u_i, u_j> = delta_ij - i M_ij, M = Q_c^T R(S) J Q_c.
+  std::vector<double> lam2(n2);
+  DEV_TRY(h, hipMemcpy(lam2.data(), h->lam, sizeof(double) * n2, hipMemcpyDeviceToHost));
+  double scale = 1.0;
+  for (double v : lam2) scale = std::max(scale, std::fabs(v));
+  const double tol = 1e-10 * scale;
+  bool sr_fresh = false;
+  for (int l0 = 0; l0 < n;) {
+    int l1 = l0 + 1;
+    while (l1 < n && 0.5 * (lam2[2 * l1] + lam2[2 * l1 + 1]) -
+                         0.5 * (lam2[2 * l1 - 2] + lam2[2 * l1 - 1]) <= tol)
+      l1++;
+    const int k = l1 - l0, k2 = 2 * k;
+    if (k > 1) {
+      if (!sr_fresh) {
+        // R(S) again: the buffer may hold another S when the factor was cached
+        DEV_TRY(h, herm_embed(n, S, lds, h->SR, n2, s));
+        sr_fresh = true;
+      }
+      const double* Qc = h->DR + (long)(2 * l0) * n2;
+      double* JQ = h->HR;    // 2n x k2 (k2 <= 2n: each fits a 2n x 2n buffer)
+      double* P = h->ER;     // 2n x k2
+      double* M = h->Cbuf;   // k2 x k2 (free after the eigenvectors are formed)
+      double* cf = h->Zbuf;  // k2 x k complex
+      DEV_TRY(h, herm_jmul(n, k2, Qc, n2, JQ, n2, s));
+      GemmArgs g{};
+      g.m = n2; g.n = k2; g.k = n2; g.A = h->SR; g.lda = n2; g.B = JQ; g.ldb = n2; g.C = P;
+      g.ldc = n2; g.alpha = 1.0; g.beta = 0.0; g.flags = GF_A_SYM_LOWER;
+      DEV_TRY(h, gemm_launch(g, s));
+      g = GemmArgs{};
+      g.m = k2; g.n = k2; g.k = n2; g.A = Qc; g.lda = n2; g.B = P; g.ldb = n2; g.C = M;
+      g.ldc = k2; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
+      DEV_TRY(h, gemm_launch(g, s));
+      std::vector<double> Mh((size_t)k2 * k2);
+      DEV_TRY(h, hipMemcpyAsync(Mh.data(), M, sizeof(double) * k2 * k2, hipMemcpyDeviceToHost, s));
+      DEV_TRY(h, hipStreamSynchronize(s));
+      // <u_i, u_j> = r_i^T R(S) r_j - i r_i^T R(S) J r_j (J r is the real form
+      // of i u, and Re <u, i v> = -Im <u, v>), so the Gram matrix is G = I - i M.
+      // Its pivoted Cholesky (rank k) picks k independent candidates u_piv;
+      // W = U_piv L^{-H} is S-orthonormal.
+      using cd = std::complex<double>;
+      auto G = [&](int i, int j) { return cd(i == j ? 1.0 : 0.0, -Mh[i + (size_t)j * k2]); };
+      std::vector<int> piv(k2);
+      for (int j = 0; j < k2; j++) piv[j] = j;
+      std::vector<double> d(k2, 1.0);
+      std::vector<cd> L((size_t)k2 * k, 0.0);  // L[row j (candidate), col a]
+      for (int a = 0; a < k; a++) {
+        int best = a;
+        for (int j = a + 1; j < k2; j++)
+          if (d[piv[j]] > d[piv[best]]) best = j;
+        std::swap(piv[a], piv[best]);
+        const int pa = piv[a];
+        if (!(d[pa] > 1e-3)) {
+          h->err = "complex eigenvector basis of a degenerate cluster could not be formed";
+          return HSDM_NO_CONVERGE;
+        }
+        const double lpp = std::sqrt(d[pa]);
+        L[pa + (size_t)a * k2] = lpp;
+        for (int j = a + 1; j < k2; j++) {
+          const int pj = piv[j];
+          cd v = G(pj, pa);
+          for (int b = 0; b < a; b++) v -= L[pj + (size_t)b * k2] * std::conj(L[pa + (size_t)b * k2]);
+          v /= lpp;
+          L[pj + (size_t)a * k2] = v;
+          d[pj] -= std::norm(v);
+        }
+      }
+      // coefficients: column a of L11^{-H} placed at the selected candidates
+      // (L11[a][b] = L[piv[a]][b], lower triangular); solve L11^H X = I
+      std::vector<cd> X((size_t)k * k, 0.0);
+      for (int c = 0; c < k; c++) {
+        for (int r = k - 1; r >= 0; r--) {
+          cd v = (r == c) ? cd(1.0) : cd(0.0);
+          for (int q = r + 1; q < k; q++) v -= std::conj(L[piv[q] + (size_t)r * k2]) * X[q + (size_t)c * k];
+          X[r + (size_t)c * k] = v / std::conj(L[piv[r] + (size_t)r * k2]);
+        }
+      }
+      std::vector<cd> coef((size_t)k2 * k, 0.0);
+      for (int c = 0; c < k; c++)
+        for (int r = 0; r < k; r++) coef[piv[r] + (size_t)c * k2] = X[r + (size_t)c * k];
+      DEV_TRY(h, hipMemcpyAsync(cf, coef.data(), sizeof(double) * 2 * k2 * k,
+                                hipMemcpyHostToDevice, s));
+      DEV_TRY(h, herm_combine(n, k2, k, Qc, n2, cf, (char*)C + (size_t)l0 * ldc * 16, ldc, s));
+      DEV_TRY(h, hipStreamSynchronize(s));
+    }
+    l0 = l1;
+  }
+  return HSDM_OK;
 }
 
 int hsdm_solve_dm_real(hsdm_handle h, int n, const double* H, int ldh, const double* S, int lds,

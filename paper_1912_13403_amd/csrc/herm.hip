@@ -72,7 +72,67 @@ __global__ void herm_pair_eval_kernel(int n, const double* lam2, double* eval) {
   if (l < n) eval[l] = 0.5 * (lam2[2 * l] + lam2[2 * l + 1]);
 }
 
+// X[i, l] = R[i, 2l] + i R[n + i, 2l]: one real eigenvector of each pair.
+__global__ __launch_bounds__(256) void herm_extract_pairs_kernel(int n, const double* R, long ldr,
+                                                                 double2* X, long ldx) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  for (int l = blockIdx.y; l < n; l += gridDim.y) {
+    const double* col = R + (long)(2 * l) * ldr;
+    X[i + (long)l * ldx] = make_double2(col[i], col[n + i]);
+  }
+}
+
+// JQ = [-Q_y; Q_x] for the k2 columns of Q = [Q_x; Q_y] (2n rows): the real
+// form of multiplication by i.
+__global__ __launch_bounds__(256) void herm_jmul_kernel(int n, int k2, const double* Q, long ldq,
+                                                        double* JQ, long ldj) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n || j >= k2) return;
+  const double x = Q[i + (long)j * ldq], y = Q[n + i + (long)j * ldq];
+  JQ[i + (long)j * ldj] = -y;
+  JQ[n + i + (long)j * ldj] = x;
+}
+
+// X[i, a] = sum_j (Q[i, j] + i Q[n + i, j]) c[j, a] for a < k (c: k2 x k complex).
+__global__ __launch_bounds__(256) void herm_combine_kernel(int n, int k2, int k, const double* Q,
+                                                           long ldq, const double2* c, double2* X,
+                                                           long ldx) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int a = blockIdx.y;
+  if (i >= n || a >= k) return;
+  double re = 0.0, im = 0.0;
+  for (int j = 0; j < k2; j++) {
+    const double x = Q[i + (long)j * ldq], y = Q[n + i + (long)j * ldq];
+    const double2 w = c[j + (long)a * k2];
+    re += x * w.x - y * w.y;
+    im += x * w.y + y * w.x;
+  }
+  X[i + (long)a * ldx] = make_double2(re, im);
+}
+
 }  // namespace
+
+hipError_t herm_extract_pairs(int n, const double* R, long ldr, void* X, long ldx, hipStream_t s) {
+  hipLaunchKernelGGL(herm_extract_pairs_kernel, dim3(ceil_div(n, 256), n < 4096 ? n : 4096),
+                     dim3(256), 0, s, n, R, ldr, (double2*)X, ldx);
+  return hipGetLastError();
+}
+
+hipError_t herm_jmul(int n, int k2, const double* Q, long ldq, double* JQ, long ldj,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(herm_jmul_kernel, dim3(ceil_div(n, 256), k2), dim3(256), 0, s, n, k2, Q, ldq,
+                     JQ, ldj);
+  return hipGetLastError();
+}
+
+hipError_t herm_combine(int n, int k2, int k, const double* Q, long ldq, const void* c, void* X,
+                        long ldx, hipStream_t s) {
+  hipLaunchKernelGGL(herm_combine_kernel, dim3(ceil_div(n, 256), k), dim3(256), 0, s, n, k2, k, Q,
+                     ldq, (const double2*)c, (double2*)X, ldx);
+  return hipGetLastError();
+}
 
 hipError_t herm_embed(int n, const void* A, long lda, double* R, long ldr, hipStream_t s) {
   const int t = ceil_div(n, TT);

@@ -35,7 +35,8 @@ HSDM_KEY_TIMING = 4
 
 EXPORTED = [
     "hsdm_init", "hsdm_finalize", "hsdm_reinit", "hsdm_set_real", "hsdm_set_int",
-    "hsdm_solve_ev_real", "hsdm_solve_dm_real", "hsdm_solve_dm_complex", "hsdm_solve_dm_batch",
+    "hsdm_solve_ev_real", "hsdm_solve_dm_real", "hsdm_solve_ev_complex", "hsdm_solve_dm_complex",
+    "hsdm_solve_dm_batch",
     "hsdm_solve_dm_group", "hsdm_task_bytes", "hsdm_workspace_bytes", "hsdm_release_tasks",
     "hsdm_cholesky_inverse", "hsdm_standard_form",
     "hsdm_tridiagonalize", "hsdm_tridiag_eigh", "hsdm_occupations", "hsdm_density",
@@ -67,6 +68,7 @@ def load_library(path: str = LIB_PATH):
         "hsdm_solve_ev_real": ([_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _vp], _i),
         "hsdm_solve_dm_real": ([_vp, _i, _vp, _i, _vp, _i, _d, _d, _vp, _i, _vp, _i, _vp,
                                 ctypes.POINTER(_d), ctypes.POINTER(_d), _vp], _i),
+        "hsdm_solve_ev_complex": ([_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _vp], _i),
         "hsdm_solve_dm_complex": ([_vp, _i, _vp, _i, _vp, _i, _d, _d, _vp, _i, _vp, _i, _vp,
                                    ctypes.POINTER(_d), ctypes.POINTER(_d), _vp], _i),
         "hsdm_solve_dm_batch": ([_vp, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _d, _d, _vp, _vp,
@@ -240,6 +242,17 @@ class Handle:
             _ld(E) if E is not None else n, w.data_ptr() if w is not None else None,
             ctypes.byref(eb), ctypes.byref(mu), _stream_ptr(self.device)))
         return dict(D=D, E=E, eval=w, mu=mu.value, band_energy=eb.value)
+
+    def hsdm_solve_ev_complex(self, H, S):
+        """All eigenpairs of a Hermitian pencil: (eval, C) with C^H S C = I."""
+        H, S = _colmajor_c(H), _colmajor_c(S)
+        n = H.shape[0]
+        w = torch.empty(n, dtype=torch.float64, device=self.device)
+        C = empty_colmajor_c(n, n, self.device)
+        self._check(self._lib.hsdm_solve_ev_complex(self._h, n, H.data_ptr(), _ld(H), S.data_ptr(),
+                                                    _ld(S), w.data_ptr(), C.data_ptr(), _ld(C),
+                                                    _stream_ptr(self.device)))
+        return w, C
 
     def hsdm_solve_dm_complex(self, H, S, n_electrons, kT, want_e=True, want_eval=True):
         """Hermitian pencil (complex128 tensors; lower triangles read)."""

@@ -158,3 +158,38 @@ def test_complex_argument_errors(torch_dev, h):
     assert call(n, p, n, p, n, 1.0, -1.0, p, n, None, n) == -8
     assert call(n, p, n, p, n, 1.0, 0.0, None, n, None, n) == -9
     assert call(n, p, n, p, n, 1.0, 0.0, p, 3, None, n) == -10
+
+
+def _check_ev_complex(H, S, w, C, w_ref):
+    n = H.shape[0]
+    Hf, Sf = _herm(H), _herm(S)
+    scale = max(_norm1(H), 1.0)
+    assert np.max(np.abs(w - w_ref)) <= 1e-10 * scale
+    res = Hf @ C - (Sf @ C) * w
+    assert np.max(np.abs(res).sum(axis=0)) / (n * scale) <= 1e-12
+    assert np.max(np.abs(C.conj().T @ Sf @ C - np.eye(n))) <= 1e-12 * n
+
+
+@pytest.mark.parametrize("n,kindex", [(1, 2), (37, 5), (150, 11), (333, 19)])
+def test_solve_ev_complex_parity(oracle, torch_dev, h, n, kindex):
+    Hu, Hd, S = inputs.kpoint_problem(kindex, n=n)
+    h.hsdm_reinit()
+    w, C = h.hsdm_solve_ev_complex(_g(torch_dev, Hu), _g(torch_dev, S))
+    ref = oracle.solve_dm_complex(Hu, S, 0.2 * n, 0.01, f_max=1.0)
+    _check_ev_complex(Hu, S, _c(w), _c(C), ref["eval"])
+
+
+def test_solve_ev_complex_degenerate_levels(torch_dev, h):
+    # the ring without flux: levels 2t cos(2 pi k / n) are degenerate pairs
+    n = 64
+    H, S = inputs.ring_flux(n, 0.0)
+    h.hsdm_reinit()
+    w, C = h.hsdm_solve_ev_complex(_g(torch_dev, H), _g(torch_dev, S))
+    eps = np.sort(-2.0 * np.cos(2.0 * np.pi * np.arange(n) / n))
+    _check_ev_complex(H, S, _c(w), _c(C), eps)
+    # H = 0: one level of multiplicity n
+    _, _, S2 = inputs.kpoint_problem(3, n=24)
+    Z = np.zeros((24, 24), dtype=np.complex128, order="F")
+    h.hsdm_reinit()
+    w2, C2 = h.hsdm_solve_ev_complex(_g(torch_dev, Z), _g(torch_dev, S2))
+    _check_ev_complex(Z, S2, _c(w2), _c(C2), np.zeros(24))
