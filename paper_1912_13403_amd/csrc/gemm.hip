@@ -404,6 +404,39 @@ __global__ void splitk_reduce_kernel(int m, int n, int nsplit, const double* par
   *c = (beta != 0.0) ? s + beta * *c : s;
 }
 
+// Split-K symmetric products of several tasks in one launch (the 128 x 32
+// tiles of the products X = tril(A) Y and X += strict_tril(A)^T Y of the
+// band reduction): workgroup blockIdx.x is tile (local % tiles, split
+// local / tiles) of item wg_item[blockIdx.x], writing its partial product.
+template <int TA, int AM>
+__global__ __launch_bounds__(256) void gemm_sym_group_kernel(const SymGroupItem* items,
+                                                             const int* wg_item) {
+  using C = G<128, 32, 4, 1, TA, 0, AM>;
+  __shared__ double smem[C::SMEM];
+  const int q = __builtin_amdgcn_readfirstlane(wg_item[blockIdx.x]);
+  const SymGroupItem& it = items[q];
+  const int local = (int)blockIdx.x - it.b0;
+  const int split = local / it.tiles, tm = local % it.tiles;
+  Prob p{it.m, it.n, it.k, it.A, it.lda, it.B, it.ldb, it.part + (long)split * it.m * it.n,
+         (long)it.m, nullptr, nullptr, nullptr};
+  const int klo = split * it.kchunk;
+  gemm_tile<128, 32, 4, 1, TA, 0, AM>(p, 1.0, 0.0, it.flags, tm, 0, smem, klo, klo + it.kchunk);
+}
+
+// C = sum of the item's split partials + beta C, item blockIdx.y
+__global__ void splitk_reduce_group_kernel(const SymGroupItem* items) {
+  const SymGroupItem& it = items[blockIdx.y];
+  const long tot = (long)it.m * it.n;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int z = 0; z < it.nsplit; z++) s += it.part[z * tot + idx];
+    const int i = (int)(idx % it.m), j = (int)(idx / it.m);
+    double* c = it.C + i + (long)j * it.ldc;
+    *c = (it.beta != 0.0) ? s + it.beta * *c : s;
+  }
+}
+
 // C = beta*C when k == 0 (or alpha == 0)
 __global__ void scale_kernel(int m, int n, double* C, long ldc, double beta, const int* ccol,
                              const int* ndev) {
@@ -581,5 +614,38 @@ hipError_t gemm_batched_dense_launch(const GemmDesc* d_desc, int count, int max_
   hipLaunchKernelGGL((gemm_batched_kernel<64, 64, 2, 2, 0, 0, AM_DENSE>), dim3(nblk, count),
                      dim3(256), 0, s, d_desc, alpha, beta, flags);
   kt_end(s);
+  return hipGetLastError();
+}
+
+size_t sym_group_item(const GemmArgs& g, int kchunk, double* part, SymGroupItem& it) {
+  it = SymGroupItem{};
+  it.m = g.m; it.n = g.n; it.k = g.k;
+  it.A = g.A; it.lda = g.lda; it.B = g.B; it.ldb = g.ldb;
+  it.C = g.C; it.ldc = g.ldc; it.part = part;
+  it.beta = g.beta;
+  it.flags = g.flags;
+  it.kchunk = kchunk;
+  it.nsplit = ceil_div(g.k, kchunk);
+  it.tiles = ceil_div(g.m, 128);
+  return (size_t)it.nsplit * it.tiles;
+}
+
+hipError_t gemm_sym_group_launch(int slt, const SymGroupItem* d_items, int count,
+                                 const int* d_map, int total_wg, int max_tot, double flops,
+                                 hipStream_t s) {
+  if (count <= 0 || total_wg <= 0) return hipSuccess;
+  if (slt) {
+    kt_begin("gemm_sym_group_kernel<1, 4>", flops, 0.0, 0, s);
+    hipLaunchKernelGGL((gemm_sym_group_kernel<1, AM_SLT>), dim3(total_wg), dim3(256), 0, s,
+                       d_items, d_map);
+  } else {
+    kt_begin("gemm_sym_group_kernel<0, 3>", flops, 0.0, 0, s);
+    hipLaunchKernelGGL((gemm_sym_group_kernel<0, AM_TRIL>), dim3(total_wg), dim3(256), 0, s,
+                       d_items, d_map);
+  }
+  kt_end(s);
+  HSDM_TRY(hipGetLastError());
+  const int bx = std::max(1, std::min(1024, ceil_div(max_tot, 256)));
+  hipLaunchKernelGGL(splitk_reduce_group_kernel, dim3(bx, count), dim3(256), 0, s, d_items);
   return hipGetLastError();
 }

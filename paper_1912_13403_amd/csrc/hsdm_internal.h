@@ -57,6 +57,27 @@ hipError_t gemm_splitk_launch(const GemmArgs& g, int kchunk, double* part, hipSt
 hipError_t gemm_batched_launch(const GemmDesc* d_desc, int count, int max_m, int max_n,
                                double alpha, double beta, int ta, int tb, int flags,
                                hipStream_t s);
+// Split-K products of several tasks in one launch, all with the 128 x 32
+// tiles: op(A) = tril(A) (slt = 0, flags as GF_A_TRIL) or strict_tril(A)^T
+// (slt = 1, as GF_A_SLT), alpha = 1, each item's nsplit partials into its
+// own part buffer (m x n each), then C = sum + beta C.  sym_group_item
+// fills an item from the product's arguments and returns its workgroup
+// count (the caller sets b0, the item's first workgroup, and writes the
+// workgroup -> item map); d_items and d_map are device arrays.
+struct SymGroupItem {
+  const double* A;
+  const double* B;
+  double* C;
+  double* part;
+  long lda, ldb, ldc;
+  double beta;
+  int m, n, k, flags, kchunk, nsplit, tiles, b0;
+};
+size_t sym_group_item(const GemmArgs& g, int kchunk, double* part, SymGroupItem& it);
+hipError_t gemm_sym_group_launch(int slt, const SymGroupItem* d_items, int count,
+                                 const int* d_map, int total_wg, int max_tot, double flops,
+                                 hipStream_t s);
+
 // The same for plain operands (no gathered columns; acol and ccol unused).
 hipError_t gemm_batched_dense_launch(const GemmDesc* d_desc, int count, int max_m, int max_n,
                                      double alpha, double beta, int flags, hipStream_t s);

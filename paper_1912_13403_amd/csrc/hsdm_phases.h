@@ -39,6 +39,8 @@ struct PanelQrTask {
 struct Sy2sbGroupHost {
   std::vector<PanelQrTask> desc;
   std::vector<int> wgmap;
+  std::vector<SymGroupItem> sym;  // grouped symmetric products of every round
+  std::vector<int> symmap;
 };
 size_t sy2sb_group_bytes(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& host);
 hipError_t sy2sb_run_group(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& host, void* d_buf,

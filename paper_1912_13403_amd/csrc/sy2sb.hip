@@ -463,24 +463,36 @@ struct Sy2sb {
   }
   // W (h x B, ld n, holding X on entry) = X - V M / 2 with Y = V T, X = A[r:, r:] Y,
   // M = Y^T X.  Vp: the panel's V (ld ldv), Tp its T; Y receives V T.
-  hipError_t make_w(int r, int h, const double* Vp, const double* Tp, double* Wp, bool correct,
-                    const double* VWc, const double* WVc) {
+  // In three steps (the middle one, the two passes of the symmetric product,
+  // can run grouped over several tasks).
+  hipError_t make_w_pre(int h, const double* Vp, const double* Tp) {
     GemmArgs g{};
     g.m = h; g.n = B; g.k = B; g.A = Vp; g.lda = ldv; g.B = Tp; g.ldb = B; g.C = Y; g.ldc = n;
     g.alpha = 1.0; g.beta = 0.0; g.flags = GF_KB_UPPER;
-    HSDM_TRY(gemm_launch(g, s));
-    // X = A[r:, r:] Y: A symmetric with its lower triangle stored,
-    // X = tril(A) Y + strict_tril(A)^T Y, both passes reading the lower triangle
+    return gemm_launch(g, s);
+  }
+  // X = A[r:, r:] Y: A symmetric with its lower triangle stored,
+  // X = tril(A) Y + strict_tril(A)^T Y, both passes reading the lower triangle
+  void sym_args(int r, int h, double* Wp, GemmArgs& tril, GemmArgs& slt) const {
     const double* Ar = A + r + (long)r * lda;
-    g = GemmArgs{};
-    g.m = h; g.n = B; g.k = h; g.A = Ar; g.lda = lda; g.B = Y; g.ldb = n; g.C = Wp; g.ldc = n;
-    g.alpha = 1.0; g.beta = 0.0; g.flags = GF_A_TRIL | GF_KA_LOWER;
-    HSDM_TRY(gemm_splitk_launch(g, SPLITK, skpart, s));
-    g.ta = 1; g.beta = 1.0; g.flags = GF_A_SLT | GF_KA_UPPER;
-    HSDM_TRY(gemm_splitk_launch(g, SPLITK, skpart, s));
+    tril = GemmArgs{};
+    tril.m = h; tril.n = B; tril.k = h; tril.A = Ar; tril.lda = lda; tril.B = Y; tril.ldb = n;
+    tril.C = Wp; tril.ldc = n; tril.alpha = 1.0; tril.beta = 0.0;
+    tril.flags = GF_A_TRIL | GF_KA_LOWER;
+    slt = tril;
+    slt.ta = 1; slt.beta = 1.0; slt.flags = GF_A_SLT | GF_KA_UPPER;
+  }
+  hipError_t make_w_sym(int r, int h, double* Wp) {
+    GemmArgs t, u;
+    sym_args(r, h, Wp, t, u);
+    HSDM_TRY(gemm_splitk_launch(t, SPLITK, skpart, s));
+    return gemm_splitk_launch(u, SPLITK, skpart, s);
+  }
+  hipError_t make_w_post(int h, const double* Vp, double* Wp, bool correct, const double* VWc,
+                         const double* WVc) {
+    GemmArgs g{};
     if (correct) {
       // X -= [V1b W1b] ([W1b V1b]^T Y): the delayed update of the first panel
-      g = GemmArgs{};
       g.m = 2 * B; g.n = B; g.k = h; g.A = WVc; g.lda = n; g.B = Y; g.ldb = n; g.C = Qc;
       g.ldc = 2 * B; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
       HSDM_TRY(gemm_splitk_launch(g, SPLITK, skpart, s));
@@ -502,6 +514,12 @@ struct Sy2sb {
     g.alpha = -0.5; g.beta = 1.0;
     return gemm_launch(g, s);
   }
+  hipError_t make_w(int r, int h, const double* Vp, const double* Tp, double* Wp, bool correct,
+                    const double* VWc, const double* WVc) {
+    HSDM_TRY(make_w_pre(h, Vp, Tp));
+    HSDM_TRY(make_w_sym(r, h, Wp));
+    return make_w_post(h, Vp, Wp, correct, VWc, WVc);
+  }
   // A[r:, r:] -= VWr WVr^T (lower), k columns
   hipError_t syr2k(int r, int h, const double* VWr, const double* WVr, int k) {
     GemmArgs g{};
@@ -511,14 +529,24 @@ struct Sy2sb {
     return gemm_launch(g, s);
   }
   // after the QR of panel p: its W, and either the trailing update (panel
-  // alone) or the update of panel p+1's columns (pair)
-  hipError_t after_first(int p) {
+  // alone) or the update of panel p+1's columns (pair).  Steps a and b come
+  // before and after the symmetric product (first_sym).
+  bool first_has_w(int p) const { return height(p) > 1; }
+  hipError_t after_first_a(int p) {
+    const int c0 = p * B, r0 = c0 + B, h = n - r0;
+    if (h <= 1) return hipSuccess;
+    return make_w_pre(h, Vst + r0 + (long)c0 * ldv, T1 + (size_t)p * B * B);
+  }
+  void first_sym(int p, GemmArgs& tril, GemmArgs& slt) const {
+    const int r0 = (p + 1) * B;
+    sym_args(r0, n - r0, VW + (size_t)n * B, tril, slt);
+  }
+  hipError_t after_first_b(int p) {
     const int c0 = p * B, r0 = c0 + B, h = n - r0;
     if (h <= 1) return hipSuccess;
     const double* V1 = Vst + r0 + (long)c0 * ldv;
-    const double* T1p = T1 + (size_t)p * B * B;
     double* W1 = VW + (size_t)n * B;
-    HSDM_TRY(make_w(r0, h, V1, T1p, W1, false, nullptr, nullptr));
+    HSDM_TRY(make_w_post(h, V1, W1, false, nullptr, nullptr));
     // VW[:, 0:2B] = [V1 W1], WV[:, 0:2B] = [W1 V1]
     HSDM_TRY(dev_copy(V1, ldv, VW, n, h, B, s));
     HSDM_TRY(dev_copy(W1, n, WV, n, h, B, s));
@@ -531,19 +559,39 @@ struct Sy2sb {
     g.tb = 1; g.flags = GF_C_LOWER_ONLY;
     return gemm_launch(g, s);
   }
+  hipError_t after_first(int p) {
+    if (!first_has_w(p)) return hipSuccess;
+    const int r0 = (p + 1) * B;
+    HSDM_TRY(after_first_a(p));
+    HSDM_TRY(make_w_sym(r0, n - r0, VW + (size_t)n * B));
+    return after_first_b(p);
+  }
   // after the QR of panel p+1 of a pair: its W (with the first panel's
   // delayed update) and the pair's rank-4B trailing update
-  hipError_t after_second(int p) {
+  hipError_t after_second_a(int p) {
+    const int r0 = (p + 1) * B, h2 = n - r0 - B, r1 = r0 + B;
+    return make_w_pre(h2, Vst + r1 + (long)r0 * ldv, T1 + (size_t)(p + 1) * B * B);
+  }
+  void second_sym(int p, GemmArgs& tril, GemmArgs& slt) const {
+    const int r1 = (p + 2) * B;
+    sym_args(r1, n - r1, VW + B + (size_t)3 * n * B, tril, slt);
+  }
+  hipError_t after_second_b(int p) {
     const int r0 = (p + 1) * B, h2 = n - r0 - B, r1 = r0 + B;
     const double* V2 = Vst + r1 + (long)r0 * ldv;
-    const double* T2p = T1 + (size_t)(p + 1) * B * B;
     double* W2 = VW + B + (size_t)3 * n * B;
-    HSDM_TRY(make_w(r1, h2, V2, T2p, W2, true, VW + B, WV + B));
+    HSDM_TRY(make_w_post(h2, V2, W2, true, VW + B, WV + B));
     // VW[B:, 2B:4B] = [V2 W2], WV[B:, 2B:4B] = [W2 V2]
     HSDM_TRY(dev_copy(V2, ldv, VW + B + (size_t)2 * n * B, n, h2, B, s));
     HSDM_TRY(dev_copy(W2, n, WV + B + (size_t)2 * n * B, n, h2, B, s));
     HSDM_TRY(dev_copy(V2, ldv, WV + B + (size_t)3 * n * B, n, h2, B, s));
     return syr2k(r1, h2, VW + B, WV + B, 4 * B);
+  }
+  hipError_t after_second(int p) {
+    const int r1 = (p + 2) * B;
+    HSDM_TRY(after_second_a(p));
+    HSDM_TRY(make_w_sym(r1, n - r1, VW + B + (size_t)3 * n * B));
+    return after_second_b(p);
   }
   hipError_t finish() {
     const long tot = (long)n * ldab;
@@ -595,23 +643,37 @@ std::vector<std::vector<std::pair<int, int>>> group_rounds(const std::vector<Sy2
   return rounds;
 }
 
-// Descriptors of the grouped QR launches in schedule order: for each round,
-// the first panels, then the second panels; each list cut into launches of
-// at most PQR_MAX_WG workgroups.  launch = (first descriptor, count, first
-// map entry, workgroups).
+// Descriptors of the grouped launches in schedule order: for each round,
+// the first panels' QRs, their symmetric products (lower-triangle pass and
+// transposed pass), then the same for the second panels.  QR lists are cut
+// into launches of at most PQR_MAX_WG workgroups.  launch = (first
+// descriptor, count, first map entry, workgroups).
 struct QrLaunch {
   int d0, nd, m0, nwg;
 };
+struct SymLaunch {
+  int d0, nd, m0, nwg, max_tot;
+  double flops;
+};
+struct Schedule {
+  std::vector<std::vector<std::pair<int, int>>> rounds;
+  std::vector<std::vector<QrLaunch>> first, second;
+  std::vector<SymLaunch> ftril, fslt, stril, sslt;  // one per round (nd = 0: none)
+};
 
-void build_schedule(const std::vector<Sy2sb>& R, Sy2sbGroupHost& host,
-                    std::vector<std::vector<QrLaunch>>& first,
-                    std::vector<std::vector<QrLaunch>>& second,
-                    std::vector<std::vector<std::pair<int, int>>>& rounds) {
-  rounds = group_rounds(R);
+void build_schedule(const std::vector<Sy2sb>& R, Sy2sbGroupHost& host, Schedule& S) {
+  S.rounds = group_rounds(R);
+  const size_t nr = S.rounds.size();
   host.desc.clear();
   host.wgmap.clear();
-  first.assign(rounds.size(), {});
-  second.assign(rounds.size(), {});
+  host.sym.clear();
+  host.symmap.clear();
+  S.first.assign(nr, {});
+  S.second.assign(nr, {});
+  S.ftril.assign(nr, SymLaunch{});
+  S.fslt.assign(nr, SymLaunch{});
+  S.stril.assign(nr, SymLaunch{});
+  S.sslt.assign(nr, SymLaunch{});
   auto emit = [&](const std::vector<PanelQrTask>& list, std::vector<QrLaunch>& out) {
     size_t i = 0;
     while (i < list.size()) {
@@ -627,14 +689,46 @@ void build_schedule(const std::vector<Sy2sb>& R, Sy2sbGroupHost& host,
       out.push_back(L);
     }
   };
-  for (size_t k = 0; k < rounds.size(); k++) {
-    std::vector<PanelQrTask> a, b;
-    for (auto& e : rounds[k]) {
-      a.push_back(R[e.first].qr_desc(e.second));
-      if (R[e.first].advance(e.second) == 2) b.push_back(R[e.first].qr_desc(e.second + 1));
+  auto emit_sym = [&](const std::vector<std::pair<GemmArgs, double*>>& list, SymLaunch& L) {
+    L = SymLaunch{(int)host.sym.size(), 0, (int)host.symmap.size(), 0, 0, 0.0};
+    for (auto& e : list) {
+      SymGroupItem it;
+      const int w = (int)sym_group_item(e.first, SPLITK, e.second, it);
+      it.b0 = L.nwg;
+      for (int q = 0; q < w; q++) host.symmap.push_back(L.nd);
+      L.nwg += w;
+      L.nd++;
+      L.max_tot = std::max(L.max_tot, it.m * it.n);
+      L.flops += (double)it.m * it.n * it.k;  // one of the two halves of 2 m n k
+      host.sym.push_back(it);
     }
-    emit(a, first[k]);
-    emit(b, second[k]);
+  };
+  for (size_t k = 0; k < nr; k++) {
+    std::vector<PanelQrTask> a, b;
+    std::vector<std::pair<GemmArgs, double*>> ft, fs, st, ss;
+    for (auto& e : S.rounds[k]) {
+      const Sy2sb& T = R[e.first];
+      a.push_back(T.qr_desc(e.second));
+      if (T.first_has_w(e.second)) {
+        GemmArgs t, u;
+        T.first_sym(e.second, t, u);
+        ft.emplace_back(t, T.skpart);
+        fs.emplace_back(u, T.skpart);
+      }
+      if (T.advance(e.second) == 2) {
+        b.push_back(T.qr_desc(e.second + 1));
+        GemmArgs t, u;
+        T.second_sym(e.second, t, u);
+        st.emplace_back(t, T.skpart);
+        ss.emplace_back(u, T.skpart);
+      }
+    }
+    emit(a, S.first[k]);
+    emit(b, S.second[k]);
+    emit_sym(ft, S.ftril[k]);
+    emit_sym(fs, S.fslt[k]);
+    emit_sym(st, S.stril[k]);
+    emit_sym(ss, S.sslt[k]);
   }
 }
 
@@ -652,15 +746,45 @@ hipError_t launch_qr_group(const QrLaunch& L, PanelQrTask* d_desc, int* d_map, c
   return hipSuccess;
 }
 
+struct GroupDev {
+  PanelQrTask* desc;
+  int* map;
+  SymGroupItem* sym;
+  int* symmap;
+};
+
+GroupDev group_dev(void* d_buf, const Sy2sbGroupHost& host) {
+  GroupDev g{};
+  char* p = (char*)d_buf;
+  g.desc = (PanelQrTask*)p;
+  p += sizeof(PanelQrTask) * (host.desc.size() + 1);
+  g.sym = (SymGroupItem*)p;
+  p += sizeof(SymGroupItem) * (host.sym.size() + 1);
+  g.map = (int*)p;
+  p += sizeof(int) * (host.wgmap.size() + 1);
+  g.symmap = (int*)p;
+  return g;
+}
+
+size_t group_bytes(const Sy2sbGroupHost& host) {
+  return sizeof(PanelQrTask) * (host.desc.size() + 1) + sizeof(SymGroupItem) * (host.sym.size() + 1) +
+         sizeof(int) * (host.wgmap.size() + 1) + sizeof(int) * (host.symmap.size() + 1);
+}
+
+hipError_t launch_sym(int slt, const SymLaunch& L, const GroupDev& D, hipStream_t s) {
+  if (L.nd == 0) return hipSuccess;
+  return gemm_sym_group_launch(slt, D.sym + L.d0, L.nd, D.symmap + L.m0, L.nwg, L.max_tot,
+                               2.0 * L.flops / 2.0, s);
+}
+
 }  // namespace
 
 size_t sy2sb_group_bytes(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& host) {
   std::vector<Sy2sb> R;
   for (int i = 0; i < nt; i++) R.emplace_back(t[i], B, nullptr);
-  std::vector<std::vector<QrLaunch>> first, second;
-  std::vector<std::vector<std::pair<int, int>>> rounds;
-  build_schedule(R, host, first, second, rounds);
-  return sizeof(PanelQrTask) * (host.desc.size() + 1) + sizeof(int) * (host.wgmap.size() + 1);
+  Schedule S;
+  build_schedule(R, host, S);
+  return group_bytes(host);
 }
 
 hipError_t sy2sb_run_group(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& host, void* d_buf,
@@ -668,15 +792,19 @@ hipError_t sy2sb_run_group(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& ho
   if (B != 32) return hipErrorInvalidValue;
   std::vector<Sy2sb> R;
   for (int i = 0; i < nt; i++) R.emplace_back(t[i], B, s);
-  std::vector<std::vector<QrLaunch>> first, second;
-  std::vector<std::vector<std::pair<int, int>>> rounds;
-  build_schedule(R, host, first, second, rounds);
-  PanelQrTask* d_desc = (PanelQrTask*)d_buf;
-  int* d_map = (int*)((char*)d_buf + sizeof(PanelQrTask) * (host.desc.size() + 1));
+  Schedule S;
+  build_schedule(R, host, S);
+  const GroupDev D = group_dev(d_buf, host);
   if (!host.desc.empty()) {
-    HSDM_TRY(hipMemcpyAsync(d_desc, host.desc.data(), sizeof(PanelQrTask) * host.desc.size(),
+    HSDM_TRY(hipMemcpyAsync(D.desc, host.desc.data(), sizeof(PanelQrTask) * host.desc.size(),
                             hipMemcpyHostToDevice, s));
-    HSDM_TRY(hipMemcpyAsync(d_map, host.wgmap.data(), sizeof(int) * host.wgmap.size(),
+    HSDM_TRY(hipMemcpyAsync(D.map, host.wgmap.data(), sizeof(int) * host.wgmap.size(),
+                            hipMemcpyHostToDevice, s));
+  }
+  if (!host.sym.empty()) {
+    HSDM_TRY(hipMemcpyAsync(D.sym, host.sym.data(), sizeof(SymGroupItem) * host.sym.size(),
+                            hipMemcpyHostToDevice, s));
+    HSDM_TRY(hipMemcpyAsync(D.symmap, host.symmap.data(), sizeof(int) * host.symmap.size(),
                             hipMemcpyHostToDevice, s));
   }
   auto flops = [&](const QrLaunch& L) {
@@ -684,18 +812,25 @@ hipError_t sy2sb_run_group(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& ho
     for (int i = 0; i < L.nd; i++) f += 2.0 * host.desc[L.d0 + i].h * B * B;
     return f;
   };
-  for (size_t k = 0; k < rounds.size(); k++) {
-    for (const QrLaunch& L : first[k]) {
+  for (size_t k = 0; k < S.rounds.size(); k++) {
+    for (const QrLaunch& L : S.first[k]) {
       const double f = flops(L);
-      HSDM_TRY(launch_qr_group(L, d_desc, d_map, &f, s));
+      HSDM_TRY(launch_qr_group(L, D.desc, D.map, &f, s));
     }
-    for (auto& e : rounds[k]) HSDM_TRY(R[e.first].after_first(e.second));
-    for (const QrLaunch& L : second[k]) {
+    for (auto& e : S.rounds[k]) HSDM_TRY(R[e.first].after_first_a(e.second));
+    HSDM_TRY(launch_sym(0, S.ftril[k], D, s));
+    HSDM_TRY(launch_sym(1, S.fslt[k], D, s));
+    for (auto& e : S.rounds[k]) HSDM_TRY(R[e.first].after_first_b(e.second));
+    for (const QrLaunch& L : S.second[k]) {
       const double f = flops(L);
-      HSDM_TRY(launch_qr_group(L, d_desc, d_map, &f, s));
+      HSDM_TRY(launch_qr_group(L, D.desc, D.map, &f, s));
     }
-    for (auto& e : rounds[k])
-      if (R[e.first].advance(e.second) == 2) HSDM_TRY(R[e.first].after_second(e.second));
+    for (auto& e : S.rounds[k])
+      if (R[e.first].advance(e.second) == 2) HSDM_TRY(R[e.first].after_second_a(e.second));
+    HSDM_TRY(launch_sym(0, S.stril[k], D, s));
+    HSDM_TRY(launch_sym(1, S.sslt[k], D, s));
+    for (auto& e : S.rounds[k])
+      if (R[e.first].advance(e.second) == 2) HSDM_TRY(R[e.first].after_second_b(e.second));
   }
   for (auto& r : R) HSDM_TRY(r.finish());
   return hipSuccess;
