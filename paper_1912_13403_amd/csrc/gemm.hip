@@ -404,28 +404,38 @@ __global__ void splitk_reduce_kernel(int m, int n, int nsplit, const double* par
   *c = (beta != 0.0) ? s + beta * *c : s;
 }
 
-// Split-K symmetric products of several tasks in one launch (the 128 x 32
-// tiles of the products X = tril(A) Y and X += strict_tril(A)^T Y of the
-// band reduction): workgroup blockIdx.x is tile (local % tiles, split
-// local / tiles) of item wg_item[blockIdx.x], writing its partial product.
-template <int TA, int AM>
-__global__ __launch_bounds__(256) void gemm_sym_group_kernel(const SymGroupItem* items,
-                                                             const int* wg_item) {
-  using C = G<128, 32, 4, 1, TA, 0, AM>;
+// Tall-skinny products of several tasks in one launch, all with the 128 x 32
+// tiles (n <= 32): workgroup blockIdx.x is tile (local % tiles, split
+// local / tiles) of item wg_item[blockIdx.x].  kchunk > 0: split-K, each
+// split writes its partial product (alpha op(A) op(B)) to part, reduced by
+// splitk_reduce_group_kernel into C = sum + beta C; kchunk = 0: the tile is
+// computed in place, C = alpha op(A) op(B) + beta C.
+template <int TA, int TB, int AM>
+__global__ __launch_bounds__(256) void gemm_group_kernel(const GemmGroupItem* items,
+                                                         const int* wg_item) {
+  using C = G<128, 32, 4, 1, TA, TB, AM>;
   __shared__ double smem[C::SMEM];
   const int q = __builtin_amdgcn_readfirstlane(wg_item[blockIdx.x]);
-  const SymGroupItem& it = items[q];
+  const GemmGroupItem& it = items[q];
   const int local = (int)blockIdx.x - it.b0;
-  const int split = local / it.tiles, tm = local % it.tiles;
-  Prob p{it.m, it.n, it.k, it.A, it.lda, it.B, it.ldb, it.part + (long)split * it.m * it.n,
-         (long)it.m, nullptr, nullptr, nullptr};
-  const int klo = split * it.kchunk;
-  gemm_tile<128, 32, 4, 1, TA, 0, AM>(p, 1.0, 0.0, it.flags, tm, 0, smem, klo, klo + it.kchunk);
+  if (it.kchunk > 0) {
+    const int split = local / it.tiles;
+    Prob p{it.m, it.n, it.k, it.A, it.lda, it.B, it.ldb, it.part + (long)split * it.m * it.n,
+           (long)it.m, nullptr, nullptr, nullptr};
+    const int klo = split * it.kchunk;
+    gemm_tile<128, 32, 4, 1, TA, TB, AM>(p, it.alpha, 0.0, it.flags, local % it.tiles, 0, smem,
+                                         klo, klo + it.kchunk);
+  } else {
+    Prob p{it.m, it.n, it.k, it.A, it.lda, it.B, it.ldb, it.C, it.ldc, nullptr, nullptr, nullptr};
+    gemm_tile<128, 32, 4, 1, TA, TB, AM>(p, it.alpha, it.beta, it.flags, local, 0, smem, 0,
+                                         1 << 30);
+  }
 }
 
-// C = sum of the item's split partials + beta C, item blockIdx.y
-__global__ void splitk_reduce_group_kernel(const SymGroupItem* items) {
-  const SymGroupItem& it = items[blockIdx.y];
+// C = sum of the item's split partials + beta C, item blockIdx.y (split items only)
+__global__ void splitk_reduce_group_kernel(const GemmGroupItem* items) {
+  const GemmGroupItem& it = items[blockIdx.y];
+  if (it.kchunk <= 0) return;
   const long tot = (long)it.m * it.n;
   for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
        idx += (long)gridDim.x * blockDim.x) {
@@ -617,34 +627,56 @@ hipError_t gemm_batched_dense_launch(const GemmDesc* d_desc, int count, int max_
   return hipGetLastError();
 }
 
-size_t sym_group_item(const GemmArgs& g, int kchunk, double* part, SymGroupItem& it) {
-  it = SymGroupItem{};
+size_t gemm_group_item(const GemmArgs& g, int kchunk, double* part, GemmGroupItem& it,
+                       double* flops) {
+  it = GemmGroupItem{};
+  if (flops) *flops = gemm_flops(g);
   it.m = g.m; it.n = g.n; it.k = g.k;
   it.A = g.A; it.lda = g.lda; it.B = g.B; it.ldb = g.ldb;
   it.C = g.C; it.ldc = g.ldc; it.part = part;
+  it.alpha = g.alpha;
   it.beta = g.beta;
   it.flags = g.flags;
-  it.kchunk = kchunk;
-  it.nsplit = ceil_div(g.k, kchunk);
   it.tiles = ceil_div(g.m, 128);
+  it.kchunk = kchunk > 0 ? kchunk : 0;
+  it.nsplit = kchunk > 0 ? ceil_div(g.k, kchunk) : 1;
   return (size_t)it.nsplit * it.tiles;
 }
 
-hipError_t gemm_sym_group_launch(int slt, const SymGroupItem* d_items, int count,
-                                 const int* d_map, int total_wg, int max_tot, double flops,
-                                 hipStream_t s) {
+hipError_t gemm_group_launch(int kind, const GemmGroupItem* d_items, int count, const int* d_map,
+                             int total_wg, int max_tot, bool split, double flops, hipStream_t s) {
   if (count <= 0 || total_wg <= 0) return hipSuccess;
-  if (slt) {
-    kt_begin("gemm_sym_group_kernel<1, 4>", flops, 0.0, 0, s);
-    hipLaunchKernelGGL((gemm_sym_group_kernel<1, AM_SLT>), dim3(total_wg), dim3(256), 0, s,
-                       d_items, d_map);
-  } else {
-    kt_begin("gemm_sym_group_kernel<0, 3>", flops, 0.0, 0, s);
-    hipLaunchKernelGGL((gemm_sym_group_kernel<0, AM_TRIL>), dim3(total_wg), dim3(256), 0, s,
-                       d_items, d_map);
+  switch (kind) {
+    case GG_TRIL:
+      kt_begin("gemm_group_kernel<0, 0, 3>", flops, 0.0, 0, s);
+      hipLaunchKernelGGL((gemm_group_kernel<0, 0, AM_TRIL>), dim3(total_wg), dim3(256), 0, s,
+                         d_items, d_map);
+      break;
+    case GG_SLT:
+      kt_begin("gemm_group_kernel<1, 0, 4>", flops, 0.0, 0, s);
+      hipLaunchKernelGGL((gemm_group_kernel<1, 0, AM_SLT>), dim3(total_wg), dim3(256), 0, s,
+                         d_items, d_map);
+      break;
+    case GG_NN:
+      kt_begin("gemm_group_kernel<0, 0, 0>", flops, 0.0, 0, s);
+      hipLaunchKernelGGL((gemm_group_kernel<0, 0, AM_DENSE>), dim3(total_wg), dim3(256), 0, s,
+                         d_items, d_map);
+      break;
+    case GG_TN:
+      kt_begin("gemm_group_kernel<1, 0, 0>", flops, 0.0, 0, s);
+      hipLaunchKernelGGL((gemm_group_kernel<1, 0, AM_DENSE>), dim3(total_wg), dim3(256), 0, s,
+                         d_items, d_map);
+      break;
+    case GG_NT:
+      kt_begin("gemm_group_kernel<0, 1, 0>", flops, 0.0, 0, s);
+      hipLaunchKernelGGL((gemm_group_kernel<0, 1, AM_DENSE>), dim3(total_wg), dim3(256), 0, s,
+                         d_items, d_map);
+      break;
+    default: return hipErrorInvalidValue;
   }
   kt_end(s);
   HSDM_TRY(hipGetLastError());
+  if (!split) return hipSuccess;
   const int bx = std::max(1, std::min(1024, ceil_div(max_tot, 256)));
   hipLaunchKernelGGL(splitk_reduce_group_kernel, dim3(bx, count), dim3(256), 0, s, d_items);
   return hipGetLastError();

@@ -57,30 +57,34 @@ hipError_t gemm_splitk_launch(const GemmArgs& g, int kchunk, double* part, hipSt
 hipError_t gemm_batched_launch(const GemmDesc* d_desc, int count, int max_m, int max_n,
                                double alpha, double beta, int ta, int tb, int flags,
                                hipStream_t s);
-// Split-K products of several tasks in one launch, all with the 128 x 32
-// tiles: op(A) = tril(A) (slt = 0, flags as GF_A_TRIL) or strict_tril(A)^T
-// (slt = 1, as GF_A_SLT), alpha = 1, each item's nsplit partials into its
-// own part buffer (m x n each), then C = sum + beta C.  sym_group_item
-// fills an item from the product's arguments and returns its workgroup
-// count (the caller sets b0, the item's first workgroup, and writes the
-// workgroup -> item map); d_items and d_map are device arrays.
-struct SymGroupItem {
+// The same for plain operands (no gathered columns; acol and ccol unused).
+hipError_t gemm_batched_dense_launch(const GemmDesc* d_desc, int count, int max_m, int max_n,
+                                     double alpha, double beta, int flags, hipStream_t s);
+// Tall-skinny products (n <= 32) of several tasks in one launch, all with the
+// 128 x 32 tiles.  kind: GG_TRIL (op(A) = tril(A), as GF_A_TRIL), GG_SLT
+// (op(A) = strict_tril(A)^T, as GF_A_SLT), GG_NN, GG_TN (A transposed),
+// GG_NT (B transposed).  An item with kchunk > 0 is split over K: its nsplit
+// partials (m x n each) go to its part buffer and are reduced into
+// C = sum + beta C when `split`; kchunk = 0 computes C = alpha op(A) op(B) +
+// beta C in place.  gemm_group_item fills an item from the product's
+// arguments (kchunk 0: in place), stores the product's algorithmic flops in
+// *flops (if given) and returns its workgroup count; the caller sets b0 (the
+// item's first workgroup) and writes the workgroup -> item map.  d_items and
+// d_map are device arrays.
+enum { GG_TRIL = 0, GG_SLT = 1, GG_NN = 2, GG_TN = 3, GG_NT = 4 };
+struct GemmGroupItem {
   const double* A;
   const double* B;
   double* C;
   double* part;
   long lda, ldb, ldc;
-  double beta;
+  double alpha, beta;
   int m, n, k, flags, kchunk, nsplit, tiles, b0;
 };
-size_t sym_group_item(const GemmArgs& g, int kchunk, double* part, SymGroupItem& it);
-hipError_t gemm_sym_group_launch(int slt, const SymGroupItem* d_items, int count,
-                                 const int* d_map, int total_wg, int max_tot, double flops,
-                                 hipStream_t s);
-
-// The same for plain operands (no gathered columns; acol and ccol unused).
-hipError_t gemm_batched_dense_launch(const GemmDesc* d_desc, int count, int max_m, int max_n,
-                                     double alpha, double beta, int flags, hipStream_t s);
+size_t gemm_group_item(const GemmArgs& g, int kchunk, double* part, GemmGroupItem& it,
+                       double* flops);
+hipError_t gemm_group_launch(int kind, const GemmGroupItem* d_items, int count, const int* d_map,
+                             int total_wg, int max_tot, bool split, double flops, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Kernel timer (ktimer.hip): per-launch HIP events on the launching stream,

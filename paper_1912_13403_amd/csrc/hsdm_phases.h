@@ -13,10 +13,11 @@ hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, d
                      hipStream_t s);
 
 // The same for several matrices at once: the tasks advance one panel pair
-// per round, and the Householder QRs of the round's panels run in shared
-// cooperative launches (each panel alone fills few compute units).  The
-// host vectors are the caller's (kept until the stream has run the work);
-// d_buf is device memory of sy2sb_group_bytes(...) bytes.
+// per round, and every step of a round runs in shared launches over the
+// tasks (each task's panel QR and tall-skinny products alone fill few
+// compute units); only the trailing rank-2B / rank-4B updates stay one
+// launch per task.  The host vectors are the caller's (kept until the stream
+// has run the work); d_buf is device memory of sy2sb_group_bytes(...) bytes.
 struct Sy2sbArgs {
   int n;
   double* A;
@@ -36,11 +37,31 @@ struct PanelQrTask {
   long ldp, ldv, span;
   int h, g0, G, pad;
 };
+// out (B x B, leading dimension ldo) = U^T W for h x B operands, from G
+// per-workgroup partial sums in part; b0: the item's first workgroup
+struct AtbGroupItem {
+  const double* U;
+  const double* W;
+  double* part;
+  double* out;
+  long ldu, ldw, ldo;
+  int h, G, b0, pad;
+};
+// dst (m x n, leading dimension ldd) = src (leading dimension lds)
+struct CopyGroupItem {
+  const double* src;
+  double* dst;
+  long lds, ldd;
+  int m, n;
+};
 struct Sy2sbGroupHost {
   std::vector<PanelQrTask> desc;
   std::vector<int> wgmap;
-  std::vector<SymGroupItem> sym;  // grouped symmetric products of every round
-  std::vector<int> symmap;
+  std::vector<GemmGroupItem> gemm;  // grouped tall-skinny products of every round
+  std::vector<int> gemmmap;
+  std::vector<AtbGroupItem> atb;
+  std::vector<int> atbmap;
+  std::vector<CopyGroupItem> copy;
 };
 size_t sy2sb_group_bytes(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& host);
 hipError_t sy2sb_run_group(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& host, void* d_buf,

@@ -17,6 +17,9 @@
 //     Both large products run on the FP64 MFMA GEMM.
 // After the last panel the band (diagonal blocks and the R factors) is
 // copied into band storage for the bulge-chasing stage.
+#include <algorithm>
+#include <tuple>
+
 #include "hsdm_internal.h"
 #include "hsdm_phases.h"
 #include "hsdm_util.h"
@@ -324,12 +327,12 @@ __global__ void band_extract_kernel(int n, int B, const double* A, long lda, dou
 }
 
 // P = U^T W for h x B tall operands: per-workgroup partial sums, then a
-// fixed-order reduction (reproducible).
+// fixed-order reduction (reproducible).  Workgroup g sums rows
+// [CH g, CH g + CH).
 template <int B>
-__global__ __launch_bounds__(NT) void atb_partial_kernel(int h, const double* U, long ldu,
-                                                         const double* W, long ldw,
-                                                         double* part) {
-  const int g = blockIdx.x, t = threadIdx.x;
+HSDM_DEV void atb_partial_body(int h, const double* U, long ldu, const double* W, long ldw,
+                               double* part, int g) {
+  const int t = threadIdx.x;
   const int r0 = g * CH, nr = min(CH, h - r0);
   __shared__ double Us[CH][B + 1], Ws[CH][B + 1];
   for (int e = t; e < CH * B; e += NT) {
@@ -347,14 +350,51 @@ __global__ __launch_bounds__(NT) void atb_partial_kernel(int h, const double* U,
 }
 
 template <int B>
-__global__ void atb_reduce_kernel(int G, const double* part, double* out, long ldo) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+HSDM_DEV void atb_reduce_body(int G, const double* part, double* out, long ldo, int e) {
   if (e >= B * B) return;
   double s = 0.0;
   for (int q = 0; q < G; q++) s += part[(size_t)q * B * B + e];
   out[(e % B) + (long)(e / B) * ldo] = s;
 }
 
+template <int B>
+__global__ __launch_bounds__(NT) void atb_partial_kernel(int h, const double* U, long ldu,
+                                                         const double* W, long ldw,
+                                                         double* part) {
+  atb_partial_body<B>(h, U, ldu, W, ldw, part, blockIdx.x);
+}
+
+template <int B>
+__global__ void atb_reduce_kernel(int G, const double* part, double* out, long ldo) {
+  atb_reduce_body<B>(G, part, out, ldo, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// The same for the items of a grouped launch: workgroup blockIdx.x works on
+// item wg_item[blockIdx.x]; the reduction takes item blockIdx.y.
+template <int B>
+__global__ __launch_bounds__(NT) void atb_partial_group_kernel(const AtbGroupItem* items,
+                                                               const int* wg_item) {
+  const int q = __builtin_amdgcn_readfirstlane(wg_item[blockIdx.x]);
+  const AtbGroupItem& it = items[q];
+  atb_partial_body<B>(it.h, it.U, it.ldu, it.W, it.ldw, it.part, (int)blockIdx.x - it.b0);
+}
+
+template <int B>
+__global__ void atb_reduce_group_kernel(const AtbGroupItem* items) {
+  const AtbGroupItem& it = items[blockIdx.y];
+  atb_reduce_body<B>(it.G, it.part, it.out, it.ldo, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Column copies of a grouped launch, item blockIdx.y.
+__global__ void copy_group_kernel(const CopyGroupItem* items) {
+  const CopyGroupItem& it = items[blockIdx.y];
+  const long tot = (long)it.m * it.n;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
+       idx += (long)gridDim.x * blockDim.x) {
+    const long i = idx % it.m, j = idx / it.m;
+    it.dst[i + j * it.ldd] = it.src[i + j * it.lds];
+  }
+}
 
 }  // namespace
 
@@ -464,12 +504,15 @@ struct Sy2sb {
   // W (h x B, ld n, holding X on entry) = X - V M / 2 with Y = V T, X = A[r:, r:] Y,
   // M = Y^T X.  Vp: the panel's V (ld ldv), Tp its T; Y receives V T.
   // In three steps (the middle one, the two passes of the symmetric product,
-  // can run grouped over several tasks).
-  hipError_t make_w_pre(int h, const double* Vp, const double* Tp) {
+  // and in a multi-task reduction every step, can run grouped over tasks).
+  GemmArgs pre_args(int h, const double* Vp, const double* Tp) const {
     GemmArgs g{};
     g.m = h; g.n = B; g.k = B; g.A = Vp; g.lda = ldv; g.B = Tp; g.ldb = B; g.C = Y; g.ldc = n;
     g.alpha = 1.0; g.beta = 0.0; g.flags = GF_KB_UPPER;
-    return gemm_launch(g, s);
+    return g;
+  }
+  hipError_t make_w_pre(int h, const double* Vp, const double* Tp) {
+    return gemm_launch(pre_args(h, Vp, Tp), s);
   }
   // X = A[r:, r:] Y: A symmetric with its lower triangle stored,
   // X = tril(A) Y + strict_tril(A)^T Y, both passes reading the lower triangle
@@ -488,37 +531,62 @@ struct Sy2sb {
     HSDM_TRY(gemm_splitk_launch(t, SPLITK, skpart, s));
     return gemm_splitk_launch(u, SPLITK, skpart, s);
   }
-  hipError_t make_w_post(int h, const double* Vp, double* Wp, bool correct, const double* VWc,
-                         const double* WVc) {
+  // the delayed update of the first panel of a pair:
+  // X -= [V1b W1b] Qc with Qc = [W1b V1b]^T Y
+  GemmArgs corr1_args(int h, const double* WVc) const {
     GemmArgs g{};
-    if (correct) {
-      // X -= [V1b W1b] ([W1b V1b]^T Y): the delayed update of the first panel
-      g.m = 2 * B; g.n = B; g.k = h; g.A = WVc; g.lda = n; g.B = Y; g.ldb = n; g.C = Qc;
-      g.ldc = 2 * B; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
-      HSDM_TRY(gemm_splitk_launch(g, SPLITK, skpart, s));
-      g = GemmArgs{};
-      g.m = h; g.n = B; g.k = 2 * B; g.A = VWc; g.lda = n; g.B = Qc; g.ldb = 2 * B; g.C = Wp;
-      g.ldc = n; g.alpha = -1.0; g.beta = 1.0;
-      HSDM_TRY(gemm_launch(g, s));
-    }
-    // M = Y^T X
-    const int G = ceil_div(h, CH);
-    hipLaunchKernelGGL((atb_partial_kernel<BB>), dim3(G), dim3(NT), 0, s, h, Y, (long)n, Wp,
-                       (long)n, apart);
-    HSDM_TRY(hipGetLastError());
-    hipLaunchKernelGGL((atb_reduce_kernel<BB>), dim3(ceil_div(B * B, 256)), dim3(256), 0, s, G,
-                       apart, M, (long)B);
-    HSDM_TRY(hipGetLastError());
-    g = GemmArgs{};
+    g.m = 2 * B; g.n = B; g.k = h; g.A = WVc; g.lda = n; g.B = Y; g.ldb = n; g.C = Qc;
+    g.ldc = 2 * B; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
+    return g;
+  }
+  GemmArgs corr2_args(int h, const double* VWc, double* Wp) const {
+    GemmArgs g{};
+    g.m = h; g.n = B; g.k = 2 * B; g.A = VWc; g.lda = n; g.B = Qc; g.ldb = 2 * B; g.C = Wp;
+    g.ldc = n; g.alpha = -1.0; g.beta = 1.0;
+    return g;
+  }
+  // M = Y^T X (partial sums per CH rows)
+  AtbGroupItem atb_item(int h, const double* Wp) const {
+    AtbGroupItem it{};
+    it.U = Y; it.ldu = n; it.W = Wp; it.ldw = n; it.part = apart; it.out = M; it.ldo = B;
+    it.h = h; it.G = ceil_div(h, CH);
+    return it;
+  }
+  // W -= V M / 2
+  GemmArgs fix_args(int h, const double* Vp, double* Wp) const {
+    GemmArgs g{};
     g.m = h; g.n = B; g.k = B; g.A = Vp; g.lda = ldv; g.B = M; g.ldb = B; g.C = Wp; g.ldc = n;
     g.alpha = -0.5; g.beta = 1.0;
-    return gemm_launch(g, s);
+    return g;
   }
-  hipError_t make_w(int r, int h, const double* Vp, const double* Tp, double* Wp, bool correct,
-                    const double* VWc, const double* WVc) {
-    HSDM_TRY(make_w_pre(h, Vp, Tp));
-    HSDM_TRY(make_w_sym(r, h, Wp));
-    return make_w_post(h, Vp, Wp, correct, VWc, WVc);
+  hipError_t make_w_post(int h, const double* Vp, double* Wp, bool correct, const double* VWc,
+                         const double* WVc) {
+    if (correct) {
+      HSDM_TRY(gemm_splitk_launch(corr1_args(h, WVc), SPLITK, skpart, s));
+      HSDM_TRY(gemm_launch(corr2_args(h, VWc, Wp), s));
+    }
+    const AtbGroupItem a = atb_item(h, Wp);
+    hipLaunchKernelGGL((atb_partial_kernel<BB>), dim3(a.G), dim3(NT), 0, s, h, a.U, a.ldu, a.W,
+                       a.ldw, a.part);
+    HSDM_TRY(hipGetLastError());
+    hipLaunchKernelGGL((atb_reduce_kernel<BB>), dim3(ceil_div(B * B, 256)), dim3(256), 0, s, a.G,
+                       a.part, a.out, a.ldo);
+    HSDM_TRY(hipGetLastError());
+    return gemm_launch(fix_args(h, Vp, Wp), s);
+  }
+  // the panel's V and W into the update operands: VW[:, o:o+2B] = [V W],
+  // WV[:, o:o+2B] = [W V] (o = 0 first panel, B rows and 2B columns in for
+  // the second panel of a pair)
+  void copies(int h, const double* Vp, const double* Wp, long o, CopyGroupItem (&c)[3]) const {
+    c[0] = CopyGroupItem{Vp, VW + o, ldv, (long)n, h, B};
+    c[1] = CopyGroupItem{Wp, WV + o, (long)n, (long)n, h, B};
+    c[2] = CopyGroupItem{Vp, WV + o + (size_t)n * B, ldv, (long)n, h, B};
+  }
+  hipError_t run_copies(int h, const double* Vp, const double* Wp, long o) {
+    CopyGroupItem c[3];
+    copies(h, Vp, Wp, o, c);
+    for (auto& x : c) HSDM_TRY(dev_copy(x.src, x.lds, x.dst, x.ldd, x.m, x.n, s));
+    return hipSuccess;
   }
   // A[r:, r:] -= VWr WVr^T (lower), k columns
   hipError_t syr2k(int r, int h, const double* VWr, const double* WVr, int k) {
@@ -528,70 +596,55 @@ struct Sy2sb {
     g.flags = GF_C_LOWER_TILES | GF_C_LOWER_ONLY;
     return gemm_launch(g, s);
   }
-  // after the QR of panel p: its W, and either the trailing update (panel
-  // alone) or the update of panel p+1's columns (pair).  Steps a and b come
-  // before and after the symmetric product (first_sym).
-  bool first_has_w(int p) const { return height(p) > 1; }
-  hipError_t after_first_a(int p) {
-    const int c0 = p * B, r0 = c0 + B, h = n - r0;
-    if (h <= 1) return hipSuccess;
-    return make_w_pre(h, Vst + r0 + (long)c0 * ldv, T1 + (size_t)p * B * B);
-  }
-  void first_sym(int p, GemmArgs& tril, GemmArgs& slt) const {
-    const int r0 = (p + 1) * B;
-    sym_args(r0, n - r0, VW + (size_t)n * B, tril, slt);
-  }
-  hipError_t after_first_b(int p) {
-    const int c0 = p * B, r0 = c0 + B, h = n - r0;
-    if (h <= 1) return hipSuccess;
-    const double* V1 = Vst + r0 + (long)c0 * ldv;
-    double* W1 = VW + (size_t)n * B;
-    HSDM_TRY(make_w_post(h, V1, W1, false, nullptr, nullptr));
-    // VW[:, 0:2B] = [V1 W1], WV[:, 0:2B] = [W1 V1]
-    HSDM_TRY(dev_copy(V1, ldv, VW, n, h, B, s));
-    HSDM_TRY(dev_copy(W1, n, WV, n, h, B, s));
-    HSDM_TRY(dev_copy(V1, ldv, WV + (size_t)n * B, n, h, B, s));
-    if (advance(p) == 1) return syr2k(r0, h, VW, WV, 2 * B);
-    // columns of panel p+1: A[r0:, r0:r0+B] -= [V1 W1] [W1 V1][0:B]^T (lower part)
+  // columns of panel p+1: A[r0:, r0:r0+B] -= [V1 W1] [W1 V1][0:B]^T (lower part)
+  GemmArgs col_args(int r0, int h) const {
     GemmArgs g{};
     g.m = h; g.n = B; g.k = 2 * B; g.A = VW; g.lda = n; g.B = WV; g.ldb = n;
     g.C = A + r0 + (long)r0 * lda; g.ldc = lda; g.alpha = -1.0; g.beta = 1.0; g.ta = 0;
     g.tb = 1; g.flags = GF_C_LOWER_ONLY;
-    return gemm_launch(g, s);
+    return g;
+  }
+  // after the QR of panel p: its W, and either the trailing update (panel
+  // alone) or the update of panel p+1's columns (pair).
+  bool first_has_w(int p) const { return height(p) > 1; }
+  const double* first_v(int p) const { return Vst + (p + 1) * B + (long)p * B * ldv; }
+  const double* first_t(int p) const { return T1 + (size_t)p * B * B; }
+  double* first_w() const { return VW + (size_t)n * B; }
+  void first_sym(int p, GemmArgs& tril, GemmArgs& slt) const {
+    const int r0 = (p + 1) * B;
+    sym_args(r0, n - r0, first_w(), tril, slt);
   }
   hipError_t after_first(int p) {
     if (!first_has_w(p)) return hipSuccess;
-    const int r0 = (p + 1) * B;
-    HSDM_TRY(after_first_a(p));
-    HSDM_TRY(make_w_sym(r0, n - r0, VW + (size_t)n * B));
-    return after_first_b(p);
+    const int r0 = (p + 1) * B, h = n - r0;
+    const double* V1 = first_v(p);
+    double* W1 = first_w();
+    HSDM_TRY(make_w_pre(h, V1, first_t(p)));
+    HSDM_TRY(make_w_sym(r0, h, W1));
+    HSDM_TRY(make_w_post(h, V1, W1, false, nullptr, nullptr));
+    HSDM_TRY(run_copies(h, V1, W1, 0));
+    if (advance(p) == 1) return syr2k(r0, h, VW, WV, 2 * B);
+    return gemm_launch(col_args(r0, h), s);
   }
   // after the QR of panel p+1 of a pair: its W (with the first panel's
   // delayed update) and the pair's rank-4B trailing update
-  hipError_t after_second_a(int p) {
-    const int r0 = (p + 1) * B, h2 = n - r0 - B, r1 = r0 + B;
-    return make_w_pre(h2, Vst + r1 + (long)r0 * ldv, T1 + (size_t)(p + 1) * B * B);
-  }
+  const double* second_v(int p) const { return Vst + (p + 2) * B + (long)(p + 1) * B * ldv; }
+  const double* second_t(int p) const { return T1 + (size_t)(p + 1) * B * B; }
+  double* second_w() const { return VW + B + (size_t)3 * n * B; }
+  static long second_off(int n_, int B_) { return B_ + (long)2 * n_ * B_; }
   void second_sym(int p, GemmArgs& tril, GemmArgs& slt) const {
     const int r1 = (p + 2) * B;
-    sym_args(r1, n - r1, VW + B + (size_t)3 * n * B, tril, slt);
-  }
-  hipError_t after_second_b(int p) {
-    const int r0 = (p + 1) * B, h2 = n - r0 - B, r1 = r0 + B;
-    const double* V2 = Vst + r1 + (long)r0 * ldv;
-    double* W2 = VW + B + (size_t)3 * n * B;
-    HSDM_TRY(make_w_post(h2, V2, W2, true, VW + B, WV + B));
-    // VW[B:, 2B:4B] = [V2 W2], WV[B:, 2B:4B] = [W2 V2]
-    HSDM_TRY(dev_copy(V2, ldv, VW + B + (size_t)2 * n * B, n, h2, B, s));
-    HSDM_TRY(dev_copy(W2, n, WV + B + (size_t)2 * n * B, n, h2, B, s));
-    HSDM_TRY(dev_copy(V2, ldv, WV + B + (size_t)3 * n * B, n, h2, B, s));
-    return syr2k(r1, h2, VW + B, WV + B, 4 * B);
+    sym_args(r1, n - r1, second_w(), tril, slt);
   }
   hipError_t after_second(int p) {
-    const int r1 = (p + 2) * B;
-    HSDM_TRY(after_second_a(p));
-    HSDM_TRY(make_w_sym(r1, n - r1, VW + B + (size_t)3 * n * B));
-    return after_second_b(p);
+    const int r1 = (p + 2) * B, h2 = n - r1;
+    const double* V2 = second_v(p);
+    double* W2 = second_w();
+    HSDM_TRY(make_w_pre(h2, V2, second_t(p)));
+    HSDM_TRY(make_w_sym(r1, h2, W2));
+    HSDM_TRY(make_w_post(h2, V2, W2, true, VW + B, WV + B));
+    HSDM_TRY(run_copies(h2, V2, W2, second_off(n, B)));
+    return syr2k(r1, h2, VW + B, WV + B, 4 * B);
   }
   hipError_t finish() {
     const long tot = (long)n * ldab;
@@ -643,38 +696,49 @@ std::vector<std::vector<std::pair<int, int>>> group_rounds(const std::vector<Sy2
   return rounds;
 }
 
-// Descriptors of the grouped launches in schedule order: for each round,
-// the first panels' QRs, their symmetric products (lower-triangle pass and
-// transposed pass), then the same for the second panels.  QR lists are cut
-// into launches of at most PQR_MAX_WG workgroups.  launch = (first
-// descriptor, count, first map entry, workgroups).
+// Grouped launches (descriptor range [d0, d0 + nd), workgroup map entries
+// from m0).  QR lists are cut into launches of at most PQR_MAX_WG
+// workgroups; every other step of a round is one launch over the tasks
+// taking part in it (nd = 0: none).
 struct QrLaunch {
   int d0, nd, m0, nwg;
 };
-struct SymLaunch {
-  int d0, nd, m0, nwg, max_tot;
+struct GemmLaunch {
+  int kind, d0, nd, m0, nwg, max_tot;
+  bool split;
   double flops;
 };
-struct Schedule {
-  std::vector<std::vector<std::pair<int, int>>> rounds;
-  std::vector<std::vector<QrLaunch>> first, second;
-  std::vector<SymLaunch> ftril, fslt, stril, sslt;  // one per round (nd = 0: none)
+struct AtbLaunch {
+  int d0, nd, m0, nwg;
+};
+struct CopyLaunch {
+  int d0, nd;
+  long max_tot;
+};
+// One round: the first panels' QRs and their W (Y = V T, the two passes of
+// X = A22 Y, M = Y^T X, W = X - V M / 2), the copies into the update
+// operands, the column update of the pairs' second panels (the single
+// panels' trailing updates run per task), then the same for the second
+// panels with the first panel's delayed update (Qc = [W1 V1]^T Y,
+// X -= [V1 W1] Qc) before M.
+struct Round {
+  std::vector<std::pair<int, int>> tasks;
+  std::vector<QrLaunch> qr1, qr2;
+  GemmLaunch pre1, tril1, slt1, fix1, col1, pre2, tril2, slt2, corr1, corr2, fix2;
+  AtbLaunch atb1, atb2;
+  CopyLaunch cp1, cp2;
 };
 
-void build_schedule(const std::vector<Sy2sb>& R, Sy2sbGroupHost& host, Schedule& S) {
-  S.rounds = group_rounds(R);
-  const size_t nr = S.rounds.size();
-  host.desc.clear();
-  host.wgmap.clear();
-  host.sym.clear();
-  host.symmap.clear();
-  S.first.assign(nr, {});
-  S.second.assign(nr, {});
-  S.ftril.assign(nr, SymLaunch{});
-  S.fslt.assign(nr, SymLaunch{});
-  S.stril.assign(nr, SymLaunch{});
-  S.sslt.assign(nr, SymLaunch{});
-  auto emit = [&](const std::vector<PanelQrTask>& list, std::vector<QrLaunch>& out) {
+int gemm_kind(const GemmArgs& g) {
+  if (g.flags & GF_A_TRIL) return GG_TRIL;
+  if (g.flags & GF_A_SLT) return GG_SLT;
+  if (g.ta) return GG_TN;
+  return g.tb ? GG_NT : GG_NN;
+}
+
+struct Builder {
+  Sy2sbGroupHost& host;
+  void qr(const std::vector<PanelQrTask>& list, std::vector<QrLaunch>& out) {
     size_t i = 0;
     while (i < list.size()) {
       QrLaunch L{(int)host.desc.size(), 0, (int)host.wgmap.size(), 0};
@@ -688,93 +752,205 @@ void build_schedule(const std::vector<Sy2sb>& R, Sy2sbGroupHost& host, Schedule&
       }
       out.push_back(L);
     }
-  };
-  auto emit_sym = [&](const std::vector<std::pair<GemmArgs, double*>>& list, SymLaunch& L) {
-    L = SymLaunch{(int)host.sym.size(), 0, (int)host.symmap.size(), 0, 0, 0.0};
+  }
+  // products (args, K slice (0: in place), split-K partial buffer), all of one kind
+  GemmLaunch gemm(const std::vector<std::tuple<GemmArgs, int, double*>>& list) {
+    GemmLaunch L{GG_NN, (int)host.gemm.size(), 0, (int)host.gemmmap.size(), 0, 0, false, 0.0};
     for (auto& e : list) {
-      SymGroupItem it;
-      const int w = (int)sym_group_item(e.first, SPLITK, e.second, it);
+      GemmGroupItem it;
+      double f = 0.0;
+      const GemmArgs& g = std::get<0>(e);
+      if (g.m <= 0 || g.n <= 0) continue;
+      L.kind = gemm_kind(g);
+      const int w = (int)gemm_group_item(g, std::get<1>(e), std::get<2>(e), it, &f);
       it.b0 = L.nwg;
-      for (int q = 0; q < w; q++) host.symmap.push_back(L.nd);
+      for (int q = 0; q < w; q++) host.gemmmap.push_back(L.nd);
       L.nwg += w;
       L.nd++;
-      L.max_tot = std::max(L.max_tot, it.m * it.n);
-      L.flops += (double)it.m * it.n * it.k;  // one of the two halves of 2 m n k
-      host.sym.push_back(it);
+      L.flops += f;
+      if (it.kchunk > 0) {
+        L.split = true;
+        L.max_tot = std::max(L.max_tot, it.m * it.n);
+      }
+      host.gemm.push_back(it);
     }
-  };
-  for (size_t k = 0; k < nr; k++) {
-    std::vector<PanelQrTask> a, b;
-    std::vector<std::pair<GemmArgs, double*>> ft, fs, st, ss;
-    for (auto& e : S.rounds[k]) {
+    return L;
+  }
+  AtbLaunch atb(const std::vector<AtbGroupItem>& list) {
+    AtbLaunch L{(int)host.atb.size(), 0, (int)host.atbmap.size(), 0};
+    for (AtbGroupItem it : list) {
+      it.b0 = L.nwg;
+      for (int q = 0; q < it.G; q++) host.atbmap.push_back(L.nd);
+      L.nwg += it.G;
+      L.nd++;
+      host.atb.push_back(it);
+    }
+    return L;
+  }
+  CopyLaunch copy(const std::vector<CopyGroupItem>& list) {
+    CopyLaunch L{(int)host.copy.size(), 0, 0};
+    for (const CopyGroupItem& it : list) {
+      L.max_tot = std::max(L.max_tot, (long)it.m * it.n);
+      L.nd++;
+      host.copy.push_back(it);
+    }
+    return L;
+  }
+};
+
+void build_schedule(const std::vector<Sy2sb>& R, Sy2sbGroupHost& host, std::vector<Round>& S) {
+  const auto rounds = group_rounds(R);
+  host.desc.clear();
+  host.wgmap.clear();
+  host.gemm.clear();
+  host.gemmmap.clear();
+  host.atb.clear();
+  host.atbmap.clear();
+  host.copy.clear();
+  S.assign(rounds.size(), Round{});
+  Builder bld{host};
+  using GL = std::vector<std::tuple<GemmArgs, int, double*>>;
+  for (size_t k = 0; k < rounds.size(); k++) {
+    Round& rd = S[k];
+    rd.tasks = rounds[k];
+    std::vector<PanelQrTask> q1, q2;
+    GL pre1, tril1, slt1, fix1, col1, pre2, tril2, slt2, corr1, corr2, fix2;
+    std::vector<AtbGroupItem> atb1, atb2;
+    std::vector<CopyGroupItem> cp1, cp2;
+    for (auto& e : rd.tasks) {
       const Sy2sb& T = R[e.first];
-      a.push_back(T.qr_desc(e.second));
-      if (T.first_has_w(e.second)) {
+      const int p = e.second;
+      q1.push_back(T.qr_desc(p));
+      if (T.first_has_w(p)) {
+        const int r0 = (p + 1) * T.B, h = T.n - r0;
+        pre1.emplace_back(T.pre_args(h, T.first_v(p), T.first_t(p)), 0, nullptr);
         GemmArgs t, u;
-        T.first_sym(e.second, t, u);
-        ft.emplace_back(t, T.skpart);
-        fs.emplace_back(u, T.skpart);
+        T.first_sym(p, t, u);
+        tril1.emplace_back(t, SPLITK, T.skpart);
+        slt1.emplace_back(u, SPLITK, T.skpart);
+        atb1.push_back(T.atb_item(h, T.first_w()));
+        fix1.emplace_back(T.fix_args(h, T.first_v(p), T.first_w()), 0, nullptr);
+        CopyGroupItem c[3];
+        T.copies(h, T.first_v(p), T.first_w(), 0, c);
+        cp1.insert(cp1.end(), c, c + 3);
+        if (T.advance(p) == 2) col1.emplace_back(T.col_args(r0, h), 0, nullptr);
       }
-      if (T.advance(e.second) == 2) {
-        b.push_back(T.qr_desc(e.second + 1));
+      if (T.advance(p) == 2) {
+        const int r1 = (p + 2) * T.B, h2 = T.n - r1;
+        q2.push_back(T.qr_desc(p + 1));
+        pre2.emplace_back(T.pre_args(h2, T.second_v(p), T.second_t(p)), 0, nullptr);
         GemmArgs t, u;
-        T.second_sym(e.second, t, u);
-        st.emplace_back(t, T.skpart);
-        ss.emplace_back(u, T.skpart);
+        T.second_sym(p, t, u);
+        tril2.emplace_back(t, SPLITK, T.skpart);
+        slt2.emplace_back(u, SPLITK, T.skpart);
+        corr1.emplace_back(T.corr1_args(h2, T.WV + T.B), h2 > SPLITK ? SPLITK : 0, T.skpart);
+        corr2.emplace_back(T.corr2_args(h2, T.VW + T.B, T.second_w()), 0, nullptr);
+        atb2.push_back(T.atb_item(h2, T.second_w()));
+        fix2.emplace_back(T.fix_args(h2, T.second_v(p), T.second_w()), 0, nullptr);
+        CopyGroupItem c[3];
+        T.copies(h2, T.second_v(p), T.second_w(), Sy2sb::second_off(T.n, T.B), c);
+        cp2.insert(cp2.end(), c, c + 3);
       }
     }
-    emit(a, S.first[k]);
-    emit(b, S.second[k]);
-    emit_sym(ft, S.ftril[k]);
-    emit_sym(fs, S.fslt[k]);
-    emit_sym(st, S.stril[k]);
-    emit_sym(ss, S.sslt[k]);
+    bld.qr(q1, rd.qr1);
+    rd.pre1 = bld.gemm(pre1);
+    rd.tril1 = bld.gemm(tril1);
+    rd.slt1 = bld.gemm(slt1);
+    rd.atb1 = bld.atb(atb1);
+    rd.fix1 = bld.gemm(fix1);
+    rd.cp1 = bld.copy(cp1);
+    rd.col1 = bld.gemm(col1);
+    bld.qr(q2, rd.qr2);
+    rd.pre2 = bld.gemm(pre2);
+    rd.tril2 = bld.gemm(tril2);
+    rd.slt2 = bld.gemm(slt2);
+    rd.corr1 = bld.gemm(corr1);
+    rd.corr2 = bld.gemm(corr2);
+    rd.atb2 = bld.atb(atb2);
+    rd.fix2 = bld.gemm(fix2);
+    rd.cp2 = bld.copy(cp2);
   }
 }
 
-hipError_t launch_qr_group(const QrLaunch& L, PanelQrTask* d_desc, int* d_map, const double* fl,
-                           hipStream_t s) {
-  PanelQrTask* tasks = d_desc + L.d0;
-  const int* map = d_map + L.m0;
+struct GroupDev {
+  PanelQrTask* desc;
+  GemmGroupItem* gemm;
+  AtbGroupItem* atb;
+  CopyGroupItem* copy;
+  int* map;
+  int* gemmmap;
+  int* atbmap;
+};
+
+// device layout: the item arrays (8-byte aligned structures), then the maps
+GroupDev group_dev(void* d_buf, const Sy2sbGroupHost& host) {
+  GroupDev g{};
+  char* p = (char*)d_buf;
+  g.desc = (PanelQrTask*)p;
+  p += sizeof(PanelQrTask) * (host.desc.size() + 1);
+  g.gemm = (GemmGroupItem*)p;
+  p += sizeof(GemmGroupItem) * (host.gemm.size() + 1);
+  g.atb = (AtbGroupItem*)p;
+  p += sizeof(AtbGroupItem) * (host.atb.size() + 1);
+  g.copy = (CopyGroupItem*)p;
+  p += sizeof(CopyGroupItem) * (host.copy.size() + 1);
+  g.map = (int*)p;
+  p += sizeof(int) * (host.wgmap.size() + 1);
+  g.gemmmap = (int*)p;
+  p += sizeof(int) * (host.gemmmap.size() + 1);
+  g.atbmap = (int*)p;
+  return g;
+}
+
+size_t group_bytes(const Sy2sbGroupHost& host) {
+  return sizeof(PanelQrTask) * (host.desc.size() + 1) +
+         sizeof(GemmGroupItem) * (host.gemm.size() + 1) +
+         sizeof(AtbGroupItem) * (host.atb.size() + 1) +
+         sizeof(CopyGroupItem) * (host.copy.size() + 1) + sizeof(int) * (host.wgmap.size() + 1) +
+         sizeof(int) * (host.gemmmap.size() + 1) + sizeof(int) * (host.atbmap.size() + 1);
+}
+
+template <class T>
+hipError_t upload(T* d, const std::vector<T>& v, hipStream_t s) {
+  if (v.empty()) return hipSuccess;
+  return hipMemcpyAsync(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s);
+}
+
+hipError_t launch_qr_group(const QrLaunch& L, const GroupDev& D, double fl, hipStream_t s) {
+  PanelQrTask* tasks = D.desc + L.d0;
+  const int* map = D.map + L.m0;
   hipLaunchKernelGGL(fill_nan_group_kernel, dim3(64, L.nd), dim3(256), 0, s, tasks);
   HSDM_TRY(hipGetLastError());
   void* args[] = {(void*)&tasks, (void*)&map};
-  kt_begin("panel_qr_group_kernel<32>", *fl, 0.0, 0, s);
+  kt_begin("panel_qr_group_kernel<32>", fl, 0.0, 0, s);
   HSDM_TRY(hipLaunchCooperativeKernel((const void*)panel_qr_group_kernel<32>, dim3(L.nwg),
                                       dim3(NT), args, 0, s));
   kt_end(s);
   return hipSuccess;
 }
 
-struct GroupDev {
-  PanelQrTask* desc;
-  int* map;
-  SymGroupItem* sym;
-  int* symmap;
-};
-
-GroupDev group_dev(void* d_buf, const Sy2sbGroupHost& host) {
-  GroupDev g{};
-  char* p = (char*)d_buf;
-  g.desc = (PanelQrTask*)p;
-  p += sizeof(PanelQrTask) * (host.desc.size() + 1);
-  g.sym = (SymGroupItem*)p;
-  p += sizeof(SymGroupItem) * (host.sym.size() + 1);
-  g.map = (int*)p;
-  p += sizeof(int) * (host.wgmap.size() + 1);
-  g.symmap = (int*)p;
-  return g;
-}
-
-size_t group_bytes(const Sy2sbGroupHost& host) {
-  return sizeof(PanelQrTask) * (host.desc.size() + 1) + sizeof(SymGroupItem) * (host.sym.size() + 1) +
-         sizeof(int) * (host.wgmap.size() + 1) + sizeof(int) * (host.symmap.size() + 1);
-}
-
-hipError_t launch_sym(int slt, const SymLaunch& L, const GroupDev& D, hipStream_t s) {
+hipError_t launch_gemm(const GemmLaunch& L, const GroupDev& D, hipStream_t s) {
   if (L.nd == 0) return hipSuccess;
-  return gemm_sym_group_launch(slt, D.sym + L.d0, L.nd, D.symmap + L.m0, L.nwg, L.max_tot,
-                               2.0 * L.flops / 2.0, s);
+  return gemm_group_launch(L.kind, D.gemm + L.d0, L.nd, D.gemmmap + L.m0, L.nwg, L.max_tot,
+                           L.split, L.flops, s);
+}
+
+hipError_t launch_atb(const AtbLaunch& L, const GroupDev& D, hipStream_t s) {
+  if (L.nd == 0) return hipSuccess;
+  hipLaunchKernelGGL((atb_partial_group_kernel<32>), dim3(L.nwg), dim3(NT), 0, s, D.atb + L.d0,
+                     (const int*)(D.atbmap + L.m0));
+  HSDM_TRY(hipGetLastError());
+  hipLaunchKernelGGL((atb_reduce_group_kernel<32>), dim3(ceil_div(32 * 32, 256), L.nd), dim3(256),
+                     0, s, (const AtbGroupItem*)(D.atb + L.d0));
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const CopyLaunch& L, const GroupDev& D, hipStream_t s) {
+  if (L.nd == 0 || L.max_tot <= 0) return hipSuccess;
+  const int bx = (int)std::max(1L, std::min(256L, (L.max_tot + 1023) / 1024));
+  hipLaunchKernelGGL(copy_group_kernel, dim3(bx, L.nd), dim3(256), 0, s,
+                     (const CopyGroupItem*)(D.copy + L.d0));
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -782,7 +958,7 @@ hipError_t launch_sym(int slt, const SymLaunch& L, const GroupDev& D, hipStream_
 size_t sy2sb_group_bytes(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& host) {
   std::vector<Sy2sb> R;
   for (int i = 0; i < nt; i++) R.emplace_back(t[i], B, nullptr);
-  Schedule S;
+  std::vector<Round> S;
   build_schedule(R, host, S);
   return group_bytes(host);
 }
@@ -792,45 +968,49 @@ hipError_t sy2sb_run_group(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& ho
   if (B != 32) return hipErrorInvalidValue;
   std::vector<Sy2sb> R;
   for (int i = 0; i < nt; i++) R.emplace_back(t[i], B, s);
-  Schedule S;
+  std::vector<Round> S;
   build_schedule(R, host, S);
   const GroupDev D = group_dev(d_buf, host);
-  if (!host.desc.empty()) {
-    HSDM_TRY(hipMemcpyAsync(D.desc, host.desc.data(), sizeof(PanelQrTask) * host.desc.size(),
-                            hipMemcpyHostToDevice, s));
-    HSDM_TRY(hipMemcpyAsync(D.map, host.wgmap.data(), sizeof(int) * host.wgmap.size(),
-                            hipMemcpyHostToDevice, s));
-  }
-  if (!host.sym.empty()) {
-    HSDM_TRY(hipMemcpyAsync(D.sym, host.sym.data(), sizeof(SymGroupItem) * host.sym.size(),
-                            hipMemcpyHostToDevice, s));
-    HSDM_TRY(hipMemcpyAsync(D.symmap, host.symmap.data(), sizeof(int) * host.symmap.size(),
-                            hipMemcpyHostToDevice, s));
-  }
-  auto flops = [&](const QrLaunch& L) {
+  HSDM_TRY(upload(D.desc, host.desc, s));
+  HSDM_TRY(upload(D.gemm, host.gemm, s));
+  HSDM_TRY(upload(D.atb, host.atb, s));
+  HSDM_TRY(upload(D.copy, host.copy, s));
+  HSDM_TRY(upload(D.map, host.wgmap, s));
+  HSDM_TRY(upload(D.gemmmap, host.gemmmap, s));
+  HSDM_TRY(upload(D.atbmap, host.atbmap, s));
+  auto qr_flops = [&](const QrLaunch& L) {
     double f = 0.0;
     for (int i = 0; i < L.nd; i++) f += 2.0 * host.desc[L.d0 + i].h * B * B;
     return f;
   };
-  for (size_t k = 0; k < S.rounds.size(); k++) {
-    for (const QrLaunch& L : S.first[k]) {
-      const double f = flops(L);
-      HSDM_TRY(launch_qr_group(L, D.desc, D.map, &f, s));
+  for (const Round& rd : S) {
+    for (const QrLaunch& L : rd.qr1) HSDM_TRY(launch_qr_group(L, D, qr_flops(L), s));
+    HSDM_TRY(launch_gemm(rd.pre1, D, s));
+    HSDM_TRY(launch_gemm(rd.tril1, D, s));
+    HSDM_TRY(launch_gemm(rd.slt1, D, s));
+    HSDM_TRY(launch_atb(rd.atb1, D, s));
+    HSDM_TRY(launch_gemm(rd.fix1, D, s));
+    HSDM_TRY(launch_copy(rd.cp1, D, s));
+    for (auto& e : rd.tasks) {
+      Sy2sb& T = R[e.first];
+      const int p = e.second, r0 = (p + 1) * B;
+      if (T.first_has_w(p) && T.advance(p) == 1) HSDM_TRY(T.syr2k(r0, T.n - r0, T.VW, T.WV, 2 * B));
     }
-    for (auto& e : S.rounds[k]) HSDM_TRY(R[e.first].after_first_a(e.second));
-    HSDM_TRY(launch_sym(0, S.ftril[k], D, s));
-    HSDM_TRY(launch_sym(1, S.fslt[k], D, s));
-    for (auto& e : S.rounds[k]) HSDM_TRY(R[e.first].after_first_b(e.second));
-    for (const QrLaunch& L : S.second[k]) {
-      const double f = flops(L);
-      HSDM_TRY(launch_qr_group(L, D.desc, D.map, &f, s));
+    HSDM_TRY(launch_gemm(rd.col1, D, s));
+    for (const QrLaunch& L : rd.qr2) HSDM_TRY(launch_qr_group(L, D, qr_flops(L), s));
+    HSDM_TRY(launch_gemm(rd.pre2, D, s));
+    HSDM_TRY(launch_gemm(rd.tril2, D, s));
+    HSDM_TRY(launch_gemm(rd.slt2, D, s));
+    HSDM_TRY(launch_gemm(rd.corr1, D, s));
+    HSDM_TRY(launch_gemm(rd.corr2, D, s));
+    HSDM_TRY(launch_atb(rd.atb2, D, s));
+    HSDM_TRY(launch_gemm(rd.fix2, D, s));
+    HSDM_TRY(launch_copy(rd.cp2, D, s));
+    for (auto& e : rd.tasks) {
+      Sy2sb& T = R[e.first];
+      const int p = e.second, r1 = (p + 2) * B;
+      if (T.advance(p) == 2) HSDM_TRY(T.syr2k(r1, T.n - r1, T.VW + B, T.WV + B, 4 * B));
     }
-    for (auto& e : S.rounds[k])
-      if (R[e.first].advance(e.second) == 2) HSDM_TRY(R[e.first].after_second_a(e.second));
-    HSDM_TRY(launch_sym(0, S.stril[k], D, s));
-    HSDM_TRY(launch_sym(1, S.sslt[k], D, s));
-    for (auto& e : S.rounds[k])
-      if (R[e.first].advance(e.second) == 2) HSDM_TRY(R[e.first].after_second_b(e.second));
   }
   for (auto& r : R) HSDM_TRY(r.finish());
   return hipSuccess;
