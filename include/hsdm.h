@@ -135,9 +135,13 @@ int hsdm_solve_dm_complex(hsdm_handle h, int n, const void *H, int ldh, const vo
  * the degeneracy window of it share the remainder equally per unit weight.
  * Each task runs the path of the single solves (its factor of S cached per
  * (S[p], n[p], lds[p]) in a task context owned by the handle and kept until
- * hsdm_finalize; hsdm_reinit forgets every task's factor); the tridiagonal
+ * hsdm_finalize; hsdm_reinit forgets every task's factor; tasks of one call
+ * with the same S[p], n[p], lds[p] share one factorization); the tridiagonal
  * eigenvectors of all tasks are kept until the joint occupations are known,
- * then each task back-transforms its occupied vectors.  Status codes as the
+ * then each task back-transforms its occupied vectors.  With several tasks
+ * their independent phases run on the handle's worker streams, which start
+ * after the work already queued on `stream` and which `stream` waits for
+ * before it continues.  Status codes as the
  * single solves; argument k is reported as -k (n, H, ... arrays: -4 for a
  * missing array or a bad n[p], -5 ... -15 for the entry of problem p). */
 int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int *n,
@@ -170,7 +174,8 @@ int hsdm_solve_ev_complex(hsdm_handle h, int n, const void *H, int ldh, const vo
  * and factor of S) are owned by the handle and picked by S identity, so a
  * task whose S (pointer, n, lds) was factored in an earlier call reuses the
  * factor; otherwise the least recently used context is taken.  Other
- * arguments and status codes as hsdm_solve_dm_batch (-3: a missing array or
+ * arguments, factor sharing within a call, the worker streams and status
+ * codes as hsdm_solve_dm_batch (-3: a missing array or
  * a bad is_complex[p], -9: n_electrons[p], -10: kT[p], -11: f_max[p]). */
 int hsdm_solve_dm_group(hsdm_handle h, int nprob, const int *is_complex, const int *n,
                         const void *const *H, const int *ldh, const void *const *S,

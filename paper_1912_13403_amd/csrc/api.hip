@@ -19,6 +19,7 @@ namespace {
 
 constexpr int BAND = 32;
 constexpr int NPHASE = 9;
+constexpr int NLANE = 4;  // worker streams of the multi-task solves
 const char* kPhaseNames[NPHASE] = {"cholesky_inverse", "standard_form", "full_to_band",
                                    "band_to_tridiagonal", "divide_conquer", "backtransform_stage2",
                                    "backtransform_stage1", "backtransform_cholesky", "density"};
@@ -107,6 +108,14 @@ struct hsdm_ctx {
   int cws_n = 0;
   double* cws = nullptr;
   double *HR, *SR, *DR, *ER;
+  // worker streams of the multi-task solves (created on first use, default
+  // priority): the tasks' independent phases run spread over them, ordered
+  // after the caller's stream by lane_ev[NLANE] and joined back through
+  // lane_ev[k]; lane k > 0 embeds Hermitian pencils in lane_buf[k]'s buffers
+  // (lane 0 in the handle's own)
+  hipStream_t lane_s[NLANE] = {};
+  hipEvent_t lane_ev[NLANE + 1] = {};
+  hsdm_ctx* lane_buf[NLANE] = {};
   // cached factor of S, keyed by the caller's S (pointer, n, ld, complex)
   const void* s_ptr = nullptr;
   int s_n = 0, s_ld = 0;
@@ -161,6 +170,67 @@ int ensure_cws(hsdm_ctx* h, int n) {
   h->ER = h->cws + 3 * q;
   h->cws_n = n;
   return HSDM_OK;
+}
+
+void free_lanes(hsdm_ctx* h) {
+  if (h->lane_s[0]) (void)hipDeviceSynchronize();
+  for (int k = 0; k < NLANE; k++) {
+    if (h->lane_s[k]) (void)hipStreamDestroy(h->lane_s[k]);
+    h->lane_s[k] = nullptr;
+    if (h->lane_buf[k]) {
+      free_cws(h->lane_buf[k]);
+      delete h->lane_buf[k];
+      h->lane_buf[k] = nullptr;
+    }
+  }
+  for (int k = 0; k <= NLANE; k++) {
+    if (h->lane_ev[k]) (void)hipEventDestroy(h->lane_ev[k]);
+    h->lane_ev[k] = nullptr;
+  }
+}
+
+int ensure_lanes(hsdm_ctx* h) {
+  if (h->lane_s[0]) return HSDM_OK;
+  for (int k = 0; k < NLANE; k++) {
+    hipError_t e = hipStreamCreateWithFlags(&h->lane_s[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->lane_ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      free_lanes(h);
+      return fail_dev(h, e, "worker stream creation");
+    }
+  }
+  hipError_t e = hipEventCreateWithFlags(&h->lane_ev[NLANE], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    free_lanes(h);
+    return fail_dev(h, e, "worker stream creation");
+  }
+  return HSDM_OK;
+}
+
+// Embedding buffers of lane k for complex sizes up to n.
+hsdm_ctx* lane_cws(hsdm_ctx* h, int k) { return k == 0 ? h : h->lane_buf[k]; }
+int ensure_lane_cws(hsdm_ctx* h, int k, int n) {
+  if (n <= 0) return HSDM_OK;
+  if (k > 0 && !h->lane_buf[k]) h->lane_buf[k] = new hsdm_ctx();
+  hsdm_ctx* b = lane_cws(h, k);
+  const int r = ensure_cws(b, n);
+  if (r && b != h) h->err = b->err;
+  return r;
+}
+
+// The lanes start after the work queued so far on s; s continues after all
+// the work queued on the lanes.
+hipError_t lanes_fork(hsdm_ctx* h, hipStream_t s) {
+  HSDM_TRY(hipEventRecord(h->lane_ev[NLANE], s));
+  for (int k = 0; k < NLANE; k++) HSDM_TRY(hipStreamWaitEvent(h->lane_s[k], h->lane_ev[NLANE], 0));
+  return hipSuccess;
+}
+hipError_t lanes_join(hsdm_ctx* h, hipStream_t s) {
+  for (int k = 0; k < NLANE; k++) {
+    HSDM_TRY(hipEventRecord(h->lane_ev[k], h->lane_s[k]));
+    HSDM_TRY(hipStreamWaitEvent(s, h->lane_ev[k], 0));
+  }
+  return hipSuccess;
 }
 
 void free_ws(hsdm_ctx* h) {
@@ -435,6 +505,7 @@ int hsdm_finalize(hsdm_handle h) {
   (void)hipSetDevice(h->device);
   for (hsdm_ctx* c : h->subs) hsdm_finalize(c);
   h->subs.clear();
+  free_lanes(h);
   if (h->d_tasks) (void)hipFree(h->d_tasks);
   if (h->d_sb) (void)hipFree(h->d_sb);
   if (h->d_qr) (void)hipFree(h->d_qr);
@@ -1044,12 +1115,9 @@ int pick_contexts(hsdm_ctx* h, int nt, const TaskSpec* T, std::vector<hsdm_ctx*>
 int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, double kT,
                 double* eb_total, double* mu_shared, double* eb_each, double* mu_each,
                 hipStream_t s) {
-  int r, nmax_c = 0;
-  for (int p = 0; p < nt; p++)
-    if (T[p].cplx && T[p].n > nmax_c) nmax_c = T[p].n;
+  int r;
   std::vector<hsdm_ctx*> ctx;
   if ((r = pick_contexts(h, nt, T, ctx))) return r;
-  if (nmax_c > 0 && (r = ensure_cws(h, nmax_c))) return r;
   if (h->d_tasks_cap < nt) {
     if (h->d_tasks) (void)hipFree(h->d_tasks);
     h->d_tasks = nullptr;
@@ -1057,43 +1125,111 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
     DEV_TRY(h, hipMalloc(&h->d_tasks, sizeof(OccTask) * nt));
     h->d_tasks_cap = nt;
   }
+  // Tasks that share an S (the same caller buffer, size and leading
+  // dimension, e.g. the spin channels of one k-point) use the factor of the
+  // first of them.  The tasks' independent phases run on the worker streams
+  // when there are several tasks: each group of tasks sharing an S on one
+  // lane, groups placed largest first on the least loaded lane.
+  std::vector<int> src(nt), lane(nt, 0);
+  for (int p = 0; p < nt; p++) {
+    src[p] = p;
+    for (int q = 0; q < p; q++)
+      if (src[q] == q && T[q].S == T[p].S && T[q].n == T[p].n && T[q].lds == T[p].lds &&
+          T[q].cplx == T[p].cplx) {
+        src[p] = q;
+        break;
+      }
+  }
+  const bool use_lanes = nt > 1;
+  std::vector<std::vector<int>> order(use_lanes ? NLANE : 1);  // tasks of each lane, in order
+  if (use_lanes) {
+    if ((r = ensure_lanes(h))) return r;
+    std::vector<int> groups;
+    std::vector<double> work(nt, 0.0);
+    for (int p = 0; p < nt; p++) {
+      const double nr = T[p].cplx ? 2.0 * T[p].n : (double)T[p].n;
+      work[src[p]] += nr * nr * nr;
+      if (src[p] == p) groups.push_back(p);
+    }
+    std::stable_sort(groups.begin(), groups.end(),
+                     [&](int x, int y) { return work[x] > work[y]; });
+    double load[NLANE] = {};
+    for (int g : groups) {
+      const int k = (int)(std::min_element(load, load + NLANE) - load);
+      load[k] += work[g];
+      for (int p = g; p < nt; p++)
+        if (src[p] == g) {
+          lane[p] = k;
+          order[k].push_back(p);
+        }
+    }
+  } else {
+    for (int p = 0; p < nt; p++) order[0].push_back(p);
+  }
+  // issue order: the lanes' task lists interleaved, so that every lane has
+  // work queued early
+  std::vector<int> issue;
+  for (size_t i = 0;; i++) {
+    bool any = false;
+    for (auto& o : order)
+      if (i < o.size()) {
+        issue.push_back(o[i]);
+        any = true;
+      }
+    if (!any) break;
+  }
+  auto stream_of = [&](int p) { return use_lanes ? h->lane_s[lane[p]] : s; };
+  for (size_t k = 0; k < order.size(); k++) {
+    int nk = 0;
+    for (int p : order[k])
+      if (T[p].cplx) nk = std::max(nk, T[p].n);
+    if ((r = ensure_lane_cws(h, (int)k, nk))) return r;
+  }
+  for (int p = 0; p < nt; p++) {
+    hsdm_ctx* c = ctx[p];
+    c->err.clear();
+    if ((r = ensure_ws(c, T[p].cplx ? 2 * T[p].n : T[p].n))) {
+      h->err = c->err;
+      return r;
+    }
+  }
   KtScope kts(h);
   for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
   h->h_tasks.assign(nt, OccTask{});
-  // 1. every task: factor, standard form, full -> band
-  for (int p = 0; p < nt; p++) {
+  if (use_lanes) DEV_TRY(h, lanes_fork(h, s));
+  // 1. every task: factor, standard form
+  for (int p : issue) {
     hsdm_ctx* c = ctx[p];
+    hsdm_ctx* L = lane_cws(h, use_lanes ? lane[p] : 0);
+    const hipStream_t ls = stream_of(p);
     const TaskSpec& t = T[p];
     c->fmax = shared ? h->fmax : t.fmax;
     c->fcut_rel = h->fcut_rel;
     c->deg_tol = h->deg_tol;
     c->timing = false;
     c->ktiming = false;
-    c->err.clear();
     const int nr = t.cplx ? 2 * t.n : t.n;
-    if ((r = ensure_ws(c, nr))) {
-      h->err = c->err;
-      return r;
-    }
     const SKey key{t.S, t.n, t.lds, t.cplx != 0};
+    const bool own = src[p] == p;
     const double *Hr = (const double*)t.H, *Sr = (const double*)t.S;
     int ldhr = t.ldh, ldsr = t.lds;
     if (t.cplx) {
-      if (!s_cached(c, key)) DEV_TRY(h, herm_embed(t.n, t.S, t.lds, h->SR, nr, s));
-      DEV_TRY(h, herm_embed(t.n, t.H, t.ldh, h->HR, nr, s));
-      Hr = h->HR;
-      Sr = h->SR;
+      if (own && !s_cached(c, key)) DEV_TRY(h, herm_embed(t.n, t.S, t.lds, L->SR, nr, ls));
+      DEV_TRY(h, herm_embed(t.n, t.H, t.ldh, L->HR, nr, ls));
+      Hr = L->HR;
+      Sr = L->SR;
       ldhr = ldsr = nr;
     }
-    hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, c->st, c->occ);
+    hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, ls, c->st, c->occ);
     DEV_TRY(h, hipGetLastError());
-    if ((r = factor_s(c, nr, Sr, ldsr, key, s))) return r;
-    if (c->deg_tol < 0.0) DEV_TRY(h, dev_norm1_sym(Hr, ldhr, nr, c->colsum, c->hnorm, s));
-    if ((r = standard_form(c, nr, Hr, ldhr, c->Linv, nr, c->Abuf, nr, s))) return r;
-    DEV_TRY(h, bt1_zero_fill(nr, BAND, c->Vst, nr, s));
+    if (own && (r = factor_s(c, nr, Sr, ldsr, key, ls))) return r;
+    if (c->deg_tol < 0.0) DEV_TRY(h, dev_norm1_sym(Hr, ldhr, nr, c->colsum, c->hnorm, ls));
+    if ((r = standard_form(c, nr, Hr, ldhr, ctx[src[p]]->Linv, nr, c->Abuf, nr, ls))) return r;
+    DEV_TRY(h, bt1_zero_fill(nr, BAND, c->Vst, nr, ls));
     h->h_tasks[p] = OccTask{c->lam, c->fvec, c->occ, c->deg_tol < 0.0 ? c->hnorm : nullptr, nr,
                             t.w};
   }
+  if (use_lanes) DEV_TRY(h, lanes_join(h, s));
   // full -> band of all tasks, pair step by pair step, the panel QRs of a
   // step in shared cooperative launches
   {
@@ -1169,20 +1305,23 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
   }
   // 3. every task: eigenpairs of the tridiagonal (all of them when the
   //    occupations are shared: they are not known yet)
-  for (int p = 0; p < nt; p++) {
+  if (use_lanes) DEV_TRY(h, lanes_fork(h, s));
+  for (int p : issue) {
     hsdm_ctx* c = ctx[p];
+    const hipStream_t ls = stream_of(p);
     const TaskSpec& t = T[p];
     const int nr = t.cplx ? 2 * t.n : t.n;
-    DEV_TRY(h, sb2st_finish(c->lay, c->AB, 2 * BAND, c->dvec, c->evec, s));
+    DEV_TRY(h, sb2st_finish(c->lay, c->AB, 2 * BAND, c->dvec, c->evec, ls));
     if (shared) {
       DEV_TRY(h, stedc_run(c->plan, c->dvec, c->evec, c->lam, c->Zbuf, nr, c->dc_scr,
-                           c->dc_iscr, nullptr, nullptr, nullptr, c->st, s));
+                           c->dc_iscr, nullptr, nullptr, nullptr, c->st, ls));
     } else {
       OccHook hook{c, nr, t.cplx ? 2.0 * t.ne : t.ne, t.kT};
       DEV_TRY(h, stedc_run(c->plan, c->dvec, c->evec, c->lam, c->Zbuf, nr, c->dc_scr,
-                           c->dc_iscr, &c->occ->m, occ_hook, &hook, c->st, s));
+                           c->dc_iscr, &c->occ->m, occ_hook, &hook, c->st, ls));
     }
   }
+  if (use_lanes) DEV_TRY(h, lanes_join(h, s));
   // 4. one chemical potential for all tasks (Eq. (16))
   hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
@@ -1216,28 +1355,32 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
     DEV_TRY(h, bt2_group_apply(nt, h->h_bt2.data(), h->h_bt2map, d_t, d_m, s));
   }
   // 6. every task: the other back-transforms, D and E
-  for (int p = 0; p < nt; p++) {
+  if (use_lanes) DEV_TRY(h, lanes_fork(h, s));
+  for (int p : issue) {
     kt_set_tag(p);
     hsdm_ctx* c = ctx[p];
+    hsdm_ctx* L = lane_cws(h, use_lanes ? lane[p] : 0);
+    const hipStream_t ls = stream_of(p);
     const TaskSpec& t = T[p];
     const int nr = t.cplx ? 2 * t.n : t.n;
     const int* m_dev = &c->occ->m;
-    DEV_TRY(h, bt1_apply(nr, BAND, c->Vst, nr, c->T1, c->Zbuf, nr, nr, m_dev, c->bt1_scr, s));
+    DEV_TRY(h, bt1_apply(nr, BAND, c->Vst, nr, c->T1, c->Zbuf, nr, nr, m_dev, c->bt1_scr, ls));
     GemmArgs g{};
-    g.m = nr; g.n = nr; g.k = nr; g.A = c->Linv; g.lda = nr; g.B = c->Zbuf; g.ldb = nr;
+    g.m = nr; g.n = nr; g.k = nr; g.A = ctx[src[p]]->Linv; g.lda = nr; g.B = c->Zbuf; g.ldb = nr;
     g.C = c->Cbuf; g.ldc = nr; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
     g.flags = GF_KA_UPPER; g.ndev = m_dev;
-    DEV_TRY(h, gemm_launch(g, s));
+    DEV_TRY(h, gemm_launch(g, ls));
     if (t.cplx) {
-      DEV_TRY(h, density_launch(nr, nr, c->Cbuf, nr, c->fvec, c->lam, h->DR, nr,
-                                t.E ? h->ER : nullptr, nr, m_dev, s));
-      DEV_TRY(h, herm_extract(t.n, h->DR, nr, t.D, t.ldd, s));
-      if (t.E) DEV_TRY(h, herm_extract(t.n, h->ER, nr, t.E, t.lde, s));
+      DEV_TRY(h, density_launch(nr, nr, c->Cbuf, nr, c->fvec, c->lam, L->DR, nr,
+                                t.E ? L->ER : nullptr, nr, m_dev, ls));
+      DEV_TRY(h, herm_extract(t.n, L->DR, nr, t.D, t.ldd, ls));
+      if (t.E) DEV_TRY(h, herm_extract(t.n, L->ER, nr, t.E, t.lde, ls));
     } else {
       DEV_TRY(h, density_launch(nr, nr, c->Cbuf, nr, c->fvec, c->lam, (double*)t.D, t.ldd,
-                                (double*)t.E, t.E ? t.lde : nr, m_dev, s));
+                                (double*)t.E, t.E ? t.lde : nr, m_dev, ls));
     }
   }
+  if (use_lanes) DEV_TRY(h, lanes_join(h, s));
   kt_set_tag(-1);
   // status of every task, then of the shared occupations
   h->tag_m.assign(nt, 0);
@@ -1357,6 +1500,8 @@ double hsdm_workspace_bytes(hsdm_handle h) {
   if (!h) return 0.0;
   double b = ctx_bytes(h);
   for (const hsdm_ctx* c : h->subs) b += ctx_bytes(c);
+  for (const hsdm_ctx* c : h->lane_buf)
+    if (c) b += ctx_bytes(c);
   return b;
 }
 
@@ -1368,8 +1513,14 @@ int hsdm_release_tasks(hsdm_handle h, double keep_bytes) {
   auto tasks_bytes = [&]() {
     double b = h->cws ? 16.0 * 8.0 * (double)h->cws_n * h->cws_n : 0.0;
     for (const hsdm_ctx* c : h->subs) b += ctx_bytes(c);
+    for (const hsdm_ctx* c : h->lane_buf)
+      if (c) b += ctx_bytes(c);
     return b;
   };
+  // the worker lanes' embedding buffers first (rebuilt by the next call
+  // that needs them), then task contexts, least recently used first
+  for (int k = NLANE - 1; k > 0 && tasks_bytes() > keep_bytes; k--)
+    if (h->lane_buf[k]) free_cws(h->lane_buf[k]);
   while (!h->subs.empty() && tasks_bytes() > keep_bytes) {
     size_t lru = 0;
     for (size_t i = 1; i < h->subs.size(); i++)

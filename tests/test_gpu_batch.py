@@ -219,3 +219,44 @@ def test_release_task_contexts(oracle, torch_dev, h):
                                 f_max=2.0)
     for D, Dr in zip(r["D"], ref["D"]):
         assert np.max(np.abs(_c(D) - Dr)) <= 1e-9
+
+
+def test_tasks_sharing_one_s_buffer(oracle, torch_dev, h):
+    """Tasks that pass the same device S share one factorization (here the
+    shared buffer is used by tasks 0, 1 and 3, not adjacent); the results
+    match the oracle on the first call and again when the factor is cached."""
+    sizes = [90, 90, 61, 90, 130]
+    probs = [inputs.sized_problem(n, cfg=1700 + i) for i, n in enumerate(sizes)]
+    Hs = [p[0] for p in probs]
+    Sa = probs[0][1]
+    Ss = [Sa, Sa, probs[2][1], Sa, probs[4][1]]
+    Sg_a = _g(torch_dev, Sa)
+    Sg = [Sg_a, Sg_a, _g(torch_dev, Ss[2]), Sg_a, _g(torch_dev, Ss[4])]
+    ne, kT = 0.4 * sum(sizes) * 2.0, 0.01
+    print(f"[batch shared S] sizes={sizes}", flush=True)
+    _set_fmax(h, 2.0)
+    h.hsdm_reinit()
+    ref = oracle.solve_dm_batch(Hs, Ss, ne, kT, f_max=2.0)
+    for _ in range(2):
+        r = h.hsdm_solve_dm_batch([_g(torch_dev, x) for x in Hs], Sg, ne, kT)
+        _check(r, ref, Hs, ne)
+
+
+def test_complex_tasks_sharing_one_s_buffer(oracle, torch_dev, h):
+    """The spin channels of each k-point pass one device S (as a caller
+    would): one factor per k-point, shared by both channels."""
+    sizes = [57, 120, 75]
+    Hs, Ss, Sg = [], [], []
+    for i, n in enumerate(sizes):
+        Hu, Hd, S = inputs.kpoint_problem(26 + i, n=n)
+        g = _g(torch_dev, S)
+        Hs += [Hu, Hd]
+        Ss += [S, S]
+        Sg += [g, g]
+    ne, kT = 0.4 * sum(sizes), 0.0
+    print(f"[batch complex shared S] sizes={sizes}", flush=True)
+    _set_fmax(h, 1.0)
+    h.hsdm_reinit()
+    r = h.hsdm_solve_dm_batch([_g(torch_dev, x) for x in Hs], Sg, ne, kT)
+    ref = oracle.solve_dm_batch(Hs, Ss, ne, kT, f_max=1.0)
+    _check(r, ref, Hs, ne)
