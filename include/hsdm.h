@@ -54,9 +54,11 @@ enum hsdm_key {
   HSDM_KEY_FCUT = 2,       /* real: states with f <= fcut * fmax get no eigenvector (f is below it); default 1e-16 */
   HSDM_KEY_DEG_TOL = 3,    /* real: kT = 0 degeneracy window; < 0 selects 1e-12 * ||H||_1 (default) */
   HSDM_KEY_TIMING = 4      /* int: 1 records per-phase times (hsdm_phase_times); 2 also times every
-                              launch of the main kernels of a solve (hsdm_kernel_stat); 3 times only
-                              the kernels launched once per solve (no event overhead on the many
-                              small launches); 0 off (default) */
+                              launch of the main kernels of a solve (hsdm_kernel_stat; multi-task
+                              solves then keep every launch on the caller's stream, so that no
+                              launch's time includes another's); 3 times only the kernels
+                              launched once per solve (no event overhead on the many small
+                              launches); 0 off (default) */
 };
 
 /* Create a handle bound to HIP device `device` (~ elsi_init, Sec. 2.1). */

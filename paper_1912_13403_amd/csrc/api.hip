@@ -66,6 +66,7 @@ struct hsdm_ctx {
   double deg_tol = -1.0;
   bool timing = false;
   bool ktiming = false;
+  bool kt_every = false;  // every launch timed: no worker streams
   KTimer* kt = nullptr;
   std::string err;
   int detail = 0;
@@ -554,6 +555,7 @@ int hsdm_set_int(hsdm_handle h, int key, long v) {
     if (v < 0 || v > 3) return -3;
     h->timing = (v != 0);
     h->ktiming = (v >= 2);
+    h->kt_every = (v == 2);
     kt_set_whole_only(h->kt, v == 3);
     return HSDM_OK;
   }
@@ -1128,8 +1130,9 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
   // Tasks that share an S (the same caller buffer, size and leading
   // dimension, e.g. the spin channels of one k-point) use the factor of the
   // first of them.  The tasks' independent phases run on the worker streams
-  // when there are several tasks: each group of tasks sharing an S on one
-  // lane, groups placed largest first on the least loaded lane.
+  // when there are several tasks (and not every launch is timed): each group
+  // of tasks sharing an S on one lane, groups placed largest first on the
+  // least loaded lane.
   std::vector<int> src(nt), lane(nt, 0);
   for (int p = 0; p < nt; p++) {
     src[p] = p;
@@ -1140,7 +1143,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
         break;
       }
   }
-  const bool use_lanes = nt > 1;
+  const bool use_lanes = nt > 1 && !h->kt_every;
   std::vector<std::vector<int>> order(use_lanes ? NLANE : 1);  // tasks of each lane, in order
   if (use_lanes) {
     if ((r = ensure_lanes(h))) return r;
@@ -1255,18 +1258,25 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
     }
   }
   // 2. bulge chasing of all bands, as many per cooperative launch as fit:
-  //    each band alone is latency-bound and fills a small part of the device
+  //    each band alone is latency-bound and fills a small part of the device.
+  //    A launch lasts as long as its largest band, so the bands go into the
+  //    launches largest first.
   {
     h->h_sb.assign(nt, Sb2stTask{});
     h->h_wgmap.clear();
-    std::vector<int> first(1, 0);  // first task of each launch
+    std::vector<int> by_size(nt);
+    for (int p = 0; p < nt; p++) by_size[p] = p;
+    std::stable_sort(by_size.begin(), by_size.end(),
+                     [&](int x, int y) { return ctx[x]->lay.n > ctx[y]->lay.n; });
+    std::vector<int> first(1, 0);  // first entry of by_size in each launch
     std::vector<double> fl(1, 0.0), by(1, 0.0);
     int in_launch = 0;
-    for (int p = 0; p < nt; p++) {
+    for (int i = 0; i < nt; i++) {
+      const int p = by_size[i];
       hsdm_ctx* c = ctx[p];
       const int w = sb2st_group_nwg(c->lay);
       if (w > 0 && in_launch + w > SB2ST_MAX_WG) {
-        first.push_back(p);
+        first.push_back(i);
         fl.push_back(0.0);
         by.push_back(0.0);
         in_launch = 0;
@@ -1298,7 +1308,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
     int off = 0;
     for (size_t g = 0; g + 1 < first.size(); g++) {
       int cnt = 0;
-      for (int p = first[g]; p < first[g + 1]; p++) cnt += h->h_sb[p].nwg;
+      for (int i = first[g]; i < first[g + 1]; i++) cnt += h->h_sb[by_size[i]].nwg;
       DEV_TRY(h, sb2st_group_launch(d_sb, d_map + off, cnt, fl[g], by[g], s));
       off += cnt;
     }

@@ -310,16 +310,16 @@ __global__ __launch_bounds__(64 * PW) __attribute__((amdgpu_waves_per_eu(2))) vo
   bt2_strip_body(n, nblk, R, nstrip, F2, goff, Z, ldz, m, done, st, blockIdx.x);
 }
 
-// Several Z's in one launch: workgroups b0 .. b0 + nstrip * NSPLIT - 1 of the
-// grid are the workgroups of task blk_task[blockIdx.x], in that task's own
-// order, so a range still waits only for a workgroup with a lower index.
+// Several Z's in one launch: workgroup blockIdx.x is workgroup
+// blk_task[2 blockIdx.x + 1] of task blk_task[2 blockIdx.x] (the host orders
+// them so that a range still waits only for a workgroup with a lower index).
 __global__ __launch_bounds__(64 * PW) __attribute__((amdgpu_waves_per_eu(2))) void bt2_group_kernel(
     const Bt2Task* tasks, const int* blk_task) {
-  const int p = __builtin_amdgcn_readfirstlane(blk_task[blockIdx.x]);
+  const int p = __builtin_amdgcn_readfirstlane(blk_task[2 * blockIdx.x]);
+  const int blk = __builtin_amdgcn_readfirstlane(blk_task[2 * blockIdx.x + 1]);
   const Bt2Task& q = tasks[p];
   const int m = q.m_dev ? *q.m_dev : q.m;
-  bt2_strip_body(q.n, q.nblk, q.R, q.nstrip, q.F2, q.goff, q.Z, q.ldz, m, q.done, q.st,
-                 (int)blockIdx.x - q.b0);
+  bt2_strip_body(q.n, q.nblk, q.R, q.nstrip, q.F2, q.goff, q.Z, q.ldz, m, q.done, q.st, blk);
 }
 
 }  // namespace
@@ -388,18 +388,22 @@ hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff,
 size_t bt2_group_map_ints(int nt, const Bt2Task* tasks) {
   size_t c = 0;
   for (int i = 0; i < nt; i++) c += (size_t)tasks[i].nstrip * NSPLIT;
-  return c;
+  return 2 * c;
 }
 
+// Workgroup order of the grouped launch: range by range, and within a range
+// task by task, strip by strip, so that a workgroup's predecessor (the
+// previous range of its strip) has a lower index and the workgroups resident
+// at any time are mostly of one range, not waiting.  The map holds (task,
+// workgroup within the task) per workgroup.
 hipError_t bt2_group_apply(int nt, Bt2Task* tasks, std::vector<int>& hmap, Bt2Task* d_tasks,
                            int* d_map, hipStream_t s) {
   hmap.clear();
-  int b0 = 0;
+  int b0 = 0;  // workgroups of the launch
   for (int i = 0; i < nt; i++) {
     Bt2Task& q = tasks[i];
     q.b0 = b0;
     const int cnt = (q.nblk > 0 && q.m > 0) ? q.nstrip * NSPLIT : 0;
-    for (int k = 0; k < cnt; k++) hmap.push_back(i);
     b0 += cnt;
     if (cnt > 0) {
       hipLaunchKernelGGL(fill_i32_kernel, dim3(ceil_div(q.nstrip, 256)), dim3(256), 0, s, q.done,
@@ -407,6 +411,15 @@ hipError_t bt2_group_apply(int nt, Bt2Task* tasks, std::vector<int>& hmap, Bt2Ta
       HSDM_TRY(hipGetLastError());
     }
   }
+  for (int k = 0; k < NSPLIT; k++)
+    for (int i = 0; i < nt; i++) {
+      const Bt2Task& q = tasks[i];
+      if (q.nblk <= 0 || q.m <= 0) continue;
+      for (int strip = 0; strip < q.nstrip; strip++) {
+        hmap.push_back(i);
+        hmap.push_back(k * q.nstrip + strip);
+      }
+    }
   if (b0 == 0) return hipSuccess;
   HSDM_TRY(hipMemcpyAsync(d_tasks, tasks, sizeof(Bt2Task) * nt, hipMemcpyHostToDevice, s));
   HSDM_TRY(hipMemcpyAsync(d_map, hmap.data(), sizeof(int) * hmap.size(), hipMemcpyHostToDevice,

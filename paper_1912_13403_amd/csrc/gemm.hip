@@ -432,6 +432,25 @@ __global__ __launch_bounds__(256) void gemm_group_kernel(const GemmGroupItem* it
   }
 }
 
+// Symmetric rank-k updates of several tasks in one launch: the lower tiles
+// (tm >= tn, row by row) of each item's square C in 128 x 128 tiles, only
+// elements on or below the diagonal written (GF_C_LOWER_ONLY).
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void syr2k_group_kernel(
+    const GemmGroupItem* items, const int* wg_item) {
+  using C = G<128, 128, 2, 4, 0, 1, AM_DENSE>;
+  __shared__ double smem[C::SMEM];
+  const int q = __builtin_amdgcn_readfirstlane(wg_item[blockIdx.x]);
+  const GemmGroupItem& it = items[q];
+  const int local = (int)blockIdx.x - it.b0;
+  int tm = (int)((sqrt(8.0 * local + 1.0) - 1.0) * 0.5);
+  while ((tm + 1) * (tm + 2) / 2 <= local) tm++;
+  while (tm * (tm + 1) / 2 > local) tm--;
+  const int tn = local - tm * (tm + 1) / 2;
+  Prob p{it.m, it.n, it.k, it.A, it.lda, it.B, it.ldb, it.C, it.ldc, nullptr, nullptr, nullptr};
+  gemm_tile<128, 128, 2, 4, 0, 1, AM_DENSE>(p, it.alpha, it.beta, it.flags, tm, tn, smem, 0,
+                                            1 << 30);
+}
+
 // C = sum of the item's split partials + beta C, item blockIdx.y (split items only)
 __global__ void splitk_reduce_group_kernel(const GemmGroupItem* items) {
   const GemmGroupItem& it = items[blockIdx.y];
@@ -627,6 +646,14 @@ hipError_t gemm_batched_dense_launch(const GemmDesc* d_desc, int count, int max_
   return hipGetLastError();
 }
 
+int gemm_group_kind(const GemmArgs& g) {
+  if (g.flags & GF_A_TRIL) return GG_TRIL;
+  if (g.flags & GF_A_SLT) return GG_SLT;
+  if ((g.flags & GF_C_LOWER_TILES) && g.m == g.n && g.ta == 0 && g.tb == 1) return GG_SYR2K;
+  if (g.ta) return GG_TN;
+  return g.tb ? GG_NT : GG_NN;
+}
+
 size_t gemm_group_item(const GemmArgs& g, int kchunk, double* part, GemmGroupItem& it,
                        double* flops) {
   it = GemmGroupItem{};
@@ -637,6 +664,13 @@ size_t gemm_group_item(const GemmArgs& g, int kchunk, double* part, GemmGroupIte
   it.alpha = g.alpha;
   it.beta = g.beta;
   it.flags = g.flags;
+  if (gemm_group_kind(g) == GG_SYR2K) {
+    const int t = ceil_div(g.m, 128);
+    it.tiles = t * (t + 1) / 2;
+    it.kchunk = 0;
+    it.nsplit = 1;
+    return (size_t)it.tiles;
+  }
   it.tiles = ceil_div(g.m, 128);
   it.kchunk = kchunk > 0 ? kchunk : 0;
   it.nsplit = kchunk > 0 ? ceil_div(g.k, kchunk) : 1;
@@ -671,6 +705,10 @@ hipError_t gemm_group_launch(int kind, const GemmGroupItem* d_items, int count, 
       kt_begin("gemm_group_kernel<0, 1, 0>", flops, 0.0, 0, s);
       hipLaunchKernelGGL((gemm_group_kernel<0, 1, AM_DENSE>), dim3(total_wg), dim3(256), 0, s,
                          d_items, d_map);
+      break;
+    case GG_SYR2K:
+      kt_begin("syr2k_group_kernel", flops, 0.0, 0, s);
+      hipLaunchKernelGGL(syr2k_group_kernel, dim3(total_wg), dim3(512), 0, s, d_items, d_map);
       break;
     default: return hipErrorInvalidValue;
   }

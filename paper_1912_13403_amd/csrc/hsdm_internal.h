@@ -60,10 +60,13 @@ hipError_t gemm_batched_launch(const GemmDesc* d_desc, int count, int max_m, int
 // The same for plain operands (no gathered columns; acol and ccol unused).
 hipError_t gemm_batched_dense_launch(const GemmDesc* d_desc, int count, int max_m, int max_n,
                                      double alpha, double beta, int flags, hipStream_t s);
-// Tall-skinny products (n <= 32) of several tasks in one launch, all with the
-// 128 x 32 tiles.  kind: GG_TRIL (op(A) = tril(A), as GF_A_TRIL), GG_SLT
-// (op(A) = strict_tril(A)^T, as GF_A_SLT), GG_NN, GG_TN (A transposed),
-// GG_NT (B transposed).  An item with kchunk > 0 is split over K: its nsplit
+// Products of several tasks in one launch.  Tall-skinny ones (n <= 32), all
+// with the 128 x 32 tiles, of kind GG_TRIL (op(A) = tril(A), as GF_A_TRIL),
+// GG_SLT (op(A) = strict_tril(A)^T, as GF_A_SLT), GG_NN, GG_TN (A
+// transposed), GG_NT (B transposed); and GG_SYR2K, the lower tiles of a
+// square C = alpha A B^T + beta C (GF_C_LOWER_TILES, m = n) in 128 x 128
+// tiles, every item in place.  gemm_group_kind tells the kind of a product.
+// A tall-skinny item with kchunk > 0 is split over K: its nsplit
 // partials (m x n each) go to its part buffer and are reduced into
 // C = sum + beta C when `split`; kchunk = 0 computes C = alpha op(A) op(B) +
 // beta C in place.  gemm_group_item fills an item from the product's
@@ -71,7 +74,7 @@ hipError_t gemm_batched_dense_launch(const GemmDesc* d_desc, int count, int max_
 // *flops (if given) and returns its workgroup count; the caller sets b0 (the
 // item's first workgroup) and writes the workgroup -> item map.  d_items and
 // d_map are device arrays.
-enum { GG_TRIL = 0, GG_SLT = 1, GG_NN = 2, GG_TN = 3, GG_NT = 4 };
+enum { GG_TRIL = 0, GG_SLT = 1, GG_NN = 2, GG_TN = 3, GG_NT = 4, GG_SYR2K = 5 };
 struct GemmGroupItem {
   const double* A;
   const double* B;
@@ -81,6 +84,7 @@ struct GemmGroupItem {
   double alpha, beta;
   int m, n, k, flags, kchunk, nsplit, tiles, b0;
 };
+int gemm_group_kind(const GemmArgs& g);
 size_t gemm_group_item(const GemmArgs& g, int kchunk, double* part, GemmGroupItem& it,
                        double* flops);
 hipError_t gemm_group_launch(int kind, const GemmGroupItem* d_items, int count, const int* d_map,

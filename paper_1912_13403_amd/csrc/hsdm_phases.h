@@ -124,7 +124,8 @@ hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff,
 // bt2_apply's arguments (m: host bound of the device count); bt2_group_apply
 // clears every task's counters and launches all their strips together.
 // tasks and hmap are the caller's host arrays (kept until the stream has run
-// the work); d_tasks holds nt descriptors, d_map bt2_group_map_ints ints.
+// the work); d_tasks holds nt descriptors, d_map bt2_group_map_ints ints
+// (two per workgroup).
 constexpr int NSPLIT = 4;
 struct SplitRanges {
   int hi[NSPLIT];  // range k covers sweep blocks lo[k] .. hi[k] (hi[k] = lo[k-1] - 1)
@@ -139,7 +140,7 @@ struct Bt2Task {
   const int* m_dev;
   int* done;
   DevStatusWord* st;
-  int n, nblk, nstrip, m, b0, pad;
+  int n, nblk, nstrip, m, b0, pad;  // b0: first workgroup of the task's share (informative)
 };
 Bt2Task bt2_task(const Sb2stLayout& L, const double* F2, const long* d_goff, double* Z,
                  long ldz, int m, const int* m_dev, int* iscratch, DevStatusWord* st);

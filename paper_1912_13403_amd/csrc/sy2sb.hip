@@ -589,12 +589,15 @@ struct Sy2sb {
     return hipSuccess;
   }
   // A[r:, r:] -= VWr WVr^T (lower), k columns
-  hipError_t syr2k(int r, int h, const double* VWr, const double* WVr, int k) {
+  GemmArgs syr2k_args(int r, int h, const double* VWr, const double* WVr, int k) const {
     GemmArgs g{};
     g.m = h; g.n = h; g.k = k; g.A = VWr; g.lda = n; g.B = WVr; g.ldb = n;
     g.C = A + r + (long)r * lda; g.ldc = lda; g.alpha = -1.0; g.beta = 1.0; g.ta = 0; g.tb = 1;
     g.flags = GF_C_LOWER_TILES | GF_C_LOWER_ONLY;
-    return gemm_launch(g, s);
+    return g;
+  }
+  hipError_t syr2k(int r, int h, const double* VWr, const double* WVr, int k) {
+    return gemm_launch(syr2k_args(r, h, VWr, WVr, k), s);
   }
   // columns of panel p+1: A[r0:, r0:r0+B] -= [V1 W1] [W1 V1][0:B]^T (lower part)
   GemmArgs col_args(int r0, int h) const {
@@ -717,24 +720,17 @@ struct CopyLaunch {
 };
 // One round: the first panels' QRs and their W (Y = V T, the two passes of
 // X = A22 Y, M = Y^T X, W = X - V M / 2), the copies into the update
-// operands, the column update of the pairs' second panels (the single
-// panels' trailing updates run per task), then the same for the second
-// panels with the first panel's delayed update (Qc = [W1 V1]^T Y,
-// X -= [V1 W1] Qc) before M.
+// operands, the trailing updates of the single panels and the column update
+// of the pairs' second panels, then the same for the second panels with the
+// first panel's delayed update (Qc = [W1 V1]^T Y, X -= [V1 W1] Qc) before M,
+// and the pairs' trailing updates.
 struct Round {
   std::vector<std::pair<int, int>> tasks;
   std::vector<QrLaunch> qr1, qr2;
-  GemmLaunch pre1, tril1, slt1, fix1, col1, pre2, tril2, slt2, corr1, corr2, fix2;
+  GemmLaunch pre1, tril1, slt1, fix1, col1, syr1, pre2, tril2, slt2, corr1, corr2, fix2, syr2;
   AtbLaunch atb1, atb2;
   CopyLaunch cp1, cp2;
 };
-
-int gemm_kind(const GemmArgs& g) {
-  if (g.flags & GF_A_TRIL) return GG_TRIL;
-  if (g.flags & GF_A_SLT) return GG_SLT;
-  if (g.ta) return GG_TN;
-  return g.tb ? GG_NT : GG_NN;
-}
 
 struct Builder {
   Sy2sbGroupHost& host;
@@ -761,7 +757,7 @@ struct Builder {
       double f = 0.0;
       const GemmArgs& g = std::get<0>(e);
       if (g.m <= 0 || g.n <= 0) continue;
-      L.kind = gemm_kind(g);
+      L.kind = gemm_group_kind(g);
       const int w = (int)gemm_group_item(g, std::get<1>(e), std::get<2>(e), it, &f);
       it.b0 = L.nwg;
       for (int q = 0; q < w; q++) host.gemmmap.push_back(L.nd);
@@ -814,7 +810,7 @@ void build_schedule(const std::vector<Sy2sb>& R, Sy2sbGroupHost& host, std::vect
     Round& rd = S[k];
     rd.tasks = rounds[k];
     std::vector<PanelQrTask> q1, q2;
-    GL pre1, tril1, slt1, fix1, col1, pre2, tril2, slt2, corr1, corr2, fix2;
+    GL pre1, tril1, slt1, fix1, col1, syr1, pre2, tril2, slt2, corr1, corr2, fix2, syr2;
     std::vector<AtbGroupItem> atb1, atb2;
     std::vector<CopyGroupItem> cp1, cp2;
     for (auto& e : rd.tasks) {
@@ -833,7 +829,10 @@ void build_schedule(const std::vector<Sy2sb>& R, Sy2sbGroupHost& host, std::vect
         CopyGroupItem c[3];
         T.copies(h, T.first_v(p), T.first_w(), 0, c);
         cp1.insert(cp1.end(), c, c + 3);
-        if (T.advance(p) == 2) col1.emplace_back(T.col_args(r0, h), 0, nullptr);
+        if (T.advance(p) == 2)
+          col1.emplace_back(T.col_args(r0, h), 0, nullptr);
+        else
+          syr1.emplace_back(T.syr2k_args(r0, h, T.VW, T.WV, 2 * T.B), 0, nullptr);
       }
       if (T.advance(p) == 2) {
         const int r1 = (p + 2) * T.B, h2 = T.n - r1;
@@ -850,6 +849,7 @@ void build_schedule(const std::vector<Sy2sb>& R, Sy2sbGroupHost& host, std::vect
         CopyGroupItem c[3];
         T.copies(h2, T.second_v(p), T.second_w(), Sy2sb::second_off(T.n, T.B), c);
         cp2.insert(cp2.end(), c, c + 3);
+        syr2.emplace_back(T.syr2k_args(r1, h2, T.VW + T.B, T.WV + T.B, 4 * T.B), 0, nullptr);
       }
     }
     bld.qr(q1, rd.qr1);
@@ -860,6 +860,7 @@ void build_schedule(const std::vector<Sy2sb>& R, Sy2sbGroupHost& host, std::vect
     rd.fix1 = bld.gemm(fix1);
     rd.cp1 = bld.copy(cp1);
     rd.col1 = bld.gemm(col1);
+    rd.syr1 = bld.gemm(syr1);
     bld.qr(q2, rd.qr2);
     rd.pre2 = bld.gemm(pre2);
     rd.tril2 = bld.gemm(tril2);
@@ -869,6 +870,7 @@ void build_schedule(const std::vector<Sy2sb>& R, Sy2sbGroupHost& host, std::vect
     rd.atb2 = bld.atb(atb2);
     rd.fix2 = bld.gemm(fix2);
     rd.cp2 = bld.copy(cp2);
+    rd.syr2 = bld.gemm(syr2);
   }
 }
 
@@ -991,11 +993,7 @@ hipError_t sy2sb_run_group(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& ho
     HSDM_TRY(launch_atb(rd.atb1, D, s));
     HSDM_TRY(launch_gemm(rd.fix1, D, s));
     HSDM_TRY(launch_copy(rd.cp1, D, s));
-    for (auto& e : rd.tasks) {
-      Sy2sb& T = R[e.first];
-      const int p = e.second, r0 = (p + 1) * B;
-      if (T.first_has_w(p) && T.advance(p) == 1) HSDM_TRY(T.syr2k(r0, T.n - r0, T.VW, T.WV, 2 * B));
-    }
+    HSDM_TRY(launch_gemm(rd.syr1, D, s));
     HSDM_TRY(launch_gemm(rd.col1, D, s));
     for (const QrLaunch& L : rd.qr2) HSDM_TRY(launch_qr_group(L, D, qr_flops(L), s));
     HSDM_TRY(launch_gemm(rd.pre2, D, s));
@@ -1006,11 +1004,7 @@ hipError_t sy2sb_run_group(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& ho
     HSDM_TRY(launch_atb(rd.atb2, D, s));
     HSDM_TRY(launch_gemm(rd.fix2, D, s));
     HSDM_TRY(launch_copy(rd.cp2, D, s));
-    for (auto& e : rd.tasks) {
-      Sy2sb& T = R[e.first];
-      const int p = e.second, r1 = (p + 2) * B;
-      if (T.advance(p) == 2) HSDM_TRY(T.syr2k(r1, T.n - r1, T.VW + B, T.WV + B, 4 * B));
-    }
+    HSDM_TRY(launch_gemm(rd.syr2, D, s));
   }
   for (auto& r : R) HSDM_TRY(r.finish());
   return hipSuccess;
