@@ -12,6 +12,16 @@
       counter reads for the plain 2 GiB device copy that run starts with,
       divided by the bytes that copy moves.  bench.py divides a kernel's
       counters by these factors to get its HBM bytes per launch.
+
+  python -m paper_1912_13403_amd.profiling timeline DIR [GAP_MS]
+      phases of every multi-task solve in a kernel trace (one solve per
+      bt2_group_kernel launch; solves are told apart by idle gaps of the
+      device longer than GAP_MS, default 2): wall time, device-busy time and
+      the largest kernels from the start of the solve to its first grouped
+      panel QR (factor and standard form), to the first bulge-chasing launch
+      (full -> band), to the last one's end (bulge chasing), to the grouped
+      stage-2 back-transform (tridiagonal eigensolver, occupations), its
+      duration, and to the end (stage-1 back-transform, L^-T, density).
 """
 from __future__ import annotations
 
@@ -108,12 +118,79 @@ def traffic(fetch_dir, write_dir, out_path, workload="cfg2_n16384"):
     return res
 
 
+def _busy(iv):
+    tot, cs, ce = 0, None, None
+    for a, b in sorted(iv):
+        if cs is None or a > ce:
+            if cs is not None:
+                tot += ce - cs
+            cs, ce = a, b
+        else:
+            ce = max(ce, b)
+    return tot + (ce - cs if cs is not None else 0)
+
+
+def timeline(d, gap_ms=2.0, top=6):
+    path = _find(d, "*kernel_trace.csv")
+    rows = []
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            rows.append((int(row["Start_Timestamp"]), int(row["End_Timestamp"]),
+                         _short(row.get("Kernel_Name", ""))))
+    rows.sort()
+    # segments separated by idle gaps; a solve is a run of segments ending
+    # with the one that holds its bt2_group_kernel
+    solves, cur, end = [], [], None
+    for r in rows:
+        if cur and r[0] - end > gap_ms * 1e6 and any(x[2] == "bt2_group_kernel" for x in cur):
+            solves.append(cur)
+            cur = []
+        cur.append(r)
+        end = r[1] if end is None else max(end, r[1])
+    if any(x[2] == "bt2_group_kernel" for x in cur):
+        solves.append(cur)
+    out = []
+    for k, sv in enumerate(solves):
+        # the solve starts at its first kernel after the previous solve's torch
+        # work (input copies and the like carry no library kernel names)
+        sv = [r for r in sv if not r[2].startswith(("at::", "__amd_rocclr"))]
+        first = lambda nm: next(r[0] for r in sv if r[2].startswith(nm))
+        lastend = lambda nm: max(r[1] for r in sv if r[2].startswith(nm))
+        t0, t1 = sv[0][0], max(r[1] for r in sv)
+        marks = [("start", t0), ("panel QR group", first("panel_qr_group_kernel")),
+                 ("bulge chasing", first("sb2st_group_kernel")),
+                 ("chasing end", lastend("sb2st_group_kernel")),
+                 ("stage-2 back-transform", first("bt2_group_kernel")),
+                 ("its end", lastend("bt2_group_kernel")), ("end", t1)]
+        phases = []
+        for (n0, x0), (n1, x1) in zip(marks, marks[1:]):
+            ks = [r for r in sv if x0 <= r[0] < x1]
+            agg = {}
+            for r in ks:
+                agg[r[2]] = agg.get(r[2], 0.0) + (r[1] - r[0]) * 1e-6
+            phases.append((n0, n1, (x1 - x0) * 1e-6, _busy([(r[0], r[1]) for r in ks]) * 1e-6,
+                           len(ks), sorted(agg.items(), key=lambda kv: -kv[1])[:top]))
+        out.append(((t1 - t0) * 1e-6, phases))
+    return out
+
+
+def print_timeline(d, gap_ms=2.0):
+    for k, (wall, phases) in enumerate(timeline(d, gap_ms)):
+        print(f"solve {k}: {wall:.1f} ms")
+        for n0, n1, w, b, nk, top in phases:
+            print(f"  {n0:>22} -> {n1:<22} {w:8.1f} ms  busy {b:8.1f} ms  {nk:6d} launches")
+            for name, ms in top:
+                print(f"  {'':>22}    {ms:8.1f} ms  {name}")
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 3 and sys.argv[1] == "stats":
         print_stats(sys.argv[2])
     elif len(sys.argv) >= 5 and sys.argv[1] == "traffic":
         r = traffic(sys.argv[2], sys.argv[3], sys.argv[4])
         print(json.dumps({k: r[k] for k in r if k != "kernels"}))
+    elif len(sys.argv) >= 3 and sys.argv[1] == "timeline":
+        print_timeline(sys.argv[2], float(sys.argv[3]) if len(sys.argv) >= 4 else 2.0)
     else:
         print(__doc__)
         sys.exit(2)
