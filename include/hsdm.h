@@ -59,6 +59,9 @@ enum hsdm_key {
                               launch's time includes another's); 3 times only the kernels
                               launched once per solve (no event overhead on the many small
                               launches); 0 off (default) */
+  , HSDM_KEY_STREAMS = 5   /* int: worker streams of the multi-task solves, 1 ... 8 (default 4);
+                              they run side by side only as far as the HIP runtime gives the
+                              process hardware queues (GPU_MAX_HW_QUEUES) */
 };
 
 /* Create a handle bound to HIP device `device` (~ elsi_init, Sec. 2.1). */

@@ -19,7 +19,7 @@ namespace {
 
 constexpr int BAND = 32;
 constexpr int NPHASE = 9;
-constexpr int NLANE = 4;  // worker streams of the multi-task solves
+constexpr int NLANE = 8;  // worker streams of the multi-task solves (at most)
 const char* kPhaseNames[NPHASE] = {"cholesky_inverse", "standard_form", "full_to_band",
                                    "band_to_tridiagonal", "divide_conquer", "backtransform_stage2",
                                    "backtransform_stage1", "backtransform_cholesky", "density"};
@@ -67,6 +67,7 @@ struct hsdm_ctx {
   bool timing = false;
   bool ktiming = false;
   bool kt_every = false;  // every launch timed: no worker streams
+  int nlane = 4;          // worker streams used by multi-task solves
   KTimer* kt = nullptr;
   std::string err;
   int detail = 0;
@@ -221,18 +222,43 @@ int ensure_lane_cws(hsdm_ctx* h, int k, int n) {
 
 // The lanes start after the work queued so far on s; s continues after all
 // the work queued on the lanes.
-hipError_t lanes_fork(hsdm_ctx* h, hipStream_t s) {
+hipError_t lanes_fork(hsdm_ctx* h, hipStream_t s, int nl) {
   HSDM_TRY(hipEventRecord(h->lane_ev[NLANE], s));
-  for (int k = 0; k < NLANE; k++) HSDM_TRY(hipStreamWaitEvent(h->lane_s[k], h->lane_ev[NLANE], 0));
+  for (int k = 0; k < nl; k++) HSDM_TRY(hipStreamWaitEvent(h->lane_s[k], h->lane_ev[NLANE], 0));
   return hipSuccess;
 }
-hipError_t lanes_join(hsdm_ctx* h, hipStream_t s) {
-  for (int k = 0; k < NLANE; k++) {
+hipError_t lanes_join(hsdm_ctx* h, hipStream_t s, int nl) {
+  for (int k = 0; k < nl; k++) {
     HSDM_TRY(hipEventRecord(h->lane_ev[k], h->lane_s[k]));
     HSDM_TRY(hipStreamWaitEvent(s, h->lane_ev[k], 0));
   }
   return hipSuccess;
 }
+
+// Forks the first nl lanes off s (nl = 0: none) and joins them back; a
+// return between fork and join (an error) still waits for the lanes' work
+// before the call returns.
+struct Lanes {
+  hsdm_ctx* h;
+  hipStream_t s;
+  int nl;
+  bool forked = false;
+  hipError_t fork() {
+    if (nl == 0) return hipSuccess;
+    forked = true;
+    return lanes_fork(h, s, nl);
+  }
+  hipError_t join() {
+    if (!forked) return hipSuccess;
+    forked = false;
+    return lanes_join(h, s, nl);
+  }
+  ~Lanes() {
+    if (!forked) return;
+    for (int k = 0; k < nl; k++) (void)hipStreamSynchronize(h->lane_s[k]);
+    (void)hipStreamSynchronize(s);
+  }
+};
 
 void free_ws(hsdm_ctx* h) {
   if (h->ws) (void)hipFree(h->ws);
@@ -557,6 +583,11 @@ int hsdm_set_int(hsdm_handle h, int key, long v) {
     h->ktiming = (v >= 2);
     h->kt_every = (v == 2);
     kt_set_whole_only(h->kt, v == 3);
+    return HSDM_OK;
+  }
+  if (key == HSDM_KEY_STREAMS) {
+    if (v < 1 || v > NLANE) return -3;
+    h->nlane = (int)v;
     return HSDM_OK;
   }
   return -2;
@@ -1144,7 +1175,8 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
       }
   }
   const bool use_lanes = nt > 1 && !h->kt_every;
-  std::vector<std::vector<int>> order(use_lanes ? NLANE : 1);  // tasks of each lane, in order
+  const int nl = use_lanes ? h->nlane : 0;
+  std::vector<std::vector<int>> order(use_lanes ? nl : 1);  // tasks of each lane, in order
   if (use_lanes) {
     if ((r = ensure_lanes(h))) return r;
     std::vector<int> groups;
@@ -1158,7 +1190,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
                      [&](int x, int y) { return work[x] > work[y]; });
     double load[NLANE] = {};
     for (int g : groups) {
-      const int k = (int)(std::min_element(load, load + NLANE) - load);
+      const int k = (int)(std::min_element(load, load + nl) - load);
       load[k] += work[g];
       for (int p = g; p < nt; p++)
         if (src[p] == g) {
@@ -1197,9 +1229,10 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
     }
   }
   KtScope kts(h);
+  Lanes lanes{h, s, nl};
   for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
   h->h_tasks.assign(nt, OccTask{});
-  if (use_lanes) DEV_TRY(h, lanes_fork(h, s));
+  DEV_TRY(h, lanes.fork());
   // 1. every task: factor, standard form
   for (int p : issue) {
     hsdm_ctx* c = ctx[p];
@@ -1232,7 +1265,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
     h->h_tasks[p] = OccTask{c->lam, c->fvec, c->occ, c->deg_tol < 0.0 ? c->hnorm : nullptr, nr,
                             t.w};
   }
-  if (use_lanes) DEV_TRY(h, lanes_join(h, s));
+  DEV_TRY(h, lanes.join());
   // full -> band of all tasks, pair step by pair step, the panel QRs of a
   // step in shared cooperative launches
   {
@@ -1315,7 +1348,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
   }
   // 3. every task: eigenpairs of the tridiagonal (all of them when the
   //    occupations are shared: they are not known yet)
-  if (use_lanes) DEV_TRY(h, lanes_fork(h, s));
+  DEV_TRY(h, lanes.fork());
   for (int p : issue) {
     hsdm_ctx* c = ctx[p];
     const hipStream_t ls = stream_of(p);
@@ -1331,7 +1364,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
                            c->dc_iscr, &c->occ->m, occ_hook, &hook, c->st, ls));
     }
   }
-  if (use_lanes) DEV_TRY(h, lanes_join(h, s));
+  DEV_TRY(h, lanes.join());
   // 4. one chemical potential for all tasks (Eq. (16))
   hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
@@ -1365,7 +1398,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
     DEV_TRY(h, bt2_group_apply(nt, h->h_bt2.data(), h->h_bt2map, d_t, d_m, s));
   }
   // 6. every task: the other back-transforms, D and E
-  if (use_lanes) DEV_TRY(h, lanes_fork(h, s));
+  DEV_TRY(h, lanes.fork());
   for (int p : issue) {
     kt_set_tag(p);
     hsdm_ctx* c = ctx[p];
@@ -1390,7 +1423,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
                                 (double*)t.E, t.E ? t.lde : nr, m_dev, ls));
     }
   }
-  if (use_lanes) DEV_TRY(h, lanes_join(h, s));
+  DEV_TRY(h, lanes.join());
   kt_set_tag(-1);
   // status of every task, then of the shared occupations
   h->tag_m.assign(nt, 0);

@@ -326,27 +326,78 @@ __global__ __launch_bounds__(256) void merge_prep_kernel(int n, const double* e,
   }
 }
 
-// Qblk = diag(Q1, Q2) of the node (dense N x N), then the recorded rotations.
-__global__ __launch_bounds__(256) void build_qblk_kernel(int n, const double* Qcur, long ldq,
-                                                         LevelBufs b, int m0) {
-  const int mi = m0 + blockIdx.y;
+// Qblk = diag(Q1, Q2) of the node (dense N x N): workgroup (x, y) of merge
+// blockIdx.z fills rows [256 x, 256 x + 256) of columns [QB y, QB y + QB).
+constexpr int QB = 32;
+__global__ __launch_bounds__(256) void qblk_fill_kernel(const double* Qcur, long ldq, LevelBufs b,
+                                                        int m0, int n) {
+  const int mi = m0 + blockIdx.z;
   const int lo = b.merges[3 * mi], mid = b.merges[3 * mi + 1], hi = b.merges[3 * mi + 2];
   const int n1 = mid - lo, N = hi - lo;
   const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= N) return;
+  const int c0 = blockIdx.y * QB;
+  if (r >= N || c0 >= N) return;
   double* Qb = b.Qblk + (long)lo * n;
   const bool top = r < n1;
-  for (int c = 0; c < N; c++) {
+  const int c1 = min(N, c0 + QB);
+  for (int c = c0; c < c1; c++) {
     const bool ctop = c < n1;
     Qb[r + (long)c * N] = (top == ctop) ? Qcur[(lo + r) + (long)(lo + c) * ldq] : 0.0;
   }
+}
+
+// The recorded deflation rotations applied to the rows of Qblk.
+__global__ __launch_bounds__(256) void qblk_rotate_kernel(int n, LevelBufs b, int m0) {
+  const int mi = m0 + blockIdx.y;
+  const int lo = b.merges[3 * mi], hi = b.merges[3 * mi + 2];
+  const int N = hi - lo;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= N) return;
+  double* Qb = b.Qblk + (long)lo * n;
+  // The rotations in order, RG at a time: the group's 2 RG entries of the
+  // row are loaded together, the rotations applied in registers (an entry
+  // that an earlier rotation of the group wrote is taken from that rotation's
+  // result), then stored in order, so one memory latency covers RG rotations.
+  constexpr int RG = 8;
   const int nrot = b.meta[(long)mi * META + 2];
-  for (int q = 0; q < nrot; q++) {
-    const int ca = b.rot_a[lo + q], cb = b.rot_b[lo + q];
-    const double c = b.rot_c[lo + q], s = b.rot_s[lo + q];
-    const double qa = Qb[r + (long)ca * N], qb = Qb[r + (long)cb * N];
-    Qb[r + (long)ca * N] = c * qa - s * qb;
-    Qb[r + (long)cb * N] = s * qa + c * qb;
+  for (int q0 = 0; q0 < nrot; q0 += RG) {
+    const int cnt = min(RG, nrot - q0);
+    int ca[RG], cb[RG];
+    double va[RG], vb[RG], cs[RG], sn[RG];
+#pragma unroll
+    for (int j = 0; j < RG; j++) {
+      if (j < cnt) {
+        ca[j] = b.rot_a[lo + q0 + j];
+        cb[j] = b.rot_b[lo + q0 + j];
+        cs[j] = b.rot_c[lo + q0 + j];
+        sn[j] = b.rot_s[lo + q0 + j];
+        va[j] = Qb[r + (long)ca[j] * N];
+        vb[j] = Qb[r + (long)cb[j] * N];
+      } else {
+        ca[j] = cb[j] = -1;
+        va[j] = vb[j] = cs[j] = sn[j] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < RG; j++) {
+      double qa = va[j], qb = vb[j];
+#pragma unroll
+      for (int i = 0; i < j; i++) {
+        if (ca[i] == ca[j]) qa = va[i];
+        else if (cb[i] == ca[j]) qa = vb[i];
+        if (ca[i] == cb[j]) qb = va[i];
+        else if (cb[i] == cb[j]) qb = vb[i];
+      }
+      va[j] = cs[j] * qa - sn[j] * qb;
+      vb[j] = sn[j] * qa + cs[j] * qb;
+    }
+#pragma unroll
+    for (int j = 0; j < RG; j++) {
+      if (j < cnt) {
+        Qb[r + (long)ca[j] * N] = va[j];
+        Qb[r + (long)cb[j] * N] = vb[j];
+      }
+    }
   }
 }
 
@@ -742,8 +793,11 @@ hipError_t stedc_run(StedcPlan* p, const double* d, const double* e, double* lam
     hipLaunchKernelGGL(merge_prep_kernel, dim3(cnt), dim3(256), 0, s, n, e, lam, Qcur, (long)n, b,
                        m0);
     HSDM_TRY(hipGetLastError());
-    hipLaunchKernelGGL(build_qblk_kernel, dim3(ceil_div(maxN, 256), cnt), dim3(256), 0, s, n, Qcur,
-                       (long)n, b, m0);
+    hipLaunchKernelGGL(qblk_fill_kernel, dim3(ceil_div(maxN, 256), ceil_div(maxN, QB), cnt),
+                       dim3(256), 0, s, Qcur, (long)n, b, m0, n);
+    HSDM_TRY(hipGetLastError());
+    hipLaunchKernelGGL(qblk_rotate_kernel, dim3(ceil_div(maxN, 256), cnt), dim3(256), 0, s, n, b,
+                       m0);
     HSDM_TRY(hipGetLastError());
     hipLaunchKernelGGL(secular_kernel, dim3(ceil_div(maxN, 4), cnt), dim3(256), 0, s, b, m0, st);
     HSDM_TRY(hipGetLastError());

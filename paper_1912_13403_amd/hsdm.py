@@ -32,6 +32,7 @@ HSDM_KEY_FMAX = 1
 HSDM_KEY_FCUT = 2
 HSDM_KEY_DEG_TOL = 3
 HSDM_KEY_TIMING = 4
+HSDM_KEY_STREAMS = 5
 
 EXPORTED = [
     "hsdm_init", "hsdm_finalize", "hsdm_reinit", "hsdm_set_real", "hsdm_set_int",

@@ -53,13 +53,15 @@ def admit(queue, budget, resident, task_bytes):
 
 
 class Server:
-    def __init__(self, device=0, hbm_budget=200e9, timing_level=0):
+    def __init__(self, device=0, hbm_budget=200e9, timing_level=0, streams=None):
         self.h = hsdm.Handle(device)
         self.dev = self.h.device
         self.budget = float(hbm_budget)
         self.s_dev = OrderedDict()  # base request id -> resident S on the device
         if timing_level:
             self.h.hsdm_set_int(hsdm.HSDM_KEY_TIMING, timing_level)
+        if streams:
+            self.h.hsdm_set_int(hsdm.HSDM_KEY_STREAMS, streams)
 
     def close(self):
         self.s_dev.clear()

@@ -260,3 +260,28 @@ def test_complex_tasks_sharing_one_s_buffer(oracle, torch_dev, h):
     r = h.hsdm_solve_dm_batch([_g(torch_dev, x) for x in Hs], Sg, ne, kT)
     ref = oracle.solve_dm_batch(Hs, Ss, ne, kT, f_max=1.0)
     _check(r, ref, Hs, ne)
+
+
+def test_worker_streams_do_not_change_results(torch_dev, h):
+    """The tasks' phases give the same bits on 1, 3 or 8 worker streams (each
+    task's kernels are the same; only their placement differs), and the
+    stream count is checked."""
+    from paper_1912_13403_amd import hsdm
+    lib = hsdm.load_library()
+    assert lib.hsdm_set_int(h._h, hsdm.HSDM_KEY_STREAMS, 0) == -3
+    assert lib.hsdm_set_int(h._h, hsdm.HSDM_KEY_STREAMS, 9) == -3
+    sizes = [60, 90, 130, 45, 77]
+    probs = [inputs.sized_problem(n, cfg=1800 + i) for i, n in enumerate(sizes)]
+    Hs = [_g(torch_dev, p[0]) for p in probs]
+    Ss = [_g(torch_dev, p[1]) for p in probs]
+    _set_fmax(h, 2.0)
+    out = []
+    for nst in (1, 3, 8):
+        h.hsdm_set_int(hsdm.HSDM_KEY_STREAMS, nst)
+        h.hsdm_reinit()
+        out.append(h.hsdm_solve_dm_batch(Hs, Ss, 300.0, 0.01))
+    h.hsdm_set_int(hsdm.HSDM_KEY_STREAMS, 4)
+    for r in out[1:]:
+        assert r["mu"] == out[0]["mu"]
+        for D, D0 in zip(r["D"], out[0]["D"]):
+            assert np.array_equal(_c(D), _c(D0))
