@@ -504,11 +504,10 @@ hipError_t launch_cfg(const Prob& p, double alpha, double beta, int flags, int n
 // (a k-contiguous A operand is read best by the 64x64 tiles: measured 58
 // against 45 TFLOP/s for 8192^3, 39 against 26 for 512 x 4838 x 8192)
 int pick_cfg(int m, int n, int nsplit, int ta) {
-  static int forced = -2;
-  if (forced == -2) {
+  static const int forced = [] {  // thread-safe one-time initialization
     const char* e = getenv("HSDM_GEMM_CFG");
-    forced = e ? atoi(e) : -1;
-  }
+    return e ? atoi(e) : -1;
+  }();
   if (forced >= 0 && forced <= 2) return forced;
   if (n <= 32) return 3;
   if (m <= 32) return 4;
