@@ -115,7 +115,6 @@ hipError_t rec(int n, double* A, long lda, double* Li, long ldi, double* T, long
   g.alpha = 1.0; g.beta = 0.0; g.ta = 0; g.tb = 1; g.flags = GF_KB_UPPER;
   HSDM_TRY(gemm_launch(g, s));
   HSDM_TRY(dev_copy(T, ldt, A21, lda, n2, n1, s));
-  HSDM_TRY(dev_fill(A + (long)n1 * lda, lda, n1, n2, 0.0, s));  // strict upper block of L
   // S22 -= L21 L21^T (lower)
   g = GemmArgs{};
   g.m = n2; g.n = n2; g.k = n1;
@@ -135,9 +134,22 @@ hipError_t rec(int n, double* A, long lda, double* Li, long ldi, double* T, long
   g.m = n2; g.n = n1; g.k = n2;
   g.A = Li22; g.lda = ldi; g.B = T; g.ldb = ldt; g.C = Li21; g.ldc = ldi;
   g.alpha = -1.0; g.beta = 0.0; g.ta = 0; g.tb = 0; g.flags = GF_KA_LOWER;
-  HSDM_TRY(gemm_launch(g, s));
-  HSDM_TRY(dev_fill(Li + (long)n1 * ldi, ldi, n1, n2, 0.0, s));  // strict upper block
-  return hipSuccess;
+  return gemm_launch(g, s);
+}
+
+// Zeros above the diagonal of an n x n matrix: workgroup (x, y) clears rows
+// [256 x, 256 x + 256) of columns y, y + gridDim.y, ...
+__global__ __launch_bounds__(256) void zero_upper_kernel(double* A, long lda, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  for (int j = blockIdx.y; j < n; j += gridDim.y)
+    if (i < j) A[i + (long)j * lda] = 0.0;
+}
+
+hipError_t zero_upper(double* A, long lda, int n, hipStream_t s) {
+  if (n <= 1) return hipSuccess;
+  hipLaunchKernelGGL(zero_upper_kernel, dim3(ceil_div(n, 256), n < 16384 ? n : 16384), dim3(256),
+                     0, s, A, lda, n);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -145,5 +157,10 @@ hipError_t rec(int n, double* A, long lda, double* Li, long ldi, double* T, long
 hipError_t chol_inv(int n, double* A, long lda, double* Li, long ldi, double* T, long ldt,
                     DevStatusWord* st, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  return rec(n, A, lda, Li, ldi, T, ldt, st, 0, s);
+  // The recursion reads the inverse's blocks above the diagonal as zeros
+  // (triangular operands are read by whole tiles) and never reads the
+  // factor's; both are cleared once, not block by block.
+  HSDM_TRY(zero_upper(Li, ldi, n, s));
+  HSDM_TRY(rec(n, A, lda, Li, ldi, T, ldt, st, 0, s));
+  return zero_upper(A, lda, n, s);
 }
