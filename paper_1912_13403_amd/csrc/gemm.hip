@@ -341,8 +341,18 @@ inline int tile_grid(long tiles_m, long tiles_n) {
   return (int)(8 * ((major + 7) / 8) * minor);
 }
 
+// Register budgets: the 8-wavefront tiles at two workgroups per CU; the
+// skinny 128 x 32 tiles (streaming a tall operand) at three, so that more
+// loads are in flight (their transposed strict-lower form would spill).
+template <int BM, int BN, int WM, int WN, int TA, int AM>
+constexpr int waves_per_eu() {
+  if (WM * WN == 8 && TA == 0) return 4;
+  if (BM == 128 && BN == 32 && AM != AM_SLT) return 3;
+  return 1;
+}
+
 template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
-__global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(WM * WN == 8 && TA == 0 ? 4 : 1))) void gemm_kernel(Prob p, double alpha, double beta,
+__global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(waves_per_eu<BM, BN, WM, WN, TA, AM>()))) void gemm_kernel(Prob p, double alpha, double beta,
                                                             int flags, int kchunk,
                                                             long split_stride) {
   using C = G<BM, BN, WM, WN, TA, TB, AM>;
@@ -411,7 +421,7 @@ __global__ void splitk_reduce_kernel(int m, int n, int nsplit, const double* par
 // splitk_reduce_group_kernel into C = sum + beta C; kchunk = 0: the tile is
 // computed in place, C = alpha op(A) op(B) + beta C.
 template <int TA, int TB, int AM>
-__global__ __launch_bounds__(256) void gemm_group_kernel(const GemmGroupItem* items,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves_per_eu<128, 32, 4, 1, TA, AM>()))) void gemm_group_kernel(const GemmGroupItem* items,
                                                          const int* wg_item) {
   using C = G<128, 32, 4, 1, TA, TB, AM>;
   __shared__ double smem[C::SMEM];
