@@ -229,10 +229,13 @@ __global__ __launch_bounds__(256) void merge_prep_kernel(int n, const double* e,
           pd = dq; pz = zq; pc = cp[q]; pm = cm[q];
           continue;
         }
-        const double r = hypot(zq, pz);
-        const double c = zq / r, s = pz / r;
-        const double off = (pd - dq) * c * s;
-        if (fabs(off) <= tol) {
+        // the rotation that zeroes z_prev has c = zq / r, s = pz / r,
+        // r = hypot(zq, pz), and leaves the coupling (pd - dq) c s; the test
+        // |(pd - dq) c s| <= tol is taken as |(pd - dq) zq pz| <= tol r^2 so
+        // that r, c and s are formed only for a rotation
+        if (fabs((pd - dq) * zq * pz) <= tol * (zq * zq + pz * pz)) {
+          const double r = hypot(zq, pz);
+          const double c = zq / r, s = pz / r;
           // rotate: new prev column = c q_prev - s q_cur (z -> 0), cur = s q_prev + c q_cur
           b.rot_a[lo + nrot] = pc;
           b.rot_b[lo + nrot] = cp[q];
