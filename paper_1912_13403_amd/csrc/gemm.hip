@@ -343,11 +343,12 @@ inline int tile_grid(long tiles_m, long tiles_n) {
 
 // Register budgets: the 8-wavefront tiles at two workgroups per CU; the
 // skinny 128 x 32 tiles (streaming a tall operand) at three, so that more
-// loads are in flight (their transposed strict-lower form would spill).
+// loads are in flight (the transposed strict-lower form then spills a few
+// registers and is still faster).
 template <int BM, int BN, int WM, int WN, int TA, int AM>
 constexpr int waves_per_eu() {
   if (WM * WN == 8 && TA == 0) return 4;
-  if (BM == 128 && BN == 32 && AM != AM_SLT) return 3;
+  if (BM == 128 && BN == 32) return 3;
   return 1;
 }
 
