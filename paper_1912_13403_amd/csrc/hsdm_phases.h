@@ -126,7 +126,7 @@ hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff,
 // tasks and hmap are the caller's host arrays (kept until the stream has run
 // the work); d_tasks holds nt descriptors, d_map bt2_group_map_ints ints
 // (two per workgroup).
-constexpr int NSPLIT = 4;
+constexpr int NSPLIT = 8;
 struct SplitRanges {
   int hi[NSPLIT];  // range k covers sweep blocks lo[k] .. hi[k] (hi[k] = lo[k-1] - 1)
   int lo[NSPLIT];
