@@ -462,6 +462,45 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void s
                                             1 << 30);
 }
 
+// The two passes of X = A Y for a symmetric A with its lower triangle stored
+// (X = tril(A) Y + strict_tril(A)^T Y), split over K, in one launch:
+// blockIdx.z = 0 writes the partials of the first pass to part1, 1 those of
+// the second to part2 (slice blockIdx.y at offset y m n, leading dimension m).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sym_pair_kernel(
+    Prob p, double* part1, double* part2, int kchunk) {
+  using C1 = G<128, 32, 4, 1, 0, 0, AM_TRIL>;
+  using C2 = G<128, 32, 4, 1, 1, 0, AM_SLT>;
+  __shared__ double smem[C1::SMEM > C2::SMEM ? C1::SMEM : C2::SMEM];
+  int tm, tn;
+  if (!map_tile(blockIdx.x, (p.m + 127) / 128, 1, tm, tn)) return;
+  const int klo = blockIdx.y * kchunk;
+  p.ldc = p.m;
+  if (blockIdx.z == 0) {
+    p.C = part1 + (long)blockIdx.y * p.m * p.n;
+    gemm_tile<128, 32, 4, 1, 0, 0, AM_TRIL>(p, 1.0, 0.0, GF_A_TRIL | GF_KA_LOWER, tm, tn, smem,
+                                            klo, klo + kchunk);
+  } else {
+    p.C = part2 + (long)blockIdx.y * p.m * p.n;
+    gemm_tile<128, 32, 4, 1, 1, 0, AM_SLT>(p, 1.0, 0.0, GF_A_SLT | GF_KA_UPPER, tm, tn, smem,
+                                           klo, klo + kchunk);
+  }
+}
+
+// C = (sum of part2's slices) + (sum of part1's slices), each summed in
+// slice order: the same roundings as the first pass reduced into C and the
+// second reduced onto it.
+__global__ void sym_pair_reduce_kernel(int m, int n, int nsplit, const double* part1,
+                                       const double* part2, double* C, long ldc) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long tot = (long)m * n;
+  if (idx >= tot) return;
+  double s1 = 0.0, s2 = 0.0;
+  for (int z = 0; z < nsplit; z++) s1 += part1[z * tot + idx];
+  for (int z = 0; z < nsplit; z++) s2 += part2[z * tot + idx];
+  const int i = (int)(idx % m), j = (int)(idx / m);
+  C[i + (long)j * ldc] = s2 + s1;
+}
+
 // C = sum of the item's split partials + beta C, item blockIdx.y (split items only)
 __global__ void splitk_reduce_group_kernel(const GemmGroupItem* items) {
   const GemmGroupItem& it = items[blockIdx.y];
@@ -653,6 +692,24 @@ hipError_t gemm_batched_dense_launch(const GemmDesc* d_desc, int count, int max_
   hipLaunchKernelGGL((gemm_batched_kernel<64, 64, 2, 2, 0, 0, AM_DENSE>), dim3(nblk, count),
                      dim3(256), 0, s, d_desc, alpha, beta, flags);
   kt_end(s);
+  return hipGetLastError();
+}
+
+hipError_t gemm_sym_pair_launch(const GemmArgs& g, int kchunk, double* part1, double* part2,
+                                hipStream_t s) {
+  if (g.m <= 0 || g.n <= 0) return hipSuccess;
+  if (g.n > 32 || g.m != g.k || kchunk <= 0 || g.ta || g.tb || !(g.flags & GF_A_TRIL))
+    return hipErrorInvalidValue;
+  const int nsplit = ceil_div(g.k, kchunk);
+  Prob p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, nullptr, (long)g.m, nullptr, nullptr, nullptr};
+  kt_begin("sym_pair_kernel", 2.0 * gemm_flops(g), 0.0, 0, s);
+  hipLaunchKernelGGL(sym_pair_kernel, dim3(tile_grid(ceil_div(g.m, 128), 1), nsplit, 2), dim3(256),
+                     0, s, p, part1, part2, kchunk);
+  kt_end(s);
+  HSDM_TRY(hipGetLastError());
+  const long tot = (long)g.m * g.n;
+  hipLaunchKernelGGL(sym_pair_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                     g.m, g.n, nsplit, part1, part2, g.C, g.ldc);
   return hipGetLastError();
 }
 

@@ -3,6 +3,15 @@
 #include <vector>
 #include "hsdm_internal.h"
 
+// gemm.hip -- X = A Y for a symmetric A (lower triangle stored), n <= 32
+// columns: g describes the first pass (GF_A_TRIL, m = k; C = g.C, alpha 1,
+// beta 0); both passes run split over K in one launch, their partials
+// (ceil(k / kchunk) m x n slices each) in part1 and part2, then one reduction
+// writes C.  The roundings are those of the two passes reduced one after
+// the other.
+hipError_t gemm_sym_pair_launch(const GemmArgs& g, int kchunk, double* part1, double* part2,
+                                hipStream_t s);
+
 // sy2sb.hip -- full -> band (half-bandwidth B).  A (lower triangle) is
 // overwritten; Vst receives the explicit panel reflectors (n x n, lower
 // trapezoid), tau1 the scalars, T1 one B x B triangular factor per panel, AB

@@ -402,10 +402,10 @@ size_t sy2sb_scratch_doubles(int n, int B) {
   const int G = ceil_div(n, CH) + 1;
   // panel exchange slots: part (B columns x G x B) + prow (B x B) + gpart (G B^2);
   // atb parts (G B^2) + Y (n x B) + VW, WV (n x 4B each) + M (B^2) + Q (2B^2)
-  // + split-K partials (nsplit x n x B)
+  // + split-K partials of the two symmetric passes (nsplit x n x B each)
   const size_t nsplit = ceil_div(n, SPLITK) + 1;
   return (size_t)G * B * B + (size_t)B * B + (size_t)2 * G * B * B + (size_t)9 * n * B +
-         3 * B * B + 64 + nsplit * n * B;
+         3 * B * B + 64 + 2 * nsplit * n * B;
 }
 
 // Panels are reduced in pairs with one trailing update per pair.  For the
@@ -436,7 +436,7 @@ struct Sy2sb {
   DevStatusWord* st;
   hipStream_t s;
   int Gmax;
-  double *part, *prow, *gpart, *apart, *Y, *VW, *WV, *M, *Qc, *skpart;
+  double *part, *prow, *gpart, *apart, *Y, *VW, *WV, *M, *Qc, *skpart, *skpart2;
 
   Sy2sb(const Sy2sbArgs& a, int B_, hipStream_t s_)
       : n(a.n), B(B_), A(a.A), lda(a.lda), Vst(a.Vst), ldv(a.ldv), tau1(a.tau1), T1(a.T1),
@@ -452,6 +452,7 @@ struct Sy2sb {
     M = WV + (size_t)n * 4 * B;            // B x B
     Qc = M + B * B;                        // 2B x B
     skpart = Qc + 2 * B * B + 64;          // split-K partials
+    skpart2 = skpart + (size_t)(ceil_div(n, SPLITK) + 1) * n * B;  // the second pass's
   }
   int npanel() const { return (n > B) ? ceil_div(n - 1, B) : 0; }
   int height(int p) const { return n - (p + 1) * B; }
@@ -528,6 +529,7 @@ struct Sy2sb {
   hipError_t make_w_sym(int r, int h, double* Wp) {
     GemmArgs t, u;
     sym_args(r, h, Wp, t, u);
+    if (h > SPLITK) return gemm_sym_pair_launch(t, SPLITK, skpart, skpart2, s);
     HSDM_TRY(gemm_splitk_launch(t, SPLITK, skpart, s));
     return gemm_splitk_launch(u, SPLITK, skpart, s);
   }
