@@ -58,3 +58,25 @@ def test_null_handle_is_argument_one(lib):
     assert lib.hsdm_set_real(None, 1, 2.0) == -1
     assert lib.hsdm_init(None, 0) == -1
     assert lib.hsdm_last_error(None) == b"null handle"
+
+
+def test_handle_keys_match_the_header(lib):
+    """The binding's key constants are the header's enum values; a null
+    handle is reported as argument 1 for the integer keys too."""
+    from paper_1912_13403_amd import hsdm
+    txt = open(HEADER).read()
+    for name in ("HSDM_KEY_FMAX", "HSDM_KEY_FCUT", "HSDM_KEY_DEG_TOL", "HSDM_KEY_TIMING",
+                 "HSDM_KEY_STREAMS"):
+        m = re.search(name + r"\s*=\s*(\d+)", txt)
+        assert m and int(m.group(1)) == getattr(hsdm, name), name
+    assert lib.hsdm_set_int(None, hsdm.HSDM_KEY_STREAMS, 4) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
