@@ -552,7 +552,9 @@ hipError_t launch_cfg(const Prob& p, double alpha, double beta, int flags, int n
 // tile configuration: 0 = 128x128 (8 waves), 1 = 128x64 (4 waves), 2 = 64x64 (4 waves),
 // 3 = 128x32 (4 waves, skinny n), 4 = 32x128 (4 waves, skinny m)
 // (a k-contiguous A operand is read best by the 64x64 tiles: measured 58
-// against 45 TFLOP/s for 8192^3, 39 against 26 for 512 x 4838 x 8192)
+// against 45 TFLOP/s for 8192^3, 39 against 26 for 512 x 4838 x 8192).
+// The environment variable HSDM_GEMM_CFG = 0, 1 or 2 forces that tile for
+// every product that is not skinny (for measuring the choice).
 int pick_cfg(int m, int n, int nsplit, int ta) {
   static const int forced = [] {  // thread-safe one-time initialization
     const char* e = getenv("HSDM_GEMM_CFG");
