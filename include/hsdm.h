@@ -62,6 +62,10 @@ enum hsdm_key {
   , HSDM_KEY_STREAMS = 5   /* int: worker streams of the multi-task solves, 1 ... 8 (default 4);
                               they run side by side only as far as the HIP runtime gives the
                               process hardware queues (GPU_MAX_HW_QUEUES) */
+  , HSDM_KEY_N_STATES = 6  /* int: number of eigenvectors the eigenpair solves form, the lowest
+                              ones (the paper's n_states: its dense runs compute only part of
+                              the eigenvectors, Sec. 3); 0 or >= n: all (default 0).  C then
+                              holds n_states columns; every eigenvalue is still returned */
 };
 
 /* Create a handle bound to HIP device `device` (~ elsi_init, Sec. 2.1). */
@@ -70,14 +74,28 @@ int hsdm_init(hsdm_handle *h, int device);
 int hsdm_finalize(hsdm_handle h);
 /* Forget the cached factor of S (~ elsi_reinit, Sec. 2.7: a new geometry
  * brings a new overlap matrix; everything else is kept).  The factor is
- * cached per (S pointer, n, lds); call this whenever S changes in place. */
+ * cached by the CONTENT of S: its size, real or complex, and a 64-bit hash of
+ * its lower triangle computed on the device at every call (one read of the
+ * lower triangle and one synchronization of the stream).  A solve whose S
+ * has the content of the cached one reuses the factor, whatever buffer holds
+ * it; any other S is factored anew, so a freed buffer reused for another S
+ * never finds a stale factor.  reinit drops the factor outright. */
 int hsdm_reinit(hsdm_handle h);
+/* Solver settings (~ the elsi_set_* routines of the API of Sec. 2.1, which
+ * configure a handle between elsi_init and the solves).  hsdm_set_real takes
+ * HSDM_KEY_FMAX, HSDM_KEY_FCUT, HSDM_KEY_DEG_TOL; hsdm_set_int takes
+ * HSDM_KEY_TIMING, HSDM_KEY_STREAMS, HSDM_KEY_N_STATES.  Returns HSDM_OK,
+ * -1 (null handle), -2 (unknown key for this call) or -3 (value out of the
+ * key's range; the setting is left unchanged).  Settings apply to the solves
+ * that follow and are kept across hsdm_reinit. */
 int hsdm_set_real(hsdm_handle h, int key, double value);
 int hsdm_set_int(hsdm_handle h, int key, long value);
 
 /* All eigenpairs of H C = S C eps (Eq. (3)).
- *   eval[n]        device, ascending eigenvalues (out)
- *   C[ldc * n]     device, eigenvectors (out), C^T S C = I
+ *   eval[n]        device, ascending eigenvalues (out), all n
+ *   C[ldc * ns]    device, eigenvectors (out) of the lowest ns = n_states
+ *                  eigenvalues (HSDM_KEY_N_STATES; all n by default),
+ *                  C^T S C = I; only those ns vectors are formed
  * Path: Cholesky S = L L^T with L^{-1} (cached), A = L^{-1} H L^{-T},
  * full-to-band, band-to-tridiagonal, divide and conquer, back-transforms. */
 int hsdm_solve_ev_real(hsdm_handle h, int n, const double *H, int ldh, const double *S, int lds,
@@ -115,7 +133,7 @@ int hsdm_solve_dm_real(hsdm_handle h, int n, const double *H, int ldh, const dou
  * E are read from the left half of the real results (D = D_R[:n, :n] +
  * i D_R[n:, :n]).  Workspace: that of a real solve of size 2n plus
  * 4 (2n)^2 doubles, allocated on the first call of each size.  The factor of
- * S is cached per (S pointer, n, lds) as in the real path.  Status codes as
+ * S is cached by the content of S as in the real path.  Status codes as
  * hsdm_solve_dm_real. */
 int hsdm_solve_dm_complex(hsdm_handle h, int n, const void *H, int ldh, const void *S, int lds,
                           double n_electrons, double kT, void *D, int ldd, void *E, int lde,
@@ -138,10 +156,11 @@ int hsdm_solve_dm_complex(hsdm_handle h, int n, const void *H, int ldh, const vo
  * kT = 0: the Fermi level is the lowest eigenvalue of all tasks at which
  * f_max * sum weight reaches n_electrons, and the states of all tasks within
  * the degeneracy window of it share the remainder equally per unit weight.
- * Each task runs the path of the single solves (its factor of S cached per
- * (S[p], n[p], lds[p]) in a task context owned by the handle and kept until
- * hsdm_finalize; hsdm_reinit forgets every task's factor; tasks of one call
- * with the same S[p], n[p], lds[p] share one factorization); the tridiagonal
+ * Each task runs the path of the single solves (its factor of S cached by
+ * the content of S[p], as in the single solves, in a task context owned by
+ * the handle and kept until hsdm_finalize; hsdm_reinit forgets every task's
+ * factor; tasks of one call with the same S[p], n[p], lds[p] share one
+ * factorization); the tridiagonal
  * eigenvectors of all tasks are kept until the joint occupations are known,
  * then each task back-transforms its occupied vectors.  With several tasks
  * their independent phases run on the handle's worker streams, which start
@@ -160,7 +179,10 @@ int hsdm_solve_dm_batch(hsdm_handle h, int nprob, int is_complex, const int *n,
  * Sec. 2.1).  H, S, C interleaved complex128, column-major, leading
  * dimensions in complex elements; lower triangles of H and S read.
  *   eval[n]        device, ascending eigenvalues (out)
- *   C[ldc * n]     device, complex eigenvectors (out), C^H S C = I
+ *   C[ldc * ns]    device, complex eigenvectors (out), C^H S C = I, of the
+ *                  lowest ns = n_states eigenvalues (HSDM_KEY_N_STATES; all n
+ *                  by default; all 2n real vectors of the embedding are
+ *                  still formed)
  * Method: the real embedding of size 2n (every eigenvalue twice); column l
  * of C is x + i y from the real eigenvector [x; y] of pair l.  For a complex
  * eigenvalue of multiplicity k (eigenvalues within 1e-10 max(1, |eps|)) the
@@ -176,9 +198,10 @@ int hsdm_solve_ev_complex(hsdm_handle h, int n, const void *H, int ldh, const vo
  * potential and band energy (HOST arrays mu[nprob], band_energy[nprob],
  * nullable).  Each task runs the path of the single solves; the bands of all
  * tasks are chased in shared cooperative launches.  Task contexts (workspace
- * and factor of S) are owned by the handle and picked by S identity, so a
- * task whose S (pointer, n, lds) was factored in an earlier call reuses the
- * factor; otherwise the least recently used context is taken.  Other
+ * and factor of S) are owned by the handle and picked by the content of S,
+ * so a task whose S was factored in an earlier call (by any buffer holding
+ * the same matrix) reuses the factor; otherwise the least recently used
+ * context is taken.  Other
  * arguments, factor sharing within a call, the worker streams and status
  * codes as hsdm_solve_dm_batch (-3: a missing array or
  * a bad is_complex[p], -9: n_electrons[p], -10: kT[p], -11: f_max[p]). */

@@ -201,13 +201,23 @@ void orc_tridiagonalize(int n, const double *Ain, double *d, double *e, double *
  *    same order as a serial update would).  At most 30 steps per
  *    eigenvalue; returns 2 if that is exceeded.                            */
 static void apply_rotations(int n, double *Z, const double *cs, const double *sn, int hi, int lo) {
-    /* rotation i acts on columns (i, i+1); applied for i = hi down to lo */
+    /* rotation i acts on columns (i, i+1); applied for i = hi down to lo.
+     * Rows are independent: each thread takes blocks of 64 rows and applies
+     * the rotations to them in the order above, so every element of Z sees
+     * exactly the sequence of operations a serial update would apply. */
+    const int RB = 64;
+    const int nblk = (n + RB - 1) / RB;
 #pragma omp parallel for schedule(static)
-    for (int r = 0; r < n; r++) {
+    for (int blk = 0; blk < nblk; blk++) {
+        const int r0 = blk * RB, r1 = (r0 + RB < n) ? r0 + RB : n;
         for (int i = hi; i >= lo; i--) {
-            double a = Z[(size_t)i * n + r], b = Z[(size_t)(i + 1) * n + r];
-            Z[(size_t)(i + 1) * n + r] = sn[i] * a + cs[i] * b;
-            Z[(size_t)i * n + r] = cs[i] * a - sn[i] * b;
+            double *zi = Z + (size_t)i * n, *zj = Z + (size_t)(i + 1) * n;
+            const double c = cs[i], s = sn[i];
+            for (int r = r0; r < r1; r++) {
+                double a = zi[r], b = zj[r];
+                zj[r] = s * a + c * b;
+                zi[r] = c * a - s * b;
+            }
         }
     }
 }

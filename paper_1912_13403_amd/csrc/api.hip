@@ -68,6 +68,7 @@ struct hsdm_ctx {
   bool ktiming = false;
   bool kt_every = false;  // every launch timed: no worker streams
   int nlane = 4;          // worker streams used by multi-task solves
+  long n_states = 0;      // eigenvectors formed by the eigenpair solves (0: all)
   KTimer* kt = nullptr;
   std::string err;
   int detail = 0;
@@ -118,11 +119,17 @@ struct hsdm_ctx {
   hipStream_t lane_s[NLANE] = {};
   hipEvent_t lane_ev[NLANE + 1] = {};
   hsdm_ctx* lane_buf[NLANE] = {};
-  // cached factor of S, keyed by the caller's S (pointer, n, ld, complex)
-  const void* s_ptr = nullptr;
-  int s_n = 0, s_ld = 0;
+  // cached factor of S, keyed by the content of the caller's S (size, real
+  // or complex, 64-bit hash of the lower triangle), never by its address: a
+  // buffer freed and reused for another S must not find the old factor
+  int s_n = 0;
   bool s_cplx = false;
+  unsigned long long s_hash = 0;
   bool s_valid = false;
+  // content hashes of the S matrices of a call (device, then pinned host)
+  unsigned long long* d_hash = nullptr;
+  unsigned long long* h_hash = nullptr;
+  int hash_cap = 0;
   // phase timing
   hipEvent_t ev[NPHASE + 1] = {};
   double phase_ms[NPHASE] = {};
@@ -407,15 +414,50 @@ int finish(hsdm_ctx* h, hipStream_t s) {
 
 bool bad_ld(int ld, int n) { return ld < (n > 1 ? n : 1); }
 
-// Identity of the caller's S for the factor cache.
+// Identity of the caller's S for the factor cache: its size, whether it is
+// complex, and the content hash of its lower triangle (the part the solvers
+// read).
 struct SKey {
-  const void* p;
-  int n, ld;
+  int n;
   bool cplx;
+  unsigned long long hash;
 };
 
 bool s_cached(const hsdm_ctx* h, const SKey& k) {
-  return h->s_valid && h->s_ptr == k.p && h->s_n == k.n && h->s_ld == k.ld && h->s_cplx == k.cplx;
+  return h->s_valid && h->s_n == k.n && h->s_cplx == k.cplx && h->s_hash == k.hash;
+}
+
+// Content hashes of cnt matrices S[p] (n[p] x n[p], leading dimension
+// lds[p], complex if cplx[p]) into out[p], with one synchronization of s.
+int s_hashes(hsdm_ctx* h, int cnt, const void* const* S, const int* n, const int* lds,
+             const int* cplx, unsigned long long* out, hipStream_t s) {
+  if (cnt <= 0) return HSDM_OK;
+  if (h->hash_cap < cnt) {
+    if (h->d_hash) (void)hipFree(h->d_hash);
+    if (h->h_hash) (void)hipHostFree(h->h_hash);
+    h->d_hash = nullptr;
+    h->h_hash = nullptr;
+    h->hash_cap = 0;
+    DEV_TRY(h, hipMalloc(&h->d_hash, sizeof(unsigned long long) * cnt));
+    DEV_TRY(h, hipHostMalloc((void**)&h->h_hash, sizeof(unsigned long long) * cnt,
+                             hipHostMallocDefault));
+    h->hash_cap = cnt;
+  }
+  DEV_TRY(h, dev_hash_clear(h->d_hash, cnt, s));
+  for (int p = 0; p < cnt; p++)
+    DEV_TRY(h, dev_hash_lower(S[p], lds[p], n[p], cplx[p], h->d_hash + p, s));
+  DEV_TRY(h, hipMemcpyAsync(h->h_hash, h->d_hash, sizeof(unsigned long long) * cnt,
+                            hipMemcpyDeviceToHost, s));
+  DEV_TRY(h, hipStreamSynchronize(s));
+  for (int p = 0; p < cnt; p++) out[p] = h->h_hash[p];
+  return HSDM_OK;
+}
+
+// The cache key of one S.
+int s_key(hsdm_ctx* h, const void* S, int n, int lds, bool cplx, SKey& key, hipStream_t s) {
+  const int c = cplx ? 1 : 0;
+  key = SKey{n, cplx, 0ull};
+  return s_hashes(h, 1, &S, &n, &lds, &c, &key.hash, s);
 }
 
 // Cholesky + inverse of the real symmetric S (n x n, lower) into the cache,
@@ -425,10 +467,9 @@ int factor_s(hsdm_ctx* h, int n, const double* S, int lds, const SKey& key, hipS
   DEV_TRY(h, dev_copy(S, lds, h->Lbuf, n, n, n, s));
   DEV_TRY(h, dev_fill(h->Linv, n, n, n, 0.0, s));
   DEV_TRY(h, chol_inv(n, h->Lbuf, n, h->Linv, n, h->Abuf, n, h->st, s));
-  h->s_ptr = key.p;
   h->s_n = key.n;
-  h->s_ld = key.ld;
   h->s_cplx = key.cplx;
+  h->s_hash = key.hash;
   h->s_valid = true;
   return HSDM_OK;
 }
@@ -541,6 +582,8 @@ int hsdm_finalize(hsdm_handle h) {
   free_cws(h);
   if (h->st) (void)hipFree(h->st);
   if (h->host) (void)hipHostFree(h->host);
+  if (h->d_hash) (void)hipFree(h->d_hash);
+  if (h->h_hash) (void)hipHostFree(h->h_hash);
   for (int i = 0; i <= NPHASE; i++)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
   kt_destroy(h->kt);
@@ -552,7 +595,6 @@ int hsdm_reinit(hsdm_handle h) {
   if (!h) return -1;
   for (hsdm_ctx* c : h->subs) hsdm_reinit(c);
   h->s_valid = false;
-  h->s_ptr = nullptr;
   return HSDM_OK;
 }
 
@@ -588,6 +630,11 @@ int hsdm_set_int(hsdm_handle h, int key, long v) {
   if (key == HSDM_KEY_STREAMS) {
     if (v < 1 || v > NLANE) return -3;
     h->nlane = (int)v;
+    return HSDM_OK;
+  }
+  if (key == HSDM_KEY_N_STATES) {
+    if (v < 0) return -3;
+    h->n_states = v;
     return HSDM_OK;
   }
   return -2;
@@ -841,14 +888,23 @@ static int dm_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S
   return HSDM_OK;
 }
 
-// Eigenpairs of the real pencil (H, S) of size n: eigenvalues into eval,
-// eigenvectors (C^T S C = I) into C; the S factor cached under `key`.
+// Eigenpairs of the real pencil (H, S) of size n: all eigenvalues into eval,
+// the eigenvectors of the lowest ns into C (C^T S C = I); the S factor cached
+// under `key`.  With ns < n the final divide-and-conquer merge forms only
+// those ns vectors (a device count in the handle's occupation record, which
+// this solve does not otherwise use) and the back-transforms take ns columns.
 static int ev_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S, int lds,
-                   const SKey& key, double* eval, double* C, int ldc, hipStream_t s) {
+                   const SKey& key, double* eval, double* C, int ldc, int ns, hipStream_t s) {
   int r;
   for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
   hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
+  const int* m_dev = nullptr;
+  if (ns < n) {
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, &h->occ->m, ns);
+    DEV_TRY(h, hipGetLastError());
+    m_dev = &h->occ->m;
+  }
   mark(h, 0, s);
   if ((r = factor_s(h, n, S, lds, key, s))) return r;
   mark(h, 1, s);
@@ -857,17 +913,22 @@ static int ev_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S
   if ((r = reduce(h, n, s, 3))) return r;
   mark(h, 4, s);
   DEV_TRY(h, stedc_run(h->plan, h->dvec, h->evec, eval, h->Zbuf, n, h->dc_scr, h->dc_iscr,
-                       nullptr, nullptr, nullptr, h->st, s));
+                       m_dev, nullptr, nullptr, h->st, s));
   mark(h, 5, s);
-  DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
-  DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, n, nullptr, h->progress, h->st, s));
+  if (ns > 0) {
+    DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
+    DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, ns, nullptr, h->progress, h->st,
+                         s));
+  }
   mark(h, 6, s);
-  DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, n, nullptr, h->bt1_scr, s));
+  if (ns > 0) DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, ns, nullptr, h->bt1_scr, s));
   mark(h, 7, s);
-  GemmArgs g{};
-  g.m = n; g.n = n; g.k = n; g.A = h->Linv; g.lda = n; g.B = h->Zbuf; g.ldb = n; g.C = C;
-  g.ldc = ldc; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.flags = GF_KA_UPPER;
-  DEV_TRY(h, gemm_launch(g, s));
+  if (ns > 0) {
+    GemmArgs g{};
+    g.m = n; g.n = ns; g.k = n; g.A = h->Linv; g.lda = n; g.B = h->Zbuf; g.ldb = n; g.C = C;
+    g.ldc = ldc; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.flags = GF_KA_UPPER;
+    DEV_TRY(h, gemm_launch(g, s));
+  }
   mark(h, 8, s);
   mark(h, 9, s);
   return HSDM_OK;
@@ -895,8 +956,11 @@ int hsdm_solve_ev_real(hsdm_handle h, int n, const double* H, int ldh, const dou
   DEV_TRY(h, hipSetDevice(h->device));
   int r = ensure_ws(h, n);
   if (r) return r;
+  SKey key;
+  if ((r = s_key(h, S, n, lds, false, key, s))) return r;
   KtScope kts(h);
-  if ((r = ev_core(h, n, H, ldh, S, lds, SKey{S, n, lds, false}, eval, C, ldc, s))) return r;
+  const int ns = (h->n_states > 0 && h->n_states < n) ? (int)h->n_states : n;
+  if ((r = ev_core(h, n, H, ldh, S, lds, key, eval, C, ldc, ns, s))) return r;
   return finish(h, s);
 }
 
@@ -918,14 +982,18 @@ int hsdm_solve_ev_complex(hsdm_handle h, int n, const void* H, int ldh, const vo
   int r = ensure_ws(h, n2);
   if (r) return r;
   if ((r = ensure_cws(h, n))) return r;
+  SKey key;
+  if ((r = s_key(h, S, n, lds, true, key, s))) return r;
   KtScope kts(h);
-  const SKey key{S, n, lds, true};
   if (!s_cached(h, key)) DEV_TRY(h, herm_embed(n, S, lds, h->SR, n2, s));
   DEV_TRY(h, herm_embed(n, H, ldh, h->HR, n2, s));
-  // real eigenpairs of the embedded pencil (each eigenvalue twice) into lam, DR
-  if ((r = ev_core(h, n2, h->HR, n2, h->SR, n2, key, h->lam, h->DR, n2, s))) return r;
+  // real eigenpairs of the embedded pencil (each eigenvalue twice) into lam,
+  // DR; every real vector is formed (a degenerate cluster at the n_states
+  // boundary needs all of its 2k candidates), the first ns pairs kept
+  const int ns = (h->n_states > 0 && h->n_states < n) ? (int)h->n_states : n;
+  if ((r = ev_core(h, n2, h->HR, n2, h->SR, n2, key, h->lam, h->DR, n2, n2, s))) return r;
   DEV_TRY(h, herm_pair_eval(n, h->lam, eval, s));
-  DEV_TRY(h, herm_extract_pairs(n, h->DR, n2, C, ldc, s));
+  DEV_TRY(h, herm_extract_pairs(n, ns, h->DR, n2, C, ldc, s));
   if ((r = finish(h, s))) return r;
   // A complex eigenvalue of multiplicity k has 2k real eigenvectors spanning
   // a k-dimensional complex space; one vector per real pair may then be
@@ -938,7 +1006,7 @@ int hsdm_solve_ev_complex(hsdm_handle h, int n, const void* H, int ldh, const vo
   for (double v : lam2) scale = std::max(scale, std::fabs(v));
   const double tol = 1e-10 * scale;
   bool sr_fresh = false;
-  for (int l0 = 0; l0 < n;) {
+  for (int l0 = 0; l0 < ns;) {
     int l1 = l0 + 1;
     while (l1 < n && 0.5 * (lam2[2 * l1] + lam2[2 * l1 + 1]) -
                          0.5 * (lam2[2 * l1 - 2] + lam2[2 * l1 - 1]) <= tol)
@@ -1013,7 +1081,9 @@ int hsdm_solve_ev_complex(hsdm_handle h, int n, const void* H, int ldh, const vo
         for (int r = 0; r < k; r++) coef[piv[r] + (size_t)c * k2] = X[r + (size_t)c * k];
       DEV_TRY(h, hipMemcpyAsync(cf, coef.data(), sizeof(double) * 2 * k2 * k,
                                 hipMemcpyHostToDevice, s));
-      DEV_TRY(h, herm_combine(n, k2, k, Qc, n2, cf, (char*)C + (size_t)l0 * ldc * 16, ldc, s));
+      // columns past ns are not the caller's: the cluster's first ns - l0 only
+      DEV_TRY(h, herm_combine(n, k2, std::min(k, ns - l0), Qc, n2, cf,
+                              (char*)C + (size_t)l0 * ldc * 16, ldc, s));
       DEV_TRY(h, hipStreamSynchronize(s));
     }
     l0 = l1;
@@ -1036,8 +1106,10 @@ int hsdm_solve_dm_real(hsdm_handle h, int n, const double* H, int ldh, const dou
   DEV_TRY(h, hipSetDevice(h->device));
   int r = ensure_ws(h, n);
   if (r) return r;
+  SKey key;
+  if ((r = s_key(h, S, n, lds, false, key, s))) return r;
   KtScope kts(h);
-  r = dm_core(h, n, H, ldh, S, lds, SKey{S, n, lds, false}, ne, kT, D, ldd, E, lde, s);
+  r = dm_core(h, n, H, ldh, S, lds, key, ne, kT, D, ldd, E, lde, s);
   if (eval && r == HSDM_OK) {
     hipLaunchKernelGGL(copy_vec_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, h->lam, eval, n);
     DEV_TRY(h, hipGetLastError());
@@ -1070,8 +1142,9 @@ int hsdm_solve_dm_complex(hsdm_handle h, int n, const void* H, int ldh, const vo
   int r = ensure_ws(h, n2);
   if (r) return r;
   if ((r = ensure_cws(h, n))) return r;
+  SKey key;
+  if ((r = s_key(h, S, n, lds, true, key, s))) return r;
   KtScope kts(h);
-  const SKey key{S, n, lds, true};
   if (!s_cached(h, key)) DEV_TRY(h, herm_embed(n, S, lds, h->SR, n2, s));
   DEV_TRY(h, herm_embed(n, H, ldh, h->HR, n2, s));
   r = dm_core(h, n2, h->HR, n2, h->SR, n2, key, 2.0 * ne, kT, h->DR, n2, E ? h->ER : nullptr, n2,
@@ -1105,11 +1178,12 @@ struct TaskSpec {
 // Task contexts for the tasks of one call: first a context that holds the
 // factor of the task's S, then the least recently used of the others
 // (created as needed).
-int pick_contexts(hsdm_ctx* h, int nt, const TaskSpec* T, std::vector<hsdm_ctx*>& ctx) {
+int pick_contexts(hsdm_ctx* h, int nt, const TaskSpec* T, const std::vector<SKey>& keys,
+                  std::vector<hsdm_ctx*>& ctx) {
   ctx.assign(nt, nullptr);
   std::vector<char> used(h->subs.size(), 0);
   for (int p = 0; p < nt; p++) {
-    const SKey key{T[p].S, T[p].n, T[p].lds, T[p].cplx != 0};
+    const SKey& key = keys[p];
     for (size_t i = 0; i < h->subs.size(); i++)
       if (!used[i] && s_cached(h->subs[i], key)) {
         used[i] = 1;
@@ -1149,8 +1223,22 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
                 double* eb_total, double* mu_shared, double* eb_each, double* mu_each,
                 hipStream_t s) {
   int r;
+  std::vector<SKey> keys(nt);
+  {
+    std::vector<const void*> sp(nt);
+    std::vector<int> sn(nt), sl(nt), sc(nt);
+    std::vector<unsigned long long> hv(nt);
+    for (int p = 0; p < nt; p++) {
+      sp[p] = T[p].S;
+      sn[p] = T[p].n;
+      sl[p] = T[p].lds;
+      sc[p] = T[p].cplx;
+    }
+    if ((r = s_hashes(h, nt, sp.data(), sn.data(), sl.data(), sc.data(), hv.data(), s))) return r;
+    for (int p = 0; p < nt; p++) keys[p] = SKey{T[p].n, T[p].cplx != 0, hv[p]};
+  }
   std::vector<hsdm_ctx*> ctx;
-  if ((r = pick_contexts(h, nt, T, ctx))) return r;
+  if ((r = pick_contexts(h, nt, T, keys, ctx))) return r;
   if (h->d_tasks_cap < nt) {
     if (h->d_tasks) (void)hipFree(h->d_tasks);
     h->d_tasks = nullptr;
@@ -1245,7 +1333,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
     c->timing = false;
     c->ktiming = false;
     const int nr = t.cplx ? 2 * t.n : t.n;
-    const SKey key{t.S, t.n, t.lds, t.cplx != 0};
+    const SKey& key = keys[p];
     const bool own = src[p] == p;
     const double *Hr = (const double*)t.H, *Sr = (const double*)t.S;
     int ldhr = t.ldh, ldsr = t.lds;

@@ -73,11 +73,11 @@ __global__ void herm_pair_eval_kernel(int n, const double* lam2, double* eval) {
 }
 
 // X[i, l] = R[i, 2l] + i R[n + i, 2l]: one real eigenvector of each pair.
-__global__ __launch_bounds__(256) void herm_extract_pairs_kernel(int n, const double* R, long ldr,
-                                                                 double2* X, long ldx) {
+__global__ __launch_bounds__(256) void herm_extract_pairs_kernel(int n, int m, const double* R,
+                                                                 long ldr, double2* X, long ldx) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  for (int l = blockIdx.y; l < n; l += gridDim.y) {
+  for (int l = blockIdx.y; l < m; l += gridDim.y) {
     const double* col = R + (long)(2 * l) * ldr;
     X[i + (long)l * ldx] = make_double2(col[i], col[n + i]);
   }
@@ -114,9 +114,11 @@ __global__ __launch_bounds__(256) void herm_combine_kernel(int n, int k2, int k,
 
 }  // namespace
 
-hipError_t herm_extract_pairs(int n, const double* R, long ldr, void* X, long ldx, hipStream_t s) {
-  hipLaunchKernelGGL(herm_extract_pairs_kernel, dim3(ceil_div(n, 256), n < 4096 ? n : 4096),
-                     dim3(256), 0, s, n, R, ldr, (double2*)X, ldx);
+hipError_t herm_extract_pairs(int n, int m, const double* R, long ldr, void* X, long ldx,
+                              hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(herm_extract_pairs_kernel, dim3(ceil_div(n, 256), m < 4096 ? m : 4096),
+                     dim3(256), 0, s, n, m, R, ldr, (double2*)X, ldx);
   return hipGetLastError();
 }
 

@@ -191,10 +191,11 @@ hipError_t herm_embed(int n, const void* A, long lda, double* R, long ldr, hipSt
 hipError_t herm_extract(int n, const double* R, long ldr, void* X, long ldx, hipStream_t s);
 hipError_t herm_pair_eval(int n, const double* lam2, double* eval, hipStream_t s);
 // Eigenvectors: herm_extract_pairs reads X[:, l] = x + i y from real column 2l
-// ([x; y]); herm_jmul forms J Q = [-Q_y; Q_x] for k2 columns (J: the real form
+// ([x; y]) for l < m; herm_jmul forms J Q = [-Q_y; Q_x] for k2 columns (J: the real form
 // of multiplication by i); herm_combine forms X[:, a] = sum_j (x_j + i y_j) c[j, a]
 // for a complex k2 x k coefficient matrix c (device, interleaved).
-hipError_t herm_extract_pairs(int n, const double* R, long ldr, void* X, long ldx, hipStream_t s);
+hipError_t herm_extract_pairs(int n, int m, const double* R, long ldr, void* X, long ldx,
+                              hipStream_t s);
 hipError_t herm_jmul(int n, int k2, const double* Q, long ldq, double* JQ, long ldj,
                      hipStream_t s);
 hipError_t herm_combine(int n, int k2, int k, const double* Q, long ldq, const void* c, void* X,

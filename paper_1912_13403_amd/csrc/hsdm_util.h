@@ -7,6 +7,12 @@ hipError_t dev_fill(double* a, long lda, int m, int n, double v, hipStream_t s);
 hipError_t dev_copy(const double* a, long lda, double* b, long ldb, int m, int n, hipStream_t s);
 hipError_t dev_sym_full(const double* a, long lda, double* b, long ldb, int n, hipStream_t s);
 hipError_t dev_mirror_lower(double* a, long lda, int n, hipStream_t s);
+// out[0] += 64-bit content hash of the lower triangle of a (n x n; cplx:
+// interleaved complex, lda in complex elements); dev_hash_clear zeroes
+// out[0 .. cnt-1] first (a kernel, not a memset, so that it can be captured).
+hipError_t dev_hash_clear(unsigned long long* out, int cnt, hipStream_t s);
+hipError_t dev_hash_lower(const void* a, long lda, int n, int cplx, unsigned long long* out,
+                          hipStream_t s);
 hipError_t dev_norm1_sym(const double* a, long lda, int n, double* colsum, double* out,
                          hipStream_t s);
 

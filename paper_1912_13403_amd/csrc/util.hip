@@ -3,6 +3,8 @@
 #include "hsdm_internal.h"
 #include "hsdm_util.h"
 
+#include <algorithm>
+
 namespace {
 
 __global__ void fill_kernel(double* a, long lda, int m, int n, double v) {
@@ -92,6 +94,46 @@ __global__ void max_kernel(const double* x, int n, double* out) {
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// 64-bit content hash of the lower triangle of a (real: double; complex:
+// interleaved pairs, the imaginary part of the diagonal left out, as the
+// solvers never read it).  Every element contributes mix(bits + position *
+// odd constant) and the contributions are added with wrap-around, an
+// order-free sum, so the result does not depend on the launch shape.  Used
+// to tell whether a cached factorization belongs to the S passed now.
+HSDM_DEV unsigned long long mix64(unsigned long long x) {
+  x ^= x >> 30;
+  x *= 0xBF58476D1CE4E5B9ull;
+  x ^= x >> 27;
+  x *= 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return x;
+}
+
+__global__ void hash_clear_kernel(unsigned long long* out, int cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) out[i] = 0ull;
+}
+
+__global__ void hash_lower_kernel(const double* a, long lda, int n, int cplx,
+                                  unsigned long long* out) {
+  const int per = cplx ? 2 : 1;
+  unsigned long long acc = 0ull;
+  for (int j = blockIdx.y; j < n; j += gridDim.y) {
+    const long rows = (long)(n - j) * per;  // values of column j from row j down
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < rows;
+         t += (long)gridDim.x * blockDim.x) {
+      const long i = j + t / per;
+      const int part = (int)(t % per);
+      if (cplx && part == 1 && i == j) continue;
+      const double v = a[(i + (long)j * lda) * per + part];
+      const unsigned long long pos = (unsigned long long)((i + (long)j * n) * per + part);
+      acc += mix64((unsigned long long)__double_as_longlong(v) + pos * 0x9E3779B97F4A7C15ull);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
+}
+
 inline unsigned grid_for(long tot) {
   long g = (tot + 255) / 256;
   if (g > 65536) g = 65536;
@@ -133,5 +175,21 @@ hipError_t dev_norm1_sym(const double* a, long lda, int n, double* colsum, doubl
   hipLaunchKernelGGL(colsum_kernel, dim3(n), dim3(256), 0, s, a, lda, n, colsum);
   HSDM_TRY(hipGetLastError());
   hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, s, colsum, n, out);
+  return hipGetLastError();
+}
+
+hipError_t dev_hash_clear(unsigned long long* out, int cnt, hipStream_t s) {
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hash_clear_kernel, dim3(ceil_div(cnt, 256)), dim3(256), 0, s, out, cnt);
+  return hipGetLastError();
+}
+
+hipError_t dev_hash_lower(const void* a, long lda, int n, int cplx, unsigned long long* out,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long rows = (long)n * (cplx ? 2 : 1);
+  const unsigned gx = (unsigned)std::min<long>(ceil_div(rows, 256), 16);
+  hipLaunchKernelGGL(hash_lower_kernel, dim3(gx, std::min(n, 32768)), dim3(256), 0, s, (const double*)a, lda, n,
+                     cplx, out);
   return hipGetLastError();
 }

@@ -13,8 +13,10 @@ calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import torch
 
@@ -33,6 +35,7 @@ HSDM_KEY_FCUT = 2
 HSDM_KEY_DEG_TOL = 3
 HSDM_KEY_TIMING = 4
 HSDM_KEY_STREAMS = 5
+HSDM_KEY_N_STATES = 6
 
 EXPORTED = [
     "hsdm_init", "hsdm_finalize", "hsdm_reinit", "hsdm_set_real", "hsdm_set_int",
@@ -149,6 +152,21 @@ def hsdm_task_bytes(n: int, is_complex: bool) -> float:
     return float(load_library().hsdm_task_bytes(int(n), int(bool(is_complex))))
 
 
+_live_handles = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_handles():
+    """Finalize every handle still open when the interpreter exits, while the
+    HIP runtime and torch are still up (interpreter-exit garbage collection
+    would otherwise run hsdm_finalize in whatever order objects die)."""
+    for h in list(_live_handles):
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
 class Handle:
     """An hsdm_handle bound to one GPU (hsdm_init / hsdm_finalize)."""
 
@@ -163,6 +181,8 @@ class Handle:
             raise HsdmError(st, "hsdm_init failed")
         self._h = h
         self._lib = lib
+        self.n_states = 0
+        _live_handles.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -193,6 +213,12 @@ class Handle:
 
     def hsdm_set_int(self, key, value):
         self._check(self._lib.hsdm_set_int(self._h, key, int(value)))
+        if key == HSDM_KEY_N_STATES:
+            self.n_states = int(value)
+
+    def _ncols(self, n):
+        """Eigenvector columns an eigenpair solve of size n writes."""
+        return self.n_states if 0 < self.n_states < n else n
 
     def hsdm_reinit(self):
         self._check(self._lib.hsdm_reinit(self._h))
@@ -220,7 +246,7 @@ class Handle:
         H, S = _colmajor(H), _colmajor(S)
         n = H.shape[0]
         w = torch.empty(n, dtype=torch.float64, device=self.device)
-        C = empty_colmajor(n, n, self.device)
+        C = empty_colmajor(n, self._ncols(n), self.device)
         self._check(self._lib.hsdm_solve_ev_real(self._h, n, H.data_ptr(), _ld(H), S.data_ptr(),
                                                  _ld(S), w.data_ptr(), C.data_ptr(), _ld(C),
                                                  _stream_ptr(self.device)))
@@ -245,11 +271,12 @@ class Handle:
         return dict(D=D, E=E, eval=w, mu=mu.value, band_energy=eb.value)
 
     def hsdm_solve_ev_complex(self, H, S):
-        """All eigenpairs of a Hermitian pencil: (eval, C) with C^H S C = I."""
+        """Eigenpairs of a Hermitian pencil: (eval, C) with C^H S C = I (C holds
+        the lowest n_states vectors when HSDM_KEY_N_STATES is set)."""
         H, S = _colmajor_c(H), _colmajor_c(S)
         n = H.shape[0]
         w = torch.empty(n, dtype=torch.float64, device=self.device)
-        C = empty_colmajor_c(n, n, self.device)
+        C = empty_colmajor_c(n, self._ncols(n), self.device)
         self._check(self._lib.hsdm_solve_ev_complex(self._h, n, H.data_ptr(), _ld(H), S.data_ptr(),
                                                     _ld(S), w.data_ptr(), C.data_ptr(), _ld(C),
                                                     _stream_ptr(self.device)))

@@ -193,3 +193,31 @@ def test_solve_ev_complex_degenerate_levels(torch_dev, h):
     h.hsdm_reinit()
     w2, C2 = h.hsdm_solve_ev_complex(_g(torch_dev, Z), _g(torch_dev, S2))
     _check_ev_complex(Z, S2, _c(w2), _c(C2), np.zeros(24))
+
+
+@pytest.mark.parametrize("case,n,ns", [("kpoint", 150, 23), ("ring", 64, 7), ("ring", 64, 8)])
+def test_solve_ev_complex_n_states(oracle, torch_dev, h, case, n, ns):
+    """HSDM_KEY_N_STATES for Hermitian pencils: the lowest ns complex vectors
+    (the flux-free ring has degenerate pairs, so ns = 7 cuts a pair: the
+    vector kept must still be an S-orthonormal eigenvector)."""
+    from paper_1912_13403_amd import hsdm
+    if case == "kpoint":
+        H, _, S = inputs.kpoint_problem(6, n=n)
+        w_ref = oracle.solve_dm_complex(H, S, 0.2 * n, 0.01, f_max=1.0)["eval"]
+    else:
+        H, S = inputs.ring_flux(n, 0.0)
+        w_ref = np.sort(-2.0 * np.cos(2.0 * np.pi * np.arange(n) / n))
+    h.hsdm_set_int(hsdm.HSDM_KEY_N_STATES, ns)
+    try:
+        h.hsdm_reinit()
+        w, C = h.hsdm_solve_ev_complex(_g(torch_dev, H), _g(torch_dev, S))
+    finally:
+        h.hsdm_set_int(hsdm.HSDM_KEY_N_STATES, 0)
+    assert tuple(C.shape) == (n, ns)
+    w, C = _c(w), _c(C)
+    Hf, Sf = _herm(H), _herm(S)
+    scale = max(_norm1(H), 1.0)
+    assert np.max(np.abs(w - w_ref)) <= 1e-10 * scale
+    res = Hf @ C - (Sf @ C) * w[:ns]
+    assert np.max(np.abs(res).sum(axis=0)) / (n * scale) <= 1e-12
+    assert np.max(np.abs(C.conj().T @ Sf @ C - np.eye(ns))) <= 1e-12 * n

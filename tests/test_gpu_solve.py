@@ -189,3 +189,85 @@ def test_partial_last_panel_after_larger_solves(oracle, torch_dev, h):
         ref = oracle.solve_dm(H, S, ne, kT)
         err = np.max(np.abs(_c(r["D"]) - ref["D"]))
         assert err <= 1e-9, f"n={n}: |dD| = {err:.3e}"
+
+
+def test_s_cache_follows_content_without_reinit(oracle, torch_dev, h):
+    """The factor cache is keyed by the content of S, never by its address:
+    S overwritten in place, and row-major inputs that the binding copies into
+    temporaries (freed after each call, so the next copy of the same size
+    usually lands at the same address), are solved correctly without
+    hsdm_reinit."""
+    torch, dev = torch_dev
+    n = 180
+    probs = [inputs.sized_problem(n, cfg=1700 + k) for k in range(3)]
+    refs = [oracle.solve_dm(H, S, 90.0, 0.01) for H, S in probs]
+    h.hsdm_reinit()
+    Hg = _g(torch_dev, probs[0][0])
+    Sg = _g(torch_dev, probs[0][1])
+    for k in (0, 1, 2, 0):
+        Hg.copy_(_g(torch_dev, probs[k][0]))
+        Sg.copy_(_g(torch_dev, probs[k][1]))
+        r = h.hsdm_solve_dm_real(Hg, Sg, 90.0, 0.01)
+        assert np.max(np.abs(_c(r["D"]) - refs[k]["D"])) <= 1e-9, f"in place, problem {k}"
+    for k in (1, 2, 1, 0):
+        H, S = probs[k]
+        Hc = torch.from_numpy(np.ascontiguousarray(H)).to(dev)  # row-major: copied
+        Sc = torch.from_numpy(np.ascontiguousarray(S)).to(dev)
+        assert Sc.stride() == (n, 1)
+        r = h.hsdm_solve_dm_real(Hc, Sc, 90.0, 0.01)
+        del Hc, Sc
+        assert np.max(np.abs(_c(r["D"]) - refs[k]["D"])) <= 1e-9, f"row-major, problem {k}"
+    # one matrix in two buffers: the cached factor serves both
+    h.hsdm_reinit()
+    S_a = _g(torch_dev, probs[2][1])
+    S_b = S_a.clone()
+    r_a = h.hsdm_solve_dm_real(_g(torch_dev, probs[2][0]), S_a, 90.0, 0.01)
+    r_b = h.hsdm_solve_dm_real(_g(torch_dev, probs[2][0]), S_b, 90.0, 0.01)
+    assert torch.equal(r_a["D"], r_b["D"])
+
+
+def test_group_s_cache_follows_content(oracle, torch_dev, h):
+    """Task contexts of the multi-task solve keep their factors across calls;
+    an S buffer overwritten with another matrix between calls (no reinit)
+    must not find the old factor."""
+    torch, dev = torch_dev
+    sizes = [150, 150, 90]
+    probs = [[inputs.sized_problem(n, cfg=1800 + 10 * k + p) for p, n in enumerate(sizes)]
+             for k in range(2)]
+    Hg = [_g(torch_dev, H) for H, _ in probs[0]]
+    Sg = [_g(torch_dev, S) for _, S in probs[0]]
+    for k in (0, 1, 0):
+        for p in range(len(sizes)):
+            Hg[p].copy_(_g(torch_dev, probs[k][p][0]))
+            Sg[p].copy_(_g(torch_dev, probs[k][p][1]))
+        tasks = [dict(H=Hg[p], S=Sg[p], n_electrons=sizes[p] / 2.0, kT=0.01, f_max=2.0)
+                 for p in range(len(sizes))]
+        outs = h.hsdm_solve_dm_group(tasks)
+        for p, o in enumerate(outs):
+            H, S = probs[k][p]
+            ref = oracle.solve_dm(H, S, sizes[p] / 2.0, 0.01)
+            assert np.max(np.abs(_c(o["D"]) - ref["D"])) <= 1e-9, f"call {k}, task {p}"
+
+
+@pytest.mark.parametrize("n,ns", [(300, 37), (300, 300), (129, 1), (200, 500)])
+def test_n_states_real(oracle, torch_dev, h, n, ns):
+    """HSDM_KEY_N_STATES: every eigenvalue, the lowest ns vectors (ns >= n
+    means all)."""
+    from paper_1912_13403_amd import hsdm
+    H, S = inputs.sized_problem(n, cfg=1900 + ns)
+    h.hsdm_set_int(hsdm.HSDM_KEY_N_STATES, ns)
+    try:
+        w, C = h.hsdm_solve_ev_real(_g(torch_dev, H), _g(torch_dev, S))
+    finally:
+        h.hsdm_set_int(hsdm.HSDM_KEY_N_STATES, 0)
+    m = min(ns, n)
+    assert tuple(C.shape) == (n, m)
+    w_ref, C_ref = oracle.solve_ev(H, S)
+    w, C = _c(w), _c(C)
+    Hf, Sf = _sym(H), _sym(S)
+    scale = oracle.norm1(H)
+    assert np.max(np.abs(w - w_ref)) <= 1e-10 * scale
+    res = Hf @ C - (Sf @ C) * w[:m]
+    assert np.max(np.abs(res).sum(axis=0)) / (n * scale) <= 1e-12
+    assert np.max(np.abs(C.T @ Sf @ C - np.eye(m))) <= 1e-12 * n
+    assert np.max(np.abs(C @ C.T - C_ref[:, :m] @ C_ref[:, :m].T)) <= 1e-9
