@@ -71,15 +71,17 @@ def make_inputs(name, dev):
 
 
 def cpu_baseline(target_n: int):
-    """Time the FP64 oracle on a bounded sample of the same workload and
-    scale it by n^3 to the benchmarked size."""
+    """Time the FP64 oracle on a bounded sample of the workload -- the n=4096
+    problem drawn with the n=16384 recipe (decay 128, S perturbation 0.05,
+    N_e = n/2, kT = 0.005), all host cores -- and project it by n^3 to the
+    benchmarked size (the oracle at n = 16384 would take most of an hour)."""
     from oracle import oracle as O
     from paper_1912_13403_amd import inputs
 
-    ns = 2560
-    H, S = inputs.real_problem(ns, 128.0, 0.05, cfg=2)
+    H, S, p = inputs.config_problem("cfg2sub_n4096")
+    ns = p["n"]
     t0 = time.perf_counter()
-    O.solve_dm(H, S, ns / 2.0, 0.005)
+    O.solve_dm(H, S, p["n_electrons"], p["kT"], f_max=p["f_max"])
     dt = time.perf_counter() - t0
     scale = (target_n / ns) ** 3
     return {
@@ -87,11 +89,54 @@ def cpu_baseline(target_n: int):
         "unit": "s",
         "cores": O.num_threads(),
         "kind": "oracle",
+        "projection": True,
         "sample": (f"oracle solve_dm on the n={ns} problem of the n={target_n} recipe "
                    f"(decay 128, S perturbation 0.05, N_e={ns // 2}, kT=0.005) took "
-                   f"{dt:.2f} s; value = that time x (n/{ns})^3"),
+                   f"{dt:.2f} s on {O.num_threads()} threads; value = that time x "
+                   f"(n/{ns})^3, a projection"),
         "sample_seconds": dt,
     }
+
+
+def oracle_timing():
+    """The oracle on the small configurations, single-threaded and on all
+    host cores (one subprocess per run, so that the thread count is fixed
+    before OpenMP starts); one JSON line."""
+    import platform
+    import subprocess
+
+    code = ("import sys, time, json; sys.path.insert(0, %r)\n"
+            "from oracle import oracle as O\n"
+            "from paper_1912_13403_amd import inputs\n"
+            "H, S, p = inputs.config_problem(sys.argv[1])\n"
+            "O.num_threads()\n"
+            "t = time.perf_counter()\n"
+            "O.solve_dm(H, S, p['n_electrons'], p['kT'], f_max=p['f_max'])\n"
+            "print(json.dumps({'s': time.perf_counter() - t, 'threads': O.num_threads()}))\n"
+            % ROOT)
+    ncpu = os.cpu_count() or 1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    runs = []
+    for name in ("cfg0_n512", "cfg1_n4096", "cfg2sub_n4096"):
+        for threads in (1, ncpu):
+            env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+            r = subprocess.run([sys.executable, "-c", code, name], env=env, capture_output=True,
+                               text=True, check=True)
+            rec = json.loads(r.stdout.strip().splitlines()[-1])
+            runs.append({"config": name, "threads": rec["threads"], "seconds": rec["s"]})
+            print(f"[oracle-timing] {name} threads={rec['threads']}: {rec['s']:.2f} s",
+                  file=sys.stderr, flush=True)
+    print(json.dumps({"oracle_timing": runs, "nproc": ncpu, "cpu_model": model,
+                      "machine": platform.machine(),
+                      "build": "gcc -O3 -march=x86-64-v3 -fopenmp -ffp-contract=off"}))
 
 
 # source file of each timed kernel (a stored traffic measurement is only used
@@ -140,31 +185,54 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
 
 
-def roofline(stats, workload, steps):
+def roofline(stats, workload, steps, chain=None):
     """Roofline of the kernel with the largest total time in the timed steps:
     algorithmic flops (or bytes) per launch over the mean launch time from the
-    HIP events recorded around every launch."""
+    HIP events recorded around every launch.  `chain`: task steps on the
+    critical path of one bulge-chasing launch (its per-task period is
+    reported beside the fractions)."""
     name = max(stats, key=lambda k: stats[k]["ms"])
     st = stats[name]
     per_launch_s = st["ms"] * 1e-3 / st["launches"]
     # the bulge chasing and the panel QR do vector work on data that one
-    # launch streams once (the band, the panel): measured against HBM with
-    # their algorithmic bytes; the GEMM-shaped kernels against the matrix cores
+    # launch must stream once (the band in and the reflectors out; the
+    # panel): measured against HBM with those algorithmic bytes, their FP64
+    # rate beside it; the GEMM-shaped kernels against the matrix cores
     by_bytes = name.startswith(("sb2st", "panel_qr")) or st["flops"] <= 0
     tflops = st["flops"] / st["launches"] / per_launch_s / 1e12
+    algo_bytes = st["bytes"] / st["launches"]
     if by_bytes:
-        achieved = st["bytes"] / st["launches"] / per_launch_s / 1e9
+        achieved = algo_bytes / per_launch_s / 1e9
         peak, unit, bound = HBM_PEAK_GBS, "GB/s", "hbm"
     else:
         achieved = tflops
         peak, unit, bound = FP64_PEAK_TFLOPS, "TFLOP/s", "mfma"
-    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": stored_traffic(workload, name),
-            "kernel": name, "launches_per_step": st["launches"] / steps,
-            "mean_launch_ms": 1e3 * per_launch_s,
-            "algorithmic_flops_per_launch": st["flops"] / st["launches"],
-            "algorithmic_bytes_per_launch": st["bytes"] / st["launches"],
-            "fp64_tflops": tflops}
+    traffic = stored_traffic(workload, name)
+    out = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+           "frac": achieved / peak, "traffic": traffic,
+           "traffic_over_algorithmic": (traffic / algo_bytes) if traffic and algo_bytes > 0
+           else None,
+           "kernel": name, "launches_per_step": st["launches"] / steps,
+           "mean_launch_ms": 1e3 * per_launch_s,
+           "algorithmic_flops_per_launch": st["flops"] / st["launches"],
+           "algorithmic_bytes_per_launch": algo_bytes,
+           "fp64_tflops": tflops, "fp64_frac": tflops / FP64_PEAK_TFLOPS}
+    if chain and name.startswith("sb2st"):
+        out["chain_task_steps"] = chain
+        out["task_period_us"] = 1e6 * per_launch_s / chain
+    return out
+
+
+def phase_table(phases_ms, phase_flops):
+    """Per-phase algorithmic flops (the method's counts), rate and fraction of
+    the FP64 matrix-core peak."""
+    out = {}
+    for k, ms in phases_ms.items():
+        fl = phase_flops.get(k, 0.0)
+        tf = fl / (ms * 1e-3) / 1e12 if ms > 0 and fl > 0 else None
+        out[k] = {"ms": ms, "algorithmic_flops": fl, "tflops": tf,
+                  "frac_fp64_peak": (tf / FP64_PEAK_TFLOPS) if tf is not None else None}
+    return out
 
 
 def batch_cpu_baseline(sizes):
@@ -383,6 +451,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-warm", action="store_true",
                     help="skip the extra solve with the S factor cached")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="time the CPU oracle on the small configurations, one thread and all "
+                         "host cores, and print that record instead of a benchmark")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 2 GiB (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters of a profiled run)")
@@ -391,6 +462,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
+    if args.oracle_timing:
+        return oracle_timing()
     if args.config in ("cfg3_batch", "cfg4_serving"):
         # read by the HIP runtime when it starts (the first device call)
         if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < MT_QUEUES:
@@ -446,7 +519,7 @@ def main():
                 h.hsdm_set_int(hsdm.HSDM_KEY_TIMING, 3)
         print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    times, phases, kstats = [], [], []
+    times, phases, pflops, kstats = [], [], [], []
     t_all = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
@@ -454,6 +527,7 @@ def main():
         torch.cuda.synchronize()
         times.append(time.perf_counter() - ts)
         phases.append(h.phase_times())
+        pflops.append(h.phase_flops())
         kstats.append(h.kernel_stats())
         print(f"[bench] step {i}: {times[-1]:.3f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -480,7 +554,9 @@ def main():
             a = agg.setdefault(k, {"ms": 0.0, "flops": 0.0, "bytes": 0.0, "launches": 0})
             for f in a:
                 a[f] += v[f]
-    roof = roofline(agg, args.config, args.steps)
+    B = 32
+    chain = 2 * max(n - 2, 0) + (n - 1 + B - 1) // B
+    roof = roofline(agg, args.config, args.steps, chain=chain)
     # per-kernel table: every launch timed (the calibration step when there
     # is one, else the timed steps)
     table, tsteps = (calib, 1) if calib else (agg, args.steps)
@@ -507,6 +583,7 @@ def main():
                    "n": n, "n_electrons": p["n_electrons"], "kT": p["kT"], "m_occupied": m},
         "roofline": roof,
         "phases_ms": ph,
+        "phases": phase_table(ph, pflops[-1]),
         "dominant_phase": max(ph, key=lambda k: ph[k]),
         "kernels": kernels,
         "warm_s_factor_s": warm,

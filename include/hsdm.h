@@ -264,6 +264,15 @@ int hsdm_status_detail(hsdm_handle h);
  * of phases written (at most cap). */
 int hsdm_phase_times(hsdm_handle h, double *times, int cap);
 const char *hsdm_phase_name(int i);
+/* Algorithmic FP64 flops of the phases of the last single solve when
+ * HSDM_KEY_TIMING is on, in the order of hsdm_phase_name(i): the counts of
+ * the method, not of this library's extra work -- Cholesky n^3/3 (0 when the
+ * factor of S was cached), standard form n^3, full -> band 4n^3/3, band ->
+ * tridiagonal 6 b n^2, divide and conquer the merge products at their sizes
+ * after deflation, back-transforms 2n^2 m, 2n^2 m and n^2 m, D and E n^2 m
+ * each (m: eigenvectors formed).  Multi-task solves write zeros.  Returns
+ * the number of phases written (at most cap). */
+int hsdm_phase_flops(hsdm_handle h, double *flops, int cap);
 
 /* Per-kernel totals of the last solve when HSDM_KEY_TIMING is 2 or 3 (HIP events
  * recorded around each launch on the solve's stream; the solve synchronizes

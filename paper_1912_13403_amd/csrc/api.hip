@@ -134,6 +134,11 @@ struct hsdm_ctx {
   hipEvent_t ev[NPHASE + 1] = {};
   double phase_ms[NPHASE] = {};
   bool phase_done[NPHASE] = {};
+  // algorithmic work of the last single solve's phases (timing on)
+  double phase_flops[NPHASE] = {};
+  int last_kind = 0;          // 1: density-matrix solve, 2: eigenpair solve
+  int last_n = 0, last_ns = 0;
+  bool last_factored = false;
 };
 
 namespace {
@@ -375,6 +380,28 @@ void mark(hsdm_ctx* h, int phase, hipStream_t s) {
   }
 }
 
+// Algorithmic flops of each phase of the last single solve (the counts of the
+// method, not of this implementation's extra work): Cholesky n^3/3 (when S
+// was factored), standard form n^3, full -> band 4n^3/3, band ->
+// tridiagonal 6 B n^2, divide and conquer the merge products at their sizes
+// after deflation (read back from the device), the back-transforms 2 n^2 m,
+// 2 n^2 m and n^2 m, D and E n^2 m each, with m the vectors formed.
+void phase_work(hsdm_ctx* h) {
+  for (int p = 0; p < NPHASE; p++) h->phase_flops[p] = 0.0;
+  if (!h->last_kind || h->last_n <= 0) return;
+  const double n = h->last_n;
+  const double m = h->last_kind == 1 ? (double)h->host->occ.m : (double)h->last_ns;
+  h->phase_flops[0] = h->last_factored ? n * n * n / 3.0 : 0.0;
+  h->phase_flops[1] = n * n * n;
+  h->phase_flops[2] = 4.0 * n * n * n / 3.0;
+  h->phase_flops[3] = sb2st_algo_flops(h->lay);
+  h->phase_flops[4] = h->plan ? stedc_last_flops(h->plan) : 0.0;
+  h->phase_flops[5] = 2.0 * n * n * m;
+  h->phase_flops[6] = 2.0 * n * n * m;
+  h->phase_flops[7] = n * n * m;
+  h->phase_flops[8] = h->last_kind == 1 ? 2.0 * n * n * m : 0.0;
+}
+
 int finish(hsdm_ctx* h, hipStream_t s) {
   DEV_TRY(h, hipMemcpyAsync(&h->host->st, h->st, sizeof(DevStatusWord), hipMemcpyDeviceToHost, s));
   DEV_TRY(h, hipMemcpyAsync(&h->host->occ, h->occ, sizeof(OccOut), hipMemcpyDeviceToHost, s));
@@ -391,6 +418,7 @@ int finish(hsdm_ctx* h, hipStream_t s) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, h->ev[p], h->ev[p + 1]) == hipSuccess) h->phase_ms[p] = ms;
     }
+    phase_work(h);
   }
   const int code = h->host->st.code;
   h->detail = h->host->st.detail;
@@ -463,7 +491,9 @@ int s_key(hsdm_ctx* h, const void* S, int n, int lds, bool cplx, SKey& key, hipS
 // Cholesky + inverse of the real symmetric S (n x n, lower) into the cache,
 // skipped when the cache holds the factor of the S that `key` names.
 int factor_s(hsdm_ctx* h, int n, const double* S, int lds, const SKey& key, hipStream_t s) {
+  h->last_factored = false;
   if (s_cached(h, key)) return HSDM_OK;
+  h->last_factored = true;
   DEV_TRY(h, dev_copy(S, lds, h->Lbuf, n, n, n, s));
   DEV_TRY(h, dev_fill(h->Linv, n, n, n, 0.0, s));
   DEV_TRY(h, chol_inv(n, h->Lbuf, n, h->Linv, n, h->Abuf, n, h->st, s));
@@ -664,6 +694,13 @@ int hsdm_phase_times(hsdm_handle h, double* times, int cap) {
 
 const char* hsdm_phase_name(int i) { return (i >= 0 && i < NPHASE) ? kPhaseNames[i] : ""; }
 
+int hsdm_phase_flops(hsdm_handle h, double* flops, int cap) {
+  if (!h || !flops) return 0;
+  int k = cap < NPHASE ? cap : NPHASE;
+  for (int i = 0; i < k; i++) flops[i] = h->phase_flops[i];
+  return k;
+}
+
 int hsdm_kernel_count(hsdm_handle h) { return h ? kt_count(h->kt) : 0; }
 
 const char* hsdm_kernel_stat(hsdm_handle h, int i, double* out) {
@@ -857,6 +894,8 @@ static int dm_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S
                    hipStream_t s) {
   int r;
   for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
+  h->last_kind = 1;
+  h->last_n = n;
   hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
   mark(h, 0, s);
@@ -897,6 +936,9 @@ static int ev_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S
                    const SKey& key, double* eval, double* C, int ldc, int ns, hipStream_t s) {
   int r;
   for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
+  h->last_kind = 2;
+  h->last_n = n;
+  h->last_ns = ns;
   hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
   const int* m_dev = nullptr;
@@ -1319,6 +1361,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
   KtScope kts(h);
   Lanes lanes{h, s, nl};
   for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
+  h->last_kind = 0;
   h->h_tasks.assign(nt, OccTask{});
   DEV_TRY(h, lanes.fork());
   // 1. every task: factor, standard form
@@ -1406,9 +1449,8 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
                              c->lay.nsweep, in_launch, w};
       for (int q = 0; q < w; q++) h->h_wgmap.push_back(p);
       in_launch += w;
-      const double nn = (double)c->lay.n * c->lay.n;
-      fl.back() += 6.0 * BAND * nn;
-      by.back() += 12.0 * BAND * nn;
+      fl.back() += sb2st_algo_flops(c->lay);
+      by.back() += sb2st_algo_bytes(c->lay);
     }
     first.push_back(nt);
     const size_t tb = sizeof(Sb2stTask) * nt;

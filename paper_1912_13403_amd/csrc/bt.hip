@@ -365,9 +365,11 @@ Bt2Task bt2_task(const Sb2stLayout& L, const double* F2, const long* d_goff, dou
 }
 
 double bt2_flops(const Sb2stLayout& L, int m) {
-  // per group and column of Z: V^T z (B^2 multiply-adds on the parallelogram),
-  // T w (B(B+1)/2) and z - V w (B^2)
-  return 2.0 * (double)L.ngroups * (2.0 * B * B + 0.5 * B * (B + 1)) * m;
+  // algorithmic: each of the B reflectors of a group (length B) applied to a
+  // column of Z is 4 B flops (about 2 n^2 m in all); the product with the
+  // block reflector's triangular factor T is this kernel's own extra work
+  // and is not counted
+  return 4.0 * (double)L.ngroups * B * B * m;
 }
 
 hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff, double* Z,

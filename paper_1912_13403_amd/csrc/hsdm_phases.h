@@ -115,6 +115,9 @@ hipError_t sb2st_prepare(const Sb2stLayout& L, double* V2, double* tau2, int* pr
 hipError_t sb2st_finish(const Sb2stLayout& L, const double* AB, int ldab, double* d, double* e,
                         hipStream_t s);
 int sb2st_group_nwg(const Sb2stLayout& L);
+// algorithmic flops and HBM bytes of one band's reduction (timer records)
+double sb2st_algo_flops(const Sb2stLayout& L);
+double sb2st_algo_bytes(const Sb2stLayout& L);
 hipError_t sb2st_group_launch(const Sb2stTask* d_tasks, const int* d_wg_task, int total_wg,
                               double flops, double bytes, hipStream_t s);
 
@@ -173,6 +176,10 @@ hipError_t bt1_apply(int n, int B, const double* Vst, long ldv, const double* T1
 // callback).
 struct StedcPlan;
 StedcPlan* stedc_plan_create(int n);
+// Flops of the merge products of the last stedc_run on this plan (2 m n k
+// per product, from the sizes the device wrote after deflation); reads the
+// device descriptors, so the run's stream must have been synchronized.
+double stedc_last_flops(const StedcPlan* p);
 void stedc_plan_destroy(StedcPlan* p);
 size_t stedc_scratch_doubles(int n);
 size_t stedc_iscratch_ints(int n);

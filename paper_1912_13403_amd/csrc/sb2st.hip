@@ -496,6 +496,17 @@ hipError_t sb2st_finish(const Sb2stLayout& L, const double* AB, int ldab, double
   return hipGetLastError();
 }
 
+// Algorithmic work of one band: about 6 B n^2 flops; HBM bytes that the
+// reduction must move: the band in ((B + 1) n doubles), the stage-2
+// reflectors (B per group, B long) and their scalars out, d and e out.  The
+// band blocks each task rewrites stay on chip in the ideal schedule and are
+// not counted.
+double sb2st_algo_flops(const Sb2stLayout& L) { return 6.0 * L.B * (double)L.n * L.n; }
+double sb2st_algo_bytes(const Sb2stLayout& L) {
+  return 8.0 * ((L.B + 1.0) * L.n + (double)L.ngroups * L.B * L.B + (double)L.ngroups * L.B +
+                2.0 * L.n);
+}
+
 int sb2st_group_nwg(const Sb2stLayout& L) {
   if (L.nsweep <= 0) return 0;
   // A sweep trails its predecessor by two tasks, so the wavefront that
@@ -540,10 +551,7 @@ hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, doub
     // wavefront group; TW = nwg * WPB keeps that true for every round)
     void* args[] = {(void*)&n, (void*)&nsweep, (void*)&AB, (void*)&ldab, (void*)&V2,
                     (void*)&tau2, (void*)&d_goff, (void*)&progress, (void*)&st};
-    // algorithmic: about 6 B n^2 flops; each task reads and writes the lower
-    // half of its diagonal block and the block below (24 B^2 bytes), n^2 / 2B tasks
-    const double nn = (double)n * n;
-    kt_begin("sb2st_kernel<32>", 6.0 * L.B * nn, 12.0 * L.B * nn, 0, s, true);
+    kt_begin("sb2st_kernel<32>", sb2st_algo_flops(L), sb2st_algo_bytes(L), 0, s, true);
     HSDM_TRY(hipLaunchCooperativeKernel((const void*)sb2st_kernel<32>, dim3(nwg), dim3(64 * WPB),
                                         args, 0, s));
     kt_end(s);

@@ -833,3 +833,14 @@ hipError_t stedc_run(StedcPlan* p, const double* d, const double* e, double* lam
 }
 
 size_t stedc_iscratch_ints(int n) { return stedc_scratch_ints(n); }
+
+double stedc_last_flops(const StedcPlan* p) {
+  if (!p || p->nmerge <= 0) return 0.0;
+  std::vector<GemmDesc> h(2 * (size_t)p->nmerge);
+  if (hipMemcpy(h.data(), p->d_desc, sizeof(GemmDesc) * h.size(), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return -1.0;
+  double f = 0.0;
+  for (const GemmDesc& g : h) f += 2.0 * (double)g.m * g.n * g.k;
+  return f;
+}

@@ -45,7 +45,7 @@ EXPORTED = [
     "hsdm_cholesky_inverse", "hsdm_standard_form",
     "hsdm_tridiagonalize", "hsdm_tridiag_eigh", "hsdm_occupations", "hsdm_density",
     "hsdm_dgemm", "hsdm_status_string", "hsdm_last_error", "hsdm_status_detail",
-    "hsdm_phase_times", "hsdm_phase_name", "hsdm_kernel_count", "hsdm_kernel_stat",
+    "hsdm_phase_times", "hsdm_phase_name", "hsdm_phase_flops", "hsdm_kernel_count", "hsdm_kernel_stat",
     "hsdm_version",
 ]
 
@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH):
         "hsdm_status_detail": ([_vp], _i),
         "hsdm_phase_times": ([_vp, ctypes.POINTER(_d), _i], _i),
         "hsdm_phase_name": ([_i], ctypes.c_char_p),
+        "hsdm_phase_flops": ([_vp, ctypes.POINTER(_d), _i], _i),
         "hsdm_kernel_count": ([_vp], _i),
         "hsdm_kernel_stat": ([_vp, _i, ctypes.POINTER(_d)], ctypes.c_char_p),
         "hsdm_version": ([], _i),
@@ -226,6 +227,12 @@ class Handle:
     def phase_times(self):
         buf = (ctypes.c_double * 16)()
         k = self._lib.hsdm_phase_times(self._h, buf, 16)
+        return {self._lib.hsdm_phase_name(i).decode(): buf[i] for i in range(k)}
+
+    def phase_flops(self):
+        """Algorithmic flops of each phase of the last single solve (timing on)."""
+        buf = (ctypes.c_double * 16)()
+        k = self._lib.hsdm_phase_flops(self._h, buf, 16)
         return {self._lib.hsdm_phase_name(i).decode(): buf[i] for i in range(k)}
 
     def kernel_stats(self):
