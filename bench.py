@@ -495,9 +495,9 @@ def main():
           flush=True)
     h = hsdm.Handle(0)
     # The first warmup step times every launch (timing level 2) to find the
-    # dominant kernel; when that kernel is launched once per solve, the timed
-    # steps record events only around such kernels (level 3), so the many
-    # small launches of a solve carry no event overhead.
+    # dominant kernel; the timed steps then record events only around that
+    # kernel's launches, so the other launches of a solve carry no event
+    # overhead.
     h.hsdm_set_int(hsdm.HSDM_KEY_TIMING, 2)
     D = hsdm.empty_colmajor(n, n, dev)
     E = hsdm.empty_colmajor(n, n, dev)
@@ -509,14 +509,16 @@ def main():
         return h.hsdm_solve_dm_real(Hd, Sd, p["n_electrons"], p["kT"], out=out)
 
     calib = None
-    for i in range(args.warmup):
+    for i in range(max(1, args.warmup)):
         step()
         torch.cuda.synchronize()
         if i == 0:
             calib = h.kernel_stats()
             dom = max(calib.items(), key=lambda kv: kv[1]["ms"]) if calib else None
-            if dom is not None and dom[1]["launches"] == 1:
-                h.hsdm_set_int(hsdm.HSDM_KEY_TIMING, 3)
+            if dom is not None:
+                # the timed steps record events only around the dominant
+                # kernel's launches (and the nine phase boundaries)
+                h.hsdm_timing_kernel(dom[0])
         print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     times, phases, pflops, kstats = [], [], [], []

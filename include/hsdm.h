@@ -283,6 +283,11 @@ int hsdm_phase_flops(hsdm_handle h, double *flops, int cap);
  * out[3] = number of launches, all for the last solve. */
 int hsdm_kernel_count(hsdm_handle h);
 const char *hsdm_kernel_stat(hsdm_handle h, int i, double *out);
+/* Restrict the per-launch timing of HSDM_KEY_TIMING 2 and 3 to the launches
+ * of the kernel named `name` (as hsdm_kernel_stat names it; NULL or "" times
+ * every kernel again), so that one kernel can be timed in every launch with
+ * no events around the others.  Returns HSDM_OK or -1 (null handle). */
+int hsdm_timing_kernel(hsdm_handle h, const char *name);
 int hsdm_version(void);
 
 #ifdef __cplusplus

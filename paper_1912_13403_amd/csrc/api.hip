@@ -703,6 +703,12 @@ int hsdm_phase_flops(hsdm_handle h, double* flops, int cap) {
 
 int hsdm_kernel_count(hsdm_handle h) { return h ? kt_count(h->kt) : 0; }
 
+int hsdm_timing_kernel(hsdm_handle h, const char* name) {
+  if (!h) return -1;
+  kt_set_only(h->kt, name);
+  return HSDM_OK;
+}
+
 const char* hsdm_kernel_stat(hsdm_handle h, int i, double* out) {
   if (!h) return nullptr;
   return kt_stat(h->kt, i, out);

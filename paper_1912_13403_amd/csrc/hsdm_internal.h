@@ -104,6 +104,8 @@ void kt_begin(const char* name, double flops, double bytes, int nbound, hipStrea
               bool whole_phase = false);
 // Restrict a timer to the launches marked whole_phase (one launch per solve).
 void kt_set_whole_only(KTimer* k, bool on);
+// Restrict a timer to the launches of one kernel (nullptr or "": all).
+void kt_set_only(KTimer* k, const char* name);
 void kt_end(hipStream_t s);
 // Records made after kt_set_tag(t) carry tag t (-1: none); a solve of several
 // tasks tags each task's launches with its index.

@@ -100,7 +100,7 @@ hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, doub
 // (sb2st_group_nwg each) add up to at most SB2ST_MAX_WG, then sb2st_finish
 // (reads d and e off the band) for each.  d_tasks and d_wg_task are device
 // arrays: one Sb2stTask per band and the task index of each workgroup.
-constexpr int SB2ST_MAX_WG = 256;  // one 8-wavefront workgroup per compute unit
+constexpr int SB2ST_MAX_WG = 1024;  // four 2-wavefront workgroups per compute unit
 struct Sb2stTask {
   double* AB;  // ldab = 2B
   double* V2;

@@ -28,6 +28,7 @@ struct KTimer {
   std::vector<double> ms, flops, bytes;
   std::vector<long> launches;
   bool whole_only = false;  // record only launches marked whole-phase
+  std::string only;         // non-empty: record only launches of this kernel
   bool pending = false;     // the last kt_begin recorded an event
 };
 
@@ -78,6 +79,10 @@ void kt_set_whole_only(KTimer* k, bool on) {
   if (k) k->whole_only = on;
 }
 
+void kt_set_only(KTimer* k, const char* name) {
+  if (k) k->only = name ? name : "";
+}
+
 void kt_reset(KTimer* k) {
   if (!k) return;
   for (KtRec& r : k->recs) {
@@ -97,6 +102,7 @@ void kt_begin(const char* name, double flops, double bytes, int nbound, hipStrea
   if (!k) return;
   k->pending = false;
   if (k->whole_only && !whole_phase) return;
+  if (!k->only.empty() && k->only != name) return;
   auto it = k->ids.find(name);
   int id;
   if (it == k->ids.end()) {

@@ -14,12 +14,23 @@
 // pipeline, each two tasks behind its predecessor.
 //
 // One wavefront runs one sweep at a time (64 lanes; the two B x B blocks of
-// a task live in registers, sums over lanes use DPP and permlane swaps);
-// workgroups of 8 wavefronts are launched cooperatively so that every
-// wavefront is resident.  Consecutive sweeps run on consecutive wavefronts:
-// inside a workgroup the hand-off is a progress counter in LDS, between
-// workgroups a counter in global memory with agent-scope release/acquire;
-// every wait is bounded and reports through the status word if it runs out.
+// a task live in registers, sums over lanes use DPP and permlane swaps).
+// Workgroups of two wavefronts are launched cooperatively so that every
+// wavefront is resident; consecutive sweeps run on consecutive wavefronts,
+// so a workgroup holds two consecutive sweeps and the sweeps in flight (about
+// n / 2B of them, each two tasks behind its predecessor) spread over many
+// compute units, one or two per unit.  (Eight wavefronts per workgroup kept
+// all sweeps in flight on a few compute units, whose memory pipelines then
+// set the pace: 212 ms against 112 ms for n = 16384.)
+//
+// Every band load and store is an agent-scope relaxed atomic: written
+// through to, and read from, the memory side shared by all XCDs.  No L2 then
+// holds band data that another XCD would miss, or could write back over a
+// newer value later, so a hand-off needs no L2 write-back or invalidation:
+// the producer waits for its own stores to complete (s_waitcnt vmcnt(0)) and
+// raises a counter (in LDS inside a workgroup, in global memory between
+// workgroups), the consumer polls it and then loads.  Every wait is bounded
+// and reports through the status word if it runs out.
 //
 // Storage: lower band storage AB[(r-c) + c*ldab], ldab = 2B (offsets up to
 // 2B-1 hold the bulge).  Each reflector H_{s,t} (v, tau; v[0] = 1) is stored
@@ -30,7 +41,7 @@
 
 namespace {
 
-constexpr int WPB = 8;  // wavefronts per workgroup
+constexpr int WPB = 2;  // wavefronts per workgroup
 constexpr int DONE = 1 << 30;      // global counter of a finished sweep
 constexpr int KROUND = 1 << 20;    // LDS counters: KROUND * round + tasks done
 constexpr int KDONE = 1 << 19;     //   ... + KDONE once the sweep is finished
@@ -117,35 +128,6 @@ HSDM_DEV double bcast8(double v) {
   return join((unsigned)lo, (unsigned)hi);
 }
 
-// Sweep s waits for sweep s-1.  Consecutive sweeps run on the wavefronts of
-// one workgroup except across workgroup boundaries, so the hand-off uses
-// workgroup scope (no cache maintenance: the wavefronts share the CU's
-// caches) when both sweeps are in the same workgroup, agent scope otherwise.
-HSDM_DEV void wait_ge(int* p, int target, bool agent, DevStatusWord* st) {
-  // poll with relaxed loads; one acquire fence once the counter is reached
-  if ((threadIdx.x & 63) == 0) {
-    long spins = 0;
-    for (;;) {
-      const int v = agent ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                          : __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (v >= target) break;
-      ++spins;
-      if (spins > (1L << 27) ||
-          ((spins & 4095) == 0 &&
-           __hip_atomic_load(&st->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
-        dev_set_status(st, DS_SYNC_TIMEOUT, 2);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-  }
-  if (agent)
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  else
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  wave_sync();
-}
-
 // Hand-offs between the wavefronts of one workgroup: a counter in LDS.
 HSDM_DEV void wait_lds(int* p, int target, DevStatusWord* st) {
   long spins = 0;
@@ -160,20 +142,52 @@ HSDM_DEV void wait_lds(int* p, int target, DevStatusWord* st) {
   wave_sync();
 }
 
+// Band loads and stores: agent-scope relaxed atomics (sc1).
+HSDM_DEV double band_ld(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+HSDM_DEV void band_st(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// All of this wave's memory operations have completed before what follows.
+HSDM_DEV void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Sweep s waits for sweep s-1 on another workgroup: lane 0 polls the global
+// counter with agent-scope relaxed loads (they miss the compute unit's
+// cache); the band loads that follow are coherent by themselves, so a
+// workgroup-scope fence (ordering only) ends the wait.
+HSDM_DEV void wait_global(int* p, int target, DevStatusWord* st) {
+  if ((threadIdx.x & 63) == 0) {
+    long spins = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      ++spins;
+      if (spins > (1L << 27) ||
+          ((spins & 4095) == 0 &&
+           __hip_atomic_load(&st->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+        dev_set_status(st, DS_SYNC_TIMEOUT, 2);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  wave_sync();
+}
+
+// The wave's band stores are complete, then the counter is raised.
 HSDM_DEV void publish_lds(int* p, int v) {
   wave_sync();
+  stores_done();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   if ((threadIdx.x & 63) == 0) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-HSDM_DEV void publish(int* p, int v, bool agent) {
+HSDM_DEV void publish_global(int* p, int v) {
   wave_sync();
-  if ((threadIdx.x & 63) == 0) {
-    if (agent)
-      __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    else
-      __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-  }
+  stores_done();
+  if ((threadIdx.x & 63) == 0) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Reflector from x (x[0] = alpha, sig = sum of x[i]^2 over i >= 1):
@@ -239,7 +253,7 @@ HSDM_DEV void sb2st_body(int n, int nsweep, double* AB, int ldab, double* V2, do
     for (int t = 0; t < ntask; t++) {
       if (s > 0) {
         if (first_wave)
-          wait_ge(progress + s - 1, t + 2, true, st);
+          wait_global(progress + s - 1, t + 2, st);
         else
           wait_lds(&lprog[wv_id - 1], kbase + t + 2, st);
       }
@@ -255,8 +269,8 @@ HSDM_DEV void sb2st_body(int n, int nsweep, double* AB, int ldab, double* V2, do
       for (int a = 0; a < 4; a++)
 #pragma unroll
         for (int b = 0; b < 4; b++) {
-          d[a][b] = blk[offd(a, b)];
-          k[a][b] = blk[B + offl(a, b)];
+          d[a][b] = band_ld(blk + offd(a, b));
+          k[a][b] = band_ld(blk + B + offl(a, b));
         }
 #pragma unroll
       for (int a = 0; a < 4; a++)
@@ -272,8 +286,8 @@ HSDM_DEV void sb2st_body(int n, int nsweep, double* AB, int ldab, double* V2, do
 #pragma unroll
         for (int a = 0; a < 4; a++) {
           const int i = I + 8 * a, j = J + 8 * a;
-          xr[a] = (i < len) ? AB[(1 + i) + (long)s * LD] : 0.0;
-          xc[a] = (j < len) ? AB[(1 + j) + (long)s * LD] : 0.0;
+          xr[a] = (i < len) ? band_ld(AB + (1 + i) + (long)s * LD) : 0.0;
+          xc[a] = (j < len) ? band_ld(AB + (1 + j) + (long)s * LD) : 0.0;
         }
         const double alpha = first_lane(xr[0]);
         double ps = 0.0;
@@ -293,7 +307,7 @@ HSDM_DEV void sb2st_body(int n, int nsweep, double* AB, int ldab, double* V2, do
           for (int a = 0; a < 4; a++) {
             const int i = I + 8 * a;
             vl[i] = vr[a];
-            if (i < len) AB[(1 + i) + (long)s * LD] = (i == 0) ? beta : 0.0;
+            if (i < len) band_st(AB + (1 + i) + (long)s * LD, (i == 0) ? beta : 0.0);
           }
         }
         wave_sync();
@@ -396,8 +410,8 @@ HSDM_DEV void sb2st_body(int n, int nsweep, double* AB, int ldab, double* V2, do
 #pragma unroll
         for (int b = 0; b < 4; b++) {
           const int i = I + 8 * a, j = J + 8 * b;
-          if (i >= j && i < len) blk[offl(a, b)] = d[a][b];
-          if (i < len2 && j < len) blk[B + offl(a, b)] = k[a][b];
+          if (i >= j && i < len) band_st(blk + offl(a, b), d[a][b]);
+          if (i < len2 && j < len) band_st(blk + B + offl(a, b), k[a][b]);
         }
       tau = tau_n;
 #pragma unroll
@@ -406,10 +420,10 @@ HSDM_DEV void sb2st_body(int n, int nsweep, double* AB, int ldab, double* V2, do
         vc[a] = vnc[a];
       }
       publish_lds(&lprog[wv_id], kbase + t + 1);
-      if (last_wave) publish(progress + s, t + 1, true);
+      if (last_wave) publish_global(progress + s, t + 1);
     }
     publish_lds(&lprog[wv_id], kbase + KDONE);
-    if (last_wave) publish(progress + s, DONE, true);
+    if (last_wave) publish_global(progress + s, DONE);
   }
 }
 
@@ -453,6 +467,17 @@ __global__ void fill_dbl_kernel(double* p, long n) {
 }
 
 }  // namespace
+
+// Workgroups of kernel fn (one of the two chasing kernels) that can be
+// resident together on the current device.
+static hipError_t resident_wg(const void* fn, int& out) {
+  int per_cu = 0, ncu = 0, dev = 0;
+  HSDM_TRY(hipGetDevice(&dev));
+  HSDM_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  HSDM_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * WPB, 0));
+  out = per_cu * ncu;
+  return out > 0 ? hipSuccess : hipErrorInvalidConfiguration;
+}
 
 Sb2stLayout sb2st_layout(int n, int B) {
   Sb2stLayout L{};
@@ -524,8 +549,12 @@ hipError_t sb2st_group_launch(const Sb2stTask* d_tasks, const int* d_wg_task, in
   if (total_wg <= 0) return hipSuccess;
   if (total_wg > SB2ST_MAX_WG) return hipErrorInvalidValue;
   void* args[] = {(void*)&d_tasks, (void*)&d_wg_task};
+  const void* fn = (const void*)sb2st_group_kernel<32>;
+  int cap = 0;
+  HSDM_TRY(resident_wg(fn, cap));
+  if (total_wg > cap) return hipErrorInvalidValue;
   kt_begin("sb2st_group_kernel<32>", flops, bytes, 0, s, true);
-  HSDM_TRY(hipLaunchCooperativeKernel((const void*)sb2st_group_kernel<32>, dim3(total_wg),
+  HSDM_TRY(hipLaunchCooperativeKernel(fn, dim3(total_wg),
                                       dim3(64 * WPB), args, 0, s));
   kt_end(s);
   return hipSuccess;
@@ -545,15 +574,16 @@ hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, doub
                        (long)L.nsweep, 0);
     HSDM_TRY(hipGetLastError());
     int nsweep = L.nsweep;
-    int nwg = ceil_div(nsweep, WPB);
-    if (nwg > SB2ST_MAX_WG) nwg = SB2ST_MAX_WG;
+    const void* fn = (const void*)sb2st_kernel<32>;
+    int nwg = ceil_div(nsweep, WPB), cap = 0;
+    HSDM_TRY(resident_wg(fn, cap));
+    if (nwg > cap) nwg = cap;
     // (sweep s and s-1 share a workgroup iff s is not the first sweep of its
     // wavefront group; TW = nwg * WPB keeps that true for every round)
     void* args[] = {(void*)&n, (void*)&nsweep, (void*)&AB, (void*)&ldab, (void*)&V2,
                     (void*)&tau2, (void*)&d_goff, (void*)&progress, (void*)&st};
     kt_begin("sb2st_kernel<32>", sb2st_algo_flops(L), sb2st_algo_bytes(L), 0, s, true);
-    HSDM_TRY(hipLaunchCooperativeKernel((const void*)sb2st_kernel<32>, dim3(nwg), dim3(64 * WPB),
-                                        args, 0, s));
+    HSDM_TRY(hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(64 * WPB), args, 0, s));
     kt_end(s);
   }
   hipLaunchKernelGGL(extract_tridiag_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, AB, ldab,

@@ -46,7 +46,7 @@ EXPORTED = [
     "hsdm_tridiagonalize", "hsdm_tridiag_eigh", "hsdm_occupations", "hsdm_density",
     "hsdm_dgemm", "hsdm_status_string", "hsdm_last_error", "hsdm_status_detail",
     "hsdm_phase_times", "hsdm_phase_name", "hsdm_phase_flops", "hsdm_kernel_count", "hsdm_kernel_stat",
-    "hsdm_version",
+    "hsdm_version", "hsdm_timing_kernel",
 ]
 
 _lib = None
@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH):
         "hsdm_kernel_count": ([_vp], _i),
         "hsdm_kernel_stat": ([_vp, _i, ctypes.POINTER(_d)], ctypes.c_char_p),
         "hsdm_version": ([], _i),
+        "hsdm_timing_kernel": ([_vp, ctypes.c_char_p], _i),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -228,6 +229,10 @@ class Handle:
         buf = (ctypes.c_double * 16)()
         k = self._lib.hsdm_phase_times(self._h, buf, 16)
         return {self._lib.hsdm_phase_name(i).decode(): buf[i] for i in range(k)}
+
+    def hsdm_timing_kernel(self, name):
+        """Time only the launches of kernel `name` (None: every kernel)."""
+        self._check(self._lib.hsdm_timing_kernel(self._h, name.encode() if name else None))
 
     def phase_flops(self):
         """Algorithmic flops of each phase of the last single solve (timing on)."""

@@ -13,6 +13,13 @@
       divided by the bytes that copy moves.  bench.py divides a kernel's
       counters by these factors to get its HBM bytes per launch.
 
+  python -m paper_1912_13403_amd.profiling mfma DIR [SIMDS]
+      per-kernel matrix-core utilisation from one `rocprofv3 --pmc
+      SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU_MFMA_MOPS_F64 GRBM_GUI_ACTIVE` run:
+      busy = sum of SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDS)
+      (SIMDS = 1024 on the 256 compute units of the MI355X), and the FP64
+      matrix flops the hardware executed (SQ_INSTS_VALU_MFMA_MOPS_F64 x 512).
+
   python -m paper_1912_13403_amd.profiling timeline DIR [GAP_MS]
       phases of every multi-task solve in a kernel trace (one solve per
       bt2_group_kernel launch; solves are told apart by idle gaps of the
@@ -118,6 +125,33 @@ def traffic(fetch_dir, write_dir, out_path, workload="cfg2_n16384"):
     return res
 
 
+def mfma(d, simds=1024):
+    """name -> dict(dispatches, util (fraction of SIMD-cycles with the matrix
+    core busy), fp64 matrix flops per dispatch)."""
+    busy = _counter(d, "SQ_VALU_MFMA_BUSY_CYCLES")
+    gui = _counter(d, "GRBM_GUI_ACTIVE")
+    mops = _counter(d, "SQ_INSTS_VALU_MFMA_MOPS_F64")
+    out = {}
+    for key, b in busy.items():
+        g = gui.get(key, 0.0)
+        a = out.setdefault(key[1], [0, 0.0, 0.0, 0.0])
+        a[0] += 1
+        a[1] += b
+        a[2] += g
+        a[3] += mops.get(key, 0.0) * 512.0
+    return {k: {"dispatches": v[0], "util": v[1] / (v[2] * simds) if v[2] > 0 else None,
+                "fp64_mfma_flops_per_dispatch": v[3] / v[0]} for k, v in out.items()}
+
+
+def print_mfma(d, simds=1024, top=12):
+    st = mfma(d, simds)
+    print(f"{'disp':>5} {'MFMA busy':>10} {'FP64 MFMA flops/disp':>22}  kernel")
+    for k, v in sorted(st.items(), key=lambda kv: -kv[1]["fp64_mfma_flops_per_dispatch"]
+                       * kv[1]["dispatches"])[:top]:
+        u = "n/a" if v["util"] is None else f"{100 * v['util']:.1f} %"
+        print(f"{v['dispatches']:5d} {u:>10} {v['fp64_mfma_flops_per_dispatch']:22.4e}  {k}")
+
+
 def _busy(iv):
     tot, cs, ce = 0, None, None
     for a, b in sorted(iv):
@@ -189,6 +223,8 @@ if __name__ == "__main__":
     elif len(sys.argv) >= 5 and sys.argv[1] == "traffic":
         r = traffic(sys.argv[2], sys.argv[3], sys.argv[4])
         print(json.dumps({k: r[k] for k in r if k != "kernels"}))
+    elif len(sys.argv) >= 3 and sys.argv[1] == "mfma":
+        print_mfma(sys.argv[2], int(sys.argv[3]) if len(sys.argv) >= 4 else 1024)
     elif len(sys.argv) >= 3 and sys.argv[1] == "timeline":
         print_timeline(sys.argv[2], float(sys.argv[3]) if len(sys.argv) >= 4 else 2.0)
     else:
