@@ -115,6 +115,23 @@ int hsdm_solve_dm_real(hsdm_handle h, int n, const double *H, int ldh, const dou
                        double n_electrons, double kT, double *D, int ldd, double *E, int lde,
                        double *eval, double *band_energy, double *mu, void *stream);
 
+/* hsdm_solve_dm_real without any device allocation, for callers that cannot
+ * allocate: code recorded into a HIP graph, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, results and status codes as
+ * hsdm_solve_dm_real, for n <= HSDM_NOALLOC_MAX_N (a larger n returns -2
+ * with the reason in hsdm_last_error).  The workspace is a static device
+ * array of the library (56 MiB, held by every GPU the library runs on until
+ * the process ends), located at hsdm_init; the call makes no hipMalloc or
+ * hipFree and no allocating library call.  Every call on one GPU shares that
+ * array, from every handle: calls that overlap on one GPU race, so callers
+ * must order them (one stream, or events).  The factor of S is never cached
+ * (each call factors S), and per-launch timing is not recorded. */
+#define HSDM_NOALLOC_MAX_N 512
+int hsdm_solve_dm_real_noalloc(hsdm_handle h, int n, const double *H, int ldh, const double *S,
+                               int lds, double n_electrons, double kT, double *D, int ldd,
+                               double *E, int lde, double *eval, double *band_energy,
+                               double *mu, void *stream);
+
 /* Density matrices of a Hermitian pencil: the complex H_k, S_k of one unit
  * task of Eq. (13) (a k-point and spin channel), through the complex solver
  * interface of Sec. 2.1.  H, S, D and E are interleaved complex128 (real,

@@ -7,6 +7,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -74,6 +75,7 @@ struct hsdm_ctx {
   int detail = 0;
   // workspace
   int ws_n = 0;
+  bool borrowed = false;  // workspace carved from the library's static scratch (never freed)
   double* ws = nullptr;
   int* iws = nullptr;
   long* d_goff = nullptr;
@@ -107,6 +109,8 @@ struct hsdm_ctx {
   std::vector<int> h_wgmap;
   void* d_sb = nullptr;  // Sb2stTask[nprob] then the workgroup -> task map
   size_t d_sb_bytes = 0;
+  hsdm_ctx* na = nullptr;        // context of the allocation-free solve (static scratch)
+  std::vector<long> na_goff;     // its group offsets (host copy, uploaded per call)
   // embedded Hermitian pencils: R(H), R(S), D_R, E_R (2n x 2n each)
   int cws_n = 0;
   double* cws = nullptr;
@@ -273,9 +277,11 @@ struct Lanes {
 };
 
 void free_ws(hsdm_ctx* h) {
-  if (h->ws) (void)hipFree(h->ws);
-  if (h->iws) (void)hipFree(h->iws);
-  if (h->d_goff) (void)hipFree(h->d_goff);
+  if (!h->borrowed) {
+    if (h->ws) (void)hipFree(h->ws);
+    if (h->iws) (void)hipFree(h->iws);
+    if (h->d_goff) (void)hipFree(h->d_goff);
+  }
   stedc_plan_destroy(h->plan);
   h->ws = nullptr;
   h->iws = nullptr;
@@ -321,36 +327,38 @@ double ws_bytes(int n) {
   return 8.0 * w.total + 4.0 * w.ints + 8.0 * (sb2st_layout(n, BAND).nblk + 1);
 }
 
+// Points the workspace pointers of h into w (WsLayout(n).total doubles) and
+// iws (WsLayout(n).ints ints).
+void carve_ws(hsdm_ctx* h, int n, double* w, int* iws) {
+  const WsLayout wl = ws_layout(n);
+  h->ws = w;
+  h->iws = iws;
+  h->Lbuf = w + wl.oL; h->Linv = w + wl.oLi; h->Abuf = w + wl.oA; h->Vst = w + wl.oV;
+  h->Zbuf = w + wl.oZ; h->Cbuf = w + wl.oC; h->T1 = w + wl.oT1; h->tau1 = w + wl.otau1;
+  h->AB = w + wl.oAB; h->sy_scr = w + wl.osy; h->dvec = w + wl.od; h->evec = w + wl.oe;
+  h->lam = w + wl.olam; h->fvec = w + wl.of; h->V2 = w + wl.oV2; h->tau2 = w + wl.otau2;
+  h->F2 = w + wl.oF2; h->dc_scr = w + wl.odc; h->bt1_scr = w + wl.obt1; h->colsum = w + wl.ocs;
+  h->hnorm = w + wl.ohn;
+  h->dc_iscr = iws;
+  h->progress = iws + stedc_iscratch_ints(n);
+  h->lay = sb2st_layout(n, BAND);
+}
+
 int ensure_ws(hsdm_ctx* h, int n) {
   if (h->ws_n == n && h->ws) return HSDM_OK;
   free_ws(h);
   const Sb2stLayout L = sb2st_layout(n, BAND);
   const WsLayout wl = ws_layout(n);
-  const size_t off = wl.total;
-  const size_t oL = wl.oL, oLi = wl.oLi, oA = wl.oA, oV = wl.oV, oZ = wl.oZ, oC = wl.oC,
-               oT1 = wl.oT1, otau1 = wl.otau1, oAB = wl.oAB, osy = wl.osy, od = wl.od,
-               oe = wl.oe, olam = wl.olam, of = wl.of, oV2 = wl.oV2, otau2 = wl.otau2,
-               oF2 = wl.oF2, odc = wl.odc, obt1 = wl.obt1, ocs = wl.ocs, ohn = wl.ohn;
-  hipError_t e = hipMalloc(&h->ws, off * sizeof(double));
+  double* w = nullptr;
+  int* iw = nullptr;
+  hipError_t e = hipMalloc(&w, wl.total * sizeof(double));
+  if (e != hipSuccess) return fail_dev(h, e, "workspace allocation");
+  e = hipMalloc(&iw, wl.ints * sizeof(int));
   if (e != hipSuccess) {
-    h->ws = nullptr;
+    (void)hipFree(w);
     return fail_dev(h, e, "workspace allocation");
   }
-  const size_t ni = wl.ints;
-  e = hipMalloc(&h->iws, ni * sizeof(int));
-  if (e != hipSuccess) {
-    free_ws(h);
-    return fail_dev(h, e, "workspace allocation");
-  }
-  double* w = h->ws;
-  h->Lbuf = w + oL; h->Linv = w + oLi; h->Abuf = w + oA; h->Vst = w + oV; h->Zbuf = w + oZ;
-  h->Cbuf = w + oC; h->T1 = w + oT1; h->tau1 = w + otau1; h->AB = w + oAB; h->sy_scr = w + osy;
-  h->dvec = w + od; h->evec = w + oe; h->lam = w + olam; h->fvec = w + of; h->V2 = w + oV2;
-  h->tau2 = w + otau2; h->F2 = w + oF2; h->dc_scr = w + odc; h->bt1_scr = w + obt1;
-  h->colsum = w + ocs; h->hnorm = w + ohn;
-  h->dc_iscr = h->iws;
-  h->progress = h->iws + stedc_iscratch_ints(n);
-  h->lay = L;
+  carve_ws(h, n, w, iw);
   std::vector<long> goff(L.nblk + 1);
   sb2st_group_offsets(L, goff.data());
   e = hipMalloc(&h->d_goff, sizeof(long) * (L.nblk + 1));
@@ -371,6 +379,44 @@ int ensure_ws(hsdm_ctx* h, int n) {
   }
   h->ws_n = n;
   return HSDM_OK;
+}
+
+// ---- the allocation-free density-matrix solve --------------------------------
+// Its workspace lives in `scratch`, a static device array of the library:
+// every GPU the library runs on holds one copy until the process ends, and
+// every call of hsdm_solve_dm_real_noalloc on that GPU uses it (calls that
+// overlap on one GPU race).  Host code never names the array except in
+// hipGetSymbolAddress: the device address of each GPU's copy is taken once
+// per device at hsdm_init and kept in scratch_dev[].
+constexpr size_t NOALLOC_BYTES = (size_t)56 << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+std::mutex scratch_mu;
+void* scratch_dev[64] = {};
+
+// With `device` current: the address of its copy of the scratch array.
+hipError_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_dev[device]) {
+    void* p = nullptr;
+    HSDM_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_dev[device] = p;
+  }
+  *out = scratch_dev[device];
+  return hipSuccess;
+}
+
+size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Scratch bytes of an allocation-free solve of size n: the workspace doubles
+// and ints, the group offsets and the divide-and-conquer plan's tables.
+size_t noalloc_bytes(int n) {
+  const WsLayout wl = ws_layout(n);
+  const Sb2stLayout L = sb2st_layout(n, BAND);
+  return up256(wl.total * sizeof(double)) + up256(wl.ints * sizeof(int)) +
+         up256(sizeof(long) * (L.nblk + 1)) + stedc_plan_device_bytes(n);
 }
 
 void mark(hsdm_ctx* h, int phase, hipStream_t s) {
@@ -594,6 +640,11 @@ int hsdm_init(hsdm_handle* out, int device) {
   }
   for (int i = 0; i <= NPHASE; i++) (void)hipEventCreate(&h->ev[i]);
   h->kt = kt_create();
+  void* scr = nullptr;
+  if (scratch_address(device, &scr) != hipSuccess) {
+    hsdm_finalize(h);
+    return HSDM_DEVICE_ERROR;
+  }
   *out = h;
   return HSDM_OK;
 }
@@ -603,6 +654,11 @@ int hsdm_finalize(hsdm_handle h) {
   (void)hipSetDevice(h->device);
   for (hsdm_ctx* c : h->subs) hsdm_finalize(c);
   h->subs.clear();
+  if (h->na) {
+    free_ws(h->na);  // the plan object only: the workspace is the static scratch
+    delete h->na;
+    h->na = nullptr;
+  }
   free_lanes(h);
   if (h->d_tasks) (void)hipFree(h->d_tasks);
   if (h->d_sb) (void)hipFree(h->d_sb);
@@ -1163,6 +1219,90 @@ int hsdm_solve_dm_real(hsdm_handle h, int n, const double* H, int ldh, const dou
     DEV_TRY(h, hipGetLastError());
   }
   if (r == HSDM_OK) r = finish(h, s);
+  if (mu) *mu = h->host->occ.mu;
+  if (band_energy) *band_energy = h->host->occ.band_energy;
+  return r;
+}
+
+int hsdm_solve_dm_real_noalloc(hsdm_handle h, int n, const double* H, int ldh, const double* S,
+                               int lds, double ne, double kT, double* D, int ldd, double* E,
+                               int lde, double* eval, double* band_energy, double* mu,
+                               void* stream) {
+  int a = check_hs(h, n, H, ldh, S, lds);
+  if (a) return a;
+  if (!(ne >= 0.0) || !std::isfinite(ne) || ne > h->fmax * n) return -7;
+  if (!(kT >= 0.0) || !std::isfinite(kT)) return -8;
+  if (!D) return -9;
+  if (bad_ld(ldd, n)) return -10;
+  if (E && bad_ld(lde, n)) return -12;
+  if (n > HSDM_NOALLOC_MAX_N) {
+    h->err = "hsdm_solve_dm_real_noalloc: n = " + std::to_string(n) + " exceeds the maximum " +
+             std::to_string(HSDM_NOALLOC_MAX_N) + " of the static scratch";
+    return -2;
+  }
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  DEV_TRY(h, hipSetDevice(h->device));
+  void* scr = nullptr;
+  DEV_TRY(h, scratch_address(h->device, &scr));  // taken at hsdm_init: no allocation here
+  if (noalloc_bytes(n) > NOALLOC_BYTES) {
+    h->err = "hsdm_solve_dm_real_noalloc: the static scratch is too small for n = " +
+             std::to_string(n);
+    return HSDM_DEVICE_ERROR;
+  }
+  // the context of the allocation-free solves: host object only, its device
+  // pointers carved from the scratch; status words and pinned results are
+  // the handle's own
+  if (!h->na) {
+    h->na = new hsdm_ctx();
+    h->na->borrowed = true;
+    h->na->device = h->device;
+  }
+  hsdm_ctx* c = h->na;
+  if (c->ws_n != n) {
+    stedc_plan_destroy(c->plan);
+    c->plan = nullptr;
+    c->ws_n = 0;
+    const WsLayout wl = ws_layout(n);
+    const Sb2stLayout L = sb2st_layout(n, BAND);
+    char* b = (char*)scr;
+    double* w = (double*)b;
+    b += up256(wl.total * sizeof(double));
+    int* iw = (int*)b;
+    b += up256(wl.ints * sizeof(int));
+    carve_ws(c, n, w, iw);
+    c->d_goff = (long*)b;
+    b += up256(sizeof(long) * (L.nblk + 1));
+    c->plan = stedc_plan_create_in(n, b);
+    h->na_goff.assign(L.nblk + 1, 0);
+    sb2st_group_offsets(L, h->na_goff.data());
+    c->ws_n = n;
+  }
+  c->st = h->st;
+  c->occ = h->occ;
+  c->host = h->host;
+  c->fmax = h->fmax;
+  c->fcut_rel = h->fcut_rel;
+  c->deg_tol = h->deg_tol;
+  c->timing = false;
+  c->ktiming = false;
+  c->s_valid = false;  // the scratch is shared: S is always factored
+  c->err.clear();
+  // another call on this GPU may have overwritten the scratch's tables
+  DEV_TRY(h, hipMemcpyAsync(c->d_goff, h->na_goff.data(), sizeof(long) * h->na_goff.size(),
+                            hipMemcpyHostToDevice, s));
+  DEV_TRY(h, stedc_plan_upload(c->plan, s));
+  int r = dm_core(c, n, H, ldh, S, lds, SKey{n, false, 0ull}, ne, kT, D, ldd, E, lde, s);
+  c->s_valid = false;
+  if (eval && r == HSDM_OK) {
+    hipLaunchKernelGGL(copy_vec_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, c->lam, eval, n);
+    DEV_TRY(h, hipGetLastError());
+  }
+  if (r == HSDM_OK) r = finish(c, s);
+  if (r != HSDM_OK) {
+    if (!c->err.empty()) h->err = c->err;
+    h->detail = c->detail;
+  }
   if (mu) *mu = h->host->occ.mu;
   if (band_energy) *band_energy = h->host->occ.band_energy;
   return r;

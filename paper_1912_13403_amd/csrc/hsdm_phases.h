@@ -176,6 +176,13 @@ hipError_t bt1_apply(int n, int B, const double* Vst, long ldv, const double* T1
 // callback).
 struct StedcPlan;
 StedcPlan* stedc_plan_create(int n);
+// A plan whose device arrays live in caller-provided device memory of
+// stedc_plan_device_bytes(n) bytes (256-byte aligned); stedc_plan_upload
+// copies its tables there on stream s (the plan's host tables stay alive
+// with the plan).  Such a plan allocates and frees no device memory.
+size_t stedc_plan_device_bytes(int n);
+StedcPlan* stedc_plan_create_in(int n, void* dev);
+hipError_t stedc_plan_upload(StedcPlan* p, hipStream_t s);
 // Flops of the merge products of the last stedc_run on this plan (2 m n k
 // per product, from the sizes the device wrote after deflation); reads the
 // device descriptors, so the run's stream must have been synchronized.

@@ -678,6 +678,8 @@ struct StedcPlan {
   int* d_leaves = nullptr;
   int* d_merges = nullptr;
   GemmDesc* d_desc = nullptr;
+  bool owns = true;  // device arrays allocated by the plan (else placed in the caller's memory)
+  std::vector<int> merges_host;
 };
 
 static int build_tree(StedcPlan* p, int lo, int hi) {
@@ -697,13 +699,13 @@ static int build_tree(StedcPlan* p, int lo, int hi) {
   return h;
 }
 
-StedcPlan* stedc_plan_create(int n) {
-  StedcPlan* p = new StedcPlan();
+static void plan_tree(StedcPlan* p, int n) {
   p->n = n;
-  if (n <= 0) return p;
+  if (n <= 0) return;
   build_tree(p, 0, n);
   p->nleaf = (int)p->leaves.size() / 2;
-  std::vector<int> all;
+  std::vector<int>& all = p->merges_host;
+  all.clear();
   for (auto& lv : p->levels) {
     p->level_first.push_back((int)all.size() / 3);
     int mx = 0;
@@ -712,6 +714,13 @@ StedcPlan* stedc_plan_create(int n) {
     all.insert(all.end(), lv.begin(), lv.end());
   }
   p->nmerge = (int)all.size() / 3;
+}
+
+StedcPlan* stedc_plan_create(int n) {
+  StedcPlan* p = new StedcPlan();
+  plan_tree(p, n);
+  if (n <= 0) return p;
+  const std::vector<int>& all = p->merges_host;
   if (hipMalloc(&p->d_leaves, sizeof(int) * p->leaves.size()) != hipSuccess) goto fail;
   if (hipMemcpy(p->d_leaves, p->leaves.data(), sizeof(int) * p->leaves.size(),
                 hipMemcpyHostToDevice) != hipSuccess)
@@ -729,11 +738,45 @@ fail:
   return nullptr;
 }
 
+size_t stedc_plan_device_bytes(int n) {
+  StedcPlan p;
+  plan_tree(&p, n);
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  return up(sizeof(int) * p.leaves.size()) + up(sizeof(int) * p.merges_host.size()) +
+         up(sizeof(GemmDesc) * 2 * (size_t)p.nmerge);
+}
+
+StedcPlan* stedc_plan_create_in(int n, void* dev) {
+  StedcPlan* p = new StedcPlan();
+  plan_tree(p, n);
+  p->owns = false;
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  char* c = (char*)dev;
+  p->d_leaves = (int*)c;
+  c += up(sizeof(int) * p->leaves.size());
+  p->d_merges = (int*)c;
+  c += up(sizeof(int) * p->merges_host.size());
+  p->d_desc = (GemmDesc*)c;
+  return p;
+}
+
+hipError_t stedc_plan_upload(StedcPlan* p, hipStream_t s) {
+  if (!p || p->n <= 0) return hipSuccess;
+  HSDM_TRY(hipMemcpyAsync(p->d_leaves, p->leaves.data(), sizeof(int) * p->leaves.size(),
+                          hipMemcpyHostToDevice, s));
+  if (p->nmerge > 0)
+    HSDM_TRY(hipMemcpyAsync(p->d_merges, p->merges_host.data(),
+                            sizeof(int) * p->merges_host.size(), hipMemcpyHostToDevice, s));
+  return hipSuccess;
+}
+
 void stedc_plan_destroy(StedcPlan* p) {
   if (!p) return;
-  if (p->d_leaves) (void)hipFree(p->d_leaves);
-  if (p->d_merges) (void)hipFree(p->d_merges);
-  if (p->d_desc) (void)hipFree(p->d_desc);
+  if (p->owns) {
+    if (p->d_leaves) (void)hipFree(p->d_leaves);
+    if (p->d_merges) (void)hipFree(p->d_merges);
+    if (p->d_desc) (void)hipFree(p->d_desc);
+  }
   delete p;
 }
 

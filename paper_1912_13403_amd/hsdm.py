@@ -46,8 +46,10 @@ EXPORTED = [
     "hsdm_tridiagonalize", "hsdm_tridiag_eigh", "hsdm_occupations", "hsdm_density",
     "hsdm_dgemm", "hsdm_status_string", "hsdm_last_error", "hsdm_status_detail",
     "hsdm_phase_times", "hsdm_phase_name", "hsdm_phase_flops", "hsdm_kernel_count", "hsdm_kernel_stat",
-    "hsdm_version", "hsdm_timing_kernel",
+    "hsdm_version", "hsdm_timing_kernel", "hsdm_solve_dm_real_noalloc",
 ]
+
+HSDM_NOALLOC_MAX_N = 512
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -72,6 +74,8 @@ def load_library(path: str = LIB_PATH):
         "hsdm_solve_ev_real": ([_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _vp], _i),
         "hsdm_solve_dm_real": ([_vp, _i, _vp, _i, _vp, _i, _d, _d, _vp, _i, _vp, _i, _vp,
                                 ctypes.POINTER(_d), ctypes.POINTER(_d), _vp], _i),
+        "hsdm_solve_dm_real_noalloc": ([_vp, _i, _vp, _i, _vp, _i, _d, _d, _vp, _i, _vp, _i,
+                                        _vp, ctypes.POINTER(_d), ctypes.POINTER(_d), _vp], _i),
         "hsdm_solve_ev_complex": ([_vp, _i, _vp, _i, _vp, _i, _vp, _vp, _i, _vp], _i),
         "hsdm_solve_dm_complex": ([_vp, _i, _vp, _i, _vp, _i, _d, _d, _vp, _i, _vp, _i, _vp,
                                    ctypes.POINTER(_d), ctypes.POINTER(_d), _vp], _i),
@@ -276,6 +280,23 @@ class Handle:
         mu = ctypes.c_double(0.0)
         eb = ctypes.c_double(0.0)
         self._check(self._lib.hsdm_solve_dm_real(
+            self._h, n, H.data_ptr(), _ld(H), S.data_ptr(), _ld(S), float(n_electrons), float(kT),
+            D.data_ptr(), _ld(D), E.data_ptr() if E is not None else None,
+            _ld(E) if E is not None else n, w.data_ptr() if w is not None else None,
+            ctypes.byref(eb), ctypes.byref(mu), _stream_ptr(self.device)))
+        return dict(D=D, E=E, eval=w, mu=mu.value, band_energy=eb.value)
+
+    def hsdm_solve_dm_real_noalloc(self, H, S, n_electrons, kT, out):
+        """hsdm_solve_dm_real_noalloc: the library allocates no device memory;
+        the caller passes the outputs out = (D, E or None, eval or None),
+        column-major float64 tensors (n <= HSDM_NOALLOC_MAX_N)."""
+        if _colmajor(H) is not H or _colmajor(S) is not S:
+            raise ValueError("H and S must be column-major float64 tensors (no copies made)")
+        n = H.shape[0]
+        D, E, w = out
+        mu = ctypes.c_double(0.0)
+        eb = ctypes.c_double(0.0)
+        self._check(self._lib.hsdm_solve_dm_real_noalloc(
             self._h, n, H.data_ptr(), _ld(H), S.data_ptr(), _ld(S), float(n_electrons), float(kT),
             D.data_ptr(), _ld(D), E.data_ptr() if E is not None else None,
             _ld(E) if E is not None else n, w.data_ptr() if w is not None else None,

@@ -70,6 +70,8 @@ def test_handle_keys_match_the_header(lib):
         m = re.search(name + r"\s*=\s*(\d+)", txt)
         assert m and int(m.group(1)) == getattr(hsdm, name), name
     assert lib.hsdm_set_int(None, hsdm.HSDM_KEY_STREAMS, 4) == -1
+    m = re.search(r"#define\s+HSDM_NOALLOC_MAX_N\s+(\d+)", txt)
+    assert m and int(m.group(1)) == hsdm.HSDM_NOALLOC_MAX_N
 
 
 def test_bench_refuses_more_than_one_gpu():
