@@ -62,6 +62,13 @@ enum hsdm_key {
   , HSDM_KEY_STREAMS = 5   /* int: worker streams of the multi-task solves, 1 ... 8 (default 4);
                               they run side by side only as far as the HIP runtime gives the
                               process hardware queues (GPU_MAX_HW_QUEUES) */
+  , HSDM_KEY_CONCURRENT = 7 /* int: 1 = this handle's solves may run at the same time as other
+                              handles' solves on the same GPU (other host threads and streams,
+                              e.g. the slots of a serving loop); their cooperative kernels (panel
+                              QR, bulge chasing), which need all their workgroups resident, then
+                              run one at a time on a stream the library keeps per device, ordered
+                              into the caller's stream by events.  0 (default): launched on the
+                              caller's stream, for a handle that has the device to itself */
   , HSDM_KEY_N_STATES = 6  /* int: number of eigenvectors the eigenpair solves form, the lowest
                               ones (the paper's n_states: its dense runs compute only part of
                               the eigenvectors, Sec. 3); 0 or >= n: all (default 0).  C then
@@ -84,7 +91,7 @@ int hsdm_reinit(hsdm_handle h);
 /* Solver settings (~ the elsi_set_* routines of the API of Sec. 2.1, which
  * configure a handle between elsi_init and the solves).  hsdm_set_real takes
  * HSDM_KEY_FMAX, HSDM_KEY_FCUT, HSDM_KEY_DEG_TOL; hsdm_set_int takes
- * HSDM_KEY_TIMING, HSDM_KEY_STREAMS, HSDM_KEY_N_STATES.  Returns HSDM_OK,
+ * HSDM_KEY_TIMING, HSDM_KEY_STREAMS, HSDM_KEY_N_STATES, HSDM_KEY_CONCURRENT.  Returns HSDM_OK,
  * -1 (null handle), -2 (unknown key for this call) or -3 (value out of the
  * key's range; the setting is left unchanged).  Settings apply to the solves
  * that follow and are kept across hsdm_reinit. */

@@ -70,12 +70,16 @@ struct hsdm_ctx {
   bool kt_every = false;  // every launch timed: no worker streams
   int nlane = 4;          // worker streams used by multi-task solves
   long n_states = 0;      // eigenvectors formed by the eigenpair solves (0: all)
+  bool concurrent = false;  // solves may overlap other handles' on the device
   KTimer* kt = nullptr;
   std::string err;
   int detail = 0;
   // workspace
   int ws_n = 0;
   bool borrowed = false;  // workspace carved from the library's static scratch (never freed)
+  void* ws_raw = nullptr;  // the one device allocation holding the workspace (not borrowed)
+  size_t ws_cap = 0;       // its size in bytes
+  std::vector<long> goff_host;  // group offsets of the carved size (uploaded with it)
   double* ws = nullptr;
   int* iws = nullptr;
   long* d_goff = nullptr;
@@ -110,7 +114,6 @@ struct hsdm_ctx {
   void* d_sb = nullptr;  // Sb2stTask[nprob] then the workgroup -> task map
   size_t d_sb_bytes = 0;
   hsdm_ctx* na = nullptr;        // context of the allocation-free solve (static scratch)
-  std::vector<long> na_goff;     // its group offsets (host copy, uploaded per call)
   // embedded Hermitian pencils: R(H), R(S), D_R, E_R (2n x 2n each)
   int cws_n = 0;
   double* cws = nullptr;
@@ -166,9 +169,11 @@ void free_cws(hsdm_ctx* h) {
 
 // Workspace of the Hermitian route for complex sizes up to n (the real
 // workspace is that of size 2n); a size-n' problem uses it with leading
-// dimension 2n'.  Zero-filled once, so the upper triangles of R(H) and R(S),
-// which nothing writes, hold zeros.
-int ensure_cws(hsdm_ctx* h, int n) {
+// dimension 2n'.  Zero-filled once, by a kernel on stream s (the caller's
+// stream, ahead of the work that uses the buffers: a null-stream memset is
+// not ordered with non-blocking streams), so the upper triangles of R(H)
+// and R(S), which nothing writes, hold zeros.
+int ensure_cws(hsdm_ctx* h, int n, hipStream_t s) {
   if (h->cws_n >= n && h->cws) return HSDM_OK;
   free_cws(h);
   const size_t q = (size_t)4 * n * n;
@@ -177,7 +182,8 @@ int ensure_cws(hsdm_ctx* h, int n) {
     h->cws = nullptr;
     return fail_dev(h, e, "workspace allocation");
   }
-  e = hipMemset(h->cws, 0, 4 * q * sizeof(double));
+  // 4 buffers of (2n)^2 doubles: a 2n x 8n column-major block
+  e = dev_fill(h->cws, 2L * n, 2 * n, 8 * n, 0.0, s);
   if (e != hipSuccess) {
     free_cws(h);
     return fail_dev(h, e, "workspace clear");
@@ -227,11 +233,11 @@ int ensure_lanes(hsdm_ctx* h) {
 
 // Embedding buffers of lane k for complex sizes up to n.
 hsdm_ctx* lane_cws(hsdm_ctx* h, int k) { return k == 0 ? h : h->lane_buf[k]; }
-int ensure_lane_cws(hsdm_ctx* h, int k, int n) {
+int ensure_lane_cws(hsdm_ctx* h, int k, int n, hipStream_t s) {
   if (n <= 0) return HSDM_OK;
   if (k > 0 && !h->lane_buf[k]) h->lane_buf[k] = new hsdm_ctx();
   hsdm_ctx* b = lane_cws(h, k);
-  const int r = ensure_cws(b, n);
+  const int r = ensure_cws(b, n, s);
   if (r && b != h) h->err = b->err;
   return r;
 }
@@ -277,11 +283,9 @@ struct Lanes {
 };
 
 void free_ws(hsdm_ctx* h) {
-  if (!h->borrowed) {
-    if (h->ws) (void)hipFree(h->ws);
-    if (h->iws) (void)hipFree(h->iws);
-    if (h->d_goff) (void)hipFree(h->d_goff);
-  }
+  if (!h->borrowed && h->ws_raw) (void)hipFree(h->ws_raw);
+  h->ws_raw = nullptr;
+  h->ws_cap = 0;
   stedc_plan_destroy(h->plan);
   h->ws = nullptr;
   h->iws = nullptr;
@@ -321,11 +325,6 @@ WsLayout ws_layout(int n) {
   return w;
 }
 
-// Device bytes of the workspace of a real solve of size n.
-double ws_bytes(int n) {
-  const WsLayout w = ws_layout(n);
-  return 8.0 * w.total + 4.0 * w.ints + 8.0 * (sb2st_layout(n, BAND).nblk + 1);
-}
 
 // Points the workspace pointers of h into w (WsLayout(n).total doubles) and
 // iws (WsLayout(n).ints ints).
@@ -344,41 +343,69 @@ void carve_ws(hsdm_ctx* h, int n, double* w, int* iws) {
   h->lay = sb2st_layout(n, BAND);
 }
 
-int ensure_ws(hsdm_ctx* h, int n) {
-  if (h->ws_n == n && h->ws) return HSDM_OK;
-  free_ws(h);
-  const Sb2stLayout L = sb2st_layout(n, BAND);
+size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Device bytes of the workspace of a solve of size n, as one block: the
+// workspace doubles and ints, the group offsets of the stage-2 reflectors
+// and the divide-and-conquer plan's tables.
+size_t ws_block_bytes(int n) {
   const WsLayout wl = ws_layout(n);
-  double* w = nullptr;
-  int* iw = nullptr;
-  hipError_t e = hipMalloc(&w, wl.total * sizeof(double));
-  if (e != hipSuccess) return fail_dev(h, e, "workspace allocation");
-  e = hipMalloc(&iw, wl.ints * sizeof(int));
-  if (e != hipSuccess) {
-    (void)hipFree(w);
-    return fail_dev(h, e, "workspace allocation");
-  }
+  const Sb2stLayout L = sb2st_layout(n, BAND);
+  return up256(wl.total * sizeof(double)) + up256(wl.ints * sizeof(int)) +
+         up256(sizeof(long) * (L.nblk + 1)) + stedc_plan_device_bytes(n);
+}
+
+// Device bytes of the workspace of a real solve of size n.
+double ws_bytes(int n) { return (double)ws_block_bytes(n); }
+
+// Points every workspace pointer of h into the block at base (ws_block_bytes(n)
+// bytes) for size n and queues the upload of its tables on stream s.  The
+// factor of S that the block held for another size is gone.
+int carve_block(hsdm_ctx* h, int n, void* base, hipStream_t s) {
+  stedc_plan_destroy(h->plan);
+  h->plan = nullptr;
+  h->ws_n = 0;
+  h->s_valid = false;
+  const WsLayout wl = ws_layout(n);
+  const Sb2stLayout L = sb2st_layout(n, BAND);
+  char* b = (char*)base;
+  double* w = (double*)b;
+  b += up256(wl.total * sizeof(double));
+  int* iw = (int*)b;
+  b += up256(wl.ints * sizeof(int));
   carve_ws(h, n, w, iw);
-  std::vector<long> goff(L.nblk + 1);
-  sb2st_group_offsets(L, goff.data());
-  e = hipMalloc(&h->d_goff, sizeof(long) * (L.nblk + 1));
-  if (e != hipSuccess) {
-    free_ws(h);
-    return fail_dev(h, e, "workspace allocation");
-  }
-  e = hipMemcpy(h->d_goff, goff.data(), sizeof(long) * (L.nblk + 1), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    free_ws(h);
-    return fail_dev(h, e, "workspace upload");
-  }
-  h->plan = stedc_plan_create(n);
+  h->d_goff = (long*)b;
+  b += up256(sizeof(long) * (L.nblk + 1));
+  h->plan = stedc_plan_create_in(n, b);
   if (!h->plan) {
-    free_ws(h);
-    h->err = "divide-and-conquer plan allocation failed";
+    h->err = "divide-and-conquer plan creation failed";
     return HSDM_DEVICE_ERROR;
   }
+  h->goff_host.assign(L.nblk + 1, 0);
+  sb2st_group_offsets(L, h->goff_host.data());
+  DEV_TRY(h, hipMemcpyAsync(h->d_goff, h->goff_host.data(), sizeof(long) * h->goff_host.size(),
+                            hipMemcpyHostToDevice, s));
+  DEV_TRY(h, stedc_plan_upload(h->plan, s));
   h->ws_n = n;
   return HSDM_OK;
+}
+
+// The workspace for size n.  The block only grows: a smaller size is carved
+// from the block in hand, so that solves of varying sizes do not free and
+// allocate device memory (a free waits for the whole device, other streams
+// included).
+int ensure_ws(hsdm_ctx* h, int n, hipStream_t s) {
+  if (h->ws_n == n && h->ws) return HSDM_OK;
+  const size_t need = ws_block_bytes(n);
+  if (!h->ws_raw || h->ws_cap < need) {
+    free_ws(h);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, need);
+    if (e != hipSuccess) return fail_dev(h, e, "workspace allocation");
+    h->ws_raw = p;
+    h->ws_cap = need;
+  }
+  return carve_block(h, n, h->ws_raw, s);
 }
 
 // ---- the allocation-free density-matrix solve --------------------------------
@@ -408,16 +435,6 @@ hipError_t scratch_address(int device, void** out) {
   return hipSuccess;
 }
 
-size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
-
-// Scratch bytes of an allocation-free solve of size n: the workspace doubles
-// and ints, the group offsets and the divide-and-conquer plan's tables.
-size_t noalloc_bytes(int n) {
-  const WsLayout wl = ws_layout(n);
-  const Sb2stLayout L = sb2st_layout(n, BAND);
-  return up256(wl.total * sizeof(double)) + up256(wl.ints * sizeof(int)) +
-         up256(sizeof(long) * (L.nblk + 1)) + stedc_plan_device_bytes(n);
-}
 
 void mark(hsdm_ctx* h, int phase, hipStream_t s) {
   if (h->timing) {
@@ -601,11 +618,19 @@ struct KtScope {
       kt_reset(h->kt);
       kt_activate(h->kt);
     }
+    coop_set_shared(h->concurrent);
   }
   ~KtScope() {
     kt_activate(nullptr);
     kt_set_tag(-1);
+    coop_set_shared(false);
   }
+};
+
+// The cooperative-launch mode of a handle for the duration of one call.
+struct CoopScope {
+  explicit CoopScope(const hsdm_ctx* h) { coop_set_shared(h->concurrent); }
+  ~CoopScope() { coop_set_shared(false); }
 };
 
 }  // namespace
@@ -723,6 +748,11 @@ int hsdm_set_int(hsdm_handle h, int key, long v) {
     h->n_states = v;
     return HSDM_OK;
   }
+  if (key == HSDM_KEY_CONCURRENT) {
+    if (v != 0 && v != 1) return -3;
+    h->concurrent = (v == 1);
+    return HSDM_OK;
+  }
   return -2;
 }
 
@@ -811,9 +841,9 @@ int hsdm_cholesky_inverse(hsdm_handle h, int n, const double* S, int lds, double
   h->err.clear();
   hipStream_t s = (hipStream_t)stream;
   DEV_TRY(h, hipSetDevice(h->device));
-  int r = ensure_ws(h, n);
+  int r = ensure_ws(h, n, s);
   if (r) return r;
-  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  HSDM_LAUNCH(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
   DEV_TRY(h, dev_copy(S, lds, L, ldl, n, n, s));
   DEV_TRY(h, dev_fill(Linv, ldli, n, n, 0.0, s));
@@ -834,9 +864,9 @@ int hsdm_standard_form(hsdm_handle h, int n, const double* H, int ldh, const dou
   h->err.clear();
   hipStream_t s = (hipStream_t)stream;
   DEV_TRY(h, hipSetDevice(h->device));
-  int r = ensure_ws(h, n);
+  int r = ensure_ws(h, n, s);
   if (r) return r;
-  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  HSDM_LAUNCH(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
   r = standard_form(h, n, H, ldh, Linv, ldli, A, lda, s);
   if (r) return r;
@@ -855,23 +885,24 @@ int hsdm_tridiagonalize(hsdm_handle h, int n, const double* A, int lda, double* 
   h->err.clear();
   hipStream_t s = (hipStream_t)stream;
   DEV_TRY(h, hipSetDevice(h->device));
-  int r = ensure_ws(h, n);
+  int r = ensure_ws(h, n, s);
   if (r) return r;
-  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  HSDM_LAUNCH(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
   DEV_TRY(h, dev_copy(A, lda, h->Abuf, n, n, n, s));
+  CoopScope cs(h);
   r = reduce(h, n, s, 0);
   if (r) return r;
-  hipLaunchKernelGGL(copy_vec_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, h->dvec, d, n);
+  HSDM_LAUNCH(copy_vec_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, h->dvec, d, n);
   DEV_TRY(h, hipGetLastError());
   if (n > 1) {
-    hipLaunchKernelGGL(copy_vec_kernel, dim3(ceil_div(n - 1, 256)), dim3(256), 0, s, h->evec, e,
+    HSDM_LAUNCH(copy_vec_kernel, dim3(ceil_div(n - 1, 256)), dim3(256), 0, s, h->evec, e,
                        n - 1);
     DEV_TRY(h, hipGetLastError());
   }
   if (Q) {
     const long tot = (long)n * n;
-    hipLaunchKernelGGL(eye_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Q,
+    HSDM_LAUNCH(eye_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Q,
                        (long)ldq, n);
     DEV_TRY(h, hipGetLastError());
     DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
@@ -893,9 +924,9 @@ int hsdm_tridiag_eigh(hsdm_handle h, int n, const double* d, const double* e, do
   h->err.clear();
   hipStream_t s = (hipStream_t)stream;
   DEV_TRY(h, hipSetDevice(h->device));
-  int r = ensure_ws(h, n);
+  int r = ensure_ws(h, n, s);
   if (r) return r;
-  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  HSDM_LAUNCH(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
   DEV_TRY(h, stedc_run(h->plan, d, e, w, Z, ldz, h->dc_scr, h->dc_iscr, nullptr, nullptr, nullptr,
                        h->st, s));
@@ -915,7 +946,7 @@ int hsdm_occupations(hsdm_handle h, int n, const double* eval, double ne, double
   h->err.clear();
   hipStream_t s = (hipStream_t)stream;
   DEV_TRY(h, hipSetDevice(h->device));
-  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  HSDM_LAUNCH(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
   DEV_TRY(h, occupations_launch(n, eval, h->fmax, ne, kT, deg_tol, nullptr, h->fcut_rel * h->fmax,
                                 f, h->occ, h->st, s));
@@ -941,7 +972,7 @@ int hsdm_density(hsdm_handle h, int n, int m, const double* C, int ldc, const do
   h->err.clear();
   hipStream_t s = (hipStream_t)stream;
   DEV_TRY(h, hipSetDevice(h->device));
-  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  HSDM_LAUNCH(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
   DEV_TRY(h, density_launch(n, m, C, ldc, f, eval, D, ldd, E, lde, nullptr, s));
   return finish(h, s);
@@ -958,7 +989,7 @@ static int dm_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S
   for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
   h->last_kind = 1;
   h->last_n = n;
-  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  HSDM_LAUNCH(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
   mark(h, 0, s);
   if ((r = factor_s(h, n, S, lds, key, s))) return r;
@@ -1001,11 +1032,11 @@ static int ev_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S
   h->last_kind = 2;
   h->last_n = n;
   h->last_ns = ns;
-  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  HSDM_LAUNCH(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
   const int* m_dev = nullptr;
   if (ns < n) {
-    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, &h->occ->m, ns);
+    HSDM_LAUNCH(set_int_kernel, dim3(1), dim3(64), 0, s, &h->occ->m, ns);
     DEV_TRY(h, hipGetLastError());
     m_dev = &h->occ->m;
   }
@@ -1058,7 +1089,7 @@ int hsdm_solve_ev_real(hsdm_handle h, int n, const double* H, int ldh, const dou
   h->err.clear();
   hipStream_t s = (hipStream_t)stream;
   DEV_TRY(h, hipSetDevice(h->device));
-  int r = ensure_ws(h, n);
+  int r = ensure_ws(h, n, s);
   if (r) return r;
   SKey key;
   if ((r = s_key(h, S, n, lds, false, key, s))) return r;
@@ -1083,9 +1114,9 @@ int hsdm_solve_ev_complex(hsdm_handle h, int n, const void* H, int ldh, const vo
   hipStream_t s = (hipStream_t)stream;
   DEV_TRY(h, hipSetDevice(h->device));
   const int n2 = 2 * n;
-  int r = ensure_ws(h, n2);
+  int r = ensure_ws(h, n2, s);
   if (r) return r;
-  if ((r = ensure_cws(h, n))) return r;
+  if ((r = ensure_cws(h, n, s))) return r;
   SKey key;
   if ((r = s_key(h, S, n, lds, true, key, s))) return r;
   KtScope kts(h);
@@ -1208,14 +1239,14 @@ int hsdm_solve_dm_real(hsdm_handle h, int n, const double* H, int ldh, const dou
   h->err.clear();
   hipStream_t s = (hipStream_t)stream;
   DEV_TRY(h, hipSetDevice(h->device));
-  int r = ensure_ws(h, n);
+  int r = ensure_ws(h, n, s);
   if (r) return r;
   SKey key;
   if ((r = s_key(h, S, n, lds, false, key, s))) return r;
   KtScope kts(h);
   r = dm_core(h, n, H, ldh, S, lds, key, ne, kT, D, ldd, E, lde, s);
   if (eval && r == HSDM_OK) {
-    hipLaunchKernelGGL(copy_vec_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, h->lam, eval, n);
+    HSDM_LAUNCH(copy_vec_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, h->lam, eval, n);
     DEV_TRY(h, hipGetLastError());
   }
   if (r == HSDM_OK) r = finish(h, s);
@@ -1245,38 +1276,28 @@ int hsdm_solve_dm_real_noalloc(hsdm_handle h, int n, const double* H, int ldh, c
   DEV_TRY(h, hipSetDevice(h->device));
   void* scr = nullptr;
   DEV_TRY(h, scratch_address(h->device, &scr));  // taken at hsdm_init: no allocation here
-  if (noalloc_bytes(n) > NOALLOC_BYTES) {
+  if (ws_block_bytes(n) > NOALLOC_BYTES) {
     h->err = "hsdm_solve_dm_real_noalloc: the static scratch is too small for n = " +
              std::to_string(n);
     return HSDM_DEVICE_ERROR;
   }
   // the context of the allocation-free solves: host object only, its device
-  // pointers carved from the scratch; status words and pinned results are
-  // the handle's own
+  // pointers carved from the scratch (its tables uploaded again on every
+  // call: another call on this GPU may have used the scratch since); status
+  // words and pinned results are the handle's own
   if (!h->na) {
     h->na = new hsdm_ctx();
     h->na->borrowed = true;
     h->na->device = h->device;
   }
   hsdm_ctx* c = h->na;
-  if (c->ws_n != n) {
-    stedc_plan_destroy(c->plan);
-    c->plan = nullptr;
-    c->ws_n = 0;
-    const WsLayout wl = ws_layout(n);
-    const Sb2stLayout L = sb2st_layout(n, BAND);
-    char* b = (char*)scr;
-    double* w = (double*)b;
-    b += up256(wl.total * sizeof(double));
-    int* iw = (int*)b;
-    b += up256(wl.ints * sizeof(int));
-    carve_ws(c, n, w, iw);
-    c->d_goff = (long*)b;
-    b += up256(sizeof(long) * (L.nblk + 1));
-    c->plan = stedc_plan_create_in(n, b);
-    h->na_goff.assign(L.nblk + 1, 0);
-    sb2st_group_offsets(L, h->na_goff.data());
-    c->ws_n = n;
+  c->err.clear();
+  {
+    const int r0 = carve_block(c, n, scr, s);
+    if (r0) {
+      h->err = c->err;
+      return r0;
+    }
   }
   c->st = h->st;
   c->occ = h->occ;
@@ -1287,15 +1308,11 @@ int hsdm_solve_dm_real_noalloc(hsdm_handle h, int n, const double* H, int ldh, c
   c->timing = false;
   c->ktiming = false;
   c->s_valid = false;  // the scratch is shared: S is always factored
-  c->err.clear();
-  // another call on this GPU may have overwritten the scratch's tables
-  DEV_TRY(h, hipMemcpyAsync(c->d_goff, h->na_goff.data(), sizeof(long) * h->na_goff.size(),
-                            hipMemcpyHostToDevice, s));
-  DEV_TRY(h, stedc_plan_upload(c->plan, s));
+  CoopScope cs(h);
   int r = dm_core(c, n, H, ldh, S, lds, SKey{n, false, 0ull}, ne, kT, D, ldd, E, lde, s);
   c->s_valid = false;
   if (eval && r == HSDM_OK) {
-    hipLaunchKernelGGL(copy_vec_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, c->lam, eval, n);
+    HSDM_LAUNCH(copy_vec_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, c->lam, eval, n);
     DEV_TRY(h, hipGetLastError());
   }
   if (r == HSDM_OK) r = finish(c, s);
@@ -1327,9 +1344,9 @@ int hsdm_solve_dm_complex(hsdm_handle h, int n, const void* H, int ldh, const vo
   hipStream_t s = (hipStream_t)stream;
   DEV_TRY(h, hipSetDevice(h->device));
   const int n2 = 2 * n;
-  int r = ensure_ws(h, n2);
+  int r = ensure_ws(h, n2, s);
   if (r) return r;
-  if ((r = ensure_cws(h, n))) return r;
+  if ((r = ensure_cws(h, n, s))) return r;
   SKey key;
   if ((r = s_key(h, S, n, lds, true, key, s))) return r;
   KtScope kts(h);
@@ -1494,12 +1511,12 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
     int nk = 0;
     for (int p : order[k])
       if (T[p].cplx) nk = std::max(nk, T[p].n);
-    if ((r = ensure_lane_cws(h, (int)k, nk))) return r;
+    if ((r = ensure_lane_cws(h, (int)k, nk, s))) return r;
   }
   for (int p = 0; p < nt; p++) {
     hsdm_ctx* c = ctx[p];
     c->err.clear();
-    if ((r = ensure_ws(c, T[p].cplx ? 2 * T[p].n : T[p].n))) {
+    if ((r = ensure_ws(c, T[p].cplx ? 2 * T[p].n : T[p].n, s))) {
       h->err = c->err;
       return r;
     }
@@ -1533,7 +1550,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
       Sr = L->SR;
       ldhr = ldsr = nr;
     }
-    hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, ls, c->st, c->occ);
+    HSDM_LAUNCH(reset_status_kernel, dim3(1), dim3(64), 0, ls, c->st, c->occ);
     DEV_TRY(h, hipGetLastError());
     if (own && (r = factor_s(c, nr, Sr, ldsr, key, ls))) return r;
     if (c->deg_tol < 0.0) DEV_TRY(h, dev_norm1_sym(Hr, ldhr, nr, c->colsum, c->hnorm, ls));
@@ -1642,7 +1659,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
   }
   DEV_TRY(h, lanes.join());
   // 4. one chemical potential for all tasks (Eq. (16))
-  hipLaunchKernelGGL(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+  HSDM_LAUNCH(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
   if (shared) {
     DEV_TRY(h, hipMemcpyAsync(h->d_tasks, h->h_tasks.data(), sizeof(OccTask) * nt,
@@ -1727,7 +1744,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
 }
 
 double ctx_bytes(const hsdm_ctx* c) {
-  double b = c->ws ? ws_bytes(c->ws_n) : 0.0;
+  double b = (c->ws_raw && !c->borrowed) ? (double)c->ws_cap : 0.0;
   if (c->cws) b += 16.0 * 8.0 * (double)c->cws_n * c->cws_n;
   return b;
 }

@@ -329,7 +329,7 @@ size_t bt2_pack_doubles(const Sb2stLayout& L) { return (size_t)L.ngroups * GREC;
 hipError_t bt2_prepare(const Sb2stLayout& L, const double* V2, const double* tau2, double* F2,
                        hipStream_t s) {
   if (L.ngroups <= 0) return hipSuccess;
-  hipLaunchKernelGGL(group_pack_kernel, dim3((unsigned)L.ngroups), dim3(256), 0, s, V2, tau2, F2);
+  HSDM_LAUNCH(group_pack_kernel, dim3((unsigned)L.ngroups), dim3(256), 0, s, V2, tau2, F2);
   return hipGetLastError();
 }
 
@@ -377,14 +377,36 @@ hipError_t bt2_apply(const Sb2stLayout& L, const double* F2, const long* d_goff,
                      hipStream_t s) {
   if (L.ngroups <= 0 || m <= 0) return hipSuccess;
   const Bt2Task q = bt2_task(L, F2, d_goff, Z, ldz, m, m_dev, iscratch, st);
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(ceil_div(q.nstrip, 256)), dim3(256), 0, s, iscratch,
+  HSDM_LAUNCH(fill_i32_kernel, dim3(ceil_div(q.nstrip, 256)), dim3(256), 0, s, iscratch,
                      q.nstrip);
   HSDM_TRY(hipGetLastError());
-  kt_begin("bt2_strip_kernel", bt2_flops(L, m), 0.0, m_dev ? m : 0, s, true);
-  hipLaunchKernelGGL(bt2_strip_kernel, dim3(q.nstrip * NSPLIT), dim3(64 * PW), 0, s, q.n, q.nblk,
-                     q.R, q.nstrip, F2, d_goff, Z, ldz, m, m_dev, iscratch, st);
-  kt_end(s);
-  return hipGetLastError();
+  if (coop_get_shared()) {
+    // beside other solves: one workgroup per strip applies every sweep
+    // block (range 0 is all of them), so no workgroup waits for another; the
+    // groups reach each column in the same order as with eight ranges
+    SplitRanges R1 = q.R;
+    for (int k = 0; k < NSPLIT; k++) {
+      R1.hi[k] = -1;
+      R1.lo[k] = 0;
+    }
+    R1.hi[0] = q.nblk - 1;
+    R1.lo[0] = 0;
+    kt_begin("bt2_strip_kernel", bt2_flops(L, m), 0.0, m_dev ? m : 0, s, true);
+    HSDM_LAUNCH(bt2_strip_kernel, dim3(q.nstrip), dim3(64 * PW), 0, s, q.n, q.nblk, R1, q.nstrip,
+                F2, d_goff, Z, ldz, m, m_dev, iscratch, st);
+    kt_end(s);
+    return hipGetLastError();
+  }
+  // workgroups wait for lower-numbered ones: a spinning kernel (see coop_launch)
+  int n_ = q.n, nblk = q.nblk, nstrip = q.nstrip, m_ = m;
+  SplitRanges R = q.R;
+  long ldz_ = ldz;
+  void* args[] = {(void*)&n_, (void*)&nblk, (void*)&R, (void*)&nstrip, (void*)&F2,
+                  (void*)&d_goff, (void*)&Z, (void*)&ldz_, (void*)&m_, (void*)&m_dev,
+                  (void*)&iscratch, (void*)&st};
+  return coop_launch("bt2_strip_kernel", bt2_flops(L, m), 0.0, true, false,
+                     (const void*)bt2_strip_kernel, dim3(q.nstrip * NSPLIT), dim3(64 * PW), args,
+                     s, m_dev ? m : 0);
 }
 
 size_t bt2_group_map_ints(int nt, const Bt2Task* tasks) {
@@ -408,7 +430,7 @@ hipError_t bt2_group_apply(int nt, Bt2Task* tasks, std::vector<int>& hmap, Bt2Ta
     const int cnt = (q.nblk > 0 && q.m > 0) ? q.nstrip * NSPLIT : 0;
     b0 += cnt;
     if (cnt > 0) {
-      hipLaunchKernelGGL(fill_i32_kernel, dim3(ceil_div(q.nstrip, 256)), dim3(256), 0, s, q.done,
+      HSDM_LAUNCH(fill_i32_kernel, dim3(ceil_div(q.nstrip, 256)), dim3(256), 0, s, q.done,
                          q.nstrip);
       HSDM_TRY(hipGetLastError());
     }
@@ -426,10 +448,9 @@ hipError_t bt2_group_apply(int nt, Bt2Task* tasks, std::vector<int>& hmap, Bt2Ta
   HSDM_TRY(hipMemcpyAsync(d_tasks, tasks, sizeof(Bt2Task) * nt, hipMemcpyHostToDevice, s));
   HSDM_TRY(hipMemcpyAsync(d_map, hmap.data(), sizeof(int) * hmap.size(), hipMemcpyHostToDevice,
                           s));
-  kt_begin("bt2_group_kernel", 0.0, 0.0, 0, s, true);
-  hipLaunchKernelGGL(bt2_group_kernel, dim3(b0), dim3(64 * PW), 0, s, d_tasks, d_map);
-  kt_end(s);
-  return hipGetLastError();
+  void* args[] = {(void*)&d_tasks, (void*)&d_map};
+  return coop_launch("bt2_group_kernel", 0.0, 0.0, true, false, (const void*)bt2_group_kernel,
+                     dim3(b0), dim3(64 * PW), args, s);
 }
 
 namespace {
@@ -526,7 +547,7 @@ size_t bt1_scratch_doubles(int n, int B_, int m) {
 
 hipError_t bt1_zero_fill(int n, int B_, double* Vst, long ldv, hipStream_t s) {
   const long tot = (long)n * n;
-  hipLaunchKernelGGL(zero_upper_panels_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+  HSDM_LAUNCH(zero_upper_panels_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
                      s, n, B_, Vst, ldv);
   return hipGetLastError();
 }
@@ -562,12 +583,12 @@ hipError_t bt1_apply(int n, int B_, const double* Vst, long ldv, const double* T
     HSDM_TRY(gemm_splitk_launch(g, BT1_GCHUNK, Gpart, s));
   }
   // T of every group: panel T's on the diagonal, then the doubling levels
-  hipLaunchKernelGGL(group_t_init_kernel, dim3(1024), dim3(256), 0, s, ngroup, np_all, B_, T1,
+  HSDM_LAUNCH(group_t_init_kernel, dim3(1024), dim3(256), 0, s, ngroup, np_all, B_, T1,
                      Tall);
   HSDM_TRY(hipGetLastError());
   for (int b = B_; b < W; b *= 2) {
     const int cnt = ngroup * (W / (2 * b));
-    hipLaunchKernelGGL(group_t_desc_kernel, dim3(ceil_div(cnt, 64)), dim3(64), 0, s, ngroup,
+    HSDM_LAUNCH(group_t_desc_kernel, dim3(ceil_div(cnt, 64)), dim3(64), 0, s, ngroup,
                        np_all, B_, b, Gall, Tall, Xall, d1, d2);
     HSDM_TRY(hipGetLastError());
     HSDM_TRY(gemm_batched_dense_launch(d1, cnt, b, b, 1.0, 0.0, GF_KB_UPPER, s));

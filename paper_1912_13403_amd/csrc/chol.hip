@@ -96,7 +96,7 @@ __global__ __launch_bounds__(64) void chol_leaf_kernel(int nb, double* A, long l
 hipError_t rec(int n, double* A, long lda, double* Li, long ldi, double* T, long ldt,
                DevStatusWord* st, int col0, hipStream_t s) {
   if (n <= LEAF) {
-    hipLaunchKernelGGL(chol_leaf_kernel, dim3(1), dim3(64), 0, s, n, A, lda, Li, ldi, st, col0);
+    HSDM_LAUNCH(chol_leaf_kernel, dim3(1), dim3(64), 0, s, n, A, lda, Li, ldi, st, col0);
     return hipGetLastError();
   }
   int n1 = ((n / 2) / LEAF) * LEAF;
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void zero_upper_kernel(double* A, long lda, in
 
 hipError_t zero_upper(double* A, long lda, int n, hipStream_t s) {
   if (n <= 1) return hipSuccess;
-  hipLaunchKernelGGL(zero_upper_kernel, dim3(ceil_div(n, 256), n < 16384 ? n : 16384), dim3(256),
+  HSDM_LAUNCH(zero_upper_kernel, dim3(ceil_div(n, 256), n < 16384 ? n : 16384), dim3(256),
                      0, s, A, lda, n);
   return hipGetLastError();
 }

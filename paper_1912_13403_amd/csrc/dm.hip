@@ -121,7 +121,7 @@ hipError_t density_launch(int n, int m, const double* C, long ldc, const double*
   const int nt = ceil_div(n, BT);
   // algorithmic: lower triangles of D (and E), n (n + 1) m flops each
   kt_begin("dm_kernel", (E ? 2.0 : 1.0) * n * (n + 1.0) * m, 0.0, m_dev ? m : 0, s, true);
-  hipLaunchKernelGGL(dm_kernel, dim3(nt, nt), dim3(NT), 0, s, n, m, m_dev, C, ldc, f, eps, D, ldd,
+  HSDM_LAUNCH(dm_kernel, dim3(nt, nt), dim3(NT), 0, s, n, m, m_dev, C, ldc, f, eps, D, ldd,
                      E, lde);
   kt_end(s);
   HSDM_TRY(hipGetLastError());

@@ -543,7 +543,7 @@ hipError_t launch_cfg(const Prob& p, double alpha, double beta, int flags, int n
                       long stride, double flops, hipStream_t s) {
   const int nblk = tile_grid(ceil_div(p.m, BM), ceil_div(p.n, BN));
   kt_begin(kernel_name<BM, BN, WM, WN, TA, TB, AM>(), flops, 0.0, p.ndev ? p.n : 0, s);
-  hipLaunchKernelGGL((gemm_kernel<BM, BN, WM, WN, TA, TB, AM>), dim3(nblk, nsplit),
+  HSDM_LAUNCH((gemm_kernel<BM, BN, WM, WN, TA, TB, AM>), dim3(nblk, nsplit),
                      dim3(64 * WM * WN), 0, s, p, alpha, beta, flags, kchunk, stride);
   kt_end(s);
   return hipGetLastError();
@@ -644,7 +644,7 @@ hipError_t gemm_launch(const GemmArgs& g, hipStream_t s) {
   if (g.k <= 0 || g.alpha == 0.0) {
     if (g.beta == 1.0) return hipSuccess;
     long tot = (long)g.m * g.n;
-    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, g.m,
+    HSDM_LAUNCH(scale_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, g.m,
                        g.n, g.C, g.ldc, g.beta, g.ccol, g.ndev);
     return hipGetLastError();
   }
@@ -668,7 +668,7 @@ hipError_t gemm_splitk_launch(const GemmArgs& g, int kchunk, double* part, hipSt
   const long stride = (long)g.m * g.n;
   HSDM_TRY(
       launch_any(p, g.ta, g.tb, am, g.alpha, 0.0, g.flags, nsplit, kchunk, stride, gemm_flops(g), s));
-  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((stride + 255) / 256)), dim3(256), 0, s,
+  HSDM_LAUNCH(splitk_reduce_kernel, dim3((unsigned)((stride + 255) / 256)), dim3(256), 0, s,
                      g.m, g.n, nsplit, part, g.C, g.ldc, g.beta, g.ndev);
   return hipGetLastError();
 }
@@ -680,7 +680,7 @@ hipError_t gemm_batched_launch(const GemmDesc* d_desc, int count, int max_m, int
   if (ta != 0 || tb != 0) return hipErrorInvalidValue;
   const int nblk = tile_grid(ceil_div(max_m, 64), ceil_div(max_n, 64));
   kt_begin("gemm_batched_kernel<64, 64, 2, 2, 0, 0, 2>", 0.0, 0.0, 0, s);
-  hipLaunchKernelGGL((gemm_batched_kernel<64, 64, 2, 2, 0, 0, AM_GATHER>), dim3(nblk, count),
+  HSDM_LAUNCH((gemm_batched_kernel<64, 64, 2, 2, 0, 0, AM_GATHER>), dim3(nblk, count),
                      dim3(256), 0, s, d_desc, alpha, beta, flags);
   kt_end(s);
   return hipGetLastError();
@@ -691,7 +691,7 @@ hipError_t gemm_batched_dense_launch(const GemmDesc* d_desc, int count, int max_
   if (count <= 0 || max_m <= 0 || max_n <= 0) return hipSuccess;
   const int nblk = tile_grid(ceil_div(max_m, 64), ceil_div(max_n, 64));
   kt_begin("gemm_batched_kernel<64, 64, 2, 2, 0, 0, 0>", 0.0, 0.0, 0, s);
-  hipLaunchKernelGGL((gemm_batched_kernel<64, 64, 2, 2, 0, 0, AM_DENSE>), dim3(nblk, count),
+  HSDM_LAUNCH((gemm_batched_kernel<64, 64, 2, 2, 0, 0, AM_DENSE>), dim3(nblk, count),
                      dim3(256), 0, s, d_desc, alpha, beta, flags);
   kt_end(s);
   return hipGetLastError();
@@ -705,12 +705,12 @@ hipError_t gemm_sym_pair_launch(const GemmArgs& g, int kchunk, double* part1, do
   const int nsplit = ceil_div(g.k, kchunk);
   Prob p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, nullptr, (long)g.m, nullptr, nullptr, nullptr};
   kt_begin("sym_pair_kernel", 2.0 * gemm_flops(g), 0.0, 0, s);
-  hipLaunchKernelGGL(sym_pair_kernel, dim3(tile_grid(ceil_div(g.m, 128), 1), nsplit, 2), dim3(256),
+  HSDM_LAUNCH(sym_pair_kernel, dim3(tile_grid(ceil_div(g.m, 128), 1), nsplit, 2), dim3(256),
                      0, s, p, part1, part2, kchunk);
   kt_end(s);
   HSDM_TRY(hipGetLastError());
   const long tot = (long)g.m * g.n;
-  hipLaunchKernelGGL(sym_pair_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+  HSDM_LAUNCH(sym_pair_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
                      g.m, g.n, nsplit, part1, part2, g.C, g.ldc);
   return hipGetLastError();
 }
@@ -752,32 +752,32 @@ hipError_t gemm_group_launch(int kind, const GemmGroupItem* d_items, int count, 
   switch (kind) {
     case GG_TRIL:
       kt_begin("gemm_group_kernel<0, 0, 3>", flops, 0.0, 0, s);
-      hipLaunchKernelGGL((gemm_group_kernel<0, 0, AM_TRIL>), dim3(total_wg), dim3(256), 0, s,
+      HSDM_LAUNCH((gemm_group_kernel<0, 0, AM_TRIL>), dim3(total_wg), dim3(256), 0, s,
                          d_items, d_map);
       break;
     case GG_SLT:
       kt_begin("gemm_group_kernel<1, 0, 4>", flops, 0.0, 0, s);
-      hipLaunchKernelGGL((gemm_group_kernel<1, 0, AM_SLT>), dim3(total_wg), dim3(256), 0, s,
+      HSDM_LAUNCH((gemm_group_kernel<1, 0, AM_SLT>), dim3(total_wg), dim3(256), 0, s,
                          d_items, d_map);
       break;
     case GG_NN:
       kt_begin("gemm_group_kernel<0, 0, 0>", flops, 0.0, 0, s);
-      hipLaunchKernelGGL((gemm_group_kernel<0, 0, AM_DENSE>), dim3(total_wg), dim3(256), 0, s,
+      HSDM_LAUNCH((gemm_group_kernel<0, 0, AM_DENSE>), dim3(total_wg), dim3(256), 0, s,
                          d_items, d_map);
       break;
     case GG_TN:
       kt_begin("gemm_group_kernel<1, 0, 0>", flops, 0.0, 0, s);
-      hipLaunchKernelGGL((gemm_group_kernel<1, 0, AM_DENSE>), dim3(total_wg), dim3(256), 0, s,
+      HSDM_LAUNCH((gemm_group_kernel<1, 0, AM_DENSE>), dim3(total_wg), dim3(256), 0, s,
                          d_items, d_map);
       break;
     case GG_NT:
       kt_begin("gemm_group_kernel<0, 1, 0>", flops, 0.0, 0, s);
-      hipLaunchKernelGGL((gemm_group_kernel<0, 1, AM_DENSE>), dim3(total_wg), dim3(256), 0, s,
+      HSDM_LAUNCH((gemm_group_kernel<0, 1, AM_DENSE>), dim3(total_wg), dim3(256), 0, s,
                          d_items, d_map);
       break;
     case GG_SYR2K:
       kt_begin("syr2k_group_kernel", flops, 0.0, 0, s);
-      hipLaunchKernelGGL(syr2k_group_kernel, dim3(total_wg), dim3(512), 0, s, d_items, d_map);
+      HSDM_LAUNCH(syr2k_group_kernel, dim3(total_wg), dim3(512), 0, s, d_items, d_map);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -785,6 +785,6 @@ hipError_t gemm_group_launch(int kind, const GemmGroupItem* d_items, int count, 
   HSDM_TRY(hipGetLastError());
   if (!split) return hipSuccess;
   const int bx = std::max(1, std::min(1024, ceil_div(max_tot, 256)));
-  hipLaunchKernelGGL(splitk_reduce_group_kernel, dim3(bx, count), dim3(256), 0, s, d_items);
+  HSDM_LAUNCH(splitk_reduce_group_kernel, dim3(bx, count), dim3(256), 0, s, d_items);
   return hipGetLastError();
 }

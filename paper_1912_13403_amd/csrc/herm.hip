@@ -117,39 +117,39 @@ __global__ __launch_bounds__(256) void herm_combine_kernel(int n, int k2, int k,
 hipError_t herm_extract_pairs(int n, int m, const double* R, long ldr, void* X, long ldx,
                               hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(herm_extract_pairs_kernel, dim3(ceil_div(n, 256), m < 4096 ? m : 4096),
+  HSDM_LAUNCH(herm_extract_pairs_kernel, dim3(ceil_div(n, 256), m < 4096 ? m : 4096),
                      dim3(256), 0, s, n, m, R, ldr, (double2*)X, ldx);
   return hipGetLastError();
 }
 
 hipError_t herm_jmul(int n, int k2, const double* Q, long ldq, double* JQ, long ldj,
                      hipStream_t s) {
-  hipLaunchKernelGGL(herm_jmul_kernel, dim3(ceil_div(n, 256), k2), dim3(256), 0, s, n, k2, Q, ldq,
+  HSDM_LAUNCH(herm_jmul_kernel, dim3(ceil_div(n, 256), k2), dim3(256), 0, s, n, k2, Q, ldq,
                      JQ, ldj);
   return hipGetLastError();
 }
 
 hipError_t herm_combine(int n, int k2, int k, const double* Q, long ldq, const void* c, void* X,
                         long ldx, hipStream_t s) {
-  hipLaunchKernelGGL(herm_combine_kernel, dim3(ceil_div(n, 256), k), dim3(256), 0, s, n, k2, k, Q,
+  HSDM_LAUNCH(herm_combine_kernel, dim3(ceil_div(n, 256), k), dim3(256), 0, s, n, k2, k, Q,
                      ldq, (const double2*)c, (double2*)X, ldx);
   return hipGetLastError();
 }
 
 hipError_t herm_embed(int n, const void* A, long lda, double* R, long ldr, hipStream_t s) {
   const int t = ceil_div(n, TT);
-  hipLaunchKernelGGL(herm_embed_kernel, dim3(t, t), dim3(256), 0, s, n, (const double2*)A, lda, R,
+  HSDM_LAUNCH(herm_embed_kernel, dim3(t, t), dim3(256), 0, s, n, (const double2*)A, lda, R,
                      ldr);
   return hipGetLastError();
 }
 
 hipError_t herm_extract(int n, const double* R, long ldr, void* X, long ldx, hipStream_t s) {
-  hipLaunchKernelGGL(herm_extract_kernel, dim3(ceil_div(n, 256), n < 4096 ? n : 4096), dim3(256), 0,
+  HSDM_LAUNCH(herm_extract_kernel, dim3(ceil_div(n, 256), n < 4096 ? n : 4096), dim3(256), 0,
                      s, n, R, ldr, (double2*)X, ldx);
   return hipGetLastError();
 }
 
 hipError_t herm_pair_eval(int n, const double* lam2, double* eval, hipStream_t s) {
-  hipLaunchKernelGGL(herm_pair_eval_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, lam2, eval);
+  HSDM_LAUNCH(herm_pair_eval_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, lam2, eval);
   return hipGetLastError();
 }

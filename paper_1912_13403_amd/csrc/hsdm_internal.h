@@ -121,6 +121,38 @@ int kt_count(const KTimer* k);
 const char* kt_stat(const KTimer* k, int i, double* out4);
 
 // ---------------------------------------------------------------------------
+// Launches of a solve that shares the device with other solves
+// (HSDM_KEY_CONCURRENT; util.hip).  Some kernels of this library spin on
+// other workgroups of their own grid: the cooperative ones (panel QR, bulge
+// chasing) on any of them, the stage-2 back-transform on lower-numbered
+// ones.  Beside kernels of other streams such a kernel can be held off: the
+// compute units it waits for stay full of other kernels' workgroups for as
+// long as those streams keep submitting, and two spinning kernels can each
+// keep out what the other waits for.  So every launch of a concurrent solve
+// passes a gate: ordinary launches share it (HSDM_LAUNCH), a spinning launch
+// holds it alone (coop_launch) from its launch until it has finished --
+// no other concurrent solve submits work meanwhile, and what they had
+// submitted before drains.  Outside concurrent solves the gate is not used.
+void coop_set_shared(bool on);
+bool coop_get_shared();
+struct LaunchGate {
+  LaunchGate();
+  ~LaunchGate();
+  bool held;
+};
+#define HSDM_LAUNCH(...)          \
+  do {                            \
+    LaunchGate hsdm_gate_;        \
+    hipLaunchKernelGGL(__VA_ARGS__); \
+  } while (0)
+// A spinning kernel (cooperative: all workgroups resident; else: waits on
+// lower-numbered workgroups only), timed by the kernel timer (nbound as in
+// kt_begin).
+hipError_t coop_launch(const char* name, double flops, double bytes, bool whole_phase,
+                       bool cooperative, const void* fn, dim3 grid, dim3 block, void** args,
+                       hipStream_t s, int nbound = 0);
+
+// ---------------------------------------------------------------------------
 // Device status word shared by all kernels of a solve (first error wins).
 enum DevStatus {
   DS_OK = 0,

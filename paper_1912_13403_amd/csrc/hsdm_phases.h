@@ -175,11 +175,11 @@ hipError_t bt1_apply(int n, int B, const double* Vst, long ldv, const double* T1
 // evaluated between the final eigenvalues and the final vectors through the
 // callback).
 struct StedcPlan;
-StedcPlan* stedc_plan_create(int n);
-// A plan whose device arrays live in caller-provided device memory of
-// stedc_plan_device_bytes(n) bytes (256-byte aligned); stedc_plan_upload
-// copies its tables there on stream s (the plan's host tables stay alive
-// with the plan).  Such a plan allocates and frees no device memory.
+// A plan's device arrays live in caller-provided device memory of
+// stedc_plan_device_bytes(n) bytes (256-byte aligned, part of the solve's
+// workspace); stedc_plan_upload copies its tables there on stream s (the
+// plan's host tables stay alive with the plan).  A plan allocates and frees
+// no device memory.
 size_t stedc_plan_device_bytes(int n);
 StedcPlan* stedc_plan_create_in(int n, void* dev);
 hipError_t stedc_plan_upload(StedcPlan* p, hipStream_t s);

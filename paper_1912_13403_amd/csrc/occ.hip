@@ -122,7 +122,7 @@ __global__ __launch_bounds__(NT) void occ_kernel(int n, const double* eps, doubl
 hipError_t occupations_launch(int n, const double* eps, double fmax, double ne, double kT,
                               double deg_tol, const double* hnorm, double fcut, double* f,
                               OccOut* out, DevStatusWord* st, hipStream_t s) {
-  hipLaunchKernelGGL(occ_kernel, dim3(1), dim3(NT), 0, s, n, eps, fmax, ne, kT, deg_tol, hnorm,
+  HSDM_LAUNCH(occ_kernel, dim3(1), dim3(NT), 0, s, n, eps, fmax, ne, kT, deg_tol, hnorm,
                      fcut, f, out, st);
   return hipGetLastError();
 }
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(NT) void occ_joint_kernel(int nt, const OccTask* T,
 hipError_t occupations_joint_launch(int nt, const OccTask* tasks, double fmax, double ne, double kT,
                                     double deg_tol, double fcut, OccOut* total, DevStatusWord* st,
                                     hipStream_t s) {
-  hipLaunchKernelGGL(occ_joint_kernel, dim3(1), dim3(NT), 0, s, nt, tasks, fmax, ne, kT, deg_tol,
+  HSDM_LAUNCH(occ_joint_kernel, dim3(1), dim3(NT), 0, s, nt, tasks, fmax, ne, kT, deg_tol,
                      fcut, total, st);
   return hipGetLastError();
 }

@@ -505,18 +505,18 @@ void sb2st_group_offsets(const Sb2stLayout& L, long* offs) {
 hipError_t sb2st_prepare(const Sb2stLayout& L, double* V2, double* tau2, int* progress,
                          hipStream_t s) {
   if (L.nsweep <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_dbl_kernel, dim3(4096), dim3(256), 0, s, V2, L.v2_doubles);
+  HSDM_LAUNCH(fill_dbl_kernel, dim3(4096), dim3(256), 0, s, V2, L.v2_doubles);
   HSDM_TRY(hipGetLastError());
-  hipLaunchKernelGGL(fill_dbl_kernel, dim3(1024), dim3(256), 0, s, tau2, L.ngroups * L.B);
+  HSDM_LAUNCH(fill_dbl_kernel, dim3(1024), dim3(256), 0, s, tau2, L.ngroups * L.B);
   HSDM_TRY(hipGetLastError());
-  hipLaunchKernelGGL(fill_int_kernel, dim3(ceil_div(L.nsweep, 256)), dim3(256), 0, s, progress,
+  HSDM_LAUNCH(fill_int_kernel, dim3(ceil_div(L.nsweep, 256)), dim3(256), 0, s, progress,
                      (long)L.nsweep, 0);
   return hipGetLastError();
 }
 
 hipError_t sb2st_finish(const Sb2stLayout& L, const double* AB, int ldab, double* d, double* e,
                         hipStream_t s) {
-  hipLaunchKernelGGL(extract_tridiag_kernel, dim3(ceil_div(L.n, 256)), dim3(256), 0, s, L.n, AB,
+  HSDM_LAUNCH(extract_tridiag_kernel, dim3(ceil_div(L.n, 256)), dim3(256), 0, s, L.n, AB,
                      ldab, d, e);
   return hipGetLastError();
 }
@@ -553,11 +553,8 @@ hipError_t sb2st_group_launch(const Sb2stTask* d_tasks, const int* d_wg_task, in
   int cap = 0;
   HSDM_TRY(resident_wg(fn, cap));
   if (total_wg > cap) return hipErrorInvalidValue;
-  kt_begin("sb2st_group_kernel<32>", flops, bytes, 0, s, true);
-  HSDM_TRY(hipLaunchCooperativeKernel(fn, dim3(total_wg),
-                                      dim3(64 * WPB), args, 0, s));
-  kt_end(s);
-  return hipSuccess;
+  return coop_launch("sb2st_group_kernel<32>", flops, bytes, true, true, fn, dim3(total_wg),
+                     dim3(64 * WPB), args, s);
 }
 
 hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, double* e, double* V2,
@@ -566,11 +563,11 @@ hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, doub
   const int n = L.n;
   if (L.B != 32 || ldab != 2 * L.B) return hipErrorInvalidValue;
   if (L.nsweep > 0) {
-    hipLaunchKernelGGL(fill_dbl_kernel, dim3(4096), dim3(256), 0, s, V2, L.v2_doubles);
+    HSDM_LAUNCH(fill_dbl_kernel, dim3(4096), dim3(256), 0, s, V2, L.v2_doubles);
     HSDM_TRY(hipGetLastError());
-    hipLaunchKernelGGL(fill_dbl_kernel, dim3(1024), dim3(256), 0, s, tau2, L.ngroups * L.B);
+    HSDM_LAUNCH(fill_dbl_kernel, dim3(1024), dim3(256), 0, s, tau2, L.ngroups * L.B);
     HSDM_TRY(hipGetLastError());
-    hipLaunchKernelGGL(fill_int_kernel, dim3(ceil_div(L.nsweep, 256)), dim3(256), 0, s, progress,
+    HSDM_LAUNCH(fill_int_kernel, dim3(ceil_div(L.nsweep, 256)), dim3(256), 0, s, progress,
                        (long)L.nsweep, 0);
     HSDM_TRY(hipGetLastError());
     int nsweep = L.nsweep;
@@ -582,11 +579,10 @@ hipError_t sb2st_run(const Sb2stLayout& L, double* AB, int ldab, double* d, doub
     // wavefront group; TW = nwg * WPB keeps that true for every round)
     void* args[] = {(void*)&n, (void*)&nsweep, (void*)&AB, (void*)&ldab, (void*)&V2,
                     (void*)&tau2, (void*)&d_goff, (void*)&progress, (void*)&st};
-    kt_begin("sb2st_kernel<32>", sb2st_algo_flops(L), sb2st_algo_bytes(L), 0, s, true);
-    HSDM_TRY(hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(64 * WPB), args, 0, s));
-    kt_end(s);
+    HSDM_TRY(coop_launch("sb2st_kernel<32>", sb2st_algo_flops(L), sb2st_algo_bytes(L), true, true,
+                         fn, dim3(nwg), dim3(64 * WPB), args, s));
   }
-  hipLaunchKernelGGL(extract_tridiag_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, AB, ldab,
+  HSDM_LAUNCH(extract_tridiag_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, AB, ldab,
                      d, e);
   return hipGetLastError();
 }

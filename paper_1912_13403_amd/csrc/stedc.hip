@@ -678,7 +678,6 @@ struct StedcPlan {
   int* d_leaves = nullptr;
   int* d_merges = nullptr;
   GemmDesc* d_desc = nullptr;
-  bool owns = true;  // device arrays allocated by the plan (else placed in the caller's memory)
   std::vector<int> merges_host;
 };
 
@@ -716,28 +715,6 @@ static void plan_tree(StedcPlan* p, int n) {
   p->nmerge = (int)all.size() / 3;
 }
 
-StedcPlan* stedc_plan_create(int n) {
-  StedcPlan* p = new StedcPlan();
-  plan_tree(p, n);
-  if (n <= 0) return p;
-  const std::vector<int>& all = p->merges_host;
-  if (hipMalloc(&p->d_leaves, sizeof(int) * p->leaves.size()) != hipSuccess) goto fail;
-  if (hipMemcpy(p->d_leaves, p->leaves.data(), sizeof(int) * p->leaves.size(),
-                hipMemcpyHostToDevice) != hipSuccess)
-    goto fail;
-  if (p->nmerge > 0) {
-    if (hipMalloc(&p->d_merges, sizeof(int) * all.size()) != hipSuccess) goto fail;
-    if (hipMemcpy(p->d_merges, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice) !=
-        hipSuccess)
-      goto fail;
-    if (hipMalloc(&p->d_desc, sizeof(GemmDesc) * 2 * p->nmerge) != hipSuccess) goto fail;
-  }
-  return p;
-fail:
-  stedc_plan_destroy(p);
-  return nullptr;
-}
-
 size_t stedc_plan_device_bytes(int n) {
   StedcPlan p;
   plan_tree(&p, n);
@@ -749,7 +726,6 @@ size_t stedc_plan_device_bytes(int n) {
 StedcPlan* stedc_plan_create_in(int n, void* dev) {
   StedcPlan* p = new StedcPlan();
   plan_tree(p, n);
-  p->owns = false;
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
   char* c = (char*)dev;
   p->d_leaves = (int*)c;
@@ -770,15 +746,7 @@ hipError_t stedc_plan_upload(StedcPlan* p, hipStream_t s) {
   return hipSuccess;
 }
 
-void stedc_plan_destroy(StedcPlan* p) {
-  if (!p) return;
-  if (p->owns) {
-    if (p->d_leaves) (void)hipFree(p->d_leaves);
-    if (p->d_merges) (void)hipFree(p->d_merges);
-    if (p->d_desc) (void)hipFree(p->d_desc);
-  }
-  delete p;
-}
+void stedc_plan_destroy(StedcPlan* p) { delete p; }
 
 // doubles: Q, Qblk, U (3 n^2) + 11 vectors of n;  ints: 11 vectors of n + meta
 size_t stedc_scratch_doubles(int n) { return (size_t)3 * n * n + (size_t)16 * n + 64; }
@@ -824,7 +792,7 @@ hipError_t stedc_run(StedcPlan* p, const double* d, const double* e, double* lam
   b.orow = iv; iv += n;
   b.odef = iv; iv += n;
 
-  hipLaunchKernelGGL(leaf_kernel, dim3(p->nleaf), dim3(64), 0, s, n, d, e, p->d_leaves, lam, Qa,
+  HSDM_LAUNCH(leaf_kernel, dim3(p->nleaf), dim3(64), 0, s, n, d, e, p->d_leaves, lam, Qa,
                      (long)n, st);
   HSDM_TRY(hipGetLastError());
   double* Qcur = Qa;
@@ -836,41 +804,41 @@ hipError_t stedc_run(StedcPlan* p, const double* d, const double* e, double* lam
     const int cnt = (int)p->levels[lv].size() / 3;
     const int maxN = p->level_maxN[lv];
     const bool final_level = (lv == nlev - 1);
-    hipLaunchKernelGGL(merge_prep_kernel, dim3(cnt), dim3(256), 0, s, n, e, lam, Qcur, (long)n, b,
+    HSDM_LAUNCH(merge_prep_kernel, dim3(cnt), dim3(256), 0, s, n, e, lam, Qcur, (long)n, b,
                        m0);
     HSDM_TRY(hipGetLastError());
-    hipLaunchKernelGGL(qblk_fill_kernel, dim3(ceil_div(maxN, 256), ceil_div(maxN, QB), cnt),
+    HSDM_LAUNCH(qblk_fill_kernel, dim3(ceil_div(maxN, 256), ceil_div(maxN, QB), cnt),
                        dim3(256), 0, s, Qcur, (long)n, b, m0, n);
     HSDM_TRY(hipGetLastError());
-    hipLaunchKernelGGL(qblk_rotate_kernel, dim3(ceil_div(maxN, 256), cnt), dim3(256), 0, s, n, b,
+    HSDM_LAUNCH(qblk_rotate_kernel, dim3(ceil_div(maxN, 256), cnt), dim3(256), 0, s, n, b,
                        m0);
     HSDM_TRY(hipGetLastError());
-    hipLaunchKernelGGL(secular_kernel, dim3(ceil_div(maxN, 4), cnt), dim3(256), 0, s, b, m0, st);
+    HSDM_LAUNCH(secular_kernel, dim3(ceil_div(maxN, 4), cnt), dim3(256), 0, s, b, m0, st);
     HSDM_TRY(hipGetLastError());
-    hipLaunchKernelGGL(zhat_kernel, dim3(ceil_div(maxN, 4), cnt), dim3(256), 0, s, b, m0);
+    HSDM_LAUNCH(zhat_kernel, dim3(ceil_div(maxN, 4), cnt), dim3(256), 0, s, b, m0);
     HSDM_TRY(hipGetLastError());
-    hipLaunchKernelGGL(order_kernel, dim3(ceil_div(maxN, 256), cnt), dim3(256), 0, s, lam, b, m0);
+    HSDM_LAUNCH(order_kernel, dim3(ceil_div(maxN, 256), cnt), dim3(256), 0, s, lam, b, m0);
     HSDM_TRY(hipGetLastError());
     if (final_level) {
       if (hook) HSDM_TRY(hook(hook_ctx, lam, s));
       if (m_dev) {
-        hipLaunchKernelGGL(limit_kernel, dim3(1), dim3(64), 0, s, b, m0, m_dev);
+        HSDM_LAUNCH(limit_kernel, dim3(1), dim3(64), 0, s, b, m0, m_dev);
         HSDM_TRY(hipGetLastError());
       }
     }
-    hipLaunchKernelGGL(vectors_kernel, dim3(maxN, cnt), dim3(256), 0, s, b, m0, n);
+    HSDM_LAUNCH(vectors_kernel, dim3(maxN, cnt), dim3(256), 0, s, b, m0, n);
     HSDM_TRY(hipGetLastError());
-    hipLaunchKernelGGL(desc_kernel, dim3(ceil_div(cnt, 64)), dim3(64), 0, s, b, m0, cnt, Qnext,
+    HSDM_LAUNCH(desc_kernel, dim3(ceil_div(cnt, 64)), dim3(64), 0, s, b, m0, cnt, Qnext,
                        (long)n, n, p->d_desc + 2 * m0);
     HSDM_TRY(hipGetLastError());
     HSDM_TRY(gemm_batched_launch(p->d_desc + 2 * m0, 2 * cnt, (maxN + 1) / 2 + 1, maxN, 1.0, 0.0,
                                  0, 0, 0, s));
-    hipLaunchKernelGGL(deflated_copy_kernel, dim3(ceil_div(maxN, 256), cnt), dim3(256), 0, s, b,
+    HSDM_LAUNCH(deflated_copy_kernel, dim3(ceil_div(maxN, 256), cnt), dim3(256), 0, s, b,
                        m0, Qnext, (long)n, n);
     HSDM_TRY(hipGetLastError());
   }
   const long tot = (long)n * (m_dev ? n : n);
-  hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Qcur,
+  HSDM_LAUNCH(copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Qcur,
                      (long)n, Z, ldz, n, n, m_dev);
   return hipGetLastError();
 }

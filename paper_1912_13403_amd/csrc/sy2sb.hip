@@ -116,6 +116,76 @@ HSDM_DEV double ld_ready(const double* p, DevStatusWord* st) {
   return v;
 }
 
+// The arithmetic both panel kernels share (the fused one and the per-column
+// launches), with every multiply-add written out so that the compiler has
+// no choice of contraction and the two give the same bits.
+struct Reflector {
+  double tau, beta, scal;
+};
+
+// reflector of column j from sigma = sum of squares below the pivot and
+// the pivot alpha: beta = -sign(alpha) sqrt(alpha^2 + sigma),
+// tau = (beta - alpha) / beta, v_i = a_ij / (alpha - beta)
+HSDM_DEV Reflector make_reflector(double sigma, double alpha) {
+  Reflector r{0.0, alpha, 0.0};
+  if (sigma > 0.0) {
+    const double nrm = sqrt(fma(alpha, alpha, sigma));
+    r.beta = (alpha >= 0.0) ? -nrm : nrm;
+    r.tau = (r.beta - alpha) / r.beta;
+    r.scal = 1.0 / (alpha - r.beta);
+  }
+  return r;
+}
+
+// w_k = tau (a_j,j+k + v^T a_:,j+k) for the pivot row value and the sum below it
+HSDM_DEV double reflector_w(const Reflector& r, double row, double dd) {
+  return r.tau * fma(dd, r.scal, row);
+}
+
+// one row's columns j .. j+B-1 (a[0] = column j) after reflector j: below
+// the pivot a_i,j+k -= v_i w_k and a_ij becomes v_i; the pivot row gets
+// a_j,j+k -= w_k and beta
+template <int B>
+HSDM_DEV void reflector_apply(double (&a)[B], bool below, bool piv, const Reflector& r,
+                              const double* wl) {
+  if (below) {
+    const double vi = a[0] * r.scal;
+#pragma unroll
+    for (int k = 1; k < B; k++) a[k] = fma(-vi, wl[k], a[k]);
+    a[0] = vi;
+  } else if (piv) {
+#pragma unroll
+    for (int k = 1; k < B; k++) a[k] -= wl[k];
+    a[0] = r.beta;
+  }
+}
+
+// entry (ca, cb) of V^T V over nrows rows of V held in LDS (zero below the
+// diagonal of the Gram matrix)
+template <int B>
+HSDM_DEV double gram_entry(const double (*Pl)[B + 1], int nrows, int ca, int cb) {
+  double sum = 0.0;
+  if (ca <= cb)
+    for (int i = 0; i < nrows; i++) sum = fma(Pl[i][ca], Pl[i][cb], sum);
+  return sum;
+}
+
+// T (upper triangular, in LDS) from the Gram matrix and the scalars:
+// T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) (V^T v_j)(0:j)
+template <int B>
+HSDM_DEV void form_t(double (*Tl)[B + 1], const double (*Gm)[B + 1], const double* taul) {
+  const int t = threadIdx.x;
+  for (int j = 0; j < B; j++) {
+    if (t < j) {
+      double sum = 0.0;
+      for (int k = t; k < j; k++) sum = fma(Tl[t][k], Gm[k][j], sum);
+      Tl[t][j] = -taul[j] * sum;
+    }
+    if (t == j) Tl[j][j] = taul[j];
+    __syncthreads();
+  }
+}
+
 __global__ void fill_nan_kernel(double* p, long cnt) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < cnt) p[i] = __builtin_nan("");
@@ -206,30 +276,11 @@ HSDM_DEV void panel_qr_body(int h, double* P, long ldp, double* V, long ldv, dou
         }
       }
       __syncthreads();
-      const double sigma = ddl[0];
-      const double alpha = rowl[0];
-      double tau = 0.0, beta = alpha, scal = 0.0;
-      if (sigma > 0.0) {
-        const double nrm = sqrt(alpha * alpha + sigma);
-        beta = (alpha >= 0.0) ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-      }
-      if (t < B) wl[t] = (t >= 1 && t < B - j) ? tau * (rowl[t] + ddl[t] * scal) : 0.0;
-      if (t == 0) taul[j] = tau;
+      const Reflector r = make_reflector(ddl[0], rowl[0]);
+      if (t < B) wl[t] = (t >= 1 && t < B - j) ? reflector_w(r, rowl[t], ddl[t]) : 0.0;
+      if (t == 0) taul[j] = r.tau;
       __syncthreads();
-      // below the pivot a_i,j+k -= (a_ij scal) w_k and a_ij becomes v_i; the
-      // pivot row gets a_j,j+k -= w_k and beta
-      if (below) {
-        const double vi = aj * scal;
-#pragma unroll
-        for (int k = 1; k < B; k++) a[k] -= vi * wl[k];
-        a[0] = vi;
-      } else if (piv) {
-#pragma unroll
-        for (int k = 1; k < B; k++) a[k] -= wl[k];
-        a[0] = beta;
-      }
+      reflector_apply(a, below, piv, r, wl);
     } else if (t == 0) {
       taul[j] = 0.0;
     }
@@ -257,9 +308,7 @@ HSDM_DEV void panel_qr_body(int h, double* P, long ldp, double* V, long ldv, dou
   // partial Gram of this workgroup's rows; workgroup 0 sums them
   for (int e = t; e < B * B; e += NT) {
     const int ca = e % B, cb = e / B;
-    double sum = 0.0;
-    if (ca <= cb)
-      for (int i = 0; i < nrows; i++) sum += Pl[i][ca] * Pl[i][cb];
+    const double sum = gram_entry<B>(Pl, nrows, ca, cb);
     if (g == 0)
       Gm[ca][cb] = sum;
     else
@@ -274,16 +323,136 @@ HSDM_DEV void panel_qr_body(int h, double* P, long ldp, double* V, long ldv, dou
     Tl[ca][cb] = 0.0;
   }
   __syncthreads();
-  // T: T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) (V^T v_j)(0:j)
-  for (int j = 0; j < B; j++) {
-    if (t < j) {
-      double sum = 0.0;
-      for (int k = t; k < j; k++) sum += Tl[t][k] * Gm[k][j];
-      Tl[t][j] = -taul[j] * sum;
+  form_t<B>(Tl, Gm, taul);
+  for (int e = t; e < B * B; e += NT) Tt[e] = Tl[e % B][e / B];
+}
+
+// The same panel QR for a solve that shares the device with other solves
+// (HSDM_KEY_CONCURRENT): the grid-wide exchange per column becomes a kernel
+// boundary, so no workgroup waits for another.  Launch j (j = -1 .. B-1) of
+// panel_step_kernel: for j >= 0 it combines the partial sums of column j
+// that launch j-1 left in `part`, forms reflector j, applies it to the
+// workgroup's rows and writes column j of the result (and of V); then it
+// writes the partial sums of column j + 1 (launch B-1: the workgroup's
+// partial Gram matrix V^T V instead).  panel_t_kernel (one workgroup) sums
+// the Gram partials and forms T.  Every step does the fused kernel's
+// arithmetic in the fused kernel's order, so the two give the same bits.
+template <int B>
+__global__ __launch_bounds__(NT) void panel_step_kernel(int h, double* P, long ldp, double* V,
+                                                        long ldv, double* tau_out, double* part,
+                                                        double* prow, double* gpart, int j) {
+  constexpr int NW = NT / 64;
+  constexpr int RG = NT / B;
+  __shared__ double red[NW][B];
+  __shared__ double ddl[B], wl[B], rowl[B];
+  __shared__ double cmb[RG][B + 1];
+  __shared__ double Pl[CH][B + 1];
+  const int g = blockIdx.x, G = gridDim.x;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int row0 = g * CH;
+  const int nrows = min(CH, h - row0);
+  const int gi = row0 + t;
+  const bool rok = t < nrows;
+  const int ncol = min(B, h);
+  // a[k]: column c0 + k of this thread's row (columns past B read as zero)
+  const int c0 = j < 0 ? 0 : j;
+  double a[B];
+#pragma unroll
+  for (int c = 0; c < B; c++) a[c] = (rok && c0 + c < B) ? P[gi + (long)(c0 + c) * ldp] : 0.0;
+  if (j >= 0 && j < ncol) {
+    const bool below = rok && gi > j;
+    const bool piv = rok && gi == j;
+    const double* pb = part + (size_t)j * G * B;
+    {
+      const int k = t % B, rg = t / B;
+      double s2 = 0.0;
+      if (k < B - j)
+        for (int q = rg; q < G; q += RG) s2 += pb[(size_t)q * B + k];
+      cmb[rg][k] = s2;
     }
-    if (t == j) Tl[j][j] = taul[j];
     __syncthreads();
+    if (t < B) {
+      double s2 = 0.0;
+      for (int r = 0; r < RG; r++) s2 += cmb[r][t];
+      ddl[t] = s2;
+      rowl[t] = prow[(size_t)j * B + t];  // the pivot row as launch j - 1 left it
+    }
+    __syncthreads();
+    const Reflector r = make_reflector(ddl[0], rowl[0]);
+    if (t < B) wl[t] = (t >= 1 && t < B - j) ? reflector_w(r, rowl[t], ddl[t]) : 0.0;
+    __syncthreads();
+    reflector_apply(a, below, piv, r, wl);
+    if (g == 0 && t == 0) tau_out[j] = r.tau;
+    if (rok) {
+#pragma unroll
+      for (int c = 0; c < B; c++)
+        if (j + c < B) P[gi + (long)(j + c) * ldp] = a[c];
+      V[gi + (long)j * ldv] = (gi > j) ? a[0] : (gi == j ? 1.0 : 0.0);
+    }
+  } else if (j >= 0 && g == 0 && t == 0) {
+    tau_out[j] = 0.0;
   }
+  const int jn = j + 1;
+  if (jn < B) {
+    // partial sums of column jn over this workgroup's rows below its pivot
+    const int sh = (j >= 0) ? 1 : 0;  // a[sh + k] holds column jn + k
+    double v[B];
+    if (jn < ncol) {
+      const bool below = rok && gi > jn;
+      const double ajn = sh ? a[1] : a[0];
+#pragma unroll
+      for (int k = 0; k < B; k++) {
+        const double x = (sh + k < B) ? a[sh + k] : 0.0;
+        v[k] = below ? ajn * x : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < B; k++) v[k] = 0.0;
+    }
+    const double ws = wave_reduce_scatter(v);
+    if (lane < 32) red[wv][rs_index(lane)] = ws;
+    // the next pivot row, for every workgroup of the next launch (P itself
+    // changes under them in that launch)
+    if (rok && gi == jn) {
+#pragma unroll
+      for (int k = 0; k < B; k++) prow[(size_t)jn * B + k] = (sh + k < B) ? a[sh + k] : 0.0;
+    }
+    __syncthreads();
+    if (t < B) {
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; w++) sum += red[w][t];
+      part[(size_t)jn * G * B + (size_t)g * B + t] = sum;
+    }
+    return;
+  }
+  // last launch: this workgroup's partial Gram of the explicit V
+  __syncthreads();
+  for (int e = t; e < CH * B; e += NT) {
+    const int r = e % CH, c = e / CH;
+    const int gr = row0 + r;
+    Pl[r][c] = (r < nrows) ? ((gr > c) ? P[gr + (long)c * ldp] : (gr == c ? 1.0 : 0.0)) : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < B * B; e += NT)
+    gpart[(size_t)g * B * B + e] = gram_entry<B>(Pl, nrows, e % B, e / B);
+}
+
+template <int B>
+__global__ __launch_bounds__(NT) void panel_t_kernel(const double* tau, double* Tt,
+                                                     const double* gpart, int G) {
+  __shared__ double Gm[B][B + 1], Tl[B][B + 1], taul[B];
+  const int t = threadIdx.x;
+  if (t < B) taul[t] = tau[t];
+  for (int e = t; e < B * B; e += NT) {
+    const int ca = e % B, cb = e / B;
+    double sum = gpart[e];
+    for (int q = 1; q < G; q++) sum += gpart[(size_t)q * B * B + e];
+    Gm[ca][cb] = sum;
+    Tl[ca][cb] = 0.0;
+  }
+  __syncthreads();
+  form_t<B>(Tl, Gm, taul);
   for (int e = t; e < B * B; e += NT) Tt[e] = Tl[e % B][e / B];
 }
 
@@ -487,7 +656,7 @@ struct Sy2sb {
   hipError_t qr_panel(int p) {
     PanelQrTask q = qr_desc(p);
     if (q.span > 0) {
-      hipLaunchKernelGGL(fill_nan_kernel, dim3((unsigned)((q.span + 255) / 256)), dim3(256), 0, s,
+      HSDM_LAUNCH(fill_nan_kernel, dim3((unsigned)((q.span + 255) / 256)), dim3(256), 0, s,
                          part, q.span);
       HSDM_TRY(hipGetLastError());
     }
@@ -496,11 +665,26 @@ struct Sy2sb {
                     (void*)&q.st};
     // algorithmic: Householder QR of the h x B panel (2 h B^2 flops), the
     // panel read and written once
-    kt_begin("panel_qr_kernel<32>", 2.0 * q.h * B * B, 16.0 * q.h * B, 0, s);
-    HSDM_TRY(hipLaunchCooperativeKernel((const void*)panel_qr_kernel<BB>, dim3(q.G), dim3(NT),
-                                        args, 0, s));
-    kt_end(s);
-    return hipSuccess;
+    if (coop_get_shared()) {
+      // beside other solves: no workgroup waits for another (one launch per
+      // column for several workgroups, an ordinary launch for one)
+      if (q.G == 1) {
+        HSDM_LAUNCH(panel_qr_kernel<BB>, dim3(1), dim3(NT), 0, s, q.h, q.P, q.ldp, q.V, q.ldv,
+                    q.tau, q.T, q.part, q.prow, q.gpart, q.st);
+        return hipGetLastError();
+      }
+      kt_begin("panel_step_kernel<32>", 2.0 * q.h * B * B, 16.0 * q.h * B, 0, s);
+      for (int j = -1; j < BB; j++) {
+        HSDM_LAUNCH(panel_step_kernel<BB>, dim3(q.G), dim3(NT), 0, s, q.h, q.P, q.ldp, q.V,
+                    q.ldv, q.tau, q.part, q.prow, q.gpart, j);
+        HSDM_TRY(hipGetLastError());
+      }
+      HSDM_LAUNCH(panel_t_kernel<BB>, dim3(1), dim3(NT), 0, s, q.tau, q.T, q.gpart, q.G);
+      kt_end(s);
+      return hipGetLastError();
+    }
+    return coop_launch("panel_qr_kernel<32>", 2.0 * q.h * B * B, 16.0 * q.h * B, false, true,
+                       (const void*)panel_qr_kernel<BB>, dim3(q.G), dim3(NT), args, s);
   }
   // W (h x B, ld n, holding X on entry) = X - V M / 2 with Y = V T, X = A[r:, r:] Y,
   // M = Y^T X.  Vp: the panel's V (ld ldv), Tp its T; Y receives V T.
@@ -568,10 +752,10 @@ struct Sy2sb {
       HSDM_TRY(gemm_launch(corr2_args(h, VWc, Wp), s));
     }
     const AtbGroupItem a = atb_item(h, Wp);
-    hipLaunchKernelGGL((atb_partial_kernel<BB>), dim3(a.G), dim3(NT), 0, s, h, a.U, a.ldu, a.W,
+    HSDM_LAUNCH((atb_partial_kernel<BB>), dim3(a.G), dim3(NT), 0, s, h, a.U, a.ldu, a.W,
                        a.ldw, a.part);
     HSDM_TRY(hipGetLastError());
-    hipLaunchKernelGGL((atb_reduce_kernel<BB>), dim3(ceil_div(B * B, 256)), dim3(256), 0, s, a.G,
+    HSDM_LAUNCH((atb_reduce_kernel<BB>), dim3(ceil_div(B * B, 256)), dim3(256), 0, s, a.G,
                        a.part, a.out, a.ldo);
     HSDM_TRY(hipGetLastError());
     return gemm_launch(fix_args(h, Vp, Wp), s);
@@ -653,7 +837,7 @@ struct Sy2sb {
   }
   hipError_t finish() {
     const long tot = (long)n * ldab;
-    hipLaunchKernelGGL(band_extract_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+    HSDM_LAUNCH(band_extract_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
                        n, B, A, lda, AB, ldab);
     return hipGetLastError();
   }
@@ -923,14 +1107,11 @@ hipError_t upload(T* d, const std::vector<T>& v, hipStream_t s) {
 hipError_t launch_qr_group(const QrLaunch& L, const GroupDev& D, double fl, hipStream_t s) {
   PanelQrTask* tasks = D.desc + L.d0;
   const int* map = D.map + L.m0;
-  hipLaunchKernelGGL(fill_nan_group_kernel, dim3(64, L.nd), dim3(256), 0, s, tasks);
+  HSDM_LAUNCH(fill_nan_group_kernel, dim3(64, L.nd), dim3(256), 0, s, tasks);
   HSDM_TRY(hipGetLastError());
   void* args[] = {(void*)&tasks, (void*)&map};
-  kt_begin("panel_qr_group_kernel<32>", fl, 0.0, 0, s);
-  HSDM_TRY(hipLaunchCooperativeKernel((const void*)panel_qr_group_kernel<32>, dim3(L.nwg),
-                                      dim3(NT), args, 0, s));
-  kt_end(s);
-  return hipSuccess;
+  return coop_launch("panel_qr_group_kernel<32>", fl, 0.0, false, true,
+                     (const void*)panel_qr_group_kernel<32>, dim3(L.nwg), dim3(NT), args, s);
 }
 
 hipError_t launch_gemm(const GemmLaunch& L, const GroupDev& D, hipStream_t s) {
@@ -941,10 +1122,10 @@ hipError_t launch_gemm(const GemmLaunch& L, const GroupDev& D, hipStream_t s) {
 
 hipError_t launch_atb(const AtbLaunch& L, const GroupDev& D, hipStream_t s) {
   if (L.nd == 0) return hipSuccess;
-  hipLaunchKernelGGL((atb_partial_group_kernel<32>), dim3(L.nwg), dim3(NT), 0, s, D.atb + L.d0,
+  HSDM_LAUNCH((atb_partial_group_kernel<32>), dim3(L.nwg), dim3(NT), 0, s, D.atb + L.d0,
                      (const int*)(D.atbmap + L.m0));
   HSDM_TRY(hipGetLastError());
-  hipLaunchKernelGGL((atb_reduce_group_kernel<32>), dim3(ceil_div(32 * 32, 256), L.nd), dim3(256),
+  HSDM_LAUNCH((atb_reduce_group_kernel<32>), dim3(ceil_div(32 * 32, 256), L.nd), dim3(256),
                      0, s, (const AtbGroupItem*)(D.atb + L.d0));
   return hipGetLastError();
 }
@@ -952,7 +1133,7 @@ hipError_t launch_atb(const AtbLaunch& L, const GroupDev& D, hipStream_t s) {
 hipError_t launch_copy(const CopyLaunch& L, const GroupDev& D, hipStream_t s) {
   if (L.nd == 0 || L.max_tot <= 0) return hipSuccess;
   const int bx = (int)std::max(1L, std::min(256L, (L.max_tot + 1023) / 1024));
-  hipLaunchKernelGGL(copy_group_kernel, dim3(bx, L.nd), dim3(256), 0, s,
+  HSDM_LAUNCH(copy_group_kernel, dim3(bx, L.nd), dim3(256), 0, s,
                      (const CopyGroupItem*)(D.copy + L.d0));
   return hipGetLastError();
 }

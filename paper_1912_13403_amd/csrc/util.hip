@@ -4,6 +4,8 @@
 #include "hsdm_util.h"
 
 #include <algorithm>
+#include <mutex>
+#include <shared_mutex>
 
 namespace {
 
@@ -145,13 +147,13 @@ inline unsigned grid_for(long tot) {
 
 hipError_t dev_fill(double* a, long lda, int m, int n, double v, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_kernel, dim3(grid_for((long)m * n)), dim3(256), 0, s, a, lda, m, n, v);
+  HSDM_LAUNCH(fill_kernel, dim3(grid_for((long)m * n)), dim3(256), 0, s, a, lda, m, n, v);
   return hipGetLastError();
 }
 
 hipError_t dev_copy(const double* a, long lda, double* b, long ldb, int m, int n, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(copy_kernel, dim3(grid_for((long)m * n)), dim3(256), 0, s, a, lda, b, ldb, m,
+  HSDM_LAUNCH(copy_kernel, dim3(grid_for((long)m * n)), dim3(256), 0, s, a, lda, b, ldb, m,
                      n);
   return hipGetLastError();
 }
@@ -159,28 +161,28 @@ hipError_t dev_copy(const double* a, long lda, double* b, long ldb, int m, int n
 hipError_t dev_sym_full(const double* a, long lda, double* b, long ldb, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   dim3 g(ceil_div(n, 32), ceil_div(n, 32));
-  hipLaunchKernelGGL(sym_full_kernel, g, dim3(256), 0, s, a, lda, b, ldb, n);
+  HSDM_LAUNCH(sym_full_kernel, g, dim3(256), 0, s, a, lda, b, ldb, n);
   return hipGetLastError();
 }
 
 hipError_t dev_mirror_lower(double* a, long lda, int n, hipStream_t s) {
   if (n <= 1) return hipSuccess;
   dim3 g(ceil_div(n, 32), ceil_div(n, 32));
-  hipLaunchKernelGGL(mirror_kernel, g, dim3(256), 0, s, a, lda, n);
+  HSDM_LAUNCH(mirror_kernel, g, dim3(256), 0, s, a, lda, n);
   return hipGetLastError();
 }
 
 hipError_t dev_norm1_sym(const double* a, long lda, int n, double* colsum, double* out,
                          hipStream_t s) {
-  hipLaunchKernelGGL(colsum_kernel, dim3(n), dim3(256), 0, s, a, lda, n, colsum);
+  HSDM_LAUNCH(colsum_kernel, dim3(n), dim3(256), 0, s, a, lda, n, colsum);
   HSDM_TRY(hipGetLastError());
-  hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, s, colsum, n, out);
+  HSDM_LAUNCH(max_kernel, dim3(1), dim3(256), 0, s, colsum, n, out);
   return hipGetLastError();
 }
 
 hipError_t dev_hash_clear(unsigned long long* out, int cnt, hipStream_t s) {
   if (cnt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(hash_clear_kernel, dim3(ceil_div(cnt, 256)), dim3(256), 0, s, out, cnt);
+  HSDM_LAUNCH(hash_clear_kernel, dim3(ceil_div(cnt, 256)), dim3(256), 0, s, out, cnt);
   return hipGetLastError();
 }
 
@@ -189,7 +191,43 @@ hipError_t dev_hash_lower(const void* a, long lda, int n, int cplx, unsigned lon
   if (n <= 0) return hipSuccess;
   const long rows = (long)n * (cplx ? 2 : 1);
   const unsigned gx = (unsigned)std::min<long>(ceil_div(rows, 256), 16);
-  hipLaunchKernelGGL(hash_lower_kernel, dim3(gx, std::min(n, 32768)), dim3(256), 0, s, (const double*)a, lda, n,
+  HSDM_LAUNCH(hash_lower_kernel, dim3(gx, std::min(n, 32768)), dim3(256), 0, s, (const double*)a, lda, n,
                      cplx, out);
   return hipGetLastError();
+}
+
+// ---- the launch gate of concurrent solves -------------------------------
+namespace {
+thread_local bool coop_shared = false;
+std::shared_mutex launch_gate;
+}  // namespace
+
+void coop_set_shared(bool on) { coop_shared = on; }
+bool coop_get_shared() { return coop_shared; }
+
+LaunchGate::LaunchGate() : held(coop_shared) {
+  if (held) launch_gate.lock_shared();
+}
+LaunchGate::~LaunchGate() {
+  if (held) launch_gate.unlock_shared();
+}
+
+hipError_t coop_launch(const char* name, double flops, double bytes, bool whole_phase,
+                       bool cooperative, const void* fn, dim3 grid, dim3 block, void** args,
+                       hipStream_t s, int nbound) {
+  auto launch = [&]() -> hipError_t {
+    kt_begin(name, flops, bytes, nbound, s, whole_phase);
+    hipError_t e = cooperative ? hipLaunchCooperativeKernel(fn, grid, block, args, 0, s)
+                               : hipLaunchKernel(fn, grid, block, args, 0, s);
+    kt_end(s);
+    return e;
+  };
+  if (!coop_shared) return launch();
+  // the gate alone: no other concurrent solve submits until this kernel has
+  // finished, and the device is drained first, so that every workgroup of
+  // the kernel is placed at once on an otherwise idle device
+  std::unique_lock<std::shared_mutex> lk(launch_gate);
+  HSDM_TRY(hipDeviceSynchronize());
+  HSDM_TRY(launch());
+  return hipStreamSynchronize(s);
 }

@@ -36,6 +36,7 @@ HSDM_KEY_DEG_TOL = 3
 HSDM_KEY_TIMING = 4
 HSDM_KEY_STREAMS = 5
 HSDM_KEY_N_STATES = 6
+HSDM_KEY_CONCURRENT = 7
 
 EXPORTED = [
     "hsdm_init", "hsdm_finalize", "hsdm_reinit", "hsdm_set_real", "hsdm_set_int",

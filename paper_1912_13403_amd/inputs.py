@@ -243,3 +243,111 @@ def request_problem(spec, base_problem=None, gram=None):
         Hu, _, S = kpoint_problem(rid % NKPT, n=n, gram=gram)
         return Hu, S
     return real_problem(n, 32.0, 0.1, cfg=1000 + rid, gram=gram)
+
+
+# ---- the request recipe drawn on the device (serving benchmark) -------------------
+#
+# The serving benchmark replays thousands of requests; drawing each one's
+# matrices on the host (an n^3 Gram product per overlap matrix) would take
+# longer than the replay.  request_problem_device draws the same recipe with
+# torch on the GPU, from a per-request seed (its own random streams, not the
+# host generator's numbers), as device tensors in column-major layout.  It
+# holds none of the solver's arithmetic.
+
+
+def _device_seed(*key):
+    return int(np.random.SeedSequence([4, *SEED_TAIL, *key]).generate_state(1, dtype=np.uint64)[0]
+               & ((1 << 62) - 1))
+
+
+def _device_banded(torch, gen, n, std, decay, width, dev, cplx=True):
+    i = torch.arange(n, device=dev)
+    d = (i[:, None] - i[None, :]).abs()
+    env = torch.exp(-d.double() / decay) * (d <= width)
+    re = torch.randn(n, n, generator=gen, device=dev, dtype=torch.float64)
+    im = torch.randn(n, n, generator=gen, device=dev, dtype=torch.float64)
+    return torch.complex(re, im) * (std * env) if cplx else re * (std * env)
+
+
+def _device_s(torch, spec, dev):
+    """Overlap matrix of a (non-repeat) request, drawn on the device."""
+    n, rid = spec["n"], spec["rid"]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(_device_seed(rid, 0))
+    B = torch.randn(n, n, generator=gen, device=dev, dtype=torch.float64)
+    S = (0.1 / n) * (B @ B.T)
+    del B
+    S = 0.5 * (S + S.T) + torch.eye(n, device=dev, dtype=torch.float64)
+    if not spec["cplx"]:
+        return S
+    k = kpoints()[rid % NKPT]
+    Sc = S.to(torch.complex128)
+    del S
+    for axis in range(3):
+        ph = complex(np.exp(2j * np.pi * k[axis]))
+        SR = _device_banded(torch, gen, n, 1.0, 8.0, 16, dev)
+        SR *= 0.1 / max(SR.abs().sum(dim=0).max().item(), SR.abs().sum(dim=1).max().item())
+        Sc += 0.5 * (ph * SR + np.conj(ph) * SR.conj().T)
+        del SR
+    return Sc
+
+
+def _device_h(torch, spec, dev):
+    """Hamiltonian of a (non-repeat) request, drawn on the device."""
+    n, rid = spec["n"], spec["rid"]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(_device_seed(rid, 1))
+    i = torch.arange(n, device=dev)
+    env = torch.exp(-(i[:, None] - i[None, :]).abs().double() / 32.0)
+    G = 0.1 * torch.randn(n, n, generator=gen, device=dev, dtype=torch.float64)
+    U = torch.triu(G * env, 1)
+    del G, env
+    H = U + U.T
+    del U
+    H.diagonal().copy_(-1.0 + 2.0 * torch.rand(n, generator=gen, device=dev, dtype=torch.float64))
+    if not spec["cplx"]:
+        return H
+    k = kpoints()[rid % NKPT]
+    Hc = H.to(torch.complex128)
+    del H
+    for axis in range(3):
+        ph = complex(np.exp(2j * np.pi * k[axis]))
+        HR = _device_banded(torch, gen, n, 0.05, 32.0, 64, dev)
+        Hc += 0.5 * (ph * HR + np.conj(ph) * HR.conj().T)
+        del HR
+    Hc.diagonal().add_(0.05 * torch.rand(n, generator=gen, device=dev, dtype=torch.float64))
+    return Hc
+
+
+def _colmajor_view(torch, X):
+    """The same (symmetric or Hermitian) matrix as a column-major tensor:
+    for a Hermitian X stored row-major, its conjugate's transposed view is X."""
+    if X.is_complex():
+        return torch.conj_physical(X).t()
+    return X.t()
+
+
+def request_problem_device(spec, base_spec=None, S=None, dev=None):
+    """(H, S) of a request as column-major device tensors drawn on the GPU by
+    the recipe of request_problem (per-request seeds; a repeat draws its base
+    request's H again and adds 1e-3 Z).  S: the base request's overlap matrix
+    when it is still on the device (returned as is), else drawn."""
+    import torch
+    base = spec if not spec["repeat"] else base_spec
+    if S is None:
+        S = _colmajor_view(torch, _device_s(torch, base, dev))
+    H = _device_h(torch, base, dev)
+    if spec["repeat"]:
+        n = spec["n"]
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(_device_seed(spec["rid"], 2))
+        Z = torch.randn(n, n, generator=gen, device=dev, dtype=torch.float64)
+        if spec["cplx"]:
+            Z = torch.complex(Z, torch.randn(n, n, generator=gen, device=dev, dtype=torch.float64))
+            Z = (torch.tril(Z, -1) + torch.tril(Z, -1).conj().T
+                 + torch.diag(torch.diagonal(Z).real).to(Z.dtype))
+        else:
+            Z = torch.tril(Z) + torch.tril(Z, -1).T
+        H = H + 1e-3 * Z
+        del Z
+    return _colmajor_view(torch, H), S

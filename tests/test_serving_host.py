@@ -3,7 +3,7 @@ request stream recipe."""
 import numpy as np
 
 from paper_1912_13403_amd import inputs
-from paper_1912_13403_amd.serving import admit, request_bytes
+from paper_1912_13403_amd.serving import admit, pick_slot, request_bytes, start_bytes
 
 
 def _tb(n, cplx):
@@ -57,3 +57,17 @@ def test_repeat_shares_s_and_perturbs_h():
             assert 1e-4 < np.abs(d).max() < 1e-2
             lo = np.tril(d)
             assert np.allclose(d, lo + np.tril(d, -1).conj().T)
+
+
+def test_slot_choice_and_start_bytes():
+    # a repeat goes to the slot that factored its S when that slot is free
+    aff = {7: 2}
+    assert pick_slot(dict(base=7), {0, 2, 3}, aff) == 2
+    assert pick_slot(dict(base=7), {0, 3}, aff) == 0
+    assert pick_slot(dict(base=9), {3, 1}, aff) == 1
+    # bytes a request adds: H, D, E, S unless resident, workspace growth only
+    r = dict(n=1000, cplx=False)
+    m = 1000 * 1000 * 8.0
+    assert start_bytes(r, 0.0, _tb, False) == 4 * m + _tb(1000, False)
+    assert start_bytes(r, 0.0, _tb, True) == 3 * m + _tb(1000, False)
+    assert start_bytes(r, 1e12, _tb, True) == 3 * m
