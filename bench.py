@@ -377,7 +377,8 @@ def serving_main(args):
     specs = inputs.request_specs(args.requests, rate=40.0, lo=256, hi=8192, seed=0)
     make = lambda req, S: inputs.request_problem_device(req, specs[req["base"]], S, dev)
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
-    srv = serving.Server(0, hbm_budget=200e9, slots=args.slots)
+    srv = serving.Server(0, hbm_budget=200e9, slots=args.slots, max_group=args.group,
+                         streams=MT_STREAMS if args.group > 1 else 0)
     # warmup: a short stream of small requests (kernels loaded, workspaces made)
     wspecs = inputs.request_specs(2 * args.slots, rate=1000.0, lo=256, hi=512, seed=99)
     wmake = lambda req, S: inputs.request_problem_device(req, wspecs[req["base"]], S, dev)
@@ -410,14 +411,16 @@ def serving_main(args):
         "config": {"workload": f"cfg4_serving: {len(specs)} requests, Poisson 40/s, n log-uniform "
                                "[256, 8192], 60% real / 40% Hermitian FP64, 30% SCF repeats, "
                                "HBM budget 200 GB, continuous batching over "
-                               f"{args.slots} slots (inputs drawn on the device at dispatch)",
-                   "requests": len(specs), "slots": args.slots,
+                               f"{args.slots} slots, up to {args.group} requests per start "
+                               "(inputs drawn on the device at dispatch)",
+                   "requests": len(specs), "slots": args.slots, "max_group": args.group,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "p99_s": summ["p99_s"],
         "mean_latency_s": summ["mean_s"],
         "solves_per_s": summ["solves_per_s"],
         "offered_rate_per_s": 40.0,
         "mean_requests_on_device_at_start": float(conc.mean()),
+        "mean_group": summ["mean_group"],
         "max_requests_on_device": int(conc.max()),
         "timed_total_s": wall,
         "roofline": None,
@@ -433,7 +436,10 @@ def main():
     ap.add_argument("--config", default="cfg2_n16384")
     ap.add_argument("--requests", type=int, default=2000,
                     help="requests replayed by --config cfg4_serving")
-    ap.add_argument("--slots", type=int, default=4,
+    ap.add_argument("--group", type=int, default=16,
+                    help="most requests started together on a slot by --config cfg4_serving "
+                         "(1: single solves)")
+    ap.add_argument("--slots", type=int, default=2,
                     help="concurrent request slots of --config cfg4_serving")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-warm", action="store_true",

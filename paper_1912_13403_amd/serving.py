@@ -2,17 +2,21 @@
 
 Requests (real or Hermitian, any size) arrive over time.  The server keeps a
 few slots; each slot is a host thread with its own library handle (marked
-concurrent, HSDM_KEY_CONCURRENT) and its own stream, so the solves of
-different slots overlap on the device.  Whenever a slot is free, the request
-at the head of the queue (arrival order, no overtaking) starts on it if its
-device memory fits the HBM budget beside everything in use; a request that
+concurrent, HSDM_KEY_CONCURRENT) and its own stream, so the work of
+different slots overlaps on the device.  Whenever a slot is free, the
+request at the head of the queue (arrival order, no overtaking) starts on it
+if its device memory fits the HBM budget beside everything in use, together
+with the requests queued behind it while they fit and the group size allows
+(max_group): one request runs through the single-solve entry points, several
+through hsdm_solve_dm_group, each with its own occupations.  A request that
 arrives while others run is admitted as soon as a slot and memory free up.
 
 A request that repeats an earlier request's S (the SCF steps of one
 geometry, the re-initialization semantics of Sec. 2.7) finds that S still
-resident on the device, and is sent to the slot whose handle factored it
-when that slot is free: the library keeps the factor of S per handle, keyed
-by the content of S, so the Cholesky factorization is skipped.
+resident on the device, and its group is sent to the slot whose handle
+factored it when that slot is free: the library keeps the factor of S per
+handle (per task context in a group), keyed by the content of S, so the
+Cholesky factorization is skipped.
 
 Latency is completion minus arrival on the host clock.  Inputs come from a
 `make(spec, base, device)` callable run on the slot's stream (host arrays
@@ -20,9 +24,9 @@ copied in, or matrices drawn on the device).
 
 Memory accounting (the budget covers the slots' library workspaces, the
 resident overlap matrices and each running request's H, D and E): a slot's
-handle keeps the workspace of its last request; resident overlap matrices
-beyond half the budget are dropped, oldest first, unless a running request
-uses them.
+handle keeps the workspace of its last solve, trimmed before a group to what
+the budget leaves (hsdm_release_tasks); resident overlap matrices beyond half
+the budget are dropped, oldest first, unless a running request uses them.
 """
 from __future__ import annotations
 
@@ -41,33 +45,34 @@ def matrix_bytes(n: int, cplx: bool) -> float:
     return float(n) * n * (16.0 if cplx else 8.0)
 
 
-def request_bytes(n: int, cplx: bool, task_bytes) -> float:
-    """Device bytes a request needs while it runs: its task context and H, D,
-    E (S is accounted with the resident overlap matrices)."""
-    return task_bytes(n, cplx) + 3.0 * matrix_bytes(n, cplx)
-
-
-def admit(queue_, budget, resident, task_bytes):
-    """Requests of `queue_` (arrival order) that fit together: the longest
-    prefix whose needs plus the resident bytes fit the budget, and at least
-    the first request.  Returns (admitted, their bytes)."""
-    out, need = [], 0.0
-    for r in queue_:
-        b = request_bytes(r["n"], r["cplx"], task_bytes)
-        if out and resident + need + b > budget:
+def take_group(waiting, max_group, budget, in_use, slot_held, busy, resident, task_bytes):
+    """The requests that start together on a free slot whose handle holds
+    slot_held bytes of workspace, with in_use bytes in use on the device
+    (every slot's workspace, the resident overlap matrices, the running
+    requests' matrices): the head of the queue (alone when nothing else runs,
+    even over the budget) and the requests behind it, in arrival order,
+    while their bytes fit and the group has fewer than max_group.  A request
+    adds H, D, E, its S unless resident (`resident`: base ids on the
+    device, or shared with an earlier member), and its task context beyond
+    what the slot already holds.  Returns (requests, bytes they add, the
+    room left for the slot's workspace)."""
+    group, mats, tasks = [], 0.0, 0.0
+    bases = set(resident)
+    for r in waiting[:max_group]:
+        m = 3.0 * matrix_bytes(r["n"], r["cplx"])
+        if r["base"] not in bases:
+            m += matrix_bytes(r["n"], r["cplx"])
+        t = task_bytes(r["n"], r["cplx"])
+        add = mats + m + max(0.0, tasks + t - slot_held)
+        if (group or busy) and in_use + add > budget:
             break
-        out.append(r)
-        need += b
-    return out, need
-
-
-def start_bytes(req, slot_held, task_bytes, s_resident):
-    """Extra device bytes a request adds when it starts on a slot whose
-    handle holds slot_held bytes of workspace: its matrices H, D, E, its S
-    unless resident, and the growth of the slot's workspace."""
-    n, cplx = req["n"], req["cplx"]
-    extra = 3.0 * matrix_bytes(n, cplx) + (0.0 if s_resident else matrix_bytes(n, cplx))
-    return extra + max(0.0, task_bytes(n, cplx) - slot_held)
+        group.append(r)
+        bases.add(r["base"])
+        mats += m
+        tasks += t
+    need = mats + max(0.0, tasks - slot_held)
+    room = max(tasks, budget - (in_use - slot_held) - mats)
+    return group, need, room
 
 
 def pick_slot(req, free_slots, affinity):
@@ -80,13 +85,15 @@ def pick_slot(req, free_slots, affinity):
 
 
 class _Slot:
-    def __init__(self, idx, device, outbox, timing_level):
+    def __init__(self, idx, device, outbox, timing_level, streams):
         self.idx = idx
         self.device = device
         self.outbox = outbox
         self.inbox = queue.Queue()
         self.h = hsdm.Handle(device)
         self.h.hsdm_set_int(hsdm.HSDM_KEY_CONCURRENT, 1)
+        if streams:
+            self.h.hsdm_set_int(hsdm.HSDM_KEY_STREAMS, streams)
         if timing_level:
             self.h.hsdm_set_int(hsdm.HSDM_KEY_TIMING, timing_level)
         self.held = 0.0  # workspace bytes the handle keeps after its last request
@@ -100,26 +107,38 @@ class _Slot:
             job = self.inbox.get()
             if job is None:
                 break
-            req, S_in, make, keep_out, t0, clock = job
+            reqs, S_in, make, keep_out, grouped, trim, t0, clock = job
             try:
                 with torch.cuda.stream(stream):
                     start = clock() - t0
-                    H, S = make(req, S_in)
-                    if S_in is None:
-                        stream.synchronize()  # S is shared with later repeats on other slots
-                    f = self.h.hsdm_solve_dm_complex if req["cplx"] else self.h.hsdm_solve_dm_real
-                    self.h.hsdm_set_real(hsdm.HSDM_KEY_FMAX, req["f_max"])
-                    o = f(H, S, req["n_electrons"], req["kT"])
+                    if trim is not None:
+                        self.h.hsdm_release_tasks(trim)
+                    mats = [make(r, S) for r, S in zip(reqs, S_in)]
+                    # a fresh S is shared with later repeats on other slots
+                    stream.synchronize()
+                    if not grouped:
+                        r, (H, S) = reqs[0], mats[0]
+                        f = self.h.hsdm_solve_dm_complex if r["cplx"] else self.h.hsdm_solve_dm_real
+                        self.h.hsdm_set_real(hsdm.HSDM_KEY_FMAX, r["f_max"])
+                        outs = [f(H, S, r["n_electrons"], r["kT"])]
+                    else:
+                        outs = self.h.hsdm_solve_dm_group(
+                            [dict(H=H, S=S, n_electrons=r["n_electrons"], kT=r["kT"],
+                                  f_max=r["f_max"]) for r, (H, S) in zip(reqs, mats)])
                     stream.synchronize()
                     done = clock() - t0
                     held = self.h.hsdm_workspace_bytes()
-                    res = dict(mu=o["mu"], band_energy=o["band_energy"], start=start, done=done)
-                    if keep_out:
-                        res["D"], res["E"] = o["D"], o["E"]
-                    del H, o
-                self.outbox.put((self.idx, req, S, res, held, None))
+                    res = []
+                    for o, k in zip(outs, keep_out):
+                        x = dict(mu=o["mu"], band_energy=o["band_energy"], start=start, done=done)
+                        if k:
+                            x["D"], x["E"] = o["D"], o["E"]
+                        res.append(x)
+                    Ss = [S for _, S in mats]
+                    del mats, outs
+                self.outbox.put((self.idx, reqs, Ss, res, held, None))
             except Exception as e:  # reported by the dispatcher
-                self.outbox.put((self.idx, req, None, None, self.held, e))
+                self.outbox.put((self.idx, reqs, None, None, self.held, e))
 
     def close(self):
         self.inbox.put(None)
@@ -128,11 +147,14 @@ class _Slot:
 
 
 class Server:
-    def __init__(self, device=0, hbm_budget=200e9, slots=4, timing_level=0):
+    def __init__(self, device=0, hbm_budget=200e9, slots=4, timing_level=0, max_group=1,
+                 streams=0):
         self.dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self.budget = float(hbm_budget)
+        self.max_group = int(max_group)
         self.outbox = queue.Queue()
-        self.slots = [_Slot(k, self.dev, self.outbox, timing_level) for k in range(slots)]
+        self.slots = [_Slot(k, self.dev, self.outbox, timing_level, streams)
+                      for k in range(slots)]
         self.s_dev = OrderedDict()  # base request id -> resident S on the device
         self.s_users = {}           # base request id -> running requests using it
         self.affinity = {}          # base request id -> slot whose handle factored its S
@@ -146,45 +168,53 @@ class Server:
         return sum(matrix_bytes(x.shape[0], x.dtype == torch.complex128)
                    for x in self.s_dev.values())
 
-    def run(self, requests, make, keep=None, clock=time.perf_counter, log=None, warm=False):
+    def run(self, requests, make, keep=None, clock=time.perf_counter, log=None):
         """Replay `requests` (dicts with rid, arrival, n, cplx, base, repeat,
         n_electrons, kT, f_max; sorted by arrival) against the clock;
         make(req, S or None) -> device (H, S) on the calling slot's stream.
         Returns one record per request: rid, arrival, start, done, latency,
-        slot, concurrent (requests running when it started), mu,
-        band_energy, and D, E when keep(rid) is true."""
+        slot, group (requests solved with it), concurrent (requests on the
+        device when it started, itself excluded), mu, band_energy, and D, E
+        when keep(rid) is true."""
         pending = list(requests)
         waiting, records = [], []
         free = set(range(len(self.slots)))
-        running = {}  # slot -> (request, matrix bytes)
+        running = {}  # slot -> (requests, bytes they added)
         t0 = clock()
-        task_bytes = hsdm.hsdm_task_bytes
         while pending or waiting or running:
             now = clock() - t0
             while pending and pending[0]["arrival"] <= now:
                 waiting.append(pending.pop(0))
-            # start the head of the queue while a slot and memory are free
+            # start the head of the queue (and those behind it) while a slot
+            # and memory are free
             while waiting and free:
-                req = waiting[0]
-                k = pick_slot(req, free, self.affinity)
-                res_s = req["base"] in self.s_dev
+                k = pick_slot(waiting[0], free, self.affinity)
+                slot = self.slots[k]
                 in_use = (sum(s.held for s in self.slots) + self._resident_bytes()
                           + sum(b for _, b in running.values()))
-                need = start_bytes(req, self.slots[k].held, task_bytes, res_s)
-                if running and in_use + need > self.budget:
+                group, need, room = take_group(waiting, self.max_group, self.budget, in_use,
+                                               slot.held, bool(running), self.s_dev,
+                                               hsdm.hsdm_task_bytes)
+                if not group:
                     break
-                waiting.pop(0)
+                del waiting[:len(group)]
                 free.discard(k)
-                mats = 3.0 * matrix_bytes(req["n"], req["cplx"])
-                running[k] = (req, mats + max(0.0, task_bytes(req["n"], req["cplx"])
-                                             - self.slots[k].held))
-                S = self.s_dev.get(req["base"])
-                if S is not None:
-                    self.s_dev.move_to_end(req["base"])
-                self.s_users[req["base"]] = self.s_users.get(req["base"], 0) + 1
-                req = dict(req, concurrent=len(running) - 1)
-                keep_out = keep is not None and keep(req["rid"])
-                self.slots[k].inbox.put((req, S, make, keep_out, t0, clock))
+                running[k] = (group, need)
+                S_in = []
+                for r in group:
+                    S = self.s_dev.get(r["base"])
+                    if S is not None:
+                        self.s_dev.move_to_end(r["base"])
+                    S_in.append(S)
+                    self.s_users[r["base"]] = self.s_users.get(r["base"], 0) + 1
+                on_dev = sum(len(g) for g, _ in running.values())
+                group = [dict(r, concurrent=on_dev - 1, group=len(group)) for r in group]
+                keep_out = [keep is not None and keep(r["rid"]) for r in group]
+                # the slot's task contexts are trimmed to the room the budget
+                # leaves (that waits for the device) only when they exceed it
+                trim = room if self.max_group > 1 and slot.held > room else None
+                slot.inbox.put((group, S_in, make, keep_out, self.max_group > 1, trim, t0,
+                                clock))
             # wait for a completion or the next arrival
             timeout = None
             if pending and (not waiting or free):
@@ -194,19 +224,27 @@ class Server:
                     time.sleep(timeout)
                 continue
             try:
-                k, req, S, res, held, err = self.outbox.get(timeout=timeout)
+                k, group, Ss, res, held, err = self.outbox.get(timeout=timeout)
             except queue.Empty:
                 continue
             if err is not None:
-                raise RuntimeError(f"request {req['rid']} failed on slot {k}") from err
+                rids = [r["rid"] for r in group]
+                raise RuntimeError(f"requests {rids} failed on slot {k}") from err
             running.pop(k)
             free.add(k)
             self.slots[k].held = held
-            self.affinity[req["base"]] = k
-            b = req["base"]
-            self.s_users[b] -= 1
-            if b not in self.s_dev:
-                self.s_dev[b] = S
+            for r, S, x in zip(group, Ss, res):
+                b = r["base"]
+                self.affinity[b] = k
+                self.s_users[b] -= 1
+                if b not in self.s_dev:
+                    self.s_dev[b] = S
+                rec = dict(rid=r["rid"], arrival=r["arrival"], start=x["start"], done=x["done"],
+                           latency=x["done"] - r["arrival"], slot=k, group=r["group"],
+                           concurrent=r["concurrent"], mu=x["mu"], band_energy=x["band_energy"])
+                if "D" in x:
+                    rec["D"], rec["E"] = x["D"], x["E"]
+                records.append(rec)
             # resident overlap matrices beyond half the budget go, oldest
             # first, unless a running request uses them
             for old in list(self.s_dev):
@@ -214,14 +252,7 @@ class Server:
                     break
                 if self.s_users.get(old, 0) == 0:
                     self.s_dev.pop(old)
-            rec = dict(rid=req["rid"], arrival=req["arrival"], start=res["start"],
-                       done=res["done"], latency=res["done"] - req["arrival"], slot=k,
-                       concurrent=req["concurrent"], mu=res["mu"],
-                       band_energy=res["band_energy"])
-            if "D" in res:
-                rec["D"], rec["E"] = res["D"], res["E"]
-            records.append(rec)
-            if log and len(records) % 50 == 0:
+            if log and len(records) // 50 != (len(records) - len(group)) // 50:
                 log(f"{len(records)} done, {len(waiting)} waiting, {len(pending)} to arrive, "
                     f"t = {clock() - t0:.1f} s")
         return records
@@ -246,4 +277,5 @@ def summarize(records):
     return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "mean_s": float(lat.mean()), "solves_per_s": len(records) / span,
             "requests": len(records),
-            "max_concurrent": max(r["concurrent"] for r in records) + 1}
+            "max_concurrent": max(r["concurrent"] for r in records) + 1,
+            "mean_group": float(np.mean([r["group"] for r in records]))}

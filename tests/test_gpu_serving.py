@@ -1,7 +1,8 @@
 """The serving loop on the GPU: a mixed stream of real and Hermitian requests
-with SCF repeats, solved in rounds through hsdm_solve_dm_group; every result
-in the mix equals the same request solved alone (single-solve entry points)
-within the parity tolerance, and the smaller ones equal the oracle."""
+with SCF repeats, started on free slots while other requests run (single
+solves, or groups through hsdm_solve_dm_group); every result in the mix
+equals the same request solved alone (single-solve entry points) within the
+parity tolerance, and the smaller ones equal the oracle."""
 import numpy as np
 import pytest
 
@@ -42,18 +43,23 @@ def _alone(torch_dev, r):
         return o["D"].cpu().numpy(), o["E"].cpu().numpy(), o["mu"], o["band_energy"]
 
 
-@pytest.mark.parametrize("budget", [200e9, 0.0])
-def test_each_result_same_alone_and_in_the_mix(oracle, torch_dev, budget):
+@pytest.mark.parametrize("budget,group", [(200e9, 1), (0.0, 1), (200e9, 4)])
+def test_each_result_same_alone_and_in_the_mix(oracle, torch_dev, budget, group):
     from paper_1912_13403_amd.serving import Server, host_maker
     reqs = _stream(12, seed=11, lo=40, hi=500)
-    print(f"[serving] budget={budget:g} sizes={[r['n'] for r in reqs]}", flush=True)
+    print(f"[serving] budget={budget:g} group={group} sizes={[r['n'] for r in reqs]}",
+          flush=True)
     problems = {r["rid"]: (r["H"], r["S"]) for r in reqs}
-    srv = Server(0, hbm_budget=budget, slots=4)
+    srv = Server(0, hbm_budget=budget, slots=2 if group > 1 else 4, max_group=group,
+                 streams=3 if group > 1 else 0)
     try:
         recs = srv.run(reqs, host_maker(problems), keep=lambda rid: True)
     finally:
         srv.close()
     assert sorted(r["rid"] for r in recs) == list(range(len(reqs)))
+    assert all(r["group"] <= group for r in recs)
+    if group > 1:
+        assert max(r["group"] for r in recs) > 1
     if budget == 0.0:
         assert all(r["concurrent"] == 0 for r in recs)  # one request at a time
     else:
@@ -78,7 +84,8 @@ def test_each_result_same_alone_and_in_the_mix(oracle, torch_dev, budget):
             assert np.max(np.abs(rec["D"].cpu().numpy() - ref["D"])) <= 1e-9
 
 
-def test_device_drawn_requests_in_the_mix(torch_dev):
+@pytest.mark.parametrize("group", [1, 4])
+def test_device_drawn_requests_in_the_mix(torch_dev, group):
     """The benchmark's device-drawn request stream (per-request seeds, SCF
     repeats reusing the resident S on the slot that factored it): every
     result equals the same request solved alone."""
@@ -87,7 +94,8 @@ def test_device_drawn_requests_in_the_mix(torch_dev):
     torch, dev = torch_dev
     specs = inputs.request_specs(16, rate=1000.0, lo=64, hi=600, seed=21)
     make = lambda req, S: inputs.request_problem_device(req, specs[req["base"]], S, dev)
-    srv = Server(0, hbm_budget=200e9, slots=3)
+    srv = Server(0, hbm_budget=200e9, slots=3 if group == 1 else 2, max_group=group,
+                 streams=3 if group > 1 else 0)
     try:
         recs = srv.run(specs, make, keep=lambda rid: True)
     finally:

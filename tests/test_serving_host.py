@@ -3,27 +3,59 @@ request stream recipe."""
 import numpy as np
 
 from paper_1912_13403_amd import inputs
-from paper_1912_13403_amd.serving import admit, pick_slot, request_bytes, start_bytes
+from paper_1912_13403_amd.serving import matrix_bytes, pick_slot, take_group
 
 
 def _tb(n, cplx):
     return (2.0 if cplx else 1.0) * 10.0 * n * n * 8.0
 
 
-def test_admission_prefix_fits_budget():
-    q = [dict(n=1000, cplx=False), dict(n=2000, cplx=True), dict(n=500, cplx=False)]
-    b = [request_bytes(r["n"], r["cplx"], _tb) for r in q]
-    got, need = admit(q, budget=b[0] + b[1] + 1.0, resident=0.0, task_bytes=_tb)
+def _req(n, cplx=False, base=None, rid=0):
+    return dict(n=n, cplx=cplx, base=rid if base is None else base, rid=rid)
+
+
+def _bytes(r, s_resident=False, held=0.0):
+    m = matrix_bytes(r["n"], r["cplx"])
+    return 3 * m + (0.0 if s_resident else m) + max(0.0, _tb(r["n"], r["cplx"]) - held)
+
+
+def test_group_prefix_fits_budget():
+    q = [_req(1000, rid=0), _req(2000, True, rid=1), _req(500, rid=2)]
+    b = [_bytes(r) for r in q]
+    got, need, _ = take_group(q, 8, b[0] + b[1] + 1.0, 0.0, 0.0, False, set(), _tb)
     assert got == q[:2] and need == b[0] + b[1]
-    # the first request is always admitted, even alone over the budget
-    got, need = admit(q, budget=1.0, resident=0.0, task_bytes=_tb)
-    assert got == q[:1]
-    # resident bytes count against the budget
-    got, _ = admit(q, budget=sum(b), resident=b[2] - 1.0, task_bytes=_tb)
+    # the head starts alone over the budget when nothing else runs ...
+    got, need, _ = take_group(q, 8, 1.0, 0.0, 0.0, False, set(), _tb)
+    assert got == q[:1] and need == b[0]
+    # ... and waits when something does
+    got, _, _ = take_group(q, 8, 1.0, 0.0, 0.0, True, set(), _tb)
+    assert got == []
+    # bytes in use count against the budget
+    got, _, _ = take_group(q, 8, sum(b), b[2] - 1.0, 0.0, False, set(), _tb)
     assert got == q[:2]
     # arrival order is kept: a later small request does not overtake
-    got, _ = admit(q, budget=b[0] + b[2] + 1.0, resident=0.0, task_bytes=_tb)
+    got, _, _ = take_group(q, 8, b[0] + b[2] + 1.0, 0.0, 0.0, False, set(), _tb)
     assert got == q[:1]
+    # the group size cap
+    got, _, _ = take_group(q, 2, 1e15, 0.0, 0.0, False, set(), _tb)
+    assert got == q[:2]
+
+
+def test_group_bytes_resident_s_and_held_workspace():
+    # a resident S, or one shared with an earlier member, is not counted again
+    q = [_req(1000, rid=0), _req(1000, base=0, rid=1)]
+    got, need, _ = take_group(q, 8, 1e15, 0.0, 0.0, False, set(), _tb)
+    assert need == _bytes(q[0]) + _bytes(q[1], s_resident=True)
+    got, need, _ = take_group(q, 8, 1e15, 0.0, 0.0, False, {0}, _tb)
+    assert need == _bytes(q[0], True) + _bytes(q[1], True)
+    # the slot's workspace covers the task contexts it already holds
+    t = _tb(1000, False)
+    got, need, room = take_group(q[:1], 8, 1e15, 5 * t, 5 * t, False, set(), _tb)
+    assert need == 4 * matrix_bytes(1000, False)
+    # room for the slot's workspace: the budget less everything else in use
+    budget = 100 * t
+    got, need, room = take_group(q[:1], 8, budget, 7 * t, 5 * t, False, set(), _tb)
+    assert room == budget - 2 * t - 4 * matrix_bytes(1000, False)
 
 
 def test_request_stream_recipe():
@@ -59,15 +91,9 @@ def test_repeat_shares_s_and_perturbs_h():
             assert np.allclose(d, lo + np.tril(d, -1).conj().T)
 
 
-def test_slot_choice_and_start_bytes():
+def test_slot_choice():
     # a repeat goes to the slot that factored its S when that slot is free
     aff = {7: 2}
     assert pick_slot(dict(base=7), {0, 2, 3}, aff) == 2
     assert pick_slot(dict(base=7), {0, 3}, aff) == 0
     assert pick_slot(dict(base=9), {3, 1}, aff) == 1
-    # bytes a request adds: H, D, E, S unless resident, workspace growth only
-    r = dict(n=1000, cplx=False)
-    m = 1000 * 1000 * 8.0
-    assert start_bytes(r, 0.0, _tb, False) == 4 * m + _tb(1000, False)
-    assert start_bytes(r, 0.0, _tb, True) == 3 * m + _tb(1000, False)
-    assert start_bytes(r, 1e12, _tb, True) == 3 * m
