@@ -1,9 +1,9 @@
 """Summaries of rocprofv3 output for the kernels of the solve.
 
   python -m paper_1912_13403_amd.profiling stats DIR
-      per-kernel calls / total / average duration from the *_kernel_stats.csv
-      (or *_kernel_trace.csv) that `rocprofv3 --kernel-trace --stats
-      --output-format csv -d DIR` wrote.
+      per-kernel calls / total / average duration from the *_kernel_trace.csv
+      that `rocprofv3 --kernel-trace --stats --output-format csv -d DIR`
+      wrote, or from the *_results.db of the default (rocpd) output format.
 
   python -m paper_1912_13403_amd.profiling traffic FETCH_DIR WRITE_DIR OUT.json
       mean FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of every kernel from two
@@ -58,9 +58,30 @@ def _short(name):
     return name[:i] if i > 0 else name
 
 
+def _stats_db(path):
+    """name -> (calls, total_ms, mean_us) from a rocpd database (the default
+    output format of rocprofv3)."""
+    import sqlite3
+    con = sqlite3.connect(path)
+    agg = {}
+    q = ("select coalesce(s.display_name, s.kernel_name), d.start, d.end "
+         "from rocpd_kernel_dispatch d "
+         "join rocpd_info_kernel_symbol s on d.kernel_id = s.id")
+    for name, t0, t1 in con.execute(q):
+        a = agg.setdefault(_short(name), [0, 0.0])
+        a[0] += 1
+        a[1] += (t1 - t0) * 1e-6
+    con.close()
+    return {k: (v[0], v[1], 1e3 * v[1] / v[0]) for k, v in agg.items()}
+
+
 def stats(d):
-    """name -> (calls, total_ms, mean_us) from a kernel trace csv."""
-    path = _find(d, "*kernel_trace.csv")
+    """name -> (calls, total_ms, mean_us) from a kernel trace csv, or from the
+    rocpd database when no csv was written."""
+    try:
+        path = _find(d, "*kernel_trace.csv")
+    except FileNotFoundError:
+        return _stats_db(_find(d, "*_results.db"))
     agg = {}
     with open(path) as fh:
         for row in csv.DictReader(fh):
