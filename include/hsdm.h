@@ -64,15 +64,34 @@ enum hsdm_key {
                               process hardware queues (GPU_MAX_HW_QUEUES) */
   , HSDM_KEY_CONCURRENT = 7 /* int: 1 = this handle's solves may run at the same time as other
                               handles' solves on the same GPU (other host threads and streams,
-                              e.g. the slots of a serving loop); their cooperative kernels (panel
-                              QR, bulge chasing), which need all their workgroups resident, then
-                              run one at a time on a stream the library keeps per device, ordered
-                              into the caller's stream by events.  0 (default): launched on the
-                              caller's stream, for a handle that has the device to itself */
+                              e.g. the slots of a serving loop).  No workgroup of such a solve
+                              then waits for another workgroup while other solves share the
+                              device: the panel QR runs as one launch per column and the stage-2
+                              back-transform as independent strips; a kernel whose workgroups
+                              must all be resident (the bulge chasing, grouped panel QRs) waits
+                              for the device to drain and runs with no other launch submitted
+                              until it ends.  Results are bitwise those of a handle with the
+                              key 0.  0 (default): for a handle that has the device to itself */
   , HSDM_KEY_N_STATES = 6  /* int: number of eigenvectors the eigenpair solves form, the lowest
                               ones (the paper's n_states: its dense runs compute only part of
                               the eigenvectors, Sec. 3); 0 or >= n: all (default 0).  C then
                               holds n_states columns; every eigenvalue is still returned */
+  , HSDM_KEY_PRECISION = 8 /* int: arithmetic of the real solves (hsdm_solve_ev_real,
+                              hsdm_solve_dm_real).  0 (default): FP64 throughout.  1: the
+                              refined form -- the full -> band reduction's trailing updates and
+                              the stage-1 back-transform in FP32 on the matrix cores, every
+                              eigenvector formed, then at most HSDM_KEY_REFINE_STEPS steps of FP64
+                              eigenpair refinement (Ogita-Aishima iterative refinement against
+                              the FP64 standard-form matrix) of the wanted ones: the lowest
+                              n_states for the eigenpair solve, the states occupied above the
+                              cut (with a margin) for the density-matrix solve; Cholesky,
+                              standard form, the tridiagonal eigensolve, occupations and D, E
+                              stay FP64.  The refinement stops after the first step whose
+                              largest correction |e_ij| is at most 1e-6 (the error left is of
+                              the order of its square).  The complex, multi-task and
+                              allocation-free solves always run the FP64 form */
+  , HSDM_KEY_REFINE_STEPS = 9 /* int: most refinement steps of the refined form, 1 ... 8
+                              (default 4) */
 };
 
 /* Create a handle bound to HIP device `device` (~ elsi_init, Sec. 2.1). */
@@ -91,7 +110,8 @@ int hsdm_reinit(hsdm_handle h);
 /* Solver settings (~ the elsi_set_* routines of the API of Sec. 2.1, which
  * configure a handle between elsi_init and the solves).  hsdm_set_real takes
  * HSDM_KEY_FMAX, HSDM_KEY_FCUT, HSDM_KEY_DEG_TOL; hsdm_set_int takes
- * HSDM_KEY_TIMING, HSDM_KEY_STREAMS, HSDM_KEY_N_STATES, HSDM_KEY_CONCURRENT.  Returns HSDM_OK,
+ * HSDM_KEY_TIMING, HSDM_KEY_STREAMS, HSDM_KEY_N_STATES, HSDM_KEY_CONCURRENT,
+ * HSDM_KEY_PRECISION, HSDM_KEY_REFINE_STEPS.  Returns HSDM_OK,
  * -1 (null handle), -2 (unknown key for this call) or -3 (value out of the
  * key's range; the setting is left unchanged).  Settings apply to the solves
  * that follow and are kept across hsdm_reinit. */
@@ -288,14 +308,24 @@ int hsdm_status_detail(hsdm_handle h);
  * of phases written (at most cap). */
 int hsdm_phase_times(hsdm_handle h, double *times, int cap);
 const char *hsdm_phase_name(int i);
+/* Record of the refinement of the last real solve in the refined form
+ * (HSDM_KEY_PRECISION = 1): returns the number of steps k (0 after an FP64
+ * solve; -1 null handle, -3 cap < 0 or out missing) and writes, for the
+ * first min(k, cap / 2) steps, out[2i] = delta (the separation below which
+ * two eigenvalues are treated as one cluster) and out[2i + 1] = the largest
+ * |e_ij| of the correction of step i. */
+int hsdm_refine_history(hsdm_handle h, double *out, int cap);
 /* Algorithmic FP64 flops of the phases of the last single solve when
  * HSDM_KEY_TIMING is on, in the order of hsdm_phase_name(i): the counts of
  * the method, not of this library's extra work -- Cholesky n^3/3 (0 when the
  * factor of S was cached), standard form n^3, full -> band 4n^3/3, band ->
  * tridiagonal 6 b n^2, divide and conquer the merge products at their sizes
  * after deflation, back-transforms 2n^2 m, 2n^2 m and n^2 m, D and E n^2 m
- * each (m: eigenvectors formed).  Multi-task solves write zeros.  Returns
- * the number of phases written (at most cap). */
+ * each (m: eigenvectors formed; the refined form transforms all n back and
+ * its refinement phase counts 8 n^2 m_r per step on the m_r refined vectors
+ * plus 2 n^2 (n - m_r) once; the other phases 0 in the FP64 form).
+ * Multi-task solves write zeros.  Returns the number of phases written (at
+ * most cap). */
 int hsdm_phase_flops(hsdm_handle h, double *flops, int cap);
 
 /* Per-kernel totals of the last solve when HSDM_KEY_TIMING is 2 or 3 (HIP events

@@ -19,11 +19,17 @@
 namespace {
 
 constexpr int BAND = 32;
-constexpr int NPHASE = 9;
+constexpr int NPHASE = 10;
 constexpr int NLANE = 8;  // worker streams of the multi-task solves (at most)
-const char* kPhaseNames[NPHASE] = {"cholesky_inverse", "standard_form", "full_to_band",
-                                   "band_to_tridiagonal", "divide_conquer", "backtransform_stage2",
-                                   "backtransform_stage1", "backtransform_cholesky", "density"};
+const char* kPhaseNames[NPHASE] = {"cholesky_inverse",     "standard_form",
+                                   "full_to_band",         "band_to_tridiagonal",
+                                   "divide_conquer",       "backtransform_stage2",
+                                   "backtransform_stage1", "refinement",
+                                   "backtransform_cholesky", "density"};
+constexpr int MAX_REFINE_STEPS = 8;
+// the refinement stops after a step whose largest correction is at most this
+// (the vectors' error is then of the order of its square)
+constexpr double REFINE_TOL = 1e-6;
 
 __global__ void reset_status_kernel(DevStatusWord* st, OccOut* occ) {
   if (threadIdx.x == 0) {
@@ -56,6 +62,7 @@ __global__ void copy_vec_kernel(const double* a, double* b, int n) {
 struct Pinned {
   DevStatusWord st;
   OccOut occ;
+  double rec[2 * MAX_REFINE_STEPS];  // refinement record of the last refined solve
 };
 
 }  // namespace
@@ -71,6 +78,16 @@ struct hsdm_ctx {
   int nlane = 4;          // worker streams used by multi-task solves
   long n_states = 0;      // eigenvectors formed by the eigenpair solves (0: all)
   bool concurrent = false;  // solves may overlap other handles' on the device
+  int precision = 0;        // 0: FP64 throughout; 1: the refined form (real pencils)
+  int refine_steps = 4;     // most refinement steps of the refined form
+  // workspace of the refined form (grown on demand)
+  void* rws_raw = nullptr;
+  size_t rws_cap = 0;
+  float *A32 = nullptr, *V32 = nullptr, *Z32 = nullptr, *bt1f = nullptr;
+  void *f32_scr = nullptr, *ref_scr = nullptr;
+  double* rrec = nullptr;
+  int last_refine = 0;      // steps of the last solve (0: FP64 form)
+  int last_mref = 0;        // columns refined by the last solve
   KTimer* kt = nullptr;
   std::string err;
   int detail = 0;
@@ -408,6 +425,41 @@ int ensure_ws(hsdm_ctx* h, int n, hipStream_t s) {
   return carve_block(h, n, h->ws_raw, s);
 }
 
+// The refined form's workspace: A, the reflectors and the eigenvectors in
+// FP32 (n x n each), the FP32 reduction's and back-transform's scratch, the
+// refinement's blocks and its record.
+int ensure_rws(hsdm_ctx* h, int n, hipStream_t s) {
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t nn = (size_t)n * n;
+  const size_t b32 = al(nn * sizeof(float));
+  const size_t bf = al(sy2sb_f32_scratch_bytes(n, BAND));
+  const size_t bb = al(bt1_f32_scratch_floats(n, BAND, n) * sizeof(float));
+  const size_t br = al(refine_scratch_bytes(n, n));
+  const size_t need = 3 * b32 + bf + bb + br + al(2 * MAX_REFINE_STEPS * sizeof(double));
+  if (h->rws_cap < need) {
+    if (h->rws_raw) {
+      DEV_TRY(h, hipStreamSynchronize(s));
+      (void)hipFree(h->rws_raw);
+      h->rws_raw = nullptr;
+      h->rws_cap = 0;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, need);
+    if (e != hipSuccess) return fail_dev(h, e, "refined-form workspace allocation");
+    h->rws_raw = p;
+    h->rws_cap = need;
+  }
+  char* p = (char*)h->rws_raw;
+  h->A32 = (float*)p; p += b32;
+  h->V32 = (float*)p; p += b32;
+  h->Z32 = (float*)p; p += b32;
+  h->f32_scr = p; p += bf;
+  h->bt1f = (float*)p; p += bb;
+  h->ref_scr = p; p += br;
+  h->rrec = (double*)p;
+  return HSDM_OK;
+}
+
 // ---- the allocation-free density-matrix solve --------------------------------
 // Its workspace lives in `scratch`, a static device array of the library:
 // every GPU the library runs on holds one copy until the process ends, and
@@ -459,10 +511,18 @@ void phase_work(hsdm_ctx* h) {
   h->phase_flops[2] = 4.0 * n * n * n / 3.0;
   h->phase_flops[3] = sb2st_algo_flops(h->lay);
   h->phase_flops[4] = h->plan ? stedc_last_flops(h->plan) : 0.0;
-  h->phase_flops[5] = 2.0 * n * n * m;
-  h->phase_flops[6] = 2.0 * n * n * m;
-  h->phase_flops[7] = n * n * m;
-  h->phase_flops[8] = h->last_kind == 1 ? 2.0 * n * n * m : 0.0;
+  // the refined form transforms every vector back and refines mref of them:
+  // per step 6 n^2 mref (A X, X^T X, X^T A X) and 2 n^2 mref (X E), the
+  // first step 2 n^2 (n - mref) more for the Rayleigh quotients of the rest
+  const double mb = h->last_refine ? n : m;
+  h->phase_flops[5] = 2.0 * n * n * mb;
+  h->phase_flops[6] = 2.0 * n * n * mb;
+  if (h->last_refine) {
+    const double mr = h->last_mref;
+    h->phase_flops[7] = h->last_refine * 8.0 * n * n * mr + 2.0 * n * n * (n - mr);
+  }
+  h->phase_flops[8] = n * n * m;
+  h->phase_flops[9] = h->last_kind == 1 ? 2.0 * n * n * m : 0.0;
 }
 
 int finish(hsdm_ctx* h, hipStream_t s) {
@@ -594,6 +654,43 @@ int reduce(hsdm_ctx* h, int n, hipStream_t s, int phase_band) {
   return HSDM_OK;
 }
 
+// The refined form's two-stage reduction: h->Abuf (lower, FP64) stays as it
+// is; its FP32 copy is reduced with FP32 trailing updates, the band chased in
+// FP64.
+int reduce_f32(hsdm_ctx* h, int n, hipStream_t s, int phase_band) {
+  DEV_TRY(h, dev_convert(h->Abuf, n, h->A32, n, n, n, s));
+  DEV_TRY(h, bt1_zero_fill(n, BAND, h->Vst, n, s));
+  DEV_TRY(h, sy2sb_f32_run(n, BAND, h->A32, n, h->Vst, n, h->V32, n, h->tau1, h->T1, h->AB,
+                           2 * BAND, h->f32_scr, h->st, s));
+  mark(h, phase_band, s);
+  DEV_TRY(h, sb2st_run(h->lay, h->AB, 2 * BAND, h->dvec, h->evec, h->V2, h->tau2, h->d_goff,
+                       h->progress, h->st, s));
+  return HSDM_OK;
+}
+
+// The refined form after the tridiagonal eigensolve (every vector, FP64):
+// both back-transforms of all n columns (stage 2 in FP64, stage 1 in FP32),
+// then `steps` refinement steps of the first mref columns against the FP64
+// standard-form matrix.  lam holds the eigenvalues on entry and the
+// refined ones (Rayleigh quotients) on exit; the vectors are in h->Zbuf.
+int refine_vectors(hsdm_ctx* h, int n, int mref, double* lam, hipStream_t s) {
+  DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
+  DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, n, nullptr, h->progress, h->st, s));
+  mark(h, 6, s);
+  DEV_TRY(h, dev_convert(h->Zbuf, n, h->Z32, n, n, n, s));
+  DEV_TRY(h, bt1_apply_f32(n, BAND, h->Vst, n, h->V32, n, h->T1, h->Z32, n, n, nullptr,
+                           h->bt1_scr, h->bt1f, s));
+  DEV_TRY(h, dev_convert(h->Z32, n, h->Zbuf, n, n, n, s));
+  mark(h, 7, s);
+  int done = 0;
+  DEV_TRY(h, refine_run(n, mref, h->Abuf, n, h->Zbuf, n, h->Z32, n, h->Cbuf, n, lam,
+                        h->refine_steps, REFINE_TOL, h->ref_scr, h->rrec, h->host->rec, &done,
+                        s));
+  h->last_refine = done;
+  h->last_mref = mref;
+  return HSDM_OK;
+}
+
 struct OccHook {
   hsdm_ctx* h;
   int n;
@@ -691,6 +788,7 @@ int hsdm_finalize(hsdm_handle h) {
   if (h->d_bt2) (void)hipFree(h->d_bt2);
   free_ws(h);
   free_cws(h);
+  if (h->rws_raw) (void)hipFree(h->rws_raw);
   if (h->st) (void)hipFree(h->st);
   if (h->host) (void)hipHostFree(h->host);
   if (h->d_hash) (void)hipFree(h->d_hash);
@@ -753,6 +851,16 @@ int hsdm_set_int(hsdm_handle h, int key, long v) {
     h->concurrent = (v == 1);
     return HSDM_OK;
   }
+  if (key == HSDM_KEY_PRECISION) {
+    if (v != 0 && v != 1) return -3;
+    h->precision = (int)v;
+    return HSDM_OK;
+  }
+  if (key == HSDM_KEY_REFINE_STEPS) {
+    if (v < 1 || v > MAX_REFINE_STEPS) return -3;
+    h->refine_steps = (int)v;
+    return HSDM_OK;
+  }
   return -2;
 }
 
@@ -776,6 +884,14 @@ int hsdm_phase_times(hsdm_handle h, double* times, int cap) {
   int k = cap < NPHASE ? cap : NPHASE;
   for (int i = 0; i < k; i++) times[i] = h->phase_ms[i];
   return k;
+}
+
+int hsdm_refine_history(hsdm_handle h, double* out, int cap) {
+  if (!h) return -1;
+  if (cap < 0 || (cap > 0 && !out)) return -3;
+  const int k = std::min(cap / 2, h->last_refine);
+  for (int i = 0; i < 2 * k; i++) out[i] = h->host->rec[i];
+  return h->last_refine;
 }
 
 const char* hsdm_phase_name(int i) { return (i >= 0 && i < NPHASE) ? kPhaseNames[i] : ""; }
@@ -989,6 +1105,9 @@ static int dm_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S
   for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
   h->last_kind = 1;
   h->last_n = n;
+  h->last_refine = 0;
+  const bool refined = h->precision == 1;
+  if (refined && (r = ensure_rws(h, n, s))) return r;
   HSDM_LAUNCH(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
   mark(h, 0, s);
@@ -997,26 +1116,43 @@ static int dm_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S
   if (h->deg_tol < 0.0) DEV_TRY(h, dev_norm1_sym(H, ldh, n, h->colsum, h->hnorm, s));
   if ((r = standard_form(h, n, H, ldh, h->Linv, n, h->Abuf, n, s))) return r;
   mark(h, 2, s);
-  if ((r = reduce(h, n, s, 3))) return r;
+  if ((r = refined ? reduce_f32(h, n, s, 3) : reduce(h, n, s, 3))) return r;
   mark(h, 4, s);
   OccHook hook{h, n, ne, kT};
   const int* m_dev = &h->occ->m;
-  DEV_TRY(h, stedc_run(h->plan, h->dvec, h->evec, h->lam, h->Zbuf, n, h->dc_scr, h->dc_iscr,
-                       m_dev, occ_hook, &hook, h->st, s));
-  mark(h, 5, s);
-  DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
-  DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, n, m_dev, h->progress, h->st, s));
-  mark(h, 6, s);
-  DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, n, m_dev, h->bt1_scr, s));
-  mark(h, 7, s);
+  if (refined) {
+    // every vector: the refinement corrects the wanted ones with all others
+    DEV_TRY(h, stedc_run(h->plan, h->dvec, h->evec, h->lam, h->Zbuf, n, h->dc_scr, h->dc_iscr,
+                         nullptr, nullptr, nullptr, h->st, s));
+    DEV_TRY(h, occ_hook(&hook, h->lam, s));
+    mark(h, 5, s);
+    // the wanted count at the unrefined eigenvalues, with a margin for the
+    // states the refinement moves across the occupation cut
+    DEV_TRY(h, hipMemcpyAsync(&h->host->occ, h->occ, sizeof(OccOut), hipMemcpyDeviceToHost, s));
+    DEV_TRY(h, hipStreamSynchronize(s));
+    const int m0 = h->host->occ.m;
+    const int mref = std::min(n, m0 + std::max(32, m0 / 32));
+    if ((r = refine_vectors(h, n, mref, h->lam, s))) return r;
+    DEV_TRY(h, occ_hook(&hook, h->lam, s));
+  } else {
+    DEV_TRY(h, stedc_run(h->plan, h->dvec, h->evec, h->lam, h->Zbuf, n, h->dc_scr, h->dc_iscr,
+                         m_dev, occ_hook, &hook, h->st, s));
+    mark(h, 5, s);
+    DEV_TRY(h, bt2_prepare(h->lay, h->V2, h->tau2, h->F2, s));
+    DEV_TRY(h, bt2_apply(h->lay, h->F2, h->d_goff, h->Zbuf, n, n, m_dev, h->progress, h->st, s));
+    mark(h, 6, s);
+    DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, n, m_dev, h->bt1_scr, s));
+    mark(h, 7, s);
+  }
+  mark(h, 8, s);
   GemmArgs g{};
   g.m = n; g.n = n; g.k = n; g.A = h->Linv; g.lda = n; g.B = h->Zbuf; g.ldb = n; g.C = h->Cbuf;
   g.ldc = n; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.flags = GF_KA_UPPER;
   g.ndev = m_dev;
   DEV_TRY(h, gemm_launch(g, s));
-  mark(h, 8, s);
-  DEV_TRY(h, density_launch(n, n, h->Cbuf, n, h->fvec, h->lam, D, ldd, E, lde, m_dev, s));
   mark(h, 9, s);
+  DEV_TRY(h, density_launch(n, n, h->Cbuf, n, h->fvec, h->lam, D, ldd, E, lde, m_dev, s));
+  mark(h, 10, s);
   return HSDM_OK;
 }
 
@@ -1026,12 +1162,38 @@ static int dm_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S
 // those ns vectors (a device count in the handle's occupation record, which
 // this solve does not otherwise use) and the back-transforms take ns columns.
 static int ev_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S, int lds,
-                   const SKey& key, double* eval, double* C, int ldc, int ns, hipStream_t s) {
+                   const SKey& key, double* eval, double* C, int ldc, int ns, hipStream_t s,
+                   bool refined = false) {
   int r;
   for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
   h->last_kind = 2;
   h->last_n = n;
   h->last_ns = ns;
+  h->last_refine = 0;
+  if (refined && (r = ensure_rws(h, n, s))) return r;
+  if (refined) {
+    HSDM_LAUNCH(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+    DEV_TRY(h, hipGetLastError());
+    mark(h, 0, s);
+    if ((r = factor_s(h, n, S, lds, key, s))) return r;
+    mark(h, 1, s);
+    if ((r = standard_form(h, n, H, ldh, h->Linv, n, h->Abuf, n, s))) return r;
+    mark(h, 2, s);
+    if ((r = reduce_f32(h, n, s, 3))) return r;
+    mark(h, 4, s);
+    DEV_TRY(h, stedc_run(h->plan, h->dvec, h->evec, eval, h->Zbuf, n, h->dc_scr, h->dc_iscr,
+                         nullptr, nullptr, nullptr, h->st, s));
+    mark(h, 5, s);
+    if ((r = refine_vectors(h, n, ns, eval, s))) return r;
+    mark(h, 8, s);
+    GemmArgs g{};
+    g.m = n; g.n = ns; g.k = n; g.A = h->Linv; g.lda = n; g.B = h->Zbuf; g.ldb = n; g.C = C;
+    g.ldc = ldc; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.flags = GF_KA_UPPER;
+    DEV_TRY(h, gemm_launch(g, s));
+    mark(h, 9, s);
+    mark(h, 10, s);
+    return HSDM_OK;
+  }
   HSDM_LAUNCH(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
   DEV_TRY(h, hipGetLastError());
   const int* m_dev = nullptr;
@@ -1058,14 +1220,15 @@ static int ev_core(hsdm_ctx* h, int n, const double* H, int ldh, const double* S
   mark(h, 6, s);
   if (ns > 0) DEV_TRY(h, bt1_apply(n, BAND, h->Vst, n, h->T1, h->Zbuf, n, ns, nullptr, h->bt1_scr, s));
   mark(h, 7, s);
+  mark(h, 8, s);
   if (ns > 0) {
     GemmArgs g{};
     g.m = n; g.n = ns; g.k = n; g.A = h->Linv; g.lda = n; g.B = h->Zbuf; g.ldb = n; g.C = C;
     g.ldc = ldc; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.flags = GF_KA_UPPER;
     DEV_TRY(h, gemm_launch(g, s));
   }
-  mark(h, 8, s);
   mark(h, 9, s);
+  mark(h, 10, s);
   return HSDM_OK;
 }
 
@@ -1095,7 +1258,7 @@ int hsdm_solve_ev_real(hsdm_handle h, int n, const double* H, int ldh, const dou
   if ((r = s_key(h, S, n, lds, false, key, s))) return r;
   KtScope kts(h);
   const int ns = (h->n_states > 0 && h->n_states < n) ? (int)h->n_states : n;
-  if ((r = ev_core(h, n, H, ldh, S, lds, key, eval, C, ldc, ns, s))) return r;
+  if ((r = ev_core(h, n, H, ldh, S, lds, key, eval, C, ldc, ns, s, h->precision == 1))) return r;
   return finish(h, s);
 }
 

@@ -11,6 +11,7 @@
 // the first, as three GEMMs per panel (the tall V_p^T Z with split-K).
 #include "hsdm_internal.h"
 #include "hsdm_phases.h"
+#include "hsdm_util.h"
 
 namespace {
 
@@ -552,11 +553,18 @@ hipError_t bt1_zero_fill(int n, int B_, double* Vst, long ldv, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t bt1_apply(int n, int B_, const double* Vst, long ldv, const double* T1, double* Z,
-                     long ldz, int m, const int* m_dev, double* scratch, hipStream_t s) {
-  if (m <= 0) return hipSuccess;
+namespace {
+
+// Gram matrices and T of every panel group (FP64, from the FP64 reflectors)
+// into the scratch; returns the pointers the application needs.
+struct Bt1Groups {
+  int np_all, W, ngroup;
+  double *Wb, *W2, *part, *Tall;
+};
+
+hipError_t bt1_groups(int n, int B_, const double* Vst, long ldv, const double* T1, int m,
+                      double* scratch, Bt1Groups& out, hipStream_t s) {
   const int np_all = npanel_of(n, B_);
-  if (np_all == 0) return hipSuccess;
   const int W = GP * B_;
   const int ngroup = ceil_div(np_all, GP);
   const size_t gsplit = ceil_div(n, BT1_GCHUNK) + 1;
@@ -570,6 +578,7 @@ hipError_t bt1_apply(int n, int B_, const double* Vst, long ldv, const double* T
   double* Xall = Gpart + gsplit * W * W;
   GemmDesc* d1 = reinterpret_cast<GemmDesc*>(Xall + (size_t)ngroup * W * W / 2);
   GemmDesc* d2 = d1 + ndesc;
+  out = Bt1Groups{np_all, W, ngroup, Wb, W2, part, Tall};
   // Gram V_q^T V_q of every group (upper blocks are used)
   for (int q = 0; q < ngroup; q++) {
     const int p0 = q * GP, np = min(GP, np_all - p0);
@@ -594,29 +603,73 @@ hipError_t bt1_apply(int n, int B_, const double* Vst, long ldv, const double* T
     HSDM_TRY(gemm_batched_dense_launch(d1, cnt, b, b, 1.0, 0.0, GF_KB_UPPER, s));
     HSDM_TRY(gemm_batched_dense_launch(d2, cnt, b, b, -1.0, 0.0, GF_KA_UPPER, s));
   }
-  for (int q = ngroup - 1; q >= 0; q--) {
-    const int p0 = q * GP, np = min(GP, np_all - p0);
+  return hipSuccess;
+}
+
+// Z <- (I - V_q T_q V_q^T) Z for the groups q, last first, in element type T
+// (V, Tall, Z and the work buffers Wb, W2, part of that type).
+template <class T>
+hipError_t bt1_groups_apply(int n, int B_, const Bt1Groups& G_, const T* V, long ldv,
+                            const T* Tall, T* Z, long ldz, int m, const int* m_dev, T* Wb, T* W2,
+                            T* part, hipStream_t s) {
+  const int W = G_.W;
+  for (int q = G_.ngroup - 1; q >= 0; q--) {
+    const int p0 = q * GP, np = min(GP, G_.np_all - p0);
     const int r0 = (p0 + 1) * B_, h = n - r0, w = np * B_;
     if (h <= 0) continue;
-    const double* Vq = Vst + r0 + (long)p0 * B_ * ldv;
-    const double* Tq = Tall + (size_t)q * W * W;
-    double* Zq = Z + r0;
+    const T* Vq = V + r0 + (long)p0 * B_ * ldv;
+    const T* Tq = Tall + (size_t)q * W * W;
+    T* Zq = Z + r0;
     // V^T Z: split K so that the product fills the chip
     const long tiles = (long)ceil_div(w, 128) * ceil_div(m, 128);
     int nsp = (int)std::min<long>(BT1_MAXSPLIT, std::max<long>(1, ceil_div(512, (int)tiles)));
     int kchunk = ceil_div(ceil_div(h, nsp), 16) * 16;
-    GemmArgs g{};
+    GemmArgsT<T> g{};
     g.m = w; g.n = m; g.k = h; g.A = Vq; g.lda = ldv; g.B = Zq; g.ldb = ldz; g.C = Wb; g.ldc = w;
     g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.ndev = m_dev;
     HSDM_TRY(gemm_splitk_launch(g, kchunk, part, s));
-    g = GemmArgs{};
+    g = GemmArgsT<T>{};
     g.m = w; g.n = m; g.k = w; g.A = Tq; g.lda = W; g.B = Wb; g.ldb = w; g.C = W2; g.ldc = w;
     g.alpha = 1.0; g.beta = 0.0; g.flags = GF_KA_UPPER; g.ndev = m_dev;
     HSDM_TRY(gemm_launch(g, s));
-    g = GemmArgs{};
+    g = GemmArgsT<T>{};
     g.m = h; g.n = m; g.k = w; g.A = Vq; g.lda = ldv; g.B = W2; g.ldb = w; g.C = Zq; g.ldc = ldz;
     g.alpha = -1.0; g.beta = 1.0; g.ndev = m_dev;
     HSDM_TRY(gemm_launch(g, s));
   }
   return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t bt1_apply(int n, int B_, const double* Vst, long ldv, const double* T1, double* Z,
+                     long ldz, int m, const int* m_dev, double* scratch, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  if (npanel_of(n, B_) == 0) return hipSuccess;
+  Bt1Groups G_;
+  HSDM_TRY(bt1_groups(n, B_, Vst, ldv, T1, m, scratch, G_, s));
+  return bt1_groups_apply<double>(n, B_, G_, Vst, ldv, G_.Tall, Z, ldz, m, m_dev, G_.Wb, G_.W2,
+                                  G_.part, s);
+}
+
+size_t bt1_f32_scratch_floats(int n, int B_, int m) {
+  const size_t W = (size_t)GP * B_;
+  const size_t ngroup = ceil_div(npanel_of(n, B_), GP) + 1;
+  return W * m * (2 + BT1_MAXSPLIT) + ngroup * W * W + 64;
+}
+
+hipError_t bt1_apply_f32(int n, int B_, const double* Vst, long ldv, const float* V32,
+                         long ldv32, const double* T1, float* Z, long ldz, int m,
+                         const int* m_dev, double* scratch, float* scratch32, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  if (npanel_of(n, B_) == 0) return hipSuccess;
+  Bt1Groups G_;
+  HSDM_TRY(bt1_groups(n, B_, Vst, ldv, T1, m, scratch, G_, s));
+  const int W = G_.W;
+  float* Wb = scratch32;
+  float* W2 = Wb + (size_t)W * m;
+  float* part = W2 + (size_t)W * m;
+  float* Tall = part + (size_t)BT1_MAXSPLIT * W * m;
+  HSDM_TRY(dev_convert(G_.Tall, W, Tall, W, W, G_.ngroup * W, s));
+  return bt1_groups_apply<float>(n, B_, G_, V32, ldv32, Tall, Z, ldz, m, m_dev, Wb, W2, part, s);
 }

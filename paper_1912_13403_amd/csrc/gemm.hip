@@ -1,4 +1,6 @@
-// FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4f64).
+// GEMM on CDNA4 matrix cores: FP64 (v_mfma_f64_16x16x4f64) and, for the
+// refined form, FP32 (v_mfma_f32_16x16x4f32, the same 16 x 16 x 4 shape and
+// operand layout; only the rows an accumulator register holds differ).
 //
 // Every dense contraction of the path runs through this kernel: the
 // Cholesky/inverse recursion, the standard-form products, the two-sided
@@ -34,14 +36,40 @@ constexpr int AM_GATHER = 2;  // op(A)[:, kk] = A[:, acol[kk]] (TA = 0)
 constexpr int AM_TRIL = 3;    // op(A) = lower triangle of A, diagonal included (TA = 0)
 constexpr int AM_SLT = 4;     // op(A) = (strict lower triangle of A)^T (TA = 1)
 
-struct Prob {
+template <class T>
+struct ProbT {
   int m, n, k;
-  const double* A; long lda;
-  const double* B; long ldb;
-  double* C; long ldc;
+  const T* A; long lda;
+  const T* B; long ldb;
+  T* C; long ldc;
   const int* acol;
   const int* ccol;
   const int* ndev;  // optional device-side column count (n is then an upper bound)
+};
+using Prob = ProbT<double>;
+
+// The 16 x 16 x 4 matrix-core step per element type.  Operands: lane l holds
+// op(A)[l % 16][l / 16] and op(B)[l / 16][l % 16]; accumulator register r
+// of lane l holds column l % 16 and row row(l / 16, r) of the block.
+template <class T>
+struct Mf;
+template <>
+struct Mf<double> {
+  using acc = dbl4;
+  static HSDM_DEV acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+  static HSDM_DEV acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static HSDM_DEV int row(int l4, int r) { return l4 + 4 * r; }
+};
+template <>
+struct Mf<float> {
+  using acc = flt4;
+  static HSDM_DEV acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+  static HSDM_DEV acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static HSDM_DEV int row(int l4, int r) { return 4 * l4 + r; }
 };
 
 template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
@@ -65,8 +93,8 @@ struct G {
 };
 
 // ---- global -> registers ------------------------------------------------------
-template <class C, int TA, int AM>
-HSDM_DEV void load_a(const Prob& p, int i0, int k0, int kb, int ke, double (&r)[C::AE]) {
+template <class C, int TA, int AM, class T>
+HSDM_DEV void load_a(const ProbT<T>& p, int i0, int k0, int kb, int ke, T (&r)[C::AE]) {
   const int t = threadIdx.x;
   if constexpr (TA == 1) {
     // op(A)[i, kk] = A[kk + i*lda]: k-contiguous
@@ -76,8 +104,8 @@ HSDM_DEV void load_a(const Prob& p, int i0, int k0, int kb, int ke, double (&r)[
       bool ok = (i < p.m) && (kk >= kb) && (kk < ke);
       if constexpr (AM == AM_SLT) ok = ok && (kk > i);
       const int ic = min(i, p.m - 1), kc = min(max(kk, kb), ke - 1);
-      const double v = p.A[kc + (long)ic * p.lda];
-      r[q] = ok ? v : 0.0;
+      const T v = p.A[kc + (long)ic * p.lda];
+      r[q] = ok ? v : T(0);
     }
   } else {
     constexpr int RS = C::NT / C::BMc;  // k columns per pass
@@ -95,14 +123,14 @@ HSDM_DEV void load_a(const Prob& p, int i0, int k0, int kb, int ke, double (&r)[
       } else {
         addr = ic + (long)kc * p.lda;
       }
-      const double v = p.A[addr];
-      r[q] = ok ? v : 0.0;
+      const T v = p.A[addr];
+      r[q] = ok ? v : T(0);
     }
   }
 }
 
-template <class C, int TA>
-HSDM_DEV void store_a(double* As, const double (&r)[C::AE]) {
+template <class C, int TA, class T>
+HSDM_DEV void store_a(T* As, const T (&r)[C::AE]) {
   const int t = threadIdx.x;
   if constexpr (TA == 1) {
 #pragma unroll
@@ -114,8 +142,8 @@ HSDM_DEV void store_a(double* As, const double (&r)[C::AE]) {
   }
 }
 
-template <class C, int TB>
-HSDM_DEV void load_b(const Prob& p, int j0, int k0, int kb, int ke, double (&r)[C::BE]) {
+template <class C, int TB, class T>
+HSDM_DEV void load_b(const ProbT<T>& p, int j0, int k0, int kb, int ke, T (&r)[C::BE]) {
   const int t = threadIdx.x;
   if constexpr (TB == 0) {
     // op(B)[kk, j] = B[kk + j*ldb]: k-contiguous
@@ -124,8 +152,8 @@ HSDM_DEV void load_b(const Prob& p, int j0, int k0, int kb, int ke, double (&r)[
       const int kk = k0 + (t % BK), j = j0 + t / BK + q * (C::NT / BK);
       const bool ok = (j < p.n) && (kk >= kb) && (kk < ke);
       const int jc = min(j, p.n - 1), kc = min(max(kk, kb), ke - 1);
-      const double v = p.B[kc + (long)jc * p.ldb];
-      r[q] = ok ? v : 0.0;
+      const T v = p.B[kc + (long)jc * p.ldb];
+      r[q] = ok ? v : T(0);
     }
   } else {
     constexpr int RS = C::NT / C::BNc;
@@ -134,14 +162,14 @@ HSDM_DEV void load_b(const Prob& p, int j0, int k0, int kb, int ke, double (&r)[
       const int j = j0 + (t % C::BNc), kk = k0 + t / C::BNc + q * RS;
       const bool ok = (j < p.n) && (kk >= kb) && (kk < ke);
       const int jc = min(j, p.n - 1), kc = min(max(kk, kb), ke - 1);
-      const double v = p.B[jc + (long)kc * p.ldb];
-      r[q] = ok ? v : 0.0;
+      const T v = p.B[jc + (long)kc * p.ldb];
+      r[q] = ok ? v : T(0);
     }
   }
 }
 
-template <class C, int TB>
-HSDM_DEV void store_b(double* Bs, const double (&r)[C::BE]) {
+template <class C, int TB, class T>
+HSDM_DEV void store_b(T* Bs, const T (&r)[C::BE]) {
   const int t = threadIdx.x;
   if constexpr (TB == 0) {
 #pragma unroll
@@ -154,9 +182,9 @@ HSDM_DEV void store_b(double* Bs, const double (&r)[C::BE]) {
 }
 
 // ---- one output tile -------------------------------------------------------------
-template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
-HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int flags, int tm, int tn,
-                        double* smem, int klo, int khi) {
+template <int BM, int BN, int WM, int WN, int TA, int TB, int AM, class T>
+HSDM_DEV void gemm_tile(const ProbT<T>& p, double alpha, double beta, int flags, int tm, int tn,
+                        T* smem, int klo, int khi) {
   using C = G<BM, BN, WM, WN, TA, TB, AM>;
   const int i0 = tm * BM, j0 = tn * BN;
   int kb = klo, ke = min(p.k, khi);
@@ -166,52 +194,53 @@ HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int flags, int
   if (flags & GF_KB_LOWER) kb = max(kb, j0);
   const int kstart = (kb / BK) * BK;
 
-  double* As0 = smem;
-  double* As1 = smem + C::ASZ;
-  double* Bs0 = smem + 2 * C::ASZ;
-  double* Bs1 = Bs0 + C::BSZ;
+  T* As0 = smem;
+  T* As1 = smem + C::ASZ;
+  T* Bs0 = smem + 2 * C::ASZ;
+  T* Bs1 = Bs0 + C::BSZ;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave % WM, wn = wave / WM;
   const int l16 = lane & 15, l4 = lane >> 4;
 
-  dbl4 acc[C::FM][C::FN];
+  using M = Mf<T>;
+  typename M::acc acc[C::FM][C::FN];
   // With alpha = +-1 the accumulators start from (beta / alpha) C, exact in
-  // FP64, so the C tile is read while the first A and B slices load instead
-  // of after the contraction.
+  // the element type, so the C tile is read while the first A and B slices
+  // load instead of after the contraction.
   const bool cinit = (beta != 0.0) && (alpha == 1.0 || alpha == -1.0);
   if (cinit) {
-    const double sc = beta * alpha;  // beta / alpha for alpha = +-1
+    const T sc = (T)(beta * alpha);  // beta / alpha for alpha = +-1
 #pragma unroll
     for (int b = 0; b < C::FN; b++) {
       const int col = j0 + wn * C::WTN + b * 16 + l16;
       const bool cok = col < p.n;
       const long cc = cok ? (p.ccol ? (long)p.ccol[col] : (long)col) : 0L;
-      const double* cp = p.C + cc * p.ldc;
+      const T* cp = p.C + cc * p.ldc;
 #pragma unroll
       for (int a = 0; a < C::FM; a++)
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-          const int row = i0 + wm * C::WTM + a * 16 + l4 + 4 * r;
+          const int row = i0 + wm * C::WTM + a * 16 + M::row(l4, r);
           bool ok = cok && row < p.m;
           if (flags & GF_C_LOWER_ONLY) ok = ok && row >= col;
-          const double v = cp[min(row, p.m - 1)];  // in bounds for every lane
-          acc[a][b][r] = ok ? sc * v : 0.0;
+          const T v = cp[min(row, p.m - 1)];  // in bounds for every lane
+          acc[a][b][r] = ok ? sc * v : T(0);
         }
     }
   } else {
 #pragma unroll
     for (int a = 0; a < C::FM; a++)
 #pragma unroll
-      for (int b = 0; b < C::FN; b++) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+      for (int b = 0; b < C::FN; b++) acc[a][b] = M::zero();
   }
 
   // one K slice of the staged tiles: 4 MFMA steps over BK
-  auto compute = [&](const double* as, const double* bs) {
+  auto compute = [&](const T* as, const T* bs) {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + l4;
-      double fa[C::FM], fb[C::FN];
+      T fa[C::FM], fb[C::FN];
 #pragma unroll
       for (int a = 0; a < C::FM; a++) {
         const int row = wm * C::WTM + a * 16 + l16;
@@ -226,17 +255,17 @@ HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int flags, int
       for (int a = 0; a < C::FM; a++)
 #pragma unroll
         for (int b = 0; b < C::FN; b++)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = M::mma(fa[a], fb[b], acc[a][b]);
     }
   };
-  double ra[C::AE], rb[C::BE];
+  T ra[C::AE], rb[C::BE];
   if constexpr (C::PF2) {
     // skinny tiles carry little work per slice: the registers hold two
     // slices ahead.  Loads are unconditional (past the last slice the last
     // one is loaded again and not used) so that every wait can be exact.
     const int nsl = (kstart < ke) ? (ke - kstart + BK - 1) / BK : 0;
     auto ks_of = [&](int j) { return kstart + BK * min(j, nsl - 1); };
-    double ra2[C::AE], rb2[C::BE];
+    T ra2[C::AE], rb2[C::BE];
     if (nsl > 0) {
       load_a<C, TA, AM>(p, i0, ks_of(0), kb, ke, ra);
       load_b<C, TB>(p, j0, ks_of(0), kb, ke, rb);
@@ -287,8 +316,8 @@ HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int flags, int
     }
   }
 
-  // epilogue: accumulator register r of a lane holds row lane/16 + 4r, column
-  // lane%16 of its 16x16 block
+  // epilogue: accumulator register r of a lane holds row M::row(lane / 16, r),
+  // column lane % 16 of its 16 x 16 block
 #pragma unroll
   for (int a = 0; a < C::FM; a++)
 #pragma unroll
@@ -296,14 +325,14 @@ HSDM_DEV void gemm_tile(const Prob& p, double alpha, double beta, int flags, int
       const int col = j0 + wn * C::WTN + b * 16 + l16;
       if (col >= p.n) continue;
       const long cc = p.ccol ? (long)p.ccol[col] : (long)col;
-      double* cp = p.C + cc * p.ldc;
+      T* cp = p.C + cc * p.ldc;
 #pragma unroll
       for (int r = 0; r < 4; r++) {
-        const int row = i0 + wm * C::WTM + a * 16 + l4 + 4 * r;
+        const int row = i0 + wm * C::WTM + a * 16 + M::row(l4, r);
         if (row >= p.m) continue;
         if ((flags & GF_C_LOWER_ONLY) && row < col) continue;
-        double v = alpha * acc[a][b][r];
-        if (beta != 0.0 && !cinit) v += beta * cp[row];
+        T v = (T)alpha * acc[a][b][r];
+        if (beta != 0.0 && !cinit) v += (T)beta * cp[row];
         cp[row] = v;
       }
     }
@@ -352,12 +381,12 @@ constexpr int waves_per_eu() {
   return 1;
 }
 
-template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
-__global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(waves_per_eu<BM, BN, WM, WN, TA, AM>()))) void gemm_kernel(Prob p, double alpha, double beta,
+template <int BM, int BN, int WM, int WN, int TA, int TB, int AM, class T>
+__global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(waves_per_eu<BM, BN, WM, WN, TA, AM>()))) void gemm_kernel(ProbT<T> p, double alpha, double beta,
                                                             int flags, int kchunk,
                                                             long split_stride) {
   using C = G<BM, BN, WM, WN, TA, TB, AM>;
-  __shared__ double smem[C::SMEM];
+  __shared__ T smem[C::SMEM];
   if (p.ndev) p.n = min(p.n, *p.ndev);
   if (p.n <= 0) return;
   const int tiles_m = (p.m + BM - 1) / BM, tiles_n = (p.n + BN - 1) / BN;
@@ -402,17 +431,18 @@ __global__ __launch_bounds__(64 * WM * WN, 512 / (64 * WM * WN)) void gemm_batch
 }
 
 // sum of nsplit partial m x n products (ld m) into C: C = sum + beta C
-__global__ void splitk_reduce_kernel(int m, int n, int nsplit, const double* part, double* C,
-                                     long ldc, double beta, const int* ndev) {
+template <class T>
+__global__ void splitk_reduce_kernel(int m, int n, int nsplit, const T* part, T* C, long ldc,
+                                     double beta, const int* ndev) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long tot = (long)m * n;
   if (idx >= tot) return;
   if (ndev && idx / m >= *ndev) return;
-  double s = 0.0;
+  T s = 0;
   for (int z = 0; z < nsplit; z++) s += part[z * tot + idx];
   const int i = (int)(idx % m), j = (int)(idx / m);
-  double* c = C + i + (long)j * ldc;
-  *c = (beta != 0.0) ? s + beta * *c : s;
+  T* c = C + i + (long)j * ldc;
+  *c = (beta != 0.0) ? s + (T)beta * *c : s;
 }
 
 // Tall-skinny products of several tasks in one launch, all with the 128 x 32
@@ -466,11 +496,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void s
 // (X = tril(A) Y + strict_tril(A)^T Y), split over K, in one launch:
 // blockIdx.z = 0 writes the partials of the first pass to part1, 1 those of
 // the second to part2 (slice blockIdx.y at offset y m n, leading dimension m).
+template <class T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sym_pair_kernel(
-    Prob p, double* part1, double* part2, int kchunk) {
+    ProbT<T> p, T* part1, T* part2, int kchunk) {
   using C1 = G<128, 32, 4, 1, 0, 0, AM_TRIL>;
   using C2 = G<128, 32, 4, 1, 1, 0, AM_SLT>;
-  __shared__ double smem[C1::SMEM > C2::SMEM ? C1::SMEM : C2::SMEM];
+  __shared__ T smem[C1::SMEM > C2::SMEM ? C1::SMEM : C2::SMEM];
   int tm, tn;
   if (!map_tile(blockIdx.x, (p.m + 127) / 128, 1, tm, tn)) return;
   const int klo = blockIdx.y * kchunk;
@@ -489,12 +520,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void s
 // C = (sum of part2's slices) + (sum of part1's slices), each summed in
 // slice order: the same roundings as the first pass reduced into C and the
 // second reduced onto it.
-__global__ void sym_pair_reduce_kernel(int m, int n, int nsplit, const double* part1,
-                                       const double* part2, double* C, long ldc) {
+template <class T>
+__global__ void sym_pair_reduce_kernel(int m, int n, int nsplit, const T* part1, const T* part2,
+                                       T* C, long ldc) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long tot = (long)m * n;
   if (idx >= tot) return;
-  double s1 = 0.0, s2 = 0.0;
+  T s1 = 0, s2 = 0;
   for (int z = 0; z < nsplit; z++) s1 += part1[z * tot + idx];
   for (int z = 0; z < nsplit; z++) s2 += part2[z * tot + idx];
   const int i = (int)(idx % m), j = (int)(idx / m);
@@ -517,33 +549,35 @@ __global__ void splitk_reduce_group_kernel(const GemmGroupItem* items) {
 }
 
 // C = beta*C when k == 0 (or alpha == 0)
-__global__ void scale_kernel(int m, int n, double* C, long ldc, double beta, const int* ccol,
+template <class T>
+__global__ void scale_kernel(int m, int n, T* C, long ldc, double beta, const int* ccol,
                              const int* ndev) {
   long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)m * n) return;
   int i = (int)(idx % m), j = (int)(idx / m);
   if (ndev && j >= *ndev) return;
   long cc = ccol ? (long)ccol[j] : (long)j;
-  double* c = C + cc * ldc + i;
-  *c = (beta != 0.0) ? beta * *c : 0.0;
+  T* c = C + cc * ldc + i;
+  *c = (beta != 0.0) ? (T)beta * *c : T(0);
 }
 
 // ---- dispatch ----------------------------------------------------------------------
-template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
+template <int BM, int BN, int WM, int WN, int TA, int TB, int AM, class T>
 const char* kernel_name() {
   static const std::string nm = "gemm_kernel<" + std::to_string(BM) + ", " + std::to_string(BN) +
                                 ", " + std::to_string(WM) + ", " + std::to_string(WN) + ", " +
                                 std::to_string(TA) + ", " + std::to_string(TB) + ", " +
-                                std::to_string(AM) + ">";
+                                std::to_string(AM) +
+                                (sizeof(T) == 4 ? ", float>" : ">");
   return nm.c_str();
 }
 
-template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
-hipError_t launch_cfg(const Prob& p, double alpha, double beta, int flags, int nsplit, int kchunk,
-                      long stride, double flops, hipStream_t s) {
+template <int BM, int BN, int WM, int WN, int TA, int TB, int AM, class T>
+hipError_t launch_cfg(const ProbT<T>& p, double alpha, double beta, int flags, int nsplit,
+                      int kchunk, long stride, double flops, hipStream_t s) {
   const int nblk = tile_grid(ceil_div(p.m, BM), ceil_div(p.n, BN));
-  kt_begin(kernel_name<BM, BN, WM, WN, TA, TB, AM>(), flops, 0.0, p.ndev ? p.n : 0, s);
-  HSDM_LAUNCH((gemm_kernel<BM, BN, WM, WN, TA, TB, AM>), dim3(nblk, nsplit),
+  kt_begin(kernel_name<BM, BN, WM, WN, TA, TB, AM, T>(), flops, 0.0, p.ndev ? p.n : 0, s);
+  HSDM_LAUNCH((gemm_kernel<BM, BN, WM, WN, TA, TB, AM, T>), dim3(nblk, nsplit),
                      dim3(64 * WM * WN), 0, s, p, alpha, beta, flags, kchunk, stride);
   kt_end(s);
   return hipGetLastError();
@@ -571,9 +605,9 @@ int pick_cfg(int m, int n, int nsplit, int ta) {
   return 2;
 }
 
-template <int TA, int TB, int AM>
-hipError_t launch_t(const Prob& p, double alpha, double beta, int flags, int nsplit, int kchunk,
-                    long stride, double fl, hipStream_t s) {
+template <int TA, int TB, int AM, class T>
+hipError_t launch_t(const ProbT<T>& p, double alpha, double beta, int flags, int nsplit,
+                    int kchunk, long stride, double fl, hipStream_t s) {
   switch (pick_cfg(p.m, p.n, nsplit, TA)) {
     case 0:
       return launch_cfg<128, 128, 2, 4, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
@@ -593,8 +627,9 @@ hipError_t launch_t(const Prob& p, double alpha, double beta, int flags, int nsp
   }
 }
 
-hipError_t launch_any(const Prob& p, int ta, int tb, int am, double alpha, double beta, int flags,
-                      int nsplit, int kchunk, long stride, double fl, hipStream_t s) {
+template <class T>
+hipError_t launch_any(const ProbT<T>& p, int ta, int tb, int am, double alpha, double beta,
+                      int flags, int nsplit, int kchunk, long stride, double fl, hipStream_t s) {
   if (am == AM_TRIL) {
     if (tb) return launch_t<0, 1, AM_TRIL>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
     return launch_t<0, 0, AM_TRIL>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
@@ -620,7 +655,8 @@ hipError_t launch_any(const Prob& p, int ta, int tb, int am, double alpha, doubl
 // Algorithmic flops of one product: 2 m n k, halved for a lower-triangular
 // result (square C), for a triangular op(A) or op(B), and for each half of a
 // symmetric operand.
-double gemm_flops(const GemmArgs& g) {
+template <class T>
+double gemm_flops(const GemmArgsT<T>& g) {
   double f = 2.0 * g.m * g.n * (double)g.k;
   if ((g.flags & (GF_C_LOWER_TILES | GF_C_LOWER_ONLY)) && g.m == g.n) f *= (g.n + 1.0) / (2.0 * g.n);
   if (g.flags & (GF_KA_LOWER | GF_KA_UPPER)) f *= 0.5;
@@ -629,7 +665,8 @@ double gemm_flops(const GemmArgs& g) {
   return f;
 }
 
-int a_mode(const GemmArgs& g) {
+template <class T>
+int a_mode(const GemmArgsT<T>& g) {
   if (g.flags & GF_A_TRIL) return AM_TRIL;
   if (g.flags & GF_A_SLT) return AM_SLT;
   if (g.flags & GF_A_SYM_LOWER) return AM_SYM;
@@ -637,40 +674,81 @@ int a_mode(const GemmArgs& g) {
   return AM_DENSE;
 }
 
-}  // namespace
-
-hipError_t gemm_launch(const GemmArgs& g, hipStream_t s) {
+template <class T>
+hipError_t gemm_launch_t(const GemmArgsT<T>& g, hipStream_t s) {
   if (g.m <= 0 || g.n <= 0) return hipSuccess;
   if (g.k <= 0 || g.alpha == 0.0) {
     if (g.beta == 1.0) return hipSuccess;
     long tot = (long)g.m * g.n;
-    HSDM_LAUNCH(scale_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, g.m,
+    HSDM_LAUNCH(scale_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, g.m,
                        g.n, g.C, g.ldc, g.beta, g.ccol, g.ndev);
     return hipGetLastError();
   }
   const int am = a_mode(g);
   if ((am == AM_SYM || am == AM_GATHER || am == AM_TRIL) && g.ta != 0) return hipErrorInvalidValue;
   if (am == AM_SLT && g.ta != 1) return hipErrorInvalidValue;
-  Prob p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.acol, g.ccol, g.ndev};
+  ProbT<T> p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.acol, g.ccol, g.ndev};
   return launch_any(p, g.ta, g.tb, am, g.alpha, g.beta, g.flags, 1, 0, 0L, gemm_flops(g), s);
 }
 
-hipError_t gemm_splitk_launch(const GemmArgs& g, int kchunk, double* part, hipStream_t s) {
+template <class T>
+hipError_t gemm_splitk_launch_t(const GemmArgsT<T>& g, int kchunk, T* part, hipStream_t s) {
   if (g.m <= 0 || g.n <= 0) return hipSuccess;
-  if (g.k <= kchunk || kchunk <= 0) return gemm_launch(g, s);
+  if (g.k <= kchunk || kchunk <= 0) return gemm_launch_t(g, s);
   const int am = a_mode(g);
   if (g.ccol || (g.flags & (GF_C_LOWER_ONLY | GF_C_LOWER_TILES)) || am == AM_GATHER ||
       am == AM_SYM)
     return hipErrorInvalidValue;
   if ((am == AM_TRIL && g.ta != 0) || (am == AM_SLT && g.ta != 1)) return hipErrorInvalidValue;
   const int nsplit = ceil_div(g.k, kchunk);
-  Prob p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, part, (long)g.m, g.acol, nullptr, g.ndev};
+  ProbT<T> p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, part, (long)g.m, g.acol, nullptr, g.ndev};
   const long stride = (long)g.m * g.n;
   HSDM_TRY(
       launch_any(p, g.ta, g.tb, am, g.alpha, 0.0, g.flags, nsplit, kchunk, stride, gemm_flops(g), s));
-  HSDM_LAUNCH(splitk_reduce_kernel, dim3((unsigned)((stride + 255) / 256)), dim3(256), 0, s,
+  HSDM_LAUNCH(splitk_reduce_kernel<T>, dim3((unsigned)((stride + 255) / 256)), dim3(256), 0, s,
                      g.m, g.n, nsplit, part, g.C, g.ldc, g.beta, g.ndev);
   return hipGetLastError();
+}
+
+template <class T>
+hipError_t gemm_sym_pair_launch_t(const GemmArgsT<T>& g, int kchunk, T* part1, T* part2,
+                                  hipStream_t s) {
+  if (g.m <= 0 || g.n <= 0) return hipSuccess;
+  if (g.n > 32 || g.m != g.k || kchunk <= 0 || g.ta || g.tb || !(g.flags & GF_A_TRIL))
+    return hipErrorInvalidValue;
+  const int nsplit = ceil_div(g.k, kchunk);
+  ProbT<T> p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, nullptr, (long)g.m, nullptr, nullptr, nullptr};
+  kt_begin(sizeof(T) == 4 ? "sym_pair_kernel<float>" : "sym_pair_kernel", 2.0 * gemm_flops(g),
+           0.0, 0, s);
+  HSDM_LAUNCH(sym_pair_kernel<T>, dim3(tile_grid(ceil_div(g.m, 128), 1), nsplit, 2), dim3(256),
+                     0, s, p, part1, part2, kchunk);
+  kt_end(s);
+  HSDM_TRY(hipGetLastError());
+  const long tot = (long)g.m * g.n;
+  HSDM_LAUNCH(sym_pair_reduce_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                     g.m, g.n, nsplit, part1, part2, g.C, g.ldc);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t gemm_launch(const GemmArgs& g, hipStream_t s) { return gemm_launch_t(g, s); }
+hipError_t gemm_launch(const GemmArgsF& g, hipStream_t s) { return gemm_launch_t(g, s); }
+
+hipError_t gemm_splitk_launch(const GemmArgs& g, int kchunk, double* part, hipStream_t s) {
+  return gemm_splitk_launch_t(g, kchunk, part, s);
+}
+hipError_t gemm_splitk_launch(const GemmArgsF& g, int kchunk, float* part, hipStream_t s) {
+  return gemm_splitk_launch_t(g, kchunk, part, s);
+}
+
+hipError_t gemm_sym_pair_launch(const GemmArgs& g, int kchunk, double* part1, double* part2,
+                                hipStream_t s) {
+  return gemm_sym_pair_launch_t(g, kchunk, part1, part2, s);
+}
+hipError_t gemm_sym_pair_launch(const GemmArgsF& g, int kchunk, float* part1, float* part2,
+                                hipStream_t s) {
+  return gemm_sym_pair_launch_t(g, kchunk, part1, part2, s);
 }
 
 hipError_t gemm_batched_launch(const GemmDesc* d_desc, int count, int max_m, int max_n,
@@ -694,24 +772,6 @@ hipError_t gemm_batched_dense_launch(const GemmDesc* d_desc, int count, int max_
   HSDM_LAUNCH((gemm_batched_kernel<64, 64, 2, 2, 0, 0, AM_DENSE>), dim3(nblk, count),
                      dim3(256), 0, s, d_desc, alpha, beta, flags);
   kt_end(s);
-  return hipGetLastError();
-}
-
-hipError_t gemm_sym_pair_launch(const GemmArgs& g, int kchunk, double* part1, double* part2,
-                                hipStream_t s) {
-  if (g.m <= 0 || g.n <= 0) return hipSuccess;
-  if (g.n > 32 || g.m != g.k || kchunk <= 0 || g.ta || g.tb || !(g.flags & GF_A_TRIL))
-    return hipErrorInvalidValue;
-  const int nsplit = ceil_div(g.k, kchunk);
-  Prob p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, nullptr, (long)g.m, nullptr, nullptr, nullptr};
-  kt_begin("sym_pair_kernel", 2.0 * gemm_flops(g), 0.0, 0, s);
-  HSDM_LAUNCH(sym_pair_kernel, dim3(tile_grid(ceil_div(g.m, 128), 1), nsplit, 2), dim3(256),
-                     0, s, p, part1, part2, kchunk);
-  kt_end(s);
-  HSDM_TRY(hipGetLastError());
-  const long tot = (long)g.m * g.n;
-  HSDM_LAUNCH(sym_pair_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                     g.m, g.n, nsplit, part1, part2, g.C, g.ldc);
   return hipGetLastError();
 }
 

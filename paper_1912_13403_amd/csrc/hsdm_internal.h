@@ -6,11 +6,12 @@
 #include <cstdint>
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
 #define HSDM_DEV __device__ __forceinline__
 
 // ---------------------------------------------------------------------------
-// GEMM: C = alpha * op(A) * op(B) + beta * C, FP64, column-major.
+// GEMM: C = alpha * op(A) * op(B) + beta * C, FP64 (or FP32), column-major.
 // op(A) is m x k, op(B) is k x n.
 enum GemmFlags {
   GF_C_LOWER_TILES = 1,   // skip output tiles that lie entirely above the diagonal
@@ -24,11 +25,14 @@ enum GemmFlags {
   GF_A_SLT = 256,         // op(A) = transpose of the strict lower triangle of A, ta = 1
 };
 
-struct GemmArgs {
+// Element type T = double (FP64 MFMA) or float (FP32 MFMA, the refined
+// form's reduction and back-transform); alpha and beta are given in double.
+template <class T>
+struct GemmArgsT {
   int m, n, k;
-  const double* A; long lda;
-  const double* B; long ldb;
-  double* C; long ldc;
+  const T* A; long lda;
+  const T* B; long ldb;
+  T* C; long ldc;
   double alpha, beta;
   int ta, tb;             // 0: as stored, 1: transposed
   int flags;
@@ -36,6 +40,8 @@ struct GemmArgs {
   const int* ccol;        // optional: column j of the product goes to C[:, ccol[j]]
   const int* ndev;        // optional: device-side column count, n is its upper bound
 };
+using GemmArgs = GemmArgsT<double>;
+using GemmArgsF = GemmArgsT<float>;
 
 // One GEMM of a device-side batch.  Sizes may be written by an earlier kernel.
 struct GemmDesc {
@@ -49,9 +55,11 @@ struct GemmDesc {
 };
 
 hipError_t gemm_launch(const GemmArgs& g, hipStream_t s);
+hipError_t gemm_launch(const GemmArgsF& g, hipStream_t s);
 // Split-K: K cut into slices of kchunk; part holds ceil(k/kchunk) * m * n
 // partial products, summed in slice order (reproducible), then C = sum + beta C.
 hipError_t gemm_splitk_launch(const GemmArgs& g, int kchunk, double* part, hipStream_t s);
+hipError_t gemm_splitk_launch(const GemmArgsF& g, int kchunk, float* part, hipStream_t s);
 // Batched launch: every descriptor uses the same alpha, beta, ta, tb, flags;
 // max_m, max_n bound the sizes any descriptor can take.
 hipError_t gemm_batched_launch(const GemmDesc* d_desc, int count, int max_m, int max_n,

@@ -11,12 +11,22 @@
 // the other.
 hipError_t gemm_sym_pair_launch(const GemmArgs& g, int kchunk, double* part1, double* part2,
                                 hipStream_t s);
+hipError_t gemm_sym_pair_launch(const GemmArgsF& g, int kchunk, float* part1, float* part2,
+                                hipStream_t s);
 
 // sy2sb.hip -- full -> band (half-bandwidth B).  A (lower triangle) is
 // overwritten; Vst receives the explicit panel reflectors (n x n, lower
 // trapezoid), tau1 the scalars, T1 one B x B triangular factor per panel, AB
 // the band in band storage (ldab >= 2B rows per column, rows > B zeroed).
 size_t sy2sb_scratch_doubles(int n, int B);
+// The refined form's reduction: A (lower triangle) in FP32 with FP32
+// trailing updates; the panel QRs in FP64 into Vst, tau1, T1 as above; V32
+// (n x n, ld ldv32) receives the FP32 roundings of the reflectors; AB the
+// band in FP64.  scratch: sy2sb_f32_scratch_bytes(n, B) bytes.
+size_t sy2sb_f32_scratch_bytes(int n, int B);
+hipError_t sy2sb_f32_run(int n, int B, float* A, long lda, double* Vst, long ldv, float* V32,
+                         long ldv32, double* tau1, double* T1, double* AB, int ldab,
+                         void* scratch, DevStatusWord* st, hipStream_t s);
 hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, double* tau1,
                      double* T1, double* AB, int ldab, double* scratch, DevStatusWord* st,
                      hipStream_t s);
@@ -168,6 +178,14 @@ size_t bt1_scratch_doubles(int n, int B, int m);
 hipError_t bt1_zero_fill(int n, int B, double* Vst, long ldv, hipStream_t s);
 hipError_t bt1_apply(int n, int B, const double* Vst, long ldv, const double* T1, double* Z,
                      long ldz, int m, const int* m_dev, double* scratch, hipStream_t s);
+// The same with the group products in FP32 on the matrix cores (the
+// refined form): the groups' T are formed in FP64 from Vst and T1 (scratch
+// as above), then applied with the FP32 reflectors V32 (ld ldv32) to the
+// FP32 Z; scratch32: bt1_f32_scratch_floats(n, B, m) floats.
+size_t bt1_f32_scratch_floats(int n, int B, int m);
+hipError_t bt1_apply_f32(int n, int B, const double* Vst, long ldv, const float* V32,
+                         long ldv32, const double* T1, float* Z, long ldz, int m,
+                         const int* m_dev, double* scratch, float* scratch32, hipStream_t s);
 
 // stedc.hip -- all eigenvalues (ascending) and eigenvectors of a symmetric
 // tridiagonal by divide and conquer.  When m_dev is given, only the first
@@ -214,3 +232,19 @@ hipError_t herm_jmul(int n, int k2, const double* Q, long ldq, double* JQ, long 
                      hipStream_t s);
 hipError_t herm_combine(int n, int k2, int k, const double* Q, long ldq, const void* c, void* X,
                         long ldx, hipStream_t s);
+
+// refine.hip -- eigenpair refinement of the refined form (Ogita-Aishima
+// iterative refinement): steps on the first m columns of X (n x n, the
+// eigenvectors of the symmetric A, lower triangle stored, within FP32
+// rounding; X32 its FP32 copy, kept in step), every column taking part in
+// the corrections, until the largest correction is at most tol or after
+// max_steps.  lam receives the Rayleigh quotients (all n; the first m
+// refined in every step); Y (n x n) is scratch; rec (device) and host_rec
+// (pinned host) receive rec[2k] = delta and rec[2k+1] = max |e_ij| of step
+// k; *steps_done the steps run (the stream is synchronized after each).
+// scratch: refine_scratch_bytes(n, m).
+size_t refine_scratch_bytes(int n, int m);
+hipError_t refine_run(int n, int m, const double* A, long lda, double* X, long ldx, float* X32,
+                      long ldx32, double* Y, long ldy, double* lam, int max_steps, double tol,
+                      void* scratch, double* rec, double* host_rec, int* steps_done,
+                      hipStream_t s);

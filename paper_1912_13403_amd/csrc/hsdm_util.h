@@ -6,6 +6,11 @@
 hipError_t dev_fill(double* a, long lda, int m, int n, double v, hipStream_t s);
 hipError_t dev_copy(const double* a, long lda, double* b, long ldb, int m, int n, hipStream_t s);
 hipError_t dev_sym_full(const double* a, long lda, double* b, long ldb, int n, hipStream_t s);
+// b = a (m x n) converted between FP64 and FP32 (round to nearest), and the
+// FP32 copy
+hipError_t dev_convert(const double* a, long lda, float* b, long ldb, int m, int n, hipStream_t s);
+hipError_t dev_convert(const float* a, long lda, double* b, long ldb, int m, int n, hipStream_t s);
+hipError_t dev_copy(const float* a, long lda, float* b, long ldb, int m, int n, hipStream_t s);
 hipError_t dev_mirror_lower(double* a, long lda, int n, hipStream_t s);
 // out[0] += 64-bit content hash of the lower triangle of a (n x n; cplx:
 // interleaved complex, lda in complex elements); dev_hash_clear zeroes

@@ -484,6 +484,43 @@ __global__ void fill_nan_group_kernel(const PanelQrTask* tasks) {
     q.part[i] = __builtin_nan("");
 }
 
+// Householder QR of one panel (the task's P, V, tau, T and exchange slots;
+// span: how many exchange slots to reset first).  Beside other solves
+// (a concurrent handle) no workgroup waits for another: one launch per
+// column for several workgroups, an ordinary launch for one; otherwise one
+// cooperative launch.  Algorithmic: 2 h B^2 flops, the panel read and
+// written once.
+hipError_t run_panel_qr(PanelQrTask q, hipStream_t s) {
+  constexpr int BB = 32;
+  const int B = BB;
+  if (q.span > 0) {
+    HSDM_LAUNCH(fill_nan_kernel, dim3((unsigned)((q.span + 255) / 256)), dim3(256), 0, s,
+                q.part, q.span);
+    HSDM_TRY(hipGetLastError());
+  }
+  void* args[] = {(void*)&q.h, (void*)&q.P, (void*)&q.ldp, (void*)&q.V, (void*)&q.ldv,
+                  (void*)&q.tau, (void*)&q.T, (void*)&q.part, (void*)&q.prow, (void*)&q.gpart,
+                  (void*)&q.st};
+  if (coop_get_shared()) {
+    if (q.G == 1) {
+      HSDM_LAUNCH(panel_qr_kernel<BB>, dim3(1), dim3(NT), 0, s, q.h, q.P, q.ldp, q.V, q.ldv,
+                  q.tau, q.T, q.part, q.prow, q.gpart, q.st);
+      return hipGetLastError();
+    }
+    kt_begin("panel_step_kernel<32>", 2.0 * q.h * B * B, 16.0 * q.h * B, 0, s);
+    for (int j = -1; j < BB; j++) {
+      HSDM_LAUNCH(panel_step_kernel<BB>, dim3(q.G), dim3(NT), 0, s, q.h, q.P, q.ldp, q.V,
+                  q.ldv, q.tau, q.part, q.prow, q.gpart, j);
+      HSDM_TRY(hipGetLastError());
+    }
+    HSDM_LAUNCH(panel_t_kernel<BB>, dim3(1), dim3(NT), 0, s, q.tau, q.T, q.gpart, q.G);
+    kt_end(s);
+    return hipGetLastError();
+  }
+  return coop_launch("panel_qr_kernel<32>", 2.0 * q.h * B * B, 16.0 * q.h * B, false, true,
+                     (const void*)panel_qr_kernel<BB>, dim3(q.G), dim3(NT), args, s);
+}
+
 // Band extraction: AB[(r-c) + c*ldab] = A[r + c*lda] for 0 <= r-c <= B, zero
 // for B < r-c < ldab.
 __global__ void band_extract_kernel(int n, int B, const double* A, long lda, double* AB,
@@ -653,39 +690,7 @@ struct Sy2sb {
     q.span = q.G > 1 ? (long)(gpart - part) + (long)B * B * q.G : 0;
     return q;
   }
-  hipError_t qr_panel(int p) {
-    PanelQrTask q = qr_desc(p);
-    if (q.span > 0) {
-      HSDM_LAUNCH(fill_nan_kernel, dim3((unsigned)((q.span + 255) / 256)), dim3(256), 0, s,
-                         part, q.span);
-      HSDM_TRY(hipGetLastError());
-    }
-    void* args[] = {(void*)&q.h, (void*)&q.P, (void*)&q.ldp, (void*)&q.V, (void*)&q.ldv,
-                    (void*)&q.tau, (void*)&q.T, (void*)&q.part, (void*)&q.prow, (void*)&q.gpart,
-                    (void*)&q.st};
-    // algorithmic: Householder QR of the h x B panel (2 h B^2 flops), the
-    // panel read and written once
-    if (coop_get_shared()) {
-      // beside other solves: no workgroup waits for another (one launch per
-      // column for several workgroups, an ordinary launch for one)
-      if (q.G == 1) {
-        HSDM_LAUNCH(panel_qr_kernel<BB>, dim3(1), dim3(NT), 0, s, q.h, q.P, q.ldp, q.V, q.ldv,
-                    q.tau, q.T, q.part, q.prow, q.gpart, q.st);
-        return hipGetLastError();
-      }
-      kt_begin("panel_step_kernel<32>", 2.0 * q.h * B * B, 16.0 * q.h * B, 0, s);
-      for (int j = -1; j < BB; j++) {
-        HSDM_LAUNCH(panel_step_kernel<BB>, dim3(q.G), dim3(NT), 0, s, q.h, q.P, q.ldp, q.V,
-                    q.ldv, q.tau, q.part, q.prow, q.gpart, j);
-        HSDM_TRY(hipGetLastError());
-      }
-      HSDM_LAUNCH(panel_t_kernel<BB>, dim3(1), dim3(NT), 0, s, q.tau, q.T, q.gpart, q.G);
-      kt_end(s);
-      return hipGetLastError();
-    }
-    return coop_launch("panel_qr_kernel<32>", 2.0 * q.h * B * B, 16.0 * q.h * B, false, true,
-                       (const void*)panel_qr_kernel<BB>, dim3(q.G), dim3(NT), args, s);
-  }
+  hipError_t qr_panel(int p) { return run_panel_qr(qr_desc(p), s); }
   // W (h x B, ld n, holding X on entry) = X - V M / 2 with Y = V T, X = A[r:, r:] Y,
   // M = Y^T X.  Vp: the panel's V (ld ldv), Tp its T; Y receives V T.
   // In three steps (the middle one, the two passes of the symmetric product,
@@ -1191,4 +1196,135 @@ hipError_t sy2sb_run_group(int nt, const Sy2sbArgs* t, int B, Sy2sbGroupHost& ho
   }
   for (auto& r : R) HSDM_TRY(r.finish());
   return hipSuccess;
+}
+
+// ---- the refined form's reduction -------------------------------------------
+// The same reduction with the trailing updates in FP32 on the matrix cores:
+// A (lower triangle) is held in FP32; each panel is copied to FP64 for its
+// Householder QR (the panel step is latency-bound, so its precision costs
+// nothing), the explicit reflectors go to Vst and T1 in FP64 as in the FP64
+// reduction, and their FP32 roundings (V32, the panel's T) drive the two-sided
+// update of the trailing block, one panel at a time:
+//   Y = V T,  X = A22 Y,  M = Y^T X,  W = X - V M / 2,  A22 <- A22 - [V W][W V]^T.
+// The result is the band of a matrix within FP32 rounding of an orthogonal
+// similarity of A; the refinement that follows the eigensolve restores FP64
+// accuracy against the FP64 standard-form matrix.
+namespace {
+
+__global__ void band_extract_f32_kernel(int n, int B, const float* A, long lda, double* AB,
+                                        int ldab) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)n * ldab) return;
+  const int off = (int)(idx % ldab), c = (int)(idx / ldab);
+  const int r = c + off;
+  AB[idx] = (off <= B && r < n) ? (double)A[r + (long)c * lda] : 0.0;
+}
+
+constexpr int F32_MCHUNK = 1024;  // K slice of M = Y^T X
+
+struct Sy2sbF32Layout {
+  double *P64, *part, *prow, *gpart;
+  float *T32, *Y, *VW, *WV, *M, *mpart, *sk1, *sk2;
+  size_t bytes;
+};
+
+Sy2sbF32Layout f32_layout(int n, int B, char* base) {
+  const int Gmax = ceil_div(n, CH) + 1;
+  const size_t nsplit = ceil_div(n, SPLITK) + 1;
+  const size_t msplit = ceil_div(n, F32_MCHUNK) + 1;
+  Sy2sbF32Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  L.P64 = (double*)take(sizeof(double) * n * B);
+  // part, prow, gpart contiguous (reset to NaN together)
+  L.part = (double*)take(sizeof(double) * ((size_t)B * Gmax * B + (size_t)B * B +
+                                           (size_t)Gmax * B * B));
+  L.prow = L.part ? L.part + (size_t)B * Gmax * B : nullptr;
+  L.gpart = L.prow ? L.prow + (size_t)B * B : nullptr;
+  L.T32 = (float*)take(sizeof(float) * B * B);
+  L.Y = (float*)take(sizeof(float) * n * B);
+  L.VW = (float*)take(sizeof(float) * n * 2 * B);
+  L.WV = (float*)take(sizeof(float) * n * 2 * B);
+  L.M = (float*)take(sizeof(float) * B * B);
+  L.mpart = (float*)take(sizeof(float) * msplit * B * B);
+  L.sk1 = (float*)take(sizeof(float) * nsplit * n * B);
+  L.sk2 = (float*)take(sizeof(float) * nsplit * n * B);
+  L.bytes = off;
+  return L;
+}
+
+}  // namespace
+
+size_t sy2sb_f32_scratch_bytes(int n, int B) { return f32_layout(n, B, nullptr).bytes; }
+
+hipError_t sy2sb_f32_run(int n, int B, float* A, long lda, double* Vst, long ldv, float* V32,
+                         long ldv32, double* tau1, double* T1, double* AB, int ldab,
+                         void* scratch, DevStatusWord* st, hipStream_t s) {
+  if (B != 32) return hipErrorInvalidValue;
+  const Sy2sbF32Layout L = f32_layout(n, B, (char*)scratch);
+  const int np = (n > B) ? ceil_div(n - 1, B) : 0;
+  for (int p = 0; p < np; p++) {
+    const int c0 = p * B, r0 = c0 + B, h = n - r0;
+    if (h <= 0) break;
+    // the panel's QR in FP64
+    HSDM_TRY(dev_convert(A + r0 + (long)c0 * lda, lda, L.P64, n, h, B, s));
+    PanelQrTask q{};
+    q.P = L.P64; q.ldp = n;
+    q.V = Vst + r0 + (long)c0 * ldv; q.ldv = ldv;
+    q.tau = tau1 + c0;
+    q.T = T1 + (size_t)p * B * B;
+    q.part = L.part; q.prow = L.prow; q.gpart = L.gpart; q.st = st;
+    q.h = h;
+    q.G = ceil_div(h, CH);
+    q.span = q.G > 1 ? (long)(L.gpart - L.part) + (long)B * B * q.G : 0;
+    HSDM_TRY(run_panel_qr(q, s));
+    HSDM_TRY(dev_convert(L.P64, n, A + r0 + (long)c0 * lda, lda, h, B, s));  // R for the band
+    // the whole column block: the zeros above the panel's first reflector
+    // row are part of the grouped reflectors of the back-transform
+    HSDM_TRY(dev_convert(Vst + (long)c0 * ldv, ldv, V32 + (long)c0 * ldv32, ldv32, n, B, s));
+    float* Vp = V32 + r0 + (long)c0 * ldv32;
+    HSDM_TRY(dev_convert(q.T, B, L.T32, B, B, B, s));
+    if (h <= 1) continue;
+    float* A22 = A + r0 + (long)r0 * lda;
+    float* W = L.VW + (size_t)n * B;  // X, then W, in place in [V W]
+    GemmArgsF g{};
+    g.m = h; g.n = B; g.k = B; g.A = Vp; g.lda = ldv32; g.B = L.T32; g.ldb = B; g.C = L.Y;
+    g.ldc = n; g.alpha = 1.0; g.beta = 0.0; g.flags = GF_KB_UPPER;
+    HSDM_TRY(gemm_launch(g, s));
+    GemmArgsF t{};
+    t.m = h; t.n = B; t.k = h; t.A = A22; t.lda = lda; t.B = L.Y; t.ldb = n; t.C = W; t.ldc = n;
+    t.alpha = 1.0; t.beta = 0.0; t.flags = GF_A_TRIL | GF_KA_LOWER;
+    if (h > SPLITK) {
+      HSDM_TRY(gemm_sym_pair_launch(t, SPLITK, L.sk1, L.sk2, s));
+    } else {
+      HSDM_TRY(gemm_splitk_launch(t, SPLITK, L.sk1, s));
+      GemmArgsF u = t;
+      u.ta = 1; u.beta = 1.0; u.flags = GF_A_SLT | GF_KA_UPPER;
+      HSDM_TRY(gemm_splitk_launch(u, SPLITK, L.sk1, s));
+    }
+    g = GemmArgsF{};
+    g.m = B; g.n = B; g.k = h; g.A = L.Y; g.lda = n; g.B = W; g.ldb = n; g.C = L.M; g.ldc = B;
+    g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
+    HSDM_TRY(gemm_splitk_launch(g, F32_MCHUNK, L.mpart, s));
+    g = GemmArgsF{};
+    g.m = h; g.n = B; g.k = B; g.A = Vp; g.lda = ldv32; g.B = L.M; g.ldb = B; g.C = W; g.ldc = n;
+    g.alpha = -0.5; g.beta = 1.0;
+    HSDM_TRY(gemm_launch(g, s));
+    HSDM_TRY(dev_copy(Vp, ldv32, L.VW, n, h, B, s));
+    HSDM_TRY(dev_copy(W, n, L.WV, n, h, B, s));
+    HSDM_TRY(dev_copy(Vp, ldv32, L.WV + (size_t)n * B, n, h, B, s));
+    g = GemmArgsF{};
+    g.m = h; g.n = h; g.k = 2 * B; g.A = L.VW; g.lda = n; g.B = L.WV; g.ldb = n; g.C = A22;
+    g.ldc = lda; g.alpha = -1.0; g.beta = 1.0; g.ta = 0; g.tb = 1;
+    g.flags = GF_C_LOWER_TILES | GF_C_LOWER_ONLY;
+    HSDM_TRY(gemm_launch(g, s));
+  }
+  const long tot = (long)n * ldab;
+  HSDM_LAUNCH(band_extract_f32_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n,
+              B, A, lda, AB, ldab);
+  return hipGetLastError();
 }

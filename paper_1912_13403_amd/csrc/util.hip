@@ -18,12 +18,13 @@ __global__ void fill_kernel(double* a, long lda, int m, int n, double v) {
   }
 }
 
-__global__ void copy_kernel(const double* a, long lda, double* b, long ldb, int m, int n) {
+template <class Ti, class To>
+__global__ void copy_kernel(const Ti* a, long lda, To* b, long ldb, int m, int n) {
   long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   long tot = (long)m * n;
   for (; idx < tot; idx += (long)gridDim.x * blockDim.x) {
     int i = (int)(idx % m), j = (int)(idx / m);
-    b[i + (long)j * ldb] = a[i + (long)j * lda];
+    b[i + (long)j * ldb] = (To)a[i + (long)j * lda];
   }
 }
 
@@ -151,11 +152,25 @@ hipError_t dev_fill(double* a, long lda, int m, int n, double v, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t dev_copy(const double* a, long lda, double* b, long ldb, int m, int n, hipStream_t s) {
+template <class Ti, class To>
+hipError_t copy_as(const Ti* a, long lda, To* b, long ldb, int m, int n, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  HSDM_LAUNCH(copy_kernel, dim3(grid_for((long)m * n)), dim3(256), 0, s, a, lda, b, ldb, m,
-                     n);
+  HSDM_LAUNCH((copy_kernel<Ti, To>), dim3(grid_for((long)m * n)), dim3(256), 0, s, a, lda, b,
+              ldb, m, n);
   return hipGetLastError();
+}
+
+hipError_t dev_copy(const double* a, long lda, double* b, long ldb, int m, int n, hipStream_t s) {
+  return copy_as(a, lda, b, ldb, m, n, s);
+}
+hipError_t dev_copy(const float* a, long lda, float* b, long ldb, int m, int n, hipStream_t s) {
+  return copy_as(a, lda, b, ldb, m, n, s);
+}
+hipError_t dev_convert(const double* a, long lda, float* b, long ldb, int m, int n, hipStream_t s) {
+  return copy_as(a, lda, b, ldb, m, n, s);
+}
+hipError_t dev_convert(const float* a, long lda, double* b, long ldb, int m, int n, hipStream_t s) {
+  return copy_as(a, lda, b, ldb, m, n, s);
 }
 
 hipError_t dev_sym_full(const double* a, long lda, double* b, long ldb, int n, hipStream_t s) {

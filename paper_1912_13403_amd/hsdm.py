@@ -37,6 +37,8 @@ HSDM_KEY_TIMING = 4
 HSDM_KEY_STREAMS = 5
 HSDM_KEY_N_STATES = 6
 HSDM_KEY_CONCURRENT = 7
+HSDM_KEY_PRECISION = 8
+HSDM_KEY_REFINE_STEPS = 9
 
 EXPORTED = [
     "hsdm_init", "hsdm_finalize", "hsdm_reinit", "hsdm_set_real", "hsdm_set_int",
@@ -47,7 +49,7 @@ EXPORTED = [
     "hsdm_tridiagonalize", "hsdm_tridiag_eigh", "hsdm_occupations", "hsdm_density",
     "hsdm_dgemm", "hsdm_status_string", "hsdm_last_error", "hsdm_status_detail",
     "hsdm_phase_times", "hsdm_phase_name", "hsdm_phase_flops", "hsdm_kernel_count", "hsdm_kernel_stat",
-    "hsdm_version", "hsdm_timing_kernel", "hsdm_solve_dm_real_noalloc",
+    "hsdm_version", "hsdm_timing_kernel", "hsdm_solve_dm_real_noalloc", "hsdm_refine_history",
 ]
 
 HSDM_NOALLOC_MAX_N = 512
@@ -106,6 +108,7 @@ def load_library(path: str = LIB_PATH):
         "hsdm_kernel_stat": ([_vp, _i, ctypes.POINTER(_d)], ctypes.c_char_p),
         "hsdm_version": ([], _i),
         "hsdm_timing_kernel": ([_vp, ctypes.c_char_p], _i),
+        "hsdm_refine_history": ([_vp, ctypes.POINTER(_d), _i], _i),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -244,6 +247,15 @@ class Handle:
         buf = (ctypes.c_double * 16)()
         k = self._lib.hsdm_phase_flops(self._h, buf, 16)
         return {self._lib.hsdm_phase_name(i).decode(): buf[i] for i in range(k)}
+
+    def refine_history(self):
+        """Steps of the last refined-form solve: [(delta, max |e_ij|), ...]
+        (empty after an FP64 solve)."""
+        buf = (ctypes.c_double * 16)()
+        k = self._lib.hsdm_refine_history(self._h, buf, 16)
+        if k < 0:
+            self._check(k)
+        return [(buf[2 * i], buf[2 * i + 1]) for i in range(min(k, 8))]
 
     def kernel_stats(self):
         """Per-kernel totals of the last solve (HSDM_KEY_TIMING = 2):
