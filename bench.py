@@ -84,10 +84,10 @@ def cpu_baseline(target_n: int):
     H, S, p = inputs.config_problem("cfg2sub_n4096")
     ns = p["n"]
     t0 = time.perf_counter()
-    O.solve_dm(H, S, p["n_electrons"], p["kT"], f_max=p["f_max"])
+    ref = O.solve_dm(H, S, p["n_electrons"], p["kT"], f_max=p["f_max"])
     dt = time.perf_counter() - t0
     scale = (target_n / ns) ** 3
-    return {
+    return ref, {
         "value": dt * scale,
         "unit": "s",
         "cores": O.num_threads(),
@@ -441,6 +441,8 @@ def main():
                          "(1: single solves)")
     ap.add_argument("--slots", type=int, default=2,
                     help="concurrent request slots of --config cfg4_serving")
+    ap.add_argument("--refine-steps", type=int, default=8,
+                    help="most refinement steps of the refined form (HSDM_KEY_REFINE_STEPS)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-warm", action="store_true",
                     help="skip the extra solve with the S factor cached")
@@ -587,9 +589,83 @@ def main():
         "timed_total_s": total,
     }
     h.close()
+    rec["refined_form"] = refined_form(args, Hd, Sd, p, D, E, w)
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(n)
+        ref, rec["cpu_baseline"] = cpu_baseline(n)
+        rec["error_vs_oracle_n4096"] = forms_vs_oracle(ref, dev)
     print(json.dumps(rec))
+
+
+def refined_form(args, Hd, Sd, p, D64, E64, w64):
+    """The refined form (HSDM_KEY_PRECISION = 1) on the same inputs: one
+    warmup and the same number of timed steps, its phases, refinement record
+    and largest differences from the FP64 form's D, E and eigenvalues."""
+    import numpy as np
+    import torch
+
+    from paper_1912_13403_amd import hsdm
+
+    h = hsdm.Handle(0)
+    try:
+        h.hsdm_set_int(hsdm.HSDM_KEY_PRECISION, 1)
+        h.hsdm_set_int(hsdm.HSDM_KEY_REFINE_STEPS, args.refine_steps)
+        h.hsdm_set_int(hsdm.HSDM_KEY_TIMING, 1)
+        times, phases = [], []
+        for i in range(1 + args.steps):
+            h.hsdm_reinit()
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            r = h.hsdm_solve_dm_real(Hd, Sd, p["n_electrons"], p["kT"])
+            torch.cuda.synchronize()
+            if i > 0:
+                times.append(time.perf_counter() - ts)
+                phases.append(h.phase_times())
+            print(f"[bench] refined form step {i}: {time.perf_counter() - ts:.3f}s",
+                  file=sys.stderr, flush=True)
+        hist = h.refine_history()
+        ph = {k: float(np.median([q[k] for q in phases])) for k in phases[0]}
+        out = {
+            "ms_per_step": 1000.0 * float(np.mean(times)),
+            "steps": args.steps,
+            "phases_ms": ph,
+            "refinement_steps": [{"delta": a, "max_correction": b} for a, b in hist],
+            "max_abs_dD_vs_fp64": float(torch.max(torch.abs(r["D"] - D64)).item()),
+            "max_abs_dE_vs_fp64": float(torch.max(torch.abs(r["E"] - E64)).item()),
+            "max_abs_deig_vs_fp64": float(torch.max(torch.abs(r["eval"] - w64)).item()),
+            "mu": r["mu"],
+            "band_energy": r["band_energy"],
+        }
+        del r
+        return out
+    finally:
+        h.close()
+
+
+def forms_vs_oracle(ref, dev):
+    """Largest errors of both forms against the FP64 oracle on the n = 4096
+    problem of the n = 16384 recipe (the oracle's solution from the CPU
+    baseline run)."""
+    import numpy as np
+    import torch
+
+    from paper_1912_13403_amd import hsdm, inputs
+
+    H, S, p = inputs.config_problem("cfg2sub_n4096")
+    Hd, Sd = torch.from_numpy(H).to(dev), torch.from_numpy(S).to(dev)
+    scale = float(np.abs(H).sum(axis=0).max())
+    res = {"norm1_H": scale}
+    for name, prec in (("fp64", 0), ("refined", 1)):
+        with hsdm.Handle(0) as h:
+            h.hsdm_set_int(hsdm.HSDM_KEY_PRECISION, prec)
+            o = h.hsdm_solve_dm_real(Hd, Sd, p["n_electrons"], p["kT"])
+            res[name] = {
+                "max_abs_dD": float(np.abs(o["D"].cpu().numpy() - ref["D"]).max()),
+                "max_abs_dE": float(np.abs(o["E"].cpu().numpy() - ref["E"]).max()),
+                "max_abs_deig": float(np.abs(o["eval"].cpu().numpy() - ref["eval"]).max()),
+                "abs_dmu": abs(o["mu"] - ref["mu"]),
+                "refinement_steps": len(h.refine_history()),
+            }
+    return res
 
 
 if __name__ == "__main__":

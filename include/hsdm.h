@@ -91,7 +91,7 @@ enum hsdm_key {
                               the order of its square).  The complex, multi-task and
                               allocation-free solves always run the FP64 form */
   , HSDM_KEY_REFINE_STEPS = 9 /* int: most refinement steps of the refined form, 1 ... 8
-                              (default 4) */
+                              (default 8) */
 };
 
 /* Create a handle bound to HIP device `device` (~ elsi_init, Sec. 2.1). */

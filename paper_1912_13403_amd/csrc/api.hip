@@ -79,7 +79,7 @@ struct hsdm_ctx {
   long n_states = 0;      // eigenvectors formed by the eigenpair solves (0: all)
   bool concurrent = false;  // solves may overlap other handles' on the device
   int precision = 0;        // 0: FP64 throughout; 1: the refined form (real pencils)
-  int refine_steps = 4;     // most refinement steps of the refined form
+  int refine_steps = 8;     // most refinement steps of the refined form
   // workspace of the refined form (grown on demand)
   void* rws_raw = nullptr;
   size_t rws_cap = 0;
