@@ -130,9 +130,11 @@ def oracle_timing():
     runs = []
     for name in ("cfg0_n512", "cfg1_n4096", "cfg2sub_n4096"):
         for threads in (1, ncpu):
-            env = dict(os.environ, OMP_NUM_THREADS=str(threads))
-            r = subprocess.run([sys.executable, "-c", code, name], env=env, capture_output=True,
-                               text=True, check=True)
+            env = dict(os.environ, OMP_NUM_THREADS=str(threads), ORC_PROGRESS="1")
+            print(f"[oracle-timing] {name} threads={threads}: start", file=sys.stderr, flush=True)
+            # the oracle's step reports go straight to this process's stderr
+            r = subprocess.run([sys.executable, "-c", code, name], env=env,
+                               stdout=subprocess.PIPE, text=True, check=True)
             rec = json.loads(r.stdout.strip().splitlines()[-1])
             runs.append({"config": name, "threads": rec["threads"], "seconds": rec["s"]})
             print(f"[oracle-timing] {name} threads={rec['threads']}: {rec['s']:.2f} s",
@@ -443,6 +445,8 @@ def main():
                     help="concurrent request slots of --config cfg4_serving")
     ap.add_argument("--refine-steps", type=int, default=8,
                     help="most refinement steps of the refined form (HSDM_KEY_REFINE_STEPS)")
+    ap.add_argument("--no-refined", action="store_true",
+                    help="skip the refined form's steps (e.g. under a profiler)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-warm", action="store_true",
                     help="skip the extra solve with the S factor cached")
@@ -589,7 +593,8 @@ def main():
         "timed_total_s": total,
     }
     h.close()
-    rec["refined_form"] = refined_form(args, Hd, Sd, p, D, E, w)
+    if not args.no_refined:
+        rec["refined_form"] = refined_form(args, Hd, Sd, p, D, E, w)
     if not args.no_cpu_baseline:
         ref, rec["cpu_baseline"] = cpu_baseline(n)
         rec["error_vs_oracle_n4096"] = forms_vs_oracle(ref, dev)

@@ -41,7 +41,23 @@
 #include <omp.h>
 #endif
 
+#include <stdio.h>
+
 #define AT(a, i, j, n) ((a)[(size_t)(j) * (size_t)(n) + (size_t)(i)])
+
+/* With ORC_PROGRESS set in the environment, the whole solves report each
+ * finished step on stderr (a long single-threaded run is then not silent).
+ * No arithmetic depends on it. */
+static void progress(const char *step, int n, int k) {
+    static int on = -1;
+    if (on < 0) on = getenv("ORC_PROGRESS") != NULL;
+    if (!on) return;
+    if (k >= 0)
+        fprintf(stderr, "[oracle] n=%d %s %d\n", n, step, k);
+    else
+        fprintf(stderr, "[oracle] n=%d %s\n", n, step);
+    fflush(stderr);
+}
 
 int orc_num_threads(void) {
 #ifdef _OPENMP
@@ -229,6 +245,7 @@ int orc_tql(int n, double *d, const double *ein, double *Z) {
     for (int i = 0; i + 1 < n; i++) e[i] = ein[i];
     int status = 0;
     for (int l = 0; l < n && !status; l++) {
+        if (l > 0 && l % 512 == 0) progress("QL: eigenvalues done", n, l);
         int steps = 0;
         for (;;) {
             int m = l;
@@ -426,12 +443,17 @@ static int eigen_pairs(int n, const double *H, const double *S, double *eval, do
     double *e = (double *)calloc((size_t)n + 1, sizeof(double));
     int st = orc_cholesky(n, S, L);
     if (st) { if (info_col) *info_col = st; st = 1; goto done; }
+    progress("Cholesky done", n, -1);
     orc_standard_form(n, H, L, A);
+    progress("standard form done", n, -1);
     orc_tridiagonalize(n, A, eval, e, Q);
+    progress("tridiagonalization done", n, -1);
     st = orc_tql(n, eval, e, Q);
     if (st) goto done;
+    progress("QL done", n, -1);
     orc_sort_pairs(n, eval, Q);
     orc_back_transform(n, n, L, Q, C);
+    progress("back-transform done", n, -1);
 done:
     if (!Lkeep) free(L);
     free(A); free(Q); free(e);
