@@ -445,6 +445,9 @@ def main():
                     help="concurrent request slots of --config cfg4_serving")
     ap.add_argument("--refine-steps", type=int, default=8,
                     help="most refinement steps of the refined form (HSDM_KEY_REFINE_STEPS)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run one untimed solve with the GEMM tile autotuner first "
+                         "(HSDM_KEY_AUTOTUNE); the timed steps use its table")
     ap.add_argument("--no-refined", action="store_true",
                     help="skip the refined form's steps (e.g. under a profiler)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -493,6 +496,17 @@ def main():
     print(f"[bench] inputs ready n={n} in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
           flush=True)
     h = hsdm.Handle(0)
+    tile_classes = None
+    if args.autotune:
+        # one untimed solve with the tile autotuner on: each product class of
+        # the solve times the candidate tiles once; the steps below use the table
+        h.hsdm_set_int(hsdm.HSDM_KEY_AUTOTUNE, 1)
+        h.hsdm_solve_dm_real(Hd, Sd, p["n_electrons"], p["kT"])
+        h.hsdm_set_int(hsdm.HSDM_KEY_AUTOTUNE, 0)
+        torch.cuda.synchronize()
+        tile_classes = hsdm.load_library().hsdm_tune_entries()
+        print(f"[bench] autotune: {tile_classes} product classes timed", file=sys.stderr,
+              flush=True)
     # The first warmup step times every launch (timing level 2) to find the
     # dominant kernel; the timed steps then record events only around that
     # kernel's launches, so the other launches of a solve carry no event
@@ -588,6 +602,8 @@ def main():
         "dominant_phase": max(ph, key=lambda k: ph[k]),
         "kernels": kernels,
         "warm_s_factor_s": warm,
+        "gemm_tiles": ({"autotuned_classes": tile_classes} if tile_classes is not None
+                       else "built-in rule"),
         "mu": r["mu"],
         "band_energy": r["band_energy"],
         "timed_total_s": total,
@@ -614,6 +630,10 @@ def refined_form(args, Hd, Sd, p, D64, E64, w64):
     try:
         h.hsdm_set_int(hsdm.HSDM_KEY_PRECISION, 1)
         h.hsdm_set_int(hsdm.HSDM_KEY_REFINE_STEPS, args.refine_steps)
+        if args.autotune:
+            h.hsdm_set_int(hsdm.HSDM_KEY_AUTOTUNE, 1)
+            h.hsdm_solve_dm_real(Hd, Sd, p["n_electrons"], p["kT"])
+            h.hsdm_set_int(hsdm.HSDM_KEY_AUTOTUNE, 0)
         h.hsdm_set_int(hsdm.HSDM_KEY_TIMING, 1)
         times, phases = [], []
         for i in range(1 + args.steps):

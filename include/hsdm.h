@@ -92,6 +92,27 @@ enum hsdm_key {
                               allocation-free solves always run the FP64 form */
   , HSDM_KEY_REFINE_STEPS = 9 /* int: most refinement steps of the refined form, 1 ... 8
                               (default 8) */
+  , HSDM_KEY_GRAPH = 11    /* int: 1 = hsdm_solve_dm_real (FP64 form, timing off, not
+                              concurrent, autotuner off) records its device work as a HIP graph
+                              on the first call with a given set of buffers (H, S, D, E and
+                              their leading dimensions), n, n_electrons, kT, settings and state
+                              of the cached factor of S, and replays that graph on later such
+                              calls -- the repeat-size solves of an SCF loop, which pass the
+                              same buffers with new contents.  The graph runs on a stream of
+                              the handle, ordered after the caller's stream and joined back into
+                              it.  At most 4 graphs are kept per handle (least recently used
+                              dropped); they are dropped when the workspace is reallocated or
+                              the key is set to 0 (default) */
+  , HSDM_KEY_AUTOTUNE = 10 /* int, process-wide (any handle sets it): 1 = the GEMM tile
+                              autotuner is on -- the first product of each class not yet in the
+                              tile table (element type, transposes, operand form, lower output,
+                              bit lengths of m, n, k) runs the candidate tiles on its own
+                              operands, C saved and restored around each run, and the fastest
+                              enters the table; that solve is slower (it synchronizes and
+                              allocates), later ones use the table.  Tiles never change a
+                              result: every tile sums each element's products over k in the
+                              same order.  0 (default): products use the table where it has
+                              their class, else the built-in rule */
 };
 
 /* Create a handle bound to HIP device `device` (~ elsi_init, Sec. 2.1). */
@@ -111,7 +132,8 @@ int hsdm_reinit(hsdm_handle h);
  * configure a handle between elsi_init and the solves).  hsdm_set_real takes
  * HSDM_KEY_FMAX, HSDM_KEY_FCUT, HSDM_KEY_DEG_TOL; hsdm_set_int takes
  * HSDM_KEY_TIMING, HSDM_KEY_STREAMS, HSDM_KEY_N_STATES, HSDM_KEY_CONCURRENT,
- * HSDM_KEY_PRECISION, HSDM_KEY_REFINE_STEPS.  Returns HSDM_OK,
+ * HSDM_KEY_PRECISION, HSDM_KEY_REFINE_STEPS, HSDM_KEY_AUTOTUNE, HSDM_KEY_GRAPH.
+ * Returns HSDM_OK,
  * -1 (null handle), -2 (unknown key for this call) or -3 (value out of the
  * key's range; the setting is left unchanged).  Settings apply to the solves
  * that follow and are kept across hsdm_reinit. */
@@ -308,6 +330,20 @@ int hsdm_status_detail(hsdm_handle h);
  * of phases written (at most cap). */
 int hsdm_phase_times(hsdm_handle h, double *times, int cap);
 const char *hsdm_phase_name(int i);
+/* How the last hsdm_solve_dm_real ran: 0 eagerly, 1 recorded as a graph
+ * and run, 2 by replaying a recorded graph (HSDM_KEY_GRAPH); -1 null handle. */
+int hsdm_last_graph(hsdm_handle h);
+/* The GEMM tile table of the autotuner (HSDM_KEY_AUTOTUNE), process-wide:
+ * hsdm_tune_entries returns its size; hsdm_tune_clear empties it;
+ * hsdm_tune_save writes it to a text file (HSDM_OK, -1 path missing,
+ * HSDM_DEVICE_ERROR if the file cannot be written); hsdm_tune_load merges
+ * such a file into it and returns the number of entries read (-1 path
+ * missing, -2 the file cannot be opened, -3 malformed: nothing merged).
+ * Needs no GPU. */
+int hsdm_tune_entries(void);
+int hsdm_tune_clear(void);
+int hsdm_tune_save(const char *path);
+int hsdm_tune_load(const char *path);
 /* Record of the refinement of the last real solve in the refined form
  * (HSDM_KEY_PRECISION = 1): returns the number of steps k (0 after an FP64
  * solve; -1 null handle, -3 cap < 0 or out missing) and writes, for the

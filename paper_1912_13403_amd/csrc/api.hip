@@ -59,6 +59,31 @@ __global__ void copy_vec_kernel(const double* a, double* b, int n) {
   if (i < n) b[i] = a[i];
 }
 
+// Everything a recorded density-matrix solve depends on: the caller's
+// buffers and settings, whether the factor of S was cached (the recorded
+// work differs), and the workspace it was recorded against.
+struct GraphKey {
+  int n, ldh, lds, ldd, lde;
+  const double *H, *S;
+  double *D, *E;
+  double ne, kT, fmax, fcut, deg_tol;
+  bool cached;
+  void* ws;
+  bool operator==(const GraphKey& o) const {
+    return n == o.n && ldh == o.ldh && lds == o.lds && ldd == o.ldd && lde == o.lde &&
+           H == o.H && S == o.S && D == o.D && E == o.E && ne == o.ne && kT == o.kT &&
+           fmax == o.fmax && fcut == o.fcut && deg_tol == o.deg_tol && cached == o.cached &&
+           ws == o.ws;
+  }
+};
+
+struct SolveGraph {
+  GraphKey key;
+  hipGraphExec_t exec;
+  long last_use;
+};
+constexpr size_t MAX_GRAPHS = 4;
+
 struct Pinned {
   DevStatusWord st;
   OccOut occ;
@@ -87,6 +112,14 @@ struct hsdm_ctx {
   void *f32_scr = nullptr, *ref_scr = nullptr;
   double* rrec = nullptr;
   int last_refine = 0;      // steps of the last solve (0: FP64 form)
+  // solves recorded as HIP graphs (HSDM_KEY_GRAPH): replayed on the handle's
+  // own stream when a call repeats a recorded one's buffers and settings
+  bool graph_mode = false;
+  std::vector<SolveGraph> graphs;
+  long graph_clock = 0;
+  hipStream_t gstream = nullptr;
+  hipEvent_t gev[2] = {};
+  int last_graph = 0;       // 0: eager, 1: recorded and run, 2: replayed
   int last_mref = 0;        // columns refined by the last solve
   KTimer* kt = nullptr;
   std::string err;
@@ -299,7 +332,13 @@ struct Lanes {
   }
 };
 
+void free_graphs(hsdm_ctx* h) {
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+  h->graphs.clear();
+}
+
 void free_ws(hsdm_ctx* h) {
+  free_graphs(h);  // recorded against this workspace
   if (!h->borrowed && h->ws_raw) (void)hipFree(h->ws_raw);
   h->ws_raw = nullptr;
   h->ws_cap = 0;
@@ -789,6 +828,9 @@ int hsdm_finalize(hsdm_handle h) {
   free_ws(h);
   free_cws(h);
   if (h->rws_raw) (void)hipFree(h->rws_raw);
+  if (h->gstream) (void)hipStreamDestroy(h->gstream);
+  for (auto& e : h->gev)
+    if (e) (void)hipEventDestroy(e);
   if (h->st) (void)hipFree(h->st);
   if (h->host) (void)hipHostFree(h->host);
   if (h->d_hash) (void)hipFree(h->d_hash);
@@ -856,6 +898,17 @@ int hsdm_set_int(hsdm_handle h, int key, long v) {
     h->precision = (int)v;
     return HSDM_OK;
   }
+  if (key == HSDM_KEY_GRAPH) {
+    if (v != 0 && v != 1) return -3;
+    h->graph_mode = (v == 1);
+    if (!h->graph_mode) free_graphs(h);
+    return HSDM_OK;
+  }
+  if (key == HSDM_KEY_AUTOTUNE) {
+    if (v != 0 && v != 1) return -3;
+    gemm_tuning(v == 1);
+    return HSDM_OK;
+  }
   if (key == HSDM_KEY_REFINE_STEPS) {
     if (v < 1 || v > MAX_REFINE_STEPS) return -3;
     h->refine_steps = (int)v;
@@ -884,6 +937,26 @@ int hsdm_phase_times(hsdm_handle h, double* times, int cap) {
   int k = cap < NPHASE ? cap : NPHASE;
   for (int i = 0; i < k; i++) times[i] = h->phase_ms[i];
   return k;
+}
+
+int hsdm_last_graph(hsdm_handle h) { return h ? h->last_graph : -1; }
+
+int hsdm_tune_entries(void) { return gemm_tune_count(); }
+
+int hsdm_tune_clear(void) {
+  gemm_tune_clear();
+  return HSDM_OK;
+}
+
+int hsdm_tune_save(const char* path) {
+  if (!path) return -1;
+  return gemm_tune_save(path) ? HSDM_OK : HSDM_DEVICE_ERROR;
+}
+
+int hsdm_tune_load(const char* path) {
+  if (!path) return -1;
+  const int r = gemm_tune_load(path);
+  return r < 0 ? (r == -1 ? -2 : -3) : r;
 }
 
 int hsdm_refine_history(hsdm_handle h, double* out, int cap) {
@@ -1389,6 +1462,76 @@ int hsdm_solve_ev_complex(hsdm_handle h, int n, const void* H, int ldh, const vo
   return HSDM_OK;
 }
 
+// The density-matrix solve as a HIP graph: the first call with a given key
+// records dm_core's launches on the handle's stream (nothing runs while
+// recording) and instantiates them; that call and every later one with the
+// same key launch the graph on the handle's stream, ordered after the
+// caller's stream by an event and joined back into it.  The host state that
+// dm_core sets while recording (the cached factor's identity, the solve's
+// kind and size) is set again for a replay.
+static int dm_graph(hsdm_ctx* h, int n, const double* H, int ldh, const double* S, int lds,
+                    const SKey& key, double ne, double kT, double* D, int ldd, double* E,
+                    int lde, hipStream_t s) {
+  if (!h->gstream) {
+    DEV_TRY(h, hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+    for (auto& e : h->gev) DEV_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  const GraphKey gk{n, ldh, lds, ldd, E ? lde : 0, H, S, D, E, ne, kT, h->fmax,
+                    h->fcut_rel, h->deg_tol, s_cached(h, key), h->ws_raw};
+  SolveGraph* g = nullptr;
+  for (auto& x : h->graphs)
+    if (x.key == gk) g = &x;
+  if (!g) {
+    if (h->graphs.size() >= MAX_GRAPHS) {
+      auto lru = std::min_element(h->graphs.begin(), h->graphs.end(),
+                                  [](const SolveGraph& a, const SolveGraph& b) {
+                                    return a.last_use < b.last_use;
+                                  });
+      (void)hipGraphExecDestroy(lru->exec);
+      h->graphs.erase(lru);
+    }
+    DEV_TRY(h, hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+    const int r = dm_core(h, n, H, ldh, S, lds, key, ne, kT, D, ldd, E, lde, h->gstream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(h->gstream, &graph);
+    if (r) {
+      if (graph) (void)hipGraphDestroy(graph);
+      h->s_valid = false;  // the factor was never computed
+      return r;
+    }
+    if (ec != hipSuccess) h->s_valid = false;
+    DEV_TRY(h, ec);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) h->s_valid = false;
+    DEV_TRY(h, ei);
+    h->graphs.push_back(SolveGraph{gk, exec, 0});
+    g = &h->graphs.back();
+    h->last_graph = 1;
+  } else {
+    for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
+    h->last_kind = 1;
+    h->last_n = n;
+    h->last_refine = 0;
+    h->last_factored = !gk.cached;
+    if (!gk.cached) {
+      h->s_n = key.n;
+      h->s_cplx = key.cplx;
+      h->s_hash = key.hash;
+      h->s_valid = true;
+    }
+    h->last_graph = 2;
+  }
+  g->last_use = ++h->graph_clock;
+  DEV_TRY(h, hipEventRecord(h->gev[0], s));
+  DEV_TRY(h, hipStreamWaitEvent(h->gstream, h->gev[0], 0));
+  DEV_TRY(h, hipGraphLaunch(g->exec, h->gstream));
+  DEV_TRY(h, hipEventRecord(h->gev[1], h->gstream));
+  DEV_TRY(h, hipStreamWaitEvent(s, h->gev[1], 0));
+  return HSDM_OK;
+}
+
 int hsdm_solve_dm_real(hsdm_handle h, int n, const double* H, int ldh, const double* S, int lds,
                        double ne, double kT, double* D, int ldd, double* E, int lde, double* eval,
                        double* band_energy, double* mu, void* stream) {
@@ -1406,8 +1549,14 @@ int hsdm_solve_dm_real(hsdm_handle h, int n, const double* H, int ldh, const dou
   if (r) return r;
   SKey key;
   if ((r = s_key(h, S, n, lds, false, key, s))) return r;
-  KtScope kts(h);
-  r = dm_core(h, n, H, ldh, S, lds, key, ne, kT, D, ldd, E, lde, s);
+  h->last_graph = 0;
+  if (h->graph_mode && !h->timing && !h->ktiming && !h->concurrent && h->precision == 0 &&
+      !gemm_tuning_on()) {
+    r = dm_graph(h, n, H, ldh, S, lds, key, ne, kT, D, ldd, E, lde, s);
+  } else {
+    KtScope kts(h);
+    r = dm_core(h, n, H, ldh, S, lds, key, ne, kT, D, ldd, E, lde, s);
+  }
   if (eval && r == HSDM_OK) {
     HSDM_LAUNCH(copy_vec_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, h->lam, eval, n);
     DEV_TRY(h, hipGetLastError());

@@ -19,8 +19,11 @@
 // dealt round-robin over the 8 XCDs, so ids are remapped such that each XCD
 // owns a contiguous run of tiles, walked in groups of 8 tile-rows so that the
 // A and B panels of one XCD stay in its L2.
+#include <atomic>
+#include <cstdio>
 #include <cstdlib>
-
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "hsdm_internal.h"
@@ -585,16 +588,11 @@ hipError_t launch_cfg(const ProbT<T>& p, double alpha, double beta, int flags, i
 
 // tile configuration: 0 = 128x128 (8 waves), 1 = 128x64 (4 waves), 2 = 64x64 (4 waves),
 // 3 = 128x32 (4 waves, skinny n), 4 = 32x128 (4 waves, skinny m)
-// (a k-contiguous A operand is read best by the 64x64 tiles: measured 58
-// against 45 TFLOP/s for 8192^3, 39 against 26 for 512 x 4838 x 8192).
-// The environment variable HSDM_GEMM_CFG = 0, 1 or 2 forces that tile for
-// every product that is not skinny (for measuring the choice).
+// The rule (a k-contiguous A operand is read best by the 64x64 tiles:
+// measured 58 against 45 TFLOP/s for 8192^3, 39 against 26 for
+// 512 x 4838 x 8192); the tuning table below overrides it for the products
+// it has timed.
 int pick_cfg(int m, int n, int nsplit, int ta) {
-  static const int forced = [] {  // thread-safe one-time initialization
-    const char* e = getenv("HSDM_GEMM_CFG");
-    return e ? atoi(e) : -1;
-  }();
-  if (forced >= 0 && forced <= 2) return forced;
   if (n <= 32) return 3;
   if (m <= 32) return 4;
   if (ta == 1) return 2;
@@ -607,8 +605,8 @@ int pick_cfg(int m, int n, int nsplit, int ta) {
 
 template <int TA, int TB, int AM, class T>
 hipError_t launch_t(const ProbT<T>& p, double alpha, double beta, int flags, int nsplit,
-                    int kchunk, long stride, double fl, hipStream_t s) {
-  switch (pick_cfg(p.m, p.n, nsplit, TA)) {
+                    int kchunk, long stride, double fl, int cfg, hipStream_t s) {
+  switch (cfg >= 0 ? cfg : pick_cfg(p.m, p.n, nsplit, TA)) {
     case 0:
       return launch_cfg<128, 128, 2, 4, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
                                                     fl, s);
@@ -629,27 +627,28 @@ hipError_t launch_t(const ProbT<T>& p, double alpha, double beta, int flags, int
 
 template <class T>
 hipError_t launch_any(const ProbT<T>& p, int ta, int tb, int am, double alpha, double beta,
-                      int flags, int nsplit, int kchunk, long stride, double fl, hipStream_t s) {
+                      int flags, int nsplit, int kchunk, long stride, double fl, hipStream_t s,
+                      int cfg = -1) {
   if (am == AM_TRIL) {
-    if (tb) return launch_t<0, 1, AM_TRIL>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
-    return launch_t<0, 0, AM_TRIL>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
+    if (tb) return launch_t<0, 1, AM_TRIL>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, cfg, s);
+    return launch_t<0, 0, AM_TRIL>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, cfg, s);
   }
   if (am == AM_SLT) {
-    if (tb) return launch_t<1, 1, AM_SLT>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
-    return launch_t<1, 0, AM_SLT>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
+    if (tb) return launch_t<1, 1, AM_SLT>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, cfg, s);
+    return launch_t<1, 0, AM_SLT>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, cfg, s);
   }
-  if (am == AM_SYM) return launch_t<0, 0, AM_SYM>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
+  if (am == AM_SYM) return launch_t<0, 0, AM_SYM>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, cfg, s);
   if (am == AM_GATHER) {
-    if (tb) return launch_t<0, 1, AM_GATHER>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
-    return launch_t<0, 0, AM_GATHER>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
+    if (tb) return launch_t<0, 1, AM_GATHER>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, cfg, s);
+    return launch_t<0, 0, AM_GATHER>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, cfg, s);
   }
   if (ta == 0 && tb == 0)
-    return launch_t<0, 0, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
+    return launch_t<0, 0, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, cfg, s);
   if (ta == 0 && tb == 1)
-    return launch_t<0, 1, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
+    return launch_t<0, 1, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, cfg, s);
   if (ta == 1 && tb == 0)
-    return launch_t<1, 0, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
-  return launch_t<1, 1, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, s);
+    return launch_t<1, 0, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, cfg, s);
+  return launch_t<1, 1, AM_DENSE>(p, alpha, beta, flags, nsplit, kchunk, stride, fl, cfg, s);
 }
 
 // Algorithmic flops of one product: 2 m n k, halved for a lower-triangular
@@ -674,6 +673,87 @@ int a_mode(const GemmArgsT<T>& g) {
   return AM_DENSE;
 }
 
+// ---- tile autotuner -----------------------------------------------------------
+// Products are classed by element size, ta, tb, A mode, lower-triangular
+// output and the bit lengths of m, n and k; the process-wide table maps a
+// class to the tile that ran it fastest.  While tuning is on, the first
+// product of a class not in the table runs each candidate tile (128x128,
+// 128x64, 64x64) twice on its own operands, C saved and restored around each
+// run, and the faster second run decides; the product is then computed once
+// more with the chosen tile.  Every tile computes each element with the same
+// sequence of multiply-adds over k (slices of 16 in order; a triangular
+// operand only adds exact zeros outside its triangle), so the choice never
+// changes a result.  Skinny products (a side <= 32), split-K products and
+// products with a device-side column count or scattered columns keep the
+// rule.
+std::mutex tune_mu;
+std::map<unsigned long long, int> tune_table;
+std::atomic<bool> tuning{false};
+
+unsigned long long tune_key(int esize, int ta, int tb, int am, int flags, int m, int n, int k) {
+  auto bl = [](int x) {
+    int b = 0;
+    while (x > 0) {
+      b++;
+      x >>= 1;
+    }
+    return (unsigned long long)b;
+  };
+  const unsigned long long lower = (flags & (GF_C_LOWER_TILES | GF_C_LOWER_ONLY)) ? 1ull : 0ull;
+  return ((unsigned long long)esize << 40) | ((unsigned long long)ta << 39) |
+         ((unsigned long long)tb << 38) | ((unsigned long long)am << 34) | (lower << 33) |
+         (bl(m) << 22) | (bl(n) << 11) | bl(k);
+}
+
+int tuned_cfg(unsigned long long key) {
+  std::lock_guard<std::mutex> lk(tune_mu);
+  auto it = tune_table.find(key);
+  return it == tune_table.end() ? -1 : it->second;
+}
+
+template <class T>
+hipError_t tune_product(const GemmArgsT<T>& g, const ProbT<T>& p, int am, unsigned long long key,
+                        double fl, hipStream_t s) {
+  const size_t row = sizeof(T) * (size_t)g.m;
+  T* save = nullptr;
+  HSDM_TRY(hipMalloc(&save, row * g.n));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  if (err == hipSuccess)
+    err = hipMemcpy2DAsync(save, row, g.C, sizeof(T) * g.ldc, row, g.n, hipMemcpyDeviceToDevice, s);
+  int best = -1;
+  float best_ms = 0.f;
+  for (int c = 0; c < 3 && err == hipSuccess; c++) {
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && err == hipSuccess; rep++) {
+      err = hipMemcpy2DAsync(g.C, sizeof(T) * g.ldc, save, row, row, g.n,
+                             hipMemcpyDeviceToDevice, s);
+      if (err == hipSuccess) err = hipEventRecord(e0, s);
+      if (err == hipSuccess)
+        err = launch_any(p, g.ta, g.tb, am, g.alpha, g.beta, g.flags, 1, 0, 0L, fl, s, c);
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    }
+    if (err == hipSuccess && (best < 0 || ms < best_ms)) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  if (err == hipSuccess)
+    err = hipMemcpy2DAsync(g.C, sizeof(T) * g.ldc, save, row, row, g.n, hipMemcpyDeviceToDevice, s);
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(save);
+  if (err == hipSuccess && best >= 0) {
+    std::lock_guard<std::mutex> lk(tune_mu);
+    tune_table[key] = best;
+  }
+  return err;
+}
+
 template <class T>
 hipError_t gemm_launch_t(const GemmArgsT<T>& g, hipStream_t s) {
   if (g.m <= 0 || g.n <= 0) return hipSuccess;
@@ -688,7 +768,16 @@ hipError_t gemm_launch_t(const GemmArgsT<T>& g, hipStream_t s) {
   if ((am == AM_SYM || am == AM_GATHER || am == AM_TRIL) && g.ta != 0) return hipErrorInvalidValue;
   if (am == AM_SLT && g.ta != 1) return hipErrorInvalidValue;
   ProbT<T> p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.acol, g.ccol, g.ndev};
-  return launch_any(p, g.ta, g.tb, am, g.alpha, g.beta, g.flags, 1, 0, 0L, gemm_flops(g), s);
+  int cfg = -1;
+  if (g.m > 32 && g.n > 32 && !g.ccol && !g.ndev) {
+    const unsigned long long key = tune_key((int)sizeof(T), g.ta, g.tb, am, g.flags, g.m, g.n, g.k);
+    cfg = tuned_cfg(key);
+    if (cfg < 0 && tuning.load()) {
+      HSDM_TRY(tune_product(g, p, am, key, gemm_flops(g), s));
+      cfg = tuned_cfg(key);
+    }
+  }
+  return launch_any(p, g.ta, g.tb, am, g.alpha, g.beta, g.flags, 1, 0, 0L, gemm_flops(g), s, cfg);
 }
 
 template <class T>
@@ -731,6 +820,57 @@ hipError_t gemm_sym_pair_launch_t(const GemmArgsT<T>& g, int kchunk, T* part1, T
 }
 
 }  // namespace
+
+void gemm_tuning(bool on) { tuning.store(on); }
+bool gemm_tuning_on() { return tuning.load(); }
+
+int gemm_tune_count() {
+  std::lock_guard<std::mutex> lk(tune_mu);
+  return (int)tune_table.size();
+}
+
+void gemm_tune_clear() {
+  std::lock_guard<std::mutex> lk(tune_mu);
+  tune_table.clear();
+}
+
+// text: one "class-key tile" pair per line, keys in hexadecimal
+bool gemm_tune_save(const char* path) {
+  std::lock_guard<std::mutex> lk(tune_mu);
+  FILE* f = fopen(path, "w");
+  if (!f) return false;
+  bool ok = fprintf(f, "hsdm-gemm-tiles 1\n") > 0;
+  for (const auto& kv : tune_table) ok = ok && fprintf(f, "%llx %d\n", kv.first, kv.second) > 0;
+  return (fclose(f) == 0) && ok;
+}
+
+int gemm_tune_load(const char* path) {
+  FILE* f = fopen(path, "r");
+  if (!f) return -1;
+  char head[32] = {};
+  int ver = 0;
+  if (fscanf(f, "%31s %d", head, &ver) != 2 || std::string(head) != "hsdm-gemm-tiles" ||
+      ver != 1) {
+    fclose(f);
+    return -2;
+  }
+  std::map<unsigned long long, int> add;
+  unsigned long long k;
+  int c;
+  int r;
+  while ((r = fscanf(f, "%llx %d", &k, &c)) == 2) {
+    if (c < 0 || c > 2) {
+      fclose(f);
+      return -2;
+    }
+    add[k] = c;
+  }
+  fclose(f);
+  if (r != EOF) return -2;
+  std::lock_guard<std::mutex> lk(tune_mu);
+  for (const auto& kv : add) tune_table[kv.first] = kv.second;
+  return (int)add.size();
+}
 
 hipError_t gemm_launch(const GemmArgs& g, hipStream_t s) { return gemm_launch_t(g, s); }
 hipError_t gemm_launch(const GemmArgsF& g, hipStream_t s) { return gemm_launch_t(g, s); }

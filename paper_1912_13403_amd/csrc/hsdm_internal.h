@@ -56,6 +56,16 @@ struct GemmDesc {
 
 hipError_t gemm_launch(const GemmArgs& g, hipStream_t s);
 hipError_t gemm_launch(const GemmArgsF& g, hipStream_t s);
+// The tile autotuner's process-wide table (gemm.hip): tuning on makes the
+// first product of each untimed class time the candidate tiles; save/load
+// write and merge the table as text (load returns the entries read, -1 if
+// the file cannot be opened, -2 if it is malformed; nothing is merged then).
+void gemm_tuning(bool on);
+bool gemm_tuning_on();
+int gemm_tune_count();
+void gemm_tune_clear();
+bool gemm_tune_save(const char* path);
+int gemm_tune_load(const char* path);
 // Split-K: K cut into slices of kchunk; part holds ceil(k/kchunk) * m * n
 // partial products, summed in slice order (reproducible), then C = sum + beta C.
 hipError_t gemm_splitk_launch(const GemmArgs& g, int kchunk, double* part, hipStream_t s);

@@ -230,6 +230,14 @@ LaunchGate::~LaunchGate() {
 hipError_t coop_launch(const char* name, double flops, double bytes, bool whole_phase,
                        bool cooperative, const void* fn, dim3 grid, dim3 block, void** args,
                        hipStream_t s, int nbound) {
+  // Captured into a graph (a solve recorded for replay), the kernel becomes
+  // an ordinary node: the graph's nodes run one after another on the device,
+  // so the kernel, whose grid never exceeds the resident workgroup count,
+  // still has all its workgroups placed at once.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (cooperative && hipStreamIsCapturing(s, &cap) == hipSuccess &&
+      cap == hipStreamCaptureStatusActive)
+    cooperative = false;
   auto launch = [&]() -> hipError_t {
     kt_begin(name, flops, bytes, nbound, s, whole_phase);
     hipError_t e = cooperative ? hipLaunchCooperativeKernel(fn, grid, block, args, 0, s)

@@ -39,6 +39,8 @@ HSDM_KEY_N_STATES = 6
 HSDM_KEY_CONCURRENT = 7
 HSDM_KEY_PRECISION = 8
 HSDM_KEY_REFINE_STEPS = 9
+HSDM_KEY_AUTOTUNE = 10
+HSDM_KEY_GRAPH = 11
 
 EXPORTED = [
     "hsdm_init", "hsdm_finalize", "hsdm_reinit", "hsdm_set_real", "hsdm_set_int",
@@ -50,6 +52,8 @@ EXPORTED = [
     "hsdm_dgemm", "hsdm_status_string", "hsdm_last_error", "hsdm_status_detail",
     "hsdm_phase_times", "hsdm_phase_name", "hsdm_phase_flops", "hsdm_kernel_count", "hsdm_kernel_stat",
     "hsdm_version", "hsdm_timing_kernel", "hsdm_solve_dm_real_noalloc", "hsdm_refine_history",
+    "hsdm_tune_entries", "hsdm_tune_clear", "hsdm_tune_save", "hsdm_tune_load",
+    "hsdm_last_graph",
 ]
 
 HSDM_NOALLOC_MAX_N = 512
@@ -109,6 +113,11 @@ def load_library(path: str = LIB_PATH):
         "hsdm_version": ([], _i),
         "hsdm_timing_kernel": ([_vp, ctypes.c_char_p], _i),
         "hsdm_refine_history": ([_vp, ctypes.POINTER(_d), _i], _i),
+        "hsdm_tune_entries": ([], _i),
+        "hsdm_tune_clear": ([], _i),
+        "hsdm_tune_save": ([ctypes.c_char_p], _i),
+        "hsdm_tune_load": ([ctypes.c_char_p], _i),
+        "hsdm_last_graph": ([_vp], _i),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

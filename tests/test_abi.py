@@ -67,7 +67,8 @@ def test_handle_keys_match_the_header(lib):
     txt = open(HEADER).read()
     for name in ("HSDM_KEY_FMAX", "HSDM_KEY_FCUT", "HSDM_KEY_DEG_TOL", "HSDM_KEY_TIMING",
                  "HSDM_KEY_STREAMS", "HSDM_KEY_N_STATES", "HSDM_KEY_CONCURRENT",
-                 "HSDM_KEY_PRECISION", "HSDM_KEY_REFINE_STEPS"):
+                 "HSDM_KEY_PRECISION", "HSDM_KEY_REFINE_STEPS", "HSDM_KEY_AUTOTUNE",
+                 "HSDM_KEY_GRAPH"):
         m = re.search(name + r"\s*=\s*(\d+)", txt)
         assert m and int(m.group(1)) == getattr(hsdm, name), name
     assert lib.hsdm_set_int(None, hsdm.HSDM_KEY_STREAMS, 4) == -1
