@@ -87,8 +87,11 @@ enum hsdm_key {
                               cut (with a margin) for the density-matrix solve; Cholesky,
                               standard form, the tridiagonal eigensolve, occupations and D, E
                               stay FP64.  The refinement stops after the first step whose
-                              largest correction |e_ij| is at most 1e-6 (the error left is of
-                              the order of its square).  The complex, multi-task and
+                              largest correction is at most 1e-6 (the error left is of the
+                              order of its square; a pair of eigenvalues too close to resolve in
+                              a step counts with the correction it would need at that step's
+                              separation), later steps correcting only the vectors still above
+                              it.  The complex, multi-task and
                               allocation-free solves always run the FP64 form */
   , HSDM_KEY_REFINE_STEPS = 9 /* int: most refinement steps of the refined form, 1 ... 8
                               (default 8) */
@@ -349,7 +352,8 @@ int hsdm_tune_load(const char *path);
  * solve; -1 null handle, -3 cap < 0 or out missing) and writes, for the
  * first min(k, cap / 2) steps, out[2i] = delta (the separation below which
  * two eigenvalues are treated as one cluster) and out[2i + 1] = the largest
- * |e_ij| of the correction of step i. */
+ * correction of step i (|e_ij|, or for a pair closer than delta the
+ * correction it would need at separation delta). */
 int hsdm_refine_history(hsdm_handle h, double *out, int cap);
 /* Algorithmic FP64 flops of the phases of the last single solve when
  * HSDM_KEY_TIMING is on, in the order of hsdm_phase_name(i): the counts of

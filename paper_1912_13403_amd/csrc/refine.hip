@@ -4,13 +4,20 @@
 // (Japan J. Indust. Appl. Math. 35 (2018), "Iterative refinement for
 // symmetric eigenvalue decomposition") against the FP64 A bring the wanted
 // ones to FP64 accuracy.  The steps stop once the largest correction is at
-// most tol (the error left is of the order of its square), or after
-// max_steps.  One step, for the first m columns of X:
+// most tol (the error left is of the order of its square) and delta has come
+// down to the smallest separation FP64 resolves, or after max_steps.  After
+// the first step only some columns are corrected: those whose measure of
+// what is left (their corrections, and for a pair still too close to
+// resolve the correction it would need) exceeds tol / 1000, and the refined
+// partners of their unfinished pairs.  One step, for the first m columns of X:
 //   R = I - X^T X,  S = X^T A X          (columns 0 .. m-1, FP64 MFMA)
 //   lambda_j = s_jj / (1 - r_jj)         (Rayleigh quotients)
 //   delta = 2 (||S - diag(lambda)|| + ||A|| ||R||)
 //   e_ij = (s_ij + lambda_j r_ij) / (lambda_j - lambda_i)  if |lambda_j - lambda_i| > delta,
 //          r_ij / 2                                        otherwise (and on the diagonal)
+//   (the measure of what is left to correct counts separations below
+//   4 sqrt(n) eps max|lambda| / tol as that separation: closer pairs cannot
+//   be resolved to tol in FP64, and their corrections are rounding noise)
 //   X[:, j] += X E[:, j]                  (the correction, FP32 MFMA: E is small)
 // Every column of X takes part in the correction of the wanted ones: the
 // eigenvalues lambda_i of the other columns are their Rayleigh quotients,
@@ -21,6 +28,7 @@
 // delta over the whole n x m block, which stays at the FP32 error level of
 // the columns that are not refined and decides the pairs with one of them.
 #include <algorithm>
+#include <vector>
 
 #include "hsdm_internal.h"
 #include "hsdm_phases.h"
@@ -74,24 +82,38 @@ __global__ __launch_bounds__(RB) void rayleigh_kernel(int n, int i0, const doubl
   if (threadIdx.x == 0) lam[i] = xy / xx;
 }
 
-// lambda_j = s_jj / g_jj (g = X^T X, so 1 - r_jj = g_jj), j < m
-__global__ void diag_lambda_kernel(int m, const double* G, const double* S, long ld,
-                                   double* lam) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < m) lam[j] = S[j + (long)j * ld] / G[j + (long)j * ld];
+// X[:, J[c]] -> XJ[:, c] for the mj corrected columns
+__global__ void gather_kernel(int n, int mj, const int* J, const double* X, long ldx, double* XJ,
+                              long ldj) {
+  const long tot = (long)n * mj;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    XJ[i + (long)c * ldj] = X[i + (long)J[c] * ldx];
+  }
 }
 
-// partial sums of ||S - diag(lambda)||_F^2 and ||R||_F^2 over the m x m
-// block (rows i < m) and over the whole n x m block
-__global__ __launch_bounds__(RB) void norms_kernel(int n, int m, const double* G,
-                                                   const double* S, long ld, const double* lam,
-                                                   double* part) {
+// lambda_j = s_jj / g_jj (g = X^T X, so 1 - r_jj = g_jj) for the corrected
+// columns j = J[c] (column c of the blocks)
+__global__ void diag_lambda_kernel(int mj, const int* J, const double* G, const double* S,
+                                   long ld, double* lam) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= mj) return;
+  const int j = J[c];
+  lam[j] = S[j + (long)c * ld] / G[j + (long)c * ld];
+}
+
+// partial sums of ||S - diag(lambda)||_F^2 and ||R||_F^2 over the rows of
+// the refined columns (i < m) and over all rows, for the corrected columns
+__global__ __launch_bounds__(RB) void norms_kernel(int n, int m, int mj, const int* J,
+                                                   const double* G, const double* S, long ld,
+                                                   const double* lam, double* part) {
   __shared__ double red[RB];
-  const long tot = (long)n * m;
+  const long tot = (long)n * mj;
   double d2 = 0.0, r2 = 0.0, d2a = 0.0, r2a = 0.0;
   for (long e = (long)blockIdx.x * RB + threadIdx.x; e < tot; e += (long)gridDim.x * RB) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    const double g = G[i + (long)j * ld], sv = S[i + (long)j * ld];
+    const int i = (int)(e % n), c = (int)(e / n), j = J[c];
+    const double g = G[i + (long)c * ld], sv = S[i + (long)c * ld];
     const double r = (i == j) ? 1.0 - g : -g;
     const double d = (i == j) ? sv - lam[j] : sv;
     if (i < m) {
@@ -115,10 +137,13 @@ __global__ __launch_bounds__(RB) void norms_kernel(int n, int m, const double* G
 }
 
 // delta = 2 (||S - diag(lambda)||_F + max_i |lambda_i| ||R||_F) of the m x m
-// block into rec[0], of the n x m block into dall[0]
+// block into rec[0], of the n x m block into dall[0]; dall[1] = the
+// smallest separation at which the rounding of a coupling (an n-term dot
+// product: about sqrt(n) eps max|lambda|) stays below tol in the measure of
+// what is left
 __global__ __launch_bounds__(RB) void delta_kernel(int n, int nblk, const double* part,
-                                                   const double* lam, double* rec,
-                                                   double* dall) {
+                                                   const double* lam, double tol, int first,
+                                                   double* rec, double* dall) {
   __shared__ double red[RB];
   double d2 = 0.0, r2 = 0.0, d2a = 0.0, r2a = 0.0, am = 0.0;
   for (int b = threadIdx.x; b < nblk; b += RB) {
@@ -135,37 +160,78 @@ __global__ __launch_bounds__(RB) void delta_kernel(int n, int nblk, const double
   am = block_max(am, red);
   if (threadIdx.x == 0) {
     rec[0] = 2.0 * (sqrt(d2) + am * sqrt(r2));
-    dall[0] = 2.0 * (sqrt(d2 + d2a) + am * sqrt(r2 + r2a));
+    // the columns that are not refined keep their FP32 error: the first
+    // step's delta over all rows stays the floor of the later steps', whose
+    // blocks hold only the columns still corrected
+    const double da = 2.0 * (sqrt(d2 + d2a) + am * sqrt(r2 + r2a));
+    if (first) dall[2] = da;
+    dall[0] = fmax(da, dall[2]);
+    dall[1] = 4.0 * sqrt((double)n) * 2.220446049250313e-16 * am / tol;
   }
 }
 
-// E (n x m, FP32) and the partial maxima of |e_ij|
-__global__ __launch_bounds__(RB) void correction_kernel(int n, int m, const double* G,
-                                                        const double* S, long ld,
-                                                        const double* lam, const double* rec,
-                                                        const double* dall, float* E, long lde,
-                                                        double* part) {
+// E (n x mj, FP32; column c corrects column J[c]), the partial maxima,
+// each refined column's largest measure as the partner of a corrected one
+// (rmax), and each corrected column's largest measure of what is left to
+// correct (cmax, as the
+// bit patterns of non-negative doubles, which order like the values;
+// zeroed before): |e_ij| for a resolved pair, and for a pair too close to
+// resolve in this step the correction it would need at separation delta,
+// |s_ij + lambda_j r_ij| / delta, so that a column whose close partner is
+// still mixed in keeps being corrected until delta has shrunk below the
+// pair's separation
+__global__ __launch_bounds__(RB) void correction_kernel(int n, int m, int mj, const int* J,
+                                                        const double* G, const double* S,
+                                                        long ld, const double* lam,
+                                                        const double* rec, const double* dall,
+                                                        float* E, long lde, double* part,
+                                                        unsigned long long* cmax,
+                                                        unsigned long long* rmax) {
   __shared__ double red[RB];
+  const double floor_ = dall[1];
   const double delta_in = rec[0], delta_all = dall[0];
-  const long tot = (long)n * m;
+  const long tot = (long)n * mj;
   double emax = 0.0;
   for (long e = (long)blockIdx.x * RB + threadIdx.x; e < tot; e += (long)gridDim.x * RB) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    const double g = G[i + (long)j * ld];
-    double v;
+    const int i = (int)(e % n), c = (int)(e / n), j = J[c];
+    const double g = G[i + (long)c * ld];
+    double v, left;
     if (i == j) {
       v = 0.5 * (1.0 - g);
+      left = fabs(v);
     } else {
       const double r = -g;
       const double dl = lam[j] - lam[i];
       const double delta = (i < m) ? delta_in : delta_all;
-      v = (fabs(dl) > delta) ? fma(lam[j], r, S[i + (long)j * ld]) / dl : 0.5 * r;
+      const double num = fma(lam[j], r, S[i + (long)c * ld]);
+      if (fabs(dl) > delta) {
+        v = num / dl;
+        left = fabs(num) / fmax(fabs(dl), floor_);
+      } else {
+        // with a column that is not refined (i >= m), r_ij is that column's
+        // own FP32 error, which no step reduces: only the coupling counts
+        v = 0.5 * r;
+        left = fabs(num) / fmax(delta, floor_);
+        if (i < m) left = fmax(left, fabs(v));
+      }
     }
-    E[i + (long)j * lde] = (float)v;
+    E[i + (long)c * lde] = (float)v;
     emax = fmax(emax, fabs(v));
+    if (left > 0.0) {
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(left);
+      atomicMax(&cmax[c], bits);
+      // the partner of the pair, if refined, needs the other half of the
+      // pair's rotation
+      if (i < m && i != j) atomicMax(&rmax[i], bits);
+    }
   }
   emax = block_max(emax, red);
   if (threadIdx.x == 0) part[blockIdx.x] = emax;
+}
+
+__global__ void clear_u64_kernel(unsigned long long* p, int cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) p[i] = 0ull;
 }
 
 __global__ __launch_bounds__(RB) void emax_kernel(int nblk, const double* part, double* rec) {
@@ -176,14 +242,14 @@ __global__ __launch_bounds__(RB) void emax_kernel(int nblk, const double* part, 
   if (threadIdx.x == 0) rec[1] = v;
 }
 
-// X[:, j] += C[:, j] and the FP32 copy, j < m
-__global__ void update_kernel(int n, int m, double* X, long ldx, float* X32, long ldx32,
-                              const float* C, long ldc) {
-  const long tot = (long)n * m;
+// X[:, J[c]] += C[:, c] and the FP32 copy
+__global__ void update_kernel(int n, int mj, const int* J, double* X, long ldx, float* X32,
+                              long ldx32, const float* C, long ldc) {
+  const long tot = (long)n * mj;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
        e += (long)gridDim.x * blockDim.x) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    const double x = X[i + (long)j * ldx] + (double)C[i + (long)j * ldc];
+    const int i = (int)(e % n), c = (int)(e / n), j = J[c];
+    const double x = X[i + (long)j * ldx] + (double)C[i + (long)c * ldc];
     X[i + (long)j * ldx] = x;
     X32[i + (long)j * ldx32] = (float)x;
   }
@@ -193,7 +259,8 @@ __global__ void update_kernel(int n, int m, double* X, long ldx, float* X32, lon
 
 size_t refine_scratch_bytes(int n, int m) {
   const size_t nm = (size_t)n * m;
-  return 2 * nm * sizeof(double) + 2 * nm * sizeof(float) + (4 * RGRID + 64) * sizeof(double);
+  return 3 * nm * sizeof(double) + 2 * nm * sizeof(float) + (4 * RGRID + 64) * sizeof(double) +
+         (size_t)m * (sizeof(int) + 2 * sizeof(unsigned long long)) + 1024;
 }
 
 hipError_t refine_run(int n, int m, const double* A, long lda, double* X, long ldx, float* X32,
@@ -206,56 +273,106 @@ hipError_t refine_run(int n, int m, const double* A, long lda, double* X, long l
   const size_t nm = (size_t)n * m;
   double* G = (double*)p;
   double* S = G + nm;
-  float* E = (float*)(S + nm);
+  double* XJ = S + nm;
+  float* E = (float*)(XJ + nm);
   float* C = E + nm;
   double* part = (double*)(C + nm);
   double* dall = part + 4 * RGRID;
-  const unsigned grid = (unsigned)std::min<long>(RGRID, std::max<long>(1, (long)(nm + RB - 1) / RB));
+  unsigned long long* cmax = (unsigned long long*)(dall + 64);
+  unsigned long long* rmax = cmax + m;
+  int* dJ = (int*)(rmax + m);
+  // the corrected columns: all m in the first step
+  std::vector<int> J(m);
+  for (int j = 0; j < m; j++) J[j] = j;
+  std::vector<unsigned long long> hmax(m), hrow(m);
   for (int k = 0; k < max_steps; k++) {
-    // Y = A X: every column in the first step (Rayleigh quotients of the
-    // columns that are not refined), the wanted ones afterwards
-    const int cols = (k == 0) ? n : m;
+    const int mj = (int)J.size();
+    const size_t nmj = (size_t)n * mj;
+    const unsigned grid =
+        (unsigned)std::min<long>(RGRID, std::max<long>(1, (long)(nmj + RB - 1) / RB));
+    HSDM_TRY(hipMemcpyAsync(dJ, J.data(), sizeof(int) * mj, hipMemcpyHostToDevice, s));
+    HSDM_LAUNCH(clear_u64_kernel, dim3(ceil_div(2 * m, 256)), dim3(256), 0, s, cmax, 2 * m);
+    HSDM_TRY(hipGetLastError());
+    const double* Xc;  // the corrected columns (ld n or ldx) and A times them (ld ldy)
+    long ldc;
     GemmArgs g{};
-    g.m = n; g.n = cols; g.k = n; g.A = A; g.lda = lda; g.B = X; g.ldb = ldx; g.C = Y; g.ldc = ldy;
-    g.alpha = 1.0; g.beta = 0.0; g.flags = GF_A_SYM_LOWER;
-    HSDM_TRY(gemm_launch(g, s));
-    if (k == 0 && m < n) {
-      HSDM_LAUNCH(rayleigh_kernel, dim3(n - m), dim3(RB), 0, s, n, m, X, ldx, Y, ldy, lam);
+    if (k == 0) {
+      // every column of Y = A X: the Rayleigh quotients of the columns that
+      // are not refined; the corrected columns are X's first m
+      g.m = n; g.n = n; g.k = n; g.A = A; g.lda = lda; g.B = X; g.ldb = ldx; g.C = Y;
+      g.ldc = ldy; g.alpha = 1.0; g.beta = 0.0; g.flags = GF_A_SYM_LOWER;
+      HSDM_TRY(gemm_launch(g, s));
+      if (m < n) {
+        HSDM_LAUNCH(rayleigh_kernel, dim3(n - m), dim3(RB), 0, s, n, m, X, ldx, Y, ldy, lam);
+        HSDM_TRY(hipGetLastError());
+      }
+      Xc = X;
+      ldc = ldx;
+    } else {
+      HSDM_LAUNCH(gather_kernel, dim3((unsigned)std::min<size_t>(4096, (nmj + 255) / 256)),
+                  dim3(256), 0, s, n, mj, dJ, X, ldx, XJ, (long)n);
       HSDM_TRY(hipGetLastError());
+      g.m = n; g.n = mj; g.k = n; g.A = A; g.lda = lda; g.B = XJ; g.ldb = n; g.C = Y;
+      g.ldc = ldy; g.alpha = 1.0; g.beta = 0.0; g.flags = GF_A_SYM_LOWER;
+      HSDM_TRY(gemm_launch(g, s));
+      Xc = XJ;
+      ldc = n;
     }
     g = GemmArgs{};
-    g.m = n; g.n = m; g.k = n; g.A = X; g.lda = ldx; g.B = X; g.ldb = ldx; g.C = G; g.ldc = n;
+    g.m = n; g.n = mj; g.k = n; g.A = X; g.lda = ldx; g.B = Xc; g.ldb = ldc; g.C = G; g.ldc = n;
     g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
     HSDM_TRY(gemm_launch(g, s));
     g.B = Y; g.ldb = ldy; g.C = S;
     HSDM_TRY(gemm_launch(g, s));
-    HSDM_LAUNCH(diag_lambda_kernel, dim3(ceil_div(m, 256)), dim3(256), 0, s, m, G, S, (long)n,
-                lam);
+    HSDM_LAUNCH(diag_lambda_kernel, dim3(ceil_div(mj, 256)), dim3(256), 0, s, mj, dJ, G, S,
+                (long)n, lam);
     HSDM_TRY(hipGetLastError());
-    HSDM_LAUNCH(norms_kernel, dim3(grid), dim3(RB), 0, s, n, m, G, S, (long)n, lam, part);
+    HSDM_LAUNCH(norms_kernel, dim3(grid), dim3(RB), 0, s, n, m, mj, dJ, G, S, (long)n, lam, part);
     HSDM_TRY(hipGetLastError());
     double* rk = rec + 2 * k;
-    HSDM_LAUNCH(delta_kernel, dim3(1), dim3(RB), 0, s, n, (int)grid, part, lam, rk, dall);
+    HSDM_LAUNCH(delta_kernel, dim3(1), dim3(RB), 0, s, n, (int)grid, part, lam, tol,
+                (int)(k == 0), rk, dall);
     HSDM_TRY(hipGetLastError());
-    HSDM_LAUNCH(correction_kernel, dim3(grid), dim3(RB), 0, s, n, m, G, S, (long)n, lam, rk,
-                dall, E, (long)n, part);
+    HSDM_LAUNCH(correction_kernel, dim3(grid), dim3(RB), 0, s, n, m, mj, dJ, G, S, (long)n, lam,
+                rk, dall, E, (long)n, part, cmax, rmax);
     HSDM_TRY(hipGetLastError());
     HSDM_LAUNCH(emax_kernel, dim3(1), dim3(RB), 0, s, (int)grid, part, rk);
     HSDM_TRY(hipGetLastError());
-    // X[:, :m] += X E in FP32
+    // X[:, J] += X E in FP32
     GemmArgsF f{};
-    f.m = n; f.n = m; f.k = n; f.A = X32; f.lda = ldx32; f.B = E; f.ldb = n; f.C = C; f.ldc = n;
+    f.m = n; f.n = mj; f.k = n; f.A = X32; f.lda = ldx32; f.B = E; f.ldb = n; f.C = C; f.ldc = n;
     f.alpha = 1.0; f.beta = 0.0;
     HSDM_TRY(gemm_launch(f, s));
-    HSDM_LAUNCH(update_kernel, dim3(grid), dim3(256), 0, s, n, m, X, ldx, X32, ldx32, C,
-                (long)n);
+    HSDM_LAUNCH(update_kernel, dim3((unsigned)std::min<size_t>(4096, (nmj + 255) / 256)),
+                dim3(256), 0, s, n, mj, dJ, X, ldx, X32, ldx32, C, (long)n);
     HSDM_TRY(hipGetLastError());
-    // the step's record to the host: a correction below tol leaves errors of
-    // its square, and the refinement stops
+    // the step's record and the columns' measures to the host: once every
+    // correction is at most tol (errors of its square are left) and delta has
+    // come down to the smallest separation FP64 resolves (every resolvable
+    // pair has been corrected as a pair), the refinement stops
     HSDM_TRY(hipMemcpyAsync(host_rec + 2 * k, rk, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HSDM_TRY(hipMemcpyAsync(hmax.data(), cmax, sizeof(unsigned long long) * mj,
+                            hipMemcpyDeviceToHost, s));
+    HSDM_TRY(hipMemcpyAsync(hrow.data(), rmax, sizeof(unsigned long long) * m,
+                            hipMemcpyDeviceToHost, s));
+    double hd[2] = {0.0, 0.0};
+    HSDM_TRY(hipMemcpyAsync(hd, dall, sizeof(hd), hipMemcpyDeviceToHost, s));
     HSDM_TRY(hipStreamSynchronize(s));
     *steps_done = k + 1;
-    if (!(host_rec[2 * k + 1] > tol)) break;
+    if (!(host_rec[2 * k + 1] > tol) && !(host_rec[2 * k] > hd[1])) break;
+    // next: the columns with something left, and the refined partners of
+    // their unfinished pairs
+    const double keep_tol = 1e-3 * tol;
+    std::vector<char> keep(m, 0);
+    for (int c = 0; c < mj; c++)
+      if (__builtin_bit_cast(double, hmax[c]) > keep_tol) keep[J[c]] = 1;
+    for (int i = 0; i < m; i++)
+      if (__builtin_bit_cast(double, hrow[i]) > keep_tol) keep[i] = 1;
+    std::vector<int> next;
+    for (int j = 0; j < m; j++)
+      if (keep[j]) next.push_back(j);
+    if (next.empty()) break;
+    J.swap(next);
   }
   return hipSuccess;
 }
