@@ -15,10 +15,11 @@
 
   python -m paper_1912_13403_amd.profiling mfma DIR [SIMDS]
       per-kernel matrix-core utilisation from one `rocprofv3 --pmc
-      SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU_MFMA_MOPS_F64 GRBM_GUI_ACTIVE` run:
-      busy = sum of SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDS)
-      (SIMDS = 1024 on the 256 compute units of the MI355X), and the FP64
-      matrix flops the hardware executed (SQ_INSTS_VALU_MFMA_MOPS_F64 x 512).
+      SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_INSTS_VALU_MFMA_MOPS_F32
+      GRBM_GUI_ACTIVE` run: busy = sum of SQ_VALU_MFMA_BUSY_CYCLES /
+      ((GRBM_GUI_ACTIVE / 8) x SIMDS) (the graphics-active count is summed over
+      the 8 XCDs; SIMDS = 1024 on the 256 compute units of the MI355X), and the
+      FP64 and FP32 matrix flops the hardware executed (MOPS x 512).
 
   python -m paper_1912_13403_amd.profiling timeline DIR [GAP_MS]
       phases of every multi-task solve in a kernel trace (one solve per
@@ -146,31 +147,42 @@ def traffic(fetch_dir, write_dir, out_path, workload="cfg2_n16384"):
     return res
 
 
-def mfma(d, simds=1024):
+def mfma(d, simds=1024, xcds=8):
     """name -> dict(dispatches, util (fraction of SIMD-cycles with the matrix
-    core busy), fp64 matrix flops per dispatch)."""
+    core busy), fp64 and fp32 matrix flops per dispatch).  GRBM_GUI_ACTIVE
+    is counted by each XCD's graphics block and summed over the xcds; the
+    busy cycles are summed over all SIMDs."""
     busy = _counter(d, "SQ_VALU_MFMA_BUSY_CYCLES")
     gui = _counter(d, "GRBM_GUI_ACTIVE")
     mops = _counter(d, "SQ_INSTS_VALU_MFMA_MOPS_F64")
+    try:
+        mops32 = _counter(d, "SQ_INSTS_VALU_MFMA_MOPS_F32")
+    except FileNotFoundError:
+        mops32 = {}
     out = {}
     for key, b in busy.items():
         g = gui.get(key, 0.0)
-        a = out.setdefault(key[1], [0, 0.0, 0.0, 0.0])
+        a = out.setdefault(key[1], [0, 0.0, 0.0, 0.0, 0.0])
         a[0] += 1
         a[1] += b
-        a[2] += g
+        a[2] += g / xcds
         a[3] += mops.get(key, 0.0) * 512.0
+        a[4] += mops32.get(key, 0.0) * 512.0
     return {k: {"dispatches": v[0], "util": v[1] / (v[2] * simds) if v[2] > 0 else None,
-                "fp64_mfma_flops_per_dispatch": v[3] / v[0]} for k, v in out.items()}
+                "fp64_mfma_flops_per_dispatch": v[3] / v[0],
+                "fp32_mfma_flops_per_dispatch": v[4] / v[0]} for k, v in out.items()}
 
 
 def print_mfma(d, simds=1024, top=12):
     st = mfma(d, simds)
-    print(f"{'disp':>5} {'MFMA busy':>10} {'FP64 MFMA flops/disp':>22}  kernel")
-    for k, v in sorted(st.items(), key=lambda kv: -kv[1]["fp64_mfma_flops_per_dispatch"]
+    print(f"{'disp':>5} {'MFMA busy':>10} {'FP64 MFMA flops/disp':>22} {'FP32 MFMA flops/disp':>22}"
+          f"  kernel")
+    for k, v in sorted(st.items(), key=lambda kv: -(kv[1]["fp64_mfma_flops_per_dispatch"]
+                                                    + kv[1]["fp32_mfma_flops_per_dispatch"])
                        * kv[1]["dispatches"])[:top]:
         u = "n/a" if v["util"] is None else f"{100 * v['util']:.1f} %"
-        print(f"{v['dispatches']:5d} {u:>10} {v['fp64_mfma_flops_per_dispatch']:22.4e}  {k}")
+        print(f"{v['dispatches']:5d} {u:>10} {v['fp64_mfma_flops_per_dispatch']:22.4e} "
+              f"{v['fp32_mfma_flops_per_dispatch']:22.4e}  {k}")
 
 
 def _busy(iv):
