@@ -29,6 +29,7 @@ namespace {
 constexpr int NT = 256;
 constexpr int CH = 256;      // panel rows per workgroup
 constexpr int SPLITK = 512;  // K slice of the symmetric product X = A22 Y
+constexpr int PGROUP = 4;    // panels per trailing update in a single reduction
 
 template <int CTRL>
 HSDM_DEV double dpp_mov(double v) {
@@ -607,15 +608,19 @@ __global__ void copy_group_kernel(const CopyGroupItem* items) {
 size_t sy2sb_scratch_doubles(int n, int B) {
   const int G = ceil_div(n, CH) + 1;
   // panel exchange slots: part (B columns x G x B) + prow (B x B) + gpart (G B^2);
-  // atb parts (G B^2) + Y (n x B) + VW, WV (n x 4B each) + M (B^2) + Q (2B^2)
-  // + split-K partials of the two symmetric passes (nsplit x n x B each)
+  // atb parts (G B^2) + Y (n x B) + VW, WV (n x 2 PGROUP B each) + M (B^2)
+  // + Q (2 PGROUP B^2) + split-K partials of the two symmetric passes
+  // (nsplit x n x B each)
   const size_t nsplit = ceil_div(n, SPLITK) + 1;
-  return (size_t)G * B * B + (size_t)B * B + (size_t)2 * G * B * B + (size_t)9 * n * B +
-         3 * B * B + 64 + 2 * nsplit * n * B;
+  return (size_t)G * B * B + (size_t)B * B + (size_t)2 * G * B * B +
+         (size_t)(1 + 4 * PGROUP) * n * B + (size_t)(1 + 2 * PGROUP) * B * B + 64 +
+         2 * nsplit * n * B;
 }
 
-// Panels are reduced in pairs with one trailing update per pair.  For the
-// pair (p, p+1), with A22 the trailing block of panel p:
+// A multi-task reduction takes the panels in pairs with one trailing update
+// per pair (a single reduction takes groups of PGROUP panels the same way,
+// Sy2sb::group_panel).  For the pair (p, p+1), with A22 the trailing block of
+// panel p:
 //   panel p:   QR -> V1, T1;  Y1 = V1 T1;  X1 = A22 Y1;  W1 = X1 - V1 (Y1^T X1) / 2;
 //              only the B columns of panel p+1 receive the update
 //              A22[:, 0:B] -= V1 W1[0:B]^T + W1 V1[0:B]^T;
@@ -653,11 +658,11 @@ struct Sy2sb {
     gpart = prow + (size_t)B * B;          // Gmax x B x B
     apart = gpart + (size_t)Gmax * B * B;
     Y = apart + (size_t)Gmax * B * B;      // n x B
-    VW = Y + (size_t)n * B;                // n x 4B  [V1 W1 V2 W2], row i <-> row r0 + i
-    WV = VW + (size_t)n * 4 * B;           // n x 4B  [W1 V1 W2 V2]
-    M = WV + (size_t)n * 4 * B;            // B x B
-    Qc = M + B * B;                        // 2B x B
-    skpart = Qc + 2 * B * B + 64;          // split-K partials
+    VW = Y + (size_t)n * B;                // n x 2 PGROUP B  [V1 W1 V2 W2 ...], row i <-> row r0 + i
+    WV = VW + (size_t)n * 2 * PGROUP * B;  // n x 2 PGROUP B  [W1 V1 W2 V2 ...]
+    M = WV + (size_t)n * 2 * PGROUP * B;   // B x B
+    Qc = M + B * B;                        // 2 PGROUP B x B
+    skpart = Qc + 2 * PGROUP * B * B + 64;  // split-K partials
     skpart2 = skpart + (size_t)(ceil_div(n, SPLITK) + 1) * n * B;  // the second pass's
   }
   int npanel() const { return (n > B) ? ceil_div(n - 1, B) : 0; }
@@ -840,6 +845,62 @@ struct Sy2sb {
     HSDM_TRY(run_copies(h2, V2, W2, second_off(n, B)));
     return syr2k(r1, h2, VW + B, WV + B, 4 * B);
   }
+  // ---- single reduction: up to PGROUP panels per trailing update ----------
+  // For the group of panels p0 .. p0 + P - 1 (panel q at rows r_q =
+  // (p0 + q + 1) B, height h_q), every panel's update
+  // U_q = V_q W_q^T + W_q V_q^T of its trailing block is held back until the
+  // group ends, except on the columns of the next panel, which need it
+  // before their QR.  Panel q's symmetric product is then corrected for the
+  // held-back updates of panels 0 .. q-1:
+  //   X_q = A[r_q:, r_q:] Y_q - [V W]_<q ([W V]_<q^T Y_q),
+  // and the group ends with one rank-2PB update of the trailing block of its
+  // last panel.  V_q and W_q are kept in VW = [V_0 W_0 V_1 W_1 ...] and
+  // WV = [W_0 V_0 W_1 V_1 ...] with row i at global row r_0 + i (panel q's
+  // columns valid from row qB on; no product reads above that).
+  int group_size(int p0) const {
+    int P = 1;
+    if (height(p0) <= 1) return 1;
+    while (P < PGROUP && p0 + P < npanel() && height(p0 + P) > 1) P++;
+    return P;
+  }
+  hipError_t group_panel(int p0, int q, int P) {
+    const int p = p0 + q, rq = (p + 1) * B, h = n - rq;
+    HSDM_TRY(qr_panel(p));
+    if (h <= 1) return hipSuccess;
+    const long o = (long)q * B;                 // row offset of panel q in VW, WV
+    const double* Vq = Vst + rq + (long)p * B * ldv;
+    double* Wq = VW + o + (size_t)(2 * q + 1) * n * B;
+    HSDM_TRY(make_w_pre(h, Vq, T1 + (size_t)p * B * B));
+    HSDM_TRY(make_w_sym(rq, h, Wq));
+    if (q > 0) {
+      // corrections for the held-back updates of panels 0 .. q-1
+      GemmArgs g{};
+      g.m = 2 * B * q; g.n = B; g.k = h; g.A = WV + o; g.lda = n; g.B = Y; g.ldb = n;
+      g.C = Qc; g.ldc = 2 * B * q; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
+      HSDM_TRY(gemm_splitk_launch(g, SPLITK, skpart, s));
+      g = GemmArgs{};
+      g.m = h; g.n = B; g.k = 2 * B * q; g.A = VW + o; g.lda = n; g.B = Qc; g.ldb = 2 * B * q;
+      g.C = Wq; g.ldc = n; g.alpha = -1.0; g.beta = 1.0;
+      HSDM_TRY(gemm_launch(g, s));
+    }
+    HSDM_TRY(make_w_post(h, Vq, Wq, false, nullptr, nullptr));
+    // V_q into VW, [W_q V_q] into WV (W_q is already in VW)
+    HSDM_TRY(dev_copy(Vq, ldv, VW + o + (size_t)2 * q * n * B, n, h, B, s));
+    HSDM_TRY(dev_copy(Wq, n, WV + o + (size_t)2 * q * n * B, n, h, B, s));
+    HSDM_TRY(dev_copy(Vq, ldv, WV + o + (size_t)(2 * q + 1) * n * B, n, h, B, s));
+    if (q + 1 < P) {
+      // the next panel's columns (rows from r_q) receive the updates of
+      // panels 0 .. q
+      GemmArgs g{};
+      g.m = h; g.n = B; g.k = 2 * B * (q + 1); g.A = VW + o; g.lda = n; g.B = WV + o;
+      g.ldb = n; g.C = A + rq + (long)rq * lda; g.ldc = lda; g.alpha = -1.0; g.beta = 1.0;
+      g.ta = 0; g.tb = 1; g.flags = GF_C_LOWER_ONLY;
+      return gemm_launch(g, s);
+    }
+    // the group's one trailing update, rank 2PB, of panel q's trailing block
+    return syr2k(rq, h, VW + o, WV + o, 2 * B * P);
+  }
+
   hipError_t finish() {
     const long tot = (long)n * ldab;
     HSDM_LAUNCH(band_extract_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
@@ -857,14 +918,9 @@ hipError_t sy2sb_run(int n, int B, double* A, long lda, double* Vst, long ldv, d
   Sy2sb R(Sy2sbArgs{n, A, lda, Vst, ldv, tau1, T1, AB, ldab, scratch, st}, B, s);
   for (int p = 0; p < R.npanel();) {
     if (R.height(p) <= 0) break;
-    HSDM_TRY(R.qr_panel(p));
-    HSDM_TRY(R.after_first(p));
-    const int adv = R.advance(p);
-    if (adv == 2) {
-      HSDM_TRY(R.qr_panel(p + 1));
-      HSDM_TRY(R.after_second(p));
-    }
-    p += adv;
+    const int P = R.group_size(p);
+    for (int q = 0; q < P; q++) HSDM_TRY(R.group_panel(p, q, P));
+    p += P;
   }
   return R.finish();
 }
