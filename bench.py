@@ -379,12 +379,15 @@ def serving_main(args):
     specs = inputs.request_specs(args.requests, rate=40.0, lo=256, hi=8192, seed=0)
     make = lambda req, S: inputs.request_problem_device(req, specs[req["base"]], S, dev)
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    prec = 1 if args.precision == "refined" else 0
+    if prec and args.group > 1:
+        raise SystemExit("the refined form serves single solves: use --group 1")
     srv = serving.Server(0, hbm_budget=200e9, slots=args.slots, max_group=args.group,
-                         streams=MT_STREAMS if args.group > 1 else 0)
+                         streams=MT_STREAMS if args.group > 1 else 0, precision=prec)
     # warmup: a short stream of small requests (kernels loaded, workspaces made)
     wspecs = inputs.request_specs(2 * args.slots, rate=1000.0, lo=256, hi=512, seed=99)
     wmake = lambda req, S: inputs.request_problem_device(req, wspecs[req["base"]], S, dev)
-    srv.run(wspecs, wmake)
+    srv.run(wspecs, wmake)  # (also sizes the refined form's workspaces)
     srv.s_dev.clear()
     srv.affinity.clear()
     torch.cuda.synchronize()
@@ -408,14 +411,16 @@ def serving_main(args):
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if not prec else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"cfg4_serving: {len(specs)} requests, Poisson 40/s, n log-uniform "
                                "[256, 8192], 60% real / 40% Hermitian FP64, 30% SCF repeats, "
                                "HBM budget 200 GB, continuous batching over "
                                f"{args.slots} slots, up to {args.group} requests per start "
-                               "(inputs drawn on the device at dispatch)",
+                               "(inputs drawn on the device at dispatch)"
+                               + (", refined form" if prec else ""),
                    "requests": len(specs), "slots": args.slots, "max_group": args.group,
+                   "precision": args.precision,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
         "p99_s": summ["p99_s"],
         "mean_latency_s": summ["mean_s"],
@@ -448,6 +453,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="run one untimed solve with the GEMM tile autotuner first "
                          "(HSDM_KEY_AUTOTUNE); the timed steps use its table")
+    ap.add_argument("--precision", choices=["fp64", "refined"], default="fp64",
+                    help="arithmetic of the single solves served by --config cfg4_serving "
+                         "(refined: HSDM_KEY_PRECISION = 1, needs --group 1)")
     ap.add_argument("--no-refined", action="store_true",
                     help="skip the refined form's steps (e.g. under a profiler)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -76,8 +76,9 @@ enum hsdm_key {
                               ones (the paper's n_states: its dense runs compute only part of
                               the eigenvectors, Sec. 3); 0 or >= n: all (default 0).  C then
                               holds n_states columns; every eigenvalue is still returned */
-  , HSDM_KEY_PRECISION = 8 /* int: arithmetic of the real solves (hsdm_solve_ev_real,
-                              hsdm_solve_dm_real).  0 (default): FP64 throughout.  1: the
+  , HSDM_KEY_PRECISION = 8 /* int: arithmetic of the single solves hsdm_solve_ev_real,
+                              hsdm_solve_dm_real and hsdm_solve_dm_complex (the latter on its
+                              real embedding).  0 (default): FP64 throughout.  1: the
                               refined form -- the full -> band reduction's trailing updates and
                               the stage-1 back-transform in FP32 on the matrix cores, every
                               eigenvector formed, then at most HSDM_KEY_REFINE_STEPS steps of FP64
@@ -91,7 +92,7 @@ enum hsdm_key {
                               order of its square; a pair of eigenvalues too close to resolve in
                               a step counts with the correction it would need at that step's
                               separation), later steps correcting only the vectors still above
-                              it.  The complex, multi-task and
+                              it.  hsdm_solve_ev_complex, the multi-task and the
                               allocation-free solves always run the FP64 form */
   , HSDM_KEY_REFINE_STEPS = 9 /* int: most refinement steps of the refined form, 1 ... 8
                               (default 8) */

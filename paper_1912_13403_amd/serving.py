@@ -8,7 +8,9 @@ request at the head of the queue (arrival order, no overtaking) starts on it
 if its device memory fits the HBM budget beside everything in use, together
 with the requests queued behind it while they fit and the group size allows
 (max_group): one request runs through the single-solve entry points, several
-through hsdm_solve_dm_group, each with its own occupations.  A request that
+through hsdm_solve_dm_group, each with its own occupations.  With
+precision = 1 the slots' single solves run the refined form
+(HSDM_KEY_PRECISION; grouped solves are always FP64).  A request that
 arrives while others run is admitted as soon as a slot and memory free up.
 
 A request that repeats an earlier request's S (the SCF steps of one
@@ -85,13 +87,15 @@ def pick_slot(req, free_slots, affinity):
 
 
 class _Slot:
-    def __init__(self, idx, device, outbox, timing_level, streams):
+    def __init__(self, idx, device, outbox, timing_level, streams, precision=0):
         self.idx = idx
         self.device = device
         self.outbox = outbox
         self.inbox = queue.Queue()
         self.h = hsdm.Handle(device)
         self.h.hsdm_set_int(hsdm.HSDM_KEY_CONCURRENT, 1)
+        if precision:
+            self.h.hsdm_set_int(hsdm.HSDM_KEY_PRECISION, precision)
         if streams:
             self.h.hsdm_set_int(hsdm.HSDM_KEY_STREAMS, streams)
         if timing_level:
@@ -148,12 +152,12 @@ class _Slot:
 
 class Server:
     def __init__(self, device=0, hbm_budget=200e9, slots=4, timing_level=0, max_group=1,
-                 streams=0):
+                 streams=0, precision=0):
         self.dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         self.budget = float(hbm_budget)
         self.max_group = int(max_group)
         self.outbox = queue.Queue()
-        self.slots = [_Slot(k, self.dev, self.outbox, timing_level, streams)
+        self.slots = [_Slot(k, self.dev, self.outbox, timing_level, streams, precision)
                       for k in range(slots)]
         self.s_dev = OrderedDict()  # base request id -> resident S on the device
         self.s_users = {}           # base request id -> running requests using it

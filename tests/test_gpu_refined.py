@@ -173,3 +173,41 @@ def test_refined_n16384_against_fp64(torch_dev, hr):
     assert dE <= 1e-9 * max(1.0, scale)
     assert dw <= 1e-10 * scale
     assert abs(out["mu"] - ref["mu"]) <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("k", [5, None])
+def test_refined_hermitian_dm_against_oracle(oracle, torch_dev, hr, k):
+    """hsdm_solve_dm_complex in the refined form (on its real embedding,
+    whose eigenvalues come in exactly degenerate pairs): every entry of D
+    and E against the oracle's Hermitian route, a small k-point task and the
+    smallest task of the batched recipe."""
+    from paper_1912_13403_amd import hsdm
+    torch, dev = torch_dev
+    if k is None:
+        sizes = inputs.kpoint_sizes()
+        k = int(np.argmin(sizes))
+        Hu, _, S = inputs.kpoint_problem(k)
+    else:
+        Hu, _, S = inputs.kpoint_problem(k, n=300)
+    n = Hu.shape[0]
+    ne, kT = 0.2 * n, 0.01
+    ref = oracle.solve_dm_complex(Hu, S, ne, kT, f_max=1.0)
+    hr.hsdm_set_real(hsdm.HSDM_KEY_FMAX, 1.0)
+    try:
+        hr.hsdm_reinit()
+        out = hr.hsdm_solve_dm_complex(torch.from_numpy(Hu).to(dev), torch.from_numpy(S).to(dev),
+                                       ne, kT)
+        hist = hr.refine_history()
+    finally:
+        hr.hsdm_set_real(hsdm.HSDM_KEY_FMAX, 2.0)
+    scale = float(np.abs(Hu).sum(axis=0).max())
+    dw = np.max(np.abs(out["eval"].cpu().numpy() - ref["eval"]))
+    dD = np.abs(out["D"].cpu().numpy() - ref["D"]).max()
+    dE = np.abs(out["E"].cpu().numpy() - ref["E"]).max()
+    print(f"[refined-herm] n={n}: {len(hist)} steps, |d eps| {dw:.2e}, |dD| {dD:.2e}, "
+          f"|dE| {dE:.2e}", flush=True)
+    assert len(hist) >= 1
+    assert dw <= 1e-10 * scale
+    assert dD <= 1e-9
+    assert dE <= 1e-9 * max(1.0, scale)
+    assert abs(out["mu"] - ref["mu"]) <= 1e-10 * scale
