@@ -496,43 +496,67 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void s
 }
 
 // The two passes of X = A Y for a symmetric A with its lower triangle stored
-// (X = tril(A) Y + strict_tril(A)^T Y), split over K, in one launch:
-// blockIdx.z = 0 writes the partials of the first pass to part1, 1 those of
-// the second to part2 (slice blockIdx.y at offset y m n, leading dimension m).
+// (X = tril(A) Y + strict_tril(A)^T Y), split over K in slices of kchunk
+// (a multiple of 128), in one launch.  Pass 1 writes the partial product of
+// 128-row tile i over K slice k to part1 (slice k at offset k m n, leading
+// dimension m), pass 2 that of its transposed form to part2.  Only the
+// (tile, slice) pairs that meet the stored triangle are computed: both
+// passes read the kchunk x kchunk block (R, C), R >= C, of the lower
+// triangle (pass 1 as the tiles of block row R over slice C, pass 2 as
+// those of block row C over slice R), and the workgroups of one block are
+// issued together on one XCD (the block is dealt to XCD id % 8, the
+// workgroup ids of one XCD in turn), so that the second pass finds the
+// block in the caches the first has just filled.
 template <class T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void sym_pair_kernel(
-    ProbT<T> p, T* part1, T* part2, int kchunk) {
+    ProbT<T> p, T* part1, T* part2, int kchunk, int ns) {
   using C1 = G<128, 32, 4, 1, 0, 0, AM_TRIL>;
   using C2 = G<128, 32, 4, 1, 1, 0, AM_SLT>;
   __shared__ T smem[C1::SMEM > C2::SMEM ? C1::SMEM : C2::SMEM];
-  int tm, tn;
-  if (!map_tile(blockIdx.x, (p.m + 127) / 128, 1, tm, tn)) return;
-  const int klo = blockIdx.y * kchunk;
+  const int tpb = kchunk / 128;  // tiles per block row
+  const int per = 2 * tpb;       // workgroups per block
+  const int x = blockIdx.x % 8, li = blockIdx.x / 8;
+  const int sb = 8 * (li / per) + x, q = li % per;
+  if (sb >= ns * (ns + 1) / 2) return;
+  int R = (int)((sqrt(8.0 * sb + 1.0) - 1.0) * 0.5);
+  while ((R + 1) * (R + 2) / 2 <= sb) R++;
+  while (R * (R + 1) / 2 > sb) R--;
+  const int Cb = sb - R * (R + 1) / 2;
+  const bool second = q >= tpb;
+  const int tm = (second ? Cb : R) * tpb + q % tpb;
+  const int split = second ? R : Cb;
+  if (tm * 128 >= p.m) return;
+  const int klo = split * kchunk;
   p.ldc = p.m;
-  if (blockIdx.z == 0) {
-    p.C = part1 + (long)blockIdx.y * p.m * p.n;
-    gemm_tile<128, 32, 4, 1, 0, 0, AM_TRIL>(p, 1.0, 0.0, GF_A_TRIL | GF_KA_LOWER, tm, tn, smem,
+  if (!second) {
+    p.C = part1 + (long)split * p.m * p.n;
+    gemm_tile<128, 32, 4, 1, 0, 0, AM_TRIL>(p, 1.0, 0.0, GF_A_TRIL | GF_KA_LOWER, tm, 0, smem,
                                             klo, klo + kchunk);
   } else {
-    p.C = part2 + (long)blockIdx.y * p.m * p.n;
-    gemm_tile<128, 32, 4, 1, 1, 0, AM_SLT>(p, 1.0, 0.0, GF_A_SLT | GF_KA_UPPER, tm, tn, smem,
+    p.C = part2 + (long)split * p.m * p.n;
+    gemm_tile<128, 32, 4, 1, 1, 0, AM_SLT>(p, 1.0, 0.0, GF_A_SLT | GF_KA_UPPER, tm, 0, smem,
                                            klo, klo + kchunk);
   }
 }
 
 // C = (sum of part2's slices) + (sum of part1's slices), each summed in
-// slice order: the same roundings as the first pass reduced into C and the
-// second reduced onto it.
+// slice order over the slices that meet the row's tile (the others hold
+// zeros in the full split-K form, and adding +0 to these sums, which start
+// from +0, changes no bit): the same roundings as the first pass reduced
+// into C and the second reduced onto it.
 template <class T>
-__global__ void sym_pair_reduce_kernel(int m, int n, int nsplit, const T* part1, const T* part2,
-                                       T* C, long ldc) {
+__global__ void sym_pair_reduce_kernel(int m, int n, int nsplit, int kchunk, const T* part1,
+                                       const T* part2, T* C, long ldc) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long tot = (long)m * n;
   if (idx >= tot) return;
-  T s1 = 0, s2 = 0;
-  for (int z = 0; z < nsplit; z++) s1 += part1[z * tot + idx];
-  for (int z = 0; z < nsplit; z++) s2 += part2[z * tot + idx];
   const int i = (int)(idx % m), j = (int)(idx / m);
+  const int t0 = (i / 128) * 128;
+  const int z1 = min(nsplit - 1, (t0 + 127) / kchunk);  // last slice of the first pass
+  const int z2 = t0 / kchunk;                            // first slice of the second
+  T s1 = 0, s2 = 0;
+  for (int z = 0; z <= z1; z++) s1 += part1[z * tot + idx];
+  for (int z = z2; z < nsplit; z++) s2 += part2[z * tot + idx];
   C[i + (long)j * ldc] = s2 + s1;
 }
 
@@ -803,19 +827,22 @@ template <class T>
 hipError_t gemm_sym_pair_launch_t(const GemmArgsT<T>& g, int kchunk, T* part1, T* part2,
                                   hipStream_t s) {
   if (g.m <= 0 || g.n <= 0) return hipSuccess;
-  if (g.n > 32 || g.m != g.k || kchunk <= 0 || g.ta || g.tb || !(g.flags & GF_A_TRIL))
+  if (g.n > 32 || g.m != g.k || kchunk <= 0 || kchunk % 128 || g.ta || g.tb ||
+      !(g.flags & GF_A_TRIL))
     return hipErrorInvalidValue;
   const int nsplit = ceil_div(g.k, kchunk);
+  const long nblocks = (long)nsplit * (nsplit + 1) / 2;
+  const long per = 2 * (kchunk / 128);
   ProbT<T> p{g.m, g.n, g.k, g.A, g.lda, g.B, g.ldb, nullptr, (long)g.m, nullptr, nullptr, nullptr};
   kt_begin(sizeof(T) == 4 ? "sym_pair_kernel<float>" : "sym_pair_kernel", 2.0 * gemm_flops(g),
            0.0, 0, s);
-  HSDM_LAUNCH(sym_pair_kernel<T>, dim3(tile_grid(ceil_div(g.m, 128), 1), nsplit, 2), dim3(256),
-                     0, s, p, part1, part2, kchunk);
+  HSDM_LAUNCH(sym_pair_kernel<T>, dim3((unsigned)(8 * per * ((nblocks + 7) / 8))), dim3(256), 0,
+              s, p, part1, part2, kchunk, nsplit);
   kt_end(s);
   HSDM_TRY(hipGetLastError());
   const long tot = (long)g.m * g.n;
   HSDM_LAUNCH(sym_pair_reduce_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                     g.m, g.n, nsplit, part1, part2, g.C, g.ldc);
+                     g.m, g.n, nsplit, kchunk, part1, part2, g.C, g.ldc);
   return hipGetLastError();
 }
 

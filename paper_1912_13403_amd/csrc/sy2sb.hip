@@ -117,6 +117,48 @@ HSDM_DEV double ld_ready(const double* p, DevStatusWord* st) {
   return v;
 }
 
+HSDM_DEV double ld_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// s + p[q0 stride] + p[(q0 + dq) stride] + ... (q < G, added in that order),
+// each slot polled until it is written.  The CHK slots of a chunk are loaded
+// together and only the unwritten ones again, so that a chunk whose slots
+// are all written costs one round trip to the memory side, not CHK.
+template <int CHK>
+HSDM_DEV double sum_ready(const double* p, long stride, int q0, int dq, int G, double s,
+                          DevStatusWord* st) {
+  for (int qb = q0; qb < G; qb += CHK * dq) {
+    double v[CHK];
+#pragma unroll
+    for (int i = 0; i < CHK; i++) {
+      const int q = qb + i * dq;
+      v[i] = (q < G) ? ld_agent(p + (long)q * stride) : 0.0;
+    }
+    long spins = 0;
+    for (;;) {
+      bool pend = false;
+#pragma unroll
+      for (int i = 0; i < CHK; i++) pend |= (v[i] != v[i]);
+      if (!pend) break;
+      if (++spins > (1L << 24) ||
+          ((spins & 1023) == 0 &&
+           __hip_atomic_load(&st->code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+        dev_set_status(st, DS_SYNC_TIMEOUT, 1);
+        return s;
+      }
+      __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+      for (int i = 0; i < CHK; i++)
+        if (v[i] != v[i]) v[i] = ld_agent(p + (long)(qb + i * dq) * stride);
+    }
+#pragma unroll
+    for (int i = 0; i < CHK; i++)
+      if (qb + i * dq < G) s += v[i];
+  }
+  return s;
+}
+
 // The arithmetic both panel kernels share (the fused one and the per-column
 // launches), with every multiply-add written out so that the compiler has
 // no choice of contraction and the two give the same bits.
@@ -253,19 +295,20 @@ HSDM_DEV void panel_qr_body(int h, double* P, long ldp, double* V, long ldv, dou
       } else {
         double* pb = part + (size_t)j * G * B;  // this column's slots (NaN before)
         double* rb = prow + (size_t)j * B;
+        double rv = 0.0;
         if (t < B) {
           double sum = 0.0;
 #pragma unroll
           for (int w = 0; w < NW; w++) sum += red[w][t];
           st_agent(&pb[(size_t)g * B + t], sum);
           if (g == 0) st_agent(&rb[t], rowl[t]);
+          rv = ld_agent(&rb[t]);  // in flight with the partial sums below
         }
         {
           // RG threads per column sum strided subsets, then a fixed-order combine
           const int k = t % B, rg = t / B;
           double s2 = 0.0;
-          if (k < B - j)
-            for (int q = rg; q < G; q += RG) s2 += ld_ready(&pb[(size_t)q * B + k], st);
+          if (k < B - j) s2 = sum_ready<8>(pb + k, B, rg, RG, G, 0.0, st);
           cmb[rg][k] = s2;
         }
         __syncthreads();
@@ -273,7 +316,7 @@ HSDM_DEV void panel_qr_body(int h, double* P, long ldp, double* V, long ldv, dou
           double s2 = 0.0;
           for (int r = 0; r < RG; r++) s2 += cmb[r][t];
           ddl[t] = s2;
-          rowl[t] = ld_ready(&rb[t], st);
+          rowl[t] = (rv == rv) ? rv : ld_ready(&rb[t], st);
         }
       }
       __syncthreads();
@@ -318,9 +361,7 @@ HSDM_DEV void panel_qr_body(int h, double* P, long ldp, double* V, long ldv, dou
   if (g != 0) return;
   for (int e = t; e < B * B; e += NT) {
     const int ca = e % B, cb = e / B;
-    double sum = Gm[ca][cb];
-    for (int q = 1; q < G; q++) sum += ld_ready(&gpart[(size_t)q * B * B + e], st);
-    Gm[ca][cb] = sum;
+    Gm[ca][cb] = sum_ready<16>(gpart + e, (long)B * B, 1, 1, G, Gm[ca][cb], st);
     Tl[ca][cb] = 0.0;
   }
   __syncthreads();
