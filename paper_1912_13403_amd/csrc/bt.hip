@@ -19,8 +19,24 @@ constexpr int B = 32;
 constexpr int H2 = 2 * B;  // rows of a group
 
 // Compact record of one group (GREC doubles): the parallelogram of V by
-// columns, Vc[32 j + i] = V[j + i][j] (i, j < B), then T column-major.
-constexpr int GREC = 2 * B * B;
+// columns, Vc[32 j + i] = V[j + i][j] (i, j < B), then the upper triangle of
+// T folded into 16 rows of B + 1: row p holds column p (entries 0 .. p) and
+// then column B-1-p (entries 0 .. B-1-p), then zeros up to a multiple of 64
+// doubles (one coalesced load per lane and step).
+constexpr int TPACK = (B / 2) * (B + 1);                  // 528
+constexpr int GREC = ((B * B + TPACK + 63) / 64) * 64;  // 1600
+
+// (row, column) of T held at position e of the folded triangle
+HSDM_DEV void tpack_index(int e, int& i, int& j) {
+  const int p = e / (B + 1), o = e - p * (B + 1);
+  if (o <= p) {
+    i = o;
+    j = p;
+  } else {
+    i = o - p - 1;
+    j = B - 1 - p;
+  }
+}
 
 // T factor of every group (T_jj = tau_j, T(0:j, j) = -tau_j T(0:j,0:j) V^T v_j),
 // then the compact record.
@@ -58,7 +74,11 @@ __global__ __launch_bounds__(256) void group_pack_kernel(const double* V2, const
   for (int e = t; e < B * B; e += 256) {
     const int j = e / B, i = e % B;
     F[e] = Vs[j + i][j];
-    F[B * B + e] = Tl[i][j];
+  }
+  for (int e = t; e < GREC - B * B; e += 256) {
+    int i = 0, j = 0;
+    if (e < TPACK) tpack_index(e, i, j);
+    F[B * B + e] = (e < TPACK) ? Tl[i][j] : 0.0;
   }
 }
 
@@ -114,6 +134,7 @@ HSDM_DEV void bt2_strip_body(int n, int nblk, const SplitRanges& R, int nstrip,
   double* Vl = Vl_all[w];
   double* Tl = Tl_all[w];
   if (lane == 0) prog[w] = -1;
+  for (int e = lane; e < B * TS; e += 64) Tl[e] = 0.0;  // below T's diagonal stays zero
   if (threadIdx.x == 0) {
     // range kr - 1 of this strip must be complete (its workgroup has a lower
     // index, so it was dispatched earlier and is running or finished)
@@ -169,8 +190,13 @@ HSDM_DEV void bt2_strip_body(int n, int nblk, const SplitRanges& R, int nstrip,
 #pragma unroll
     for (int q = 0; q < NST; q++) {
       const int e = q * 64 + lane;
-      if (q < NST / 2) Vl[(e >> 5) * VS + (e & 31)] = r[q];
-      else Tl[((e - B * B) >> 5) * TS + (e & 31)] = r[q];
+      if (q < B * B / 64) {
+        Vl[(e >> 5) * VS + (e & 31)] = r[q];
+      } else if (e - B * B < TPACK) {
+        int i, j;
+        tpack_index(e - B * B, i, j);
+        Tl[j * TS + i] = r[q];
+      }
     }
     __builtin_amdgcn_wave_barrier();
     asm volatile("" ::: "memory");
