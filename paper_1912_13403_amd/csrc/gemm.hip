@@ -261,6 +261,43 @@ HSDM_DEV void gemm_tile(const ProbT<T>& p, double alpha, double beta, int flags,
           acc[a][b] = M::mma(fa[a], fb[b], acc[a][b]);
     }
   };
+  // A tile that lies wholly inside its operands stages the slices that need
+  // no masking with no per-slice address arithmetic: element q of a thread
+  // sits at a fixed byte offset from a base that is the same for the whole
+  // workgroup (the slice's corner plus q times a uniform stride).  For a
+  // triangular operand these are the slices on the stored side of the
+  // tile's diagonal block.
+  constexpr bool PLAIN = (AM == AM_DENSE) || (AM == AM_TRIL) || (AM == AM_SLT);
+  const bool whole = PLAIN && (i0 + BM <= p.m) && (j0 + BN <= p.n) &&
+                     (p.lda < (1L << 22)) && (p.ldb < (1L << 22));
+  const int tid = threadIdx.x;
+  const unsigned oa = (unsigned)(sizeof(T) * (TA == 0 ? (tid % BM) + (long)(tid / BM) * p.lda
+                                                       : (tid % BK) + (long)(tid / BK) * p.lda));
+  const unsigned ob = (unsigned)(sizeof(T) * (TB == 0 ? (tid % BK) + (long)(tid / BK) * p.ldb
+                                                       : (tid % BN) + (long)(tid / BN) * p.ldb));
+  const long sa = (long)sizeof(T) * (TA == 0 ? (C::NT / BM) : (C::NT / BK)) * p.lda;
+  const long sb = (long)sizeof(T) * (TB == 0 ? (C::NT / BK) : (C::NT / BN)) * p.ldb;
+  auto plain = [&](int k) {
+    if (!whole || k < kb || k + BK > ke) return false;
+    if constexpr (AM == AM_TRIL) return k + BK - 1 <= i0;  // every k <= every row
+    if constexpr (AM == AM_SLT) return k >= i0 + BM;       // every k > every row
+    return true;
+  };
+  auto stage = [&](int k, T (&xa)[C::AE], T (&xb)[C::BE]) {
+    if (plain(k)) {
+      const char* a = (const char*)(TA == 0 ? p.A + i0 + (long)k * p.lda
+                                            : p.A + k + (long)i0 * p.lda);
+      const char* b = (const char*)(TB == 0 ? p.B + k + (long)j0 * p.ldb
+                                            : p.B + j0 + (long)k * p.ldb);
+#pragma unroll
+      for (int q = 0; q < C::AE; q++) xa[q] = *(const T*)(a + q * sa + oa);
+#pragma unroll
+      for (int q = 0; q < C::BE; q++) xb[q] = *(const T*)(b + q * sb + ob);
+    } else {
+      load_a<C, TA, AM>(p, i0, k, kb, ke, xa);
+      load_b<C, TB>(p, j0, k, kb, ke, xb);
+    }
+  };
   T ra[C::AE], rb[C::BE];
   if constexpr (C::PF2) {
     // skinny tiles carry little work per slice: the registers hold two
@@ -270,25 +307,21 @@ HSDM_DEV void gemm_tile(const ProbT<T>& p, double alpha, double beta, int flags,
     auto ks_of = [&](int j) { return kstart + BK * min(j, nsl - 1); };
     T ra2[C::AE], rb2[C::BE];
     if (nsl > 0) {
-      load_a<C, TA, AM>(p, i0, ks_of(0), kb, ke, ra);
-      load_b<C, TB>(p, j0, ks_of(0), kb, ke, rb);
+      stage(ks_of(0), ra, rb);
       store_a<C, TA>(As0, ra);
       store_b<C, TB>(Bs0, rb);
-      load_a<C, TA, AM>(p, i0, ks_of(1), kb, ke, ra2);
-      load_b<C, TB>(p, j0, ks_of(1), kb, ke, rb2);
+      stage(ks_of(1), ra2, rb2);
     }
     __syncthreads();
     for (int j = 0; j < nsl; j += 2) {
       // As0/Bs0: slice j; ra2/rb2: slice j+1 in flight
-      load_a<C, TA, AM>(p, i0, ks_of(j + 2), kb, ke, ra);
-      load_b<C, TB>(p, j0, ks_of(j + 2), kb, ke, rb);
+      stage(ks_of(j + 2), ra, rb);
       compute(As0, Bs0);
       store_a<C, TA>(As1, ra2);
       store_b<C, TB>(Bs1, rb2);
       __syncthreads();
       if (j + 1 >= nsl) break;
-      load_a<C, TA, AM>(p, i0, ks_of(j + 3), kb, ke, ra2);
-      load_b<C, TB>(p, j0, ks_of(j + 3), kb, ke, rb2);
+      stage(ks_of(j + 3), ra2, rb2);
       compute(As1, Bs1);
       store_a<C, TA>(As0, ra);
       store_b<C, TB>(Bs0, rb);
@@ -296,8 +329,7 @@ HSDM_DEV void gemm_tile(const ProbT<T>& p, double alpha, double beta, int flags,
     }
   } else {
     if (kstart < ke) {
-      load_a<C, TA, AM>(p, i0, kstart, kb, ke, ra);
-      load_b<C, TB>(p, j0, kstart, kb, ke, rb);
+      stage(kstart, ra, rb);
       store_a<C, TA>(As0, ra);
       store_b<C, TB>(Bs0, rb);
     }
@@ -305,10 +337,7 @@ HSDM_DEV void gemm_tile(const ProbT<T>& p, double alpha, double beta, int flags,
     int buf = 0;
     for (int k0 = kstart; k0 < ke; k0 += BK) {
       const bool more = k0 + BK < ke;
-      if (more) {
-        load_a<C, TA, AM>(p, i0, k0 + BK, kb, ke, ra);
-        load_b<C, TB>(p, j0, k0 + BK, kb, ke, rb);
-      }
+      if (more) stage(k0 + BK, ra, rb);
       compute(buf ? As1 : As0, buf ? Bs1 : Bs0);
       if (more) {
         store_a<C, TA>(buf ? As0 : As1, ra);
