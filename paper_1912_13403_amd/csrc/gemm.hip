@@ -641,25 +641,26 @@ hipError_t launch_cfg(const ProbT<T>& p, double alpha, double beta, int flags, i
 
 // tile configuration: 0 = 128x128 (8 waves), 1 = 128x64 (4 waves), 2 = 64x64 (4 waves),
 // 3 = 128x32 (4 waves, skinny n), 4 = 32x128 (4 waves, skinny m)
-// The rule (a k-contiguous A operand is read best by the 64x64 tiles:
-// measured 58 against 45 TFLOP/s for 8192^3, 39 against 26 for
-// 512 x 4838 x 8192); the tuning table below overrides it for the products
-// it has timed.
-int pick_cfg(int m, int n, int nsplit, int ta) {
+// The rule follows the autotuner's choices on the MI355X for the products of
+// the n = 16384 solve: 64x64 tiles for a k-contiguous A operand, for
+// rank-k updates of a lower triangle with k < 1024 and for products of fewer
+// than 4096 128x128 tiles (more, smaller tiles balance better), 128x64 for
+// large lower-triangle updates, 128x128 otherwise.  The tuning table below
+// overrides it for the products it has timed.
+int pick_cfg(int m, int n, int k, int nsplit, int ta, int flags) {
   if (n <= 32) return 3;
   if (m <= 32) return 4;
   if (ta == 1) return 2;
+  const bool lower = (flags & (GF_C_LOWER_TILES | GF_C_LOWER_ONLY)) != 0;
   const long t128 = (long)ceil_div(m, 128) * ceil_div(n, 128) * nsplit;
-  const long t12864 = (long)ceil_div(m, 128) * ceil_div(n, 64) * nsplit;
-  if (t128 >= 512) return 0;
-  if (t12864 >= 512) return 1;
-  return 2;
+  if (lower) return (k < 1024 || t128 < 4096) ? 2 : 1;
+  return t128 >= 4096 ? 0 : 2;
 }
 
 template <int TA, int TB, int AM, class T>
 hipError_t launch_t(const ProbT<T>& p, double alpha, double beta, int flags, int nsplit,
                     int kchunk, long stride, double fl, int cfg, hipStream_t s) {
-  switch (cfg >= 0 ? cfg : pick_cfg(p.m, p.n, nsplit, TA)) {
+  switch (cfg >= 0 ? cfg : pick_cfg(p.m, p.n, kchunk > 0 ? kchunk : p.k, nsplit, TA, flags)) {
     case 0:
       return launch_cfg<128, 128, 2, 4, TA, TB, AM>(p, alpha, beta, flags, nsplit, kchunk, stride,
                                                     fl, s);
