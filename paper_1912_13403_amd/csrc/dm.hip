@@ -38,7 +38,26 @@ __global__ __launch_bounds__(NT) void dm_kernel(int n, int m_host, const int* m_
     for (int b = 0; b < 2; b++) acc[a][b] = dbl4{0, 0, 0, 0};
   // staging: thread t moves row t % 128 of the 128 x 16 slices, columns t / 128 and t / 128 + 8
   double ra[2], rb[2], sf[2], se[2];
+  // a tile wholly inside C stages its full slices from workgroup-uniform
+  // bases plus fixed per-thread byte offsets (no per-slice address arithmetic)
+  const bool whole = (i0 + BT <= n) && (j0 + BT <= n) && (ldc < (1L << 22));
+  const unsigned off = (unsigned)(sizeof(double) * ((t % BT) + (long)(t / BT) * ldc));
+  const long qstride = (long)sizeof(double) * 8 * ldc;
   auto load = [&](int k0) {
+    if (whole && k0 + BK <= m) {
+      const char* ca = (const char*)(C + i0 + (long)k0 * ldc);
+      const char* cb = (const char*)(C + j0 + (long)k0 * ldc);
+#pragma unroll
+      for (int q = 0; q < 2; q++) {
+        ra[q] = *(const double*)(ca + q * qstride + off);
+        rb[q] = *(const double*)(cb + q * qstride + off);
+        const int kk = k0 + t / BT + 8 * q;
+        const double fk = f[kk];
+        sf[q] = fk;
+        se[q] = fk * eps[kk];
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < 2; q++) {
       const int kk = k0 + t / BT + 8 * q;
