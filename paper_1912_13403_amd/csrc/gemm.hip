@@ -424,6 +424,11 @@ __global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(wa
   const int tiles_m = (p.m + BM - 1) / BM, tiles_n = (p.n + BN - 1) / BN;
   int tm, tn;
   if (!map_tile(blockIdx.x, tiles_m, tiles_n, tm, tn)) return;
+  // a triangular operand makes the k range grow with the tile row (column):
+  // the longest tiles go first, so that the launch does not end on a few
+  // of them
+  if (flags & GF_KA_LOWER) tm = tiles_m - 1 - tm;
+  if (flags & GF_KB_UPPER) tn = tiles_n - 1 - tn;
   if ((flags & GF_C_LOWER_TILES) && (tm + 1) * BM - 1 < tn * BN) return;
   if (kchunk > 0) {
     // split-K: slice blockIdx.y writes its partial product to C + y*split_stride
