@@ -410,6 +410,7 @@ template <int BM, int BN, int WM, int WN, int TA, int AM>
 constexpr int waves_per_eu() {
   if (WM * WN == 8 && TA == 0) return 4;
   if (BM == 128 && BN == 32) return 3;
+  if (BM == 64 && BN == 64) return 4;
   return 1;
 }
 
