@@ -646,9 +646,12 @@ hipError_t bt1_groups_apply(int n, int B_, const Bt1Groups& G_, const T* V, long
     const T* Vq = V + r0 + (long)p0 * B_ * ldv;
     const T* Tq = Tall + (size_t)q * W * W;
     T* Zq = Z + r0;
-    // V^T Z: split K so that the product fills the chip
+    // V^T Z: split K so that the product fills the chip.  With the vectors
+    // counted on the device m is only a bound: the split then follows the
+    // rows alone.
     const long tiles = (long)ceil_div(w, 128) * ceil_div(m, 128);
-    int nsp = (int)std::min<long>(BT1_MAXSPLIT, std::max<long>(1, ceil_div(512, (int)tiles)));
+    int nsp = m_dev ? std::min(BT1_MAXSPLIT, std::max(1, h / 2048))
+                    : (int)std::min<long>(BT1_MAXSPLIT, std::max<long>(1, ceil_div(512, (int)tiles)));
     int kchunk = ceil_div(ceil_div(h, nsp), 16) * 16;
     GemmArgsT<T> g{};
     g.m = w; g.n = m; g.k = h; g.A = Vq; g.lda = ldv; g.B = Zq; g.ldb = ldz; g.C = Wb; g.ldc = w;

@@ -656,9 +656,9 @@ hipError_t launch_cfg(const ProbT<T>& p, double alpha, double beta, int flags, i
 int pick_cfg(int m, int n, int k, int nsplit, int ta, int flags) {
   if (n <= 32) return 3;
   if (m <= 32) return 4;
-  if (ta == 1) return 2;
   const bool lower = (flags & (GF_C_LOWER_TILES | GF_C_LOWER_ONLY)) != 0;
   const long t128 = (long)ceil_div(m, 128) * ceil_div(n, 128) * nsplit;
+  if (ta == 1) return (nsplit > 1 && t128 >= 512) ? 0 : 2;
   if (lower) return (k < 1024 || t128 < 4096) ? 2 : 1;
   return t128 >= 4096 ? 0 : 2;
 }
