@@ -267,7 +267,8 @@ HSDM_DEV void gemm_tile(const ProbT<T>& p, double alpha, double beta, int flags,
   // workgroup (the slice's corner plus q times a uniform stride).  For a
   // triangular operand these are the slices on the stored side of the
   // tile's diagonal block.
-  constexpr bool PLAIN = (AM == AM_DENSE) || (AM == AM_TRIL) || (AM == AM_SLT);
+  constexpr bool PLAIN =
+      (AM == AM_DENSE) || (AM == AM_TRIL) || (AM == AM_SLT) || (AM == AM_GATHER && TA == 0);
   const bool whole = PLAIN && (i0 + BM <= p.m) && (j0 + BN <= p.n) &&
                      (p.lda < (1L << 22)) && (p.ldb < (1L << 22));
   const int tid = threadIdx.x;
@@ -289,8 +290,18 @@ HSDM_DEV void gemm_tile(const ProbT<T>& p, double alpha, double beta, int flags,
                                             : p.A + k + (long)i0 * p.lda);
       const char* b = (const char*)(TB == 0 ? p.B + k + (long)j0 * p.ldb
                                             : p.B + j0 + (long)k * p.ldb);
+      if constexpr (AM == AM_GATHER) {
+        // column k + kk of op(A) is column acol[k + kk] of A
+        const char* ai = (const char*)(p.A + i0) + sizeof(T) * (tid % BM);
 #pragma unroll
-      for (int q = 0; q < C::AE; q++) xa[q] = *(const T*)(a + q * sa + oa);
+        for (int q = 0; q < C::AE; q++) {
+          const int kk = k + tid / BM + q * (C::NT / BM);
+          xa[q] = *(const T*)(ai + (long)sizeof(T) * p.acol[kk] * p.lda);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < C::AE; q++) xa[q] = *(const T*)(a + q * sa + oa);
+      }
 #pragma unroll
       for (int q = 0; q < C::BE; q++) xb[q] = *(const T*)(b + q * sb + ob);
     } else {
@@ -442,7 +453,7 @@ __global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(wa
 }
 
 template <int BM, int BN, int WM, int WN, int TA, int TB, int AM>
-__global__ __launch_bounds__(64 * WM * WN, 512 / (64 * WM * WN)) void gemm_batched_kernel(const GemmDesc* desc,
+__global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(waves_per_eu<BM, BN, WM, WN, TA, AM>()))) void gemm_batched_kernel(const GemmDesc* desc,
                                                                     double alpha, double beta,
                                                                     int flags) {
   using C = G<BM, BN, WM, WN, TA, TB, AM>;
