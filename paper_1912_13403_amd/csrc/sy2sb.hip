@@ -229,6 +229,33 @@ HSDM_DEV void form_t(double (*Tl)[B + 1], const double (*Gm)[B + 1], const doubl
   }
 }
 
+// The three h x B copies that file a panel's V and W for the group's
+// held-back updates, in one launch: dv1 = V, dw = W, dv2 = V (ld ldd).
+template <class T>
+__global__ void file_vw_kernel(int h, int B, const T* V, long ldv, const T* W, long ldw,
+                               T* dv1, T* dw, T* dv2, long ldd) {
+  const long tot = (long)h * B;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % h), c = (int)(e / h);
+    const T v = V[i + (long)c * ldv];
+    dv1[i + (long)c * ldd] = v;
+    dv2[i + (long)c * ldd] = v;
+    dw[i + (long)c * ldd] = W[i + (long)c * ldw];
+  }
+}
+
+template <class T>
+hipError_t file_vw(int h, int B, const T* V, long ldv, const T* W, long ldw, T* dv1, T* dw,
+                   T* dv2, long ldd, hipStream_t s) {
+  if (h <= 0) return hipSuccess;
+  const long tot = (long)h * B;
+  const unsigned g = (unsigned)std::min<long>((tot + 255) / 256, 4096);
+  HSDM_LAUNCH(file_vw_kernel<T>, dim3(g), dim3(256), 0, s, h, B, V, ldv, W, ldw, dv1, dw, dv2,
+              ldd);
+  return hipGetLastError();
+}
+
 __global__ void fill_nan_kernel(double* p, long cnt) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < cnt) p[i] = __builtin_nan("");
@@ -926,9 +953,9 @@ struct Sy2sb {
     }
     HSDM_TRY(make_w_post(h, Vq, Wq, false, nullptr, nullptr));
     // V_q into VW, [W_q V_q] into WV (W_q is already in VW)
-    HSDM_TRY(dev_copy(Vq, ldv, VW + o + (size_t)2 * q * n * B, n, h, B, s));
-    HSDM_TRY(dev_copy(Wq, n, WV + o + (size_t)2 * q * n * B, n, h, B, s));
-    HSDM_TRY(dev_copy(Vq, ldv, WV + o + (size_t)(2 * q + 1) * n * B, n, h, B, s));
+    HSDM_TRY(file_vw(h, B, Vq, ldv, (const double*)Wq, (long)n, VW + o + (size_t)2 * q * n * B,
+                     WV + o + (size_t)2 * q * n * B, WV + o + (size_t)(2 * q + 1) * n * B,
+                     (long)n, s));
     if (q + 1 < P) {
       // the next panel's columns (rows from r_q) receive the updates of
       // panels 0 .. q
@@ -1411,9 +1438,8 @@ hipError_t sy2sb_f32_run(int n, int B, float* A, long lda, double* Vst, long ldv
     g.m = h; g.n = B; g.k = B; g.A = Vp; g.lda = ldv32; g.B = L.M; g.ldb = B; g.C = W; g.ldc = n;
     g.alpha = -0.5; g.beta = 1.0;
     HSDM_TRY(gemm_launch(g, s));
-    HSDM_TRY(dev_copy(Vp, ldv32, L.VW, n, h, B, s));
-    HSDM_TRY(dev_copy(W, n, L.WV, n, h, B, s));
-    HSDM_TRY(dev_copy(Vp, ldv32, L.WV + (size_t)n * B, n, h, B, s));
+    HSDM_TRY(file_vw(h, B, (const float*)Vp, ldv32, (const float*)W, (long)n, L.VW, L.WV,
+                     L.WV + (size_t)n * B, (long)n, s));
     g = GemmArgsF{};
     g.m = h; g.n = h; g.k = 2 * B; g.A = L.VW; g.lda = n; g.B = L.WV; g.ldb = n; g.C = A22;
     g.ldc = lda; g.alpha = -1.0; g.beta = 1.0; g.ta = 0; g.tb = 1;

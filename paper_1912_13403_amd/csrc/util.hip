@@ -120,21 +120,29 @@ __global__ void hash_clear_kernel(unsigned long long* out, int cnt) {
 __global__ void hash_lower_kernel(const double* a, long lda, int n, int cplx,
                                   unsigned long long* out) {
   const int per = cplx ? 2 : 1;
+  const int sh = cplx ? 1 : 0;  // value t of a column: row t >> sh, part t & sh
   unsigned long long acc = 0ull;
   for (int j = blockIdx.y; j < n; j += gridDim.y) {
     const long rows = (long)(n - j) * per;  // values of column j from row j down
     for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < rows;
          t += (long)gridDim.x * blockDim.x) {
-      const long i = j + t / per;
-      const int part = (int)(t % per);
+      const long i = j + (t >> sh);
+      const int part = (int)(t & sh);
       if (cplx && part == 1 && i == j) continue;
       const double v = a[(i + (long)j * lda) * per + part];
       const unsigned long long pos = (unsigned long long)((i + (long)j * n) * per + part);
       acc += mix64((unsigned long long)__double_as_longlong(v) + pos * 0x9E3779B97F4A7C15ull);
     }
   }
+  // one atomic per workgroup (the sum is order-free)
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if ((threadIdx.x & 63) == 0 && acc) atomicAdd(out, acc);
+  __shared__ unsigned long long wsum[4];
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (t) atomicAdd(out, t);
+  }
 }
 
 inline unsigned grid_for(long tot) {
@@ -206,7 +214,7 @@ hipError_t dev_hash_lower(const void* a, long lda, int n, int cplx, unsigned lon
   if (n <= 0) return hipSuccess;
   const long rows = (long)n * (cplx ? 2 : 1);
   const unsigned gx = (unsigned)std::min<long>(ceil_div(rows, 256), 16);
-  HSDM_LAUNCH(hash_lower_kernel, dim3(gx, std::min(n, 32768)), dim3(256), 0, s, (const double*)a, lda, n,
+  HSDM_LAUNCH(hash_lower_kernel, dim3(gx, std::min(n, 2048)), dim3(256), 0, s, (const double*)a, lda, n,
                      cplx, out);
   return hipGetLastError();
 }
