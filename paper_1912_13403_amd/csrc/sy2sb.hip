@@ -823,12 +823,7 @@ struct Sy2sb {
     g.alpha = -0.5; g.beta = 1.0;
     return g;
   }
-  hipError_t make_w_post(int h, const double* Vp, double* Wp, bool correct, const double* VWc,
-                         const double* WVc) {
-    if (correct) {
-      HSDM_TRY(gemm_splitk_launch(corr1_args(h, WVc), SPLITK, skpart, s));
-      HSDM_TRY(gemm_launch(corr2_args(h, VWc, Wp), s));
-    }
+  hipError_t make_w_post(int h, const double* Vp, double* Wp) {
     const AtbGroupItem a = atb_item(h, Wp);
     HSDM_LAUNCH((atb_partial_kernel<BB>), dim3(a.G), dim3(NT), 0, s, h, a.U, a.ldu, a.W,
                        a.ldw, a.part);
@@ -846,12 +841,7 @@ struct Sy2sb {
     c[1] = CopyGroupItem{Wp, WV + o, (long)n, (long)n, h, B};
     c[2] = CopyGroupItem{Vp, WV + o + (size_t)n * B, ldv, (long)n, h, B};
   }
-  hipError_t run_copies(int h, const double* Vp, const double* Wp, long o) {
-    CopyGroupItem c[3];
-    copies(h, Vp, Wp, o, c);
-    for (auto& x : c) HSDM_TRY(dev_copy(x.src, x.lds, x.dst, x.ldd, x.m, x.n, s));
-    return hipSuccess;
-  }
+
   // A[r:, r:] -= VWr WVr^T (lower), k columns
   GemmArgs syr2k_args(int r, int h, const double* VWr, const double* WVr, int k) const {
     GemmArgs g{};
@@ -881,18 +871,7 @@ struct Sy2sb {
     const int r0 = (p + 1) * B;
     sym_args(r0, n - r0, first_w(), tril, slt);
   }
-  hipError_t after_first(int p) {
-    if (!first_has_w(p)) return hipSuccess;
-    const int r0 = (p + 1) * B, h = n - r0;
-    const double* V1 = first_v(p);
-    double* W1 = first_w();
-    HSDM_TRY(make_w_pre(h, V1, first_t(p)));
-    HSDM_TRY(make_w_sym(r0, h, W1));
-    HSDM_TRY(make_w_post(h, V1, W1, false, nullptr, nullptr));
-    HSDM_TRY(run_copies(h, V1, W1, 0));
-    if (advance(p) == 1) return syr2k(r0, h, VW, WV, 2 * B);
-    return gemm_launch(col_args(r0, h), s);
-  }
+
   // after the QR of panel p+1 of a pair: its W (with the first panel's
   // delayed update) and the pair's rank-4B trailing update
   const double* second_v(int p) const { return Vst + (p + 2) * B + (long)(p + 1) * B * ldv; }
@@ -903,16 +882,7 @@ struct Sy2sb {
     const int r1 = (p + 2) * B;
     sym_args(r1, n - r1, second_w(), tril, slt);
   }
-  hipError_t after_second(int p) {
-    const int r1 = (p + 2) * B, h2 = n - r1;
-    const double* V2 = second_v(p);
-    double* W2 = second_w();
-    HSDM_TRY(make_w_pre(h2, V2, second_t(p)));
-    HSDM_TRY(make_w_sym(r1, h2, W2));
-    HSDM_TRY(make_w_post(h2, V2, W2, true, VW + B, WV + B));
-    HSDM_TRY(run_copies(h2, V2, W2, second_off(n, B)));
-    return syr2k(r1, h2, VW + B, WV + B, 4 * B);
-  }
+
   // ---- single reduction: up to PGROUP panels per trailing update ----------
   // For the group of panels p0 .. p0 + P - 1 (panel q at rows r_q =
   // (p0 + q + 1) B, height h_q), every panel's update
@@ -951,7 +921,7 @@ struct Sy2sb {
       g.C = Wq; g.ldc = n; g.alpha = -1.0; g.beta = 1.0;
       HSDM_TRY(gemm_launch(g, s));
     }
-    HSDM_TRY(make_w_post(h, Vq, Wq, false, nullptr, nullptr));
+    HSDM_TRY(make_w_post(h, Vq, Wq));
     // V_q into VW, [W_q V_q] into WV (W_q is already in VW)
     HSDM_TRY(file_vw(h, B, Vq, ldv, (const double*)Wq, (long)n, VW + o + (size_t)2 * q * n * B,
                      WV + o + (size_t)2 * q * n * B, WV + o + (size_t)(2 * q + 1) * n * B,
