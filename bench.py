@@ -154,6 +154,7 @@ KERNEL_SOURCES = {
     "bt2_strip_kernel": ["bt.hip", "hsdm_internal.h"],
     "panel_qr_kernel": ["sy2sb.hip", "hsdm_internal.h"],
     "dm_kernel": ["dm.hip", "hsdm_internal.h", "hsdm_util.h"],
+    "sym_pair_kernel": ["gemm.hip", "hsdm_internal.h", "hsdm_util.h"],
 }
 
 
