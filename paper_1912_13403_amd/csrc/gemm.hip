@@ -662,7 +662,8 @@ hipError_t launch_cfg(const ProbT<T>& p, double alpha, double beta, int flags, i
 // the n = 16384 solve: 64x64 tiles for a k-contiguous A operand, for
 // rank-k updates of a lower triangle with k < 1024 and for products of fewer
 // than 4096 128x128 tiles (more, smaller tiles balance better), 128x64 for
-// large lower-triangle updates, 128x128 otherwise.  The tuning table below
+// large lower-triangle updates and for products of 16384 or more 128x128
+// tiles, 128x128 otherwise.  The tuning table below
 // overrides it for the products it has timed.
 int pick_cfg(int m, int n, int k, int nsplit, int ta, int flags) {
   if (n <= 32) return 3;
@@ -671,6 +672,7 @@ int pick_cfg(int m, int n, int k, int nsplit, int ta, int flags) {
   const long t128 = (long)ceil_div(m, 128) * ceil_div(n, 128) * nsplit;
   if (ta == 1) return (nsplit > 1 && t128 >= 512) ? 0 : 2;
   if (lower) return (k < 1024 || t128 < 4096) ? 2 : 1;
+  if (t128 >= 16384) return 1;
   return t128 >= 4096 ? 0 : 2;
 }
 
