@@ -28,6 +28,7 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int CH = 256;      // panel rows per workgroup
+constexpr int ACH = 128;     // rows per workgroup of the tall U^T W products
 constexpr int SPLITK = 512;  // K slice of the symmetric product X = A22 Y
 constexpr int PGROUP = 4;    // panels per trailing update in a single reduction
 
@@ -603,15 +604,15 @@ __global__ void band_extract_kernel(int n, int B, const double* A, long lda, dou
 
 // P = U^T W for h x B tall operands: per-workgroup partial sums, then a
 // fixed-order reduction (reproducible).  Workgroup g sums rows
-// [CH g, CH g + CH).
+// [ACH g, ACH g + ACH).
 template <int B>
 HSDM_DEV void atb_partial_body(int h, const double* U, long ldu, const double* W, long ldw,
                                double* part, int g) {
   const int t = threadIdx.x;
-  const int r0 = g * CH, nr = min(CH, h - r0);
-  __shared__ double Us[CH][B + 1], Ws[CH][B + 1];
-  for (int e = t; e < CH * B; e += NT) {
-    const int i = e % CH, c = e / CH;
+  const int r0 = g * ACH, nr = min(ACH, h - r0);
+  __shared__ double Us[ACH][B + 1], Ws[ACH][B + 1];
+  for (int e = t; e < ACH * B; e += NT) {
+    const int i = e % ACH, c = e / ACH;
     Us[i][c] = (i < nr) ? U[r0 + i + (long)c * ldu] : 0.0;
     Ws[i][c] = (i < nr) ? W[r0 + i + (long)c * ldw] : 0.0;
   }
@@ -674,13 +675,13 @@ __global__ void copy_group_kernel(const CopyGroupItem* items) {
 }  // namespace
 
 size_t sy2sb_scratch_doubles(int n, int B) {
-  const int G = ceil_div(n, CH) + 1;
+  const int G = ceil_div(n, CH) + 1, AG = ceil_div(n, ACH) + 1;
   // panel exchange slots: part (B columns x G x B) + prow (B x B) + gpart (G B^2);
-  // atb parts (G B^2) + Y (n x B) + VW, WV (n x 2 PGROUP B each) + M (B^2)
+  // atb parts (AG B^2) + Y (n x B) + VW, WV (n x 2 PGROUP B each) + M (B^2)
   // + Q (2 PGROUP B^2) + split-K partials of the two symmetric passes
   // (nsplit x n x B each)
   const size_t nsplit = ceil_div(n, SPLITK) + 1;
-  return (size_t)G * B * B + (size_t)B * B + (size_t)2 * G * B * B +
+  return (size_t)G * B * B + (size_t)B * B + (size_t)G * B * B + (size_t)AG * B * B +
          (size_t)(1 + 4 * PGROUP) * n * B + (size_t)(1 + 2 * PGROUP) * B * B + 64 +
          2 * nsplit * n * B;
 }
@@ -724,8 +725,8 @@ struct Sy2sb {
     part = a.scratch;                      // B x Gmax x B exchange slots
     prow = part + (size_t)B * Gmax * B;    // B x B
     gpart = prow + (size_t)B * B;          // Gmax x B x B
-    apart = gpart + (size_t)Gmax * B * B;
-    Y = apart + (size_t)Gmax * B * B;      // n x B
+    apart = gpart + (size_t)Gmax * B * B;  // (n / ACH + 1) x B x B
+    Y = apart + (size_t)(ceil_div(n, ACH) + 1) * B * B;  // n x B
     VW = Y + (size_t)n * B;                // n x 2 PGROUP B  [V1 W1 V2 W2 ...], row i <-> row r0 + i
     WV = VW + (size_t)n * 2 * PGROUP * B;  // n x 2 PGROUP B  [W1 V1 W2 V2 ...]
     M = WV + (size_t)n * 2 * PGROUP * B;   // B x B
@@ -809,11 +810,11 @@ struct Sy2sb {
     g.ldc = n; g.alpha = -1.0; g.beta = 1.0;
     return g;
   }
-  // M = Y^T X (partial sums per CH rows)
+  // M = Y^T X (partial sums per ACH rows)
   AtbGroupItem atb_item(int h, const double* Wp) const {
     AtbGroupItem it{};
     it.U = Y; it.ldu = n; it.W = Wp; it.ldw = n; it.part = apart; it.out = M; it.ldo = B;
-    it.h = h; it.G = ceil_div(h, CH);
+    it.h = h; it.G = ceil_div(h, ACH);
     return it;
   }
   // W -= V M / 2
@@ -915,7 +916,7 @@ struct Sy2sb {
       GemmArgs g{};
       g.m = 2 * B * q; g.n = B; g.k = h; g.A = WV + o; g.lda = n; g.B = Y; g.ldb = n;
       g.C = Qc; g.ldc = 2 * B * q; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
-      HSDM_TRY(gemm_splitk_launch(g, SPLITK, skpart, s));
+      HSDM_TRY(gemm_splitk_launch(g, SPLITK / 2, skpart, s));
       g = GemmArgs{};
       g.m = h; g.n = B; g.k = 2 * B * q; g.A = VW + o; g.lda = n; g.B = Qc; g.ldb = 2 * B * q;
       g.C = Wq; g.ldc = n; g.alpha = -1.0; g.beta = 1.0;
