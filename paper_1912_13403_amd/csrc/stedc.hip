@@ -169,31 +169,34 @@ __global__ __launch_bounds__(256) void merge_prep_kernel(int n, const double* e,
   const double sgn = (beta >= 0.0) ? 1.0 : -1.0;
   const double rs2 = 0.70710678118654752440;
   const int t = threadIdx.x;
-  // sorted merge of the two ascending halves (ties: first half first)
-  for (int c = t; c < N; c += 256) {
-    const double dc = lam[lo + c];
-    int pos;
-    if (c < n1) {
-      int a = 0, z = N - n1;  // count of second-half values < dc
-      while (a < z) {
-        const int h = (a + z) >> 1;
-        if (lam[mid + h] < dc) a = h + 1; else z = h;
-      }
-      pos = c + a;
-    } else {
-      int a = 0, z = n1;  // count of first-half values <= dc
-      while (a < z) {
-        const int h = (a + z) >> 1;
-        if (lam[lo + h] <= dc) a = h + 1; else z = h;
-      }
-      pos = (c - n1) + a;
+  // sorted merge of the two ascending halves (ties: first half first), by
+  // merge path: thread t writes outputs [t per, t per + per); it finds how
+  // many of them before its first come from the first half by one binary
+  // search along its diagonal, then merges its run sequentially
+  const int n2 = N - n1;
+  const int per = (N + 255) / 256;
+  const int d0 = min(N, t * per), d1 = min(N, d0 + per);
+  if (d0 < d1) {
+    const double* A = lam + lo;   // first half, n1 ascending
+    const double* Bh = lam + mid;  // second half, n2 ascending
+    int a = max(0, d0 - n2), z = min(d0, n1);
+    while (a < z) {
+      const int h = (a + z) >> 1;
+      if (A[h] <= Bh[d0 - h - 1]) a = h + 1; else z = h;
     }
-    const double zc = (c < n1) ? Qcur[(mid - 1) + (long)(lo + c) * ldq] * rs2
-                               : sgn * Qcur[mid + (long)(lo + c) * ldq] * rs2;
-    b.dsort[lo + pos] = dc;
-    b.zsort[lo + pos] = zc;
-    b.perm[lo + pos] = c;
-    b.msk[lo + pos] = (c < n1) ? 1 : 2;
+    int i = a, j = d0 - a;
+    for (int pos = d0; pos < d1; pos++) {
+      const bool first = (j >= n2) || (i < n1 && A[i] <= Bh[j]);
+      const int c = first ? i : n1 + j;
+      const double dc = first ? A[i] : Bh[j];
+      const double zc = first ? Qcur[(mid - 1) + (long)(lo + c) * ldq] * rs2
+                              : sgn * Qcur[mid + (long)(lo + c) * ldq] * rs2;
+      b.dsort[lo + pos] = dc;
+      b.zsort[lo + pos] = zc;
+      b.perm[lo + pos] = c;
+      b.msk[lo + pos] = first ? 1 : 2;
+      if (first) i++; else j++;
+    }
   }
   __syncthreads();
   __shared__ double cd[CHK], cz[CHK];
