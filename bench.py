@@ -288,6 +288,9 @@ def batch_main(args):
     h.hsdm_set_real(hsdm.HSDM_KEY_FMAX, 1.0)
     h.hsdm_set_int(hsdm.HSDM_KEY_TIMING, 2)
     h.hsdm_set_int(hsdm.HSDM_KEY_STREAMS, MT_STREAMS)
+    refined = args.precision == "refined"
+    if refined:
+        h.hsdm_set_int(hsdm.HSDM_KEY_PRECISION, 1)
 
     def step():
         h.hsdm_reinit()
@@ -315,6 +318,20 @@ def batch_main(args):
     h.hsdm_solve_dm_batch(Hs, Ss, ne, kT)
     torch.cuda.synchronize()
     warm = time.perf_counter() - ts
+    vs_fp64 = None
+    if refined:
+        # the same batch in the FP64 form, for the differences of the results
+        h.hsdm_set_int(hsdm.HSDM_KEY_PRECISION, 0)
+        h.hsdm_reinit()
+        f = h.hsdm_solve_dm_batch(Hs, Ss, ne, kT)
+        torch.cuda.synchronize()
+        vs_fp64 = {
+            "max_abs_dD": max(torch.max(torch.abs(a - b)).item() for a, b in zip(r["D"], f["D"])),
+            "max_abs_dE": max(torch.max(torch.abs(a - b)).item() for a, b in zip(r["E"], f["E"])),
+            "abs_dmu": abs(r["mu"] - f["mu"]),
+            "abs_dband_energy": abs(r["band_energy"] - f["band_energy"]),
+        }
+        del f
     agg = {}
     for ks in kstats:
         for k, v in ks.items():
@@ -349,11 +366,13 @@ def batch_main(args):
         "higher_is_better": True,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if refined else "f64",
         "data": "synthetic",
         "config": {"workload": f"cfg3_batch: {ntask} Hermitian FP64 generalized tasks "
                                f"(32 k-points x 2 spins, n_k in [{min(sizes)}, {max(sizes)}]), "
-                               f"one mu, N_e={ne:.1f}, kT={kT}, f_max=1, cold S factors",
+                               f"one mu, N_e={ne:.1f}, kT={kT}, f_max=1, cold S factors"
+                               + (", refined form" if refined else ""),
+                   "precision": args.precision,
                    "tasks": ntask, "sum_n": sum(sizes), "n_electrons": ne, "kT": kT,
                    "worker_streams": MT_STREAMS,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))},
@@ -364,6 +383,8 @@ def batch_main(args):
         "band_energy": r["band_energy"],
         "timed_total_s": total,
     }
+    if vs_fp64 is not None:
+        rec["refined_vs_fp64"] = vs_fp64
     h.close()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = batch_cpu_baseline(sizes)
@@ -381,8 +402,6 @@ def serving_main(args):
     make = lambda req, S: inputs.request_problem_device(req, specs[req["base"]], S, dev)
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
     prec = 1 if args.precision == "refined" else 0
-    if prec and args.group > 1:
-        raise SystemExit("the refined form serves single solves: use --group 1")
     srv = serving.Server(0, hbm_budget=200e9, slots=args.slots, max_group=args.group,
                          streams=MT_STREAMS if args.group > 1 else 0, precision=prec)
     # warmup: a short stream of small requests (kernels loaded, workspaces made)
@@ -455,8 +474,8 @@ def main():
                     help="run one untimed solve with the GEMM tile autotuner first "
                          "(HSDM_KEY_AUTOTUNE); the timed steps use its table")
     ap.add_argument("--precision", choices=["fp64", "refined"], default="fp64",
-                    help="arithmetic of the single solves served by --config cfg4_serving "
-                         "(refined: HSDM_KEY_PRECISION = 1, needs --group 1)")
+                    help="arithmetic of the solves of --config cfg3_batch and cfg4_serving "
+                         "(refined: HSDM_KEY_PRECISION = 1)")
     ap.add_argument("--no-refined", action="store_true",
                     help="skip the refined form's steps (e.g. under a profiler)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -76,9 +76,10 @@ enum hsdm_key {
                               ones (the paper's n_states: its dense runs compute only part of
                               the eigenvectors, Sec. 3); 0 or >= n: all (default 0).  C then
                               holds n_states columns; every eigenvalue is still returned */
-  , HSDM_KEY_PRECISION = 8 /* int: arithmetic of the single solves hsdm_solve_ev_real,
-                              hsdm_solve_dm_real and hsdm_solve_dm_complex (the latter on its
-                              real embedding).  0 (default): FP64 throughout.  1: the
+  , HSDM_KEY_PRECISION = 8 /* int: arithmetic of hsdm_solve_ev_real, hsdm_solve_dm_real,
+                              hsdm_solve_dm_complex (on its real embedding) and the multi-task
+                              hsdm_solve_dm_batch and hsdm_solve_dm_group.  0 (default): FP64
+                              throughout.  1: the
                               refined form -- the full -> band reduction's trailing updates and
                               the stage-1 back-transform in FP32 on the matrix cores, every
                               eigenvector formed, then at most HSDM_KEY_REFINE_STEPS steps of FP64
@@ -92,8 +93,12 @@ enum hsdm_key {
                               order of its square; a pair of eigenvalues too close to resolve in
                               a step counts with the correction it would need at that step's
                               separation), later steps correcting only the vectors still above
-                              it.  hsdm_solve_ev_complex, the multi-task and the
-                              allocation-free solves always run the FP64 form */
+                              it.  In a multi-task solve every task's reduction, eigensolve
+                              and refinement run one task after another on the caller's stream,
+                              the wanted vectors chosen at the shared (batch) or own (group)
+                              occupations of the unrefined eigenvalues, the occupations taken
+                              again at the refined ones.  hsdm_solve_ev_complex and the
+                              allocation-free solve always run the FP64 form */
   , HSDM_KEY_REFINE_STEPS = 9 /* int: most refinement steps of the refined form, 1 ... 8
                               (default 8) */
   , HSDM_KEY_GRAPH = 11    /* int: 1 = hsdm_solve_dm_real (FP64 form, timing off, not

@@ -1833,6 +1833,24 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
       return r;
     }
   }
+  // The refined form (HSDM_KEY_PRECISION = 1): every task's FP32 reduction
+  // and, after the occupations, its refinement run one task after another
+  // on s (their bulge chasing, panel QRs and stage-2 back-transform need
+  // their workgroups placed together, so they do not share the device), in
+  // one workspace of the handle sized for the largest task; each task keeps
+  // its FP64 reflectors, eigenvectors and standard-form matrix in its own.
+  const bool refined = h->precision == 1;
+  if (refined) {
+    int nmax = 0;
+    for (int p = 0; p < nt; p++) nmax = std::max(nmax, T[p].cplx ? 2 * T[p].n : T[p].n);
+    if ((r = ensure_rws(h, nmax, s))) return r;
+    for (int p = 0; p < nt; p++) {
+      hsdm_ctx* c = ctx[p];
+      c->A32 = h->A32; c->V32 = h->V32; c->Z32 = h->Z32; c->f32_scr = h->f32_scr;
+      c->bt1f = h->bt1f; c->ref_scr = h->ref_scr; c->rrec = h->rrec;
+      c->refine_steps = h->refine_steps;
+    }
+  }
   KtScope kts(h);
   Lanes lanes{h, s, nl};
   for (int p = 0; p < NPHASE; p++) h->phase_done[p] = false;
@@ -1872,9 +1890,29 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
                             t.w};
   }
   DEV_TRY(h, lanes.join());
+  if (refined) {
+    // every task on s: FP32 reduction with FP64 panels, bulge chasing,
+    // every eigenpair of the tridiagonal (the refinement corrects the
+    // wanted vectors with all the others)
+    for (int p : issue) {
+      hsdm_ctx* c = ctx[p];
+      const TaskSpec& t = T[p];
+      const int nr = t.cplx ? 2 * t.n : t.n;
+      if ((r = reduce_f32(c, nr, s, 3))) {
+        h->err = c->err;
+        return r;
+      }
+      DEV_TRY(h, stedc_run(c->plan, c->dvec, c->evec, c->lam, c->Zbuf, nr, c->dc_scr,
+                           c->dc_iscr, nullptr, nullptr, nullptr, c->st, s));
+      if (!shared) {
+        OccHook hook{c, nr, t.cplx ? 2.0 * t.ne : t.ne, t.kT};
+        DEV_TRY(h, occ_hook(&hook, c->lam, s));
+      }
+    }
+  }
   // full -> band of all tasks, pair step by pair step, the panel QRs of a
   // step in shared cooperative launches
-  {
+  if (!refined) {
     h->sy_args.resize(nt);
     for (int p = 0; p < nt; p++) {
       hsdm_ctx* c = ctx[p];
@@ -1900,7 +1938,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
   //    each band alone is latency-bound and fills a small part of the device.
   //    A launch lasts as long as its largest band, so the bands go into the
   //    launches largest first.
-  {
+  if (!refined) {
     h->h_sb.assign(nt, Sb2stTask{});
     h->h_wgmap.clear();
     std::vector<int> by_size(nt);
@@ -1955,6 +1993,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
   //    occupations are shared: they are not known yet)
   DEV_TRY(h, lanes.fork());
   for (int p : issue) {
+    if (refined) break;
     hsdm_ctx* c = ctx[p];
     const hipStream_t ls = stream_of(p);
     const TaskSpec& t = T[p];
@@ -1979,16 +2018,51 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
     DEV_TRY(h, occupations_joint_launch(nt, h->d_tasks, h->fmax, ne, kT, h->deg_tol,
                                         h->fcut_rel * h->fmax, h->occ, h->st, s));
   }
+  if (refined) {
+    // the wanted count of each task at the unrefined eigenvalues, with a
+    // margin for the states the refinement moves across the occupation
+    // cut; the refinement of those vectors (both back-transforms of every
+    // vector first); the occupations again at the refined eigenvalues
+    for (int p = 0; p < nt; p++)
+      DEV_TRY(h, hipMemcpyAsync(&ctx[p]->host->occ, ctx[p]->occ, sizeof(OccOut),
+                                hipMemcpyDeviceToHost, s));
+    DEV_TRY(h, hipStreamSynchronize(s));
+    for (int p : issue) {
+      hsdm_ctx* c = ctx[p];
+      const TaskSpec& t = T[p];
+      const int nr = t.cplx ? 2 * t.n : t.n;
+      const int m0 = c->host->occ.m;
+      const int mref = std::min(nr, m0 + std::max(32, m0 / 32));
+      // the FP32 reflectors of stage 1 (the shared workspace held another
+      // task's meanwhile): the FP64 ones rounded, as the reduction made them
+      DEV_TRY(h, dev_convert(c->Vst, nr, c->V32, nr, nr, nr, s));
+      if ((r = refine_vectors(c, nr, mref, c->lam, s))) {
+        h->err = c->err;
+        return r;
+      }
+      if (!shared) {
+        OccHook hook{c, nr, t.cplx ? 2.0 * t.ne : t.ne, t.kT};
+        DEV_TRY(h, occ_hook(&hook, c->lam, s));
+      }
+    }
+    if (shared) {
+      HSDM_LAUNCH(reset_status_kernel, dim3(1), dim3(64), 0, s, h->st, h->occ);
+      DEV_TRY(h, hipGetLastError());
+      DEV_TRY(h, occupations_joint_launch(nt, h->d_tasks, h->fmax, ne, kT, h->deg_tol,
+                                          h->fcut_rel * h->fmax, h->occ, h->st, s));
+    }
+  }
   // 5. stage-2 back-transform of all tasks' occupied vectors in one launch
+  // (the refined form has transformed every vector back already)
   h->h_bt2.resize(nt);
-  for (int p = 0; p < nt; p++) {
+  for (int p = 0; p < nt && !refined; p++) {
     hsdm_ctx* c = ctx[p];
     const int nr = T[p].cplx ? 2 * T[p].n : T[p].n;
     DEV_TRY(h, bt2_prepare(c->lay, c->V2, c->tau2, c->F2, s));
     h->h_bt2[p] = bt2_task(c->lay, c->F2, c->d_goff, c->Zbuf, nr, nr, &c->occ->m, c->progress,
                            c->st);
   }
-  {
+  if (!refined) {
     const size_t need = sizeof(Bt2Task) * (nt + 1) +
                         sizeof(int) * (bt2_group_map_ints(nt, h->h_bt2.data()) + 1);
     if (h->d_bt2_bytes < need) {
@@ -2012,7 +2086,8 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
     const TaskSpec& t = T[p];
     const int nr = t.cplx ? 2 * t.n : t.n;
     const int* m_dev = &c->occ->m;
-    DEV_TRY(h, bt1_apply(nr, BAND, c->Vst, nr, c->T1, c->Zbuf, nr, nr, m_dev, c->bt1_scr, ls));
+    if (!refined)
+      DEV_TRY(h, bt1_apply(nr, BAND, c->Vst, nr, c->T1, c->Zbuf, nr, nr, m_dev, c->bt1_scr, ls));
     GemmArgs g{};
     g.m = nr; g.n = nr; g.k = nr; g.A = ctx[src[p]]->Linv; g.lda = nr; g.B = c->Zbuf; g.ldb = nr;
     g.C = c->Cbuf; g.ldc = nr; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;

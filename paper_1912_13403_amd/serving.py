@@ -9,8 +9,8 @@ if its device memory fits the HBM budget beside everything in use, together
 with the requests queued behind it while they fit and the group size allows
 (max_group): one request runs through the single-solve entry points, several
 through hsdm_solve_dm_group, each with its own occupations.  With
-precision = 1 the slots' single solves run the refined form
-(HSDM_KEY_PRECISION; grouped solves are always FP64).  A request that
+precision = 1 the slots' solves, single and grouped, run the refined form
+(HSDM_KEY_PRECISION).  A request that
 arrives while others run is admitted as soon as a slot and memory free up.
 
 A request that repeats an earlier request's S (the SCF steps of one

@@ -211,3 +211,80 @@ def test_refined_hermitian_dm_against_oracle(oracle, torch_dev, hr, k):
     assert dD <= 1e-9
     assert dE <= 1e-9 * max(1.0, scale)
     assert abs(out["mu"] - ref["mu"]) <= 1e-10 * scale
+
+
+def _herm_norm1(A):
+    lo = np.tril(A, -1)
+    return float(np.abs(lo + lo.conj().T + np.diag(np.real(np.diag(A)))).sum(axis=0).max())
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_refined_batch_shared_mu_against_oracle(oracle, torch_dev, hr, cplx):
+    """hsdm_solve_dm_batch in the refined form: every task's FP32 reduction
+    and all its eigenpairs, one chemical potential at the unrefined
+    eigenvalues to choose the vectors to refine, the refinement, the shared
+    occupations again; every entry of every task's D and E, mu and the band
+    energy against the oracle's shared-mu route."""
+    from paper_1912_13403_amd import hsdm
+    torch, dev = torch_dev
+    if cplx:
+        sizes = [40, 97, 150]
+        Hs, Ss = [], []
+        for i, n in enumerate(sizes):
+            Hu, Hd, S = inputs.kpoint_problem(20 + i, n=n)
+            Hs += [Hu, Hd]
+            Ss += [S, S]
+        weights, fmax = None, 1.0
+        ne, kT = 0.4 * sum(sizes), 0.01
+    else:
+        sizes, weights = [47, 130, 300], [0.5, 2.0, 1.0]
+        probs = [inputs.sized_problem(n, cfg=1400 + n) for n in sizes]
+        Hs, Ss = [p[0] for p in probs], [p[1] for p in probs]
+        fmax = 2.0
+        ne, kT = 0.45 * sum(w * n for w, n in zip(weights, sizes)) * 2.0, 0.01
+    hr.hsdm_set_real(hsdm.HSDM_KEY_FMAX, fmax)
+    try:
+        hr.hsdm_reinit()
+        r = hr.hsdm_solve_dm_batch([_g(torch_dev, x) for x in Hs], [_g(torch_dev, x) for x in Ss],
+                                   ne, kT, weights=weights)
+    finally:
+        hr.hsdm_set_real(hsdm.HSDM_KEY_FMAX, 2.0)
+    ref = oracle.solve_dm_batch(Hs, Ss, ne, kT, weights=weights, f_max=fmax)
+    scale = max(_herm_norm1(H) for H in Hs)
+    dD = max(np.max(np.abs(_c(D) - Dr)) for D, Dr in zip(r["D"], ref["D"]))
+    dE = max(np.max(np.abs(_c(E) - Er)) for E, Er in zip(r["E"], ref["E"]))
+    print(f"[refined batch] cplx={cplx}: |dD| {dD:.2e}, |dE| {dE:.2e}, "
+          f"|dmu| {abs(r['mu'] - ref['mu']):.2e}", flush=True)
+    assert dD <= 1e-9
+    assert dE <= 1e-9 * max(1.0, scale)
+    assert abs(r["mu"] - ref["mu"]) <= 1e-10 * scale
+    assert abs(r["band_energy"] - ref["band_energy"]) <= 1e-10 * scale * max(ne, 1.0)
+
+
+def test_refined_group_against_oracle(oracle, torch_dev, hr):
+    """hsdm_solve_dm_group in the refined form: independent real and
+    Hermitian problems, each with its own occupations, against the oracle."""
+    torch, dev = torch_dev
+    H1, S1 = inputs.sized_problem(120, cfg=1501)
+    H2, S2 = inputs.sized_problem(257, cfg=1502)
+    Hu, _, S3 = inputs.kpoint_problem(7, n=90)
+    tasks = [dict(H=_g(torch_dev, H1), S=_g(torch_dev, S1), n_electrons=60.0, kT=0.01,
+                  f_max=2.0),
+             dict(H=_g(torch_dev, H2), S=_g(torch_dev, S2), n_electrons=101.0, kT=0.0,
+                  f_max=2.0),
+             dict(H=torch.from_numpy(Hu).to(dev), S=torch.from_numpy(S3).to(dev),
+                  n_electrons=30.0, kT=0.02, f_max=1.0)]
+    hr.hsdm_reinit()
+    outs = hr.hsdm_solve_dm_group(tasks)
+    refs = [oracle.solve_dm(H1, S1, 60.0, 0.01), oracle.solve_dm(H2, S2, 101.0, 0.0),
+            oracle.solve_dm_complex(Hu, S3, 30.0, 0.02, f_max=1.0)]
+    for i, (o, ref, H) in enumerate(zip(outs, refs, [H1, H2, Hu])):
+        scale = _herm_norm1(H)
+        print(f"[refined group] task {i}: |dD| {np.max(np.abs(_c(o['D']) - ref['D'])):.2e}, "
+              f"mu {o['mu']:.6f} / {ref['mu']:.6f}, Eb {o['band_energy']:.6f} / "
+              f"{ref['band_energy']:.6f}", flush=True)
+    for o, ref, H in zip(outs, refs, [H1, H2, Hu]):
+        scale = _herm_norm1(H)
+        assert np.max(np.abs(_c(o["D"]) - ref["D"])) <= 1e-9
+        assert np.max(np.abs(_c(o["E"]) - ref["E"])) <= 1e-9 * max(1.0, scale)
+        assert abs(o["band_energy"] - ref["band_energy"]) <= 1e-10 * scale * 100.0
