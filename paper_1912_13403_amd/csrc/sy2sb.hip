@@ -862,8 +862,10 @@ struct Sy2sb {
     g.tb = 1; g.flags = GF_C_LOWER_ONLY;
     return g;
   }
-  // after the QR of panel p: its W, and either the trailing update (panel
-  // alone) or the update of panel p+1's columns (pair).
+  // Operands of the multi-task reduction's pair steps (the grouped launches
+  // build their descriptors from these): after the QR of panel p, its W and
+  // either the trailing update (panel alone) or the update of panel p+1's
+  // columns (pair).
   bool first_has_w(int p) const { return height(p) > 1; }
   const double* first_v(int p) const { return Vst + (p + 1) * B + (long)p * B * ldv; }
   const double* first_t(int p) const { return T1 + (size_t)p * B * B; }
