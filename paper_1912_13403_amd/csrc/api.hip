@@ -2133,6 +2133,7 @@ int solve_tasks(hsdm_ctx* h, int nt, const TaskSpec* T, bool shared, double ne, 
 double ctx_bytes(const hsdm_ctx* c) {
   double b = (c->ws_raw && !c->borrowed) ? (double)c->ws_cap : 0.0;
   if (c->cws) b += 16.0 * 8.0 * (double)c->cws_n * c->cws_n;
+  if (c->rws_raw) b += (double)c->rws_cap;  // the refined form's workspace
   return b;
 }
 
