@@ -157,7 +157,28 @@ struct LevelBufs {
   double* U;     // node block at U + lo * n, ld k
 };
 
+// The test of two neighbouring undeflated entries (prev: pd, pz; current:
+// dq, zq): the rotation that zeroes pz has c = zq / r, s = pz / r,
+// r = hypot(zq, pz), and leaves the coupling (pd - dq) c s; the test
+// |(pd - dq) c s| <= tol is taken as |(pd - dq) zq pz| <= tol r^2 so that r,
+// c and s are formed only for a rotation.
+HSDM_DEV bool close_pair(double pd, double pz, double dq, double zq, double tol) {
+  return fabs((pd - dq) * zq * pz) <= tol * (zq * zq + pz * pz);
+}
+
 // Per merge: z, sorted merge of the halves, deflation, grouping.
+//
+// Deflation is the scan of LAPACK's dlaed2 in the sorted order: an entry
+// with rho |z| <= tol is deflated; each other entry is compared with the
+// undeflated entry before it and, when the two are close (close_pair), a
+// rotation deflates the earlier one and the later one carries on with the
+// rotated values.  Only the rotations make the scan sequential: without
+// one, the undeflated entries keep their own values in order.  The kernel
+// therefore first sorts the entries in parallel (ballots and prefix counts)
+// and tests every neighbouring pair with the unrotated values; the first
+// pair that the sequential scan would rotate is among them (no rotation
+// precedes it), so when no pair is close the result is the scan's exactly,
+// and otherwise the sequential scan runs (by one thread).
 __global__ __launch_bounds__(256) void merge_prep_kernel(int n, const double* e, const double* lam,
                                                          const double* Qcur, long ldq,
                                                          LevelBufs b, int m0) {
@@ -168,7 +189,8 @@ __global__ __launch_bounds__(256) void merge_prep_kernel(int n, const double* e,
   const double rho = 2.0 * fabs(beta);
   const double sgn = (beta >= 0.0) ? 1.0 : -1.0;
   const double rs2 = 0.70710678118654752440;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const unsigned long long lanes_below = (1ull << lane) - 1ull;
   // sorted merge of the two ascending halves (ties: first half first), by
   // merge path: thread t writes outputs [t per, t per + per); it finds how
   // many of them before its first come from the first half by one binary
@@ -187,140 +209,201 @@ __global__ __launch_bounds__(256) void merge_prep_kernel(int n, const double* e,
     int i = a, j = d0 - a;
     for (int pos = d0; pos < d1; pos++) {
       const bool first = (j >= n2) || (i < n1 && A[i] <= Bh[j]);
-      const int c = first ? i : n1 + j;
-      const double dc = first ? A[i] : Bh[j];
-      const double zc = first ? Qcur[(mid - 1) + (long)(lo + c) * ldq] * rs2
-                              : sgn * Qcur[mid + (long)(lo + c) * ldq] * rs2;
-      b.dsort[lo + pos] = dc;
-      b.zsort[lo + pos] = zc;
-      b.perm[lo + pos] = c;
+      b.dsort[lo + pos] = first ? A[i] : Bh[j];
+      b.perm[lo + pos] = first ? i : n1 + j;
       b.msk[lo + pos] = first ? 1 : 2;
       if (first) i++; else j++;
     }
   }
   __syncthreads();
+  // z of each sorted entry: the last row of its top-half vector or the first
+  // row of its bottom-half vector (times the sign of beta), over sqrt 2
+  for (int pos = t; pos < N; pos += 256) {
+    const int c = b.perm[lo + pos];
+    const bool first = c < n1;
+    b.zsort[lo + pos] = first ? Qcur[(mid - 1) + (long)(lo + c) * ldq] * rs2
+                              : sgn * Qcur[mid + (long)(lo + c) * ldq] * rs2;
+  }
+  __syncthreads();
   __shared__ double cd[CHK], cz[CHK];
   __shared__ int cp[CHK], cm[CHK];
+  __shared__ int wcnt[2][3][4];  // per chunk parity: counts of each wavefront
+  __shared__ int close_seen, kk_s;
   const double dmax = fmax(fabs(b.dsort[lo]), fabs(b.dsort[lo + N - 1]));
   const double tol = 8.0 * DBL_EPSILON * fmax(dmax, rho);
-  // sequential scan by thread 0 over LDS-staged chunks
-  int k = 0, ndef = 0, nrot = 0;
-  bool have_prev = false;
-  double pd = 0.0, pz = 0.0;
-  int pc = 0, pm = 0;
-  for (int base = 0; base < N; base += CHK) {
-    const int cnt = min(CHK, N - base);
-    __syncthreads();
-    for (int q = t; q < cnt; q += 256) {
-      cd[q] = b.dsort[lo + base + q];
-      cz[q] = b.zsort[lo + base + q];
-      cp[q] = b.perm[lo + base + q];
-      cm[q] = b.msk[lo + base + q];
+  if (t == 0) close_seen = 0;
+  // undeflated entries (in order) to dk/zk/colk/gpos, deflated ones to defval/defcol
+  int kb = 0, db = 0;
+  for (int base = 0, par = 0; base < N; base += 256, par ^= 1) {
+    const int q = base + t;
+    const bool valid = q < N;
+    double dq = 0.0, zq = 0.0;
+    int pq = 0, mq = 0;
+    if (valid) {
+      dq = b.dsort[lo + q];
+      zq = b.zsort[lo + q];
+      pq = b.perm[lo + q];
+      mq = b.msk[lo + q];
+    }
+    const bool defl = valid && (rho * fabs(zq) <= tol);
+    const bool keep = valid && !defl;
+    const unsigned long long bk = __ballot(keep), bd = __ballot(defl);
+    if (lane == 0) {
+      wcnt[par][0][wv] = __popcll(bk);
+      wcnt[par][1][wv] = __popcll(bd);
     }
     __syncthreads();
-    if (t == 0) {
-      for (int q = 0; q < cnt; q++) {
-        const double dq = cd[q], zq = cz[q];
-        if (rho * fabs(zq) <= tol) {
-          b.defval[lo + ndef] = dq;
-          b.defcol[lo + ndef] = cp[q];
-          ndef++;
-          continue;
-        }
-        if (!have_prev) {
-          have_prev = true;
-          pd = dq; pz = zq; pc = cp[q]; pm = cm[q];
-          continue;
-        }
-        // the rotation that zeroes z_prev has c = zq / r, s = pz / r,
-        // r = hypot(zq, pz), and leaves the coupling (pd - dq) c s; the test
-        // |(pd - dq) c s| <= tol is taken as |(pd - dq) zq pz| <= tol r^2 so
-        // that r, c and s are formed only for a rotation
-        if (fabs((pd - dq) * zq * pz) <= tol * (zq * zq + pz * pz)) {
-          const double r = hypot(zq, pz);
-          const double c = zq / r, s = pz / r;
-          // rotate: new prev column = c q_prev - s q_cur (z -> 0), cur = s q_prev + c q_cur
-          b.rot_a[lo + nrot] = pc;
-          b.rot_b[lo + nrot] = cp[q];
-          b.rot_c[lo + nrot] = c;
-          b.rot_s[lo + nrot] = s;
-          nrot++;
-          const double dprev = c * c * pd + s * s * dq;
-          const double dcur = s * s * pd + c * c * dq;
-          b.defval[lo + ndef] = dprev;
-          b.defcol[lo + ndef] = pc;
-          ndef++;
-          pd = dcur; pz = r; pc = cp[q]; pm = pm | cm[q];
-        } else {
-          b.dk[lo + k] = pd;
-          b.zk[lo + k] = pz;
-          b.colk[lo + k] = pc;
-          b.gpos[lo + k] = pm;  // mask for now
-          k++;
-          pd = dq; pz = zq; pc = cp[q]; pm = cm[q];
+    int ko = kb + __popcll(bk & lanes_below), dof = db + __popcll(bd & lanes_below);
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+      if (w < wv) {
+        ko += wcnt[par][0][w];
+        dof += wcnt[par][1][w];
+      }
+      kb += wcnt[par][0][w];
+      db += wcnt[par][1][w];
+    }
+    if (keep) {
+      b.dk[lo + ko] = dq;
+      b.zk[lo + ko] = zq;
+      b.colk[lo + ko] = pq;
+      b.gpos[lo + ko] = mq;  // mask for now
+    }
+    if (defl) {
+      b.defval[lo + dof] = dq;
+      b.defcol[lo + dof] = pq;
+    }
+  }
+  __syncthreads();
+  for (int j = 1 + t; j < kb; j += 256)
+    if (close_pair(b.dk[lo + j - 1], b.zk[lo + j - 1], b.dk[lo + j], b.zk[lo + j], tol))
+      close_seen = 1;
+  __syncthreads();
+  int k = kb, ndef = db, nrot = 0;
+  if (close_seen) {
+    // sequential scan by thread 0 over LDS-staged chunks (it rewrites every
+    // output above)
+    k = 0;
+    ndef = 0;
+    bool have_prev = false;
+    double pd = 0.0, pz = 0.0;
+    int pc = 0, pm = 0;
+    for (int base = 0; base < N; base += CHK) {
+      const int cnt = min(CHK, N - base);
+      __syncthreads();
+      for (int q = t; q < cnt; q += 256) {
+        cd[q] = b.dsort[lo + base + q];
+        cz[q] = b.zsort[lo + base + q];
+        cp[q] = b.perm[lo + base + q];
+        cm[q] = b.msk[lo + base + q];
+      }
+      __syncthreads();
+      if (t == 0) {
+        for (int q = 0; q < cnt; q++) {
+          const double dq = cd[q], zq = cz[q];
+          if (rho * fabs(zq) <= tol) {
+            b.defval[lo + ndef] = dq;
+            b.defcol[lo + ndef] = cp[q];
+            ndef++;
+            continue;
+          }
+          if (!have_prev) {
+            have_prev = true;
+            pd = dq; pz = zq; pc = cp[q]; pm = cm[q];
+            continue;
+          }
+          if (close_pair(pd, pz, dq, zq, tol)) {
+            const double r = hypot(zq, pz);
+            const double c = zq / r, s = pz / r;
+            // rotate: new prev column = c q_prev - s q_cur (z -> 0), cur = s q_prev + c q_cur
+            b.rot_a[lo + nrot] = pc;
+            b.rot_b[lo + nrot] = cp[q];
+            b.rot_c[lo + nrot] = c;
+            b.rot_s[lo + nrot] = s;
+            nrot++;
+            const double dprev = c * c * pd + s * s * dq;
+            const double dcur = s * s * pd + c * c * dq;
+            b.defval[lo + ndef] = dprev;
+            b.defcol[lo + ndef] = pc;
+            ndef++;
+            pd = dcur; pz = r; pc = cp[q]; pm = pm | cm[q];
+          } else {
+            b.dk[lo + k] = pd;
+            b.zk[lo + k] = pz;
+            b.colk[lo + k] = pc;
+            b.gpos[lo + k] = pm;  // mask for now
+            k++;
+            pd = dq; pz = zq; pc = cp[q]; pm = cm[q];
+          }
         }
       }
     }
-  }
-  if (t == 0) {
-    if (have_prev) {
+    if (t == 0 && have_prev) {
       b.dk[lo + k] = pd;
       b.zk[lo + k] = pz;
       b.colk[lo + k] = pc;
       b.gpos[lo + k] = pm;
       k++;
     }
+  }
+  if (t == 0) {
     int* meta = b.meta + (long)mi * META;
     meta[0] = k;
     meta[1] = ndef;
     meta[2] = nrot;
     b.rho[mi] = rho;
+    kk_s = k;
   }
   __syncthreads();
-  // grouping: top-only (mask 1) | mixed (3) | bottom-only (2), stable, by
-  // block-wide prefix sums over chunks of 256
-  __shared__ int scan[3][256];
+  // grouping: top-only (mask 1) | mixed (3) | bottom-only (2), stable: the
+  // totals of each kind first, then each entry's place from ballots
+  const int kk = kk_s;
   __shared__ int tot3[3];
-  const int kk = b.meta[(long)mi * META];
   if (t < 3) tot3[t] = 0;
   __syncthreads();
-  for (int base = 0; base < kk; base += 256) {
-    const int j = base + t;
-    const int mk = (j < kk) ? b.gpos[lo + j] : 0;
-    scan[0][t] = (mk == 1);
-    scan[1][t] = (mk == 3);
-    scan[2][t] = (mk == 2);
-    __syncthreads();
-    if (t < 3) {
-      int a = 0;
-      for (int q = 0; q < 256; q++) a += scan[t][q];
-      tot3[t] += a;
+  {
+    int c3[3] = {0, 0, 0};
+    for (int j = t; j < kk; j += 256) {
+      const int mk = b.gpos[lo + j];
+      c3[0] += (mk == 1);
+      c3[1] += (mk == 3);
+      c3[2] += (mk == 2);
     }
-    __syncthreads();
+#pragma unroll
+    for (int y = 0; y < 3; y++)
+      if (c3[y]) atomicAdd(&tot3[y], c3[y]);
   }
+  __syncthreads();
   const int nt = tot3[0], nm = tot3[1], nb = tot3[2];
   int run[3] = {0, nt, nt + nm};
-  for (int base = 0; base < kk; base += 256) {
+  for (int base = 0, par = 0; base < kk; base += 256, par ^= 1) {
     const int j = base + t;
     const int mk = (j < kk) ? b.gpos[lo + j] : 0;
     const int ty = (mk == 1) ? 0 : ((mk == 3) ? 1 : 2);
-    for (int y = 0; y < 3; y++) scan[y][t] = (j < kk && ty == y);
+    unsigned long long bm[3];
+#pragma unroll
+    for (int y = 0; y < 3; y++) bm[y] = __ballot(j < kk && ty == y);
+    if (lane == 0) {
+#pragma unroll
+      for (int y = 0; y < 3; y++) wcnt[par][y][wv] = __popcll(bm[y]);
+    }
     __syncthreads();
-    // inclusive Hillis-Steele scan of the three flag rows
-    for (int o = 1; o < 256; o <<= 1) {
-      int v[3];
-      for (int y = 0; y < 3; y++) v[y] = (t >= o) ? scan[y][t - o] : 0;
-      __syncthreads();
-      for (int y = 0; y < 3; y++) scan[y][t] += v[y];
-      __syncthreads();
+    int pos = 0;
+#pragma unroll
+    for (int y = 0; y < 3; y++) {
+      int pre = 0, tot = 0;
+#pragma unroll
+      for (int w = 0; w < 4; w++) {
+        if (w < wv) pre += wcnt[par][y][w];
+        tot += wcnt[par][y][w];
+      }
+      if (y == ty) pos = run[y] + pre + __popcll(bm[y] & lanes_below);
+      run[y] += tot;
     }
     if (j < kk) {
-      const int gp = run[ty] + scan[ty][t] - 1;
-      b.gpos[lo + j] = gp;
-      b.acol[lo + gp] = b.colk[lo + j];
+      b.gpos[lo + j] = pos;
+      b.acol[lo + pos] = b.colk[lo + j];
     }
-    for (int y = 0; y < 3; y++) run[y] += scan[y][255];
-    __syncthreads();
   }
   if (t == 0) {
     int* meta = b.meta + (long)mi * META;
