@@ -115,6 +115,13 @@ def _tridiag_cases():
     d = np.repeat(rng.standard_normal(30), 20)
     e = 1e-14 * rng.standard_normal(599)
     out.append(("clustered600", d, e))
+    # every diagonal value twice, far apart in the matrix, weak couplings:
+    # merges see close pairs across their halves (rotations) among entries
+    # that are not deflated
+    v = rng.standard_normal(350)
+    d = np.concatenate([v, v[::-1]])
+    e = 1e-3 * rng.standard_normal(699)
+    out.append(("pairs700", d, e))
     return out
 
 
