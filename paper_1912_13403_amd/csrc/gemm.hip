@@ -487,8 +487,7 @@ __global__ void splitk_reduce_kernel(int m, int n, int nsplit, const T* part, T*
   const long tot = (long)m * n;
   if (idx >= tot) return;
   if (ndev && idx / m >= *ndev) return;
-  T s = 0;
-  for (int z = 0; z < nsplit; z++) s += part[z * tot + idx];
+  const T s = sum_in_order(part + idx, tot, nsplit, T(0));
   const int i = (int)(idx % m), j = (int)(idx / m);
   T* c = C + i + (long)j * ldc;
   *c = (beta != 0.0) ? s + (T)beta * *c : s;
@@ -600,9 +599,8 @@ __global__ void sym_pair_reduce_kernel(int m, int n, int nsplit, int kchunk, con
   const int t0 = (i / 128) * 128;
   const int z1 = min(nsplit - 1, (t0 + 127) / kchunk);  // last slice of the first pass
   const int z2 = t0 / kchunk;                            // first slice of the second
-  T s1 = 0, s2 = 0;
-  for (int z = 0; z <= z1; z++) s1 += part1[z * tot + idx];
-  for (int z = z2; z < nsplit; z++) s2 += part2[z * tot + idx];
+  const T s1 = sum_in_order(part1 + idx, tot, z1 + 1, T(0));
+  const T s2 = sum_in_order(part2 + z2 * tot + idx, tot, nsplit - z2, T(0));
   C[i + (long)j * ldc] = s2 + s1;
 }
 
@@ -613,8 +611,7 @@ __global__ void splitk_reduce_group_kernel(const GemmGroupItem* items) {
   const long tot = (long)it.m * it.n;
   for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
        idx += (long)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int z = 0; z < it.nsplit; z++) s += it.part[z * tot + idx];
+    const double s = sum_in_order(it.part + idx, tot, it.nsplit, 0.0);
     const int i = (int)(idx % it.m), j = (int)(idx / it.m);
     double* c = it.C + i + (long)j * it.ldc;
     *c = (it.beta != 0.0) ? s + it.beta * *c : s;

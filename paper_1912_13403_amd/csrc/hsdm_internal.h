@@ -189,6 +189,22 @@ HSDM_DEV void dev_set_status(DevStatusWord* st, int code, int detail) {
   if (atomicCAS(&st->code, 0, code) == 0) st->detail = detail;
 }
 
+// s + p[0] + p[stride] + ... + p[(cnt - 1) stride], added in that order.  The
+// loads go out 16 at a time, so a long sum by few threads (the partials of a
+// split product) waits for memory once per 16 terms, not once per term.
+template <class T>
+HSDM_DEV T sum_in_order(const T* p, long stride, int cnt, T s) {
+  for (int z = 0; z < cnt; z += 16) {
+    T v[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) v[i] = (z + i < cnt) ? p[(long)(z + i) * stride] : T(0);
+#pragma unroll
+    for (int i = 0; i < 16; i++)
+      if (z + i < cnt) s += v[i];
+  }
+  return s;
+}
+
 // Launch-error helper.
 #define HSDM_TRY(x)                          \
   do {                                       \

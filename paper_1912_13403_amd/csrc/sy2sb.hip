@@ -617,19 +617,26 @@ HSDM_DEV void atb_partial_body(int h, const double* U, long ldu, const double* W
     Ws[i][c] = (i < nr) ? W[r0 + i + (long)c * ldw] : 0.0;
   }
   __syncthreads();
-  for (int e = t; e < B * B; e += NT) {
-    const int a = e % B, b = e / B;
-    double s = 0.0;
-    for (int i = 0; i < nr; i++) s += Us[i][a] * Ws[i][b];
-    part[(size_t)g * B * B + e] = s;
+  // thread t: entries e = t + NT j, which share the column a = t % B of U
+  static_assert(NT % B == 0, "the entries of one thread share a column of U");
+  constexpr int PER = B * B / NT;
+  const int a = t % B;
+  double s[PER];
+#pragma unroll
+  for (int j = 0; j < PER; j++) s[j] = 0.0;
+  for (int i = 0; i < nr; i++) {
+    const double u = Us[i][a];
+#pragma unroll
+    for (int j = 0; j < PER; j++) s[j] += u * Ws[i][(t + NT * j) / B];
   }
+#pragma unroll
+  for (int j = 0; j < PER; j++) part[(size_t)g * B * B + t + NT * j] = s[j];
 }
 
 template <int B>
 HSDM_DEV void atb_reduce_body(int G, const double* part, double* out, long ldo, int e) {
   if (e >= B * B) return;
-  double s = 0.0;
-  for (int q = 0; q < G; q++) s += part[(size_t)q * B * B + e];
+  const double s = sum_in_order(part + e, (long)B * B, G, 0.0);
   out[(e % B) + (long)(e / B) * ldo] = s;
 }
 
