@@ -215,19 +215,24 @@ HSDM_DEV double gram_entry(const double (*Pl)[B + 1], int nrows, int ca, int cb)
 }
 
 // T (upper triangular, in LDS) from the Gram matrix and the scalars:
-// T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) (V^T v_j)(0:j)
+// T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) (V^T v_j)(0:j).
+// Thread t forms row t of T and reads only entries of row t it wrote itself
+// at earlier steps (T(t, k), t <= k < j), so the steps need no barrier
+// between them.
 template <int B>
 HSDM_DEV void form_t(double (*Tl)[B + 1], const double (*Gm)[B + 1], const double* taul) {
   const int t = threadIdx.x;
-  for (int j = 0; j < B; j++) {
-    if (t < j) {
-      double sum = 0.0;
-      for (int k = t; k < j; k++) sum = fma(Tl[t][k], Gm[k][j], sum);
-      Tl[t][j] = -taul[j] * sum;
+  if (t < B) {
+    for (int j = 0; j < B; j++) {
+      if (t < j) {
+        double sum = 0.0;
+        for (int k = t; k < j; k++) sum = fma(Tl[t][k], Gm[k][j], sum);
+        Tl[t][j] = -taul[j] * sum;
+      }
+      if (t == j) Tl[j][j] = taul[j];
     }
-    if (t == j) Tl[j][j] = taul[j];
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // The three h x B copies that file a panel's V and W for the group's
@@ -377,16 +382,46 @@ HSDM_DEV void panel_qr_body(int h, double* P, long ldp, double* V, long ldv, dou
   }
   if (g == 0 && t < B) tau_out[t] = taul[t];
   __syncthreads();
-  // partial Gram of this workgroup's rows; workgroup 0 sums them
-  for (int e = t; e < B * B; e += NT) {
-    const int ca = e % B, cb = e / B;
-    const double sum = gram_entry<B>(Pl, nrows, ca, cb);
-    if (g == 0)
-      Gm[ca][cb] = sum;
-    else
-      st_agent(&gpart[(size_t)g * B * B + e], sum);
+  // partial Gram of this workgroup's rows (gram_entry's values: the upper
+  // triangle, zeros below it); workgroup 0 sums them.  Thread t < 136 forms
+  // the 2 x 2 block (bi, bj), bi <= bj, of the upper triangle, reading each
+  // of its four columns once per row; each entry is gram_entry's chain of
+  // fused multiply-adds over the rows in order.
+  {
+    auto put = [&](int ca, int cb, double v) {
+      if (g == 0)
+        Gm[ca][cb] = v;
+      else
+        st_agent(&gpart[(size_t)g * B * B + ca + (size_t)cb * B], v);
+    };
+    constexpr int NUB = (B / 2) * (B / 2 + 1) / 2;
+    static_assert(NUB <= NT, "one 2 x 2 block per thread");
+    if (t < NUB) {
+      int bj = 0;
+      while ((bj + 1) * (bj + 2) / 2 <= t) bj++;
+      const int bi = t - bj * (bj + 1) / 2;
+      const int c0 = 2 * bi, c1 = 2 * bj;
+      double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+      for (int i = 0; i < nrows; i++) {
+        const double a0 = Pl[i][c0], a1 = Pl[i][c0 + 1], b0 = Pl[i][c1], b1 = Pl[i][c1 + 1];
+        s00 = fma(a0, b0, s00);
+        s01 = fma(a0, b1, s01);
+        s10 = fma(a1, b0, s10);
+        s11 = fma(a1, b1, s11);
+      }
+      put(c0, c1, s00);
+      put(c0, c1 + 1, s01);
+      put(c0 + 1, c1, bi == bj ? 0.0 : s10);  // below the diagonal in a diagonal block
+      put(c0 + 1, c1 + 1, s11);
+    }
+    // the blocks below the diagonal
+    for (int e = t; e < B * B; e += NT) {
+      const int ca = e % B, cb = e / B;
+      if (ca / 2 > cb / 2) put(ca, cb, 0.0);
+    }
   }
   if (g != 0) return;
+  __syncthreads();
   for (int e = t; e < B * B; e += NT) {
     const int ca = e % B, cb = e / B;
     Gm[ca][cb] = sum_ready<16>(gpart + e, (long)B * B, 1, 1, G, Gm[ca][cb], st);
