@@ -273,7 +273,7 @@ __global__ void fill_nan_kernel(double* p, long cnt) {
 // Workgroup g holds rows [256 g, 256 g + 256) of the panel, one row per
 // thread in registers; the column sums of each step are reduced inside the
 // wavefronts by shuffles, across the 4 wavefronts through LDS and across
-// the workgroups through global partial sums and one grid barrier.
+// the workgroups through the exchange slots of global memory.
 template <int B>
 HSDM_DEV void panel_qr_body(int h, double* P, long ldp, double* V, long ldv, double* tau_out,
                             double* Tt, double* part, double* prow, double* gpart,
