@@ -675,16 +675,22 @@ HSDM_DEV void atb_reduce_body(int G, const double* part, double* out, long ldo, 
   out[(e % B) + (long)(e / B) * ldo] = s;
 }
 
+// U^T W for U of gridDim.y blocks of B columns: workgroup (g, c) forms the
+// partial of rows [ACH g, ACH g + ACH) of column block c (the partials of
+// block c follow those of block c - 1); the reduction's blockIdx.y = c sums
+// block c's into rows [B c, B c + B) of out.
 template <int B>
 __global__ __launch_bounds__(NT) void atb_partial_kernel(int h, const double* U, long ldu,
                                                          const double* W, long ldw,
                                                          double* part) {
-  atb_partial_body<B>(h, U, ldu, W, ldw, part, blockIdx.x);
+  atb_partial_body<B>(h, U + (long)blockIdx.y * B * ldu, ldu, W, ldw,
+                      part + (size_t)blockIdx.y * gridDim.x * B * B, blockIdx.x);
 }
 
 template <int B>
 __global__ void atb_reduce_kernel(int G, const double* part, double* out, long ldo) {
-  atb_reduce_body<B>(G, part, out, ldo, blockIdx.x * blockDim.x + threadIdx.x);
+  atb_reduce_body<B>(G, part + (size_t)blockIdx.y * G * B * B, out + (long)blockIdx.y * B, ldo,
+                     blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // The same for the items of a grouped launch: workgroup blockIdx.x works on
@@ -866,14 +872,21 @@ struct Sy2sb {
     g.alpha = -0.5; g.beta = 1.0;
     return g;
   }
+  // out (nblk B x B, leading dimension ldo) = U^T W for h x (nblk B) U and
+  // h x B W; part holds ceil(h / ACH) nblk B^2 partials
+  hipError_t atb(int h, const double* U, long ldu, const double* W, long ldw, int nblk,
+                 double* part, double* out, long ldo) {
+    const int G = ceil_div(h, ACH);
+    HSDM_LAUNCH((atb_partial_kernel<BB>), dim3(G, nblk), dim3(NT), 0, s, h, U, ldu, W, ldw,
+                part);
+    HSDM_TRY(hipGetLastError());
+    HSDM_LAUNCH((atb_reduce_kernel<BB>), dim3(ceil_div(B * B, 256), nblk), dim3(256), 0, s, G,
+                part, out, ldo);
+    return hipGetLastError();
+  }
   hipError_t make_w_post(int h, const double* Vp, double* Wp) {
     const AtbGroupItem a = atb_item(h, Wp);
-    HSDM_LAUNCH((atb_partial_kernel<BB>), dim3(a.G), dim3(NT), 0, s, h, a.U, a.ldu, a.W,
-                       a.ldw, a.part);
-    HSDM_TRY(hipGetLastError());
-    HSDM_LAUNCH((atb_reduce_kernel<BB>), dim3(ceil_div(B * B, 256)), dim3(256), 0, s, a.G,
-                       a.part, a.out, a.ldo);
-    HSDM_TRY(hipGetLastError());
+    HSDM_TRY(atb(h, a.U, a.ldu, a.W, a.ldw, 1, a.part, a.out, a.ldo));
     return gemm_launch(fix_args(h, Vp, Wp), s);
   }
   // the panel's V and W into the update operands: VW[:, o:o+2B] = [V W],
@@ -956,12 +969,12 @@ struct Sy2sb {
     HSDM_TRY(make_w_pre(h, Vq, T1 + (size_t)p * B * B));
     HSDM_TRY(make_w_sym(rq, h, Wq));
     if (q > 0) {
-      // corrections for the held-back updates of panels 0 .. q-1
+      // corrections for the held-back updates of panels 0 .. q-1:
+      // Qc = [W V]_<q^T Y (2q blocks of B columns, partials in skpart)
+      const size_t need = (size_t)ceil_div(h, ACH) * 2 * q * B * B;
+      if (need > (size_t)(ceil_div(n, SPLITK) + 1) * n * B) return hipErrorInvalidValue;
+      HSDM_TRY(atb(h, WV + o, n, Y, n, 2 * q, skpart, Qc, 2 * B * q));
       GemmArgs g{};
-      g.m = 2 * B * q; g.n = B; g.k = h; g.A = WV + o; g.lda = n; g.B = Y; g.ldb = n;
-      g.C = Qc; g.ldc = 2 * B * q; g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0;
-      HSDM_TRY(gemm_splitk_launch(g, SPLITK / 2, skpart, s));
-      g = GemmArgs{};
       g.m = h; g.n = B; g.k = 2 * B * q; g.A = VW + o; g.lda = n; g.B = Qc; g.ldb = 2 * B * q;
       g.C = Wq; g.ldc = n; g.alpha = -1.0; g.beta = 1.0;
       HSDM_TRY(gemm_launch(g, s));
