@@ -565,11 +565,11 @@ size_t bt1_scratch_doubles(int n, int B_, int m) {
   const size_t ngroup = ceil_div(npanel_of(n, B_), GP) + 1;
   const size_t gsplit = ceil_div(n, BT1_GCHUNK) + 1;
   const size_t ndesc = ngroup * GP;
-  // V^T Z and T (V^T Z) (W x m each), split-K partials, the Gram of every
-  // group with the partials of one, T of every group, the pair products of
-  // one level, two descriptor arrays
-  return W * m * (2 + BT1_MAXSPLIT) + W * W * (2 * ngroup + gsplit) + ngroup * W * W / 2 +
-         2 * ndesc * (sizeof(GemmDesc) / sizeof(double) + 1) + 64;
+  // V^T Z and T (V^T Z) (W x m each), split-K partials, one group's V^T
+  // (W x n), the Gram of every group with the partials of one, T of every
+  // group, the pair products of one level, two descriptor arrays
+  return W * m * (2 + BT1_MAXSPLIT) + W * (size_t)n + W * W * (2 * ngroup + gsplit) +
+         ngroup * W * W / 2 + 2 * ndesc * (sizeof(GemmDesc) / sizeof(double) + 1) + 64;
 }
 
 hipError_t bt1_zero_fill(int n, int B_, double* Vst, long ldv, hipStream_t s) {
@@ -585,7 +585,7 @@ namespace {
 // into the scratch; returns the pointers the application needs.
 struct Bt1Groups {
   int np_all, W, ngroup;
-  double *Wb, *W2, *part, *Tall;
+  double *Wb, *W2, *part, *Vt, *Tall;
 };
 
 hipError_t bt1_groups(int n, int B_, const double* Vst, long ldv, const double* T1, int m,
@@ -598,13 +598,14 @@ hipError_t bt1_groups(int n, int B_, const double* Vst, long ldv, const double* 
   double* Wb = scratch;
   double* W2 = Wb + (size_t)W * m;
   double* part = W2 + (size_t)W * m;
-  double* Gall = part + (size_t)BT1_MAXSPLIT * W * m;
+  double* Vt = part + (size_t)BT1_MAXSPLIT * W * m;
+  double* Gall = Vt + (size_t)W * n;
   double* Tall = Gall + (size_t)ngroup * W * W;
   double* Gpart = Tall + (size_t)ngroup * W * W;
   double* Xall = Gpart + gsplit * W * W;
   GemmDesc* d1 = reinterpret_cast<GemmDesc*>(Xall + (size_t)ngroup * W * W / 2);
   GemmDesc* d2 = d1 + ndesc;
-  out = Bt1Groups{np_all, W, ngroup, Wb, W2, part, Tall};
+  out = Bt1Groups{np_all, W, ngroup, Wb, W2, part, Vt, Tall};
   // Gram V_q^T V_q of every group (upper blocks are used)
   for (int q = 0; q < ngroup; q++) {
     const int p0 = q * GP, np = min(GP, np_all - p0);
@@ -632,12 +633,32 @@ hipError_t bt1_groups(int n, int B_, const double* Vst, long ldv, const double* 
   return hipSuccess;
 }
 
+// Vt (w x h, leading dimension w) = V^T for V h x w (leading dimension ldv):
+// 32 x 32 tiles through LDS, so that both the reads and the writes coalesce
+template <class T>
+__global__ __launch_bounds__(256) void transpose_kernel(int h, int w, const T* V, long ldv, T* Vt) {
+  __shared__ T tile[32][33];
+  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int i = i0 + tx, j = j0 + k;
+    tile[k][tx] = (i < h && j < w) ? V[i + (long)j * ldv] : T(0);
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int j = j0 + tx, i = i0 + k;
+    if (i < h && j < w) Vt[j + (long)i * w] = tile[tx][k];
+  }
+}
+
 // Z <- (I - V_q T_q V_q^T) Z for the groups q, last first, in element type T
-// (V, Tall, Z and the work buffers Wb, W2, part of that type).
+// (V, Tall, Z and the work buffers Wb, W2, part of that type).  With Vt
+// (room for w x h) each group's V^T is formed there first, so that V^T Z
+// reads its A operand along its columns, as the 128 x 128 tiles stage it.
 template <class T>
 hipError_t bt1_groups_apply(int n, int B_, const Bt1Groups& G_, const T* V, long ldv,
                             const T* Tall, T* Z, long ldz, int m, const int* m_dev, T* Wb, T* W2,
-                            T* part, hipStream_t s) {
+                            T* part, T* Vt, hipStream_t s) {
   const int W = G_.W;
   for (int q = G_.ngroup - 1; q >= 0; q--) {
     const int p0 = q * GP, np = min(GP, G_.np_all - p0);
@@ -656,6 +677,12 @@ hipError_t bt1_groups_apply(int n, int B_, const Bt1Groups& G_, const T* V, long
     GemmArgsT<T> g{};
     g.m = w; g.n = m; g.k = h; g.A = Vq; g.lda = ldv; g.B = Zq; g.ldb = ldz; g.C = Wb; g.ldc = w;
     g.alpha = 1.0; g.beta = 0.0; g.ta = 1; g.tb = 0; g.ndev = m_dev;
+    if (Vt) {
+      HSDM_LAUNCH(transpose_kernel<T>, dim3(ceil_div(h, 32), ceil_div(w, 32)), dim3(256), 0, s, h,
+                  w, Vq, ldv, Vt);
+      HSDM_TRY(hipGetLastError());
+      g.A = Vt; g.lda = w; g.ta = 0;
+    }
     HSDM_TRY(gemm_splitk_launch(g, kchunk, part, s));
     g = GemmArgsT<T>{};
     g.m = w; g.n = m; g.k = w; g.A = Tq; g.lda = W; g.B = Wb; g.ldb = w; g.C = W2; g.ldc = w;
@@ -678,7 +705,7 @@ hipError_t bt1_apply(int n, int B_, const double* Vst, long ldv, const double* T
   Bt1Groups G_;
   HSDM_TRY(bt1_groups(n, B_, Vst, ldv, T1, m, scratch, G_, s));
   return bt1_groups_apply<double>(n, B_, G_, Vst, ldv, G_.Tall, Z, ldz, m, m_dev, G_.Wb, G_.W2,
-                                  G_.part, s);
+                                  G_.part, G_.Vt, s);
 }
 
 size_t bt1_f32_scratch_floats(int n, int B_, int m) {
@@ -700,5 +727,6 @@ hipError_t bt1_apply_f32(int n, int B_, const double* Vst, long ldv, const float
   float* part = W2 + (size_t)W * m;
   float* Tall = part + (size_t)BT1_MAXSPLIT * W * m;
   HSDM_TRY(dev_convert(G_.Tall, W, Tall, W, W, G_.ngroup * W, s));
-  return bt1_groups_apply<float>(n, B_, G_, V32, ldv32, Tall, Z, ldz, m, m_dev, Wb, W2, part, s);
+  return bt1_groups_apply<float>(n, B_, G_, V32, ldv32, Tall, Z, ldz, m, m_dev, Wb, W2, part,
+                                 (float*)nullptr, s);
 }
