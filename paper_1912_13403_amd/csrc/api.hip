@@ -745,8 +745,6 @@ hipError_t occ_hook(void* ctx, const double* lam, hipStream_t s) {
                             h->st, s);
 }
 
-int check_handle(hsdm_handle h) { return h ? 0 : -1; }
-
 // Kernel timing for the duration of one solve (finish() folds the records).
 struct KtScope {
   explicit KtScope(hsdm_ctx* h) {
