@@ -636,6 +636,14 @@ def main():
         "band_energy": r["band_energy"],
         "timed_total_s": total,
     }
+    # the device's own rates beside the published peaks the roofline uses
+    mf = h.hsdm_probe(0, 20000)
+    cp = h.hsdm_probe(1, float(1 << 30))
+    rec["measured_peaks"] = {
+        "fp64_mfma_tflops": mf[0], "hbm_copy_gbps": cp[0],
+        "method": "hsdm_probe after the timed steps: FP64 16x16x4 MFMA chains on 2 workgroups "
+                  "of 4 wavefronts per CU (8 independent accumulators per wavefront, 20000 "
+                  "rounds); a 1 GiB device copy (bytes read + written), second launch timed"}
     h.close()
     if not args.no_refined:
         rec["refined_form"] = refined_form(args, Hd, Sd, p, D, E, w)

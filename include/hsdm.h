@@ -388,6 +388,17 @@ const char *hsdm_kernel_stat(hsdm_handle h, int i, double *out);
  * every kernel again), so that one kernel can be timed in every launch with
  * no events around the others.  Returns HSDM_OK or -1 (null handle). */
 int hsdm_timing_kernel(hsdm_handle h, const char *name);
+/* Measurement utility for the roofline's peaks, not a step of the method:
+ * which = 0 runs `size` rounds (1 .. 1e7) of eight independent FP64 16x16x4
+ * matrix-core products on every wavefront of two four-wavefront workgroups
+ * per compute unit; which = 1 copies a buffer of `size` bytes (16 .. 64e9)
+ * to another with one 16-byte load and store per thread and step.  Each is
+ * launched twice on `stream` and the second launch is timed with HIP events:
+ * out[0] = TFLOP/s (which = 0) or GB/s of bytes read plus written (1),
+ * out[1] = ms, out[2] = flops or bytes.  The copy allocates and frees its two
+ * buffers.  Returns HSDM_OK, -1 null handle, -2 which not 0 or 1, -3 size
+ * out of range, -4 out missing, HSDM_DEVICE_ERROR (see hsdm_last_error). */
+int hsdm_probe(hsdm_handle h, int which, double size, double *out, void *stream);
 int hsdm_version(void);
 
 #ifdef __cplusplus

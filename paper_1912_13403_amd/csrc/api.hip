@@ -769,6 +769,13 @@ struct CoopScope {
 
 }  // namespace
 
+// probe.hip: the device's sustained FP64 matrix-core rate (iters rounds per
+// wavefront) and HBM copy bandwidth (two buffers of `bytes`), each timed on
+// its second launch: out[0] = TFLOP/s or GB/s (bytes read + written), out[1]
+// = ms, out[2] = flops or bytes.
+hipError_t probe_fp64_mfma(int iters, double* out, hipStream_t s);
+hipError_t probe_hbm_copy(double bytes, double* out, hipStream_t s);
+
 extern "C" {
 
 int hsdm_version(void) { return 100; }
@@ -1012,6 +1019,21 @@ int hsdm_dgemm(hsdm_handle h, char transa, char transb, int m, int n, int k, dou
   g.alpha = alpha; g.beta = beta; g.ta = ta; g.tb = tb;
   DEV_TRY(h, gemm_launch(g, s));
   DEV_TRY(h, hipStreamSynchronize(s));
+  return HSDM_OK;
+}
+
+int hsdm_probe(hsdm_handle h, int which, double size, double* out, void* stream) {
+  if (!h) return -1;
+  if (which != 0 && which != 1) return -2;
+  if (!(size >= (which == 0 ? 1.0 : 16.0)) || size > (which == 0 ? 1e7 : 64e9)) return -3;
+  if (!out) return -4;
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  DEV_TRY(h, hipSetDevice(h->device));
+  if (which == 0)
+    DEV_TRY(h, probe_fp64_mfma((int)size, out, s));
+  else
+    DEV_TRY(h, probe_hbm_copy(size, out, s));
   return HSDM_OK;
 }
 

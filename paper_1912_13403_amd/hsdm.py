@@ -53,7 +53,7 @@ EXPORTED = [
     "hsdm_phase_times", "hsdm_phase_name", "hsdm_phase_flops", "hsdm_kernel_count", "hsdm_kernel_stat",
     "hsdm_version", "hsdm_timing_kernel", "hsdm_solve_dm_real_noalloc", "hsdm_refine_history",
     "hsdm_tune_entries", "hsdm_tune_clear", "hsdm_tune_save", "hsdm_tune_load",
-    "hsdm_last_graph",
+    "hsdm_last_graph", "hsdm_probe",
 ]
 
 HSDM_NOALLOC_MAX_N = 512
@@ -118,6 +118,7 @@ def load_library(path: str = LIB_PATH):
         "hsdm_tune_save": ([ctypes.c_char_p], _i),
         "hsdm_tune_load": ([ctypes.c_char_p], _i),
         "hsdm_last_graph": ([_vp], _i),
+        "hsdm_probe": ([_vp, _i, _d, ctypes.POINTER(_d), _vp], _i),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -250,6 +251,14 @@ class Handle:
     def hsdm_timing_kernel(self, name):
         """Time only the launches of kernel `name` (None: every kernel)."""
         self._check(self._lib.hsdm_timing_kernel(self._h, name.encode() if name else None))
+
+    def hsdm_probe(self, which, size):
+        """Measured FP64 matrix-core rate (which 0: TFLOP/s over `size` rounds per
+        wavefront) or HBM copy bandwidth (which 1: GB/s over a `size`-byte
+        buffer), as (rate, ms, flops or bytes)."""
+        out = (ctypes.c_double * 3)()
+        self._check(self._lib.hsdm_probe(self._h, int(which), float(size), out, None))
+        return out[0], out[1], out[2]
 
     def phase_flops(self):
         """Algorithmic flops of each phase of the last single solve (timing on)."""

@@ -58,6 +58,8 @@ def test_null_handle_is_argument_one(lib):
     assert lib.hsdm_set_real(None, 1, 2.0) == -1
     assert lib.hsdm_init(None, 0) == -1
     assert lib.hsdm_last_error(None) == b"null handle"
+    out = (ctypes.c_double * 3)()
+    assert lib.hsdm_probe(None, 0, 100.0, out, None) == -1
 
 
 def test_handle_keys_match_the_header(lib):
@@ -84,3 +86,24 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_no_unresolved_own_symbols(lib):
+    """Every function the library calls is defined in it or in a versioned
+    system library: a loader that binds at load time finds nothing missing."""
+    import shutil
+    import subprocess
+    from paper_1912_13403_amd import hsdm
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "--undefined-only", hsdm.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    missing = [ln.split()[-1] for ln in out.splitlines()
+               if ln.split() and ln.split()[0] == "U" and "@" not in ln]
+    assert missing == []
+
+
+def test_library_loads_with_immediate_binding():
+    from paper_1912_13403_amd import hsdm
+    ctypes.CDLL(hsdm.LIB_PATH, mode=os.RTLD_NOW)
